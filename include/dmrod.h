@@ -1,0 +1,168 @@
+/*
+ * dmrod.h -- C ABI of the MI355X implicit Discrete Elastic Rods library (libdmrod.so).
+ *
+ * The library advances rods and rod networks with the fully implicit backward-Euler
+ * step of DisMech (arXiv 2311.18126): stretch, bend and twist energies (Eq. 2-8),
+ * elastic force as minus the energy gradient (Eq. 9), optional flat-floor contact and
+ * smooth Coulomb friction (Eq. 10-13), the implicit equations of motion (Eq. 14-15)
+ * solved by Newton's method with the exact Jacobian (Eq. 16), elastic joints
+ * (Elastic Joints subsection) and natural-curvature actuation (Actuation subsection).
+ * Every step of the Newton iteration runs in HIP kernels on the GPU in FP64.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns a dm_status.  Negative values are errors and leave the
+ *    simulation unchanged; the message of the last non-OK status of the calling thread is
+ *    available from dm_last_error().  No function aborts, exits or lets a C++ exception out.
+ *  - Pointers marked "host" are read or written during the call only; the caller keeps
+ *    ownership.  Pointers marked "device" are device memory on the simulation's device,
+ *    caller-owned; the library reads/writes them on the simulation's stream and the call
+ *    returns after that work completes.
+ *  - Units are SI.  Positions are [N][3] row-major doubles; twist angles are per edge.
+ *  - A dm_sim is used by one host thread at a time.  Different sims may share a device.
+ */
+#ifndef DMROD_H
+#define DMROD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DM_OK = 0,
+  DM_NOT_CONVERGED = 1,        /* warning: some systems did not converge; their state is
+                                  left at the start of the failing step and they stop
+                                  advancing (see dm_get_stats) */
+  DM_ERR_INVALID_ARG = -1,     /* bad pointer, size, index or non-finite input */
+  DM_ERR_STATE = -2,           /* call not allowed in this phase (e.g. add after finalize) */
+  DM_ERR_HIP = -3,             /* a HIP runtime call failed (message names it) */
+  DM_ERR_OOM = -4,             /* device allocation failed */
+  DM_ERR_SINGULAR = -5,        /* a Newton linear system had a zero or non-finite pivot;
+                                  that system's state is left at the start of the step */
+  DM_ERR_UNSUPPORTED = -6      /* topology or option this library does not implement */
+} dm_status;
+
+typedef struct dm_sim dm_sim;  /* opaque; created by dm_create, freed by dm_destroy */
+
+/* Simulation-wide settings.  dm_config_default() fills sensible defaults. */
+typedef struct {
+  double gravity[3];      /* m/s^2, acts on node positions as m_i g (misc. force, Eq. 13 text) */
+  double newton_tol;      /* Newton stops when the 2-norm of the residual of Eq. 15 over
+                             free DOFs is <= newton_tol (absolute, N and N m mixed) */
+  double stagnation_tol;  /* ...or when the residual was already <= stagnation_tol and the
+                             last Newton iteration failed to halve it: the FP64 rounding
+                             floor of stiff systems can lie above newton_tol.  0 disables. */
+  int max_iter;           /* Newton iterations per step before DM_NOT_CONVERGED */
+  int line_search;        /* 1: halve the Newton step (at most 10 times) until the residual
+                             norm decreases (the paper's optional line search) */
+  int floor_contact;      /* 1: flat floor z = floor_z with the IMC energy (Eq. 10-11) and
+                             friction (Eq. 12-13) on every node */
+  double floor_z;         /* floor height [m] */
+  double delta;           /* IMC distance tolerance [m]; K1 = 15/delta */
+  double nu;              /* slipping tolerance [m/s]; K2 = 15/nu */
+  double mu;              /* friction coefficient */
+  double k_contact;       /* stiffness multiplying the IMC energy [N/m] */
+  double damping;         /* viscous damping eta [1/s]: F = -eta m (x - x_n)/dt */
+  int device;             /* HIP device ordinal */
+  void* stream;           /* hipStream_t to run on; NULL = the default stream */
+  int block_size;         /* threads per system workgroup: 0 = automatic, else 64..512,
+                             a multiple of 64 */
+} dm_config;
+
+/* Per-system counters accumulated over the last dm_step call. */
+typedef struct {
+  int steps_done;         /* time steps completed */
+  int newton_iters;       /* Newton iterations summed over those steps */
+  int status;             /* dm_status of this system for the call */
+  int floor_steps;        /* steps that ended by the stagnation rule, not newton_tol */
+  double residual;        /* residual norm at the last Newton iterate */
+} dm_stats;
+
+void dm_config_default(dm_config* cfg);
+
+/* Create an empty simulation on cfg->device. */
+dm_status dm_create(const dm_config* cfg, dm_sim** out);
+
+/* Add a rod of n_nodes >= 2 nodes.  x0 (host, [n_nodes][3]) is both the initial and the
+ * undeformed shape (rest edge lengths, and rest curvature unless set).  radius h gives
+ * A = pi h^2, I = pi h^4/4, J = pi h^4/2; shear modulus G = E/(2(1+poisson)).
+ * Node masses are lumped: half of each incident edge's rho*A*length.  *rod_id receives the
+ * rod index (0, 1, ... in order of addition). */
+dm_status dm_add_rod(dm_sim* sim, int n_nodes, const double* x0, double radius, double E,
+                     double poisson, double density, int* rod_id);
+
+/* Elastic joint: node node_b of rod_b becomes the same node as node_a of rod_a.  Bending
+ * and twisting act on every pair of edges meeting there (Elastic Joints subsection).
+ * Supported topologies: each connected set of rods either is one rod, or meets at a single
+ * shared node that is an end node of every rod in the set (at most 8 rods). */
+dm_status dm_add_joint(dm_sim* sim, int rod_a, int node_a, int rod_b, int node_b);
+
+/* Clamp nodes (all three coordinates) and optionally twist angles of a rod.
+ * nodes: host array of n node indices; edges: host array of n_edges edge indices. */
+dm_status dm_fix_nodes(dm_sim* sim, int rod, const int* nodes, int n);
+dm_status dm_fix_edges(dm_sim* sim, int rod, const int* edges, int n_edges);
+
+/* Natural curvature of a rod's interior nodes 1..N-2 (Actuation subsection), host array
+ * [N-2][2] in 1/m along the two material directors.  The integrated value used in Eq. 6 is
+ * kbar times the rest Voronoi length.  Allowed before and after finalize. */
+dm_status dm_set_natural_curvature(dm_sim* sim, int rod, const double* kbar);
+
+/* Sinusoidal actuation kappa1(t) = A sin(2 pi f t + phi) [1/m] on every interior node of
+ * the rod (second component zero), evaluated on the device at the end time of each step. */
+dm_status dm_set_actuation_sine(dm_sim* sim, int rod, double A, double f, double phi);
+
+/* Constant external loads: force (host [N][3], N) on the rod's nodes and twisting moment
+ * (host [N-1], N m) on its edges.  Either pointer may be NULL. */
+dm_status dm_set_external_load(dm_sim* sim, int rod, const double* force, const double* moment);
+
+/* Freeze the topology, build the device layout and upload.  No adds afterwards. */
+dm_status dm_finalize(dm_sim* sim);
+
+/* Advance every system by nsteps steps of size dt in one persistent launch.
+ * stats: NULL or host array of dm_num_systems() entries.  Returns DM_OK, DM_NOT_CONVERGED
+ * or DM_ERR_SINGULAR (the worst over systems), or an error. */
+dm_status dm_step(dm_sim* sim, double dt, int nsteps, dm_stats* stats);
+
+/* Number of independent systems (connected rod sets) and the system holding a rod. */
+int dm_num_systems(const dm_sim* sim);
+int dm_rod_system(const dm_sim* sim, int rod);
+int dm_num_rods(const dm_sim* sim);
+int dm_rod_nodes(const dm_sim* sim, int rod);
+
+/* State of one rod in its own node/edge order: x [N][3], theta [N-1], v [N][3],
+ * theta_dot [N-1]; any pointer may be NULL.  Host memory. */
+dm_status dm_get_rod_state(dm_sim* sim, int rod, double* x, double* theta, double* v,
+                           double* theta_dot);
+dm_status dm_set_rod_state(dm_sim* sim, int rod, const double* x, const double* theta,
+                           const double* v, const double* theta_dot);
+
+/* Bulk state in the library's global node/edge numbering (rod after rod, joint nodes
+ * once), host or device (on_device != 0) arrays: x [n_nodes][3], theta [n_edges],
+ * v [n_nodes][3], theta_dot [n_edges].  Sizes from dm_num_nodes / dm_num_edges.  The
+ * global index of rod r's node i is dm_node_index(r, i). */
+int dm_num_nodes(const dm_sim* sim);
+int dm_num_edges(const dm_sim* sim);
+int dm_node_index(const dm_sim* sim, int rod, int node);
+int dm_edge_index(const dm_sim* sim, int rod, int edge);
+dm_status dm_get_state(dm_sim* sim, double* x, double* theta, double* v, double* theta_dot,
+                       int on_device);
+dm_status dm_set_state(dm_sim* sim, const double* x, const double* theta, const double* v,
+                       const double* theta_dot, int on_device);
+
+/* Full checkpoint: state plus the step-start reference frames, reference twist and time,
+ * packed into a caller buffer of dm_checkpoint_size() doubles (host or device). */
+size_t dm_checkpoint_size(const dm_sim* sim);
+dm_status dm_save_checkpoint(dm_sim* sim, double* buf, int on_device);
+dm_status dm_load_checkpoint(dm_sim* sim, const double* buf, int on_device);
+
+/* Simulation time [s]. */
+double dm_time(const dm_sim* sim);
+
+const char* dm_last_error(void);
+void dm_destroy(dm_sim* sim);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DMROD_H */

@@ -476,10 +476,13 @@ class StepInfo:
     history: list
 
 
-def newton_solve(sys, st, dt, kappa_bar, tol=1e-9, max_iter=50, q0=None, polish=0, line_search=False):
+def newton_solve(sys, st, dt, kappa_bar, tol=1e-9, max_iter=50, q0=None, polish=0, line_search=False,
+                 stag_tol=1e-6):
     """Newton's method on the residual.  Initial guess q_n unless q0 is given.
-    Stops when the 2-norm of the residual over free DOFs is <= tol; `polish` extra
-    iterations may follow (used to reach the rounding floor in tests).
+    Stops when the 2-norm of the residual over free DOFs is <= tol, or when the residual
+    was already <= stag_tol and the last iteration failed to halve it (the FP64 rounding
+    floor of a stiff rod can lie above tol); `polish` extra iterations may follow (used
+    to reach the rounding floor in tests).
     With line_search (the paper's optional globalisation), the Newton step is halved
     (at most 10 times) until the residual norm decreases."""
     free = ~sys.fixed
@@ -492,6 +495,8 @@ def newton_solve(sys, st, dt, kappa_bar, tol=1e-9, max_iter=50, q0=None, polish=
     while True:
         r = float(torch.linalg.norm(R[free]))
         hist.append(r)
+        if r > tol and len(hist) >= 2 and hist[-2] <= stag_tol and r > 0.5 * hist[-2] and extra == 0:
+            return q, StepInfo(it, r, True, hist)
         if r <= tol:
             if extra >= polish:
                 return q, StepInfo(it, r, True, hist)

@@ -1,0 +1,302 @@
+"""MI355X-native implicit Discrete Elastic Rods (DisMech, arXiv 2311.18126).
+
+Thin ctypes binding of libdmrod.so (include/dmrod.h).  The binding only marshals
+arguments: every part of the time step runs in the library's HIP kernels.  Importing
+this package never builds or falls back to anything; `lib()` raises if the shared
+library is missing or cannot be loaded.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int, c_size_t, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdmrod.so")
+
+DM_OK = 0
+DM_NOT_CONVERGED = 1
+DM_ERR_INVALID_ARG = -1
+DM_ERR_STATE = -2
+DM_ERR_HIP = -3
+DM_ERR_OOM = -4
+DM_ERR_SINGULAR = -5
+DM_ERR_UNSUPPORTED = -6
+
+
+class DmConfig(ctypes.Structure):
+    _fields_ = [("gravity", c_double * 3), ("newton_tol", c_double), ("stagnation_tol", c_double), ("max_iter", c_int),
+                ("line_search", c_int), ("floor_contact", c_int), ("floor_z", c_double),
+                ("delta", c_double), ("nu", c_double), ("mu", c_double), ("k_contact", c_double),
+                ("damping", c_double), ("device", c_int), ("stream", c_void_p), ("block_size", c_int)]
+
+
+class DmStats(ctypes.Structure):
+    _fields_ = [("steps_done", c_int), ("newton_iters", c_int), ("status", c_int), ("floor_steps", c_int),
+                ("residual", c_double)]
+
+
+_DP = POINTER(c_double)
+_IP = POINTER(c_int)
+_SIGS = {
+    "dm_config_default": (None, [POINTER(DmConfig)]),
+    "dm_create": (c_int, [POINTER(DmConfig), POINTER(c_void_p)]),
+    "dm_add_rod": (c_int, [c_void_p, c_int, _DP, c_double, c_double, c_double, c_double, _IP]),
+    "dm_add_joint": (c_int, [c_void_p, c_int, c_int, c_int, c_int]),
+    "dm_fix_nodes": (c_int, [c_void_p, c_int, _IP, c_int]),
+    "dm_fix_edges": (c_int, [c_void_p, c_int, _IP, c_int]),
+    "dm_set_natural_curvature": (c_int, [c_void_p, c_int, _DP]),
+    "dm_set_actuation_sine": (c_int, [c_void_p, c_int, c_double, c_double, c_double]),
+    "dm_set_external_load": (c_int, [c_void_p, c_int, _DP, _DP]),
+    "dm_finalize": (c_int, [c_void_p]),
+    "dm_step": (c_int, [c_void_p, c_double, c_int, POINTER(DmStats)]),
+    "dm_num_systems": (c_int, [c_void_p]),
+    "dm_rod_system": (c_int, [c_void_p, c_int]),
+    "dm_num_rods": (c_int, [c_void_p]),
+    "dm_rod_nodes": (c_int, [c_void_p, c_int]),
+    "dm_get_rod_state": (c_int, [c_void_p, c_int, _DP, _DP, _DP, _DP]),
+    "dm_set_rod_state": (c_int, [c_void_p, c_int, _DP, _DP, _DP, _DP]),
+    "dm_num_nodes": (c_int, [c_void_p]),
+    "dm_num_edges": (c_int, [c_void_p]),
+    "dm_node_index": (c_int, [c_void_p, c_int, c_int]),
+    "dm_edge_index": (c_int, [c_void_p, c_int, c_int]),
+    "dm_get_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
+    "dm_set_state": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int]),
+    "dm_checkpoint_size": (c_size_t, [c_void_p]),
+    "dm_save_checkpoint": (c_int, [c_void_p, c_void_p, c_int]),
+    "dm_load_checkpoint": (c_int, [c_void_p, c_void_p, c_int]),
+    "dm_time": (c_double, [c_void_p]),
+    "dm_last_error": (c_char_p, []),
+    "dm_destroy": (None, [c_void_p]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libdmrod.so (built by paper_2311_18126_amd.build); raise if it is not there."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2311_18126_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class DmError(RuntimeError):
+    def __init__(self, status, where):
+        msg = lib().dm_last_error().decode(errors="replace")
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+def _check(status, where, allow=(DM_OK,)):
+    if status not in allow:
+        raise DmError(status, where)
+    return status
+
+
+def _dp(a):
+    return a.ctypes.data_as(_DP)
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+class Sim:
+    """One dm_sim.  Build with add_rod / add_joint / ..., then finalize() and step()."""
+
+    def __init__(self, gravity=(0.0, 0.0, -9.81), newton_tol=1e-9, max_iter=50, line_search=False,
+                 floor=None, damping=0.0, device=0, stream=None, block_size=0, stagnation_tol=1e-6):
+        L = lib()
+        cfg = DmConfig()
+        L.dm_config_default(ctypes.byref(cfg))
+        for i in range(3):
+            cfg.gravity[i] = float(gravity[i])
+        cfg.newton_tol = float(newton_tol)
+        cfg.stagnation_tol = float(stagnation_tol)
+        cfg.max_iter = int(max_iter)
+        cfg.line_search = int(bool(line_search))
+        if floor is not None:
+            cfg.floor_contact = 1
+            cfg.floor_z = float(floor["z"])
+            cfg.delta = float(floor["delta"])
+            cfg.nu = float(floor["nu"])
+            cfg.mu = float(floor["mu"])
+            cfg.k_contact = float(floor["k_c"])
+        cfg.damping = float(damping)
+        cfg.device = int(device)
+        cfg.stream = stream
+        cfg.block_size = int(block_size)
+        h = c_void_p()
+        _check(L.dm_create(ctypes.byref(cfg), ctypes.byref(h)), "dm_create")
+        self._h = h
+        self.cfg = cfg
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- construction -------------------------------------------------------
+    def add_rod(self, x0, radius, E, poisson=0.5, density=1000.0):
+        x0 = _f64(x0)
+        rid = c_int()
+        _check(lib().dm_add_rod(self._h, x0.shape[0], _dp(x0), radius, E, poisson, density, ctypes.byref(rid)),
+               "dm_add_rod")
+        return rid.value
+
+    def add_joint(self, rod_a, node_a, rod_b, node_b):
+        _check(lib().dm_add_joint(self._h, rod_a, node_a, rod_b, node_b), "dm_add_joint")
+
+    def fix_nodes(self, rod, nodes):
+        a = np.ascontiguousarray(nodes, dtype=np.int32)
+        _check(lib().dm_fix_nodes(self._h, rod, a.ctypes.data_as(_IP), a.size), "dm_fix_nodes")
+
+    def fix_edges(self, rod, edges):
+        a = np.ascontiguousarray(edges, dtype=np.int32)
+        _check(lib().dm_fix_edges(self._h, rod, a.ctypes.data_as(_IP), a.size), "dm_fix_edges")
+
+    def set_natural_curvature(self, rod, kbar):
+        k = _f64(kbar)
+        _check(lib().dm_set_natural_curvature(self._h, rod, _dp(k)), "dm_set_natural_curvature")
+
+    def set_actuation_sine(self, rod, A, f, phi):
+        _check(lib().dm_set_actuation_sine(self._h, rod, A, f, phi), "dm_set_actuation_sine")
+
+    def set_external_load(self, rod, force=None, moment=None):
+        fp = _f64(force) if force is not None else None
+        mp = _f64(moment) if moment is not None else None
+        _check(lib().dm_set_external_load(self._h, rod, _dp(fp) if fp is not None else None,
+                                          _dp(mp) if mp is not None else None), "dm_set_external_load")
+
+    def finalize(self):
+        _check(lib().dm_finalize(self._h), "dm_finalize")
+
+    # -- stepping -----------------------------------------------------------
+    def step(self, dt, nsteps=1, allow_failure=False):
+        """Advance all systems; returns a structured numpy array of per-system statistics."""
+        n = lib().dm_num_systems(self._h)
+        st = (DmStats * max(n, 1))()
+        s = lib().dm_step(self._h, float(dt), int(nsteps), st)
+        if not allow_failure:
+            _check(s, "dm_step")
+        self.last_status = s
+        out = np.zeros(n, dtype=[("steps", np.int32), ("iters", np.int32), ("status", np.int32),
+                                 ("floor_steps", np.int32), ("residual", np.float64)])
+        for i in range(n):
+            out[i] = (st[i].steps_done, st[i].newton_iters, st[i].status, st[i].floor_steps, st[i].residual)
+        return out
+
+    # -- state --------------------------------------------------------------
+    @property
+    def num_systems(self):
+        return lib().dm_num_systems(self._h)
+
+    @property
+    def num_nodes(self):
+        return lib().dm_num_nodes(self._h)
+
+    @property
+    def num_edges(self):
+        return lib().dm_num_edges(self._h)
+
+    def rod_system(self, rod):
+        return lib().dm_rod_system(self._h, rod)
+
+    def rod_state(self, rod):
+        n = lib().dm_rod_nodes(self._h, rod)
+        x, v = np.zeros((n, 3)), np.zeros((n, 3))
+        th, om = np.zeros(n - 1), np.zeros(n - 1)
+        _check(lib().dm_get_rod_state(self._h, rod, _dp(x), _dp(th), _dp(v), _dp(om)), "dm_get_rod_state")
+        return x, th, v, om
+
+    def set_rod_state(self, rod, x=None, theta=None, v=None, theta_dot=None):
+        args = [(_dp(_f64(a)) if a is not None else None) for a in (x, theta, v, theta_dot)]
+        _check(lib().dm_set_rod_state(self._h, rod, *args), "dm_set_rod_state")
+
+    def state(self):
+        """Bulk state in the library's global numbering (host numpy arrays)."""
+        x, v = np.zeros((self.num_nodes, 3)), np.zeros((self.num_nodes, 3))
+        th, om = np.zeros(self.num_edges), np.zeros(self.num_edges)
+        _check(lib().dm_get_state(self._h, x.ctypes.data, th.ctypes.data, v.ctypes.data, om.ctypes.data, 0),
+               "dm_get_state")
+        return x, th, v, om
+
+    def state_torch(self, device="cuda"):
+        """Bulk state copied device-to-device into new torch tensors."""
+        import torch
+        x = torch.empty((self.num_nodes, 3), dtype=torch.float64, device=device)
+        v = torch.empty_like(x)
+        th = torch.empty(self.num_edges, dtype=torch.float64, device=device)
+        om = torch.empty_like(th)
+        _check(lib().dm_get_state(self._h, x.data_ptr(), th.data_ptr(), v.data_ptr(), om.data_ptr(), 1),
+               "dm_get_state")
+        return x, th, v, om
+
+    def node_index(self, rod, node):
+        return lib().dm_node_index(self._h, rod, node)
+
+    def edge_index(self, rod, edge):
+        return lib().dm_edge_index(self._h, rod, edge)
+
+    def checkpoint(self):
+        n = lib().dm_checkpoint_size(self._h)
+        buf = np.zeros(n)
+        _check(lib().dm_save_checkpoint(self._h, buf.ctypes.data, 0), "dm_save_checkpoint")
+        return buf
+
+    def restore(self, buf):
+        buf = _f64(buf)
+        _check(lib().dm_load_checkpoint(self._h, buf.ctypes.data, 0), "dm_load_checkpoint")
+
+    @property
+    def time(self):
+        return lib().dm_time(self._h)
+
+
+def sim_from_description(desc, **overrides):
+    """Build and finalize a Sim from a `workloads` description (marshalling only)."""
+    kw = dict(gravity=desc["gravity"], newton_tol=desc["tol"], max_iter=desc["max_iter"],
+              floor=desc.get("floor"), damping=desc.get("damping", 0.0),
+              line_search=desc.get("line_search", False))
+    kw.update(overrides)
+    sim = Sim(**kw)
+    for r in desc["rods"]:
+        rid = sim.add_rod(r["x0"], r["radius"], r["E"], r["poisson"], r["density"])
+        if r["fixed_nodes"]:
+            sim.fix_nodes(rid, r["fixed_nodes"])
+        if r["fixed_edges"]:
+            sim.fix_edges(rid, r["fixed_edges"])
+        if r.get("kbar") is not None:
+            sim.set_natural_curvature(rid, r["kbar"])
+        if r.get("actuation") is not None:
+            sim.set_actuation_sine(rid, *r["actuation"])
+        if r.get("force") is not None or r.get("moment") is not None:
+            sim.set_external_load(rid, r.get("force"), r.get("moment"))
+    for (ra, na, rb, nb) in desc["joints"]:
+        sim.add_joint(ra, na, rb, nb)
+    sim.finalize()
+    if "initial_tip_velocity" in desc:
+        for rid in range(len(desc["rods"])):
+            x, th, v, om = sim.rod_state(rid)
+            v[-1] = desc["initial_tip_velocity"]
+            sim.set_rod_state(rid, v=v)
+    return sim

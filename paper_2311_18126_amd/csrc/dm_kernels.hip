@@ -1,0 +1,679 @@
+// dm_kernels.hip -- the implicit DER time step on gfx950, FP64 throughout.
+//
+// One workgroup advances one system (a rod, or rods joined at a shared end node) for
+// `nsteps` backward-Euler steps (Eq. 14-15), each solved by Newton's method (Eq. 16).
+// Per Newton iteration:
+//   1. element evaluation, one lane per item: bend/twist stencils (Eq. 4-8, exact gradient
+//      and Hessian), stretch edges (Eq. 2-3), nodes (inertia, gravity, damping, floor
+//      contact Eq. 10-11 and friction Eq. 12-13);
+//   2. atomic-free gather assembly: one lane per chain node owns its four band rows and
+//      sums the contributions of the elements touching them; border rows are gathered into
+//      a small dense matrix in LDS;
+//   3. banded LU without pivoting: each arm is eliminated by one wavefront holding an 11x11
+//      window, one column per lane (lanes 0..10) plus the right-hand side (lane 11), with
+//      the pivot column broadcast by readlane; the arms' Schur complements meet in the dense
+//      border, solved with partial pivoting; then each arm back-substitutes;
+//   4. q <- q - alpha * delta, with optional step halving (line search).
+// After convergence the step is committed: velocity update, reference frames carried to
+// the new tangents by time-parallel transport, reference twist recorded for its branch.
+#include <hip/hip_runtime.h>
+#include "dm_layout.h"
+#include "dm_math.h"
+
+#define DM_STATUS_OK 0
+#define DM_STATUS_NOT_CONVERGED 1
+#define DM_STATUS_SINGULAR (-5)
+
+namespace {
+
+__device__ __forceinline__ v3 ld3(const double* a, int n, int i) { return mk3(a[i], a[n + i], a[2 * n + i]); }
+__device__ __forceinline__ void st3(double* a, int n, int i, v3 v) { a[i] = v.x; a[n + i] = v.y; a[2 * n + i] = v.z; }
+
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  long long b = __double_as_longlong(v);
+  int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), lane);
+  int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) s += red[i];
+    red[32] = s;
+  }
+  __syncthreads();
+  return red[32];
+}
+
+// ---------------------------------------------------------------------------
+// element evaluation
+// ---------------------------------------------------------------------------
+
+__device__ void eval_stencil(const DmStepArgs& A, int s, double t_end) {
+  const DmDev& D = A.d;
+  const int NS = D.n_st_tot, NE = D.n_edges_tot, NN = D.n_nodes_tot;
+  const int np = D.sn[s], nc = D.sn[NS + s], nn = D.sn[2 * NS + s];
+  const int ef = D.se[s], ee = D.se[NS + s];
+  const int sg = D.ssign[s];
+  const double sf = (sg & 1) ? -1.0 : 1.0, se = (sg & 2) ? -1.0 : 1.0;
+  double k1b = D.kbar[s], k2b = D.kbar[NS + s];
+  const double amp = D.act[s];
+  if (!isnan(amp)) {   // actuation: kappa1 = A sin(2 pi f t + phi), integrated over Vbar
+    k1b = amp * sin(6.283185307179586476925286766559 * D.act[NS + s] * t_end + D.act[2 * NS + s]) * D.Vbar[s];
+    k2b = 0.0;
+  }
+  double g[DM_ST_G], H[DM_ST_H];
+  stencil_eval(ld3(D.x, NN, np), ld3(D.x, NN, nc), ld3(D.x, NN, nn), sf * D.th[ef], se * D.th[ee],
+               sf * ld3(D.tref, NE, ef), ld3(D.d1ref, NE, ef), se * ld3(D.tref, NE, ee), ld3(D.d1ref, NE, ee),
+               D.bref[s], k1b, k2b, D.tbar[s], D.kbend[s], D.ktwist[s], sf, se, g, H);
+#pragma unroll
+  for (int a = 0; a < DM_ST_G; ++a) D.st_g[a * NS + s] = g[a];
+#pragma unroll
+  for (int k = 0; k < DM_ST_H; ++k) D.st_H[k * NS + s] = H[k];
+}
+
+// Stretch (Eq. 2-3): gradient EA (|e|/ebar - 1) t with respect to the edge vector and its
+// Hessian (EA/ebar) t t^T + EA (1/ebar - 1/|e|)(I - t t^T).
+__device__ void eval_edge(const DmStepArgs& A, int e) {
+  const DmDev& D = A.d;
+  const int NE = D.n_edges_tot, NN = D.n_nodes_tot;
+  v3 d = ld3(D.x, NN, D.en[NE + e]) - ld3(D.x, NN, D.en[e]);
+  double l = sqrt(dot(d, d));
+  v3 t = (1.0 / l) * d;
+  double EA = D.EA[e], eb = D.ebar[e];
+  double f = EA * (l / eb - 1.0);
+  double c1 = EA / eb, c2 = EA * (1.0 / eb - 1.0 / l);
+  double tt[3] = {t.x, t.y, t.z};
+  D.ed[0 * NE + e] = f * t.x;
+  D.ed[1 * NE + e] = f * t.y;
+  D.ed[2 * NE + e] = f * t.z;
+  int k = 3;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = i; j < 3; ++j) D.ed[(k++) * NE + e] = (c1 - c2) * tt[i] * tt[j] + (i == j ? c2 : 0.0);
+}
+
+__device__ __forceinline__ double edge_K(const DmDev& D, int NE, int e, int i, int j) {
+  const int a = i < j ? i : j, b = i < j ? j : i;
+  const int idx = (a == 0) ? b : (a == 1 ? 2 + b : 5);   // xx xy xz yy yz zz
+  return D.ed[(3 + idx) * NE + e];
+}
+
+// IMC floor energy profile (Eq. 10): first and second derivative in D, K1 = 15/delta,
+// quadratic branch extended below D = 0.
+__device__ __forceinline__ void contact_profile(double Dd, double C, double delta, double* e1, double* e2) {
+  const double K1 = 15.0 / delta;
+  if (Dd <= C - delta) { *e1 = -2.0 * (C - Dd); *e2 = 2.0; }
+  else if (Dd < C + delta) {
+    double z = K1 * (C - Dd);
+    double ez = exp(z);
+    double sp = log1p(ez) / K1;
+    double sig = ez / (1.0 + ez);
+    *e1 = -2.0 * sp * sig;
+    *e2 = 2.0 * sig * sig + 2.0 * sp * K1 * sig * (1.0 - sig);
+  } else { *e1 = 0.0; *e2 = 0.0; }
+}
+
+// gamma(|u|)/|u| of Eq. 12 as a function of s = |u|^2, and its derivative in s; the exact
+// limit series is used below s = 1e-8 / K2^2 so that u = 0 is smooth.
+__device__ __forceinline__ void friction_ratio(double s, double K2, double* g, double* dg) {
+  if (s < 1e-8 / (K2 * K2)) {
+    *g = 0.5 * K2 * (1.0 - K2 * K2 * s / 12.0);
+    *dg = -K2 * K2 * K2 / 24.0;
+  } else {
+    double r = sqrt(s);
+    double em = exp(-K2 * r);
+    double gam = 2.0 / (1.0 + em) - 1.0;
+    double gp = 2.0 * K2 * em / ((1.0 + em) * (1.0 + em));
+    *g = gam / r;
+    *dg = (gp * r - gam) / (2.0 * s * r);
+  }
+}
+
+// Node terms of the residual (Eq. 15) and Jacobian: inertia, gravity, constant load,
+// damping, floor contact (Eq. 10-11) and friction (Eq. 12-13).
+__device__ void eval_node(const DmStepArgs& A, int n) {
+  const DmDev& D = A.d;
+  const int NN = D.n_nodes_tot;
+  const double dt = A.dt, m = D.mass[n];
+  v3 x = ld3(D.x, NN, n), x0 = ld3(D.x0, NN, n), v = ld3(D.v, NN, n), F = ld3(D.force, NN, n);
+  const double im = m / (dt * dt);
+  double R[3], J[9];
+  double xa[3] = {x.x, x.y, x.z}, x0a[3] = {x0.x, x0.y, x0.z}, va[3] = {v.x, v.y, v.z}, Fa[3] = {F.x, F.y, F.z};
+  const double jd = im + A.damping * m / dt;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    R[c] = im * (xa[c] - x0a[c] - dt * va[c]) - m * A.g[c] - Fa[c] + A.damping * m * (xa[c] - x0a[c]) / dt;
+#pragma unroll
+    for (int c2 = 0; c2 < 3; ++c2) J[3 * c + c2] = (c == c2) ? jd : 0.0;
+  }
+  if (A.floor_on) {
+    double e1, e2;
+    contact_profile(x.z - A.floor_z, D.radius[n], A.delta, &e1, &e2);
+    const double Fn = -A.kc * e1, dFn = -A.kc * e2;     // normal force and d/dz
+    R[2] -= Fn;
+    J[8] -= dFn;
+    if (Fn != 0.0) {
+      const double K2 = 15.0 / A.nu;
+      double u0 = (x.x - x0.x) / dt, u1 = (x.y - x0.y) / dt;
+      double rg, dg;
+      friction_ratio(u0 * u0 + u1 * u1, K2, &rg, &dg);
+      const double aF = fabs(Fn), sF = Fn > 0.0 ? 1.0 : -1.0;
+      const double mu = A.mu;
+      // residual gets -F_fr = mu |Fn| ratio u
+      R[0] += mu * aF * rg * u0;
+      R[1] += mu * aF * rg * u1;
+      const double cc = mu * aF / dt;
+      J[0] += cc * (rg + 2.0 * dg * u0 * u0);
+      J[1] += cc * (2.0 * dg * u0 * u1);
+      J[3] += cc * (2.0 * dg * u1 * u0);
+      J[4] += cc * (rg + 2.0 * dg * u1 * u1);
+      J[2] += mu * sF * dFn * rg * u0;
+      J[5] += mu * sF * dFn * rg * u1;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) D.nd[c * NN + n] = R[c];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) D.nd[(3 + k) * NN + n] = J[k];
+}
+
+// ---------------------------------------------------------------------------
+// gather assembly
+// ---------------------------------------------------------------------------
+
+// Contributions of chain elements to chain row 4k + COMP; emit(rel, value) receives the
+// column as rel = column - 4k.  Returns the residual entry.
+template <int COMP, class Emit>
+__device__ __forceinline__ double row_contrib(const DmStepArgs& A, const DmChain& ch, int k, Emit& emit) {
+  const DmDev& D = A.d;
+  const int NS = D.n_st_tot, NE = D.n_edges_tot, NN = D.n_nodes_tot;
+  const int N = ch.n_nodes;
+  double Rr = 0.0;
+  if (COMP < 3) {
+    const int node = D.chain_node[ch.node_tab + k];
+    if (D.node_owner[node] == ch.global_id) {
+      Rr += D.nd[COMP * NN + node];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) emit(c, D.nd[(3 + 3 * COMP + c) * NN + node]);
+    }
+    if (k <= N - 2) {   // edge k: node k is its tail
+      const int e = D.chain_edge[ch.edge_tab + k];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) { double K = edge_K(D, NE, e, COMP, c); emit(c, K); emit(4 + c, -K); }
+      Rr -= D.ed[COMP * NE + e];
+    }
+    if (k >= 1) {       // edge k-1: node k is its head
+      const int e = D.chain_edge[ch.edge_tab + k - 1];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) { double K = edge_K(D, NE, e, COMP, c); emit(-4 + c, -K); emit(c, K); }
+      Rr += D.ed[COMP * NE + e];
+    }
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj) {
+      const int j = k + dj;
+      if (j >= 1 && j <= N - 2) {
+        const int s = ch.st_off + j - 1;
+        const int a = 4 * (1 - dj) + COMP;
+        Rr += D.st_g[a * NS + s];
+#pragma unroll
+        for (int b = 0; b < 11; ++b) emit(4 * (dj - 1) + b, D.st_H[hidx(a, b) * NS + s]);
+      }
+    }
+  } else {
+    const int e = D.chain_edge[ch.edge_tab + k];
+    const double I = D.Ith[e] / (A.dt * A.dt);
+    emit(3, I);
+    Rr += I * (D.th[e] - D.th0[e] - A.dt * D.om[e]) - D.moment[e];
+#pragma unroll
+    for (int dj = 0; dj <= 1; ++dj) {
+      const int j = k + dj;
+      if (j >= 1 && j <= N - 2) {
+        const int s = ch.st_off + j - 1;
+        const int a = dj == 0 ? 7 : 3;
+        Rr += D.st_g[a * NS + s];
+#pragma unroll
+        for (int b = 0; b < 11; ++b) emit(4 * (dj - 1) + b, D.st_H[hidx(a, b) * NS + s]);
+      }
+    }
+  }
+  return Rr;
+}
+
+template <int COMP>
+__device__ __forceinline__ double band_row(const DmStepArgs& A, const DmChain& ch, int k,
+                                           unsigned fixmask, unsigned bmask) {
+  const int r = 4 * k + COMP;
+  const bool rowb = (r >= ch.b_lo && r < ch.b_hi);
+  const bool rowfix = (fixmask >> (8 + COMP)) & 1u;
+  double acc[DM_NDIAG];
+#pragma unroll
+  for (int o = 0; o < DM_NDIAG; ++o) acc[o] = 0.0;
+  auto emit = [&](int rel, double v) {
+    const int idx = rel + 8;
+    const bool drop = ((fixmask >> idx) & 1u) || (rowb && ((bmask >> idx) & 1u));
+    acc[rel - COMP + 10] += drop ? 0.0 : v;
+  };
+  double Rr = row_contrib<COMP>(A, ch, k, emit);
+  if (rowfix) {
+#pragma unroll
+    for (int o = 0; o < DM_NDIAG; ++o) acc[o] = (o == 10) ? 1.0 : 0.0;
+    Rr = 0.0;
+  }
+  double* out = A.d.band + (size_t)(ch.dof_off + r) * DM_NDIAG;
+#pragma unroll
+  for (int o = 0; o < DM_NDIAG; ++o) out[o] = acc[o];
+  A.d.R[ch.dof_off + r] = Rr;
+  return (rowfix || rowb) ? 0.0 : Rr * Rr;
+}
+
+// Band rows of chain node k (4 rows; 3 for the last node).  Returns the squared residual of
+// its free, non-border rows.
+__device__ double band_node(const DmStepArgs& A, const DmChain& ch, int k) {
+  const DmDev& D = A.d;
+  const int n = 4 * ch.n_nodes - 1;
+  unsigned fixmask = 0u, bmask = 0u;
+#pragma unroll
+  for (int i = 0; i < 20; ++i) {
+    const int r = 4 * (k - 2) + i;
+    if (r >= 0 && r < n) {
+      fixmask |= (unsigned)D.cfix[ch.dof_off + r] << i;
+      bmask |= (unsigned)(r >= ch.b_lo && r < ch.b_hi) << i;
+    }
+  }
+  double s = band_row<0>(A, ch, k, fixmask, bmask);
+  s += band_row<1>(A, ch, k, fixmask, bmask);
+  s += band_row<2>(A, ch, k, fixmask, bmask);
+  if (k < ch.n_nodes - 1) s += band_row<3>(A, ch, k, fixmask, bmask);
+  return s;
+}
+
+// Dense border row b: pristine border-border entries of every chain touching it plus the
+// joint stencils; right-hand side in column nb.  Returns its squared residual if free.
+__device__ double border_row(const DmStepArgs& A, const DmSystem& S, int b, double* Bt, int ld) {
+  const DmDev& D = A.d;
+  const int NS = D.n_st_tot;
+  double* row = Bt + b * ld;
+  for (int j = 0; j <= S.nb; ++j) row[j] = 0.0;
+  if (D.bfix[S.bfix_off + b]) { row[b] = 1.0; return 0.0; }
+  double rhs = 0.0;
+  for (int q = 0; q < DM_MAX_BSRC; ++q) {
+    const int ci = D.bsrc[2 * (S.bsrc_off + b * DM_MAX_BSRC + q)];
+    if (ci < 0) break;
+    const int r = D.bsrc[2 * (S.bsrc_off + b * DM_MAX_BSRC + q) + 1];
+    const DmChain ch = D.chain[ci];
+    rhs += D.R[ch.dof_off + r];
+    const int k = r >> 2;
+    auto emit = [&](int rel, double v) {
+      const int col = 4 * k + rel;
+      if (col < ch.b_lo || col >= ch.b_hi) return;
+      const int bc = D.bmap[ch.bmap_off + col - ch.b_lo];
+      if (D.bfix[S.bfix_off + bc]) return;
+      row[bc] += v;
+    };
+    switch (r & 3) {
+      case 0: row_contrib<0>(A, ch, k, emit); break;
+      case 1: row_contrib<1>(A, ch, k, emit); break;
+      case 2: row_contrib<2>(A, ch, k, emit); break;
+      default: row_contrib<3>(A, ch, k, emit); break;
+    }
+  }
+  for (int js = 0; js < S.n_jst; ++js) {
+    const int* bj = D.bjst + S.bjst_off + js * 11;
+    const int s = S.jst0 + js;
+    for (int a = 0; a < 11; ++a) {
+      if (bj[a] != b) continue;
+      rhs += D.st_g[a * NS + s];
+      for (int c = 0; c < 11; ++c) {
+        const int bc = bj[c];
+        if (bc >= 0 && !D.bfix[S.bfix_off + bc]) row[bc] += D.st_H[hidx(a, c) * NS + s];
+      }
+    }
+  }
+  row[S.nb] = rhs;
+  return rhs * rhs;
+}
+
+// ---------------------------------------------------------------------------
+// banded elimination of one arm by one wavefront
+// ---------------------------------------------------------------------------
+
+struct ArmView {
+  const double* band; const double* R; double* fac;
+  int dof_off, n, first, dir, count, fac_off;
+  __device__ __forceinline__ int cd(int l) const { return first + dir * l; }
+  __device__ __forceinline__ double a(int l, int l2) const {
+    const int r = cd(l), r2 = cd(l2);
+    if (r < 0 || r >= n || r2 < 0 || r2 >= n) return 0.0;
+    const int o = r2 - r + DM_HALF_BAND;
+    if (o < 0 || o >= DM_NDIAG) return 0.0;
+    return band[(size_t)(dof_off + r) * DM_NDIAG + o];
+  }
+  __device__ __forceinline__ double rhs(int l) const { return l < count ? R[dof_off + cd(l)] : 0.0; }
+};
+
+// Eliminate window position k (k % 11 == T).  Lane s < 11 holds the column congruent to s
+// (mod 11) in register slots indexed by row mod 11; lane 11 holds the right-hand side.
+template <int T>
+__device__ __forceinline__ void elim_step(double (&w)[DM_WIN], int k, int lane, const ArmView& V, int& bad) {
+  const double piv = readlane_d(w[T], T);
+  if (!(fabs(piv) > 1e-300) || !isfinite(piv)) bad = 1;
+  const double inv = 1.0 / piv;
+  double cv[DM_WIN];
+#pragma unroll
+  for (int i = 1; i < DM_WIN; ++i) cv[i] = readlane_d(w[(T + i) % DM_WIN], T);
+  const double u = w[T];
+  double* rec = V.fac + (size_t)(V.fac_off + k) * DM_FAC;
+  if (lane < DM_WIN) {
+    const int j = (lane - T + DM_WIN) % DM_WIN;
+    rec[j] = (j == 0) ? inv : u;
+  } else if (lane == DM_WIN) {
+    rec[DM_WIN] = u;
+  }
+  const double us = u * inv;
+#pragma unroll
+  for (int i = 1; i < DM_WIN; ++i) w[(T + i) % DM_WIN] -= cv[i] * us;
+  if (lane == T) {          // this lane's column was the pivot column: load column k + 11
+#pragma unroll
+    for (int i = 1; i < DM_WIN; ++i) w[(T + i) % DM_WIN] = V.a(k + i, k + DM_WIN);
+    w[T] = V.a(k + DM_WIN, k + DM_WIN);
+  } else if (lane < DM_WIN) {   // load the entry of the new row k + 11
+    const int cs = k + 1 + ((lane - T - 1 + 2 * DM_WIN) % DM_WIN);
+    w[T] = V.a(k + DM_WIN, cs);
+  } else if (lane == DM_WIN) {
+    w[T] = V.rhs(k + DM_WIN);
+  }
+}
+
+#define DM_UNROLL11(M) M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10)
+
+__device__ void sweep_arm(const DmStepArgs& A, const DmArm& arm, double* delta_lds, int* bad_flag) {
+  const DmDev& D = A.d;
+  const DmChain ch = D.chain[arm.chain];
+  ArmView V{D.band, D.R, D.fac, ch.dof_off, 4 * ch.n_nodes - 1, arm.first, arm.dir, arm.count, arm.fac_off};
+  const int lane = threadIdx.x & 63;
+  double w[DM_WIN];
+#pragma unroll
+  for (int r = 0; r < DM_WIN; ++r)
+    w[r] = (lane < DM_WIN) ? V.a(r, lane) : (lane == DM_WIN ? V.rhs(r) : 0.0);
+  int bad = 0;
+  for (int k0 = 0; k0 < arm.count; k0 += DM_WIN) {
+#define DM_E(T) if (k0 + T < arm.count) elim_step<T>(w, k0 + T, lane, V, bad);
+    DM_UNROLL11(DM_E)
+#undef DM_E
+  }
+  // trailing (border) block of the window = this arm's Schur complement contribution
+  const int c0 = arm.count % DM_WIN, nt = arm.n_trail;
+  if (lane < DM_WIN) {
+    const int j = (lane - c0 + DM_WIN) % DM_WIN;
+    if (j < nt) {
+#pragma unroll
+      for (int q = 0; q < DM_WIN; ++q) {
+        const int i = (q - c0 + DM_WIN) % DM_WIN;
+        if (i < nt) delta_lds[i * 10 + j] = w[q];
+      }
+    }
+  } else if (lane == DM_WIN) {
+#pragma unroll
+    for (int q = 0; q < DM_WIN; ++q) {
+      const int i = (q - c0 + DM_WIN) % DM_WIN;
+      if (i < nt) delta_lds[100 + i] = w[q];
+    }
+  }
+  if (bad && lane == 0) *bad_flag = 1;
+}
+
+template <int T>
+__device__ __forceinline__ void back_step(double (&xv)[DM_WIN], int l, const ArmView& V, double* out, int lane) {
+  const double* f = V.fac + (size_t)(V.fac_off + l) * DM_FAC;
+  double s = f[DM_WIN];
+#pragma unroll
+  for (int j = 1; j < DM_WIN; ++j) s -= f[j] * xv[(T + j) % DM_WIN];
+  const double xl = s * f[0];
+  xv[T] = xl;
+  if (lane == 0) out[V.dof_off + V.cd(l)] = xl;
+}
+
+__device__ void backsub_arm(const DmStepArgs& A, const DmArm& arm, const double* xB) {
+  const DmDev& D = A.d;
+  const DmChain ch = D.chain[arm.chain];
+  ArmView V{D.band, D.R, D.fac, ch.dof_off, 4 * ch.n_nodes - 1, arm.first, arm.dir, arm.count, arm.fac_off};
+  const int lane = threadIdx.x & 63;
+  const int c0 = arm.count % DM_WIN;
+  double xv[DM_WIN];
+#pragma unroll
+  for (int q = 0; q < DM_WIN; ++q) {
+    const int i = (q - c0 + DM_WIN) % DM_WIN;
+    double val = 0.0;
+    if (i < arm.n_trail) val = xB[D.bmap[ch.bmap_off + V.cd(arm.count + i) - ch.b_lo]];
+    xv[q] = val;
+  }
+  if (arm.count == 0) return;
+  for (int lb = ((arm.count - 1) / DM_WIN) * DM_WIN; lb >= 0; lb -= DM_WIN) {
+#define DM_B(T) if (lb + (10 - T) < arm.count) back_step<10 - T>(xv, lb + (10 - T), V, D.delta, lane);
+    DM_UNROLL11(DM_B)
+#undef DM_B
+  }
+}
+
+// Dense border: add the arms' Schur contributions (fixed order), then Gaussian elimination
+// with partial pivoting and back substitution.  All threads take part.
+__device__ void border_solve(const DmStepArgs& A, const DmSystem& S, double* Bt, int ld,
+                             const double* deltas, double* xB, double* scal, int* bad_flag) {
+  const DmDev& D = A.d;
+  const int nb = S.nb, tid = threadIdx.x, nt = blockDim.x;
+  for (int a = 0; a < S.n_arms; ++a) {
+    const DmArm arm = D.arm[S.arm0 + a];
+    const DmChain ch = D.chain[arm.chain];
+    const double* dl = deltas + a * 110;
+    const int ntr = arm.n_trail;
+    for (int p = tid; p < ntr * (ntr + 1); p += nt) {
+      const int i = p / (ntr + 1), j = p % (ntr + 1);
+      const int bi = D.bmap[ch.bmap_off + (arm.first + arm.dir * (arm.count + i)) - ch.b_lo];
+      if (D.bfix[S.bfix_off + bi]) continue;
+      if (j < ntr) {
+        const int bj = D.bmap[ch.bmap_off + (arm.first + arm.dir * (arm.count + j)) - ch.b_lo];
+        if (!D.bfix[S.bfix_off + bj]) Bt[bi * ld + bj] += dl[i * 10 + j];
+      } else {
+        Bt[bi * ld + nb] += dl[100 + i];
+      }
+    }
+    __syncthreads();
+  }
+  for (int p = 0; p < nb; ++p) {
+    if (tid == 0) {
+      int im = p;
+      double vm = fabs(Bt[p * ld + p]);
+      for (int i = p + 1; i < nb; ++i) { double v = fabs(Bt[i * ld + p]); if (v > vm) { vm = v; im = i; } }
+      if (im != p)
+        for (int j = 0; j <= nb; ++j) { double t = Bt[p * ld + j]; Bt[p * ld + j] = Bt[im * ld + j]; Bt[im * ld + j] = t; }
+      if (!(vm > 1e-300) || !isfinite(vm)) *bad_flag = 1;
+      scal[0] = 1.0 / Bt[p * ld + p];
+    }
+    __syncthreads();
+    const int w = nb - p;   // columns p+1 .. nb
+    for (int q = tid; q < (nb - p - 1) * w; q += nt) {
+      const int i = p + 1 + q / w, j = p + 1 + q % w;
+      Bt[i * ld + j] -= Bt[i * ld + p] * scal[0] * Bt[p * ld + j];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    for (int i = nb - 1; i >= 0; --i) {
+      double s = Bt[i * ld + nb];
+      for (int j = i + 1; j < nb; ++j) s -= Bt[i * ld + j] * xB[j];
+      xB[i] = s / Bt[i * ld + i];
+    }
+  }
+  __syncthreads();
+}
+
+// q <- q - alpha delta over the system's nodes and edges.
+__device__ void apply_update(const DmStepArgs& A, const DmSystem& S, const double* xB, double alpha) {
+  const DmDev& D = A.d;
+  const int NN = D.n_nodes_tot;
+  for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x) {
+    const int n = S.node0 + i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int h = D.node_home[c * NN + n];
+      const double d = h >= 0 ? D.delta[h] : xB[-1 - h];
+      D.x[c * NN + n] -= alpha * d;
+    }
+  }
+  for (int i = threadIdx.x; i < S.n_edges; i += blockDim.x) {
+    const int e = S.edge0 + i;
+    const int h = D.edge_home[e];
+    const double d = h >= 0 ? D.delta[h] : xB[-1 - h];
+    D.th[e] -= alpha * d;
+  }
+}
+
+__device__ void rollback(const DmStepArgs& A, const DmSystem& S) {
+  const DmDev& D = A.d;
+  const int NN = D.n_nodes_tot;
+  for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) D.x[c * NN + S.node0 + i] = D.x0[c * NN + S.node0 + i];
+  for (int i = threadIdx.x; i < S.n_edges; i += blockDim.x) D.th[S.edge0 + i] = D.th0[S.edge0 + i];
+}
+
+// Velocity update (after Eq. 16) and the step-end reference frames.
+__device__ void commit(const DmStepArgs& A, const DmSystem& S) {
+  const DmDev& D = A.d;
+  const int NN = D.n_nodes_tot, NE = D.n_edges_tot, NS = D.n_st_tot;
+  for (int i = threadIdx.x; i < S.n_st; i += blockDim.x) {
+    const int s = S.st0 + i;
+    const int np = D.sn[s], nc = D.sn[NS + s], nn = D.sn[2 * NS + s];
+    const int ef = D.se[s], ee = D.se[NS + s];
+    const int sg = D.ssign[s];
+    const double sf = (sg & 1) ? -1.0 : 1.0, se = (sg & 2) ? -1.0 : 1.0;
+    v3 a = ld3(D.x, NN, nc) - ld3(D.x, NN, np), b = ld3(D.x, NN, nn) - ld3(D.x, NN, nc);
+    v3 tf = (1.0 / sqrt(dot(a, a))) * a, te = (1.0 / sqrt(dot(b, b))) * b;
+    v3 d1f = transport_perp(sf * ld3(D.tref, NE, ef), tf, ld3(D.d1ref, NE, ef));
+    v3 d1e = transport_perp(se * ld3(D.tref, NE, ee), te, ld3(D.d1ref, NE, ee));
+    D.bref[s] = ref_twist(tf, d1f, te, d1e, D.bref[s], false);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < S.n_edges; i += blockDim.x) {
+    const int e = S.edge0 + i;
+    v3 d = ld3(D.x, NN, D.en[NE + e]) - ld3(D.x, NN, D.en[e]);
+    v3 t = (1.0 / sqrt(dot(d, d))) * d;
+    v3 d1 = transport_perp(ld3(D.tref, NE, e), t, ld3(D.d1ref, NE, e));
+    st3(D.tref, NE, e, t);
+    st3(D.d1ref, NE, e, d1);
+    D.om[e] = (D.th[e] - D.th0[e]) / A.dt;
+    D.th0[e] = D.th[e];
+  }
+  for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x) {
+    const int n = S.node0 + i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      D.v[c * NN + n] = (D.x[c * NN + n] - D.x0[c * NN + n]) / A.dt;
+      D.x0[c * NN + n] = D.x[c * NN + n];
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace
+
+__global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs A) {
+  extern __shared__ double lds[];
+  const DmDev& D = A.d;
+  const int sid = D.order[blockIdx.x];
+  const DmSystem S = D.sys[sid];
+  const int ld = A.max_nb + 1;
+  double* Bt = lds;                                   // [max_nb][max_nb + 1]
+  double* deltas = Bt + A.max_nb * ld;                // [max_arms][110]
+  double* xB = deltas + A.max_arms * 110;             // [max_nb]
+  double* red = xB + A.max_nb;                        // [40]
+  int* flags = reinterpret_cast<int*>(red + 40);      // [4]
+  const int tid = threadIdx.x, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  if (tid == 0) flags[0] = 0;
+  int status = DM_STATUS_OK, iters = 0, steps = 0, floor_hits = 0;
+  double res = 0.0;
+  double t = D.time[sid];
+  __syncthreads();
+  for (int step = 0; step < A.nsteps; ++step) {
+    const double t_end = t + A.dt;
+    bool conv = false;
+    int newton = 0, halvings = 0;
+    double alpha = 1.0, res_prev = 0.0;
+    while (true) {
+      for (int i = tid; i < S.n_st; i += blockDim.x) eval_stencil(A, S.st0 + i, t_end);
+      for (int i = tid; i < S.n_edges; i += blockDim.x) eval_edge(A, S.edge0 + i);
+      for (int i = tid; i < S.n_nodes; i += blockDim.x) eval_node(A, S.node0 + i);
+      __syncthreads();
+      double r2 = 0.0;
+      for (int i = tid; i < S.chain_nodes; i += blockDim.x) {
+        int c = 0, k = i;
+        while (k >= D.chain[S.chain0 + c].n_nodes) { k -= D.chain[S.chain0 + c].n_nodes; ++c; }
+        r2 += band_node(A, D.chain[S.chain0 + c], k);
+      }
+      __syncthreads();
+      for (int b = tid; b < S.nb; b += blockDim.x) r2 += border_row(A, S, b, Bt, ld);
+      res = sqrt(block_sum(r2, red));
+      if (res > A.tol && newton > 0 && res_prev <= A.stag_tol && res > 0.5 * res_prev) {
+        conv = true;    // stagnation at the FP64 rounding floor of the residual
+        ++floor_hits;
+        break;
+      }
+      if (A.line_search && newton > 0 && res >= res_prev && halvings < 10) {
+        apply_update(A, S, xB, -0.5 * alpha);      // back off to half of the current step
+        alpha *= 0.5;
+        ++halvings;
+        __syncthreads();
+        continue;
+      }
+      if (res <= A.tol) { conv = true; break; }
+      if (newton >= A.max_iter || !isfinite(res)) break;
+      res_prev = res;
+      alpha = 1.0;
+      halvings = 0;
+      for (int a = wave; a < S.n_arms; a += nwaves) sweep_arm(A, D.arm[S.arm0 + a], deltas + a * 110, flags);
+      __syncthreads();
+      border_solve(A, S, Bt, ld, deltas, xB, red + 34, flags);
+      for (int a = wave; a < S.n_arms; a += nwaves) backsub_arm(A, D.arm[S.arm0 + a], xB);
+      __syncthreads();
+      if (flags[0]) break;
+      apply_update(A, S, xB, 1.0);
+      ++newton;
+      __syncthreads();
+    }
+    iters += newton;
+    if (!conv) {
+      status = flags[0] ? DM_STATUS_SINGULAR : DM_STATUS_NOT_CONVERGED;
+      rollback(A, S);
+      break;
+    }
+    commit(A, S);
+    t = t_end;
+    ++steps;
+  }
+  if (tid == 0) {
+    D.time[sid] = t;
+    D.s_steps[sid] = steps;
+    D.s_iters[sid] = iters;
+    D.s_status[sid] = status;
+    D.s_res[sid] = res;
+    D.s_floor[sid] = floor_hits;
+  }
+}
+
+extern "C" hipError_t dm_launch_step(const DmStepArgs* args, int block, size_t lds_bytes, hipStream_t stream) {
+  hipLaunchKernelGGL(dm_step_kernel, dim3(args->n_systems), dim3(block), lds_bytes, stream, *args);
+  return hipGetLastError();
+}

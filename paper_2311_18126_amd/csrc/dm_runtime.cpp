@@ -1,0 +1,894 @@
+// dm_runtime.cpp -- host runtime of libdmrod: rod/joint construction, topology and DOF
+// numbering, stencil tables, banded/border layouts, upload and launch (C ABI of dmrod.h).
+//
+// Host work happens once per finalize: joint merging, the rest quantities of every edge
+// and stencil, the initial reference frames, and the solver layout.  Every Newton
+// iteration and time step runs in dm_step_kernel on the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/dmrod.h"
+#include "dm_layout.h"
+#include "dm_math.h"
+
+extern "C" hipError_t dm_launch_step(const DmStepArgs* args, int block, size_t lds_bytes, hipStream_t stream);
+
+namespace {
+
+thread_local std::string g_err;
+
+dm_status fail(dm_status s, const std::string& msg) { g_err = msg; return s; }
+
+#define DM_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return fail(DM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct Rod {
+  int n = 0;
+  std::vector<double> x0;               // [n][3]
+  double h = 0, E = 0, nu = 0, rho = 0;
+  std::vector<double> kbar;             // [n-2][2], 1/m
+  bool has_kbar = false;
+  bool act = false;
+  double A = 0, f = 0, phi = 0;
+  std::vector<double> force;            // [n][3]
+  std::vector<double> moment;           // [n-1]
+  std::vector<char> nfix, efix;
+};
+
+template <class T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+};
+
+}  // namespace
+
+struct dm_sim {
+  dm_config cfg{};
+  bool finalized = false;
+  std::vector<Rod> rods;
+  std::vector<std::array<int, 4>> joints;
+  hipStream_t stream = nullptr;
+  // layout
+  int n_nodes = 0, n_edges = 0, n_st = 0, n_sys = 0, n_chains = 0, n_arms = 0, n_dof = 0;
+  int max_nb = 0, max_arms = 0, block = 0;
+  std::vector<int> rod_sys;
+  std::vector<std::vector<int>> rod_node, rod_edge;   // global ids per rod node / edge
+  std::vector<int> rod_st0;                            // global stencil id of rod node 1
+  std::vector<DmSystem> sys;
+  std::vector<double> h_Vbar, h_kbend, h_ktwist;       // needed for natural-curvature updates
+  std::vector<double> h_kbar, h_act, h_kappa_rest;
+  std::vector<void*> allocs;
+  DmDev dev{};
+  double time = 0.0;
+};
+
+namespace {
+
+template <class T>
+dm_status upload(dm_sim* s, const std::vector<T>& h, T** out) {
+  size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(T);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return fail(DM_ERR_OOM, "hipMalloc failed (" + std::to_string(bytes) + " bytes)");
+  s->allocs.push_back(p);
+  if (!h.empty()) DM_HIP(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  *out = static_cast<T*>(p);
+  return DM_OK;
+}
+
+template <class T>
+dm_status alloc(dm_sim* s, size_t n, T** out) {
+  size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return fail(DM_ERR_OOM, "hipMalloc failed (" + std::to_string(bytes) + " bytes)");
+  s->allocs.push_back(p);
+  DM_HIP(hipMemset(p, 0, bytes));
+  *out = static_cast<T*>(p);
+  return DM_OK;
+}
+
+bool finite_all(const double* a, size_t n) {
+  for (size_t i = 0; i < n; ++i) if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+struct UF {
+  std::vector<int> p;
+  explicit UF(int n) : p(n) { std::iota(p.begin(), p.end(), 0); }
+  int find(int i) { while (p[i] != i) { p[i] = p[p[i]]; i = p[i]; } return i; }
+  void join(int a, int b) { a = find(a); b = find(b); if (a != b) p[b] = a; }
+};
+
+// Initial reference directors of one rod: d1 of the first edge is z projected off its
+// tangent (x when the tangent is within 1e-6 of z), then space-parallel transport along the
+// rod, so that a rod's initial shape has zero reference twist.
+void initial_frames(const std::vector<v3>& t, std::vector<v3>& d1) {
+  d1.resize(t.size());
+  v3 z = mk3(0, 0, 1);
+  if (std::fabs(dot(t[0], z)) > 1.0 - 1e-6) z = mk3(1, 0, 0);
+  v3 d = z - dot(z, t[0]) * t[0];
+  d1[0] = (1.0 / std::sqrt(dot(d, d))) * d;
+  for (size_t j = 1; j < t.size(); ++j) d1[j] = transport_perp(t[j - 1], t[j], d1[j - 1]);
+}
+
+dm_status do_finalize(dm_sim* s) {
+  const int nr = (int)s->rods.size();
+  if (nr == 0) return fail(DM_ERR_STATE, "dm_finalize: no rods");
+  // ---- rod-node keys, joint merging, connected rod sets
+  std::vector<int> key0(nr + 1, 0);
+  for (int r = 0; r < nr; ++r) key0[r + 1] = key0[r] + s->rods[r].n;
+  UF nodes(key0[nr]), rodset(nr);
+  for (auto& j : s->joints) {
+    nodes.join(key0[j[0]] + j[1], key0[j[2]] + j[3]);
+    rodset.join(j[0], j[2]);
+  }
+  std::map<int, std::vector<int>> comp;
+  for (int r = 0; r < nr; ++r) comp[rodset.find(r)].push_back(r);
+  std::vector<std::vector<int>> groups;
+  for (auto& kv : comp) groups.push_back(kv.second);
+  std::sort(groups.begin(), groups.end(), [](const std::vector<int>& a, const std::vector<int>& b) { return a[0] < b[0]; });
+
+  s->rod_sys.assign(nr, -1);
+  s->rod_node.assign(nr, {});
+  s->rod_edge.assign(nr, {});
+  s->rod_st0.assign(nr, -1);
+  // host arrays
+  std::vector<double> X, mass, radius, force, Ith, ebar, EA, moment;
+  std::vector<int> en0, en1;
+  std::vector<int> sn0, sn1, sn2, sef, see, ssign, st_rod;
+  std::vector<double> Vbar, kbend, ktwist, kbar0, kbar1, tbar, act0, act1, act2, bref;
+  std::vector<char> nfix, efix;
+  std::vector<DmChain> chains;
+  std::vector<DmArm> arms;
+  std::vector<int> chain_node, chain_edge, bmap, bsrc, bjst, node_owner;
+  std::vector<unsigned char> bfix, cfix;
+  std::vector<DmSystem> systems;
+  std::vector<v3> tref, d1ref;
+  std::vector<int> node_home_c[3], edge_home;
+  int dof_total = 0, fac_total = 0;
+
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const std::vector<int>& rods = groups[gi];
+    DmSystem S{};
+    S.node0 = (int)mass.size();
+    S.edge0 = (int)ebar.size();
+    S.st0 = (int)Vbar.size();
+    S.chain0 = (int)chains.size();
+    S.arm0 = (int)arms.size();
+    // global node ids: first occurrence in rod order
+    std::map<int, int> gid;
+    for (int r : rods) {
+      s->rod_sys[r] = (int)gi;
+      for (int i = 0; i < s->rods[r].n; ++i) {
+        int k = nodes.find(key0[r] + i);
+        auto it = gid.find(k);
+        if (it == gid.end()) {
+          int g = (int)mass.size();
+          gid[k] = g;
+          const double* p = &s->rods[r].x0[3 * i];
+          X.push_back(p[0]); X.push_back(p[1]); X.push_back(p[2]);
+          mass.push_back(0.0); radius.push_back(0.0);
+          force.push_back(0.0); force.push_back(0.0); force.push_back(0.0);
+          nfix.push_back(0);
+          node_owner.push_back(-1);
+          s->rod_node[r].push_back(g);
+        } else {
+          s->rod_node[r].push_back(it->second);
+        }
+      }
+    }
+    // topology check: single rod, or every rod has exactly one end at a single shared node
+    std::map<int, int> mult;
+    for (int r : rods) for (int g : s->rod_node[r]) mult[g]++;
+    std::vector<int> shared;
+    for (auto& kv : mult) if (kv.second > 1) shared.push_back(kv.first);
+    int hub = -1;
+    if (rods.size() == 1) {
+      if (!shared.empty()) return fail(DM_ERR_UNSUPPORTED, "rod " + std::to_string(rods[0]) + " is joined to itself");
+    } else {
+      if (shared.size() != 1) return fail(DM_ERR_UNSUPPORTED, "joined rods must meet at exactly one shared node");
+      if (rods.size() > DM_MAX_CHAINS) return fail(DM_ERR_UNSUPPORTED, "more than 8 rods at one joint");
+      hub = shared[0];
+      for (int r : rods) {
+        const auto& rn = s->rod_node[r];
+        int ends = (rn.front() == hub) + (rn.back() == hub);
+        int inner = 0;
+        for (size_t i = 1; i + 1 < rn.size(); ++i) inner += (rn[i] == hub);
+        if (ends != 1 || inner != 0)
+          return fail(DM_ERR_UNSUPPORTED, "joint node must be an end node of every joined rod (rod " + std::to_string(r) + ")");
+      }
+    }
+    // edges, masses, rest lengths
+    for (int r : rods) {
+      const Rod& R = s->rods[r];
+      const double Ar = M_PI * R.h * R.h;
+      for (int j = 0; j + 1 < R.n; ++j) {
+        int a = s->rod_node[r][j], b = s->rod_node[r][j + 1];
+        v3 pa = mk3(X[3 * a], X[3 * a + 1], X[3 * a + 2]), pb = mk3(X[3 * b], X[3 * b + 1], X[3 * b + 2]);
+        v3 d = pb - pa;
+        double L0 = std::sqrt(dot(d, d));
+        if (!(L0 > 0.0)) return fail(DM_ERR_INVALID_ARG, "rod " + std::to_string(r) + " has a zero-length edge");
+        s->rod_edge[r].push_back((int)ebar.size());
+        en0.push_back(a); en1.push_back(b);
+        ebar.push_back(L0);
+        EA.push_back(R.E * Ar);
+        Ith.push_back(R.rho * (M_PI * std::pow(R.h, 4) / 2.0) * L0);
+        moment.push_back(R.moment.empty() ? 0.0 : R.moment[j]);
+        efix.push_back(R.efix.empty() ? 0 : R.efix[j]);
+        mass[a] += 0.5 * R.rho * Ar * L0;
+        mass[b] += 0.5 * R.rho * Ar * L0;
+        radius[a] = std::max(radius[a], R.h);
+        radius[b] = std::max(radius[b], R.h);
+        tref.push_back((1.0 / L0) * d);
+      }
+      for (int i = 0; i < R.n; ++i) {
+        int g = s->rod_node[r][i];
+        if (!R.force.empty()) for (int c = 0; c < 3; ++c) force[3 * g + c] += R.force[3 * i + c];
+        if (!R.nfix.empty() && R.nfix[i]) nfix[g] = 1;
+      }
+      // initial frames of this rod
+      std::vector<v3> t(s->rod_edge[r].size()), d1;
+      for (size_t j = 0; j < t.size(); ++j) t[j] = tref[s->rod_edge[r][j]];
+      initial_frames(t, d1);
+      d1ref.resize(tref.size());
+      for (size_t j = 0; j < t.size(); ++j) d1ref[s->rod_edge[r][j]] = d1[j];
+    }
+    // stencils: rod-interior (chain) stencils, then pairs of edges at the joint
+    auto push_st = [&](int p, int c, int n, int f, int e, int sg, int rf, int re, int rodid) {
+      sn0.push_back(p); sn1.push_back(c); sn2.push_back(n); sef.push_back(f); see.push_back(e); ssign.push_back(sg);
+      st_rod.push_back(rodid);
+      double V = 0.5 * (ebar[f] + ebar[e]);
+      const Rod& A = s->rods[rf];
+      const Rod& B = s->rods[re];
+      double EIa = A.E * M_PI * std::pow(A.h, 4) / 4.0, EIb = B.E * M_PI * std::pow(B.h, 4) / 4.0;
+      double GJa = A.E / (2.0 * (1.0 + A.nu)) * M_PI * std::pow(A.h, 4) / 2.0;
+      double GJb = B.E / (2.0 * (1.0 + B.nu)) * M_PI * std::pow(B.h, 4) / 2.0;
+      Vbar.push_back(V);
+      kbend.push_back(0.5 * (EIa + EIb) / V);
+      ktwist.push_back(0.5 * (GJa + GJb) / V);
+      // rest strains of the initial shape (theta = 0), frames in the stencil's orientation
+      double sf = (sg & 1) ? -1.0 : 1.0, se = (sg & 2) ? -1.0 : 1.0;
+      double k1, k2, b;
+      stencil_strains(sf * tref[f], d1ref[f], 0.0, se * tref[e], d1ref[e], 0.0, 0.0, true, &k1, &k2, &b);
+      bref.push_back(b);
+      s->h_kappa_rest.push_back(k1);
+      s->h_kappa_rest.push_back(k2);
+      tbar.push_back(rodid >= 0 ? 0.0 : b);
+      kbar0.push_back(k1); kbar1.push_back(k2);
+      act0.push_back(NAN); act1.push_back(0.0); act2.push_back(0.0);
+    };
+    for (int r : rods) {
+      const Rod& R = s->rods[r];
+      s->rod_st0[r] = (int)Vbar.size();
+      for (int i = 1; i + 1 < R.n; ++i) {
+        push_st(s->rod_node[r][i - 1], s->rod_node[r][i], s->rod_node[r][i + 1], s->rod_edge[r][i - 1],
+                s->rod_edge[r][i], 0, r, r, r);
+        int st = (int)Vbar.size() - 1;
+        if (R.has_kbar) {
+          kbar0[st] = R.kbar[2 * (i - 1)] * Vbar[st];
+          kbar1[st] = R.kbar[2 * (i - 1) + 1] * Vbar[st];
+        }
+        if (R.act) { act0[st] = R.A; act1[st] = R.f; act2[st] = R.phi; }
+      }
+    }
+    S.jst0 = (int)Vbar.size();
+    std::vector<int> edge_rod(ebar.size(), -1);
+    for (int r : rods) for (int e : s->rod_edge[r]) edge_rod[e] = r;
+    if (hub >= 0) {
+      std::vector<std::pair<int, int>> inc;   // (edge, +1 leaves hub / -1 enters hub), sorted by edge
+      for (int r : rods) {
+        const auto& rn = s->rod_node[r];
+        if (rn.front() == hub) inc.push_back({s->rod_edge[r].front(), +1});
+        else inc.push_back({s->rod_edge[r].back(), -1});
+      }
+      std::sort(inc.begin(), inc.end());
+      for (size_t p = 0; p < inc.size(); ++p)
+        for (size_t q = p + 1; q < inc.size(); ++q) {
+          int ja = inc[p].first, da = inc[p].second, jb = inc[q].first, db = inc[q].second;
+          int f, e, sfr = 0, ser = 0;
+          if (da == -1 && db == +1) { f = ja; e = jb; }
+          else if (db == -1 && da == +1) { f = jb; e = ja; }
+          else if (da == +1 && db == +1) { f = ja; e = jb; sfr = 1; }
+          else { f = ja; e = jb; ser = 1; }
+          int np = sfr ? en1[f] : en0[f];
+          int nn = ser ? en0[e] : en1[e];
+          push_st(np, hub, nn, f, e, sfr | (ser << 1), edge_rod[f], edge_rod[e], -1);
+        }
+    }
+    S.n_jst = (int)Vbar.size() - S.jst0;
+    S.n_nodes = (int)mass.size() - S.node0;
+    S.n_edges = (int)ebar.size() - S.edge0;
+    S.n_st = (int)Vbar.size() - S.st0;
+    // ---- chains, border, arms
+    S.n_chains = (int)rods.size();
+    S.nb = (hub >= 0) ? 3 + 4 * (int)rods.size() : 0;
+    std::vector<std::vector<std::pair<int, int>>> src;   // border index -> (chain, dof)
+    int chain_nodes = 0;
+    for (size_t a = 0; a < rods.size(); ++a) {
+      int r = rods[a];
+      const Rod& R = s->rods[r];
+      DmChain C{};
+      C.n_nodes = R.n;
+      C.node_tab = (int)chain_node.size();
+      C.edge_tab = (int)chain_edge.size();
+      C.st_off = s->rod_st0[r];
+      C.dof_off = dof_total;
+      C.global_id = (int)chains.size();
+      for (int g : s->rod_node[r]) chain_node.push_back(g);
+      for (int e : s->rod_edge[r]) chain_edge.push_back(e);
+      const int n = 4 * R.n - 1;
+      C.bmap_off = (int)bmap.size();
+      std::vector<DmArm> ca;
+      if (hub < 0) {
+        if (n <= 10) {
+          C.b_lo = 0; C.b_hi = n;
+        } else {
+          int m = (n - 10) / 2;
+          C.b_lo = m; C.b_hi = m + 10;
+          if (m > 0) ca.push_back(DmArm{C.global_id, +1, 0, m, 10, 0});
+          if (n - m - 10 > 0) ca.push_back(DmArm{C.global_id, -1, n - 1, n - m - 10, 10, 0});
+        }
+        S.nb = C.b_hi - C.b_lo;
+        src.assign(S.nb, {});
+        for (int i = C.b_lo; i < C.b_hi; ++i) { bmap.push_back(i - C.b_lo); src[i - C.b_lo].push_back({C.global_id, i}); }
+      } else {
+        bool at_start = s->rod_node[r].front() == hub;
+        if (src.empty()) src.assign(S.nb, {});
+        const int base = 3 + 4 * (int)a;
+        int map7[7];
+        if (at_start) {
+          C.b_lo = 0; C.b_hi = std::min(7, n);
+          map7[0] = 0; map7[1] = 1; map7[2] = 2; map7[3] = base; map7[4] = base + 1; map7[5] = base + 2; map7[6] = base + 3;
+          if (n - 7 > 0) ca.push_back(DmArm{C.global_id, -1, n - 1, n - 7, 7, 0});
+          else if (n < 7) return fail(DM_ERR_UNSUPPORTED, "joined rod too short");
+        } else {
+          C.b_lo = n - 7; C.b_hi = n;
+          // chain DOFs n-7..n-1: x_{N-2} (3), theta_{N-2}, x_{N-1} = hub (3)
+          map7[0] = base + 1; map7[1] = base + 2; map7[2] = base + 3; map7[3] = base; map7[4] = 0; map7[5] = 1; map7[6] = 2;
+          if (n - 7 > 0) ca.push_back(DmArm{C.global_id, +1, 0, n - 7, 7, 0});
+        }
+        for (int i = 0; i < C.b_hi - C.b_lo; ++i) {
+          bmap.push_back(map7[i]);
+          src[map7[i]].push_back({C.global_id, C.b_lo + i});
+        }
+      }
+      for (auto& A : ca) {
+        A.fac_off = fac_total;
+        fac_total += A.count;
+        arms.push_back(A);
+      }
+      // clamps per chain DOF
+      for (int k = 0; k < R.n; ++k) {
+        int g = s->rod_node[r][k];
+        for (int c = 0; c < 3; ++c) cfix.push_back(nfix[g]);
+        if (k + 1 < R.n) cfix.push_back(efix[s->rod_edge[r][k]]);
+      }
+      for (int g : s->rod_node[r]) if (node_owner[g] < 0) node_owner[g] = C.global_id;
+      chains.push_back(C);
+      dof_total += n;
+      chain_nodes += R.n;
+    }
+    S.n_arms = (int)arms.size() - S.arm0;
+    S.chain_nodes = chain_nodes;
+    S.n_dof = dof_total - chains[S.chain0].dof_off;
+    S.bsrc_off = (int)bsrc.size() / 2;   // in units of (chain, dof) slots
+    for (int b = 0; b < S.nb; ++b) {
+      if ((int)src[b].size() > DM_MAX_BSRC) return fail(DM_ERR_UNSUPPORTED, "border source table overflow");
+      for (int q = 0; q < DM_MAX_BSRC; ++q) {
+        if (q < (int)src[b].size()) { bsrc.push_back(src[b][q].first); bsrc.push_back(src[b][q].second); }
+        else { bsrc.push_back(-1); bsrc.push_back(-1); }
+      }
+    }
+    S.bfix_off = (int)bfix.size();
+    for (int b = 0; b < S.nb; ++b) {
+      auto pr = src[b][0];
+      const DmChain& C = chains[pr.first];
+      bfix.push_back(cfix[C.dof_off + pr.second]);
+    }
+    // joint stencils: border index of each local DOF
+    S.bjst_off = (int)bjst.size();
+    for (int js = 0; js < S.n_jst; ++js) {
+      int st = S.jst0 + js;
+      auto nodeb = [&](int g, int c) -> int {
+        if (g == hub) return c;
+        for (int a = 0; a < S.n_chains; ++a) {
+          const DmChain& C = chains[S.chain0 + a];
+          for (int i = C.b_lo; i < C.b_hi; ++i) {
+            int k = i >> 2, cc = i & 3;
+            if (cc == c && chain_node[C.node_tab + k] == g) return bmap[C.bmap_off + i - C.b_lo];
+          }
+        }
+        return -1;
+      };
+      auto edgeb = [&](int e) -> int {
+        for (int a = 0; a < S.n_chains; ++a) {
+          const DmChain& C = chains[S.chain0 + a];
+          for (int i = C.b_lo; i < C.b_hi; ++i)
+            if ((i & 3) == 3 && chain_edge[C.edge_tab + (i >> 2)] == e) return bmap[C.bmap_off + i - C.b_lo];
+        }
+        return -1;
+      };
+      int loc[11];
+      for (int c = 0; c < 3; ++c) { loc[c] = nodeb(sn0[st], c); loc[4 + c] = nodeb(sn1[st], c); loc[8 + c] = nodeb(sn2[st], c); }
+      loc[3] = edgeb(sef[st]);
+      loc[7] = edgeb(see[st]);
+      for (int i = 0; i < 11; ++i) {
+        if (loc[i] < 0) return fail(DM_ERR_UNSUPPORTED, "joint stencil DOF outside the joint border");
+        bjst.push_back(loc[i]);
+      }
+    }
+    s->max_nb = std::max(s->max_nb, S.nb);
+    s->max_arms = std::max(s->max_arms, S.n_arms);
+    systems.push_back(S);
+  }
+  // ---- homes of every DOF (delta index or border)
+  const int NN = (int)mass.size(), NE = (int)ebar.size();
+  for (int c = 0; c < 3; ++c) node_home_c[c].assign(NN, 0);
+  edge_home.assign(NE, 0);
+  for (const DmSystem& S : systems)
+    for (int a = 0; a < S.n_chains; ++a) {
+      const DmChain& C = chains[S.chain0 + a];
+      for (int k = 0; k < C.n_nodes; ++k) {
+        for (int c = 0; c < 4; ++c) {
+          int r = 4 * k + c;
+          if (c == 3 && k == C.n_nodes - 1) break;
+          int home = (r >= C.b_lo && r < C.b_hi) ? -1 - bmap[C.bmap_off + r - C.b_lo] : C.dof_off + r;
+          if (c < 3) node_home_c[c][chain_node[C.node_tab + k]] = home;
+          else edge_home[chain_edge[C.edge_tab + k]] = home;
+        }
+      }
+    }
+  // launch order: largest systems first
+  std::vector<int> order(systems.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return systems[a].n_dof > systems[b].n_dof; });
+
+  s->n_nodes = NN; s->n_edges = NE; s->n_st = (int)Vbar.size();
+  s->n_sys = (int)systems.size(); s->n_chains = (int)chains.size(); s->n_arms = (int)arms.size(); s->n_dof = dof_total;
+  s->sys = systems;
+  s->h_Vbar = Vbar; s->h_kbend = kbend; s->h_ktwist = ktwist;
+  s->h_kbar.resize(2 * s->n_st); s->h_act.resize(3 * s->n_st);
+  for (int i = 0; i < s->n_st; ++i) {
+    s->h_kbar[i] = kbar0[i]; s->h_kbar[s->n_st + i] = kbar1[i];
+    s->h_act[i] = act0[i]; s->h_act[s->n_st + i] = act1[i]; s->h_act[2 * s->n_st + i] = act2[i];
+  }
+  // ---- SoA packing and upload
+  auto soa3 = [](const std::vector<double>& aos) {
+    size_t n = aos.size() / 3;
+    std::vector<double> o(aos.size());
+    for (size_t i = 0; i < n; ++i) for (int c = 0; c < 3; ++c) o[c * n + i] = aos[3 * i + c];
+    return o;
+  };
+  auto soav = [](const std::vector<v3>& a) {
+    size_t n = a.size();
+    std::vector<double> o(3 * n);
+    for (size_t i = 0; i < n; ++i) { o[i] = a[i].x; o[n + i] = a[i].y; o[2 * n + i] = a[i].z; }
+    return o;
+  };
+  std::vector<int> en(2 * NE), sn(3 * s->n_st), se(2 * s->n_st), nh(3 * NN);
+  for (int e = 0; e < NE; ++e) { en[e] = en0[e]; en[NE + e] = en1[e]; }
+  for (int i = 0; i < s->n_st; ++i) {
+    sn[i] = sn0[i]; sn[s->n_st + i] = sn1[i]; sn[2 * s->n_st + i] = sn2[i];
+    se[i] = sef[i]; se[s->n_st + i] = see[i];
+  }
+  for (int c = 0; c < 3; ++c) for (int n = 0; n < NN; ++n) nh[c * NN + n] = node_home_c[c][n];
+  DmDev& D = s->dev;
+  dm_status st;
+  auto up = [&](const auto& vec, auto& field) -> dm_status {
+    using T = typename std::remove_reference_t<decltype(vec)>::value_type;
+    T* p = nullptr;
+    dm_status r = upload(s, vec, &p);
+    field = p;
+    return r;
+  };
+#define UP(vec, field) if ((st = up(vec, D.field)) != DM_OK) return st;
+  UP(systems, sys) UP(chains, chain) UP(arms, arm) UP(order, order) UP(chain_node, chain_node) UP(chain_edge, chain_edge)
+  UP(bmap, bmap) UP(bsrc, bsrc) UP(bjst, bjst) UP(bfix, bfix) UP(cfix, cfix)
+  UP(mass, mass) UP(radius, radius)
+  std::vector<double> forceS = soa3(force);
+  UP(forceS, force) UP(node_owner, node_owner) UP(nh, node_home)
+  UP(en, en) UP(ebar, ebar) UP(EA, EA) UP(Ith, Ith) UP(moment, moment) UP(edge_home, edge_home)
+  UP(sn, sn) UP(se, se) UP(ssign, ssign) UP(Vbar, Vbar) UP(kbend, kbend) UP(ktwist, ktwist)
+  UP(s->h_kbar, kbar) UP(tbar, tbar) UP(s->h_act, act)
+  std::vector<double> XS = soa3(X), trefS = soav(tref), d1S = soav(d1ref);
+  UP(XS, x) UP(XS, x0) UP(trefS, tref) UP(d1S, d1ref) UP(bref, bref)
+#undef UP
+  if ((st = alloc(s, 3 * (size_t)NN, &D.v)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)NE, &D.th)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)NE, &D.th0)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)NE, &D.om)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)s->n_sys, &D.time)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)DM_ST_G * s->n_st, &D.st_g)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)DM_ST_H * s->n_st, &D.st_H)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)DM_ED * NE, &D.ed)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)DM_ND * NN, &D.nd)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)DM_NDIAG * dof_total, &D.band)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)dof_total, &D.R)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)DM_FAC * std::max(fac_total, 1), &D.fac)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)dof_total, &D.delta)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)s->n_sys, &D.s_steps)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)s->n_sys, &D.s_iters)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)s->n_sys, &D.s_status)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)s->n_sys, &D.s_res)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)s->n_sys, &D.s_floor)) != DM_OK) return st;
+  D.n_nodes_tot = NN; D.n_edges_tot = NE; D.n_st_tot = s->n_st;
+  // natural curvature and actuation may be set again later; keep a copy of stencil->rod
+  s->finalized = true;
+  int blk = s->cfg.block_size;
+  if (blk <= 0) {
+    blk = 128;
+    while (blk < 64 * s->max_arms && blk < 1024) blk *= 2;
+    if (s->max_arms > 2) blk = std::max(blk, 512);
+  }
+  s->block = blk;
+  return DM_OK;
+}
+
+dm_status check_rod(const dm_sim* s, int rod) {
+  if (!s) return fail(DM_ERR_INVALID_ARG, "null sim");
+  if (rod < 0 || rod >= (int)s->rods.size()) return fail(DM_ERR_INVALID_ARG, "rod index out of range");
+  return DM_OK;
+}
+
+dm_status upload_kbar(dm_sim* s) {
+  DM_HIP(hipMemcpy((void*)s->dev.kbar, s->h_kbar.data(), s->h_kbar.size() * sizeof(double), hipMemcpyHostToDevice));
+  DM_HIP(hipMemcpy((void*)s->dev.act, s->h_act.data(), s->h_act.size() * sizeof(double), hipMemcpyHostToDevice));
+  return DM_OK;
+}
+
+size_t state_doubles(const dm_sim* s) { return 3 * (size_t)s->n_nodes * 3 + 3 * (size_t)s->n_edges + 6 * (size_t)s->n_edges + s->n_st + s->n_sys; }
+
+}  // namespace
+
+extern "C" {
+
+void dm_config_default(dm_config* c) {
+  if (!c) return;
+  std::memset(c, 0, sizeof(*c));
+  c->gravity[2] = -9.81;
+  c->newton_tol = 1e-9;
+  c->stagnation_tol = 1e-6;
+  c->max_iter = 50;
+  c->delta = 5e-4;
+  c->nu = 1e-3;
+  c->mu = 0.0;
+  c->k_contact = 0.0;
+}
+
+dm_status dm_create(const dm_config* cfg, dm_sim** out) {
+  if (!cfg || !out) return fail(DM_ERR_INVALID_ARG, "dm_create: null argument");
+  if (!(cfg->newton_tol >= 0.0) || !(cfg->stagnation_tol >= 0.0) || cfg->max_iter < 1) return fail(DM_ERR_INVALID_ARG, "dm_create: bad Newton settings");
+  if (cfg->block_size != 0 && (cfg->block_size < 64 || cfg->block_size > 512 || cfg->block_size % 64))
+    return fail(DM_ERR_INVALID_ARG, "dm_create: block_size must be 0 or a multiple of 64 in [64, 512]");
+  if (cfg->floor_contact && (!(cfg->delta > 0) || !(cfg->nu > 0) || !(cfg->k_contact >= 0) || !(cfg->mu >= 0)))
+    return fail(DM_ERR_INVALID_ARG, "dm_create: bad contact parameters");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(DM_ERR_HIP, "dm_create: no HIP device");
+  if (cfg->device < 0 || cfg->device >= ndev) return fail(DM_ERR_INVALID_ARG, "dm_create: device out of range");
+  DM_HIP(hipSetDevice(cfg->device));
+  dm_sim* s = new dm_sim();
+  s->cfg = *cfg;
+  s->stream = static_cast<hipStream_t>(cfg->stream);
+  *out = s;
+  return DM_OK;
+}
+
+dm_status dm_add_rod(dm_sim* s, int n, const double* x0, double h, double E, double nu, double rho, int* rod_id) {
+  if (!s || !x0) return fail(DM_ERR_INVALID_ARG, "dm_add_rod: null argument");
+  if (s->finalized) return fail(DM_ERR_STATE, "dm_add_rod after dm_finalize");
+  if (n < 2) return fail(DM_ERR_INVALID_ARG, "dm_add_rod: need at least 2 nodes");
+  if (!(h > 0) || !(E > 0) || !(rho > 0) || !(nu > -1.0) || !finite_all(x0, 3 * (size_t)n))
+    return fail(DM_ERR_INVALID_ARG, "dm_add_rod: non-positive or non-finite parameter");
+  Rod r;
+  r.n = n; r.x0.assign(x0, x0 + 3 * n); r.h = h; r.E = E; r.nu = nu; r.rho = rho;
+  r.nfix.assign(n, 0); r.efix.assign(n - 1, 0);
+  s->rods.push_back(std::move(r));
+  if (rod_id) *rod_id = (int)s->rods.size() - 1;
+  return DM_OK;
+}
+
+dm_status dm_add_joint(dm_sim* s, int ra, int na, int rb, int nb) {
+  if (!s) return fail(DM_ERR_INVALID_ARG, "null sim");
+  if (s->finalized) return fail(DM_ERR_STATE, "dm_add_joint after dm_finalize");
+  dm_status st;
+  if ((st = check_rod(s, ra)) != DM_OK || (st = check_rod(s, rb)) != DM_OK) return st;
+  if (na < 0 || na >= s->rods[ra].n || nb < 0 || nb >= s->rods[rb].n) return fail(DM_ERR_INVALID_ARG, "dm_add_joint: node index out of range");
+  if (ra == rb) return fail(DM_ERR_UNSUPPORTED, "dm_add_joint: a rod joined to itself");
+  s->joints.push_back({ra, na, rb, nb});
+  return DM_OK;
+}
+
+dm_status dm_fix_nodes(dm_sim* s, int rod, const int* nodes, int n) {
+  dm_status st;
+  if ((st = check_rod(s, rod)) != DM_OK) return st;
+  if (s->finalized) return fail(DM_ERR_STATE, "dm_fix_nodes after dm_finalize");
+  if (n > 0 && !nodes) return fail(DM_ERR_INVALID_ARG, "dm_fix_nodes: null nodes");
+  for (int i = 0; i < n; ++i) if (nodes[i] < 0 || nodes[i] >= s->rods[rod].n) return fail(DM_ERR_INVALID_ARG, "dm_fix_nodes: index out of range");
+  for (int i = 0; i < n; ++i) s->rods[rod].nfix[nodes[i]] = 1;
+  return DM_OK;
+}
+
+dm_status dm_fix_edges(dm_sim* s, int rod, const int* edges, int n) {
+  dm_status st;
+  if ((st = check_rod(s, rod)) != DM_OK) return st;
+  if (s->finalized) return fail(DM_ERR_STATE, "dm_fix_edges after dm_finalize");
+  if (n > 0 && !edges) return fail(DM_ERR_INVALID_ARG, "dm_fix_edges: null edges");
+  for (int i = 0; i < n; ++i) if (edges[i] < 0 || edges[i] >= s->rods[rod].n - 1) return fail(DM_ERR_INVALID_ARG, "dm_fix_edges: index out of range");
+  for (int i = 0; i < n; ++i) s->rods[rod].efix[edges[i]] = 1;
+  return DM_OK;
+}
+
+dm_status dm_set_natural_curvature(dm_sim* s, int rod, const double* kbar) {
+  dm_status st;
+  if ((st = check_rod(s, rod)) != DM_OK) return st;
+  Rod& R = s->rods[rod];
+  if (R.n < 3) return DM_OK;
+  if (!kbar) return fail(DM_ERR_INVALID_ARG, "dm_set_natural_curvature: null kbar");
+  if (!finite_all(kbar, 2 * (size_t)(R.n - 2))) return fail(DM_ERR_INVALID_ARG, "dm_set_natural_curvature: non-finite value");
+  R.kbar.assign(kbar, kbar + 2 * (R.n - 2));
+  R.has_kbar = true;
+  if (s->finalized) {
+    for (int i = 1; i + 1 < R.n; ++i) {
+      int st_ = s->rod_st0[rod] + i - 1;
+      s->h_kbar[st_] = kbar[2 * (i - 1)] * s->h_Vbar[st_];
+      s->h_kbar[s->n_st + st_] = kbar[2 * (i - 1) + 1] * s->h_Vbar[st_];
+    }
+    return upload_kbar(s);
+  }
+  return DM_OK;
+}
+
+dm_status dm_set_actuation_sine(dm_sim* s, int rod, double A, double f, double phi) {
+  dm_status st;
+  if ((st = check_rod(s, rod)) != DM_OK) return st;
+  if (!std::isfinite(A) || !std::isfinite(f) || !std::isfinite(phi)) return fail(DM_ERR_INVALID_ARG, "dm_set_actuation_sine: non-finite");
+  Rod& R = s->rods[rod];
+  R.act = true; R.A = A; R.f = f; R.phi = phi;
+  if (s->finalized) {
+    for (int i = 1; i + 1 < R.n; ++i) {
+      int st_ = s->rod_st0[rod] + i - 1;
+      s->h_act[st_] = A; s->h_act[s->n_st + st_] = f; s->h_act[2 * s->n_st + st_] = phi;
+    }
+    return upload_kbar(s);
+  }
+  return DM_OK;
+}
+
+dm_status dm_set_external_load(dm_sim* s, int rod, const double* force, const double* moment) {
+  dm_status st;
+  if ((st = check_rod(s, rod)) != DM_OK) return st;
+  if (s->finalized) return fail(DM_ERR_STATE, "dm_set_external_load after dm_finalize");
+  Rod& R = s->rods[rod];
+  if (force) {
+    if (!finite_all(force, 3 * (size_t)R.n)) return fail(DM_ERR_INVALID_ARG, "dm_set_external_load: non-finite force");
+    R.force.assign(force, force + 3 * R.n);
+  }
+  if (moment) {
+    if (!finite_all(moment, (size_t)R.n - 1)) return fail(DM_ERR_INVALID_ARG, "dm_set_external_load: non-finite moment");
+    R.moment.assign(moment, moment + R.n - 1);
+  }
+  return DM_OK;
+}
+
+dm_status dm_finalize(dm_sim* s) {
+  if (!s) return fail(DM_ERR_INVALID_ARG, "null sim");
+  if (s->finalized) return fail(DM_ERR_STATE, "dm_finalize called twice");
+  DM_HIP(hipSetDevice(s->cfg.device));
+  dm_status st = do_finalize(s);
+  if (st != DM_OK) {
+    for (void* p : s->allocs) (void)hipFree(p);
+    s->allocs.clear();
+    s->finalized = false;
+  }
+  return st;
+}
+
+dm_status dm_step(dm_sim* s, double dt, int nsteps, dm_stats* stats) {
+  if (!s) return fail(DM_ERR_INVALID_ARG, "null sim");
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_step before dm_finalize");
+  if (!(dt > 0) || !std::isfinite(dt) || nsteps < 0) return fail(DM_ERR_INVALID_ARG, "dm_step: bad dt or nsteps");
+  if (nsteps == 0) return DM_OK;
+  DM_HIP(hipSetDevice(s->cfg.device));
+  DmStepArgs A{};
+  A.d = s->dev;
+  A.dt = dt;
+  A.tol = s->cfg.newton_tol;
+  A.stag_tol = s->cfg.stagnation_tol;
+  for (int c = 0; c < 3; ++c) A.g[c] = s->cfg.gravity[c];
+  A.damping = s->cfg.damping;
+  A.floor_on = s->cfg.floor_contact;
+  A.floor_z = s->cfg.floor_z; A.delta = s->cfg.delta; A.nu = s->cfg.nu; A.mu = s->cfg.mu; A.kc = s->cfg.k_contact;
+  A.max_iter = s->cfg.max_iter;
+  A.nsteps = nsteps;
+  A.line_search = s->cfg.line_search;
+  A.n_systems = s->n_sys;
+  A.max_nb = std::max(s->max_nb, 1);
+  A.max_arms = std::max(s->max_arms, 1);
+  size_t lds = sizeof(double) * ((size_t)A.max_nb * (A.max_nb + 1) + (size_t)A.max_arms * 110 + A.max_nb + 40 + 2);
+  DM_HIP(dm_launch_step(&A, s->block, lds, s->stream));
+  DM_HIP(hipStreamSynchronize(s->stream));
+  std::vector<int> steps(s->n_sys), iters(s->n_sys), status(s->n_sys), floors(s->n_sys);
+  std::vector<double> res(s->n_sys);
+  DM_HIP(hipMemcpy(steps.data(), s->dev.s_steps, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
+  DM_HIP(hipMemcpy(iters.data(), s->dev.s_iters, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
+  DM_HIP(hipMemcpy(status.data(), s->dev.s_status, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
+  DM_HIP(hipMemcpy(res.data(), s->dev.s_res, sizeof(double) * s->n_sys, hipMemcpyDeviceToHost));
+  DM_HIP(hipMemcpy(floors.data(), s->dev.s_floor, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
+  dm_status worst = DM_OK;
+  for (int i = 0; i < s->n_sys; ++i) {
+    if (stats) {
+      stats[i].steps_done = steps[i]; stats[i].newton_iters = iters[i]; stats[i].status = status[i];
+      stats[i].floor_steps = floors[i]; stats[i].residual = res[i];
+    }
+    if (status[i] == DM_ERR_SINGULAR) worst = DM_ERR_SINGULAR;
+    else if (status[i] == DM_NOT_CONVERGED && worst == DM_OK) worst = DM_NOT_CONVERGED;
+  }
+  s->time += dt * nsteps;
+  if (worst == DM_ERR_SINGULAR) return fail(DM_ERR_SINGULAR, "dm_step: zero or non-finite pivot in some system");
+  if (worst == DM_NOT_CONVERGED) { g_err = "dm_step: Newton did not converge in some system"; }
+  return worst;
+}
+
+int dm_num_systems(const dm_sim* s) { return s ? s->n_sys : 0; }
+int dm_rod_system(const dm_sim* s, int rod) { return (s && rod >= 0 && rod < (int)s->rod_sys.size()) ? s->rod_sys[rod] : -1; }
+int dm_num_rods(const dm_sim* s) { return s ? (int)s->rods.size() : 0; }
+int dm_rod_nodes(const dm_sim* s, int rod) { return (s && rod >= 0 && rod < (int)s->rods.size()) ? s->rods[rod].n : -1; }
+int dm_num_nodes(const dm_sim* s) { return s ? s->n_nodes : 0; }
+int dm_num_edges(const dm_sim* s) { return s ? s->n_edges : 0; }
+int dm_node_index(const dm_sim* s, int rod, int node) {
+  if (!s || !s->finalized || rod < 0 || rod >= (int)s->rods.size() || node < 0 || node >= s->rods[rod].n) return -1;
+  return s->rod_node[rod][node];
+}
+int dm_edge_index(const dm_sim* s, int rod, int edge) {
+  if (!s || !s->finalized || rod < 0 || rod >= (int)s->rods.size() || edge < 0 || edge >= s->rods[rod].n - 1) return -1;
+  return s->rod_edge[rod][edge];
+}
+
+dm_status dm_get_state(dm_sim* s, double* x, double* th, double* v, double* om, int on_device) {
+  if (!s) return fail(DM_ERR_INVALID_ARG, "null sim");
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_get_state before dm_finalize");
+  DM_HIP(hipSetDevice(s->cfg.device));
+  DM_HIP(hipStreamSynchronize(s->stream));
+  const int NN = s->n_nodes, NE = s->n_edges;
+  std::vector<double> buf(3 * (size_t)NN);
+  auto get3 = [&](const double* src, double* dst) -> dm_status {
+    DM_HIP(hipMemcpy(buf.data(), src, sizeof(double) * 3 * NN, hipMemcpyDeviceToHost));
+    std::vector<double> aos(3 * (size_t)NN);
+    for (int n = 0; n < NN; ++n) for (int c = 0; c < 3; ++c) aos[3 * n + c] = buf[c * NN + n];
+    DM_HIP(hipMemcpy(dst, aos.data(), sizeof(double) * 3 * NN, on_device ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+    return DM_OK;
+  };
+  dm_status st;
+  if (x && (st = get3(s->dev.x, x)) != DM_OK) return st;
+  if (v && (st = get3(s->dev.v, v)) != DM_OK) return st;
+  hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  if (th) DM_HIP(hipMemcpy(th, s->dev.th, sizeof(double) * NE, k));
+  if (om) DM_HIP(hipMemcpy(om, s->dev.om, sizeof(double) * NE, k));
+  return DM_OK;
+}
+
+dm_status dm_set_state(dm_sim* s, const double* x, const double* th, const double* v, const double* om, int on_device) {
+  if (!s) return fail(DM_ERR_INVALID_ARG, "null sim");
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_set_state before dm_finalize");
+  DM_HIP(hipSetDevice(s->cfg.device));
+  DM_HIP(hipStreamSynchronize(s->stream));
+  const int NN = s->n_nodes, NE = s->n_edges;
+  auto put3 = [&](const double* src, double* dst, double* dst2) -> dm_status {
+    std::vector<double> aos(3 * (size_t)NN), soa(3 * (size_t)NN);
+    DM_HIP(hipMemcpy(aos.data(), src, sizeof(double) * 3 * NN, on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
+    if (!finite_all(aos.data(), aos.size())) return fail(DM_ERR_INVALID_ARG, "dm_set_state: non-finite value");
+    for (int n = 0; n < NN; ++n) for (int c = 0; c < 3; ++c) soa[c * NN + n] = aos[3 * n + c];
+    DM_HIP(hipMemcpy(dst, soa.data(), sizeof(double) * 3 * NN, hipMemcpyHostToDevice));
+    if (dst2) DM_HIP(hipMemcpy(dst2, soa.data(), sizeof(double) * 3 * NN, hipMemcpyHostToDevice));
+    return DM_OK;
+  };
+  dm_status st;
+  if (x && (st = put3(x, s->dev.x, s->dev.x0)) != DM_OK) return st;
+  if (v && (st = put3(v, s->dev.v, nullptr)) != DM_OK) return st;
+  hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  if (th) { DM_HIP(hipMemcpy(s->dev.th, th, sizeof(double) * NE, k)); DM_HIP(hipMemcpy(s->dev.th0, th, sizeof(double) * NE, k)); }
+  if (om) DM_HIP(hipMemcpy(s->dev.om, om, sizeof(double) * NE, k));
+  return DM_OK;
+}
+
+dm_status dm_get_rod_state(dm_sim* s, int rod, double* x, double* th, double* v, double* om) {
+  dm_status st;
+  if ((st = check_rod(s, rod)) != DM_OK) return st;
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_get_rod_state before dm_finalize");
+  std::vector<double> X(3 * (size_t)s->n_nodes), V(3 * (size_t)s->n_nodes), T(s->n_edges), O(s->n_edges);
+  if ((st = dm_get_state(s, X.data(), T.data(), V.data(), O.data(), 0)) != DM_OK) return st;
+  const auto& rn = s->rod_node[rod];
+  const auto& re = s->rod_edge[rod];
+  for (size_t i = 0; i < rn.size(); ++i) for (int c = 0; c < 3; ++c) {
+    if (x) x[3 * i + c] = X[3 * rn[i] + c];
+    if (v) v[3 * i + c] = V[3 * rn[i] + c];
+  }
+  for (size_t j = 0; j < re.size(); ++j) { if (th) th[j] = T[re[j]]; if (om) om[j] = O[re[j]]; }
+  return DM_OK;
+}
+
+dm_status dm_set_rod_state(dm_sim* s, int rod, const double* x, const double* th, const double* v, const double* om) {
+  dm_status st;
+  if ((st = check_rod(s, rod)) != DM_OK) return st;
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_set_rod_state before dm_finalize");
+  std::vector<double> X(3 * (size_t)s->n_nodes), V(3 * (size_t)s->n_nodes), T(s->n_edges), O(s->n_edges);
+  if ((st = dm_get_state(s, X.data(), T.data(), V.data(), O.data(), 0)) != DM_OK) return st;
+  const auto& rn = s->rod_node[rod];
+  const auto& re = s->rod_edge[rod];
+  for (size_t i = 0; i < rn.size(); ++i) for (int c = 0; c < 3; ++c) {
+    if (x) X[3 * rn[i] + c] = x[3 * i + c];
+    if (v) V[3 * rn[i] + c] = v[3 * i + c];
+  }
+  for (size_t j = 0; j < re.size(); ++j) { if (th) T[re[j]] = th[j]; if (om) O[re[j]] = om[j]; }
+  return dm_set_state(s, X.data(), T.data(), V.data(), O.data(), 0);
+}
+
+size_t dm_checkpoint_size(const dm_sim* s) { return s && s->finalized ? state_doubles(s) : 0; }
+
+dm_status dm_save_checkpoint(dm_sim* s, double* buf, int on_device) {
+  if (!s || !buf) return fail(DM_ERR_INVALID_ARG, "dm_save_checkpoint: null argument");
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_save_checkpoint before dm_finalize");
+  DM_HIP(hipStreamSynchronize(s->stream));
+  const size_t NN = s->n_nodes, NE = s->n_edges;
+  hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+  double* p = buf;
+  DM_HIP(hipMemcpy(p, s->dev.x, sizeof(double) * 3 * NN, k)); p += 3 * NN;
+  DM_HIP(hipMemcpy(p, s->dev.x0, sizeof(double) * 3 * NN, k)); p += 3 * NN;
+  DM_HIP(hipMemcpy(p, s->dev.v, sizeof(double) * 3 * NN, k)); p += 3 * NN;
+  DM_HIP(hipMemcpy(p, s->dev.th, sizeof(double) * NE, k)); p += NE;
+  DM_HIP(hipMemcpy(p, s->dev.th0, sizeof(double) * NE, k)); p += NE;
+  DM_HIP(hipMemcpy(p, s->dev.om, sizeof(double) * NE, k)); p += NE;
+  DM_HIP(hipMemcpy(p, s->dev.tref, sizeof(double) * 3 * NE, k)); p += 3 * NE;
+  DM_HIP(hipMemcpy(p, s->dev.d1ref, sizeof(double) * 3 * NE, k)); p += 3 * NE;
+  DM_HIP(hipMemcpy(p, s->dev.bref, sizeof(double) * s->n_st, k)); p += s->n_st;
+  DM_HIP(hipMemcpy(p, s->dev.time, sizeof(double) * s->n_sys, k));
+  return DM_OK;
+}
+
+dm_status dm_load_checkpoint(dm_sim* s, const double* buf, int on_device) {
+  if (!s || !buf) return fail(DM_ERR_INVALID_ARG, "dm_load_checkpoint: null argument");
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_load_checkpoint before dm_finalize");
+  DM_HIP(hipStreamSynchronize(s->stream));
+  const size_t NN = s->n_nodes, NE = s->n_edges;
+  hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  const double* p = buf;
+  DM_HIP(hipMemcpy(s->dev.x, p, sizeof(double) * 3 * NN, k)); p += 3 * NN;
+  DM_HIP(hipMemcpy(s->dev.x0, p, sizeof(double) * 3 * NN, k)); p += 3 * NN;
+  DM_HIP(hipMemcpy(s->dev.v, p, sizeof(double) * 3 * NN, k)); p += 3 * NN;
+  DM_HIP(hipMemcpy(s->dev.th, p, sizeof(double) * NE, k)); p += NE;
+  DM_HIP(hipMemcpy(s->dev.th0, p, sizeof(double) * NE, k)); p += NE;
+  DM_HIP(hipMemcpy(s->dev.om, p, sizeof(double) * NE, k)); p += NE;
+  DM_HIP(hipMemcpy(s->dev.tref, p, sizeof(double) * 3 * NE, k)); p += 3 * NE;
+  DM_HIP(hipMemcpy(s->dev.d1ref, p, sizeof(double) * 3 * NE, k)); p += 3 * NE;
+  DM_HIP(hipMemcpy(s->dev.bref, p, sizeof(double) * s->n_st, k)); p += s->n_st;
+  DM_HIP(hipMemcpy(s->dev.time, p, sizeof(double) * s->n_sys, k));
+  return DM_OK;
+}
+
+double dm_time(const dm_sim* s) { return s ? s->time : 0.0; }
+
+const char* dm_last_error(void) { return g_err.c_str(); }
+
+void dm_destroy(dm_sim* s) {
+  if (!s) return;
+  if (s->finalized || !s->allocs.empty()) {
+    (void)hipSetDevice(s->cfg.device);
+    (void)hipStreamSynchronize(s->stream);
+    for (void* p : s->allocs) (void)hipFree(p);
+  }
+  delete s;
+}
+
+}  // extern "C"

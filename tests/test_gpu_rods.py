@@ -1,0 +1,205 @@
+"""GPU parity of the HIP implicit DER step against the CPU oracle (single rods and batches).
+
+Tolerances: relative 2-norm of node positions 1e-9 after one step and 1e-6 after 100 steps
+(the target stated for this path); twists are a gauge quantity and are compared with an
+absolute tolerance.  Long oracle trajectories come from tests/golden (written by
+tests/golden/make_golden.py, which calls only the oracle)."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def dm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2311_18126_amd as m
+    assert os.path.exists(m.LIB_PATH), "libdmrod.so is not built"
+    return m
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def test_cantilever_one_step_matches_live_oracle(dm):
+    from oracle import der
+    d = W.cantilever(steps=1)
+    say("case: cantilever N=51 one step")
+    sim = dm.sim_from_description(d)
+    st = sim.step(d["dt"], 1)
+    x, th, v, om = sim.rod_state(0)
+    _, ost, infos, _ = der.simulate(d, steps=1, polish=1)
+    assert st["status"][0] == 0 and st["steps"][0] == 1
+    assert rel(x, ost.x.numpy()) < 1e-9
+    assert rel(v, ost.v.numpy()) < 1e-7
+    assert np.abs(th - ost.theta.numpy()).max() < 1e-9
+
+
+def test_cantilever_100_steps_matches_golden(dm):
+    g = np.load(os.path.join(GOLD, "cantilever.npz"))
+    d = W.cantilever()
+    say("case: cantilever N=51 100 steps")
+    sim = dm.sim_from_description(d)
+    done = 0
+    for k in (1, 10, 100):
+        st = sim.step(d["dt"], k - done)
+        done = k
+        x, th, _, _ = sim.rod_state(0)
+        tol = 1e-9 if k == 1 else 1e-6
+        assert rel(x, g[f"x_{k}_0"]) < tol, (k, rel(x, g[f"x_{k}_0"]))
+    assert st["status"][0] == 0
+
+
+def test_helix_with_twist_coupling_matches_golden(dm):
+    g = np.load(os.path.join(GOLD, "helix.npz"))
+    d = W.paper_helix(steps=20)
+    say("case: helix N=100 20 steps")
+    sim = dm.sim_from_description(d)
+    sim.step(d["dt"], 1)
+    x, th, _, _ = sim.rod_state(0)
+    assert rel(x, g["x_1_0"]) < 1e-9
+    sim.step(d["dt"], 19)
+    x, th, _, _ = sim.rod_state(0)
+    assert rel(x, g["x_20_0"]) < 1e-7
+    assert np.abs(th - g["th_20_0"]).max() < 1e-6
+
+
+def test_full_batch_sampled_rods_match_golden(dm):
+    """The 1024-rod batch in one persistent launch (the benchmark configuration); sampled
+    rods, including the longest and the shortest, against the oracle run rod by rod."""
+    g = np.load(os.path.join(GOLD, "batch.npz"))
+    d = W.rod_batch(1024)
+    say("case: batch 1024 rods, 2 steps")
+    sim = dm.sim_from_description(d)
+    ids = [int(i) for i in g["rods"]]
+    st = sim.step(d["dt"], 1)
+    assert (st["status"] == 0).all(), np.unique(st["status"], return_counts=True)
+    for j, r in enumerate(ids):
+        x, _, _, _ = sim.rod_state(r)
+        assert rel(x, g[f"x_1_0_r{j}"]) < 1e-9, (r, rel(x, g[f"x_1_0_r{j}"]))
+    sim.step(d["dt"], 1)
+    for j, r in enumerate(ids):
+        x, _, _, _ = sim.rod_state(r)
+        assert rel(x, g[f"x_2_0_r{j}"]) < 1e-9, (r, rel(x, g[f"x_2_0_r{j}"]))
+
+
+def test_small_batch_of_uneven_rods_matches_live_oracle(dm):
+    """Rods of 2..40 nodes (edge cases: no interior stencil, no arm, one arm) stepped together."""
+    from oracle import der
+    rng = np.random.Generator(np.random.PCG64(7))
+    rods = []
+    for n in (2, 3, 4, 5, 7, 9, 13, 40):
+        kb = rng.normal(0, 2.0, size=(max(n - 2, 0), 2))
+        rods.append(W.rod(W.straight_nodes(n, 0.3 + 0.01 * n), 2e-3, 1e6, kbar=kb if n > 2 else None))
+    d = W.desc(rods, dt=1e-3, steps=3)
+    say("case: uneven small rods, 3 steps")
+    sim = dm.sim_from_description(d)
+    sim.step(d["dt"], 3)
+    for r in range(len(rods)):
+        _, ost, _, _ = der.simulate(W.subset(d, [r]), steps=3, polish=1)
+        x, _, _, _ = sim.rod_state(r)
+        assert rel(x, ost.x.numpy()) < 1e-9, (r, rel(x, ost.x.numpy()))
+
+
+def test_free_rod_with_damping_and_loads_matches_live_oracle(dm):
+    from oracle import der
+    rng = np.random.Generator(np.random.PCG64(8))
+    n = 17
+    force = rng.normal(0, 1e-3, size=(n, 3))
+    mom = rng.normal(0, 1e-6, size=n - 1)
+    kb = rng.normal(0, 3.0, size=(n - 2, 2))
+    r = W.rod(W.helix_nodes(n, 0.03, 0.04, 0.3), 1.5e-3, 5e6, kbar=kb, fixed_nodes=(), fixed_edges=(),
+              force=force, moment=mom)
+    d = W.desc([r], dt=2e-3, steps=4, damping=3.0)
+    say("case: free helix with damping and loads, 4 steps")
+    sim = dm.sim_from_description(d)
+    sim.step(d["dt"], 4)
+    x, th, v, om = sim.rod_state(0)
+    _, ost, _, _ = der.simulate(d, steps=4, polish=1)
+    assert rel(x, ost.x.numpy()) < 1e-9
+    assert np.abs(th - ost.theta.numpy()).max() < 1e-8
+
+
+def test_runs_are_bitwise_deterministic(dm):
+    d = W.rod_batch(64, seed=5, nmax=120)
+    out = []
+    for _ in range(2):
+        sim = dm.sim_from_description(d)
+        sim.step(d["dt"], 3)
+        out.append(sim.state())
+        sim.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
+def test_checkpoint_roundtrip_reproduces_the_trajectory(dm):
+    d = W.rod_batch(16, seed=9, nmax=80)
+    sim = dm.sim_from_description(d)
+    sim.step(d["dt"], 2)
+    ck = sim.checkpoint()
+    sim.step(d["dt"], 3)
+    a = sim.state()
+    sim.restore(ck)
+    sim.step(d["dt"], 3)
+    b = sim.state()
+    for u, w in zip(a, b):
+        assert np.array_equal(u, w)
+
+
+def test_non_convergence_is_reported_and_rolled_back(dm):
+    d = W.rod_batch(4, seed=2, nmax=60)
+    sim = dm.sim_from_description(d, max_iter=1)
+    x0 = sim.state()[0]
+    st = sim.step(d["dt"], 2, allow_failure=True)
+    assert sim.last_status == dm.DM_NOT_CONVERGED
+    assert (st["status"] == dm.DM_NOT_CONVERGED).all() and (st["steps"] == 0).all()
+    assert np.array_equal(sim.state()[0], x0)
+
+
+def test_invalid_arguments_are_rejected(dm):
+    sim = dm.Sim()
+    with pytest.raises(dm.DmError) as e:
+        sim.add_rod(np.zeros((1, 3)), 1e-3, 1e7)
+    assert e.value.status == dm.DM_ERR_INVALID_ARG
+    with pytest.raises(dm.DmError) as e:
+        sim.add_rod(np.full((3, 3), np.nan), 1e-3, 1e7)
+    assert e.value.status == dm.DM_ERR_INVALID_ARG
+    rid = sim.add_rod(W.straight_nodes(5, 1.0), 1e-3, 1e7)
+    with pytest.raises(dm.DmError) as e:
+        sim.set_natural_curvature(rid, np.full((3, 2), np.inf))
+    assert e.value.status == dm.DM_ERR_INVALID_ARG
+    with pytest.raises(dm.DmError) as e:
+        sim.step(1e-3, 1)
+    assert e.value.status == dm.DM_ERR_STATE
+    sim.finalize()
+    with pytest.raises(dm.DmError) as e:
+        sim.finalize()
+    assert e.value.status == dm.DM_ERR_STATE
+    with pytest.raises(dm.DmError) as e:
+        sim.add_rod(W.straight_nodes(5, 1.0), 1e-3, 1e7)
+    assert e.value.status == dm.DM_ERR_STATE
+    with pytest.raises(dm.DmError) as e:
+        sim.step(-1.0, 1)
+    assert e.value.status == dm.DM_ERR_INVALID_ARG
+
+
+def test_unsupported_topology_is_rejected(dm):
+    sim = dm.Sim()
+    a = sim.add_rod(W.straight_nodes(5, 1.0), 1e-3, 1e7)
+    b = sim.add_rod(W.straight_nodes(5, 1.0, (0, 1, 0)), 1e-3, 1e7)
+    sim.add_joint(a, 2, b, 2)      # joint in the middle of both rods
+    with pytest.raises(dm.DmError) as e:
+        sim.finalize()
+    assert e.value.status == dm.DM_ERR_UNSUPPORTED

@@ -17,7 +17,7 @@ A description is a plain dict:
      "joints": [(rod_a, node_a, rod_b, node_b), ...],   # node_b merged into node_a
      "gravity": (gx, gy, gz), "dt", "steps", "tol", "max_iter",
      "floor": None or {"z", "delta", "nu", "mu", "k_c"},
-     "damping": eta [1/s]}
+     "damping": eta [1/s], "line_search": bool (optional, default False)}
 
 All randomness is NumPy PCG64 with the seeds stated per workload.
 """
@@ -125,7 +125,9 @@ def star_robots(n_instances: int = 4096, seed: int = 1, limbs: int = 6, limb_nod
             if a > 0:
                 joints.append((base, 0, base + a, 0))
     floor = {"z": 0.0, "delta": delta, "nu": 1e-3, "mu": 0.5, "k_c": node_weight / delta}
-    return _desc(rods, dt=1e-3, steps=steps, joints=joints, floor=floor)
+    d = _desc(rods, dt=1e-3, steps=steps, joints=joints, floor=floor)
+    d["line_search"] = True
+    return d
 
 
 def warm_start_eval(n_rods: int = 1024, seed: int = 3, steps: int = 1000) -> dict:
@@ -181,7 +183,9 @@ def paper_friction(push: float = 5.0, dt: float = 5e-3, steps: int = 300, n_node
     node_weight = rho * math.pi * h * h * (L / (n_nodes - 1)) * 9.8
     rod = _rod(x0, h, 1e5, 0.5, rho, fixed_nodes=(), fixed_edges=(), force=force)
     floor = {"z": 0.0, "delta": 5e-4, "nu": 1e-3, "mu": 0.4, "k_c": node_weight / 5e-4}
-    return _desc([rod], dt=dt, steps=steps, gravity=(0.0, 0.0, -9.8), floor=floor)
+    d = _desc([rod], dt=dt, steps=steps, gravity=(0.0, 0.0, -9.8), floor=floor)
+    d["line_search"] = True
+    return d
 
 
 def subset(desc: dict, rod_ids) -> dict:
