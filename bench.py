@@ -1,0 +1,177 @@
+"""Benchmark: batched implicit DER steps on one MI355X, node-steps/s at a 1e-9 Newton residual.
+
+Workload: 1024 independent clamped rods, N ~ U{20..400} nodes (seed 0), L ~ U(0.5, 2) m,
+h ~ U(1e-3, 5e-3) m, E = 10^U(6, 8) Pa, natural curvature ~ N(0, 2^2) 1/m, gravity,
+dt = 1e-3 s, FP64, all rods in one persistent launch.  A "step" is one backward-Euler time
+step of the whole batch.  Prints one JSON line (see the design doc for every field).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "node-steps/s, batched implicit DER at 1e-9 residual; plain vs warm-started"
+# Algorithmic FP64 work of one Newton iteration per rod node: frames, strains, stretch and
+# bend/twist gradients and Hessians, assembly, banded LU and solves, update (closed-form
+# operation count of the method).
+FLOPS_PER_NODE_ITER = 4.0e3
+PEAK_FP64_VALU_TFLOPS = 78.6          # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+KERNEL_SOURCES = ["paper_2311_18126_amd/csrc/dm_kernels.hip", "paper_2311_18126_amd/csrc/dm_math.h",
+                  "paper_2311_18126_amd/csrc/dm_layout.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dm_step_kernel_rod_batch_traffic.json")
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(n_launch_steps):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None if the
+    summary is missing or was taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t["bytes_per_step"] * n_launch_steps
+
+
+def cpu_baseline(desc, budget_s=20.0):
+    """The CPU oracle, as is, on a bounded sample of the same workload: seeded rods of the
+    batch, one step each, until the time budget is used (rank 0, one GPU only)."""
+    import torch
+
+    import workloads as W
+    from oracle import der
+    threads = min(os.cpu_count() or 1, 16)
+    torch.set_num_threads(threads)
+    rng = np.random.Generator(np.random.PCG64(123))
+    order = rng.permutation(len(desc["rods"]))
+    nodes, t_used, rods = 0, 0.0, 0
+    for r in order:
+        sub = W.subset(desc, [int(r)])
+        t0 = time.perf_counter()
+        der.simulate(sub, steps=1)
+        t_used += time.perf_counter() - t0
+        nodes += sub["rods"][0]["x0"].shape[0]
+        rods += 1
+        if t_used > budget_s:
+            break
+    return {"value": nodes / t_used, "unit": "node-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{rods} seeded rods of the 1024-rod batch, 1 step each, {t_used:.1f} s"}
+
+
+def per_rod_baseline(dm, desc, steps, n=16):
+    """The plain per-rod GPU step: seeded rods of the batch, each in its own simulation and
+    launch (one workgroup at a time), same steps and residual."""
+    rng = np.random.Generator(np.random.PCG64(321))
+    ids = rng.choice(len(desc["rods"]), n, replace=False)
+    import torch
+    import workloads as W
+    nodes, t_used = 0, 0.0
+    for r in ids:
+        sub = W.subset(desc, [int(r)])
+        sim = dm.sim_from_description(sub, stream=torch.cuda.current_stream().cuda_stream)
+        sim.step(sub["dt"], 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(sub["dt"], steps)
+        torch.cuda.synchronize()
+        t_used += time.perf_counter() - t0
+        nodes += sub["rods"][0]["x0"].shape[0] * steps
+        sim.close()
+    return nodes / t_used
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-per-rod", action="store_true")
+    ap.add_argument("--block", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); independent rod batches "
+              "shard by rods across GPUs with no communication, which this build does not launch.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2311_18126_amd as dm
+    import workloads as W
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    desc = W.rod_batch(1024)
+    n_nodes = np.array([r["x0"].shape[0] for r in desc["rods"]])
+    stream = torch.cuda.current_stream()
+    sim = dm.sim_from_description(desc, stream=stream.cuda_stream, block_size=args.block)
+    dt = desc["dt"]
+    if args.warmup > 0:
+        sim.step(dt, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = sim.step(dt, args.steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_s = sim.last_kernel_ms / 1e3
+    assert (stats["status"] == 0).all() and (stats["steps"] == args.steps).all(), np.unique(stats["status"])
+    # systems are rods here, in order
+    iters = stats["iters"].astype(np.float64)
+    node_steps = float(n_nodes.sum()) * args.steps
+    flops = FLOPS_PER_NODE_ITER * float((n_nodes * iters).sum())
+    achieved = flops / kernel_s / 1e12
+    traffic = measured_traffic(args.steps)
+    out = {
+        "metric": METRIC,
+        "value": node_steps / wall,
+        "unit": "node-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "1024 clamped rods, N~U{20..400} (seed 0), L~U(0.5,2) m, h~U(1,5) mm, "
+                               "E=10^U(6,8) Pa, kbar~N(0,2^2)/m, gravity, dt=1e-3 s, Newton tol 1e-9",
+                   "rods": int(len(n_nodes)), "nodes": int(n_nodes.sum()), "dt": dt,
+                   "launch": "one persistent launch per call, one workgroup per rod",
+                   "block_size": sim.block_size},
+        "newton_iters_per_step": float(iters.sum() / len(iters) / args.steps),
+        "floor_steps": int(stats["floor_steps"].sum()),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": traffic,
+                     "kernel": "dm_step_kernel", "kernel_ms": 1e3 * kernel_s,
+                     "algorithmic_flops": flops},
+    }
+    if not args.no_per_rod:
+        out["per_rod_plain_value"] = per_rod_baseline(dm, desc, min(args.steps, 20))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(desc)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -159,6 +159,11 @@ dm_status dm_load_checkpoint(dm_sim* sim, const double* buf, int on_device);
 /* Simulation time [s]. */
 double dm_time(const dm_sim* sim);
 
+/* Duration [ms] of the last dm_step's kernel, from HIP events recorded on the simulation's
+ * stream immediately before and after the launch; and the workgroup size it used. */
+double dm_last_kernel_ms(const dm_sim* sim);
+int dm_block_size(const dm_sim* sim);
+
 const char* dm_last_error(void);
 void dm_destroy(dm_sim* sim);
 

@@ -68,6 +68,8 @@ _SIGS = {
     "dm_save_checkpoint": (c_int, [c_void_p, c_void_p, c_int]),
     "dm_load_checkpoint": (c_int, [c_void_p, c_void_p, c_int]),
     "dm_time": (c_double, [c_void_p]),
+    "dm_last_kernel_ms": (c_double, [c_void_p]),
+    "dm_block_size": (c_int, [c_void_p]),
     "dm_last_error": (c_char_p, []),
     "dm_destroy": (None, [c_void_p]),
 }
@@ -270,6 +272,15 @@ class Sim:
     @property
     def time(self):
         return lib().dm_time(self._h)
+
+    @property
+    def last_kernel_ms(self):
+        """Duration of the last step() kernel from HIP events on the simulation's stream."""
+        return lib().dm_last_kernel_ms(self._h)
+
+    @property
+    def block_size(self):
+        return lib().dm_block_size(self._h)
 
 
 def sim_from_description(desc, **overrides):

@@ -17,8 +17,21 @@
 // After convergence the step is committed: velocity update, reference frames carried to
 // the new tangents by time-parallel transport, reference twist recorded for its branch.
 #include <hip/hip_runtime.h>
+#define DM_KERNEL_TU
 #include "dm_layout.h"
 #include "dm_math.h"
+
+#ifdef DM_PHASE_TIMING
+// Per-phase wall-clock accumulation (100 MHz counter) for diagnosis builds only; every phase
+// still runs in full.
+#define DM_T0() unsigned long long _t_last = wall_clock64(); unsigned long long _t_acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#define DM_TP(k) do { unsigned long long _n = wall_clock64(); _t_acc[k] += _n - _t_last; _t_last = _n; } while (0)
+#define DM_TSAVE(sid) do { if (threadIdx.x == 0 && A.d.dbg) for (int _i = 0; _i < 8; ++_i) A.d.dbg[(sid) * 8 + _i] = (double)_t_acc[_i]; } while (0)
+#else
+#define DM_T0()
+#define DM_TP(k)
+#define DM_TSAVE(sid)
+#endif
 
 #define DM_STATUS_OK 0
 #define DM_STATUS_NOT_CONVERGED 1
@@ -26,8 +39,8 @@
 
 namespace {
 
-__device__ __forceinline__ v3 ld3(const double* a, int n, int i) { return mk3(a[i], a[n + i], a[2 * n + i]); }
-__device__ __forceinline__ void st3(double* a, int n, int i, v3 v) { a[i] = v.x; a[n + i] = v.y; a[2 * n + i] = v.z; }
+__device__ __forceinline__ v3 ld3(const double DM_G* a, int n, int i) { return mk3(a[i], a[n + i], a[2 * n + i]); }
+__device__ __forceinline__ void st3(double DM_G* a, int n, int i, v3 v) { a[i] = v.x; a[n + i] = v.y; a[2 * n + i] = v.z; }
 
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   long long b = __double_as_longlong(v);
@@ -42,7 +55,7 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ double block_sum(double v, double* red) {
+__device__ double block_sum(double v, double DM_L* red) {
   v = wave_sum(v);
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) red[w] = v;
@@ -60,32 +73,56 @@ __device__ double block_sum(double v, double* red) {
 // element evaluation
 // ---------------------------------------------------------------------------
 
-__device__ void eval_stencil(const DmStepArgs& A, int s, double t_end) {
+// One lane of a stencil pair.  Pass 0 evaluates the stencil as stored with derivatives
+// seeded on its f edge; pass 1 evaluates the same stencil with its orientation reversed
+// (nodes and edges swapped, edges reversed), which leaves the energy unchanged once the
+// second natural-curvature component changes sign, so that both lanes run the same code.
+// Pass 1's Hessian columns are the e-edge columns of the stored stencil, reached through the
+// signed permutation e_f <-> -e_e, theta_f <-> -theta_e (an even number of sign flips per
+// Hessian entry, so only the indices move).
+__device__ __noinline__ void eval_stencil(const DmStepArgs& A, int s, int pass, double t_end) {
   const DmDev& D = A.d;
   const int NS = D.n_st_tot, NE = D.n_edges_tot, NN = D.n_nodes_tot;
-  const int np = D.sn[s], nc = D.sn[NS + s], nn = D.sn[2 * NS + s];
-  const int ef = D.se[s], ee = D.se[NS + s];
+  int np = D.sn[s], nc = D.sn[NS + s], nn = D.sn[2 * NS + s];
+  int ef = D.se[s], ee = D.se[NS + s];
   const int sg = D.ssign[s];
-  const double sf = (sg & 1) ? -1.0 : 1.0, se = (sg & 2) ? -1.0 : 1.0;
+  double sf = (sg & 1) ? -1.0 : 1.0, se = (sg & 2) ? -1.0 : 1.0;
   double k1b = D.kbar[s], k2b = D.kbar[NS + s];
   const double amp = D.act[s];
   if (!isnan(amp)) {   // actuation: kappa1 = A sin(2 pi f t + phi), integrated over Vbar
     k1b = amp * sin(6.283185307179586476925286766559 * D.act[NS + s] * t_end + D.act[2 * NS + s]) * D.Vbar[s];
     k2b = 0.0;
   }
-  double g[DM_ST_G], H[DM_ST_H];
-  stencil_eval(ld3(D.x, NN, np), ld3(D.x, NN, nc), ld3(D.x, NN, nn), sf * D.th[ef], se * D.th[ee],
+  if (pass) {
+    const int tn = np; np = nn; nn = tn;
+    const int te = ef; ef = ee; ee = te;
+    const double ts = sf; sf = -se; se = -ts;
+    k2b = -k2b;
+  }
+  const v3 xc = ld3(D.x, NN, nc);
+  double g8[8], H8f[8][4];
+  stencil_pass(xc - ld3(D.x, NN, np), ld3(D.x, NN, nn) - xc, sf * D.th[ef], se * D.th[ee],
                sf * ld3(D.tref, NE, ef), ld3(D.d1ref, NE, ef), se * ld3(D.tref, NE, ee), ld3(D.d1ref, NE, ee),
-               D.bref[s], k1b, k2b, D.tbar[s], D.kbend[s], D.ktwist[s], sf, se, g, H);
+               D.bref[s], k1b, k2b, D.tbar[s], D.kbend[s], D.ktwist[s], g8, H8f);
+  if (!pass) {
 #pragma unroll
-  for (int a = 0; a < DM_ST_G; ++a) D.st_g[a * NS + s] = g[a];
+    for (int a = 0; a < 8; ++a) D.st_g[a * NS + s] = g8[a];
+  }
 #pragma unroll
-  for (int k = 0; k < DM_ST_H; ++k) D.st_H[k * NS + s] = H[k];
+  for (int a = 0; a < 8; ++a) {
+    // pass 1 maps variable a of the reversed stencil to its stored-stencil variable
+    const int ra = pass ? (a < 3 ? a + 3 : (a < 6 ? a - 3 : 13 - a)) : a;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int w = (k < 3 ? k : 6) + (pass ? (k < 3 ? 3 : 1) : 0);
+      D.st_H[(ra * 8 + w) * NS + s] = H8f[a][k];
+    }
+  }
 }
 
 // Stretch (Eq. 2-3): gradient EA (|e|/ebar - 1) t with respect to the edge vector and its
 // Hessian (EA/ebar) t t^T + EA (1/ebar - 1/|e|)(I - t t^T).
-__device__ void eval_edge(const DmStepArgs& A, int e) {
+__device__ __noinline__ void eval_edge(const DmStepArgs& A, int e) {
   const DmDev& D = A.d;
   const int NE = D.n_edges_tot, NN = D.n_nodes_tot;
   v3 d = ld3(D.x, NN, D.en[NE + e]) - ld3(D.x, NN, D.en[e]);
@@ -144,7 +181,7 @@ __device__ __forceinline__ void friction_ratio(double s, double K2, double* g, d
 
 // Node terms of the residual (Eq. 15) and Jacobian: inertia, gravity, constant load,
 // damping, floor contact (Eq. 10-11) and friction (Eq. 12-13).
-__device__ void eval_node(const DmStepArgs& A, int n) {
+__device__ __noinline__ void eval_node(const DmStepArgs& A, int n) {
   const DmDev& D = A.d;
   const int NN = D.n_nodes_tot;
   const double dt = A.dt, m = D.mass[n];
@@ -194,6 +231,37 @@ __device__ void eval_node(const DmStepArgs& A, int n) {
 // gather assembly
 // ---------------------------------------------------------------------------
 
+// Row L (compile-time local DOF) of a chain stencil's gradient and Hessian, expanded from the
+// 8-variable form: local DOF l = sum of coef * variable (loc_terms, orientation +1 in a chain).
+// emit(rel0 + b, H_local[L][b]) for b = 0..10; returns g_local[L].
+template <int L, class Emit>
+__device__ __forceinline__ double stencil_row(const DmDev& D, int s, int rel0, Emit& emit) {
+  const int NS = D.n_st_tot;
+  int va[2], vb[2];
+  double ca[2], cb[2];
+  const int na = loc_terms(L, 1.0, 1.0, va, ca);
+  double r8[8];
+  double gl = 0.0;
+#pragma unroll
+  for (int w = 0; w < 8; ++w) r8[w] = 0.0;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    if (t < na) {
+      gl += ca[t] * D.st_g[va[t] * NS + s];
+#pragma unroll
+      for (int w = 0; w < 8; ++w) r8[w] += ca[t] * D.st_H[(va[t] * 8 + w) * NS + s];
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < 11; ++b) {
+    const int nb = loc_terms(b, 1.0, 1.0, vb, cb);
+    double v = cb[0] * r8[vb[0]];
+    if (nb > 1) v += cb[1] * r8[vb[1]];
+    emit(rel0 + b, v);
+  }
+  return gl;
+}
+
 // Contributions of chain elements to chain row 4k + COMP; emit(rel, value) receives the
 // column as rel = column - 4k.  Returns the residual entry.
 template <int COMP, class Emit>
@@ -221,58 +289,47 @@ __device__ __forceinline__ double row_contrib(const DmStepArgs& A, const DmChain
       for (int c = 0; c < 3; ++c) { double K = edge_K(D, NE, e, COMP, c); emit(-4 + c, -K); emit(c, K); }
       Rr += D.ed[COMP * NE + e];
     }
-#pragma unroll
-    for (int dj = -1; dj <= 1; ++dj) {
-      const int j = k + dj;
-      if (j >= 1 && j <= N - 2) {
-        const int s = ch.st_off + j - 1;
-        const int a = 4 * (1 - dj) + COMP;
-        Rr += D.st_g[a * NS + s];
-#pragma unroll
-        for (int b = 0; b < 11; ++b) emit(4 * (dj - 1) + b, D.st_H[hidx(a, b) * NS + s]);
-      }
-    }
+    // stencils centred on nodes k-1, k, k+1 (node k is their next, centre, previous node)
+    if (k - 1 >= 1 && k - 1 <= N - 2) Rr += stencil_row<8 + COMP>(D, ch.st_off + k - 2, -8, emit);
+    if (k >= 1 && k <= N - 2) Rr += stencil_row<4 + COMP>(D, ch.st_off + k - 1, -4, emit);
+    if (k + 1 >= 1 && k + 1 <= N - 2) Rr += stencil_row<COMP>(D, ch.st_off + k, 0, emit);
   } else {
     const int e = D.chain_edge[ch.edge_tab + k];
     const double I = D.Ith[e] / (A.dt * A.dt);
     emit(3, I);
     Rr += I * (D.th[e] - D.th0[e] - A.dt * D.om[e]) - D.moment[e];
-#pragma unroll
-    for (int dj = 0; dj <= 1; ++dj) {
-      const int j = k + dj;
-      if (j >= 1 && j <= N - 2) {
-        const int s = ch.st_off + j - 1;
-        const int a = dj == 0 ? 7 : 3;
-        Rr += D.st_g[a * NS + s];
-#pragma unroll
-        for (int b = 0; b < 11; ++b) emit(4 * (dj - 1) + b, D.st_H[hidx(a, b) * NS + s]);
-      }
-    }
+    if (k >= 1 && k <= N - 2) Rr += stencil_row<7>(D, ch.st_off + k - 1, -4, emit);
+    if (k + 1 >= 1 && k + 1 <= N - 2) Rr += stencil_row<3>(D, ch.st_off + k, 0, emit);
   }
   return Rr;
 }
 
+// Band row 4k + COMP.  Contributions are summed per diagonal first; clamped columns, and
+// border columns of a border row (those couplings live in the dense border), are zeroed
+// afterwards.  fixmask / bmask: bit i describes chain DOF 4k - 12 + i.
 template <int COMP>
 __device__ __forceinline__ double band_row(const DmStepArgs& A, const DmChain& ch, int k,
                                            unsigned fixmask, unsigned bmask) {
   const int r = 4 * k + COMP;
-  const bool rowb = (r >= ch.b_lo && r < ch.b_hi);
-  const bool rowfix = (fixmask >> (8 + COMP)) & 1u;
+  const bool rowb = (bmask >> (12 + COMP)) & 1u;
+  const bool rowfix = (fixmask >> (12 + COMP)) & 1u;
   double acc[DM_NDIAG];
 #pragma unroll
   for (int o = 0; o < DM_NDIAG; ++o) acc[o] = 0.0;
-  auto emit = [&](int rel, double v) {
-    const int idx = rel + 8;
-    const bool drop = ((fixmask >> idx) & 1u) || (rowb && ((bmask >> idx) & 1u));
-    acc[rel - COMP + 10] += drop ? 0.0 : v;
-  };
+  auto emit = [&](int rel, double v) { acc[rel - COMP + 10] += v; };
   double Rr = row_contrib<COMP>(A, ch, k, emit);
+  const unsigned drop = fixmask | (rowb ? bmask : 0u);
+#pragma unroll
+  for (int o = 0; o < DM_NDIAG; ++o) {
+    // column r - 10 + o is chain DOF 4k - 12 + (COMP + 2 + o)
+    if ((drop >> (COMP + 2 + o)) & 1u) acc[o] = 0.0;
+  }
   if (rowfix) {
 #pragma unroll
     for (int o = 0; o < DM_NDIAG; ++o) acc[o] = (o == 10) ? 1.0 : 0.0;
     Rr = 0.0;
   }
-  double* out = A.d.band + (size_t)(ch.dof_off + r) * DM_NDIAG;
+  double DM_G* out = A.d.band + (size_t)(ch.dof_off + r) * DM_NDIAG;
 #pragma unroll
   for (int o = 0; o < DM_NDIAG; ++o) out[o] = acc[o];
   A.d.R[ch.dof_off + r] = Rr;
@@ -281,15 +338,15 @@ __device__ __forceinline__ double band_row(const DmStepArgs& A, const DmChain& c
 
 // Band rows of chain node k (4 rows; 3 for the last node).  Returns the squared residual of
 // its free, non-border rows.
-__device__ double band_node(const DmStepArgs& A, const DmChain& ch, int k) {
+__device__ __noinline__ double band_node(const DmStepArgs& A, const DmChain& ch, int k) {
   const DmDev& D = A.d;
   const int n = 4 * ch.n_nodes - 1;
   unsigned fixmask = 0u, bmask = 0u;
 #pragma unroll
-  for (int i = 0; i < 20; ++i) {
-    const int r = 4 * (k - 2) + i;
+  for (int i = 0; i < 32; ++i) {
+    const int r = 4 * k - 12 + i;
     if (r >= 0 && r < n) {
-      fixmask |= (unsigned)D.cfix[ch.dof_off + r] << i;
+      fixmask |= (unsigned)(D.cfix[ch.dof_off + r] != 0) << i;
       bmask |= (unsigned)(r >= ch.b_lo && r < ch.b_hi) << i;
     }
   }
@@ -302,10 +359,10 @@ __device__ double band_node(const DmStepArgs& A, const DmChain& ch, int k) {
 
 // Dense border row b: pristine border-border entries of every chain touching it plus the
 // joint stencils; right-hand side in column nb.  Returns its squared residual if free.
-__device__ double border_row(const DmStepArgs& A, const DmSystem& S, int b, double* Bt, int ld) {
+__device__ __noinline__ double border_row(const DmStepArgs& A, const DmSystem& S, int b, double DM_L* Bt, int ld) {
   const DmDev& D = A.d;
   const int NS = D.n_st_tot;
-  double* row = Bt + b * ld;
+  double DM_L* row = Bt + b * ld;
   for (int j = 0; j <= S.nb; ++j) row[j] = 0.0;
   if (D.bfix[S.bfix_off + b]) { row[b] = 1.0; return 0.0; }
   double rhs = 0.0;
@@ -331,14 +388,24 @@ __device__ double border_row(const DmStepArgs& A, const DmSystem& S, int b, doub
     }
   }
   for (int js = 0; js < S.n_jst; ++js) {
-    const int* bj = D.bjst + S.bjst_off + js * 11;
+    const int DM_G* bj = D.bjst + S.bjst_off + js * 11;
     const int s = S.jst0 + js;
+    const int sg = D.ssign[s];
+    const double sf = (sg & 1) ? -1.0 : 1.0, se = (sg & 2) ? -1.0 : 1.0;
     for (int a = 0; a < 11; ++a) {
       if (bj[a] != b) continue;
-      rhs += D.st_g[a * NS + s];
+      int va[2], vc[2];
+      double ca[2], cc[2];
+      const int na = loc_terms(a, sf, se, va, ca);
+      for (int t = 0; t < na; ++t) rhs += ca[t] * D.st_g[va[t] * NS + s];
       for (int c = 0; c < 11; ++c) {
         const int bc = bj[c];
-        if (bc >= 0 && !D.bfix[S.bfix_off + bc]) row[bc] += D.st_H[hidx(a, c) * NS + s];
+        if (bc < 0 || D.bfix[S.bfix_off + bc]) continue;
+        const int nc = loc_terms(c, sf, se, vc, cc);
+        double h = 0.0;
+        for (int t = 0; t < na; ++t)
+          for (int u = 0; u < nc; ++u) h += ca[t] * cc[u] * D.st_H[(va[t] * 8 + vc[u]) * NS + s];
+        row[bc] += h;
       }
     }
   }
@@ -351,23 +418,60 @@ __device__ double border_row(const DmStepArgs& A, const DmSystem& S, int b, doub
 // ---------------------------------------------------------------------------
 
 struct ArmView {
-  const double* band; const double* R; double* fac;
+  const double DM_G* band; const double DM_G* R; double DM_G* fac;
   int dof_off, n, first, dir, count, fac_off;
   __device__ __forceinline__ int cd(int l) const { return first + dir * l; }
-  __device__ __forceinline__ double a(int l, int l2) const {
+  // address of band entry (l, l2) in arm-local numbering; ok = false outside the band
+  __device__ __forceinline__ const double DM_G* ap(int l, int l2, bool& ok) const {
     const int r = cd(l), r2 = cd(l2);
-    if (r < 0 || r >= n || r2 < 0 || r2 >= n) return 0.0;
     const int o = r2 - r + DM_HALF_BAND;
-    if (o < 0 || o >= DM_NDIAG) return 0.0;
-    return band[(size_t)(dof_off + r) * DM_NDIAG + o];
+    ok = (r >= 0) & (r < n) & (r2 >= 0) & (r2 < n) & (o >= 0) & (o < DM_NDIAG);
+    return band + (ok ? (size_t)(dof_off + r) * DM_NDIAG + o : (size_t)dof_off * DM_NDIAG);
   }
-  __device__ __forceinline__ double rhs(int l) const { return l < count ? R[dof_off + cd(l)] : 0.0; }
+  // address of the right-hand side of local row l; ok = false for the border rows
+  __device__ __forceinline__ const double DM_G* rp(int l, bool& ok) const {
+    ok = l < count;
+    return R + (ok ? dof_off + cd(l) : dof_off);
+  }
+  __device__ __forceinline__ double a(int l, int l2) const {
+    bool ok;
+    const double v = *ap(l, l2, ok);
+    return ok ? v : 0.0;
+  }
 };
+
+// One window entry for lane `lane`: band entry (l, l2) for lanes 0..10, the right-hand side of
+// row l for lane 11; a single load whose address depends on the lane, with no branch.
+__device__ __forceinline__ double window_entry(const ArmView& V, int l, int l2, int lane) {
+  bool oka, okr;
+  const double DM_G* pa = V.ap(l, l2, oka);
+  const double DM_G* pr = V.rp(l, okr);
+  const bool rhs = (lane == DM_WIN);
+  const double v = *(rhs ? pr : pa);
+  return (rhs ? okr : (oka & (lane < DM_WIN))) ? v : 0.0;
+}
+
+// Loads of block k0 .. k0+10 for one lane s: buf[0..10] = the column this lane takes over at
+// its pivot step k0 + s (rows k+1 .. k+11 of column k+11); buf[11 + T] = the entry of the row
+// entering at step k0 + T in this lane's column (lane 11: that row's right-hand side).  The
+// band is not modified during elimination, so these are loaded one block ahead.
+__device__ __forceinline__ void load_window_block(double (&buf)[2 * DM_WIN], int k0, int lane, const ArmView& V) {
+  const int s = lane < DM_WIN ? lane : 0;
+  const int kp = k0 + s;
+#pragma unroll
+  for (int i = 1; i <= DM_WIN; ++i) buf[i - 1] = V.a(kp + i, kp + DM_WIN);
+#pragma unroll
+  for (int T = 0; T < DM_WIN; ++T) {
+    const int k = k0 + T;
+    buf[DM_WIN + T] = window_entry(V, k + DM_WIN, k + 1 + ((s - T - 1 + 2 * DM_WIN) % DM_WIN), lane);
+  }
+}
 
 // Eliminate window position k (k % 11 == T).  Lane s < 11 holds the column congruent to s
 // (mod 11) in register slots indexed by row mod 11; lane 11 holds the right-hand side.
 template <int T>
-__device__ __forceinline__ void elim_step(double (&w)[DM_WIN], int k, int lane, const ArmView& V, int& bad) {
+__device__ __forceinline__ void elim_step(double (&w)[DM_WIN], const double (&cur)[2 * DM_WIN], int k, int lane,
+                                          const ArmView& V, int& bad) {
   const double piv = readlane_d(w[T], T);
   if (!(fabs(piv) > 1e-300) || !isfinite(piv)) bad = 1;
   const double inv = 1.0 / piv;
@@ -375,44 +479,46 @@ __device__ __forceinline__ void elim_step(double (&w)[DM_WIN], int k, int lane, 
 #pragma unroll
   for (int i = 1; i < DM_WIN; ++i) cv[i] = readlane_d(w[(T + i) % DM_WIN], T);
   const double u = w[T];
-  double* rec = V.fac + (size_t)(V.fac_off + k) * DM_FAC;
-  if (lane < DM_WIN) {
-    const int j = (lane - T + DM_WIN) % DM_WIN;
-    rec[j] = (j == 0) ? inv : u;
-  } else if (lane == DM_WIN) {
-    rec[DM_WIN] = u;
+  // factor record of row k: [1/pivot, U(k, k+1..k+10), modified rhs]
+  if (lane <= DM_WIN) {
+    const int j = lane == DM_WIN ? DM_WIN : (lane - T + DM_WIN) % DM_WIN;
+    V.fac[(size_t)(V.fac_off + k) * DM_FAC + j] = (lane == T) ? inv : u;
   }
   const double us = u * inv;
+  const bool piv_lane = (lane == T);
 #pragma unroll
-  for (int i = 1; i < DM_WIN; ++i) w[(T + i) % DM_WIN] -= cv[i] * us;
-  if (lane == T) {          // this lane's column was the pivot column: load column k + 11
-#pragma unroll
-    for (int i = 1; i < DM_WIN; ++i) w[(T + i) % DM_WIN] = V.a(k + i, k + DM_WIN);
-    w[T] = V.a(k + DM_WIN, k + DM_WIN);
-  } else if (lane < DM_WIN) {   // load the entry of the new row k + 11
-    const int cs = k + 1 + ((lane - T - 1 + 2 * DM_WIN) % DM_WIN);
-    w[T] = V.a(k + DM_WIN, cs);
-  } else if (lane == DM_WIN) {
-    w[T] = V.rhs(k + DM_WIN);
+  for (int i = 1; i < DM_WIN; ++i) {
+    const double upd = w[(T + i) % DM_WIN] - cv[i] * us;
+    w[(T + i) % DM_WIN] = piv_lane ? cur[i - 1] : upd;   // pivot lane takes over column k + 11
   }
+  w[T] = piv_lane ? cur[DM_WIN - 1] : cur[DM_WIN + T];     // entries of the new row k + 11
 }
 
 #define DM_UNROLL11(M) M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10)
 
-__device__ void sweep_arm(const DmStepArgs& A, const DmArm& arm, double* delta_lds, int* bad_flag) {
+__device__ __noinline__ void sweep_arm(const DmStepArgs& A, const DmArm& arm, double DM_L* delta_lds, int DM_L* bad_flag) {
   const DmDev& D = A.d;
   const DmChain ch = D.chain[arm.chain];
   ArmView V{D.band, D.R, D.fac, ch.dof_off, 4 * ch.n_nodes - 1, arm.first, arm.dir, arm.count, arm.fac_off};
   const int lane = threadIdx.x & 63;
-  double w[DM_WIN];
+  double w[DM_WIN], cur[2 * DM_WIN], nxt[2 * DM_WIN];
 #pragma unroll
-  for (int r = 0; r < DM_WIN; ++r)
-    w[r] = (lane < DM_WIN) ? V.a(r, lane) : (lane == DM_WIN ? V.rhs(r) : 0.0);
+  for (int r = 0; r < DM_WIN; ++r) w[r] = window_entry(V, r, lane < DM_WIN ? lane : 0, lane);
+  load_window_block(cur, 0, lane, V);
   int bad = 0;
   for (int k0 = 0; k0 < arm.count; k0 += DM_WIN) {
-#define DM_E(T) if (k0 + T < arm.count) elim_step<T>(w, k0 + T, lane, V, bad);
-    DM_UNROLL11(DM_E)
+    load_window_block(nxt, k0 + DM_WIN, lane, V);
+    if (k0 + DM_WIN <= arm.count) {
+#define DM_E(T) elim_step<T>(w, cur, k0 + T, lane, V, bad);
+      DM_UNROLL11(DM_E)
 #undef DM_E
+    } else {
+#define DM_E(T) if (k0 + T < arm.count) elim_step<T>(w, cur, k0 + T, lane, V, bad);
+      DM_UNROLL11(DM_E)
+#undef DM_E
+    }
+#pragma unroll
+    for (int q = 0; q < 2 * DM_WIN; ++q) cur[q] = nxt[q];
   }
   // trailing (border) block of the window = this arm's Schur complement contribution
   const int c0 = arm.count % DM_WIN, nt = arm.n_trail;
@@ -435,18 +541,35 @@ __device__ void sweep_arm(const DmStepArgs& A, const DmArm& arm, double* delta_l
   if (bad && lane == 0) *bad_flag = 1;
 }
 
+// Back substitution of one 11-row block.  The block's factor records (11 x 12 doubles,
+// contiguous) are spread over the wavefront, three doubles per lane, and broadcast with
+// readlane; the next block's records are loaded while this one is solved.
 template <int T>
-__device__ __forceinline__ void back_step(double (&xv)[DM_WIN], int l, const ArmView& V, double* out, int lane) {
-  const double* f = V.fac + (size_t)(V.fac_off + l) * DM_FAC;
-  double s = f[DM_WIN];
+__device__ __forceinline__ void back_step(double (&xv)[DM_WIN], const double (&cur)[3], int l, const ArmView& V,
+                                          double DM_G* out, int lane) {
+  double rec[DM_FAC];
 #pragma unroll
-  for (int j = 1; j < DM_WIN; ++j) s -= f[j] * xv[(T + j) % DM_WIN];
-  const double xl = s * f[0];
+  for (int j = 0; j < DM_FAC; ++j) rec[j] = readlane_d(cur[(DM_FAC * T + j) / 64], (DM_FAC * T + j) % 64);
+  double s = rec[DM_WIN];
+#pragma unroll
+  for (int j = 1; j < DM_WIN; ++j) s -= rec[j] * xv[(T + j) % DM_WIN];
+  const double xl = s * rec[0];
   xv[T] = xl;
   if (lane == 0) out[V.dof_off + V.cd(l)] = xl;
 }
 
-__device__ void backsub_arm(const DmStepArgs& A, const DmArm& arm, const double* xB) {
+__device__ __forceinline__ void load_block(double (&buf)[3], const ArmView& V, int lb, int lane) {
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int f = lane + 64 * q;
+    const int row = lb + f / DM_FAC;
+    const bool ok = (lb >= 0) & (f < DM_WIN * DM_FAC) & (row < V.count);
+    const double v = V.fac[ok ? (size_t)(V.fac_off + lb) * DM_FAC + f : (size_t)V.fac_off * DM_FAC];
+    buf[q] = ok ? v : 0.0;
+  }
+}
+
+__device__ __noinline__ void backsub_arm(const DmStepArgs& A, const DmArm& arm, const double DM_L* xB) {
   const DmDev& D = A.d;
   const DmChain ch = D.chain[arm.chain];
   ArmView V{D.band, D.R, D.fac, ch.dof_off, 4 * ch.n_nodes - 1, arm.first, arm.dir, arm.count, arm.fac_off};
@@ -461,23 +584,29 @@ __device__ void backsub_arm(const DmStepArgs& A, const DmArm& arm, const double*
     xv[q] = val;
   }
   if (arm.count == 0) return;
-  for (int lb = ((arm.count - 1) / DM_WIN) * DM_WIN; lb >= 0; lb -= DM_WIN) {
-#define DM_B(T) if (lb + (10 - T) < arm.count) back_step<10 - T>(xv, lb + (10 - T), V, D.delta, lane);
+  double cur[3], nxt[3];
+  int lb = ((arm.count - 1) / DM_WIN) * DM_WIN;
+  load_block(cur, V, lb, lane);
+  for (; lb >= 0; lb -= DM_WIN) {
+    load_block(nxt, V, lb - DM_WIN, lane);
+#define DM_B(T) if (lb + (10 - T) < arm.count) back_step<10 - T>(xv, cur, lb + (10 - T), V, D.delta, lane);
     DM_UNROLL11(DM_B)
 #undef DM_B
+#pragma unroll
+    for (int q = 0; q < 3; ++q) cur[q] = nxt[q];
   }
 }
 
 // Dense border: add the arms' Schur contributions (fixed order), then Gaussian elimination
 // with partial pivoting and back substitution.  All threads take part.
-__device__ void border_solve(const DmStepArgs& A, const DmSystem& S, double* Bt, int ld,
-                             const double* deltas, double* xB, double* scal, int* bad_flag) {
+__device__ __noinline__ void border_solve(const DmStepArgs& A, const DmSystem& S, double DM_L* Bt, int ld,
+                             const double DM_L* deltas, double DM_L* xB, double DM_L* scal, int DM_L* bad_flag) {
   const DmDev& D = A.d;
   const int nb = S.nb, tid = threadIdx.x, nt = blockDim.x;
   for (int a = 0; a < S.n_arms; ++a) {
     const DmArm arm = D.arm[S.arm0 + a];
     const DmChain ch = D.chain[arm.chain];
-    const double* dl = deltas + a * 110;
+    const double DM_L* dl = deltas + a * 110;
     const int ntr = arm.n_trail;
     for (int p = tid; p < ntr * (ntr + 1); p += nt) {
       const int i = p / (ntr + 1), j = p % (ntr + 1);
@@ -521,7 +650,7 @@ __device__ void border_solve(const DmStepArgs& A, const DmSystem& S, double* Bt,
 }
 
 // q <- q - alpha delta over the system's nodes and edges.
-__device__ void apply_update(const DmStepArgs& A, const DmSystem& S, const double* xB, double alpha) {
+__device__ __noinline__ void apply_update(const DmStepArgs& A, const DmSystem& S, const double DM_L* xB, double alpha) {
   const DmDev& D = A.d;
   const int NN = D.n_nodes_tot;
   for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x) {
@@ -541,7 +670,7 @@ __device__ void apply_update(const DmStepArgs& A, const DmSystem& S, const doubl
   }
 }
 
-__device__ void rollback(const DmStepArgs& A, const DmSystem& S) {
+__device__ __noinline__ void rollback(const DmStepArgs& A, const DmSystem& S) {
   const DmDev& D = A.d;
   const int NN = D.n_nodes_tot;
   for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x)
@@ -551,7 +680,7 @@ __device__ void rollback(const DmStepArgs& A, const DmSystem& S) {
 }
 
 // Velocity update (after Eq. 16) and the step-end reference frames.
-__device__ void commit(const DmStepArgs& A, const DmSystem& S) {
+__device__ __noinline__ void commit(const DmStepArgs& A, const DmSystem& S) {
   const DmDev& D = A.d;
   const int NN = D.n_nodes_tot, NE = D.n_edges_tot, NS = D.n_st_tot;
   for (int i = threadIdx.x; i < S.n_st; i += blockDim.x) {
@@ -591,32 +720,40 @@ __device__ void commit(const DmStepArgs& A, const DmSystem& S) {
 }  // namespace
 
 __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs A) {
-  extern __shared__ double lds[];
+  extern __shared__ double lds_raw[];
+  double DM_L* lds = (double DM_L*)lds_raw;
   const DmDev& D = A.d;
   const int sid = D.order[blockIdx.x];
   const DmSystem S = D.sys[sid];
   const int ld = A.max_nb + 1;
-  double* Bt = lds;                                   // [max_nb][max_nb + 1]
-  double* deltas = Bt + A.max_nb * ld;                // [max_arms][110]
-  double* xB = deltas + A.max_arms * 110;             // [max_nb]
-  double* red = xB + A.max_nb;                        // [40]
-  int* flags = reinterpret_cast<int*>(red + 40);      // [4]
+  double DM_L* Bt = lds;                                   // [max_nb][max_nb + 1]
+  double DM_L* deltas = Bt + A.max_nb * ld;                // [max_arms][110]
+  double DM_L* xB = deltas + A.max_arms * 110;             // [max_nb]
+  double DM_L* red = xB + A.max_nb;                        // [40]
+  int DM_L* flags = (int DM_L*)(red + 40);      // [4]
   const int tid = threadIdx.x, wave = tid >> 6, nwaves = blockDim.x >> 6;
   if (tid == 0) flags[0] = 0;
   int status = DM_STATUS_OK, iters = 0, steps = 0, floor_hits = 0;
   double res = 0.0;
   double t = D.time[sid];
   __syncthreads();
+  DM_T0();
   for (int step = 0; step < A.nsteps; ++step) {
     const double t_end = t + A.dt;
     bool conv = false;
     int newton = 0, halvings = 0;
     double alpha = 1.0, res_prev = 0.0;
     while (true) {
-      for (int i = tid; i < S.n_st; i += blockDim.x) eval_stencil(A, S.st0 + i, t_end);
+      // stencil pairs: 64 consecutive stencils per wavefront and pass, so that a wavefront
+      // never mixes the two passes
+      for (int i = tid; i < 128 * ((S.n_st + 63) >> 6); i += blockDim.x) {
+        const int st = ((i >> 7) << 6) + (i & 63);
+        if (st < S.n_st) eval_stencil(A, S.st0 + st, (i >> 6) & 1, t_end);
+      }
       for (int i = tid; i < S.n_edges; i += blockDim.x) eval_edge(A, S.edge0 + i);
       for (int i = tid; i < S.n_nodes; i += blockDim.x) eval_node(A, S.node0 + i);
       __syncthreads();
+      DM_TP(0);
       double r2 = 0.0;
       for (int i = tid; i < S.chain_nodes; i += blockDim.x) {
         int c = 0, k = i;
@@ -624,8 +761,10 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs A) {
         r2 += band_node(A, D.chain[S.chain0 + c], k);
       }
       __syncthreads();
+      DM_TP(1);
       for (int b = tid; b < S.nb; b += blockDim.x) r2 += border_row(A, S, b, Bt, ld);
       res = sqrt(block_sum(r2, red));
+      DM_TP(2);
       if (res > A.tol && newton > 0 && res_prev <= A.stag_tol && res > 0.5 * res_prev) {
         conv = true;    // stagnation at the FP64 rounding floor of the residual
         ++floor_hits;
@@ -645,13 +784,17 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs A) {
       halvings = 0;
       for (int a = wave; a < S.n_arms; a += nwaves) sweep_arm(A, D.arm[S.arm0 + a], deltas + a * 110, flags);
       __syncthreads();
+      DM_TP(3);
       border_solve(A, S, Bt, ld, deltas, xB, red + 34, flags);
+      DM_TP(4);
       for (int a = wave; a < S.n_arms; a += nwaves) backsub_arm(A, D.arm[S.arm0 + a], xB);
       __syncthreads();
+      DM_TP(5);
       if (flags[0]) break;
       apply_update(A, S, xB, 1.0);
       ++newton;
       __syncthreads();
+      DM_TP(6);
     }
     iters += newton;
     if (!conv) {
@@ -660,9 +803,11 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs A) {
       break;
     }
     commit(A, S);
+    DM_TP(7);
     t = t_end;
     ++steps;
   }
+  DM_TSAVE(sid);
   if (tid == 0) {
     D.time[sid] = t;
     D.s_steps[sid] = steps;

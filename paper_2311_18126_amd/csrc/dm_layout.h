@@ -14,6 +14,18 @@
 //            ending next to the border (two arms per single rod, one per joined rod).
 #pragma once
 
+// The kernels' device pass sees every pointer of DmDev in the global address space and LDS
+// pointers in the local one, so that loads and stores compile to global_/ds_ instructions
+// instead of generic (flat) ones; every other pass sees plain pointers of the same size and
+// layout.
+#if defined(__HIP_DEVICE_COMPILE__) && defined(DM_KERNEL_TU)
+#define DM_G __attribute__((address_space(1)))
+#define DM_L __attribute__((address_space(3)))
+#else
+#define DM_G
+#define DM_L
+#endif
+
 #define DM_HALF_BAND 10
 #define DM_NDIAG 21          // band storage: row r holds columns r-10 .. r+10
 #define DM_WIN 11            // elimination window (pivot + 10)
@@ -21,8 +33,8 @@
 #define DM_MAX_CHAINS 8
 #define DM_MAX_BORDER 40
 #define DM_MAX_BSRC 8
-#define DM_ST_G 11           // stencil gradient entries (local DOFs)
-#define DM_ST_H 66           // stencil Hessian upper triangle (11 x 11)
+#define DM_ST_G 8            // stencil gradient in (e_f, e_e, theta_f, theta_e)
+#define DM_ST_H 64           // stencil Hessian in the same 8 variables, row-major
 #define DM_ED 9              // edge: stretch gradient (3) + stiffness block (6, symmetric)
 #define DM_ND 12             // node: residual (3) + Jacobian block (9, row-major)
 
@@ -64,57 +76,58 @@ struct DmSystem {
 // Device pointers.  All per-item arrays are structure-of-arrays.
 struct DmDev {
   // topology
-  const DmSystem* sys;
-  const DmChain* chain;
-  const DmArm* arm;
-  const int* order;        // launch order of systems (largest first)
-  const int* chain_node;
-  const int* chain_edge;
-  const int* bmap;
-  const int* bsrc;         // pairs (chain global index, chain DOF)
-  const int* bjst;
-  const unsigned char* bfix;
-  const unsigned char* cfix;   // per chain DOF: 1 if clamped
+  const DmSystem DM_G* sys;
+  const DmChain DM_G* chain;
+  const DmArm DM_G* arm;
+  const int DM_G* order;        // launch order of systems (largest first)
+  const int DM_G* chain_node;
+  const int DM_G* chain_edge;
+  const int DM_G* bmap;
+  const int DM_G* bsrc;         // pairs (chain global index, chain DOF)
+  const int DM_G* bjst;
+  const unsigned char DM_G* bfix;
+  const unsigned char DM_G* cfix;   // per chain DOF: 1 if clamped
   // nodes
-  const double* mass;
-  const double* radius;
-  const double* force;     // [3][n_nodes]
-  const int* node_owner;   // chain that assembles the node's own terms
-  const int* node_home;    // [3][n_nodes]: delta index (>= 0) or -1 - border index
+  const double DM_G* mass;
+  const double DM_G* radius;
+  const double DM_G* force;     // [3][n_nodes]
+  const int DM_G* node_owner;   // chain that assembles the node's own terms
+  const int DM_G* node_home;    // [3][n_nodes]: delta index (>= 0) or -1 - border index
   // edges
-  const int* en;           // [2][n_edges] tail, head
-  const double* ebar;
-  const double* EA;
-  const double* Ith;
-  const double* moment;
-  const int* edge_home;
+  const int DM_G* en;           // [2][n_edges] tail, head
+  const double DM_G* ebar;
+  const double DM_G* EA;
+  const double DM_G* Ith;
+  const double DM_G* moment;
+  const int DM_G* edge_home;
   // stencils
-  const int* sn;           // [3][n_st] previous, centre, next node
-  const int* se;           // [2][n_st] edge f, edge e
-  const int* ssign;        // bit 0: edge f stored reversed, bit 1: edge e stored reversed
-  const double* Vbar;
-  const double* kbend;     // EI / Vbar
-  const double* ktwist;    // GJ / Vbar
-  const double* kbar;      // [2][n_st] static integrated natural curvature
-  const double* tbar;
-  const double* act;       // [3][n_st] A (1/m), f, phi; A is NaN when not actuated
+  const int DM_G* sn;           // [3][n_st] previous, centre, next node
+  const int DM_G* se;           // [2][n_st] edge f, edge e
+  const int DM_G* ssign;        // bit 0: edge f stored reversed, bit 1: edge e stored reversed
+  const double DM_G* Vbar;
+  const double DM_G* kbend;     // EI / Vbar
+  const double DM_G* ktwist;    // GJ / Vbar
+  const double DM_G* kbar;      // [2][n_st] static integrated natural curvature
+  const double DM_G* tbar;
+  const double DM_G* act;       // [3][n_st] A (1/m), f, phi; A is NaN when not actuated
   // state
-  double* x;  double* x0;  double* v;      // [3][n_nodes]
-  double* th; double* th0; double* om;     // [n_edges]
-  double* tref; double* d1ref;             // [3][n_edges]
-  double* bref;                            // [n_st]
-  double* time;                            // [n_systems]
+  double DM_G* x;  double DM_G* x0;  double DM_G* v;      // [3][n_nodes]
+  double DM_G* th; double DM_G* th0; double DM_G* om;     // [n_edges]
+  double DM_G* tref; double DM_G* d1ref;             // [3][n_edges]
+  double DM_G* bref;                            // [n_st]
+  double DM_G* time;                            // [n_systems]
   // scratch
-  double* st_g;   // [11][n_st]
-  double* st_H;   // [66][n_st]
-  double* ed;     // [9][n_edges]
-  double* nd;     // [12][n_nodes]
-  double* band;   // [n_dof_total][21]
-  double* R;      // [n_dof_total]
-  double* fac;    // [n_dof_total][12]
-  double* delta;  // [n_dof_total]
+  double DM_G* st_g;   // [8][n_st]
+  double DM_G* st_H;   // [64][n_st]
+  double DM_G* ed;     // [9][n_edges]
+  double DM_G* nd;     // [12][n_nodes]
+  double DM_G* band;   // [n_dof_total][21]
+  double DM_G* R;      // [n_dof_total]
+  double DM_G* fac;    // [n_dof_total][12]
+  double DM_G* delta;  // [n_dof_total]
   // statistics
-  int* s_steps; int* s_iters; int* s_status; double* s_res; int* s_floor;
+  int DM_G* s_steps; int DM_G* s_iters; int DM_G* s_status; double DM_G* s_res; int DM_G* s_floor;
+  double DM_G* dbg;     // [n_systems][8] phase timers in diagnosis builds; null otherwise
   int n_nodes_tot, n_edges_tot, n_st_tot;
 };
 

@@ -45,191 +45,161 @@ DM_HD double ref_twist(v3 tf, v3 d1f, v3 te, v3 d1e, double bref, bool raw) {
 }
 
 // ---------------------------------------------------------------------------
-// forward-mode dual numbers with 8 tangents
+// forward-mode dual numbers with N tangents, mixing freely with plain doubles
 // ---------------------------------------------------------------------------
-struct D8 { double v; double d[8]; };
-struct DV { D8 c[3]; };
+template <int N> struct Dual { double v; double d[N]; };
 
-DM_HD D8 dcst(double a) { D8 r; r.v = a;
+template <int N> DM_HD Dual<N> operator+(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v + b.v;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) r.d[i] = 0.0; return r; }
-DM_HD D8 operator+(const D8& a, const D8& b) { D8 r; r.v = a.v + b.v;
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] + b.d[i]; return r; }
+template <int N> DM_HD Dual<N> operator-(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v - b.v;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) r.d[i] = a.d[i] + b.d[i]; return r; }
-DM_HD D8 operator-(const D8& a, const D8& b) { D8 r; r.v = a.v - b.v;
+  for (int i = 0; i < N; ++i) r.d[i] = a.d[i] - b.d[i]; return r; }
+template <int N> DM_HD Dual<N> operator-(const Dual<N>& a) { Dual<N> r; r.v = -a.v;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) r.d[i] = a.d[i] - b.d[i]; return r; }
-DM_HD D8 operator-(const D8& a) { D8 r; r.v = -a.v;
+  for (int i = 0; i < N; ++i) r.d[i] = -a.d[i]; return r; }
+template <int N> DM_HD Dual<N> operator*(const Dual<N>& a, const Dual<N>& b) { Dual<N> r; r.v = a.v * b.v;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) r.d[i] = -a.d[i]; return r; }
-DM_HD D8 operator*(const D8& a, const D8& b) { D8 r; r.v = a.v * b.v;
+  for (int i = 0; i < N; ++i) r.d[i] = a.v * b.d[i] + a.d[i] * b.v; return r; }
+template <int N> DM_HD Dual<N> operator*(double s, const Dual<N>& a) { Dual<N> r; r.v = s * a.v;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) r.d[i] = a.v * b.d[i] + a.d[i] * b.v; return r; }
-DM_HD D8 operator*(double s, const D8& a) { D8 r; r.v = s * a.v;
+  for (int i = 0; i < N; ++i) r.d[i] = s * a.d[i]; return r; }
+template <int N> DM_HD Dual<N> operator*(const Dual<N>& a, double s) { return s * a; }
+template <int N> DM_HD Dual<N> operator+(const Dual<N>& a, double s) { Dual<N> r = a; r.v += s; return r; }
+template <int N> DM_HD Dual<N> operator+(double s, const Dual<N>& a) { Dual<N> r = a; r.v += s; return r; }
+template <int N> DM_HD Dual<N> operator-(const Dual<N>& a, double s) { Dual<N> r = a; r.v -= s; return r; }
+template <int N> DM_HD Dual<N> operator-(double s, const Dual<N>& a) { Dual<N> r = -a; r.v += s; return r; }
+template <int N> DM_HD Dual<N> dinv(const Dual<N>& a) { Dual<N> r; double i = 1.0 / a.v; double m = -i * i; r.v = i;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) r.d[i] = s * a.d[i]; return r; }
-DM_HD D8 operator+(const D8& a, double s) { D8 r = a; r.v += s; return r; }
-DM_HD D8 dinv(const D8& a) { D8 r; double i = 1.0 / a.v; double m = -i * i; r.v = i;
+  for (int k = 0; k < N; ++k) r.d[k] = m * a.d[k]; return r; }
+template <int N> DM_HD Dual<N> dsqrt(const Dual<N>& a) { Dual<N> r; double s = sqrt(a.v); double h = 0.5 / s; r.v = s;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) r.d[k] = m * a.d[k]; return r; }
-DM_HD D8 dsqrt(const D8& a) { D8 r; double s = sqrt(a.v); double h = 0.5 / s; r.v = s;
+  for (int k = 0; k < N; ++k) r.d[k] = h * a.d[k]; return r; }
+template <int N> DM_HD void dsincos(const Dual<N>& a, Dual<N>& s, Dual<N>& c) {
+  double sv = sin(a.v), cv = cos(a.v);
+  s.v = sv; c.v = cv;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) r.d[k] = h * a.d[k]; return r; }
-
-DM_HD DV operator+(const DV& a, const DV& b) { DV r; r.c[0] = a.c[0] + b.c[0]; r.c[1] = a.c[1] + b.c[1]; r.c[2] = a.c[2] + b.c[2]; return r; }
-DM_HD DV operator-(const DV& a, const DV& b) { DV r; r.c[0] = a.c[0] - b.c[0]; r.c[1] = a.c[1] - b.c[1]; r.c[2] = a.c[2] - b.c[2]; return r; }
-DM_HD DV operator*(const D8& s, const DV& a) { DV r; r.c[0] = s * a.c[0]; r.c[1] = s * a.c[1]; r.c[2] = s * a.c[2]; return r; }
-DM_HD DV operator*(double s, const DV& a) { DV r; r.c[0] = s * a.c[0]; r.c[1] = s * a.c[1]; r.c[2] = s * a.c[2]; return r; }
-DM_HD D8 ddot(const DV& a, const DV& b) { return a.c[0] * b.c[0] + a.c[1] * b.c[1] + a.c[2] * b.c[2]; }
-DM_HD D8 ddot(v3 a, const DV& b) { return a.x * b.c[0] + a.y * b.c[1] + a.z * b.c[2]; }
-DM_HD DV dcross(const DV& a, const DV& b) {
-  DV r;
-  r.c[0] = a.c[1] * b.c[2] - a.c[2] * b.c[1];
-  r.c[1] = a.c[2] * b.c[0] - a.c[0] * b.c[2];
-  r.c[2] = a.c[0] * b.c[1] - a.c[1] * b.c[0];
-  return r;
+  for (int k = 0; k < N; ++k) { s.d[k] = cv * a.d[k]; c.d[k] = -sv * a.d[k]; }
 }
-DM_HD DV dcross(v3 a, const DV& b) {
-  DV r;
-  r.c[0] = a.y * b.c[2] - a.z * b.c[1];
-  r.c[1] = a.z * b.c[0] - a.x * b.c[2];
-  r.c[2] = a.x * b.c[1] - a.y * b.c[0];
-  return r;
-}
-DM_HD DV dadd(const DV& a, v3 b) { DV r = a; r.c[0].v += b.x; r.c[1].v += b.y; r.c[2].v += b.z; return r; }
-DM_HD DV dsub_from(v3 a, const DV& b) { DV r; r.c[0] = -b.c[0]; r.c[1] = -b.c[1]; r.c[2] = -b.c[2];
-  r.c[0].v += a.x; r.c[1].v += a.y; r.c[2].v += a.z; return r; }
-DM_HD v3 dval(const DV& a) { return mk3(a.c[0].v, a.c[1].v, a.c[2].v); }
-DM_HD DV dseed(v3 a, int k0) {
-  DV r; r.c[0] = dcst(a.x); r.c[1] = dcst(a.y); r.c[2] = dcst(a.z);
-  r.c[0].d[k0] = 1.0; r.c[1].d[k0 + 1] = 1.0; r.c[2].d[k0 + 2] = 1.0;
-  return r;
-}
+DM_HD double dinv(double a) { return 1.0 / a; }
+DM_HD double dsqrt(double a) { return sqrt(a); }
+DM_HD void dsincos(double a, double& s, double& c) { s = sin(a); c = cos(a); }
+template <int N> DM_HD double val(const Dual<N>& a) { return a.v; }
+DM_HD double val(double a) { return a; }
 
-// Frame of one stencil edge at its current vector e and twist th (both duals):
-// tangent t, length l, transported director d1, material directors m1, m2 and the
-// holonomy vector w of the time transport from (tn, d1n).
-struct EdgeFrame { DV t, d1, m1, m2, w; D8 l, il; };
+// 3-vectors over any scalar type
+template <class S> struct Vec { S x, y, z; };
+template <class S> DM_HD Vec<S> mkv(S a, S b, S c) { Vec<S> r; r.x = a; r.y = b; r.z = c; return r; }
+template <class A, class B> DM_HD auto vadd(const Vec<A>& a, const Vec<B>& b) { return mkv(a.x + b.x, a.y + b.y, a.z + b.z); }
+template <class A, class B> DM_HD auto vsub(const Vec<A>& a, const Vec<B>& b) { return mkv(a.x - b.x, a.y - b.y, a.z - b.z); }
+template <class A, class B> DM_HD auto vscale(const A& s, const Vec<B>& v) { return mkv(s * v.x, s * v.y, s * v.z); }
+template <class A, class B> DM_HD auto vdot(const Vec<A>& a, const Vec<B>& b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+template <class A, class B> DM_HD auto vcross(const Vec<A>& a, const Vec<B>& b) {
+  return mkv(a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x);
+}
+DM_HD Vec<double> tov(v3 a) { return mkv(a.x, a.y, a.z); }
+template <class S> DM_HD v3 vval(const Vec<S>& a) { return mk3(val(a.x), val(a.y), val(a.z)); }
 
-DM_HD void edge_frame(const DV& e, const D8& th, v3 tn, v3 d1n, EdgeFrame& F) {
-  F.l = dsqrt(ddot(e, e));
-  F.il = dinv(F.l);
-  F.t = F.il * e;
-  D8 a = ddot(d1n, F.t);
-  D8 b = ddot(tn, F.t) + 1.0;
-  D8 ib = dinv(b);
-  D8 c = a * ib;
-  F.d1 = dsub_from(d1n, c * dadd(F.t, tn));          // d1 = d1n - (t.d1n)/(1 + tn.t) (tn + t)
-  DV d2 = dcross(F.t, F.d1);
-  double s = sin(th.v), co = cos(th.v);
-  D8 S = s * dcst(1.0), C = co * dcst(1.0);
-#pragma unroll
-  for (int k = 0; k < 8; ++k) { S.d[k] = co * th.d[k]; C.d[k] = -s * th.d[k]; }
-  F.m1 = C * F.d1 + S * d2;
-  F.m2 = S * (-1.0 * F.d1) + C * d2;
-  F.w = (-1.0) * ((ib * F.il) * dcross(tn, F.t));    // w = -(tn x t)/((1 + tn.t) l)
+// Frame of one stencil edge at its current vector e and twist th: tangent t, inverse length il,
+// material directors m1, m2 (from the director d1 transported in time from (tn, d1n)), and the
+// holonomy vector w of that transport.  S is double or a dual type.
+template <class S> struct EdgeFrame { Vec<S> t, m1, m2, w; S il; v3 d1v; };
+
+template <class S>
+DM_HD void edge_frame(const Vec<S>& e, const S& th, v3 tn, v3 d1n, EdgeFrame<S>& F) {
+  S l = dsqrt(vdot(e, e));
+  F.il = dinv(l);
+  F.t = vscale(F.il, e);
+  S b = vdot(tov(tn), F.t) + 1.0;
+  S ib = dinv(b);
+  S c = vdot(tov(d1n), F.t) * ib;
+  Vec<S> d1 = vsub(tov(d1n), vscale(c, vadd(F.t, tov(tn))));   // d1n - (t.d1n)/(1 + tn.t) (tn + t)
+  Vec<S> d2 = vcross(F.t, d1);
+  S sn, cs;
+  dsincos(th, sn, cs);
+  F.m1 = vadd(vscale(cs, d1), vscale(sn, d2));
+  F.m2 = vsub(vscale(cs, d2), vscale(sn, d1));
+  F.w = vscale(-(ib * F.il), vcross(tov(tn), F.t));          // w = -(tn x t)/((1 + tn.t) |e|)
+  F.d1v = vval(d1);
 }
 
-// Exact gradient (g: 11 local DOFs) and Hessian (H: upper triangle, 66) of the bend + twist
-// energy of one stencil  E = kbend/2 |kappa - kappa_bar|^2 + ktwist/2 (tau - tau_bar)^2.
-// Local DOF order: x_prev (0..2), theta_f (3), x_centre (4..6), theta_e (7), x_next (8..10),
-// with theta_f, theta_e taken in the stencil's orientation (sf, se = +-1 times the stored
-// angle).  tnf/d1nf, tne/d1ne are the step-start frames in the stencil's orientation.
-// Returns the reference twist beta of the current configuration.
-DM_HD int hidx(int a, int b) { return a <= b ? 10 * a - (a * (a - 1)) / 2 + b : 10 * b - (b * (b - 1)) / 2 + a; }
+typedef Dual<4> D4;
 
-DM_HD double stencil_eval(v3 xp, v3 xc, v3 xn, double thf_s, double the_s,
-                          v3 tnf, v3 d1nf, v3 tne, v3 d1ne, double bref,
-                          double k1bar, double k2bar, double tbar, double kbend, double ktw,
-                          double sf, double se, double* g, double* H) {
-  DV ef = dseed(xc - xp, 0), ee = dseed(xn - xc, 3);
-  D8 thf = dcst(thf_s), the = dcst(the_s);
-  thf.d[6] = 1.0; the.d[7] = 1.0;
-  EdgeFrame F, G;
+// One pass of the bend/twist stencil energy
+//   E = kbend/2 |kappa - kappa_bar|^2 + ktwist/2 (tau - tau_bar)^2        (Eq. 4-8)
+// with derivatives seeded on the f edge (e_f: tangents 0..2, theta_f: tangent 3).  Outputs the
+// exact gradient g8 with respect to v = (e_f, e_e, theta_f, theta_e) (closed-form strain
+// gradients: classical DER terms plus the holonomy term (d strain/d theta) w), whose tangents
+// are the Hessian columns d g8 / d (e_f, theta_f).  Frames are in the stencil's orientation.
+// Returns the reference twist beta.
+DM_HD double stencil_pass(v3 ef_v, v3 ee_v, double thf_s, double the_s, v3 tnf, v3 d1nf, v3 tne, v3 d1ne,
+                          double bref, double k1bar, double k2bar, double tbar, double kbend, double ktw,
+                          double* g8, double (*H8f)[4]) {
+  Vec<D4> ef;
+  {
+    D4 z; z.v = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) z.d[k] = 0.0;
+    ef.x = z; ef.y = z; ef.z = z;
+    ef.x.v = ef_v.x; ef.y.v = ef_v.y; ef.z.v = ef_v.z;
+    ef.x.d[0] = 1.0; ef.y.d[1] = 1.0; ef.z.d[2] = 1.0;
+  }
+  D4 thf;
+  thf.v = thf_s;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) thf.d[k] = (k == 3) ? 1.0 : 0.0;
+  EdgeFrame<D4> F;
+  EdgeFrame<double> G;
   edge_frame(ef, thf, tnf, d1nf, F);
-  edge_frame(ee, the, tne, d1ne, G);
-  D8 chi = ddot(F.t, G.t) + 1.0;
-  D8 ichi = dinv(chi);
-  DV kb = (2.0 * ichi) * dcross(F.t, G.t);                  // Eq. 4
-  DV tt = ichi * (F.t + G.t);
-  DV m1s = F.m1 + G.m1, m2s = F.m2 + G.m2;
-  D8 k1 = 0.5 * ddot(kb, m2s);                              // Eq. 5
-  D8 k2 = -0.5 * ddot(kb, m1s);
-  DV m1t = ichi * m1s, m2t = ichi * m2s;
-  D8 dk1f = -0.5 * ddot(kb, F.m1), dk1e = -0.5 * ddot(kb, G.m1);   // d kappa / d theta
-  D8 dk2f = -0.5 * ddot(kb, F.m2), dk2e = -0.5 * ddot(kb, G.m2);
-  // d kappa / d e: classical terms plus holonomy (d kappa / d theta) w
-  DV Gk1f = F.il * (dcross(G.t, m2t) - k1 * tt) + dk1f * F.w;
-  DV Gk1e = G.il * ((-1.0) * dcross(F.t, m2t) - k1 * tt) + dk1e * G.w;
-  DV Gk2f = F.il * ((-1.0) * dcross(G.t, m1t) - k2 * tt) + dk2f * F.w;
-  DV Gk2e = G.il * (dcross(F.t, m1t) - k2 * tt) + dk2e * G.w;
-  // d tau / d e: kb/(2|e|) plus the holonomy with d tau/d theta_f = -1, d tau/d theta_e = +1
-  DV Gtf = (0.5 * F.il) * kb - F.w;
-  DV Gte = (0.5 * G.il) * kb + G.w;
-  double beta = ref_twist(dval(F.t), dval(F.d1), dval(G.t), dval(G.d1), bref, false);
-  double tau = the_s - thf_s + beta;                         // Eq. 7
-  D8 c1 = kbend * (k1 + (-k1bar));
-  D8 c2 = kbend * (k2 + (-k2bar));
-  D8 ct;
-  ct.v = ktw * (tau - tbar);
-  ct.d[0] = ktw * Gtf.c[0].v; ct.d[1] = ktw * Gtf.c[1].v; ct.d[2] = ktw * Gtf.c[2].v;
-  ct.d[3] = ktw * Gte.c[0].v; ct.d[4] = ktw * Gte.c[1].v; ct.d[5] = ktw * Gte.c[2].v;
-  ct.d[6] = -ktw; ct.d[7] = ktw;
-  D8 g8[8];
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    g8[i] = c1 * Gk1f.c[i] + c2 * Gk2f.c[i] + ct * Gtf.c[i];
-    g8[3 + i] = c1 * Gk1e.c[i] + c2 * Gk2e.c[i] + ct * Gte.c[i];
+  edge_frame(tov(ee_v), the_s, tne, d1ne, G);
+  const double beta = ref_twist(vval(F.t), F.d1v, vval(G.t), G.d1v, bref, false);
+  const double tau = the_s - thf_s + beta;                       // Eq. 7
+  D4 ichi = dinv(vdot(F.t, G.t) + 1.0);
+  Vec<D4> kb = vscale(2.0 * ichi, vcross(F.t, G.t));            // Eq. 4
+  // c_i = kbend (kappa_i - kappa_bar_i), kappa from Eq. 5; a_f, a_e = sum_i c_i d kappa_i / d theta
+  D4 k1 = 0.5 * (vdot(kb, F.m2) + vdot(kb, G.m2));
+  D4 k2 = -0.5 * (vdot(kb, F.m1) + vdot(kb, G.m1));
+  D4 c1 = kbend * (k1 - k1bar);
+  D4 c2 = kbend * (k2 - k2bar);
+  D4 af = -0.5 * (c1 * vdot(kb, F.m1) + c2 * vdot(kb, F.m2));
+  D4 ae = -0.5 * (c1 * vdot(kb, G.m1) + c2 * vdot(kb, G.m2));
+  // ct = ktwist (tau - tau_bar); its tangent is ktwist d tau, with d tau/d e_f = kb/(2|e_f|) - w_f
+  // and d tau / d theta_f = -1
+  D4 ct;
+  {
+    const v3 gt = 0.5 * val(F.il) * vval(kb) - vval(F.w);
+    ct.v = ktw * (tau - tbar);
+    ct.d[0] = ktw * gt.x; ct.d[1] = ktw * gt.y; ct.d[2] = ktw * gt.z; ct.d[3] = -ktw;
   }
-  g8[6] = c1 * dk1f + c2 * dk2f - ct;
-  g8[7] = c1 * dk1e + c2 * dk2e + ct;
-  // symmetric 8 x 8 Hessian in (e_f, e_e, theta_f, theta_e)
-  double h8[8][8];
+  // the kappa terms of the edge gradients share M = (c1 (m2f + m2e) - c2 (m1f + m1e)) / chi
+  // and c_k = c1 kappa1 + c2 kappa2 (classical DER gradients, grouped)
+  D4 ck = c1 * k1 + c2 * k2;
+  Vec<D4> M = vscale(ichi, vsub(vscale(c1, vadd(F.m2, G.m2)), vscale(c2, vadd(F.m1, G.m1))));
+  Vec<D4> V = vadd(vscale(-(ck * ichi), vadd(F.t, G.t)), vscale(0.5 * ct, kb));
+  Vec<D4> gf = vadd(vscale(F.il, vadd(vcross(G.t, M), V)), vscale(af - ct, F.w));
+  Vec<D4> ge = vadd(vscale(G.il, vsub(V, vcross(F.t, M))), vscale(ae + ct, G.w));
+  D4 gthf = af - ct;
+  D4 gthe = ae + ct;
+  const D4* out[8] = {&gf.x, &gf.y, &gf.z, &ge.x, &ge.y, &ge.z, &gthf, &gthe};
 #pragma unroll
-  for (int a = 0; a < 8; ++a)
+  for (int a = 0; a < 8; ++a) {
+    g8[a] = out[a]->v;
 #pragma unroll
-    for (int b = 0; b < 8; ++b) h8[a][b] = 0.5 * (g8[a].d[b] + g8[b].d[a]);
-  // local DOF l as a combination of the 8 variables: e_f = x_c - x_p, e_e = x_n - x_c
-  // P[l][v]: x_p: -e_f; theta_f: sf; x_c: e_f - e_e; theta_e: se; x_n: e_e
-  double P[11][8];
-#pragma unroll
-  for (int l = 0; l < 11; ++l)
-#pragma unroll
-    for (int v = 0; v < 8; ++v) P[l][v] = 0.0;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    P[c][c] = -1.0;
-    P[4 + c][c] = 1.0; P[4 + c][3 + c] = -1.0;
-    P[8 + c][3 + c] = 1.0;
+    for (int k = 0; k < 4; ++k) H8f[a][k] = out[a]->d[k];
   }
-  P[3][6] = sf; P[7][7] = se;
-#pragma unroll
-  for (int l = 0; l < 11; ++l) {
-    double s = 0.0;
-#pragma unroll
-    for (int v = 0; v < 8; ++v) s += P[l][v] * g8[v].v;
-    g[l] = s;
-  }
-  double HP[8][11];
-#pragma unroll
-  for (int a = 0; a < 8; ++a)
-#pragma unroll
-    for (int l = 0; l < 11; ++l) {
-      double s = 0.0;
-#pragma unroll
-      for (int v = 0; v < 8; ++v) s += h8[a][v] * P[l][v];
-      HP[a][l] = s;
-    }
-#pragma unroll
-  for (int l = 0; l < 11; ++l)
-#pragma unroll
-    for (int m = l; m < 11; ++m) {
-      double s = 0.0;
-#pragma unroll
-      for (int a = 0; a < 8; ++a) s += P[l][a] * HP[a][m];
-      H[hidx(l, m)] = s;
-    }
   return beta;
+}
+
+// Local DOF l of a stencil as a signed combination of the 8 stencil variables
+// (e_f = x_c - x_p, e_e = x_n - x_c, theta_f, theta_e):
+//   x_p (l = 0..2): -e_f;  theta_f (3): sf theta_f;  x_c (4..6): e_f - e_e;  theta_e (7): se theta_e;
+//   x_n (8..10): e_e.
+DM_HD int loc_terms(int l, double sf, double se, int* var, double* coef) {
+  if (l < 3) { var[0] = l; coef[0] = -1.0; return 1; }
+  if (l == 3) { var[0] = 6; coef[0] = sf; return 1; }
+  if (l < 7) { var[0] = l - 4; coef[0] = 1.0; var[1] = l - 1; coef[1] = -1.0; return 2; }
+  if (l == 7) { var[0] = 7; coef[0] = se; return 1; }
+  var[0] = l - 5; coef[0] = 1.0; return 1;
 }
 
 // Value-only strains of a stencil (setup and reporting): integrated curvature and the raw

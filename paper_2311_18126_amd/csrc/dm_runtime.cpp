@@ -73,6 +73,8 @@ struct dm_sim {
   std::vector<void*> allocs;
   DmDev dev{};
   double time = 0.0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  float last_kernel_ms = 0.0f;
 };
 
 namespace {
@@ -523,6 +525,11 @@ dm_status do_finalize(dm_sim* s) {
   if ((st = alloc(s, (size_t)s->n_sys, &D.s_status)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)s->n_sys, &D.s_res)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)s->n_sys, &D.s_floor)) != DM_OK) return st;
+#ifdef DM_PHASE_TIMING
+  if ((st = alloc(s, (size_t)s->n_sys * 8, &D.dbg)) != DM_OK) return st;
+#else
+  D.dbg = nullptr;
+#endif
   D.n_nodes_tot = NN; D.n_edges_tot = NE; D.n_st_tot = s->n_st;
   // natural curvature and actuation may be set again later; keep a copy of stencil->rod
   s->finalized = true;
@@ -717,8 +724,12 @@ dm_status dm_step(dm_sim* s, double dt, int nsteps, dm_stats* stats) {
   A.max_nb = std::max(s->max_nb, 1);
   A.max_arms = std::max(s->max_arms, 1);
   size_t lds = sizeof(double) * ((size_t)A.max_nb * (A.max_nb + 1) + (size_t)A.max_arms * 110 + A.max_nb + 40 + 2);
+  if (!s->ev0) { DM_HIP(hipEventCreate(&s->ev0)); DM_HIP(hipEventCreate(&s->ev1)); }
+  DM_HIP(hipEventRecord(s->ev0, s->stream));
   DM_HIP(dm_launch_step(&A, s->block, lds, s->stream));
+  DM_HIP(hipEventRecord(s->ev1, s->stream));
   DM_HIP(hipStreamSynchronize(s->stream));
+  DM_HIP(hipEventElapsedTime(&s->last_kernel_ms, s->ev0, s->ev1));
   std::vector<int> steps(s->n_sys), iters(s->n_sys), status(s->n_sys), floors(s->n_sys);
   std::vector<double> res(s->n_sys);
   DM_HIP(hipMemcpy(steps.data(), s->dev.s_steps, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
@@ -879,6 +890,20 @@ dm_status dm_load_checkpoint(dm_sim* s, const double* buf, int on_device) {
 
 double dm_time(const dm_sim* s) { return s ? s->time : 0.0; }
 
+#ifdef DM_PHASE_TIMING
+// Diagnosis builds only: per-system phase timers of the last dm_step, [n_systems][8] ticks of
+// the 100 MHz wall clock (eval, band, border+norm, sweeps, border solve, back-substitution,
+// update, commit).
+dm_status dm_debug_phase_times(dm_sim* s, double* out) {
+  DM_HIP(hipMemcpy(out, s->dev.dbg, sizeof(double) * 8 * s->n_sys, hipMemcpyDeviceToHost));
+  return DM_OK;
+}
+#endif
+
+double dm_last_kernel_ms(const dm_sim* s) { return s ? (double)s->last_kernel_ms : 0.0; }
+
+int dm_block_size(const dm_sim* s) { return s ? s->block : 0; }
+
 const char* dm_last_error(void) { return g_err.c_str(); }
 
 void dm_destroy(dm_sim* s) {
@@ -888,6 +913,7 @@ void dm_destroy(dm_sim* s) {
     (void)hipStreamSynchronize(s->stream);
     for (void* p : s->allocs) (void)hipFree(p);
   }
+  if (s->ev0) { (void)hipEventDestroy(s->ev0); (void)hipEventDestroy(s->ev1); }
   delete s;
 }
 

@@ -43,7 +43,9 @@ def test_cantilever_one_step_matches_live_oracle(dm):
     _, ost, infos, _ = der.simulate(d, steps=1, polish=1)
     assert st["status"][0] == 0 and st["steps"][0] == 1
     assert rel(x, ost.x.numpy()) < 1e-9
-    assert rel(v, ost.v.numpy()) < 1e-7
+    # v = (x - x_n)/dt: a converged step may sit anywhere within the Newton tolerance,
+    # 1e-9 N / (m/dt^2) ~ 1.6e-9 m here, i.e. ~2e-7 of |v|
+    assert rel(v, ost.v.numpy()) < 1e-6
     assert np.abs(th - ost.theta.numpy()).max() < 1e-9
 
 
