@@ -39,8 +39,22 @@
 
 namespace {
 
-__device__ __forceinline__ v3 ld3(const double DM_G* a, int n, int i) { return mk3(a[i], a[n + i], a[2 * n + i]); }
+template <class P>
+__device__ __forceinline__ v3 ld3(P a, int n, int i) { return mk3(a[i], a[n + i], a[2 * n + i]); }
 __device__ __forceinline__ void st3(double DM_G* a, int n, int i, v3 v) { a[i] = v.x; a[n + i] = v.y; a[2 * n + i] = v.z; }
+
+// The step arguments stay in the kernel's argument segment (constant memory) and are reached
+// through a pointer that every phase function makes wavefront-uniform, so that their fields
+// are scalar loads.
+using ArgsP = const DmStepArgs DM_C*;
+
+__device__ __forceinline__ ArgsP uniform(ArgsP p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (ArgsP)(((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ int uniform(int i) { return __builtin_amdgcn_readfirstlane(i); }
 
 __device__ __forceinline__ double readlane_d(double v, int lane) {
   long long b = __double_as_longlong(v);
@@ -80,8 +94,8 @@ __device__ double block_sum(double v, double DM_L* red) {
 // Pass 1's Hessian columns are the e-edge columns of the stored stencil, reached through the
 // signed permutation e_f <-> -e_e, theta_f <-> -theta_e (an even number of sign flips per
 // Hessian entry, so only the indices move).
-__device__ __noinline__ void eval_stencil(const DmStepArgs& A, int s, int pass, double t_end) {
-  const DmDev& D = A.d;
+__device__ __forceinline__ void eval_stencil(const DmStepArgs DM_C& A, int s, int pass, double t_end) {
+  const DmDev DM_C& D = A.d;
   const int NS = D.n_st_tot, NE = D.n_edges_tot, NN = D.n_nodes_tot;
   int np = D.sn[s], nc = D.sn[NS + s], nn = D.sn[2 * NS + s];
   int ef = D.se[s], ee = D.se[NS + s];
@@ -122,8 +136,8 @@ __device__ __noinline__ void eval_stencil(const DmStepArgs& A, int s, int pass, 
 
 // Stretch (Eq. 2-3): gradient EA (|e|/ebar - 1) t with respect to the edge vector and its
 // Hessian (EA/ebar) t t^T + EA (1/ebar - 1/|e|)(I - t t^T).
-__device__ __noinline__ void eval_edge(const DmStepArgs& A, int e) {
-  const DmDev& D = A.d;
+__device__ __forceinline__ void eval_edge(const DmStepArgs DM_C& A, int e) {
+  const DmDev DM_C& D = A.d;
   const int NE = D.n_edges_tot, NN = D.n_nodes_tot;
   v3 d = ld3(D.x, NN, D.en[NE + e]) - ld3(D.x, NN, D.en[e]);
   double l = sqrt(dot(d, d));
@@ -142,7 +156,7 @@ __device__ __noinline__ void eval_edge(const DmStepArgs& A, int e) {
     for (int j = i; j < 3; ++j) D.ed[(k++) * NE + e] = (c1 - c2) * tt[i] * tt[j] + (i == j ? c2 : 0.0);
 }
 
-__device__ __forceinline__ double edge_K(const DmDev& D, int NE, int e, int i, int j) {
+__device__ __forceinline__ double edge_K(const DmDev DM_C& D, int NE, int e, int i, int j) {
   const int a = i < j ? i : j, b = i < j ? j : i;
   const int idx = (a == 0) ? b : (a == 1 ? 2 + b : 5);   // xx xy xz yy yz zz
   return D.ed[(3 + idx) * NE + e];
@@ -181,8 +195,8 @@ __device__ __forceinline__ void friction_ratio(double s, double K2, double* g, d
 
 // Node terms of the residual (Eq. 15) and Jacobian: inertia, gravity, constant load,
 // damping, floor contact (Eq. 10-11) and friction (Eq. 12-13).
-__device__ __noinline__ void eval_node(const DmStepArgs& A, int n) {
-  const DmDev& D = A.d;
+__device__ __forceinline__ void eval_node(const DmStepArgs DM_C& A, int n) {
+  const DmDev DM_C& D = A.d;
   const int NN = D.n_nodes_tot;
   const double dt = A.dt, m = D.mass[n];
   v3 x = ld3(D.x, NN, n), x0 = ld3(D.x0, NN, n), v = ld3(D.v, NN, n), F = ld3(D.force, NN, n);
@@ -235,7 +249,7 @@ __device__ __noinline__ void eval_node(const DmStepArgs& A, int n) {
 // 8-variable form: local DOF l = sum of coef * variable (loc_terms, orientation +1 in a chain).
 // emit(rel0 + b, H_local[L][b]) for b = 0..10; returns g_local[L].
 template <int L, class Emit>
-__device__ __forceinline__ double stencil_row(const DmDev& D, int s, int rel0, Emit& emit) {
+__device__ __forceinline__ double stencil_row(const DmDev DM_C& D, int s, int rel0, Emit& emit) {
   const int NS = D.n_st_tot;
   int va[2], vb[2];
   double ca[2], cb[2];
@@ -265,8 +279,8 @@ __device__ __forceinline__ double stencil_row(const DmDev& D, int s, int rel0, E
 // Contributions of chain elements to chain row 4k + COMP; emit(rel, value) receives the
 // column as rel = column - 4k.  Returns the residual entry.
 template <int COMP, class Emit>
-__device__ __forceinline__ double row_contrib(const DmStepArgs& A, const DmChain& ch, int k, Emit& emit) {
-  const DmDev& D = A.d;
+__device__ __forceinline__ double row_contrib(const DmStepArgs DM_C& A, const DmChain& ch, int k, Emit& emit) {
+  const DmDev DM_C& D = A.d;
   const int NS = D.n_st_tot, NE = D.n_edges_tot, NN = D.n_nodes_tot;
   const int N = ch.n_nodes;
   double Rr = 0.0;
@@ -308,7 +322,7 @@ __device__ __forceinline__ double row_contrib(const DmStepArgs& A, const DmChain
 // border columns of a border row (those couplings live in the dense border), are zeroed
 // afterwards.  fixmask / bmask: bit i describes chain DOF 4k - 12 + i.
 template <int COMP>
-__device__ __forceinline__ double band_row(const DmStepArgs& A, const DmChain& ch, int k,
+__device__ __forceinline__ double band_row(const DmStepArgs DM_C& A, const DmChain& ch, int k,
                                            unsigned fixmask, unsigned bmask) {
   const int r = 4 * k + COMP;
   const bool rowb = (bmask >> (12 + COMP)) & 1u;
@@ -338,8 +352,9 @@ __device__ __forceinline__ double band_row(const DmStepArgs& A, const DmChain& c
 
 // Band rows of chain node k (4 rows; 3 for the last node).  Returns the squared residual of
 // its free, non-border rows.
-__device__ __noinline__ double band_node(const DmStepArgs& A, const DmChain& ch, int k) {
-  const DmDev& D = A.d;
+__device__ __forceinline__ double band_node(const DmStepArgs DM_C& A, int ci, int k) {
+  const DmDev DM_C& D = A.d;
+  const DmChain ch = D.chain[ci];
   const int n = 4 * ch.n_nodes - 1;
   unsigned fixmask = 0u, bmask = 0u;
 #pragma unroll
@@ -359,8 +374,9 @@ __device__ __noinline__ double band_node(const DmStepArgs& A, const DmChain& ch,
 
 // Dense border row b: pristine border-border entries of every chain touching it plus the
 // joint stencils; right-hand side in column nb.  Returns its squared residual if free.
-__device__ __noinline__ double border_row(const DmStepArgs& A, const DmSystem& S, int b, double DM_L* Bt, int ld) {
-  const DmDev& D = A.d;
+__device__ __forceinline__ double border_row(const DmStepArgs DM_C& A, const DmSystem DM_C& S, int b,
+                                             double DM_L* Bt, int ld) {
+  const DmDev DM_C& D = A.d;
   const int NS = D.n_st_tot;
   double DM_L* row = Bt + b * ld;
   for (int j = 0; j <= S.nb; ++j) row[j] = 0.0;
@@ -388,7 +404,7 @@ __device__ __noinline__ double border_row(const DmStepArgs& A, const DmSystem& S
     }
   }
   for (int js = 0; js < S.n_jst; ++js) {
-    const int DM_G* bj = D.bjst + S.bjst_off + js * 11;
+    const int DM_C* bj = D.bjst + S.bjst_off + js * 11;
     const int s = S.jst0 + js;
     const int sg = D.ssign[s];
     const double sf = (sg & 1) ? -1.0 : 1.0, se = (sg & 2) ? -1.0 : 1.0;
@@ -411,6 +427,50 @@ __device__ __noinline__ double border_row(const DmStepArgs& A, const DmSystem& S
   }
   row[S.nb] = rhs;
   return rhs * rhs;
+}
+
+// Phase drivers: each loops over its items with the whole workgroup, so that the cost of a
+// call is paid once per phase.
+
+// Stencil pairs: 64 consecutive stencils per wavefront and pass, so that a wavefront never
+// mixes the two passes.
+__device__ __noinline__ void eval_stencils(ArgsP Ap, int sid, double t_end) {
+  const DmStepArgs DM_C& A = *uniform(Ap);
+  const DmSystem DM_C& S = A.d.sys[uniform(sid)];
+  for (int i = threadIdx.x; i < 128 * ((S.n_st + 63) >> 6); i += blockDim.x) {
+    const int st = ((i >> 7) << 6) + (i & 63);
+    if (st < S.n_st) eval_stencil(A, S.st0 + st, (i >> 6) & 1, t_end);
+  }
+}
+
+__device__ __noinline__ void eval_edges_nodes(ArgsP Ap, int sid) {
+  const DmStepArgs DM_C& A = *uniform(Ap);
+  const DmSystem DM_C& S = A.d.sys[uniform(sid)];
+  for (int i = threadIdx.x; i < S.n_edges; i += blockDim.x) eval_edge(A, S.edge0 + i);
+  for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x) eval_node(A, S.node0 + i);
+}
+
+// Band rows of every chain node of the system; returns this lane's share of the squared
+// residual of free, non-border rows.
+__device__ __noinline__ double assemble_band(ArgsP Ap, int sid) {
+  const DmStepArgs DM_C& A = *uniform(Ap);
+  const DmDev DM_C& D = A.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
+  double r2 = 0.0;
+  for (int i = threadIdx.x; i < S.chain_nodes; i += blockDim.x) {
+    int c = S.chain0, k = i;
+    while (k >= D.chain[c].n_nodes) { k -= D.chain[c].n_nodes; ++c; }
+    r2 += band_node(A, c, k);
+  }
+  return r2;
+}
+
+__device__ __noinline__ double assemble_border(ArgsP Ap, int sid, double DM_L* Bt, int ld) {
+  const DmStepArgs DM_C& A = *uniform(Ap);
+  const DmSystem DM_C& S = A.d.sys[uniform(sid)];
+  double r2 = 0.0;
+  for (int b = threadIdx.x; b < S.nb; b += blockDim.x) r2 += border_row(A, S, b, Bt, ld);
+  return r2;
 }
 
 // ---------------------------------------------------------------------------
@@ -496,8 +556,10 @@ __device__ __forceinline__ void elim_step(double (&w)[DM_WIN], const double (&cu
 
 #define DM_UNROLL11(M) M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10)
 
-__device__ __noinline__ void sweep_arm(const DmStepArgs& A, const DmArm& arm, double DM_L* delta_lds, int DM_L* bad_flag) {
-  const DmDev& D = A.d;
+__device__ __noinline__ void sweep_arm(ArgsP Ap, int ai, double DM_L* delta_lds, int DM_L* bad_flag) {
+  const DmStepArgs DM_C& A = *uniform(Ap);
+  const DmDev DM_C& D = A.d;
+  const DmArm DM_C& arm = D.arm[uniform(ai)];
   const DmChain ch = D.chain[arm.chain];
   ArmView V{D.band, D.R, D.fac, ch.dof_off, 4 * ch.n_nodes - 1, arm.first, arm.dir, arm.count, arm.fac_off};
   const int lane = threadIdx.x & 63;
@@ -569,8 +631,10 @@ __device__ __forceinline__ void load_block(double (&buf)[3], const ArmView& V, i
   }
 }
 
-__device__ __noinline__ void backsub_arm(const DmStepArgs& A, const DmArm& arm, const double DM_L* xB) {
-  const DmDev& D = A.d;
+__device__ __noinline__ void backsub_arm(ArgsP Ap, int ai, const double DM_L* xB) {
+  const DmStepArgs DM_C& A = *uniform(Ap);
+  const DmDev DM_C& D = A.d;
+  const DmArm DM_C& arm = D.arm[uniform(ai)];
   const DmChain ch = D.chain[arm.chain];
   ArmView V{D.band, D.R, D.fac, ch.dof_off, 4 * ch.n_nodes - 1, arm.first, arm.dir, arm.count, arm.fac_off};
   const int lane = threadIdx.x & 63;
@@ -599,9 +663,11 @@ __device__ __noinline__ void backsub_arm(const DmStepArgs& A, const DmArm& arm, 
 
 // Dense border: add the arms' Schur contributions (fixed order), then Gaussian elimination
 // with partial pivoting and back substitution.  All threads take part.
-__device__ __noinline__ void border_solve(const DmStepArgs& A, const DmSystem& S, double DM_L* Bt, int ld,
+__device__ __noinline__ void border_solve(ArgsP Ap, int sid, double DM_L* Bt, int ld,
                              const double DM_L* deltas, double DM_L* xB, double DM_L* scal, int DM_L* bad_flag) {
-  const DmDev& D = A.d;
+  const DmStepArgs DM_C& A = *uniform(Ap);
+  const DmDev DM_C& D = A.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
   const int nb = S.nb, tid = threadIdx.x, nt = blockDim.x;
   for (int a = 0; a < S.n_arms; ++a) {
     const DmArm arm = D.arm[S.arm0 + a];
@@ -650,8 +716,10 @@ __device__ __noinline__ void border_solve(const DmStepArgs& A, const DmSystem& S
 }
 
 // q <- q - alpha delta over the system's nodes and edges.
-__device__ __noinline__ void apply_update(const DmStepArgs& A, const DmSystem& S, const double DM_L* xB, double alpha) {
-  const DmDev& D = A.d;
+__device__ __noinline__ void apply_update(ArgsP Ap, int sid, const double DM_L* xB, double alpha) {
+  const DmStepArgs DM_C& A = *uniform(Ap);
+  const DmDev DM_C& D = A.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
   const int NN = D.n_nodes_tot;
   for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x) {
     const int n = S.node0 + i;
@@ -670,8 +738,10 @@ __device__ __noinline__ void apply_update(const DmStepArgs& A, const DmSystem& S
   }
 }
 
-__device__ __noinline__ void rollback(const DmStepArgs& A, const DmSystem& S) {
-  const DmDev& D = A.d;
+__device__ __noinline__ void rollback(ArgsP Ap, int sid) {
+  const DmStepArgs DM_C& A = *uniform(Ap);
+  const DmDev DM_C& D = A.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
   const int NN = D.n_nodes_tot;
   for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x)
 #pragma unroll
@@ -680,8 +750,10 @@ __device__ __noinline__ void rollback(const DmStepArgs& A, const DmSystem& S) {
 }
 
 // Velocity update (after Eq. 16) and the step-end reference frames.
-__device__ __noinline__ void commit(const DmStepArgs& A, const DmSystem& S) {
-  const DmDev& D = A.d;
+__device__ __noinline__ void commit(ArgsP Ap, int sid) {
+  const DmStepArgs DM_C& A = *uniform(Ap);
+  const DmDev DM_C& D = A.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
   const int NN = D.n_nodes_tot, NE = D.n_edges_tot, NS = D.n_st_tot;
   for (int i = threadIdx.x; i < S.n_st; i += blockDim.x) {
     const int s = S.st0 + i;
@@ -719,12 +791,15 @@ __device__ __noinline__ void commit(const DmStepArgs& A, const DmSystem& S) {
 
 }  // namespace
 
-__global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs A) {
+__global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
   extern __shared__ double lds_raw[];
   double DM_L* lds = (double DM_L*)lds_raw;
-  const DmDev& D = A.d;
+  // the by-value argument sits at offset 0 of the argument segment
+  const ArgsP Ap = (ArgsP)__builtin_amdgcn_kernarg_segment_ptr();
+  const DmStepArgs DM_C& A = *Ap;
+  const DmDev DM_C& D = A.d;
   const int sid = D.order[blockIdx.x];
-  const DmSystem S = D.sys[sid];
+  const DmSystem DM_C& S = D.sys[sid];
   const int ld = A.max_nb + 1;
   double DM_L* Bt = lds;                                   // [max_nb][max_nb + 1]
   double DM_L* deltas = Bt + A.max_nb * ld;                // [max_arms][110]
@@ -744,25 +819,14 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs A) {
     int newton = 0, halvings = 0;
     double alpha = 1.0, res_prev = 0.0;
     while (true) {
-      // stencil pairs: 64 consecutive stencils per wavefront and pass, so that a wavefront
-      // never mixes the two passes
-      for (int i = tid; i < 128 * ((S.n_st + 63) >> 6); i += blockDim.x) {
-        const int st = ((i >> 7) << 6) + (i & 63);
-        if (st < S.n_st) eval_stencil(A, S.st0 + st, (i >> 6) & 1, t_end);
-      }
-      for (int i = tid; i < S.n_edges; i += blockDim.x) eval_edge(A, S.edge0 + i);
-      for (int i = tid; i < S.n_nodes; i += blockDim.x) eval_node(A, S.node0 + i);
+      eval_stencils(Ap, sid, t_end);
+      eval_edges_nodes(Ap, sid);
       __syncthreads();
       DM_TP(0);
-      double r2 = 0.0;
-      for (int i = tid; i < S.chain_nodes; i += blockDim.x) {
-        int c = 0, k = i;
-        while (k >= D.chain[S.chain0 + c].n_nodes) { k -= D.chain[S.chain0 + c].n_nodes; ++c; }
-        r2 += band_node(A, D.chain[S.chain0 + c], k);
-      }
+      double r2 = assemble_band(Ap, sid);
       __syncthreads();
       DM_TP(1);
-      for (int b = tid; b < S.nb; b += blockDim.x) r2 += border_row(A, S, b, Bt, ld);
+      r2 += assemble_border(Ap, sid, Bt, ld);
       res = sqrt(block_sum(r2, red));
       DM_TP(2);
       if (res > A.tol && newton > 0 && res_prev <= A.stag_tol && res > 0.5 * res_prev) {
@@ -771,7 +835,7 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs A) {
         break;
       }
       if (A.line_search && newton > 0 && res >= res_prev && halvings < 10) {
-        apply_update(A, S, xB, -0.5 * alpha);      // back off to half of the current step
+        apply_update(Ap, sid, xB, -0.5 * alpha);      // back off to half of the current step
         alpha *= 0.5;
         ++halvings;
         __syncthreads();
@@ -782,16 +846,16 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs A) {
       res_prev = res;
       alpha = 1.0;
       halvings = 0;
-      for (int a = wave; a < S.n_arms; a += nwaves) sweep_arm(A, D.arm[S.arm0 + a], deltas + a * 110, flags);
+      for (int a = wave; a < S.n_arms; a += nwaves) sweep_arm(Ap, S.arm0 + a, deltas + a * 110, flags);
       __syncthreads();
       DM_TP(3);
-      border_solve(A, S, Bt, ld, deltas, xB, red + 34, flags);
+      border_solve(Ap, sid, Bt, ld, deltas, xB, red + 34, flags);
       DM_TP(4);
-      for (int a = wave; a < S.n_arms; a += nwaves) backsub_arm(A, D.arm[S.arm0 + a], xB);
+      for (int a = wave; a < S.n_arms; a += nwaves) backsub_arm(Ap, S.arm0 + a, xB);
       __syncthreads();
       DM_TP(5);
       if (flags[0]) break;
-      apply_update(A, S, xB, 1.0);
+      apply_update(Ap, sid, xB, 1.0);
       ++newton;
       __syncthreads();
       DM_TP(6);
@@ -799,10 +863,10 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs A) {
     iters += newton;
     if (!conv) {
       status = flags[0] ? DM_STATUS_SINGULAR : DM_STATUS_NOT_CONVERGED;
-      rollback(A, S);
+      rollback(Ap, sid);
       break;
     }
-    commit(A, S);
+    commit(Ap, sid);
     DM_TP(7);
     t = t_end;
     ++steps;

@@ -14,16 +14,19 @@
 //            ending next to the border (two arms per single rod, one per joined rod).
 #pragma once
 
-// The kernels' device pass sees every pointer of DmDev in the global address space and LDS
-// pointers in the local one, so that loads and stores compile to global_/ds_ instructions
-// instead of generic (flat) ones; every other pass sees plain pointers of the same size and
-// layout.
+// The kernels' device pass sees the arrays the step writes in the global address space, the
+// arrays it only reads (topology, parameters) in the constant one, and LDS pointers in the
+// local one, so that loads and stores compile to global_/s_load/ds_ instructions instead of
+// generic (flat) ones and read-only data need not be reloaded around stores; every other pass
+// sees plain pointers of the same size and layout.
 #if defined(__HIP_DEVICE_COMPILE__) && defined(DM_KERNEL_TU)
 #define DM_G __attribute__((address_space(1)))
 #define DM_L __attribute__((address_space(3)))
+#define DM_C __attribute__((address_space(4)))
 #else
 #define DM_G
 #define DM_L
+#define DM_C
 #endif
 
 #define DM_HALF_BAND 10
@@ -76,40 +79,40 @@ struct DmSystem {
 // Device pointers.  All per-item arrays are structure-of-arrays.
 struct DmDev {
   // topology
-  const DmSystem DM_G* sys;
-  const DmChain DM_G* chain;
-  const DmArm DM_G* arm;
-  const int DM_G* order;        // launch order of systems (largest first)
-  const int DM_G* chain_node;
-  const int DM_G* chain_edge;
-  const int DM_G* bmap;
-  const int DM_G* bsrc;         // pairs (chain global index, chain DOF)
-  const int DM_G* bjst;
-  const unsigned char DM_G* bfix;
-  const unsigned char DM_G* cfix;   // per chain DOF: 1 if clamped
+  const DmSystem DM_C* sys;
+  const DmChain DM_C* chain;
+  const DmArm DM_C* arm;
+  const int DM_C* order;        // launch order of systems (largest first)
+  const int DM_C* chain_node;
+  const int DM_C* chain_edge;
+  const int DM_C* bmap;
+  const int DM_C* bsrc;         // pairs (chain global index, chain DOF)
+  const int DM_C* bjst;
+  const unsigned char DM_C* bfix;
+  const unsigned char DM_C* cfix;   // per chain DOF: 1 if clamped
   // nodes
-  const double DM_G* mass;
-  const double DM_G* radius;
-  const double DM_G* force;     // [3][n_nodes]
-  const int DM_G* node_owner;   // chain that assembles the node's own terms
-  const int DM_G* node_home;    // [3][n_nodes]: delta index (>= 0) or -1 - border index
+  const double DM_C* mass;
+  const double DM_C* radius;
+  const double DM_C* force;     // [3][n_nodes]
+  const int DM_C* node_owner;   // chain that assembles the node's own terms
+  const int DM_C* node_home;    // [3][n_nodes]: delta index (>= 0) or -1 - border index
   // edges
-  const int DM_G* en;           // [2][n_edges] tail, head
-  const double DM_G* ebar;
-  const double DM_G* EA;
-  const double DM_G* Ith;
-  const double DM_G* moment;
-  const int DM_G* edge_home;
+  const int DM_C* en;           // [2][n_edges] tail, head
+  const double DM_C* ebar;
+  const double DM_C* EA;
+  const double DM_C* Ith;
+  const double DM_C* moment;
+  const int DM_C* edge_home;
   // stencils
-  const int DM_G* sn;           // [3][n_st] previous, centre, next node
-  const int DM_G* se;           // [2][n_st] edge f, edge e
-  const int DM_G* ssign;        // bit 0: edge f stored reversed, bit 1: edge e stored reversed
-  const double DM_G* Vbar;
-  const double DM_G* kbend;     // EI / Vbar
-  const double DM_G* ktwist;    // GJ / Vbar
-  const double DM_G* kbar;      // [2][n_st] static integrated natural curvature
-  const double DM_G* tbar;
-  const double DM_G* act;       // [3][n_st] A (1/m), f, phi; A is NaN when not actuated
+  const int DM_C* sn;           // [3][n_st] previous, centre, next node
+  const int DM_C* se;           // [2][n_st] edge f, edge e
+  const int DM_C* ssign;        // bit 0: edge f stored reversed, bit 1: edge e stored reversed
+  const double DM_C* Vbar;
+  const double DM_C* kbend;     // EI / Vbar
+  const double DM_C* ktwist;    // GJ / Vbar
+  const double DM_C* kbar;      // [2][n_st] static integrated natural curvature
+  const double DM_C* tbar;
+  const double DM_C* act;       // [3][n_st] A (1/m), f, phi; A is NaN when not actuated
   // state
   double DM_G* x;  double DM_G* x0;  double DM_G* v;      // [3][n_nodes]
   double DM_G* th; double DM_G* th0; double DM_G* om;     // [n_edges]
