@@ -156,6 +156,30 @@ size_t dm_checkpoint_size(const dm_sim* sim);
 dm_status dm_save_checkpoint(dm_sim* sim, double* buf, int on_device);
 dm_status dm_load_checkpoint(dm_sim* sim, const double* buf, int on_device);
 
+/* Natural curvature of every rod at once: kbar is the concatenation, in rod order, of each
+ * rod's [N-2][2] array in 1/m (as dm_set_natural_curvature), host or device
+ * (on_device != 0, only after finalize). */
+dm_status dm_set_natural_curvature_all(dm_sim* sim, const double* kbar, int on_device);
+
+/* Trajectory for the discrete adjoint (gradient-based fitting of natural curvature, which
+ * the paper's Real2Sim section does with finite differences, Eq. 20).
+ * dm_rollout: nsteps steps of size dt from the current state, each one backward-Euler step
+ * solved to the Newton tolerance; a full-state checkpoint is kept (device memory owned by
+ * the sim) every ckpt_every steps.  tips receives the position of each rod's last node after
+ * every step, [nsteps][n_rods][3], host or device.  A step that does not converge ends the
+ * call with its status and no usable trajectory.
+ * dm_adjoint: for the last dm_rollout and a loss L of its tip trajectory, takes dL/dtips
+ * ([nsteps][n_rods][3], host or device) and writes dL/dkbar, the gradient with respect to
+ * every rod's natural curvature in the layout of dm_set_natural_curvature_all (host or
+ * device).  It recomputes each checkpoint interval forward, then runs the implicit-function
+ * adjoint of every step backward (transposed Newton system, step-start frames and natural
+ * curvature differentiated exactly); the sim is back at the rollout's final state after the
+ * call.  Both return DM_ERR_UNSUPPORTED for joined rods, floor contact or actuated rods, and
+ * DM_ERR_STATE if dm_adjoint has no completed rollout. */
+dm_status dm_rollout(dm_sim* sim, double dt, int nsteps, int ckpt_every, double* tips, int on_device);
+dm_status dm_adjoint(dm_sim* sim, const double* dL_dtips, int in_on_device, double* dL_dkbar,
+                     int out_on_device);
+
 /* Simulation time [s]. */
 double dm_time(const dm_sim* sim);
 

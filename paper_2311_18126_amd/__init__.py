@@ -67,6 +67,9 @@ _SIGS = {
     "dm_checkpoint_size": (c_size_t, [c_void_p]),
     "dm_save_checkpoint": (c_int, [c_void_p, c_void_p, c_int]),
     "dm_load_checkpoint": (c_int, [c_void_p, c_void_p, c_int]),
+    "dm_set_natural_curvature_all": (c_int, [c_void_p, c_void_p, c_int]),
+    "dm_rollout": (c_int, [c_void_p, c_double, c_int, c_int, c_void_p, c_int]),
+    "dm_adjoint": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int]),
     "dm_time": (c_double, [c_void_p]),
     "dm_last_kernel_ms": (c_double, [c_void_p]),
     "dm_block_size": (c_int, [c_void_p]),
@@ -266,8 +269,68 @@ class Sim:
         return buf
 
     def restore(self, buf):
+        """Load a checkpoint from a host array or a device tensor (checkpoint_torch)."""
+        if _is_cuda_tensor(buf):
+            _check(lib().dm_load_checkpoint(self._h, buf.data_ptr(), 1), "dm_load_checkpoint")
+            return
         buf = _f64(buf)
         _check(lib().dm_load_checkpoint(self._h, buf.ctypes.data, 0), "dm_load_checkpoint")
+
+    def checkpoint_torch(self, device="cuda"):
+        import torch
+        buf = torch.empty(lib().dm_checkpoint_size(self._h), dtype=torch.float64, device=device)
+        _check(lib().dm_save_checkpoint(self._h, buf.data_ptr(), 1), "dm_save_checkpoint")
+        return buf
+
+    @property
+    def num_rods(self):
+        return lib().dm_num_rods(self._h)
+
+    def rod_nodes(self, rod):
+        return lib().dm_rod_nodes(self._h, rod)
+
+    @property
+    def kbar_size(self):
+        """Length of the concatenated natural-curvature vector (2 (N_r - 2) per rod)."""
+        return sum(2 * max(self.rod_nodes(r) - 2, 0) for r in range(self.num_rods))
+
+    def set_natural_curvature_all(self, kbar):
+        """Every rod's natural curvature [N_r-2][2] (1/m), concatenated in rod order; a host
+        array or a float64 device tensor."""
+        if _is_cuda_tensor(kbar):
+            k = kbar.detach().contiguous()
+            _check(lib().dm_set_natural_curvature_all(self._h, k.data_ptr(), 1), "dm_set_natural_curvature_all")
+        else:
+            k = _f64(kbar).reshape(-1)
+            _check(lib().dm_set_natural_curvature_all(self._h, k.ctypes.data, 0), "dm_set_natural_curvature_all")
+
+    def rollout(self, dt, nsteps, ckpt_every=20, out=None):
+        """nsteps steps with a checkpoint every ckpt_every steps, for adjoint(); returns the tip
+        (last node) of every rod after every step, (nsteps, n_rods, 3), into `out` (a float64
+        device tensor) or a new host array."""
+        if out is not None:
+            _check(lib().dm_rollout(self._h, dt, nsteps, ckpt_every, out.data_ptr(), 1), "dm_rollout")
+            return out
+        tips = np.zeros((nsteps, self.num_rods, 3))
+        _check(lib().dm_rollout(self._h, dt, nsteps, ckpt_every, tips.ctypes.data, 0), "dm_rollout")
+        return tips
+
+    def adjoint(self, dL_dtips, out=None):
+        """Gradient of a tip-trajectory loss with respect to the concatenated natural curvature,
+        from dL/dtips of the last rollout (host array or device tensor); into `out` (float64
+        device tensor) or a new host array."""
+        if _is_cuda_tensor(dL_dtips):
+            g = dL_dtips.detach().contiguous()
+            src, on_dev = g.data_ptr(), 1
+        else:
+            g = _f64(dL_dtips)
+            src, on_dev = g.ctypes.data, 0
+        if out is not None:
+            _check(lib().dm_adjoint(self._h, src, on_dev, out.data_ptr(), 1), "dm_adjoint")
+            return out
+        res = np.zeros(self.kbar_size)
+        _check(lib().dm_adjoint(self._h, src, on_dev, res.ctypes.data, 0), "dm_adjoint")
+        return res
 
     @property
     def time(self):
@@ -281,6 +344,35 @@ class Sim:
     @property
     def block_size(self):
         return lib().dm_block_size(self._h)
+
+
+def _is_cuda_tensor(a):
+    return getattr(a, "is_cuda", False) and hasattr(a, "data_ptr")
+
+
+def tip_trajectory(kbar, sim, start, dt, nsteps, ckpt_every=20):
+    """Differentiable GPU rollout: the tip trajectory (nsteps, n_rods, 3) of `sim` started from
+    the checkpoint `start` (checkpoint_torch) with natural curvature `kbar` (concatenated,
+    float64 device tensor).  Its backward is the library's discrete adjoint (dm_adjoint).
+    The Sim should run on torch's current stream."""
+    import torch
+
+    class _TipTrajectory(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, k):
+            sim.restore(start)
+            sim.set_natural_curvature_all(k)
+            tips = torch.empty((nsteps, sim.num_rods, 3), dtype=torch.float64, device=k.device)
+            sim.rollout(dt, nsteps, ckpt_every, out=tips)
+            return tips
+
+        @staticmethod
+        def backward(ctx, g):
+            grad = torch.empty(sim.kbar_size, dtype=torch.float64, device=g.device)
+            sim.adjoint(g.contiguous(), out=grad)
+            return grad
+
+    return _TipTrajectory.apply(kbar)
 
 
 def sim_from_description(desc, **overrides):

@@ -789,6 +789,242 @@ __device__ __noinline__ void commit(ArgsP Ap, int sid) {
   __syncthreads();
 }
 
+
+// ---------------------------------------------------------------------------
+// discrete adjoint of a stored trajectory segment (single-rod systems, no contact)
+//
+// Backward over step n -> n+1 with the state cotangents of n+1 held in ax, av, ath, aom,
+// atref, ad1:
+//   commit: v = (x - x_n)/dt, omega = (theta - theta_n)/dt, t_ref' = t(x),
+//           d1_ref' = transport(t_ref, t(x), d1_ref) give the cotangent qbar of the Newton
+//           root q = (x, theta) and direct cotangents of the step-start state;
+//   implicit-function theorem: lambda = J^-1 qbar with J the step's Jacobian at q (symmetric
+//           without friction), assembled and factorised by the same phases as the step;
+//   every step-start input p of the residual receives -lambda^T dR/dp: inertia and damping
+//           in closed form, the step-start frames and the natural curvature through the
+//           stencil gradient in dual numbers seeded on those parameters.
+// ---------------------------------------------------------------------------
+using AdjP = const DmAdjArgs DM_C*;
+
+__device__ __forceinline__ AdjP uniform(AdjP p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (AdjP)(((unsigned long long)hi << 32) | lo);
+}
+
+// Working state of step i of the segment: x, theta = q (state i+1); x0, v, theta0, omega,
+// frames and reference twist = state i.
+__device__ __noinline__ void adj_load_states(AdjP Pp, int sid, int i) {
+  const DmAdjArgs DM_C& P = *uniform(Pp);
+  const DmDev DM_C& D = P.s.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
+  const int NN = D.n_nodes_tot, NE = D.n_edges_tot;
+  const size_t o_v = 3 * (size_t)NN, o_th = 6 * (size_t)NN, o_om = o_th + NE, o_tr = o_om + NE;
+  const size_t o_d1 = o_tr + 3 * (size_t)NE, o_b = o_d1 + 3 * (size_t)NE;
+  const double DM_C* s0 = P.a.seg + (size_t)uniform(i) * (size_t)P.a.stride;
+  const double DM_C* s1 = s0 + P.a.stride;
+  for (int k = threadIdx.x; k < S.n_nodes; k += blockDim.x) {
+    const int n = S.node0 + k;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      D.x[c * NN + n] = s1[c * NN + n];
+      D.x0[c * NN + n] = s0[c * NN + n];
+      D.v[c * NN + n] = s0[o_v + c * NN + n];
+    }
+  }
+  for (int k = threadIdx.x; k < S.n_edges; k += blockDim.x) {
+    const int e = S.edge0 + k;
+    D.th[e] = s1[o_th + e];
+    D.th0[e] = s0[o_th + e];
+    D.om[e] = s0[o_om + e];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      D.tref[c * NE + e] = s0[o_tr + c * NE + e];
+      D.d1ref[c * NE + e] = s0[o_d1 + c * NE + e];
+    }
+  }
+  for (int k = threadIdx.x; k < S.n_st; k += blockDim.x) D.bref[S.st0 + k] = s0[o_b + S.st0 + k];
+}
+
+// Loss gradient of the tip after step g + 1, then the commit's vector-Jacobian product per
+// edge: cotangents of t_ref and d1_ref of the step start, and of the new edge vector (pe).
+__device__ __noinline__ void adj_commit_vjp(AdjP Pp, int sid, int g) {
+  const DmAdjArgs DM_C& P = *uniform(Pp);
+  const DmDev DM_C& D = P.s.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
+  const DmAdjDev DM_C& J = P.a;
+  const int NN = D.n_nodes_tot, NE = D.n_edges_tot;
+  if (threadIdx.x == 0) {
+    const DmChain DM_C& ch = D.chain[S.chain0];
+    const int tip = D.chain_node[ch.node_tab + ch.n_nodes - 1];
+    const double DM_C* dl = J.dLdtip + ((size_t)uniform(g) * J.n_rods + ch.rod) * 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) J.ax[c * NN + tip] += dl[c];
+  }
+  for (int k = threadIdx.x; k < S.n_edges; k += blockDim.x) {
+    const int e = S.edge0 + k;
+    const v3 d = ld3(D.x, NN, D.en[NE + e]) - ld3(D.x, NN, D.en[e]);
+    const double il = 1.0 / sqrt(dot(d, d));
+    const v3 t = il * d;
+    // u = v - c (a + b), c = (b.v)/(1 + a.b): a = t_ref, b = t, v = d1_ref
+    const v3 a = ld3(D.tref, NE, e), v = ld3(D.d1ref, NE, e), ub = ld3(J.ad1, NE, e);
+    const v3 sab = a + t;
+    const double iden = 1.0 / (1.0 + dot(a, t));
+    const double bv = dot(t, v), c = bv * iden, us = dot(ub, sab);
+    const v3 vb = ub - (us * iden) * t;
+    const v3 ab = (us * bv * iden * iden) * t - c * ub;
+    const v3 bb = (-us) * (iden * v - (bv * iden * iden) * a) - c * ub;
+    const v3 tb = ld3(J.atref, NE, e) + bb;
+    const v3 eb = il * (tb - dot(t, tb) * t);           // through t = e / |e|
+    st3(J.pe, NE, e, eb);
+    st3(J.atref, NE, e, ab);
+    st3(J.ad1, NE, e, vb);
+  }
+}
+
+// Right-hand side qbar of the adjoint solve, in the band (R) and the border column of Bt.
+__device__ __noinline__ void adj_rhs(AdjP Pp, int sid, double DM_L* Bt, int ld) {
+  const DmAdjArgs DM_C& P = *uniform(Pp);
+  const DmDev DM_C& D = P.s.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
+  const DmAdjDev DM_C& J = P.a;
+  const int NN = D.n_nodes_tot, NE = D.n_edges_tot;
+  const double idt = 1.0 / P.s.dt;
+  const DmChain DM_C& ch = D.chain[S.chain0];
+  const int n = 4 * ch.n_nodes - 1;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    const int k = r >> 2, c = r & 3;
+    double qb;
+    if (c < 3) {
+      const int node = D.chain_node[ch.node_tab + k];
+      qb = J.ax[c * NN + node] + J.av[c * NN + node] * idt;
+      if (k >= 1) qb += J.pe[c * NE + D.chain_edge[ch.edge_tab + k - 1]];
+      if (k <= ch.n_nodes - 2) qb -= J.pe[c * NE + D.chain_edge[ch.edge_tab + k]];
+    } else {
+      const int e = D.chain_edge[ch.edge_tab + k];
+      qb = J.ath[e] + J.aom[e] * idt;
+    }
+    if (D.cfix[ch.dof_off + r]) qb = 0.0;
+    if (r >= ch.b_lo && r < ch.b_hi) Bt[D.bmap[ch.bmap_off + r - ch.b_lo] * ld + S.nb] = qb;
+    else D.R[ch.dof_off + r] = qb;
+  }
+}
+
+__device__ __noinline__ void adj_store_lambda(AdjP Pp, int sid, const double DM_L* xB) {
+  const DmAdjArgs DM_C& P = *uniform(Pp);
+  const DmDev DM_C& D = P.s.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
+  const int NN = D.n_nodes_tot;
+  for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x) {
+    const int n = S.node0 + i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int h = D.node_home[c * NN + n];
+      P.a.lam[c * NN + n] = h >= 0 ? D.delta[h] : xB[-1 - h];
+    }
+  }
+  for (int i = threadIdx.x; i < S.n_edges; i += blockDim.x) {
+    const int e = S.edge0 + i;
+    const int h = D.edge_home[e];
+    P.a.lam[3 * NN + e] = h >= 0 ? D.delta[h] : xB[-1 - h];
+  }
+}
+
+// Per stencil: derivatives of psi = lambda_loc . g_loc with respect to the step-start frames
+// of both edges and the natural curvature, in four passes of four tangents:
+// (t_f, kbar1), (d1_f, kbar2), (t_e), (d1_e), stored as pst[4 pass + tangent].
+__device__ __noinline__ void adj_stencils(AdjP Pp, int sid) {
+  const DmAdjArgs DM_C& P = *uniform(Pp);
+  const DmDev DM_C& D = P.s.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
+  const int NS = D.n_st_tot, NE = D.n_edges_tot, NN = D.n_nodes_tot;
+  for (int i = threadIdx.x; i < S.n_st; i += blockDim.x) {
+    const int s = S.st0 + i;
+    const int np = D.sn[s], nc = D.sn[NS + s], nn = D.sn[2 * NS + s];
+    const int ef = D.se[s], ee = D.se[NS + s];
+    const int sg = D.ssign[s];
+    const double sf = (sg & 1) ? -1.0 : 1.0, se = (sg & 2) ? -1.0 : 1.0;
+    const v3 xc = ld3(D.x, NN, nc);
+    const v3 efv = xc - ld3(D.x, NN, np), eev = ld3(D.x, NN, nn) - xc;
+    const v3 lp = ld3(P.a.lam, NN, np), lc = ld3(P.a.lam, NN, nc), ln = ld3(P.a.lam, NN, nn);
+    const v3 l0 = lc - lp, l1 = ln - lc;
+    const double l8[8] = {l0.x, l0.y, l0.z, l1.x, l1.y, l1.z, sf * P.a.lam[3 * NN + ef], se * P.a.lam[3 * NN + ee]};
+    const v3 tnf = sf * ld3(D.tref, NE, ef), d1nf = ld3(D.d1ref, NE, ef);
+    const v3 tne = se * ld3(D.tref, NE, ee), d1ne = ld3(D.d1ref, NE, ee);
+    for (int pass = 0; pass < 4; ++pass) {
+      // seeds selected by value (tangent k of pass p is 1 on that pass's parameter)
+      const double w0 = pass == 0 ? 1.0 : 0.0, w1 = pass == 1 ? 1.0 : 0.0;
+      const double w2 = pass == 2 ? 1.0 : 0.0, w3 = pass == 3 ? 1.0 : 0.0;
+      Vec<D4> TNF = liftv<D4>(tnf), D1NF = liftv<D4>(d1nf), TNE = liftv<D4>(tne), D1NE = liftv<D4>(d1ne);
+      D4 K1 = lift<D4>(D.kbar[s]), K2 = lift<D4>(D.kbar[NS + s]);
+      TNF.x.d[0] = w0; TNF.y.d[1] = w0; TNF.z.d[2] = w0; K1.d[3] = w0;
+      D1NF.x.d[0] = w1; D1NF.y.d[1] = w1; D1NF.z.d[2] = w1; K2.d[3] = w1;
+      TNE.x.d[0] = w2; TNE.y.d[1] = w2; TNE.z.d[2] = w2;
+      D1NE.x.d[0] = w3; D1NE.y.d[1] = w3; D1NE.z.d[2] = w3;
+      D4 g8[8];
+      stencil_grad_g(liftv<D4>(efv), liftv<D4>(eev), lift<D4>(sf * D.th[ef]), lift<D4>(se * D.th[ee]), TNF, D1NF,
+                     TNE, D1NE, D.bref[s], K1, K2, D.tbar[s], D.kbend[s], D.ktwist[s], g8);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        double acc = 0.0;
+#pragma unroll
+        for (int a = 0; a < 8; ++a) acc += l8[a] * g8[a].d[k];
+        P.a.pst[(4 * pass + k) * NS + s] = acc;
+      }
+    }
+  }
+}
+
+// Cotangents of the step-start state (and the natural-curvature gradient) from lambda.
+__device__ __noinline__ void adj_update(AdjP Pp, int sid) {
+  const DmAdjArgs DM_C& P = *uniform(Pp);
+  const DmDev DM_C& D = P.s.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
+  const DmAdjDev DM_C& J = P.a;
+  const int NS = D.n_st_tot, NE = D.n_edges_tot, NN = D.n_nodes_tot;
+  const double dt = P.s.dt, idt = 1.0 / dt, damp = P.s.damping;
+  for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x) {
+    const int n = S.node0 + i;
+    const double m = D.mass[n];
+    const double cx = m * idt * idt + damp * m * idt;     // -dR_x/dx_n
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const double lx = J.lam[c * NN + n];
+      J.ax[c * NN + n] = -J.av[c * NN + n] * idt + cx * lx;
+      J.av[c * NN + n] = m * idt * lx;
+    }
+  }
+  const DmChain DM_C& ch = D.chain[S.chain0];
+  const int N = ch.n_nodes;
+  for (int k = threadIdx.x; k < N - 1; k += blockDim.x) {
+    const int e = D.chain_edge[ch.edge_tab + k];
+    const double lt = J.lam[3 * NN + e], I = D.Ith[e];
+    J.ath[e] = -J.aom[e] * idt + I * idt * idt * lt;
+    J.aom[e] = I * idt * lt;
+    v3 tb = ld3(J.atref, NE, e), db = ld3(J.ad1, NE, e);
+    if (k + 1 <= N - 2) {          // edge k is the f edge of the stencil centred on node k+1
+      const int s = ch.st_off + k;
+      const double sf = (D.ssign[s] & 1) ? -1.0 : 1.0;
+      tb = tb - sf * mk3(J.pst[0 * NS + s], J.pst[1 * NS + s], J.pst[2 * NS + s]);
+      db = db - mk3(J.pst[4 * NS + s], J.pst[5 * NS + s], J.pst[6 * NS + s]);
+    }
+    if (k >= 1 && k <= N - 2) {    // and the e edge of the stencil centred on node k
+      const int s = ch.st_off + k - 1;
+      const double se = (D.ssign[s] & 2) ? -1.0 : 1.0;
+      tb = tb - se * mk3(J.pst[8 * NS + s], J.pst[9 * NS + s], J.pst[10 * NS + s]);
+      db = db - mk3(J.pst[12 * NS + s], J.pst[13 * NS + s], J.pst[14 * NS + s]);
+    }
+    st3(J.atref, NE, e, tb);
+    st3(J.ad1, NE, e, db);
+  }
+  for (int i = threadIdx.x; i < S.n_st; i += blockDim.x) {
+    const int s = S.st0 + i;
+    J.akap[s] -= J.pst[3 * NS + s];
+    J.akap[NS + s] -= J.pst[7 * NS + s];
+  }
+}
+
 }  // namespace
 
 __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
@@ -884,5 +1120,73 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
 
 extern "C" hipError_t dm_launch_step(const DmStepArgs* args, int block, size_t lds_bytes, hipStream_t stream) {
   hipLaunchKernelGGL(dm_step_kernel, dim3(args->n_systems), dim3(block), lds_bytes, stream, *args);
+  return hipGetLastError();
+}
+
+// Backward over the steps of one stored segment, last step first; one workgroup per system.
+__global__ void __launch_bounds__(512) dm_adjoint_kernel(DmAdjArgs) {
+  extern __shared__ double lds_raw[];
+  double DM_L* lds = (double DM_L*)lds_raw;
+  const AdjP Pp = (AdjP)__builtin_amdgcn_kernarg_segment_ptr();
+  const ArgsP Ap = (ArgsP)__builtin_amdgcn_kernarg_segment_ptr();   // the step arguments lead
+  const DmAdjArgs DM_C& P = *Pp;
+  const DmStepArgs DM_C& A = P.s;
+  const DmDev DM_C& D = A.d;
+  const int sid = D.order[blockIdx.x];
+  const DmSystem DM_C& S = D.sys[sid];
+  const int ld = A.max_nb + 1;
+  double DM_L* Bt = lds;
+  double DM_L* deltas = Bt + A.max_nb * ld;
+  double DM_L* xB = deltas + A.max_arms * 110;
+  double DM_L* red = xB + A.max_nb;
+  int DM_L* flags = (int DM_L*)(red + 40);
+  const int tid = threadIdx.x, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  if (tid == 0) flags[0] = 0;
+  int status = DM_STATUS_OK;
+  __syncthreads();
+  for (int i = P.a.seg_len - 1; i >= 0; --i) {
+    adj_load_states(Pp, sid, i);
+    __syncthreads();
+    adj_commit_vjp(Pp, sid, P.a.step0 + i);
+    eval_stencils(Ap, sid, 0.0);
+    eval_edges_nodes(Ap, sid);
+    __syncthreads();
+    assemble_band(Ap, sid);
+    __syncthreads();
+    assemble_border(Ap, sid, Bt, ld);
+    __syncthreads();
+    adj_rhs(Pp, sid, Bt, ld);
+    __syncthreads();
+    for (int a = wave; a < S.n_arms; a += nwaves) sweep_arm(Ap, S.arm0 + a, deltas + a * 110, flags);
+    __syncthreads();
+    border_solve(Ap, sid, Bt, ld, deltas, xB, red + 34, flags);
+    for (int a = wave; a < S.n_arms; a += nwaves) backsub_arm(Ap, S.arm0 + a, xB);
+    __syncthreads();
+    if (flags[0]) { status = DM_STATUS_SINGULAR; break; }
+    adj_store_lambda(Pp, sid, xB);
+    __syncthreads();
+    adj_stencils(Pp, sid);
+    __syncthreads();
+    adj_update(Pp, sid);
+    __syncthreads();
+  }
+  if (tid == 0) D.s_status[sid] = status;
+}
+
+__global__ void dm_gather_tips_kernel(const double* x, int nn, const int* tip, int n, double* out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n)
+    for (int c = 0; c < 3; ++c) out[3 * r + c] = x[c * nn + tip[r]];
+}
+
+extern "C" hipError_t dm_launch_adjoint(const DmAdjArgs* args, int block, size_t lds_bytes, hipStream_t stream) {
+  hipLaunchKernelGGL(dm_adjoint_kernel, dim3(args->s.n_systems), dim3(block), lds_bytes, stream, *args);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t dm_launch_gather_tips(const double* x, int nn, const int* tip, int n, double* out,
+                                            hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dm_gather_tips_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, x, nn, tip, n, out);
   return hipGetLastError();
 }

@@ -50,6 +50,7 @@ struct DmChain {
   int b_lo, b_hi;  // border DOF range [b_lo, b_hi) in chain numbering
   int bmap_off;    // offset into bmap: border index of chain DOF b_lo + i
   int global_id;   // index of this chain in the chain array
+  int rod;         // user rod id of this chain
 };
 
 struct DmArm {
@@ -144,4 +145,27 @@ struct DmStepArgs {
   int max_iter, nsteps, line_search;
   int n_systems;
   int max_nb, max_arms;
+};
+
+// Discrete adjoint of a stored trajectory segment (single-rod systems without contact).
+// A stored state holds, at offsets in doubles: x [3][NN] at 0, v [3][NN] at 3NN,
+// theta [NE] at 6NN, omega [NE] at 6NN+NE, t_ref [3][NE] at 6NN+2NE, d1_ref [3][NE] at
+// 6NN+5NE, beta_ref [NS] at 6NN+8NE, time [n_systems] at 6NN+8NE+NS.
+struct DmAdjDev {
+  const double DM_C* seg;       // states 0 .. seg_len of the segment, `stride` doubles apart
+  const double DM_C* dLdtip;    // [n_steps][n_rods][3]: loss gradient w.r.t. the tip after step g+1
+  double DM_G* ax;  double DM_G* av;      // [3][NN] cotangents of x, v
+  double DM_G* ath; double DM_G* aom;     // [NE] cotangents of theta, omega
+  double DM_G* atref; double DM_G* ad1;   // [3][NE] cotangents of t_ref, d1_ref
+  double DM_G* akap;                      // [2][NS] accumulated gradient w.r.t. integrated kbar
+  double DM_G* lam;                       // [3][NN] then [NE]: the adjoint solution lambda
+  double DM_G* pst;                       // [16][NS] per-stencil parameter derivatives
+  double DM_G* pe;                        // [3][NE] per-edge cotangent of the edge vector
+  long long stride;
+  int seg_len, step0, n_rods;
+};
+
+struct DmAdjArgs {
+  DmStepArgs s;                 // first member: the step arguments at offset 0
+  DmAdjDev a;
 };

@@ -214,3 +214,75 @@ DM_HD void stencil_strains(v3 tf, v3 d1f, double thf, v3 te, v3 d1e, double the,
   *k2 = -0.5 * dot(kb, m1f + m1e);
   *beta = ref_twist(tf, d1f, te, d1e, bref, raw);
 }
+
+// ---------------------------------------------------------------------------
+// Fully generic form of the stencil gradient, for derivatives with respect to the step-start
+// frames and the natural curvature (the discrete adjoint).  Every input may carry tangents;
+// the reference twist is then evaluated as a dual angle (atan2 derivative
+// (x dy - y dx) / (x^2 + y^2)), its 2 pi branch taken from bref as in ref_twist.
+// ---------------------------------------------------------------------------
+template <int N> DM_HD Dual<N> datan2(const Dual<N>& y, const Dual<N>& x) {
+  Dual<N> r;
+  r.v = atan2(y.v, x.v);
+  const double q = 1.0 / (x.v * x.v + y.v * y.v);
+#pragma unroll
+  for (int k = 0; k < N; ++k) r.d[k] = (x.v * y.d[k] - y.v * x.d[k]) * q;
+  return r;
+}
+DM_HD double datan2(double y, double x) { return atan2(y, x); }
+
+template <class S> DM_HD S lift(double v) { S r{}; r.v = v; return r; }
+template <> DM_HD double lift<double>(double v) { return v; }
+template <class S> DM_HD Vec<S> liftv(v3 a) { return mkv(lift<S>(a.x), lift<S>(a.y), lift<S>(a.z)); }
+
+template <class S>
+DM_HD void edge_frame_g(const Vec<S>& e, const S& th, const Vec<S>& tn, const Vec<S>& d1n, EdgeFrame<S>& F,
+                        Vec<S>& d1) {
+  S l = dsqrt(vdot(e, e));
+  F.il = dinv(l);
+  F.t = vscale(F.il, e);
+  S ib = dinv(vdot(tn, F.t) + 1.0);
+  S c = vdot(d1n, F.t) * ib;
+  d1 = vsub(d1n, vscale(c, vadd(F.t, tn)));
+  Vec<S> d2 = vcross(F.t, d1);
+  S sn, cs;
+  dsincos(th, sn, cs);
+  F.m1 = vadd(vscale(cs, d1), vscale(sn, d2));
+  F.m2 = vsub(vscale(cs, d2), vscale(sn, d1));
+  F.w = vscale(-(ib * F.il), vcross(tn, F.t));
+}
+
+// Gradient g8 of the stencil energy with respect to (e_f, e_e, theta_f, theta_e) (the same
+// closed forms as stencil_pass), with every argument generic.
+template <class S>
+DM_HD void stencil_grad_g(const Vec<S>& ef, const Vec<S>& ee, const S& thf, const S& the, const Vec<S>& tnf,
+                          const Vec<S>& d1nf, const Vec<S>& tne, const Vec<S>& d1ne, double bref, const S& k1bar,
+                          const S& k2bar, double tbar, double kbend, double ktw, S* g8) {
+  EdgeFrame<S> F, G;
+  Vec<S> d1f, d1e;
+  edge_frame_g(ef, thf, tnf, d1nf, F, d1f);
+  edge_frame_g(ee, the, tne, d1ne, G, d1e);
+  // reference twist (Eq. 7) as a differentiable angle on the branch nearest bref
+  Vec<S> u = vsub(d1f, vscale(vdot(G.t, d1f) * dinv(vdot(F.t, G.t) + 1.0), vadd(F.t, G.t)));
+  S beta = datan2(vdot(vcross(u, d1e), G.t), vdot(u, d1e));
+  const double two_pi = 6.283185307179586476925286766559;
+  beta = beta + two_pi * rint((bref - val(beta)) / two_pi);
+  S tau = the - thf + beta;
+  S ichi = dinv(vdot(F.t, G.t) + 1.0);
+  Vec<S> kb = vscale(2.0 * ichi, vcross(F.t, G.t));
+  S k1 = 0.5 * (vdot(kb, F.m2) + vdot(kb, G.m2));
+  S k2 = -0.5 * (vdot(kb, F.m1) + vdot(kb, G.m1));
+  S c1 = kbend * (k1 - k1bar);
+  S c2 = kbend * (k2 - k2bar);
+  S af = -0.5 * (c1 * vdot(kb, F.m1) + c2 * vdot(kb, F.m2));
+  S ae = -0.5 * (c1 * vdot(kb, G.m1) + c2 * vdot(kb, G.m2));
+  S ct = ktw * (tau - tbar);
+  S ck = c1 * k1 + c2 * k2;
+  Vec<S> M = vscale(ichi, vsub(vscale(c1, vadd(F.m2, G.m2)), vscale(c2, vadd(F.m1, G.m1))));
+  Vec<S> V = vadd(vscale(-(ck * ichi), vadd(F.t, G.t)), vscale(0.5 * ct, kb));
+  Vec<S> gf = vadd(vscale(F.il, vadd(vcross(G.t, M), V)), vscale(af - ct, F.w));
+  Vec<S> ge = vadd(vscale(G.il, vsub(V, vcross(F.t, M))), vscale(ae + ct, G.w));
+  g8[0] = gf.x; g8[1] = gf.y; g8[2] = gf.z;
+  g8[3] = ge.x; g8[4] = ge.y; g8[5] = ge.z;
+  g8[6] = af - ct; g8[7] = ae + ct;
+}

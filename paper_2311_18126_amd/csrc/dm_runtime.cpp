@@ -21,6 +21,9 @@
 #include "dm_math.h"
 
 extern "C" hipError_t dm_launch_step(const DmStepArgs* args, int block, size_t lds_bytes, hipStream_t stream);
+extern "C" hipError_t dm_launch_adjoint(const DmAdjArgs* args, int block, size_t lds_bytes, hipStream_t stream);
+extern "C" hipError_t dm_launch_gather_tips(const double* x, int nn, const int* tip, int n, double* out,
+                                            hipStream_t stream);
 
 namespace {
 
@@ -75,6 +78,16 @@ struct dm_sim {
   double time = 0.0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   float last_kernel_ms = 0.0f;
+  // trajectory and adjoint buffers, allocated on first use and grown as needed
+  double* ck = nullptr;   size_t ck_n = 0;      // checkpoints of dm_rollout
+  double* seg = nullptr;  size_t seg_n = 0;     // states of one recomputed segment + final state
+  double* adj = nullptr;  size_t adj_n = 0;     // adjoint arrays
+  double* tips_dev = nullptr; size_t tips_n = 0;
+  double* dl_dev = nullptr;   size_t dl_n = 0;
+  int* tip_nodes = nullptr;
+  int roll_steps = 0, roll_ckpt = 0;
+  double roll_dt = 0.0;
+  bool roll_valid = false;
 };
 
 namespace {
@@ -328,6 +341,7 @@ dm_status do_finalize(dm_sim* s) {
       C.st_off = s->rod_st0[r];
       C.dof_off = dof_total;
       C.global_id = (int)chains.size();
+      C.rod = r;
       for (int g : s->rod_node[r]) chain_node.push_back(g);
       for (int e : s->rod_edge[r]) chain_edge.push_back(e);
       const int n = 4 * R.n - 1;
@@ -557,6 +571,95 @@ dm_status upload_kbar(dm_sim* s) {
 
 size_t state_doubles(const dm_sim* s) { return 3 * (size_t)s->n_nodes * 3 + 3 * (size_t)s->n_edges + 6 * (size_t)s->n_edges + s->n_st + s->n_sys; }
 
+
+// Step arguments and LDS size of a launch.
+void fill_step_args(const dm_sim* s, double dt, int nsteps, DmStepArgs& A) {
+  A = DmStepArgs{};
+  A.d = s->dev;
+  A.dt = dt;
+  A.tol = s->cfg.newton_tol;
+  A.stag_tol = s->cfg.stagnation_tol;
+  for (int c = 0; c < 3; ++c) A.g[c] = s->cfg.gravity[c];
+  A.damping = s->cfg.damping;
+  A.floor_on = s->cfg.floor_contact;
+  A.floor_z = s->cfg.floor_z; A.delta = s->cfg.delta; A.nu = s->cfg.nu; A.mu = s->cfg.mu; A.kc = s->cfg.k_contact;
+  A.max_iter = s->cfg.max_iter;
+  A.nsteps = nsteps;
+  A.line_search = s->cfg.line_search;
+  A.n_systems = s->n_sys;
+  A.max_nb = std::max(s->max_nb, 1);
+  A.max_arms = std::max(s->max_arms, 1);
+}
+
+size_t step_lds(const DmStepArgs& A) {
+  return sizeof(double) * ((size_t)A.max_nb * (A.max_nb + 1) + (size_t)A.max_arms * 110 + A.max_nb + 40 + 2);
+}
+
+// Device buffer of at least n doubles (contents not kept when it grows).
+dm_status grow(double** p, size_t* cap, size_t n) {
+  if (*cap >= n && *p) return DM_OK;
+  if (*p) { DM_HIP(hipFree(*p)); *p = nullptr; *cap = 0; }
+  void* q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(double)) != hipSuccess)
+    return fail(DM_ERR_OOM, "hipMalloc failed (" + std::to_string(n * sizeof(double)) + " bytes)");
+  *p = static_cast<double*>(q);
+  *cap = n;
+  return DM_OK;
+}
+
+// One stored state: x, v, theta, omega, t_ref, d1_ref, beta_ref, time (the layout the
+// adjoint kernel reads).
+size_t traj_stride(const dm_sim* s) {
+  return 6 * (size_t)s->n_nodes + 8 * (size_t)s->n_edges + (size_t)s->n_st + (size_t)s->n_sys;
+}
+
+dm_status save_state(dm_sim* s, double* dst) {
+  const size_t NN = s->n_nodes, NE = s->n_edges;
+  const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+  double* p = dst;
+  DM_HIP(hipMemcpyAsync(p, s->dev.x, sizeof(double) * 3 * NN, k, s->stream)); p += 3 * NN;
+  DM_HIP(hipMemcpyAsync(p, s->dev.v, sizeof(double) * 3 * NN, k, s->stream)); p += 3 * NN;
+  DM_HIP(hipMemcpyAsync(p, s->dev.th, sizeof(double) * NE, k, s->stream)); p += NE;
+  DM_HIP(hipMemcpyAsync(p, s->dev.om, sizeof(double) * NE, k, s->stream)); p += NE;
+  DM_HIP(hipMemcpyAsync(p, s->dev.tref, sizeof(double) * 3 * NE, k, s->stream)); p += 3 * NE;
+  DM_HIP(hipMemcpyAsync(p, s->dev.d1ref, sizeof(double) * 3 * NE, k, s->stream)); p += 3 * NE;
+  DM_HIP(hipMemcpyAsync(p, s->dev.bref, sizeof(double) * s->n_st, k, s->stream)); p += s->n_st;
+  DM_HIP(hipMemcpyAsync(p, s->dev.time, sizeof(double) * s->n_sys, k, s->stream));
+  return DM_OK;
+}
+
+dm_status load_state(dm_sim* s, const double* src) {
+  const size_t NN = s->n_nodes, NE = s->n_edges;
+  const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+  const double* p = src;
+  DM_HIP(hipMemcpyAsync(s->dev.x, p, sizeof(double) * 3 * NN, k, s->stream));
+  DM_HIP(hipMemcpyAsync(s->dev.x0, p, sizeof(double) * 3 * NN, k, s->stream)); p += 3 * NN;
+  DM_HIP(hipMemcpyAsync(s->dev.v, p, sizeof(double) * 3 * NN, k, s->stream)); p += 3 * NN;
+  DM_HIP(hipMemcpyAsync(s->dev.th, p, sizeof(double) * NE, k, s->stream));
+  DM_HIP(hipMemcpyAsync(s->dev.th0, p, sizeof(double) * NE, k, s->stream)); p += NE;
+  DM_HIP(hipMemcpyAsync(s->dev.om, p, sizeof(double) * NE, k, s->stream)); p += NE;
+  DM_HIP(hipMemcpyAsync(s->dev.tref, p, sizeof(double) * 3 * NE, k, s->stream)); p += 3 * NE;
+  DM_HIP(hipMemcpyAsync(s->dev.d1ref, p, sizeof(double) * 3 * NE, k, s->stream)); p += 3 * NE;
+  DM_HIP(hipMemcpyAsync(s->dev.bref, p, sizeof(double) * s->n_st, k, s->stream)); p += s->n_st;
+  DM_HIP(hipMemcpyAsync(s->dev.time, p, sizeof(double) * s->n_sys, k, s->stream));
+  return DM_OK;
+}
+
+// The adjoint covers independent rods without contact or time-dependent actuation.
+dm_status adjoint_supported(const dm_sim* s) {
+  if (s->cfg.floor_contact) return fail(DM_ERR_UNSUPPORTED, "adjoint: floor contact is not supported");
+  for (const DmSystem& S : s->sys)
+    if (S.n_chains != 1 || S.n_jst != 0) return fail(DM_ERR_UNSUPPORTED, "adjoint: joined rods are not supported");
+  for (const Rod& R : s->rods)
+    if (R.act) return fail(DM_ERR_UNSUPPORTED, "adjoint: actuated rods are not supported");
+  return DM_OK;
+}
+
+size_t kbar_total(const dm_sim* s) {
+  size_t n = 0;
+  for (const Rod& R : s->rods) n += 2 * (size_t)std::max(R.n - 2, 0);
+  return n;
+}
 }  // namespace
 
 extern "C" {
@@ -696,6 +799,7 @@ dm_status dm_finalize(dm_sim* s) {
   dm_status st = do_finalize(s);
   if (st != DM_OK) {
     for (void* p : s->allocs) (void)hipFree(p);
+    for (double* p : {s->ck, s->seg, s->adj, s->tips_dev, s->dl_dev}) if (p) (void)hipFree(p);
     s->allocs.clear();
     s->finalized = false;
   }
@@ -708,22 +812,9 @@ dm_status dm_step(dm_sim* s, double dt, int nsteps, dm_stats* stats) {
   if (!(dt > 0) || !std::isfinite(dt) || nsteps < 0) return fail(DM_ERR_INVALID_ARG, "dm_step: bad dt or nsteps");
   if (nsteps == 0) return DM_OK;
   DM_HIP(hipSetDevice(s->cfg.device));
-  DmStepArgs A{};
-  A.d = s->dev;
-  A.dt = dt;
-  A.tol = s->cfg.newton_tol;
-  A.stag_tol = s->cfg.stagnation_tol;
-  for (int c = 0; c < 3; ++c) A.g[c] = s->cfg.gravity[c];
-  A.damping = s->cfg.damping;
-  A.floor_on = s->cfg.floor_contact;
-  A.floor_z = s->cfg.floor_z; A.delta = s->cfg.delta; A.nu = s->cfg.nu; A.mu = s->cfg.mu; A.kc = s->cfg.k_contact;
-  A.max_iter = s->cfg.max_iter;
-  A.nsteps = nsteps;
-  A.line_search = s->cfg.line_search;
-  A.n_systems = s->n_sys;
-  A.max_nb = std::max(s->max_nb, 1);
-  A.max_arms = std::max(s->max_arms, 1);
-  size_t lds = sizeof(double) * ((size_t)A.max_nb * (A.max_nb + 1) + (size_t)A.max_arms * 110 + A.max_nb + 40 + 2);
+  DmStepArgs A;
+  fill_step_args(s, dt, nsteps, A);
+  const size_t lds = step_lds(A);
   if (!s->ev0) { DM_HIP(hipEventCreate(&s->ev0)); DM_HIP(hipEventCreate(&s->ev1)); }
   DM_HIP(hipEventRecord(s->ev0, s->stream));
   DM_HIP(dm_launch_step(&A, s->block, lds, s->stream));
@@ -750,6 +841,162 @@ dm_status dm_step(dm_sim* s, double dt, int nsteps, dm_stats* stats) {
   if (worst == DM_ERR_SINGULAR) return fail(DM_ERR_SINGULAR, "dm_step: zero or non-finite pivot in some system");
   if (worst == DM_NOT_CONVERGED) { g_err = "dm_step: Newton did not converge in some system"; }
   return worst;
+}
+
+dm_status dm_set_natural_curvature_all(dm_sim* s, const double* kbar, int on_device) {
+  if (!s || !kbar) return fail(DM_ERR_INVALID_ARG, "dm_set_natural_curvature_all: null argument");
+  const size_t n = kbar_total(s);
+  std::vector<double> h(n);
+  if (on_device) {
+    if (!s->finalized) return fail(DM_ERR_STATE, "dm_set_natural_curvature_all: device input before dm_finalize");
+    DM_HIP(hipSetDevice(s->cfg.device));
+    DM_HIP(hipStreamSynchronize(s->stream));
+    if (n) DM_HIP(hipMemcpy(h.data(), kbar, n * sizeof(double), hipMemcpyDeviceToHost));
+  } else {
+    h.assign(kbar, kbar + n);
+  }
+  if (!finite_all(h.data(), n)) return fail(DM_ERR_INVALID_ARG, "dm_set_natural_curvature_all: non-finite value");
+  size_t off = 0;
+  for (size_t r = 0; r < s->rods.size(); ++r) {
+    Rod& R = s->rods[r];
+    if (R.n < 3) continue;
+    R.kbar.assign(h.begin() + off, h.begin() + off + 2 * (R.n - 2));
+    R.has_kbar = true;
+    if (s->finalized)
+      for (int i = 1; i + 1 < R.n; ++i) {
+        const int st_ = s->rod_st0[r] + i - 1;
+        s->h_kbar[st_] = R.kbar[2 * (i - 1)] * s->h_Vbar[st_];
+        s->h_kbar[s->n_st + st_] = R.kbar[2 * (i - 1) + 1] * s->h_Vbar[st_];
+      }
+    off += 2 * (R.n - 2);
+  }
+  return s->finalized ? upload_kbar(s) : DM_OK;
+}
+
+dm_status dm_rollout(dm_sim* s, double dt, int nsteps, int ckpt_every, double* tips, int on_device) {
+  if (!s || !tips) return fail(DM_ERR_INVALID_ARG, "dm_rollout: null argument");
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_rollout before dm_finalize");
+  if (!(dt > 0) || !std::isfinite(dt) || nsteps <= 0 || ckpt_every <= 0)
+    return fail(DM_ERR_INVALID_ARG, "dm_rollout: bad dt, nsteps or ckpt_every");
+  dm_status st;
+  if ((st = adjoint_supported(s)) != DM_OK) return st;
+  DM_HIP(hipSetDevice(s->cfg.device));
+  s->roll_valid = false;
+  const size_t W = traj_stride(s);
+  const int nck = (nsteps + ckpt_every - 1) / ckpt_every;
+  const int nr = (int)s->rods.size();
+  if ((st = grow(&s->ck, &s->ck_n, (size_t)nck * W)) != DM_OK) return st;
+  if (!s->tip_nodes) {
+    std::vector<int> tn(nr);
+    for (int r = 0; r < nr; ++r) tn[r] = s->rod_node[r].back();
+    int* p = nullptr;
+    if ((st = upload(s, tn, &p)) != DM_OK) return st;
+    s->tip_nodes = p;
+  }
+  double* tdev = tips;
+  if (!on_device) {
+    if ((st = grow(&s->tips_dev, &s->tips_n, (size_t)nsteps * nr * 3)) != DM_OK) return st;
+    tdev = s->tips_dev;
+  }
+  for (int k = 0; k < nsteps; ++k) {
+    if (k % ckpt_every == 0 && (st = save_state(s, s->ck + (size_t)(k / ckpt_every) * W)) != DM_OK) return st;
+    st = dm_step(s, dt, 1, nullptr);
+    if (st != DM_OK) return fail(st, "dm_rollout: step " + std::to_string(k) + " failed: " + g_err);
+    DM_HIP(dm_launch_gather_tips(s->dev.x, s->n_nodes, s->tip_nodes, nr, tdev + (size_t)k * nr * 3, s->stream));
+  }
+  if (!on_device)
+    DM_HIP(hipMemcpyAsync(tips, tdev, sizeof(double) * (size_t)nsteps * nr * 3, hipMemcpyDeviceToHost, s->stream));
+  DM_HIP(hipStreamSynchronize(s->stream));
+  s->roll_steps = nsteps;
+  s->roll_ckpt = ckpt_every;
+  s->roll_dt = dt;
+  s->roll_valid = true;
+  return DM_OK;
+}
+
+dm_status dm_adjoint(dm_sim* s, const double* dL_dtips, int in_on_device, double* dL_dkbar, int out_on_device) {
+  if (!s || !dL_dtips || !dL_dkbar) return fail(DM_ERR_INVALID_ARG, "dm_adjoint: null argument");
+  if (!s->finalized || !s->roll_valid) return fail(DM_ERR_STATE, "dm_adjoint needs a completed dm_rollout");
+  dm_status st;
+  if ((st = adjoint_supported(s)) != DM_OK) return st;
+  DM_HIP(hipSetDevice(s->cfg.device));
+  const size_t NN = s->n_nodes, NE = s->n_edges, NS = s->n_st, W = traj_stride(s);
+  const int T = s->roll_steps, C = s->roll_ckpt, nr = (int)s->rods.size();
+  const int nck = (T + C - 1) / C;
+  const double dt = s->roll_dt;
+  const double* dl = dL_dtips;
+  if (!in_on_device) {
+    if ((st = grow(&s->dl_dev, &s->dl_n, (size_t)T * nr * 3)) != DM_OK) return st;
+    DM_HIP(hipMemcpyAsync(s->dl_dev, dL_dtips, sizeof(double) * (size_t)T * nr * 3, hipMemcpyHostToDevice, s->stream));
+    dl = s->dl_dev;
+  }
+  // adjoint arrays: ax, av [3NN]; ath, aom [NE]; atref, ad1 [3NE]; akap [2NS]; lam [3NN+NE];
+  // pst [16NS]; pe [3NE]
+  const size_t na = 9 * NN + 12 * NE + 18 * NS;
+  if ((st = grow(&s->adj, &s->adj_n, na)) != DM_OK) return st;
+  DM_HIP(hipMemsetAsync(s->adj, 0, sizeof(double) * na, s->stream));
+  if ((st = grow(&s->seg, &s->seg_n, (size_t)(C + 2) * W)) != DM_OK) return st;
+  double* fin = s->seg + (size_t)(C + 1) * W;
+  if ((st = save_state(s, fin)) != DM_OK) return st;
+  const double t_end = s->time;
+  DmAdjArgs P;
+  fill_step_args(s, dt, 1, P.s);
+  const size_t lds = step_lds(P.s);
+  double* q = s->adj;
+  P.a = DmAdjDev{};
+  P.a.seg = s->seg;
+  P.a.dLdtip = dl;
+  P.a.ax = q; q += 3 * NN;
+  P.a.av = q; q += 3 * NN;
+  P.a.ath = q; q += NE;
+  P.a.aom = q; q += NE;
+  P.a.atref = q; q += 3 * NE;
+  P.a.ad1 = q; q += 3 * NE;
+  P.a.akap = q; q += 2 * NS;
+  P.a.lam = q; q += 3 * NN + NE;
+  P.a.pst = q; q += 16 * NS;
+  P.a.pe = q;
+  P.a.stride = (long long)W;
+  P.a.n_rods = nr;
+  std::vector<int> status(s->n_sys);
+  for (int j = nck - 1; j >= 0; --j) {
+    const int g0 = j * C, len = std::min(C, T - g0);
+    if ((st = load_state(s, s->ck + (size_t)j * W)) != DM_OK) return st;
+    if ((st = save_state(s, s->seg)) != DM_OK) return st;
+    for (int i = 0; i < len; ++i) {
+      st = dm_step(s, dt, 1, nullptr);
+      if (st != DM_OK) return fail(st, "dm_adjoint: recomputed step " + std::to_string(g0 + i) + " failed: " + g_err);
+      if ((st = save_state(s, s->seg + (size_t)(i + 1) * W)) != DM_OK) return st;
+    }
+    P.a.seg_len = len;
+    P.a.step0 = g0;
+    DM_HIP(dm_launch_adjoint(&P, s->block, lds, s->stream));
+    DM_HIP(hipMemcpyAsync(status.data(), s->dev.s_status, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost, s->stream));
+    DM_HIP(hipStreamSynchronize(s->stream));
+    for (int v : status)
+      if (v != 0) return fail(DM_ERR_SINGULAR, "dm_adjoint: zero or non-finite pivot in an adjoint solve");
+  }
+  if ((st = load_state(s, fin)) != DM_OK) return st;
+  s->time = t_end;
+  std::vector<double> akap(2 * NS);
+  DM_HIP(hipMemcpyAsync(akap.data(), P.a.akap, sizeof(double) * 2 * NS, hipMemcpyDeviceToHost, s->stream));
+  DM_HIP(hipStreamSynchronize(s->stream));
+  std::vector<double> out(kbar_total(s));
+  size_t off = 0;
+  for (int r = 0; r < nr; ++r) {
+    const int n = s->rods[r].n;
+    for (int i = 1; i + 1 < n; ++i) {
+      const int st_ = s->rod_st0[r] + i - 1;
+      for (int c = 0; c < 2; ++c) out[off + 2 * (i - 1) + c] = akap[c * NS + st_] * s->h_Vbar[st_];
+    }
+    off += 2 * (size_t)std::max(n - 2, 0);
+  }
+  if (out_on_device) {
+    if (!out.empty()) DM_HIP(hipMemcpy(dL_dkbar, out.data(), sizeof(double) * out.size(), hipMemcpyHostToDevice));
+  } else {
+    std::copy(out.begin(), out.end(), dL_dkbar);
+  }
+  return DM_OK;
 }
 
 int dm_num_systems(const dm_sim* s) { return s ? s->n_sys : 0; }
@@ -898,6 +1145,13 @@ dm_status dm_debug_phase_times(dm_sim* s, double* out) {
   DM_HIP(hipMemcpy(out, s->dev.dbg, sizeof(double) * 8 * s->n_sys, hipMemcpyDeviceToHost));
   return DM_OK;
 }
+// Diagnosis builds only: the adjoint arrays after the last dm_adjoint (ax, av, ath, aom,
+// atref, ad1, akap, lam, pst, pe in that order); returns their total length.
+size_t dm_debug_adjoint_arrays(dm_sim* s, double* out) {
+  const size_t na = 9 * (size_t)s->n_nodes + 12 * (size_t)s->n_edges + 18 * (size_t)s->n_st;
+  if (out && s->adj) (void)hipMemcpy(out, s->adj, sizeof(double) * na, hipMemcpyDeviceToHost);
+  return na;
+}
 #endif
 
 double dm_last_kernel_ms(const dm_sim* s) { return s ? (double)s->last_kernel_ms : 0.0; }
@@ -912,6 +1166,7 @@ void dm_destroy(dm_sim* s) {
     (void)hipSetDevice(s->cfg.device);
     (void)hipStreamSynchronize(s->stream);
     for (void* p : s->allocs) (void)hipFree(p);
+    for (double* p : {s->ck, s->seg, s->adj, s->tips_dev, s->dl_dev}) if (p) (void)hipFree(p);
   }
   if (s->ev0) { (void)hipEventDestroy(s->ev0); (void)hipEventDestroy(s->ev1); }
   delete s;

@@ -17,6 +17,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 import workloads as W  # noqa: E402
+from oracle import adjoint as AD  # noqa: E402
 from oracle import der  # noqa: E402
 
 OUT = os.path.dirname(os.path.abspath(__file__))
@@ -80,7 +81,35 @@ def golden_star():
     return run(d, list(range(6)), {1, 5, 20})
 
 
-GOLDEN = {"cantilever": golden_cantilever, "batch": golden_batch, "helix": golden_helix, "star": golden_star}
+# discrete adjoint: rods of the 100-node adjoint workload's material and length, shortened to
+# 20 nodes and 30 steps; case 0 starts from zero natural curvature (as the fitting problem
+# does), case 1 from a seeded nonzero one
+ADJ_RODS, ADJ_NODES, ADJ_STEPS = 2, 20, 30
+
+
+def adjoint_case():
+    d, target_kbar = W.adjoint_rods(n_rods=ADJ_RODS, n_nodes=ADJ_NODES, steps=ADJ_STEPS)
+    return d, [target_kbar[r] for r in range(ADJ_RODS)]
+
+
+def golden_adjoint():
+    d, kstar = adjoint_case()
+    _, _, target = AD.rollout(d, kstar)
+    out = {"target_tips": target.numpy()}
+    rng = np.random.Generator(np.random.PCG64(4))
+    starts = [[np.zeros((ADJ_NODES - 2, 2)) for _ in range(ADJ_RODS)],
+              [rng.normal(0.0, 1.0, size=(ADJ_NODES - 2, 2)) for _ in range(ADJ_RODS)]]
+    for c, k0 in enumerate(starts):
+        L, g, tips = AD.loss_and_grad(d, k0, target)
+        out[f"kbar0_{c}"] = np.stack(k0)
+        out[f"loss_{c}"] = np.array(L)
+        out[f"grad_{c}"] = np.stack([gi.numpy() for gi in g])
+        out[f"tips_{c}"] = tips.numpy()
+    return out
+
+
+GOLDEN = {"cantilever": golden_cantilever, "batch": golden_batch, "helix": golden_helix, "star": golden_star,
+          "adjoint": golden_adjoint}
 
 
 if __name__ == "__main__":
