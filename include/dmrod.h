@@ -68,6 +68,8 @@ typedef struct {
   void* stream;           /* hipStream_t to run on; NULL = the default stream */
   int block_size;         /* threads per system workgroup: 0 = automatic, else 64..512,
                              a multiple of 64 */
+  int warm_max_iter;      /* Newton iterations allowed to a warm-started solve before it is
+                             redone from the step-start state (0 = max_iter) */
 } dm_config;
 
 /* Per-system counters accumulated over the last dm_step call. */
@@ -76,6 +78,8 @@ typedef struct {
   int newton_iters;       /* Newton iterations summed over those steps */
   int status;             /* dm_status of this system for the call */
   int floor_steps;        /* steps that ended by the stagnation rule, not newton_tol */
+  int fallbacks;          /* warm-started steps whose Newton solve failed and was redone
+                             from the step-start state (see dm_set_warm_start) */
   double residual;        /* residual norm at the last Newton iterate */
 } dm_stats;
 
@@ -179,6 +183,60 @@ dm_status dm_set_natural_curvature_all(dm_sim* sim, const double* kbar, int on_d
 dm_status dm_rollout(dm_sim* sim, double dt, int nsteps, int ckpt_every, double* tips, int on_device);
 dm_status dm_adjoint(dm_sim* sim, const double* dL_dtips, int in_on_device, double* dL_dkbar,
                      int out_on_device);
+
+/* ---- Learned warm start of the Newton solve ----------------------------------------------
+ * Not part of the paper's method: a small network predicts each node's displacement over a
+ * step and the prediction is Newton's initial guess (Eq. 16 is still iterated to newton_tol,
+ * and a warm-started step whose solve fails is redone from the step-start state).
+ * Network: 20 features per node -> 256 -> 256 -> 3, ReLU, bfloat16 operands with float32
+ * accumulation on the matrix cores; parameters are float32 master weights laid out as
+ * W1 [256][20], b1 [256], W2 [256][256], b2 [256], W3 [3][256], b3 [3] (dm_mlp_num_params()).
+ * Features of node i of a rod (raw, float64, row-major [rows][20]; a missing neighbour at a rod
+ * end is replicated): v_{i-1} - v_i, v_{i+1} - v_i, v_i, the velocity change over the last
+ * step a_i = v_i - v_prev_i, x_{i-1} - 2 x_i + x_{i+1}, log10 E, radius, mean rest length of the
+ * edges at i, and the natural curvature at i in 1/m (nearest
+ * interior node at the ends).  Inputs are standardised ((f - mean)/std per feature); the
+ * output y is the displacement beyond the second-order extrapolation in units of a
+ * per-component scale: dx = dt (v + a) + scale * y.  Targets passed to training are raw
+ * dx - dt (v + a) (float64 [rows][3]).
+ * A dm_mlp owns its device buffers; row counts are at most max_rows.  All pointers to
+ * features, targets, outputs and gradients are device memory. */
+typedef struct dm_mlp dm_mlp;
+size_t dm_mlp_num_params(void);
+dm_status dm_mlp_create(int device, void* stream, int max_rows, dm_mlp** out);
+/* params: float32 [dm_mlp_num_params()], host or device; resets Adam's moments and step. */
+dm_status dm_mlp_set_params(dm_mlp* net, const float* params, int on_device);
+dm_status dm_mlp_get_params(dm_mlp* net, float* params, int on_device);
+/* Standardisation: host arrays mean [20], std [20], output scale [3] (all std, scale > 0). */
+dm_status dm_mlp_set_normalisation(dm_mlp* net, const double* mean, const double* std, const double* scale);
+dm_status dm_mlp_get_normalisation(dm_mlp* net, double* mean, double* std, double* scale);
+/* Mean and standard deviation of each feature and the root-mean-square of each target
+ * component over n rows of raw features F and targets T. */
+dm_status dm_mlp_fit_normalisation(dm_mlp* net, const double* F, const double* T, int n);
+/* Y [n][3] (float32): the network's standardised output for raw features F [n][20]. */
+dm_status dm_mlp_forward(dm_mlp* net, const double* F, int n, float* Y);
+/* Loss = (1/n) sum |y - T/scale|^2 and its gradient with respect to every parameter
+ * (float32 [dm_mlp_num_params()], device); loss is a host pointer (may be NULL). */
+dm_status dm_mlp_gradients(dm_mlp* net, const double* F, const double* T, int n, float* grads, double* loss);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, learning rate lr) on that loss. */
+dm_status dm_mlp_train_step(dm_mlp* net, const double* F, const double* T, int n, float lr, double* loss);
+const char* dm_mlp_last_error(void);
+void dm_mlp_destroy(dm_mlp* net);
+
+/* Rows of the simulation's feature matrix: one per rod node (a node shared by k rods appears
+ * k times; the prediction of the rod that assembles the node's own terms is used). */
+int dm_ws_rows(const dm_sim* sim);
+/* Raw features of every row at the current (step-start) state into F [rows][20] (device). */
+dm_status dm_ws_features(dm_sim* sim, double* F);
+/* Training targets after a step: dt (v_{n+1} - v_n - a_n) per row into T [rows][3] (device),
+ * with v_n and a_n taken from the step-start features F_prev. */
+dm_status dm_ws_targets(dm_sim* sim, const double* F_prev, double dt, double* T);
+/* Warm start of dm_step: mode 0 off (Newton from x_n), 1 explicit predictor x_n + dt v_n,
+ * 2 the network on top of the second-order extrapolation x_n + dt (v_n + a_n) (net must have
+ * max_rows >= dm_ws_rows), 3 that extrapolation alone.  With mode 1..3 dm_step launches one
+ * step at a time and reports fallbacks in dm_stats.  The sim keeps a reference to net.
+ * After dm_set_state or dm_load_checkpoint the last-step velocity change a is zero. */
+dm_status dm_set_warm_start(dm_sim* sim, dm_mlp* net, int mode);
 
 /* Simulation time [s]. */
 double dm_time(const dm_sim* sim);

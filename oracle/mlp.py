@@ -8,17 +8,17 @@ start predicts each node's displacement over the step with a small network and h
 Newton as the initial guess; Newton still decides convergence.  Definitions (the network is
 not in the paper; these are the build's own, stated in the design notes):
 
-* features of node i of a rod (20): x_{i-1} - x_i, x_{i+1} - x_i (zero where the neighbour is
-  missing), the velocities of nodes i-1, i, i+1 (a missing neighbour replicated), the natural
-  curvature at node i in 1/m (the nearest interior node's at the rod ends), log10 E, the
-  radius, and the mean rest length of the edges at node i;
+* features of node i of a rod (20; a missing neighbour at a rod end replicated):
+  v_{i-1} - v_i, v_{i+1} - v_i, v_i, the velocity change over the last step a_i = v_i - v_prev_i,
+  x_{i-1} - 2 x_i + x_{i+1}, log10 E, the radius, the mean rest length of the edges at node i,
+  and the natural curvature at node i in 1/m (the nearest interior node's at the rod ends);
 * standardisation: z = (f - mean) / std per feature, computed in float64, rounded to float32;
 * network 20 -> 256 -> 256 -> 3 with ReLU; every GEMM input (activations, weights and
   back-propagated gradients) is rounded to bfloat16 (round to nearest, ties to even); products
   of bfloat16 values are exact and are accumulated here in float64 (the kernels accumulate in
   float32); biases and master weights are float32;
-* output: the displacement beyond the explicit predictor, dx = dt v_i + sy * y, with sy the
-  per-component standard deviation of (dx - dt v) over the training data;
+* output: the displacement beyond the second-order extrapolation, dx = dt (v_i + a_i) + s y,
+  with s the per-component root-mean-square of (dx - dt (v + a)) over the training data;
 * loss: mean over the batch of the squared error summed over the three components; Adam
   (beta 0.9 / 0.999, eps 1e-8) on the float32 master weights.
 
@@ -59,31 +59,27 @@ def to_f32(a):
 # features
 # ---------------------------------------------------------------------------
 
-def rod_features(x, v, kbar, E, h, ebar):
-    """Features (N, 20) of one rod: x, v (N, 3) at the start of the step, kbar (N-2, 2) in
-    1/m (or None for zero), E, h scalars, ebar (N-1,) rest edge lengths."""
+def rod_features(x, v, v_prev, kbar, E, h, ebar):
+    """Features (N, 20) of one rod: x, v, v_prev (N, 3) at the start of the step (v_prev the
+    velocity before the previous step), kbar (N-2, 2) in 1/m (or None for zero), E, h scalars,
+    ebar (N-1,) rest edge lengths."""
     x = np.asarray(x, dtype=np.float64)
     v = np.asarray(v, dtype=np.float64)
+    a = v - np.asarray(v_prev, dtype=np.float64)
     n = x.shape[0]
     f = np.zeros((n, N_IN))
     for i in range(n):
-        if i >= 1:
-            f[i, 0:3] = x[i - 1] - x[i]
-        if i <= n - 2:
-            f[i, 3:6] = x[i + 1] - x[i]
-        f[i, 6:9] = v[max(i - 1, 0)]
-        f[i, 9:12] = v[i]
-        f[i, 12:15] = v[min(i + 1, n - 1)]
+        im, ip = max(i - 1, 0), min(i + 1, n - 1)
+        f[i, 0:3] = v[im] - v[i]
+        f[i, 3:6] = v[ip] - v[i]
+        f[i, 6:9] = v[i]
+        f[i, 9:12] = a[i]
+        f[i, 12:15] = x[im] - 2.0 * x[i] + x[ip]
+        f[i, 15] = np.log10(E)
+        f[i, 16] = h
+        f[i, 17] = ebar[0] if i == 0 else (ebar[n - 2] if i == n - 1 else 0.5 * (ebar[i - 1] + ebar[i]))
         if n >= 3 and kbar is not None:
-            f[i, 15:17] = kbar[min(max(i, 1), n - 2) - 1]
-        f[i, 17] = np.log10(E)
-        f[i, 18] = h
-        if i == 0:
-            f[i, 19] = ebar[0]
-        elif i == n - 1:
-            f[i, 19] = ebar[n - 2]
-        else:
-            f[i, 19] = 0.5 * (ebar[i - 1] + ebar[i])
+            f[i, 18:20] = kbar[min(max(i, 1), n - 2) - 1]
     return f
 
 

@@ -9,7 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from ctypes import POINTER, c_char_p, c_double, c_int, c_size_t, c_void_p
+from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_size_t, c_void_p
 
 import numpy as np
 
@@ -30,12 +30,13 @@ class DmConfig(ctypes.Structure):
     _fields_ = [("gravity", c_double * 3), ("newton_tol", c_double), ("stagnation_tol", c_double), ("max_iter", c_int),
                 ("line_search", c_int), ("floor_contact", c_int), ("floor_z", c_double),
                 ("delta", c_double), ("nu", c_double), ("mu", c_double), ("k_contact", c_double),
-                ("damping", c_double), ("device", c_int), ("stream", c_void_p), ("block_size", c_int)]
+                ("damping", c_double), ("device", c_int), ("stream", c_void_p), ("block_size", c_int),
+                ("warm_max_iter", c_int)]
 
 
 class DmStats(ctypes.Structure):
     _fields_ = [("steps_done", c_int), ("newton_iters", c_int), ("status", c_int), ("floor_steps", c_int),
-                ("residual", c_double)]
+                ("fallbacks", c_int), ("residual", c_double)]
 
 
 _DP = POINTER(c_double)
@@ -70,6 +71,22 @@ _SIGS = {
     "dm_set_natural_curvature_all": (c_int, [c_void_p, c_void_p, c_int]),
     "dm_rollout": (c_int, [c_void_p, c_double, c_int, c_int, c_void_p, c_int]),
     "dm_adjoint": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int]),
+    "dm_mlp_num_params": (c_size_t, []),
+    "dm_mlp_create": (c_int, [c_int, c_void_p, c_int, POINTER(c_void_p)]),
+    "dm_mlp_set_params": (c_int, [c_void_p, c_void_p, c_int]),
+    "dm_mlp_get_params": (c_int, [c_void_p, c_void_p, c_int]),
+    "dm_mlp_set_normalisation": (c_int, [c_void_p, _DP, _DP, _DP]),
+    "dm_mlp_get_normalisation": (c_int, [c_void_p, _DP, _DP, _DP]),
+    "dm_mlp_fit_normalisation": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
+    "dm_mlp_forward": (c_int, [c_void_p, c_void_p, c_int, c_void_p]),
+    "dm_mlp_gradients": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, _DP]),
+    "dm_mlp_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_float, _DP]),
+    "dm_mlp_last_error": (c_char_p, []),
+    "dm_mlp_destroy": (None, [c_void_p]),
+    "dm_ws_rows": (c_int, [c_void_p]),
+    "dm_ws_features": (c_int, [c_void_p, c_void_p]),
+    "dm_ws_targets": (c_int, [c_void_p, c_void_p, c_double, c_void_p]),
+    "dm_set_warm_start": (c_int, [c_void_p, c_void_p, c_int]),
     "dm_time": (c_double, [c_void_p]),
     "dm_last_kernel_ms": (c_double, [c_void_p]),
     "dm_block_size": (c_int, [c_void_p]),
@@ -123,7 +140,8 @@ class Sim:
     """One dm_sim.  Build with add_rod / add_joint / ..., then finalize() and step()."""
 
     def __init__(self, gravity=(0.0, 0.0, -9.81), newton_tol=1e-9, max_iter=50, line_search=False,
-                 floor=None, damping=0.0, device=0, stream=None, block_size=0, stagnation_tol=1e-6):
+                 floor=None, damping=0.0, device=0, stream=None, block_size=0, stagnation_tol=1e-6,
+                 warm_max_iter=0):
         L = lib()
         cfg = DmConfig()
         L.dm_config_default(ctypes.byref(cfg))
@@ -144,6 +162,7 @@ class Sim:
         cfg.device = int(device)
         cfg.stream = stream
         cfg.block_size = int(block_size)
+        cfg.warm_max_iter = int(warm_max_iter)
         h = c_void_p()
         _check(L.dm_create(ctypes.byref(cfg), ctypes.byref(h)), "dm_create")
         self._h = h
@@ -205,9 +224,10 @@ class Sim:
             _check(s, "dm_step")
         self.last_status = s
         out = np.zeros(n, dtype=[("steps", np.int32), ("iters", np.int32), ("status", np.int32),
-                                 ("floor_steps", np.int32), ("residual", np.float64)])
+                                 ("floor_steps", np.int32), ("fallbacks", np.int32), ("residual", np.float64)])
         for i in range(n):
-            out[i] = (st[i].steps_done, st[i].newton_iters, st[i].status, st[i].floor_steps, st[i].residual)
+            out[i] = (st[i].steps_done, st[i].newton_iters, st[i].status, st[i].floor_steps, st[i].fallbacks,
+                      st[i].residual)
         return out
 
     # -- state --------------------------------------------------------------
@@ -283,6 +303,30 @@ class Sim:
         return buf
 
     @property
+    def ws_rows(self):
+        """Rows of the warm-start feature matrix (one per rod node)."""
+        return lib().dm_ws_rows(self._h)
+
+    def ws_features(self, out):
+        """Raw warm-start features of every row at the current state into `out`, a float64
+        device tensor (ws_rows, 20)."""
+        _check(lib().dm_ws_features(self._h, out.data_ptr()), "dm_ws_features")
+        return out
+
+    def ws_targets(self, features_prev, dt, out):
+        """Targets dt (v_{n+1} - v_n) after a step, from the step-start features, into `out`
+        (float64 device tensor (ws_rows, 3))."""
+        _check(lib().dm_ws_targets(self._h, features_prev.data_ptr(), dt, out.data_ptr()), "dm_ws_targets")
+        return out
+
+    def set_warm_start(self, net=None, mode=None):
+        """Warm start of step(): None/0 off, 1 explicit predictor, 2 the network `net`."""
+        if mode is None:
+            mode = 0 if net is None else 2
+        _check(lib().dm_set_warm_start(self._h, net._h if net is not None else None, mode), "dm_set_warm_start")
+        self._ws_net = net
+
+    @property
     def num_rods(self):
         return lib().dm_num_rods(self._h)
 
@@ -344,6 +388,71 @@ class Sim:
     @property
     def block_size(self):
         return lib().dm_block_size(self._h)
+
+
+class Mlp:
+    """The warm-start network (dm_mlp): float32 master weights, bfloat16 matrix-core kernels."""
+
+    def __init__(self, max_rows, device=0, stream=None):
+        h = c_void_p()
+        _check(lib().dm_mlp_create(device, stream, int(max_rows), ctypes.byref(h)), "dm_mlp_create")
+        self._h = h
+        self.max_rows = int(max_rows)
+
+    @staticmethod
+    def num_params():
+        return lib().dm_mlp_num_params()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dm_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        if _is_cuda_tensor(params):
+            _check(lib().dm_mlp_set_params(self._h, params.data_ptr(), 1), "dm_mlp_set_params")
+        else:
+            p = np.ascontiguousarray(params, dtype=np.float32)
+            _check(lib().dm_mlp_set_params(self._h, p.ctypes.data, 0), "dm_mlp_set_params")
+
+    def get_params(self):
+        p = np.zeros(self.num_params(), dtype=np.float32)
+        _check(lib().dm_mlp_get_params(self._h, p.ctypes.data, 0), "dm_mlp_get_params")
+        return p
+
+    def set_normalisation(self, mean, std, scale):
+        m, sd, sc = _f64(mean), _f64(std), _f64(scale)
+        _check(lib().dm_mlp_set_normalisation(self._h, _dp(m), _dp(sd), _dp(sc)), "dm_mlp_set_normalisation")
+
+    def get_normalisation(self):
+        m, sd, sc = np.zeros(20), np.zeros(20), np.zeros(3)
+        _check(lib().dm_mlp_get_normalisation(self._h, _dp(m), _dp(sd), _dp(sc)), "dm_mlp_get_normalisation")
+        return m, sd, sc
+
+    def fit_normalisation(self, F, T):
+        _check(lib().dm_mlp_fit_normalisation(self._h, F.data_ptr(), T.data_ptr(), F.shape[0]), "dm_mlp_fit_normalisation")
+
+    def forward(self, F, out):
+        _check(lib().dm_mlp_forward(self._h, F.data_ptr(), F.shape[0], out.data_ptr()), "dm_mlp_forward")
+        return out
+
+    def gradients(self, F, T, out):
+        loss = c_double()
+        _check(lib().dm_mlp_gradients(self._h, F.data_ptr(), T.data_ptr(), F.shape[0], out.data_ptr(),
+                                      ctypes.byref(loss)), "dm_mlp_gradients")
+        return loss.value
+
+    def train_step(self, F, T, lr=1e-3):
+        loss = c_double()
+        _check(lib().dm_mlp_train_step(self._h, F.data_ptr(), T.data_ptr(), F.shape[0], lr, ctypes.byref(loss)),
+               "dm_mlp_train_step")
+        return loss.value
 
 
 def _is_cuda_tensor(a):

@@ -782,6 +782,7 @@ __device__ __noinline__ void commit(ArgsP Ap, int sid) {
     const int n = S.node0 + i;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
+      D.vprev[c * NN + n] = D.v[c * NN + n];
       D.v[c * NN + n] = (D.x[c * NN + n] - D.x0[c * NN + n]) / A.dt;
       D.x0[c * NN + n] = D.x[c * NN + n];
     }
@@ -1044,57 +1045,71 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
   int DM_L* flags = (int DM_L*)(red + 40);      // [4]
   const int tid = threadIdx.x, wave = tid >> 6, nwaves = blockDim.x >> 6;
   if (tid == 0) flags[0] = 0;
-  int status = DM_STATUS_OK, iters = 0, steps = 0, floor_hits = 0;
+  int status = DM_STATUS_OK, iters = 0, steps = 0, floor_hits = 0, fallbacks = 0;
   double res = 0.0;
   double t = D.time[sid];
+  // accumulating launches (one step each) leave a system alone once it has failed
+  const int nsteps = (A.accum && D.s_status[sid] != DM_STATUS_OK) ? 0 : A.nsteps;
   __syncthreads();
   DM_T0();
-  for (int step = 0; step < A.nsteps; ++step) {
+  for (int step = 0; step < nsteps; ++step) {
     const double t_end = t + A.dt;
     bool conv = false;
-    int newton = 0, halvings = 0;
-    double alpha = 1.0, res_prev = 0.0;
-    while (true) {
-      eval_stencils(Ap, sid, t_end);
-      eval_edges_nodes(Ap, sid);
-      __syncthreads();
-      DM_TP(0);
-      double r2 = assemble_band(Ap, sid);
-      __syncthreads();
-      DM_TP(1);
-      r2 += assemble_border(Ap, sid, Bt, ld);
-      res = sqrt(block_sum(r2, red));
-      DM_TP(2);
-      if (res > A.tol && newton > 0 && res_prev <= A.stag_tol && res > 0.5 * res_prev) {
-        conv = true;    // stagnation at the FP64 rounding floor of the residual
-        ++floor_hits;
-        break;
-      }
-      if (A.line_search && newton > 0 && res >= res_prev && halvings < 10) {
-        apply_update(Ap, sid, xB, -0.5 * alpha);      // back off to half of the current step
-        alpha *= 0.5;
-        ++halvings;
+    int newton = 0;
+    // attempt 0 starts from the current positions (the step start, or a warm-start guess);
+    // with a warm start, a failed attempt is repeated from the step start
+    for (int attempt = 0; attempt < (A.warm ? 2 : 1) && !conv; ++attempt) {
+      if (attempt == 1) {
+        rollback(Ap, sid);
+        if (tid == 0) flags[0] = 0;
+        ++fallbacks;
         __syncthreads();
-        continue;
       }
-      if (res <= A.tol) { conv = true; break; }
-      if (newton >= A.max_iter || !isfinite(res)) break;
-      res_prev = res;
-      alpha = 1.0;
-      halvings = 0;
-      for (int a = wave; a < S.n_arms; a += nwaves) sweep_arm(Ap, S.arm0 + a, deltas + a * 110, flags);
-      __syncthreads();
-      DM_TP(3);
-      border_solve(Ap, sid, Bt, ld, deltas, xB, red + 34, flags);
-      DM_TP(4);
-      for (int a = wave; a < S.n_arms; a += nwaves) backsub_arm(Ap, S.arm0 + a, xB);
-      __syncthreads();
-      DM_TP(5);
-      if (flags[0]) break;
-      apply_update(Ap, sid, xB, 1.0);
-      ++newton;
-      __syncthreads();
-      DM_TP(6);
+      int it = 0, halvings = 0;
+      double alpha = 1.0, res_prev = 0.0;
+      while (true) {
+        eval_stencils(Ap, sid, t_end);
+        eval_edges_nodes(Ap, sid);
+        __syncthreads();
+        DM_TP(0);
+        double r2 = assemble_band(Ap, sid);
+        __syncthreads();
+        DM_TP(1);
+        r2 += assemble_border(Ap, sid, Bt, ld);
+        res = sqrt(block_sum(r2, red));
+        DM_TP(2);
+        if (res > A.tol && it > 0 && res_prev <= A.stag_tol && res > 0.5 * res_prev) {
+          conv = true;    // stagnation at the FP64 rounding floor of the residual
+          ++floor_hits;
+          break;
+        }
+        if (A.line_search && it > 0 && res >= res_prev && halvings < 10) {
+          apply_update(Ap, sid, xB, -0.5 * alpha);      // back off to half of the current step
+          alpha *= 0.5;
+          ++halvings;
+          __syncthreads();
+          continue;
+        }
+        if (res <= A.tol) { conv = true; break; }
+        if (it >= (A.warm && attempt == 0 ? A.warm_max_iter : A.max_iter) || !isfinite(res)) break;
+        res_prev = res;
+        alpha = 1.0;
+        halvings = 0;
+        for (int a = wave; a < S.n_arms; a += nwaves) sweep_arm(Ap, S.arm0 + a, deltas + a * 110, flags);
+        __syncthreads();
+        DM_TP(3);
+        border_solve(Ap, sid, Bt, ld, deltas, xB, red + 34, flags);
+        DM_TP(4);
+        for (int a = wave; a < S.n_arms; a += nwaves) backsub_arm(Ap, S.arm0 + a, xB);
+        __syncthreads();
+        DM_TP(5);
+        if (flags[0]) break;
+        apply_update(Ap, sid, xB, 1.0);
+        ++it;
+        ++newton;
+        __syncthreads();
+        DM_TP(6);
+      }
     }
     iters += newton;
     if (!conv) {
@@ -1108,13 +1123,21 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
     ++steps;
   }
   DM_TSAVE(sid);
-  if (tid == 0) {
+  if (tid == 0 && nsteps > 0) {
     D.time[sid] = t;
-    D.s_steps[sid] = steps;
-    D.s_iters[sid] = iters;
     D.s_status[sid] = status;
     D.s_res[sid] = res;
-    D.s_floor[sid] = floor_hits;
+    if (A.accum) {
+      D.s_steps[sid] += steps;
+      D.s_iters[sid] += iters;
+      D.s_floor[sid] += floor_hits;
+      D.s_fallback[sid] += fallbacks;
+    } else {
+      D.s_steps[sid] = steps;
+      D.s_iters[sid] = iters;
+      D.s_floor[sid] = floor_hits;
+      D.s_fallback[sid] = fallbacks;
+    }
   }
 }
 

@@ -116,6 +116,7 @@ struct DmDev {
   const double DM_C* act;       // [3][n_st] A (1/m), f, phi; A is NaN when not actuated
   // state
   double DM_G* x;  double DM_G* x0;  double DM_G* v;      // [3][n_nodes]
+  double DM_G* vprev;                           // [3][n_nodes] velocity before the last step
   double DM_G* th; double DM_G* th0; double DM_G* om;     // [n_edges]
   double DM_G* tref; double DM_G* d1ref;             // [3][n_edges]
   double DM_G* bref;                            // [n_st]
@@ -131,6 +132,7 @@ struct DmDev {
   double DM_G* delta;  // [n_dof_total]
   // statistics
   int DM_G* s_steps; int DM_G* s_iters; int DM_G* s_status; double DM_G* s_res; int DM_G* s_floor;
+  int DM_G* s_fallback;  // warm-started attempts that had to restart from the step start
   double DM_G* dbg;     // [n_systems][8] phase timers in diagnosis builds; null otherwise
   int n_nodes_tot, n_edges_tot, n_st_tot;
 };
@@ -143,6 +145,9 @@ struct DmStepArgs {
   double floor_z, delta, nu, mu, kc;
   int floor_on;
   int max_iter, nsteps, line_search;
+  int warm;        // 1: the current positions are a warm-start guess; on failure restart from x_n
+  int warm_max_iter;   // Newton iterations allowed to the warm-started attempt
+  int accum;       // 1: add to the statistics (one-step launches) and skip systems that failed
   int n_systems;
   int max_nb, max_arms;
 };

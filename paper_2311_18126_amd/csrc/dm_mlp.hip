@@ -1,0 +1,614 @@
+// dm_mlp.hip -- learned warm start of the Newton solve: a 20-256-256-3 ReLU network whose
+// matrix products run on the matrix cores in bfloat16 with float32 accumulation
+// (v_mfma_f32_16x16x32_bf16), its training (loss, backward pass, Adam), and the per-node
+// features and displacement prediction of the implicit step.
+//
+// Matrix layout: every GEMM operand is stored with its reduction index contiguous, so both
+// MFMA operands are 16-byte loads: activations row-major [rows][K] for the batch-row products
+// and transposed [K][rows] for the weight gradients, whose reduction runs over the batch.
+// Rounding points: every GEMM input is rounded to bfloat16 (nearest, ties to even); biases,
+// accumulators, master weights and Adam moments are float32.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string>
+#include <vector>
+
+#define DM_KERNEL_TU
+#include "dm_layout.h"
+#include "dmrod.h"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16;
+
+namespace {
+
+constexpr int NI = 20, NH = 256, NO = 3;
+constexpr int KX = 32;                    // input width padded to one MFMA reduction step
+constexpr int NOP = 16;                   // output width padded to one MFMA tile
+constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NI, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH;
+constexpr int OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NO * NH, NPARAM = OFF_B3 + NO;
+constexpr int ROWS_WG = 64;               // batch rows per workgroup of the row GEMM (4 waves x 16)
+constexpr int WG_CHUNK = 4096;            // batch rows per split of the weight-gradient GEMM
+
+__device__ __forceinline__ u16 bf16_bits(float v) {
+  const uint32_t b = __float_as_uint(v);
+  if (v != v) return 0x7FC0;
+  return (u16)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_val(u16 h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ bf16x8 ld8(const u16* p) { return *reinterpret_cast<const bf16x8*>(p); }
+
+enum { EPI_HIDDEN = 0, EPI_OUTPUT = 1, EPI_DGRAD = 2 };
+
+// out = epilogue(A[rows][K] . Bm[N][K]^T).  One wavefront per 16 rows; lane l supplies
+// A[l % 16][8 (l / 16) + 0..7] and, per 16-column tile t, Bm[16 t + l % 16][8 (l / 16) + 0..7],
+// and receives C[4 (l / 16) + j][16 t + l % 16], j = 0..3.
+//   EPI_HIDDEN: + bias, ReLU, bfloat16 to out [rows][N] and outT [N][rows];
+//   EPI_OUTPUT: + bias, float32 to outF [rows][3] (columns 0..2);
+//   EPI_DGRAD : times the ReLU mask (mask [rows][N] > 0), bfloat16 to out (if given) and outT.
+template <int K, int N, int EPI>
+__global__ void __launch_bounds__(256) row_gemm(const u16* __restrict__ A, const u16* __restrict__ Bm,
+                                                const float* __restrict__ bias, const u16* __restrict__ mask,
+                                                int rows, u16* __restrict__ out, u16* __restrict__ outT,
+                                                float* __restrict__ outF) {
+  const int l = threadIdx.x & 63;
+  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  if (row0 >= rows) return;
+  const int lr = l & 15, lk = 8 * (l >> 4);
+  f32x4 acc[N / 16];
+#pragma unroll
+  for (int t = 0; t < N / 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const bf16x8 a = ld8(A + (size_t)(row0 + lr) * K + k0 + lk);
+#pragma unroll
+    for (int t = 0; t < N / 16; ++t) acc[t] = mfma(a, ld8(Bm + (size_t)(16 * t + lr) * K + k0 + lk), acc[t]);
+  }
+  const int r0 = row0 + 4 * (l >> 4);
+#pragma unroll
+  for (int t = 0; t < N / 16; ++t) {
+    const int n = 16 * t + lr;
+    if (EPI == EPI_OUTPUT) {
+      if (n < NO)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) outF[(size_t)(r0 + j) * NO + n] = acc[t][j] + bias[n];
+    } else {
+      u16 h[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float v = acc[t][j];
+        if (EPI == EPI_HIDDEN) v = fmaxf(v + bias[n], 0.0f);
+        else {
+          const u16 m = mask[(size_t)(r0 + j) * N + n];
+          v = (m != 0 && !(m & 0x8000)) ? v : 0.0f;
+        }
+        h[j] = bf16_bits(v);
+        if (out) out[(size_t)(r0 + j) * N + n] = h[j];
+      }
+      uint2 pk;
+      pk.x = (uint32_t)h[0] | ((uint32_t)h[1] << 16);
+      pk.y = (uint32_t)h[2] | ((uint32_t)h[3] << 16);
+      *reinterpret_cast<uint2*>(outT + (size_t)n * rows + r0) = pk;
+    }
+  }
+}
+
+// Partial weight gradients over one split of the batch: part[s][m][n] = sum_k At[m][k] Bt[n][k]
+// over k in split s, and (for the first column block) bpart[s][m] = sum_k At[m][k].  One
+// wavefront per 16 x NT output block.
+template <int M, int N>
+__global__ void __launch_bounds__(64) wgrad_gemm(const u16* __restrict__ At, const u16* __restrict__ Bt, int ld,
+                                                 float* __restrict__ part, float* __restrict__ bpart) {
+  constexpr int NT = N < 64 ? N : 64;
+  const int l = threadIdx.x;
+  const int mt = blockIdx.x / (N / NT), nt = blockIdx.x % (N / NT);
+  const int m0 = 16 * mt, n0 = NT * nt, s = blockIdx.y;
+  const int kb = s * WG_CHUNK, ke = min(kb + WG_CHUNK, ld);
+  const int lr = l & 15, lk = 8 * (l >> 4);
+  f32x4 acc[NT / 16];
+#pragma unroll
+  for (int t = 0; t < NT / 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float bs = 0.0f;
+  for (int k0 = kb; k0 < ke; k0 += 32) {
+    const bf16x8 a = ld8(At + (size_t)(m0 + lr) * ld + k0 + lk);
+    if (nt == 0) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) bs += (float)a[j];
+    }
+#pragma unroll
+    for (int t = 0; t < NT / 16; ++t) acc[t] = mfma(a, ld8(Bt + (size_t)(n0 + 16 * t + lr) * ld + k0 + lk), acc[t]);
+  }
+  float* P = part + (size_t)s * M * N;
+#pragma unroll
+  for (int t = 0; t < NT / 16; ++t)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) P[(size_t)(m0 + 4 * (l >> 4) + j) * N + n0 + 16 * t + lr] = acc[t][j];
+  if (nt == 0) {
+    bs += __shfl_xor(bs, 16, 64);
+    bs += __shfl_xor(bs, 32, 64);
+    if (l < 16) bpart[(size_t)s * M + m0 + l] = bs;
+  }
+}
+
+// Sum of the splits into the parameter-shaped gradient: rows x cols of the padded product,
+// keeping rows < keep_r and columns < keep_c, row-major at dst; bias sums to dst_b.
+__global__ void reduce_splits(const float* __restrict__ part, const float* __restrict__ bpart, int ns, int M, int N,
+                              int keep_r, int keep_c, float* __restrict__ dst, float* __restrict__ dst_b) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < keep_r * keep_c) {
+    const int r = i / keep_c, c = i % keep_c;
+    double s = 0.0;
+    for (int k = 0; k < ns; ++k) s += part[(size_t)k * M * N + (size_t)r * N + c];
+    dst[i] = (float)s;
+  }
+  if (i < keep_r) {
+    double s = 0.0;
+    for (int k = 0; k < ns; ++k) s += bpart[(size_t)k * M + i];
+    dst_b[i] = (float)s;
+  }
+}
+
+// Standardised, bfloat16-rounded input rows (and their transpose) from raw float64 features;
+// rows >= n are zero.
+__global__ void standardise(const double* __restrict__ F, int n, int rows, const double* __restrict__ mean,
+                            const double* __restrict__ sd, u16* __restrict__ X, u16* __restrict__ XT) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  for (int c = 0; c < KX; ++c) {
+    u16 h = 0;
+    if (r < n && c < NI) h = bf16_bits((float)((F[(size_t)r * NI + c] - mean[c]) / sd[c]));
+    X[(size_t)r * KX + c] = h;
+    XT[(size_t)c * rows + r] = h;
+  }
+}
+
+// Squared-error loss against standardised targets T/ystd and its gradient 2 (y - t)/n, rounded
+// to bfloat16 into dY [rows][32] and dYT [16][rows] (zero padding); per-block loss sums.
+__global__ void __launch_bounds__(256) loss_grad(const float* __restrict__ Y, const double* __restrict__ T,
+                                                 const double* __restrict__ ystd, int n, int rows,
+                                                 u16* __restrict__ dY, u16* __restrict__ dYT, double* __restrict__ lpart) {
+  __shared__ double red[256];
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  double ls = 0.0;
+  if (r < rows) {
+    for (int c = 0; c < KX; ++c) {
+      u16 h = 0;
+      if (r < n && c < NO) {
+        const double t = (double)(float)(T[(size_t)r * NO + c] / ystd[c]);
+        const double d = (double)Y[(size_t)r * NO + c] - t;
+        ls += d * d;
+        h = bf16_bits((float)(2.0 * d / n));
+      }
+      dY[(size_t)r * KX + c] = h;
+      if (c < NOP) dYT[(size_t)c * rows + r] = h;
+    }
+  }
+  red[threadIdx.x] = ls;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
+}
+
+// Adam on the float32 master weights (bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t).
+__global__ void adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v, const float* __restrict__ g,
+                     int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// bfloat16 operand copies of the master weights: W1 [256][32], W2 [256][256], W2^T, W3 [16][256],
+// W3^T [256][32] (zero padding).
+__global__ void prepare_weights(const float* __restrict__ P, u16* __restrict__ W1b, u16* __restrict__ W2b,
+                                u16* __restrict__ W2tb, u16* __restrict__ W3b, u16* __restrict__ W3tb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < NH * NH) {
+    const int r = i / NH, c = i % NH;
+    W2b[i] = bf16_bits(P[OFF_W2 + i]);
+    W2tb[(size_t)c * NH + r] = bf16_bits(P[OFF_W2 + i]);
+  }
+  if (i < NH * KX) {
+    const int r = i / KX, c = i % KX;
+    W1b[i] = c < NI ? bf16_bits(P[OFF_W1 + r * NI + c]) : 0;
+    W3tb[i] = c < NO ? bf16_bits(P[OFF_W3 + c * NH + r]) : 0;
+  }
+  if (i < NOP * NH) {
+    const int r = i / NH, c = i % NH;
+    W3b[i] = r < NO ? bf16_bits(P[OFF_W3 + r * NH + c]) : 0;
+  }
+}
+
+// Sums and sums of squares of features and targets over a data set, one block per column.
+__global__ void column_moments(const double* __restrict__ F, const double* __restrict__ T, int n,
+                               double* __restrict__ out /*[23][2]*/) {
+  __shared__ double s1[256], s2[256];
+  const int c = blockIdx.x;
+  double a = 0.0, b = 0.0;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    const double x = c < NI ? F[(size_t)r * NI + c] : T[(size_t)r * NO + c - NI];
+    a += x;
+    b += x * x;
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) { s1[threadIdx.x] += s1[threadIdx.x + o]; s2[threadIdx.x] += s2[threadIdx.x + o]; }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { out[2 * c] = s1[0]; out[2 * c + 1] = s2[0]; }
+}
+
+// ---------------------------------------------------------------------------
+// features and prediction on a simulation's state (one row per chain node)
+// ---------------------------------------------------------------------------
+
+// Raw features of chain node entry i (missing neighbours of a rod end replicated):
+// v_{i-1} - v_i, v_{i+1} - v_i, v_i, a_i = v_i - v_prev_i (velocity change over the last
+// step), x_{i-1} - 2 x_i + x_{i+1}, log10 E, radius, mean rest length of the edges at i, and
+// the natural curvature at i in 1/m (nearest interior node at the ends).
+__global__ void node_features(DmDev D, int rows, const int* __restrict__ cn_chain, const double* __restrict__ nconst,
+                              double* __restrict__ F) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  const int NN = D.n_nodes_tot, NS = D.n_st_tot;
+  const int c = cn_chain[i];
+  const DmChain ch = D.chain[c];
+  const int k = i - ch.node_tab, N = ch.n_nodes;
+  const int n0 = D.chain_node[ch.node_tab + k];
+  const int nm = D.chain_node[ch.node_tab + (k >= 1 ? k - 1 : k)];
+  const int np = D.chain_node[ch.node_tab + (k <= N - 2 ? k + 1 : k)];
+  double* f = F + (size_t)i * NI;
+  for (int q = 0; q < 3; ++q) {
+    const double vi = D.v[q * NN + n0];
+    f[q] = D.v[q * NN + nm] - vi;
+    f[3 + q] = D.v[q * NN + np] - vi;
+    f[6 + q] = vi;
+    f[9 + q] = vi - D.vprev[q * NN + n0];
+    f[12 + q] = D.x0[q * NN + nm] - 2.0 * D.x0[q * NN + n0] + D.x0[q * NN + np];
+  }
+  for (int q = 0; q < 3; ++q) f[15 + q] = nconst[(size_t)i * 3 + q];
+  if (N >= 3) {
+    const int kc = k < 1 ? 1 : (k > N - 2 ? N - 2 : k);
+    const int s = ch.st_off + kc - 1;
+    f[18] = D.kbar[s] / D.Vbar[s];
+    f[19] = D.kbar[NS + s] / D.Vbar[s];
+  } else {
+    f[18] = f[19] = 0.0;
+  }
+}
+
+// Initial Newton guess on free position DOFs, written by the chain that owns the node:
+// x = x_n + dt v_n (explicit predictor), + dt (v_n - v_prev) (second-order extrapolation), and
+// with the network + scale * y.
+__global__ void apply_guess(DmDev D, int rows, const int* __restrict__ cn_chain, double dt, int second_order,
+                            const float* __restrict__ Y, const double* __restrict__ scale) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  const int NN = D.n_nodes_tot;
+  const int c = cn_chain[i];
+  const DmChain ch = D.chain[c];
+  const int k = i - ch.node_tab;
+  const int n0 = D.chain_node[ch.node_tab + k];
+  if (D.node_owner[n0] != c) return;
+  for (int q = 0; q < 3; ++q) {
+    if (D.cfix[ch.dof_off + 4 * k + q]) continue;
+    const double v = D.v[q * NN + n0];
+    double d = dt * v;
+    if (second_order) d += dt * (v - D.vprev[q * NN + n0]);
+    if (Y) d += scale[q] * (double)Y[(size_t)i * NO + q];
+    D.x[q * NN + n0] = D.x0[q * NN + n0] + d;
+  }
+}
+
+// Training targets after a step: the displacement beyond the second-order extrapolation,
+// dt (v_{n+1} - v_n - a_n), with v_n and a_n read from the step-start features.
+__global__ void node_targets(DmDev D, int rows, const double* __restrict__ Fprev, double dt, double* __restrict__ T) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows) return;
+  const int NN = D.n_nodes_tot;
+  const int n0 = D.chain_node[i];
+  for (int q = 0; q < 3; ++q) {
+    const double* f = Fprev + (size_t)i * NI;
+    T[(size_t)i * NO + q] = dt * (D.v[q * NN + n0] - f[6 + q] - f[9 + q]);   // f: v_n, a_n
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+namespace {
+thread_local std::string g_mlp_err;
+dm_status mfail(dm_status s, const std::string& m) { g_mlp_err = m; return s; }
+#define MH(call)                                                                                  \
+  do {                                                                                            \
+    hipError_t e_ = (call);                                                                       \
+    if (e_ != hipSuccess) return mfail(DM_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+int rup(int a, int b) { return (a + b - 1) / b * b; }
+}  // namespace
+
+struct dm_mlp {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  int max_rows = 0;                       // padded row capacity (multiple of 64)
+  std::vector<void*> allocs;
+  float *P = nullptr, *M = nullptr, *V = nullptr, *G = nullptr, *Y = nullptr, *part = nullptr, *bpart = nullptr;
+  u16 *W1b = nullptr, *W2b = nullptr, *W2tb = nullptr, *W3b = nullptr, *W3tb = nullptr;
+  u16 *X = nullptr, *XT = nullptr, *H1 = nullptr, *H1T = nullptr, *H2 = nullptr, *H2T = nullptr;
+  u16 *dY = nullptr, *dYT = nullptr, *dH2 = nullptr, *dH2T = nullptr, *dH1T = nullptr;
+  double *mean = nullptr, *sd = nullptr, *ystd = nullptr, *lpart = nullptr, *moments = nullptr;
+  int t = 0;
+};
+
+namespace {
+
+template <class T>
+dm_status malloc_n(dm_mlp* m, T** p, size_t n) {
+  void* q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return mfail(DM_ERR_OOM, "dm_mlp: hipMalloc failed");
+  m->allocs.push_back(q);
+  *p = static_cast<T*>(q);
+  return hipMemset(q, 0, std::max<size_t>(n, 1) * sizeof(T)) == hipSuccess ? DM_OK : mfail(DM_ERR_HIP, "hipMemset");
+}
+
+dm_status check_rows(const dm_mlp* m, int n) {
+  if (!m) return mfail(DM_ERR_INVALID_ARG, "null network");
+  if (n <= 0 || n > m->max_rows) return mfail(DM_ERR_INVALID_ARG, "dm_mlp: row count outside 1..max_rows");
+  return DM_OK;
+}
+
+// Forward pass on raw features F (device, [n][20]); leaves Y [rows][3] (standardised outputs)
+// and every activation needed by the backward pass.
+dm_status forward_rows(dm_mlp* m, const double* F, int n, int rows) {
+  hipStream_t st = m->stream;
+  hipLaunchKernelGGL(standardise, dim3((rows + 255) / 256), dim3(256), 0, st, F, n, rows, m->mean, m->sd, m->X, m->XT);
+  const dim3 g(rows / ROWS_WG), b(256);
+  hipLaunchKernelGGL((row_gemm<KX, NH, EPI_HIDDEN>), g, b, 0, st, m->X, m->W1b, m->P + OFF_B1, nullptr, rows, m->H1,
+                     m->H1T, nullptr);
+  hipLaunchKernelGGL((row_gemm<NH, NH, EPI_HIDDEN>), g, b, 0, st, m->H1, m->W2b, m->P + OFF_B2, nullptr, rows, m->H2,
+                     m->H2T, nullptr);
+  hipLaunchKernelGGL((row_gemm<NH, NOP, EPI_OUTPUT>), g, b, 0, st, m->H2, m->W3b, m->P + OFF_B3, nullptr, rows,
+                     nullptr, nullptr, m->Y);
+  MH(hipGetLastError());
+  return DM_OK;
+}
+
+dm_status prepare(dm_mlp* m) {
+  hipLaunchKernelGGL(prepare_weights, dim3((NH * NH + 255) / 256), dim3(256), 0, m->stream, m->P, m->W1b, m->W2b,
+                     m->W2tb, m->W3b, m->W3tb);
+  MH(hipGetLastError());
+  return DM_OK;
+}
+
+// Loss and gradients into m->G for rows 0..n-1 of raw features F and raw targets T.
+dm_status gradients(dm_mlp* m, const double* F, const double* T, int n, double* loss) {
+  const int rows = rup(n, ROWS_WG);
+  dm_status s;
+  if ((s = forward_rows(m, F, n, rows)) != DM_OK) return s;
+  hipStream_t st = m->stream;
+  const int nb = (rows + 255) / 256;
+  hipLaunchKernelGGL(loss_grad, dim3(nb), dim3(256), 0, st, m->Y, T, m->ystd, n, rows, m->dY, m->dYT, m->lpart);
+  const dim3 g(rows / ROWS_WG), b(256);
+  hipLaunchKernelGGL((row_gemm<KX, NH, EPI_DGRAD>), g, b, 0, st, m->dY, m->W3tb, nullptr, m->H2, rows, m->dH2,
+                     m->dH2T, nullptr);
+  hipLaunchKernelGGL((row_gemm<NH, NH, EPI_DGRAD>), g, b, 0, st, m->dH2, m->W2tb, nullptr, m->H1, rows, nullptr,
+                     m->dH1T, nullptr);
+  const int ns = (rows + WG_CHUNK - 1) / WG_CHUNK;
+  float* G = m->G;
+  auto red = [&](int M_, int N_, int kr, int kc, float* dst, float* dstb) {
+    hipLaunchKernelGGL(reduce_splits, dim3((kr * kc + 255) / 256), dim3(256), 0, st, m->part, m->bpart, ns, M_, N_, kr,
+                       kc, dst, dstb);
+  };
+  hipLaunchKernelGGL((wgrad_gemm<NH, NH>), dim3((NH / 16) * (NH / 64), ns), dim3(64), 0, st, m->dH2T, m->H1T, rows,
+                     m->part, m->bpart);
+  red(NH, NH, NH, NH, G + OFF_W2, G + OFF_B2);
+  hipLaunchKernelGGL((wgrad_gemm<NH, KX>), dim3((NH / 16) * 1, ns), dim3(64), 0, st, m->dH1T, m->XT, rows, m->part,
+                     m->bpart);
+  red(NH, KX, NH, NI, G + OFF_W1, G + OFF_B1);
+  hipLaunchKernelGGL((wgrad_gemm<NOP, NH>), dim3(1 * (NH / 64), ns), dim3(64), 0, st, m->dYT, m->H2T, rows, m->part,
+                     m->bpart);
+  red(NOP, NH, NO, NH, G + OFF_W3, G + OFF_B3);
+  MH(hipGetLastError());
+  if (loss) {
+    std::vector<double> lp(nb);
+    MH(hipMemcpyAsync(lp.data(), m->lpart, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+    MH(hipStreamSynchronize(st));
+    double L = 0.0;
+    for (double v : lp) L += v;
+    *loss = L / n;
+  }
+  return DM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t dm_mlp_num_params(void) { return NPARAM; }
+const char* dm_mlp_last_error(void) { return g_mlp_err.c_str(); }
+
+dm_status dm_mlp_create(int device, void* stream, int max_rows, dm_mlp** out) {
+  if (!out || max_rows <= 0) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_create: bad arguments");
+  MH(hipSetDevice(device));
+  dm_mlp* m = new dm_mlp();
+  m->device = device;
+  m->stream = (hipStream_t)stream;
+  m->max_rows = rup(max_rows, ROWS_WG);
+  const size_t R = m->max_rows;
+  const int ns = (m->max_rows + WG_CHUNK - 1) / WG_CHUNK;
+  dm_status s = DM_OK;
+  auto A = [&](auto** p, size_t n) { if (s == DM_OK) s = malloc_n(m, p, n); };
+  A(&m->P, NPARAM); A(&m->M, NPARAM); A(&m->V, NPARAM); A(&m->G, NPARAM); A(&m->Y, R * NO);
+  A(&m->part, (size_t)ns * NH * NH); A(&m->bpart, (size_t)ns * NH);
+  A(&m->W1b, NH * KX); A(&m->W2b, NH * NH); A(&m->W2tb, NH * NH); A(&m->W3b, NOP * NH); A(&m->W3tb, NH * KX);
+  A(&m->X, R * KX); A(&m->XT, R * KX); A(&m->H1, R * NH); A(&m->H1T, R * NH); A(&m->H2, R * NH); A(&m->H2T, R * NH);
+  A(&m->dY, R * KX); A(&m->dYT, R * NOP); A(&m->dH2, R * NH); A(&m->dH2T, R * NH); A(&m->dH1T, R * NH);
+  A(&m->mean, NI); A(&m->sd, NI); A(&m->ystd, NO); A(&m->lpart, R / 256 + 1); A(&m->moments, 2 * (NI + NO));
+  if (s != DM_OK) { dm_mlp_destroy(m); return s; }
+  std::vector<double> one(NI, 1.0);
+  if (hipMemcpy(m->sd, one.data(), sizeof(double) * NI, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(m->ystd, one.data(), sizeof(double) * NO, hipMemcpyHostToDevice) != hipSuccess) {
+    dm_mlp_destroy(m);
+    return mfail(DM_ERR_HIP, "dm_mlp_create: hipMemcpy");
+  }
+  *out = m;
+  return DM_OK;
+}
+
+dm_status dm_mlp_set_params(dm_mlp* m, const float* params, int on_device) {
+  if (!m || !params) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_set_params: null argument");
+  MH(hipSetDevice(m->device));
+  MH(hipMemcpyAsync(m->P, params, sizeof(float) * NPARAM, on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                    m->stream));
+  MH(hipMemsetAsync(m->M, 0, sizeof(float) * NPARAM, m->stream));
+  MH(hipMemsetAsync(m->V, 0, sizeof(float) * NPARAM, m->stream));
+  m->t = 0;
+  dm_status s = prepare(m);
+  MH(hipStreamSynchronize(m->stream));
+  return s;
+}
+
+dm_status dm_mlp_get_params(dm_mlp* m, float* params, int on_device) {
+  if (!m || !params) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_get_params: null argument");
+  MH(hipMemcpyAsync(params, m->P, sizeof(float) * NPARAM, on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                    m->stream));
+  MH(hipStreamSynchronize(m->stream));
+  return DM_OK;
+}
+
+dm_status dm_mlp_set_normalisation(dm_mlp* m, const double* mean, const double* sd, const double* ystd) {
+  if (!m || !mean || !sd || !ystd) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_set_normalisation: null argument");
+  for (int i = 0; i < NI; ++i)
+    if (!(sd[i] > 0) || !std::isfinite(mean[i])) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_set_normalisation: bad value");
+  for (int i = 0; i < NO; ++i)
+    if (!(ystd[i] > 0)) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_set_normalisation: bad value");
+  MH(hipMemcpy(m->mean, mean, sizeof(double) * NI, hipMemcpyHostToDevice));
+  MH(hipMemcpy(m->sd, sd, sizeof(double) * NI, hipMemcpyHostToDevice));
+  MH(hipMemcpy(m->ystd, ystd, sizeof(double) * NO, hipMemcpyHostToDevice));
+  return DM_OK;
+}
+
+dm_status dm_mlp_get_normalisation(dm_mlp* m, double* mean, double* sd, double* ystd) {
+  if (!m || !mean || !sd || !ystd) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_get_normalisation: null argument");
+  MH(hipMemcpy(mean, m->mean, sizeof(double) * NI, hipMemcpyDeviceToHost));
+  MH(hipMemcpy(sd, m->sd, sizeof(double) * NI, hipMemcpyDeviceToHost));
+  MH(hipMemcpy(ystd, m->ystd, sizeof(double) * NO, hipMemcpyDeviceToHost));
+  return DM_OK;
+}
+
+dm_status dm_mlp_fit_normalisation(dm_mlp* m, const double* F, const double* T, int n) {
+  if (!m || !F || !T || n < 2) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_fit_normalisation: bad arguments");
+  MH(hipSetDevice(m->device));
+  hipLaunchKernelGGL(column_moments, dim3(NI + NO), dim3(256), 0, m->stream, F, T, n, m->moments);
+  MH(hipGetLastError());
+  std::vector<double> mo(2 * (NI + NO));
+  MH(hipMemcpyAsync(mo.data(), m->moments, sizeof(double) * mo.size(), hipMemcpyDeviceToHost, m->stream));
+  MH(hipStreamSynchronize(m->stream));
+  double mean[NI], sd[NI], ys[NO];
+  for (int c = 0; c < NI + NO; ++c) {
+    const double mu = mo[2 * c] / n;
+    const double var = std::max(mo[2 * c + 1] / n - mu * mu, 0.0);
+    const double s = var > 1e-30 * std::max(1.0, mu * mu) ? std::sqrt(var) : 1.0;
+    if (c < NI) { mean[c] = mu; sd[c] = s; }
+    else ys[c - NI] = std::sqrt(mo[2 * c + 1] / n) > 0 ? std::sqrt(mo[2 * c + 1] / n) : 1.0;
+  }
+  return dm_mlp_set_normalisation(m, mean, sd, ys);
+}
+
+dm_status dm_mlp_forward(dm_mlp* m, const double* F, int n, float* Y) {
+  dm_status s;
+  if ((s = check_rows(m, n)) != DM_OK) return s;
+  if (!F || !Y) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_forward: null argument");
+  MH(hipSetDevice(m->device));
+  if ((s = forward_rows(m, F, n, rup(n, ROWS_WG))) != DM_OK) return s;
+  MH(hipMemcpyAsync(Y, m->Y, sizeof(float) * NO * (size_t)n, hipMemcpyDeviceToDevice, m->stream));
+  MH(hipStreamSynchronize(m->stream));
+  return DM_OK;
+}
+
+dm_status dm_mlp_gradients(dm_mlp* m, const double* F, const double* T, int n, float* grads, double* loss) {
+  dm_status s;
+  if ((s = check_rows(m, n)) != DM_OK) return s;
+  if (!F || !T || !grads) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_gradients: null argument");
+  MH(hipSetDevice(m->device));
+  if ((s = gradients(m, F, T, n, loss)) != DM_OK) return s;
+  MH(hipMemcpyAsync(grads, m->G, sizeof(float) * NPARAM, hipMemcpyDeviceToDevice, m->stream));
+  MH(hipStreamSynchronize(m->stream));
+  return DM_OK;
+}
+
+dm_status dm_mlp_train_step(dm_mlp* m, const double* F, const double* T, int n, float lr, double* loss) {
+  dm_status s;
+  if ((s = check_rows(m, n)) != DM_OK) return s;
+  if (!F || !T || !(lr > 0)) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_train_step: bad arguments");
+  MH(hipSetDevice(m->device));
+  if ((s = gradients(m, F, T, n, loss)) != DM_OK) return s;
+  m->t += 1;
+  const float c1 = (float)(1.0 - std::pow(0.9, m->t)), c2 = (float)(1.0 - std::pow(0.999, m->t));
+  hipLaunchKernelGGL(adam, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->P, m->M, m->V, m->G, NPARAM, lr,
+                     0.9f, 0.999f, 1e-8f, c1, c2);
+  MH(hipGetLastError());
+  return prepare(m);
+}
+
+void dm_mlp_destroy(dm_mlp* m) {
+  if (!m) return;
+  (void)hipSetDevice(m->device);
+  (void)hipStreamSynchronize(m->stream);
+  for (void* p : m->allocs) (void)hipFree(p);
+  delete m;
+}
+
+// --- used by the simulation runtime --------------------------------------------------------
+
+int dm_mlp_capacity(const dm_mlp* m) { return m ? m->max_rows : 0; }
+
+hipError_t dm_ws_launch_features(const DmDev* D, int rows, const int* cn_chain, const double* nconst, double* F,
+                                 hipStream_t st) {
+  hipLaunchKernelGGL(node_features, dim3((rows + 255) / 256), dim3(256), 0, st, *D, rows, cn_chain, nconst, F);
+  return hipGetLastError();
+}
+
+hipError_t dm_ws_launch_targets(const DmDev* D, int rows, const int* cn_chain, const double* Fprev, double dt,
+                                double* T, hipStream_t st) {
+  (void)cn_chain;
+  hipLaunchKernelGGL(node_targets, dim3((rows + 255) / 256), dim3(256), 0, st, *D, rows, Fprev, dt, T);
+  return hipGetLastError();
+}
+
+// Guess for the next step: explicit predictor, + second-order term if second_order, + the
+// network's correction if m is given (F must then hold the step-start features of every row).
+hipError_t dm_ws_launch_guess(const DmDev* D, int rows, const int* cn_chain, double dt, int second_order, dm_mlp* m,
+                              const double* F, hipStream_t st) {
+  const float* Y = nullptr;
+  const double* scale = nullptr;
+  if (m) {
+    m->stream = st;
+    if (forward_rows(m, F, rows, rup(rows, ROWS_WG)) != DM_OK) return hipErrorUnknown;
+    Y = m->Y;
+    scale = m->ystd;
+  }
+  hipLaunchKernelGGL(apply_guess, dim3((rows + 255) / 256), dim3(256), 0, st, *D, rows, cn_chain, dt, second_order, Y,
+                     scale);
+  return hipGetLastError();
+}
+
+}  // extern "C"

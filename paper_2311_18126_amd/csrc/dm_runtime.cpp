@@ -24,6 +24,13 @@ extern "C" hipError_t dm_launch_step(const DmStepArgs* args, int block, size_t l
 extern "C" hipError_t dm_launch_adjoint(const DmAdjArgs* args, int block, size_t lds_bytes, hipStream_t stream);
 extern "C" hipError_t dm_launch_gather_tips(const double* x, int nn, const int* tip, int n, double* out,
                                             hipStream_t stream);
+extern "C" int dm_mlp_capacity(const dm_mlp* m);
+extern "C" hipError_t dm_ws_launch_features(const DmDev* D, int rows, const int* cn_chain, const double* nconst,
+                                            double* F, hipStream_t st);
+extern "C" hipError_t dm_ws_launch_targets(const DmDev* D, int rows, const int* cn_chain, const double* Fprev,
+                                           double dt, double* T, hipStream_t st);
+extern "C" hipError_t dm_ws_launch_guess(const DmDev* D, int rows, const int* cn_chain, double dt, int second_order,
+                                         dm_mlp* m, const double* F, hipStream_t st);
 
 namespace {
 
@@ -85,6 +92,13 @@ struct dm_sim {
   double* tips_dev = nullptr; size_t tips_n = 0;
   double* dl_dev = nullptr;   size_t dl_n = 0;
   int* tip_nodes = nullptr;
+  // warm start: per feature row (rod node) its chain and constants (log10 E, h, mean ebar)
+  int ws_rows = 0;
+  int* cn_chain = nullptr;
+  double* nconst = nullptr;
+  double* ws_F = nullptr; size_t ws_F_n = 0;
+  dm_mlp* ws_net = nullptr;
+  int ws_mode = 0;
   int roll_steps = 0, roll_ckpt = 0;
   double roll_dt = 0.0;
   bool roll_valid = false;
@@ -522,6 +536,7 @@ dm_status do_finalize(dm_sim* s) {
   UP(XS, x) UP(XS, x0) UP(trefS, tref) UP(d1S, d1ref) UP(bref, bref)
 #undef UP
   if ((st = alloc(s, 3 * (size_t)NN, &D.v)) != DM_OK) return st;
+  if ((st = alloc(s, 3 * (size_t)NN, &D.vprev)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)NE, &D.th)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)NE, &D.th0)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)NE, &D.om)) != DM_OK) return st;
@@ -539,6 +554,28 @@ dm_status do_finalize(dm_sim* s) {
   if ((st = alloc(s, (size_t)s->n_sys, &D.s_status)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)s->n_sys, &D.s_res)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)s->n_sys, &D.s_floor)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)s->n_sys, &D.s_fallback)) != DM_OK) return st;
+  {
+    // warm-start feature rows: one per chain node
+    std::vector<int> cnc(chain_node.size());
+    std::vector<double> nc(3 * chain_node.size());
+    for (const DmChain& C : chains) {
+      const Rod& R = s->rods[C.rod];
+      for (int k = 0; k < C.n_nodes; ++k) {
+        const int i = C.node_tab + k;
+        cnc[i] = C.global_id;
+        const double el = k == 0 ? ebar[chain_edge[C.edge_tab]]
+                        : (k == C.n_nodes - 1 ? ebar[chain_edge[C.edge_tab + k - 1]]
+                                              : 0.5 * (ebar[chain_edge[C.edge_tab + k - 1]] + ebar[chain_edge[C.edge_tab + k]]));
+        nc[3 * i] = std::log10(R.E);
+        nc[3 * i + 1] = R.h;
+        nc[3 * i + 2] = el;
+      }
+    }
+    s->ws_rows = (int)chain_node.size();
+    if ((st = upload(s, cnc, &s->cn_chain)) != DM_OK) return st;
+    if ((st = upload(s, nc, &s->nconst)) != DM_OK) return st;
+  }
 #ifdef DM_PHASE_TIMING
   if ((st = alloc(s, (size_t)s->n_sys * 8, &D.dbg)) != DM_OK) return st;
 #else
@@ -584,6 +621,7 @@ void fill_step_args(const dm_sim* s, double dt, int nsteps, DmStepArgs& A) {
   A.floor_on = s->cfg.floor_contact;
   A.floor_z = s->cfg.floor_z; A.delta = s->cfg.delta; A.nu = s->cfg.nu; A.mu = s->cfg.mu; A.kc = s->cfg.k_contact;
   A.max_iter = s->cfg.max_iter;
+  A.warm_max_iter = s->cfg.warm_max_iter > 0 ? s->cfg.warm_max_iter : s->cfg.max_iter;
   A.nsteps = nsteps;
   A.line_search = s->cfg.line_search;
   A.n_systems = s->n_sys;
@@ -634,7 +672,8 @@ dm_status load_state(dm_sim* s, const double* src) {
   const double* p = src;
   DM_HIP(hipMemcpyAsync(s->dev.x, p, sizeof(double) * 3 * NN, k, s->stream));
   DM_HIP(hipMemcpyAsync(s->dev.x0, p, sizeof(double) * 3 * NN, k, s->stream)); p += 3 * NN;
-  DM_HIP(hipMemcpyAsync(s->dev.v, p, sizeof(double) * 3 * NN, k, s->stream)); p += 3 * NN;
+  DM_HIP(hipMemcpyAsync(s->dev.v, p, sizeof(double) * 3 * NN, k, s->stream));
+  DM_HIP(hipMemcpyAsync(s->dev.vprev, p, sizeof(double) * 3 * NN, k, s->stream)); p += 3 * NN;
   DM_HIP(hipMemcpyAsync(s->dev.th, p, sizeof(double) * NE, k, s->stream));
   DM_HIP(hipMemcpyAsync(s->dev.th0, p, sizeof(double) * NE, k, s->stream)); p += NE;
   DM_HIP(hipMemcpyAsync(s->dev.om, p, sizeof(double) * NE, k, s->stream)); p += NE;
@@ -679,7 +718,8 @@ void dm_config_default(dm_config* c) {
 
 dm_status dm_create(const dm_config* cfg, dm_sim** out) {
   if (!cfg || !out) return fail(DM_ERR_INVALID_ARG, "dm_create: null argument");
-  if (!(cfg->newton_tol >= 0.0) || !(cfg->stagnation_tol >= 0.0) || cfg->max_iter < 1) return fail(DM_ERR_INVALID_ARG, "dm_create: bad Newton settings");
+  if (!(cfg->newton_tol >= 0.0) || !(cfg->stagnation_tol >= 0.0) || cfg->max_iter < 1 || cfg->warm_max_iter < 0)
+    return fail(DM_ERR_INVALID_ARG, "dm_create: bad Newton settings");
   if (cfg->block_size != 0 && (cfg->block_size < 64 || cfg->block_size > 512 || cfg->block_size % 64))
     return fail(DM_ERR_INVALID_ARG, "dm_create: block_size must be 0 or a multiple of 64 in [64, 512]");
   if (cfg->floor_contact && (!(cfg->delta > 0) || !(cfg->nu > 0) || !(cfg->k_contact >= 0) || !(cfg->mu >= 0)))
@@ -816,12 +856,36 @@ dm_status dm_step(dm_sim* s, double dt, int nsteps, dm_stats* stats) {
   fill_step_args(s, dt, nsteps, A);
   const size_t lds = step_lds(A);
   if (!s->ev0) { DM_HIP(hipEventCreate(&s->ev0)); DM_HIP(hipEventCreate(&s->ev1)); }
-  DM_HIP(hipEventRecord(s->ev0, s->stream));
-  DM_HIP(dm_launch_step(&A, s->block, lds, s->stream));
-  DM_HIP(hipEventRecord(s->ev1, s->stream));
+  if (s->ws_mode == 0) {
+    DM_HIP(hipEventRecord(s->ev0, s->stream));
+    DM_HIP(dm_launch_step(&A, s->block, lds, s->stream));
+    DM_HIP(hipEventRecord(s->ev1, s->stream));
+  } else {
+    // one launch per step: guess, then the step with restart-on-failure, statistics summed
+    dm_status st;
+    if (s->ws_mode == 2 && (st = grow(&s->ws_F, &s->ws_F_n, (size_t)s->ws_rows * 20)) != DM_OK) return st;
+    DM_HIP(hipMemsetAsync(s->dev.s_steps, 0, sizeof(int) * s->n_sys, s->stream));
+    DM_HIP(hipMemsetAsync(s->dev.s_iters, 0, sizeof(int) * s->n_sys, s->stream));
+    DM_HIP(hipMemsetAsync(s->dev.s_status, 0, sizeof(int) * s->n_sys, s->stream));
+    DM_HIP(hipMemsetAsync(s->dev.s_floor, 0, sizeof(int) * s->n_sys, s->stream));
+    DM_HIP(hipMemsetAsync(s->dev.s_fallback, 0, sizeof(int) * s->n_sys, s->stream));
+    A.nsteps = 1;
+    A.warm = 1;
+    A.accum = 1;
+    DM_HIP(hipEventRecord(s->ev0, s->stream));
+    for (int k = 0; k < nsteps; ++k) {
+      if (s->ws_mode == 2)
+        DM_HIP(dm_ws_launch_features(&s->dev, s->ws_rows, s->cn_chain, s->nconst, s->ws_F, s->stream));
+      DM_HIP(dm_ws_launch_guess(&s->dev, s->ws_rows, s->cn_chain, dt, s->ws_mode >= 2,
+                                s->ws_mode == 2 ? s->ws_net : nullptr, s->ws_F, s->stream));
+      DM_HIP(dm_launch_step(&A, s->block, lds, s->stream));
+    }
+    DM_HIP(hipEventRecord(s->ev1, s->stream));
+  }
   DM_HIP(hipStreamSynchronize(s->stream));
   DM_HIP(hipEventElapsedTime(&s->last_kernel_ms, s->ev0, s->ev1));
-  std::vector<int> steps(s->n_sys), iters(s->n_sys), status(s->n_sys), floors(s->n_sys);
+  std::vector<int> steps(s->n_sys), iters(s->n_sys), status(s->n_sys), floors(s->n_sys), falls(s->n_sys);
+  DM_HIP(hipMemcpy(falls.data(), s->dev.s_fallback, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
   std::vector<double> res(s->n_sys);
   DM_HIP(hipMemcpy(steps.data(), s->dev.s_steps, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
   DM_HIP(hipMemcpy(iters.data(), s->dev.s_iters, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
@@ -832,7 +896,7 @@ dm_status dm_step(dm_sim* s, double dt, int nsteps, dm_stats* stats) {
   for (int i = 0; i < s->n_sys; ++i) {
     if (stats) {
       stats[i].steps_done = steps[i]; stats[i].newton_iters = iters[i]; stats[i].status = status[i];
-      stats[i].floor_steps = floors[i]; stats[i].residual = res[i];
+      stats[i].floor_steps = floors[i]; stats[i].residual = res[i]; stats[i].fallbacks = falls[i];
     }
     if (status[i] == DM_ERR_SINGULAR) worst = DM_ERR_SINGULAR;
     else if (status[i] == DM_NOT_CONVERGED && worst == DM_OK) worst = DM_NOT_CONVERGED;
@@ -871,6 +935,37 @@ dm_status dm_set_natural_curvature_all(dm_sim* s, const double* kbar, int on_dev
     off += 2 * (R.n - 2);
   }
   return s->finalized ? upload_kbar(s) : DM_OK;
+}
+
+int dm_ws_rows(const dm_sim* s) { return s && s->finalized ? s->ws_rows : 0; }
+
+dm_status dm_ws_features(dm_sim* s, double* F) {
+  if (!s || !F) return fail(DM_ERR_INVALID_ARG, "dm_ws_features: null argument");
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_ws_features before dm_finalize");
+  DM_HIP(hipSetDevice(s->cfg.device));
+  DM_HIP(dm_ws_launch_features(&s->dev, s->ws_rows, s->cn_chain, s->nconst, F, s->stream));
+  DM_HIP(hipStreamSynchronize(s->stream));
+  return DM_OK;
+}
+
+dm_status dm_ws_targets(dm_sim* s, const double* F_prev, double dt, double* T) {
+  if (!s || !F_prev || !T) return fail(DM_ERR_INVALID_ARG, "dm_ws_targets: null argument");
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_ws_targets before dm_finalize");
+  DM_HIP(hipSetDevice(s->cfg.device));
+  DM_HIP(dm_ws_launch_targets(&s->dev, s->ws_rows, s->cn_chain, F_prev, dt, T, s->stream));
+  DM_HIP(hipStreamSynchronize(s->stream));
+  return DM_OK;
+}
+
+dm_status dm_set_warm_start(dm_sim* s, dm_mlp* net, int mode) {
+  if (!s) return fail(DM_ERR_INVALID_ARG, "null sim");
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_set_warm_start before dm_finalize");
+  if (mode < 0 || mode > 3) return fail(DM_ERR_INVALID_ARG, "dm_set_warm_start: mode must be 0, 1, 2 or 3");
+  if (mode == 2 && (!net || dm_mlp_capacity(net) < s->ws_rows))
+    return fail(DM_ERR_INVALID_ARG, "dm_set_warm_start: network missing or max_rows below dm_ws_rows");
+  s->ws_mode = mode;
+  s->ws_net = mode == 2 ? net : nullptr;
+  return DM_OK;
 }
 
 dm_status dm_rollout(dm_sim* s, double dt, int nsteps, int ckpt_every, double* tips, int on_device) {
@@ -1054,7 +1149,7 @@ dm_status dm_set_state(dm_sim* s, const double* x, const double* th, const doubl
   };
   dm_status st;
   if (x && (st = put3(x, s->dev.x, s->dev.x0)) != DM_OK) return st;
-  if (v && (st = put3(v, s->dev.v, nullptr)) != DM_OK) return st;
+  if (v && (st = put3(v, s->dev.v, s->dev.vprev)) != DM_OK) return st;
   hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   if (th) { DM_HIP(hipMemcpy(s->dev.th, th, sizeof(double) * NE, k)); DM_HIP(hipMemcpy(s->dev.th0, th, sizeof(double) * NE, k)); }
   if (om) DM_HIP(hipMemcpy(s->dev.om, om, sizeof(double) * NE, k));
@@ -1124,7 +1219,8 @@ dm_status dm_load_checkpoint(dm_sim* s, const double* buf, int on_device) {
   const double* p = buf;
   DM_HIP(hipMemcpy(s->dev.x, p, sizeof(double) * 3 * NN, k)); p += 3 * NN;
   DM_HIP(hipMemcpy(s->dev.x0, p, sizeof(double) * 3 * NN, k)); p += 3 * NN;
-  DM_HIP(hipMemcpy(s->dev.v, p, sizeof(double) * 3 * NN, k)); p += 3 * NN;
+  DM_HIP(hipMemcpy(s->dev.v, p, sizeof(double) * 3 * NN, k));
+  DM_HIP(hipMemcpy(s->dev.vprev, p, sizeof(double) * 3 * NN, k)); p += 3 * NN;
   DM_HIP(hipMemcpy(s->dev.th, p, sizeof(double) * NE, k)); p += NE;
   DM_HIP(hipMemcpy(s->dev.th0, p, sizeof(double) * NE, k)); p += NE;
   DM_HIP(hipMemcpy(s->dev.om, p, sizeof(double) * NE, k)); p += NE;

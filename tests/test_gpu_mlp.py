@@ -1,0 +1,162 @@
+"""GPU parity of the warm-start network kernels (dm_mlp_*) and feature kernels against the
+oracle (oracle/mlp.py) on the same seeded inputs.
+
+Tolerances: both sides round every GEMM input to bfloat16 at the same points; products are
+exact, but the GPU accumulates in float32 in the matrix cores' order and the oracle in
+float64, so a pre-activation within ~K 2^-24 of a bfloat16 rounding boundary can round the
+other way.  Such flips change single activations by one bfloat16 ulp (2^-8 relative) and
+occur in a fraction ~K 2^-24 / 2^-8 ~ 1e-3 of the entries of a 256-wide layer, which moves
+outputs and gradients by ~1e-4 relative in norm; the tests allow 1e-3 (forward) and 3e-3
+(gradients).  Adam is elementwise float32 and is checked to 1e-6 relative."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mlp as OM
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2311_18126_amd as m
+    assert os.path.exists(m.LIB_PATH), "libdmrod.so is not built"
+    return m
+
+
+def flat(p):
+    return np.concatenate([p[k].reshape(-1) for k in ("W1", "b1", "W2", "b2", "W3", "b3")]).astype(np.float32)
+
+
+def unflat(v):
+    out, o = {}, 0
+    for k, shp in (("W1", (256, 20)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)), ("W3", (3, 256)), ("b3", (3,))):
+        n = int(np.prod(shp))
+        out[k] = v[o:o + n].reshape(shp)
+        o += n
+    return out
+
+
+def raw_case(n, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    F = rng.normal(size=(n, 20)) * rng.uniform(0.1, 5.0, 20) + rng.normal(size=20)
+    T = rng.normal(size=(n, 3)) * np.array([1e-4, 3e-5, 2e-4])
+    mean, std = F.mean(0), F.std(0)
+    scale = np.sqrt((T * T).mean(0))
+    return F, T, mean, std, scale
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def test_forward_matches_oracle(dm):
+    import torch
+    n = 3000                                   # 47 workgroups of 64 rows and a ragged tail
+    F, T, mean, std, scale = raw_case(n, 1)
+    p = OM.init_params(11)
+    p["b1"][:] = np.random.Generator(np.random.PCG64(2)).normal(0, 0.1, 256)
+    net = dm.Mlp(4096)
+    net.set_params(flat(p))
+    net.set_normalisation(mean, std, scale)
+    Fd = torch.tensor(F, device="cuda")
+    Y = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    y = net.forward(Fd, Y).cpu().numpy()
+    ref, _ = OM.forward(p, OM.standardise(F, mean, std))
+    rel = np.linalg.norm(y - ref) / np.linalg.norm(ref)
+    say(f"forward relative error {rel:.2e}")
+    assert rel < 1e-3
+    assert np.abs(y - ref).max() < 1e-2 * np.abs(ref).max()
+
+
+def test_gradients_match_oracle(dm):
+    import torch
+    n = 9000                                   # three splits of the batch reduction and a ragged tail
+    F, T, mean, std, scale = raw_case(n, 3)
+    p = OM.init_params(12)
+    net = dm.Mlp(n)
+    net.set_params(flat(p))
+    net.set_normalisation(mean, std, scale)
+    G = torch.empty(dm.Mlp.num_params(), dtype=torch.float32, device="cuda")
+    L = net.gradients(torch.tensor(F, device="cuda"), torch.tensor(T, device="cuda"), G)
+    g = unflat(G.cpu().numpy())
+    Ts = OM.to_f32(T / scale)
+    Lr, _, gr = OM.loss_and_backward(p, OM.standardise(F, mean, std), Ts)
+    say(f"loss {L:.6e} oracle {Lr:.6e}")
+    assert abs(L - Lr) < 1e-5 * Lr
+    for k in gr:
+        rel = np.linalg.norm(g[k] - gr[k]) / np.linalg.norm(gr[k])
+        say(f"  {k}: relative error {rel:.2e}")
+        assert rel < 3e-3, k
+
+
+def test_adam_step_applies_the_update_rule(dm):
+    import torch
+    n = 2048
+    F, T, mean, std, scale = raw_case(n, 5)
+    p = OM.init_params(13)
+    net = dm.Mlp(n)
+    net.set_params(flat(p))
+    net.set_normalisation(mean, std, scale)
+    Fd, Td = torch.tensor(F, device="cuda"), torch.tensor(T, device="cuda")
+    m, v = OM.zeros_like(p), OM.zeros_like(p)
+    cur = {k: a.copy() for k, a in p.items()}
+    G = torch.empty(dm.Mlp.num_params(), dtype=torch.float32, device="cuda")
+    for t in (1, 2, 3):
+        net.gradients(Fd, Td, G)
+        g = unflat(G.cpu().numpy().astype(np.float64))
+        OM.adam_step(cur, g, m, v, t, lr=1e-3)
+        net.train_step(Fd, Td, 1e-3)
+        got = unflat(net.get_params())
+        for k in cur:
+            assert np.abs(got[k] - cur[k]).max() <= 1e-6 * max(1.0, np.abs(cur[k]).max()), (t, k)
+
+
+def test_features_and_targets_match_oracle(dm):
+    import torch
+    d = W.rod_batch(6, seed=4, nmin=3, nmax=40)
+    sim = dm.sim_from_description(d)
+    sim.step(d["dt"], 2)
+    vprev = [sim.rod_state(r)[2] for r in range(len(d["rods"]))]
+    sim.step(d["dt"], 1)
+    rows = sim.ws_rows
+    assert rows == sum(r["x0"].shape[0] for r in d["rods"])
+    F = torch.empty((rows, 20), dtype=torch.float64, device="cuda")
+    sim.ws_features(F)
+    Fh = F.cpu().numpy()
+    o = 0
+    vnow = []
+    for r, rd in enumerate(d["rods"]):
+        x, _, v, _ = sim.rod_state(r)
+        n = x.shape[0]
+        eb = np.linalg.norm(np.diff(rd["x0"], axis=0), axis=1)
+        ref = OM.rod_features(x, v, vprev[r], rd["kbar"], rd["E"], rd["radius"], eb)
+        assert np.allclose(Fh[o:o + n], ref, rtol=1e-13, atol=1e-15), r
+        vnow.append(v)
+        o += n
+    sim.step(d["dt"], 1)
+    T = torch.empty((rows, 3), dtype=torch.float64, device="cuda")
+    sim.ws_targets(F, d["dt"], T)
+    Th = T.cpu().numpy()
+    o = 0
+    for r in range(len(d["rods"])):
+        v1 = sim.rod_state(r)[2]
+        n = v1.shape[0]
+        ref = d["dt"] * (v1 - vnow[r] - (vnow[r] - vprev[r]))
+        assert np.allclose(Th[o:o + n], ref, rtol=1e-12, atol=1e-18)
+        o += n
+
+
+def test_normalisation_fit_matches_numpy(dm):
+    import torch
+    F, T, _, _, _ = raw_case(5000, 7)
+    net = dm.Mlp(64)
+    net.fit_normalisation(torch.tensor(F, device="cuda"), torch.tensor(T, device="cuda"))
+    mean, std, scale = net.get_normalisation()
+    assert np.allclose(mean, F.mean(0), rtol=1e-10, atol=1e-12)
+    assert np.allclose(std, F.std(0), rtol=1e-8)
+    assert np.allclose(scale, np.sqrt((T * T).mean(0)), rtol=1e-10)

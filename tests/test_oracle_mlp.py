@@ -18,20 +18,23 @@ def test_bf16_rounding_matches_the_library_conversion():
     assert np.isnan(mlp.bf16_round(np.array([np.nan], dtype=np.float32))[0])
 
 
-def test_features_of_a_straight_rod_at_rest():
+def test_features_of_a_straight_rod():
     n = 5
     x = np.stack([np.linspace(0, 0.4, n), np.zeros(n), np.zeros(n)], 1)
+    x[2, 2] = 0.01
     v = np.zeros((n, 3))
     v[:, 2] = np.arange(n)
+    vp = np.zeros((n, 3))
+    vp[:, 2] = 0.5 * np.arange(n)
     kb = np.arange(2 * (n - 2), dtype=float).reshape(n - 2, 2)
-    f = mlp.rod_features(x, v, kb, 1e7, 2e-3, np.full(n - 1, 0.1))
-    assert np.allclose(f[0, 0:3], 0) and np.allclose(f[0, 3:6], [0.1, 0, 0])
-    assert np.allclose(f[-1, 3:6], 0) and np.allclose(f[-1, 0:3], [-0.1, 0, 0])
-    assert f[0, 8] == 0 and f[0, 11] == 0 and f[0, 14] == 1          # replicated neighbour
-    assert f[-1, 14] == n - 1 and f[2, 8] == 1 and f[2, 14] == 3
-    assert np.array_equal(f[0, 15:17], kb[0]) and np.array_equal(f[-1, 15:17], kb[-1])
-    assert np.array_equal(f[2, 15:17], kb[1])
-    assert np.allclose(f[:, 17], 7.0) and np.allclose(f[:, 18], 2e-3) and np.allclose(f[:, 19], 0.1)
+    f = mlp.rod_features(x, v, vp, kb, 1e7, 2e-3, np.full(n - 1, 0.1))
+    assert f[0, 2] == 0.0 and f[0, 5] == 1.0 and f[-1, 5] == 0.0 and f[-1, 2] == -1.0   # replicated ends
+    assert f[2, 8] == 2 and f[2, 11] == 1.0                          # v and a = v - v_prev
+    assert np.allclose(f[2, 12:15], [0.0, 0.0, -0.02]) and np.allclose(f[1, 12:15], [0.0, 0.0, 0.01])
+    assert np.allclose(f[0, 12:15], [0.1, 0.0, 0.0])                 # x_1 - x_0 at the end
+    assert np.allclose(f[:, 15], 7.0) and np.allclose(f[:, 16], 2e-3) and np.allclose(f[:, 17], 0.1)
+    assert np.array_equal(f[0, 18:20], kb[0]) and np.array_equal(f[-1, 18:20], kb[-1])
+    assert np.array_equal(f[2, 18:20], kb[1])
 
 
 def test_backward_without_rounding_matches_automatic_differentiation():
