@@ -70,6 +70,8 @@ typedef struct {
                              a multiple of 64 */
   int warm_max_iter;      /* Newton iterations allowed to a warm-started solve before it is
                              redone from the step-start state (0 = max_iter) */
+  int use_graphs;         /* 1 (default): warm-started stepping replays one captured HIP graph
+                             per step instead of launching its kernels one by one */
 } dm_config;
 
 /* Per-system counters accumulated over the last dm_step call. */
@@ -237,6 +239,14 @@ dm_status dm_ws_targets(dm_sim* sim, const double* F_prev, double dt, double* T)
  * step at a time and reports fallbacks in dm_stats.  The sim keeps a reference to net.
  * After dm_set_state or dm_load_checkpoint the last-step velocity change a is zero. */
 dm_status dm_set_warm_start(dm_sim* sim, dm_mlp* net, int mode);
+
+/* Autotuner: times the step kernel at each workgroup size (64, 128, 256, 512 threads) over
+ * trial_steps steps of size dt from the current state, keeps the fastest, and restores the
+ * state afterwards (the last-step velocity change of the warm start is reset).  cache_path
+ * (NULL for none) names a text file of "signature block" lines: a signature of the system
+ * layout and device found there is used without timing; a new one is appended.  block_out
+ * (may be NULL) receives the chosen size. */
+dm_status dm_autotune(dm_sim* sim, double dt, int trial_steps, const char* cache_path, int* block_out);
 
 /* Simulation time [s]. */
 double dm_time(const dm_sim* sim);

@@ -31,7 +31,7 @@ class DmConfig(ctypes.Structure):
                 ("line_search", c_int), ("floor_contact", c_int), ("floor_z", c_double),
                 ("delta", c_double), ("nu", c_double), ("mu", c_double), ("k_contact", c_double),
                 ("damping", c_double), ("device", c_int), ("stream", c_void_p), ("block_size", c_int),
-                ("warm_max_iter", c_int)]
+                ("warm_max_iter", c_int), ("use_graphs", c_int)]
 
 
 class DmStats(ctypes.Structure):
@@ -87,6 +87,7 @@ _SIGS = {
     "dm_ws_features": (c_int, [c_void_p, c_void_p]),
     "dm_ws_targets": (c_int, [c_void_p, c_void_p, c_double, c_void_p]),
     "dm_set_warm_start": (c_int, [c_void_p, c_void_p, c_int]),
+    "dm_autotune": (c_int, [c_void_p, c_double, c_int, c_char_p, POINTER(c_int)]),
     "dm_time": (c_double, [c_void_p]),
     "dm_last_kernel_ms": (c_double, [c_void_p]),
     "dm_block_size": (c_int, [c_void_p]),
@@ -141,7 +142,7 @@ class Sim:
 
     def __init__(self, gravity=(0.0, 0.0, -9.81), newton_tol=1e-9, max_iter=50, line_search=False,
                  floor=None, damping=0.0, device=0, stream=None, block_size=0, stagnation_tol=1e-6,
-                 warm_max_iter=0):
+                 warm_max_iter=0, use_graphs=True):
         L = lib()
         cfg = DmConfig()
         L.dm_config_default(ctypes.byref(cfg))
@@ -163,6 +164,7 @@ class Sim:
         cfg.stream = stream
         cfg.block_size = int(block_size)
         cfg.warm_max_iter = int(warm_max_iter)
+        cfg.use_graphs = int(bool(use_graphs))
         h = c_void_p()
         _check(L.dm_create(ctypes.byref(cfg), ctypes.byref(h)), "dm_create")
         self._h = h
@@ -265,6 +267,15 @@ class Sim:
                "dm_get_state")
         return x, th, v, om
 
+    def set_state(self, x=None, theta=None, v=None, theta_dot=None):
+        """Set the bulk state (global numbering, host arrays; None leaves a part unchanged)."""
+        args = []
+        for a, shp in ((x, (self.num_nodes, 3)), (theta, (self.num_edges,)), (v, (self.num_nodes, 3)),
+                       (theta_dot, (self.num_edges,))):
+            args.append(None if a is None else _f64(a, shp))
+        ptr = [a.ctypes.data if a is not None else None for a in args]
+        _check(lib().dm_set_state(self._h, ptr[0], ptr[1], ptr[2], ptr[3], 0), "dm_set_state")
+
     def state_torch(self, device="cuda"):
         """Bulk state copied device-to-device into new torch tensors."""
         import torch
@@ -301,6 +312,13 @@ class Sim:
         buf = torch.empty(lib().dm_checkpoint_size(self._h), dtype=torch.float64, device=device)
         _check(lib().dm_save_checkpoint(self._h, buf.data_ptr(), 1), "dm_save_checkpoint")
         return buf
+
+    def autotune(self, dt, trial_steps=3, cache=None):
+        """Pick the step kernel's workgroup size by timing (cached in the file `cache`)."""
+        b = c_int()
+        _check(lib().dm_autotune(self._h, float(dt), int(trial_steps), cache.encode() if cache else None,
+                                 ctypes.byref(b)), "dm_autotune")
+        return b.value
 
     @property
     def ws_rows(self):

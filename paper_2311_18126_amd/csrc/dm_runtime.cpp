@@ -14,6 +14,7 @@
 #include <numeric>
 #include <string>
 #include <type_traits>
+#include <fstream>
 #include <vector>
 
 #include "../../include/dmrod.h"
@@ -99,6 +100,14 @@ struct dm_sim {
   double* ws_F = nullptr; size_t ws_F_n = 0;
   dm_mlp* ws_net = nullptr;
   int ws_mode = 0;
+  // captured warm-started step (rebuilt when dt, mode, network or block size change)
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  double g_dt = 0.0;
+  int g_mode = -1, g_block = 0;
+  dm_mlp* g_net = nullptr;
+  double* tune_ck = nullptr; size_t tune_ck_n = 0;
   int roll_steps = 0, roll_ckpt = 0;
   double roll_dt = 0.0;
   bool roll_valid = false;
@@ -710,6 +719,7 @@ void dm_config_default(dm_config* c) {
   c->newton_tol = 1e-9;
   c->stagnation_tol = 1e-6;
   c->max_iter = 50;
+  c->use_graphs = 1;
   c->delta = 5e-4;
   c->nu = 1e-3;
   c->mu = 0.0;
@@ -861,26 +871,50 @@ dm_status dm_step(dm_sim* s, double dt, int nsteps, dm_stats* stats) {
     DM_HIP(dm_launch_step(&A, s->block, lds, s->stream));
     DM_HIP(hipEventRecord(s->ev1, s->stream));
   } else {
-    // one launch per step: guess, then the step with restart-on-failure, statistics summed
+    // one step at a time: guess, then the step with restart-on-failure, statistics summed;
+    // replayed from a captured graph unless graphs are off
     dm_status st;
     if (s->ws_mode == 2 && (st = grow(&s->ws_F, &s->ws_F_n, (size_t)s->ws_rows * 20)) != DM_OK) return st;
-    DM_HIP(hipMemsetAsync(s->dev.s_steps, 0, sizeof(int) * s->n_sys, s->stream));
-    DM_HIP(hipMemsetAsync(s->dev.s_iters, 0, sizeof(int) * s->n_sys, s->stream));
-    DM_HIP(hipMemsetAsync(s->dev.s_status, 0, sizeof(int) * s->n_sys, s->stream));
-    DM_HIP(hipMemsetAsync(s->dev.s_floor, 0, sizeof(int) * s->n_sys, s->stream));
-    DM_HIP(hipMemsetAsync(s->dev.s_fallback, 0, sizeof(int) * s->n_sys, s->stream));
+    hipStream_t rs = s->stream;
+    if (s->cfg.use_graphs && !rs) {       // capture needs a stream other than the null stream
+      if (!s->cap_stream) DM_HIP(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+      DM_HIP(hipDeviceSynchronize());
+      rs = s->cap_stream;
+    }
+    for (int* p : {s->dev.s_steps, s->dev.s_iters, s->dev.s_status, s->dev.s_floor, s->dev.s_fallback})
+      DM_HIP(hipMemsetAsync(p, 0, sizeof(int) * s->n_sys, rs));
     A.nsteps = 1;
     A.warm = 1;
     A.accum = 1;
-    DM_HIP(hipEventRecord(s->ev0, s->stream));
-    for (int k = 0; k < nsteps; ++k) {
-      if (s->ws_mode == 2)
-        DM_HIP(dm_ws_launch_features(&s->dev, s->ws_rows, s->cn_chain, s->nconst, s->ws_F, s->stream));
-      DM_HIP(dm_ws_launch_guess(&s->dev, s->ws_rows, s->cn_chain, dt, s->ws_mode >= 2,
-                                s->ws_mode == 2 ? s->ws_net : nullptr, s->ws_F, s->stream));
-      DM_HIP(dm_launch_step(&A, s->block, lds, s->stream));
+    dm_mlp* net = s->ws_mode == 2 ? s->ws_net : nullptr;
+    auto one_step = [&](hipStream_t q) -> hipError_t {
+      hipError_t e = hipSuccess;
+      if (s->ws_mode == 2) e = dm_ws_launch_features(&s->dev, s->ws_rows, s->cn_chain, s->nconst, s->ws_F, q);
+      if (e == hipSuccess) e = dm_ws_launch_guess(&s->dev, s->ws_rows, s->cn_chain, dt, s->ws_mode >= 2, net, s->ws_F, q);
+      if (e == hipSuccess) e = dm_launch_step(&A, s->block, lds, q);
+      return e;
+    };
+    if (s->cfg.use_graphs &&
+        (!s->gexec || s->g_dt != dt || s->g_mode != s->ws_mode || s->g_net != net || s->g_block != s->block)) {
+      if (s->gexec) { DM_HIP(hipGraphExecDestroy(s->gexec)); s->gexec = nullptr; }
+      if (s->graph) { DM_HIP(hipGraphDestroy(s->graph)); s->graph = nullptr; }
+      DM_HIP(hipStreamBeginCapture(rs, hipStreamCaptureModeThreadLocal));
+      hipError_t ce = one_step(rs);
+      hipGraph_t g = nullptr;
+      hipError_t ee = hipStreamEndCapture(rs, &g);
+      if (ce != hipSuccess) { if (g) (void)hipGraphDestroy(g); DM_HIP(ce); }
+      DM_HIP(ee);
+      s->graph = g;
+      DM_HIP(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
+      s->g_dt = dt; s->g_mode = s->ws_mode; s->g_net = net; s->g_block = s->block;
     }
-    DM_HIP(hipEventRecord(s->ev1, s->stream));
+    DM_HIP(hipEventRecord(s->ev0, rs));
+    for (int k = 0; k < nsteps; ++k) {
+      if (s->cfg.use_graphs) DM_HIP(hipGraphLaunch(s->gexec, rs));
+      else DM_HIP(one_step(rs));
+    }
+    DM_HIP(hipEventRecord(s->ev1, rs));
+    DM_HIP(hipStreamSynchronize(rs));
   }
   DM_HIP(hipStreamSynchronize(s->stream));
   DM_HIP(hipEventElapsedTime(&s->last_kernel_ms, s->ev0, s->ev1));
@@ -1094,6 +1128,60 @@ dm_status dm_adjoint(dm_sim* s, const double* dL_dtips, int in_on_device, double
   return DM_OK;
 }
 
+dm_status dm_autotune(dm_sim* s, double dt, int trial_steps, const char* cache_path, int* block_out) {
+  if (!s) return fail(DM_ERR_INVALID_ARG, "null sim");
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_autotune before dm_finalize");
+  if (!(dt > 0) || trial_steps < 1) return fail(DM_ERR_INVALID_ARG, "dm_autotune: bad dt or trial_steps");
+  DM_HIP(hipSetDevice(s->cfg.device));
+  hipDeviceProp_t prop;
+  DM_HIP(hipGetDeviceProperties(&prop, s->cfg.device));
+  int max_cn = 0;
+  for (const DmSystem& S : s->sys) max_cn = std::max(max_cn, S.chain_nodes);
+  char sig[512];
+  std::snprintf(sig, sizeof(sig), "dmrod1 %s sys=%d nodes=%d maxcn=%d arms=%d nb=%d dof=%d mode=%d", prop.gcnArchName,
+                s->n_sys, s->n_nodes, max_cn, s->max_arms, s->max_nb, s->n_dof, s->ws_mode);
+  for (char* c = sig; *c; ++c) if (*c == '\n') *c = ' ';
+  if (cache_path) {
+    std::ifstream in(cache_path);
+    std::string line;
+    while (std::getline(in, line)) {
+      const size_t p = line.rfind(' ');
+      if (p != std::string::npos && line.substr(0, p) == sig) {
+        const int b = std::atoi(line.c_str() + p + 1);
+        if (b >= 64 && b <= 512 && b % 64 == 0) {
+          s->block = b;
+          if (block_out) *block_out = b;
+          return DM_OK;
+        }
+      }
+    }
+  }
+  dm_status st;
+  const size_t n = state_doubles(s);
+  if ((st = grow(&s->tune_ck, &s->tune_ck_n, n)) != DM_OK) return st;
+  if ((st = dm_save_checkpoint(s, s->tune_ck, 1)) != DM_OK) return st;
+  const double t0 = s->time;
+  const int old = s->block;
+  int best = old;
+  float best_ms = 0.0f;
+  for (int b : {64, 128, 256, 512}) {
+    if ((st = dm_load_checkpoint(s, s->tune_ck, 1)) != DM_OK) return st;
+    s->block = b;
+    st = dm_step(s, dt, trial_steps, nullptr);
+    if (st == DM_OK && (best_ms == 0.0f || s->last_kernel_ms < best_ms)) { best_ms = s->last_kernel_ms; best = b; }
+  }
+  if ((st = dm_load_checkpoint(s, s->tune_ck, 1)) != DM_OK) return st;
+  s->time = t0;
+  s->block = best;
+  g_err.clear();
+  if (cache_path) {
+    std::ofstream out(cache_path, std::ios::app);
+    if (out) out << sig << ' ' << best << '\n';
+  }
+  if (block_out) *block_out = best;
+  return DM_OK;
+}
+
 int dm_num_systems(const dm_sim* s) { return s ? s->n_sys : 0; }
 int dm_rod_system(const dm_sim* s, int rod) { return (s && rod >= 0 && rod < (int)s->rod_sys.size()) ? s->rod_sys[rod] : -1; }
 int dm_num_rods(const dm_sim* s) { return s ? (int)s->rods.size() : 0; }
@@ -1264,6 +1352,10 @@ void dm_destroy(dm_sim* s) {
     for (void* p : s->allocs) (void)hipFree(p);
     for (double* p : {s->ck, s->seg, s->adj, s->tips_dev, s->dl_dev}) if (p) (void)hipFree(p);
   }
+  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
+  if (s->graph) (void)hipGraphDestroy(s->graph);
+  if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+  if (s->tune_ck) (void)hipFree(s->tune_ck);
   if (s->ev0) { (void)hipEventDestroy(s->ev0); (void)hipEventDestroy(s->ev1); }
   delete s;
 }
