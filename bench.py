@@ -99,6 +99,103 @@ def per_rod_baseline(dm, desc, steps, n=16):
     return nodes / t_used
 
 
+def timed_steps(sim, dt, steps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = sim.step(dt, steps)
+    torch.cuda.synchronize()
+    return st, time.perf_counter() - t0
+
+
+def warm_start_section(dm, steps, log):
+    """Learned warm start: a network trained on the 1024-rod batch's own trajectories (seed 0,
+    100 steps, every second one), evaluated on 1024 fresh rods (N ~ U{50..400}, seed 3) against
+    the plain step and the analytic predictors at the same residual."""
+    import torch
+
+    import workloads as W
+    from paper_2311_18126_amd import warm_start as WS
+    train = W.rod_batch(1024)
+    sim = dm.sim_from_description(train)
+    t0 = time.perf_counter()
+    F, T = WS.collect(sim, train["dt"], 100, every=2)
+    t_collect = time.perf_counter() - t0
+    n_train = int(F.shape[0])
+    sim.close()
+    ev = W.warm_start_eval(1024, steps=steps)
+    rows = sum(r["x0"].shape[0] for r in ev["rods"])
+    net = dm.Mlp(max_rows=max(rows, 65536))
+    net.set_params(WS.init_params(0))
+    t0 = time.perf_counter()
+    hist = WS.train(net, F, T, epochs=3, batch=8192, lr=1e-3)
+    hist += WS.train(net, F, T, epochs=2, batch=8192, lr=3e-4)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"warm start: {F.shape[0]} training rows, collect {t_collect:.1f} s, train {t_train:.1f} s, "
+        f"loss {hist[0]:.3f} -> {hist[-1]:.3f}")
+    del F, T
+    nodes = float(sum(r["x0"].shape[0] for r in ev["rods"]))
+    out = {"workload": "1024 fresh clamped rods, N~U{50..400} (seed 3), other parameters as the batch",
+           "steps": steps, "training_rows": n_train, "train_s": t_train,
+           "final_training_loss": hist[-1]}
+    for name, mode in (("plain", 0), ("explicit_predictor", 1), ("extrapolation", 3), ("network", 2)):
+        sim = dm.sim_from_description(ev)
+        sim.set_warm_start(net if mode == 2 else None, mode)
+        sim.step(ev["dt"], 2)
+        st, wall = timed_steps(sim, ev["dt"], steps)
+        assert (st["status"] == 0).all()
+        out[f"{name}_value"] = nodes * steps / wall
+        out[f"{name}_iters_per_step"] = float(st["iters"].sum() / st["iters"].size / steps)
+        if mode == 2:
+            out["network_fallbacks"] = int(st["fallbacks"].sum())
+        sim.close()
+    net.close()
+    return out
+
+
+def star_section(dm, steps):
+    """4096 six-limb stars on the floor with actuation (joined rods, arrowhead solve)."""
+    import workloads as W
+    d = W.star_robots(4096)
+    sim = dm.sim_from_description(d)
+    sim.step(d["dt"], 1)
+    st, wall = timed_steps(sim, d["dt"], steps)
+    assert (st["status"] == 0).all()
+    nodes = float(sim.num_nodes)
+    return {"workload": "4096 stars: 6 limbs x 30 nodes on a shared hub, floor contact and friction, "
+                        "sinusoidal actuation (seed 1)", "steps": steps, "value": nodes * steps / wall,
+            "unit": "node-steps/s", "newton_iters_per_step": float(st["iters"].mean() / steps),
+            "block_size": sim.block_size}
+
+
+def adjoint_section(dm):
+    """Gradient of the tip-trajectory loss with respect to natural curvature: 256 rods x 100
+    nodes x 200 steps, checkpoint every 20 (forward rollout + recompute + backward)."""
+    import torch
+
+    import workloads as W
+    d, kstar = W.adjoint_rods()
+    T = d["steps"]
+    sim = dm.sim_from_description(d)
+    start = sim.checkpoint_torch()
+    sim.set_natural_curvature_all(kstar.reshape(-1))
+    target = sim.rollout(d["dt"], T, ckpt_every=20)
+    sim.restore(start)
+    sim.set_natural_curvature_all(np.zeros(kstar.size))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tips = sim.rollout(d["dt"], T, ckpt_every=20)
+    t1 = time.perf_counter()
+    g = sim.adjoint(2.0 * (tips - target))
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    nodes = 256 * 100.0
+    return {"workload": "256 rods x 100 nodes x 200 steps, dt 1e-3, checkpoint every 20", "forward_s": t1 - t0,
+            "backward_s": t2 - t1, "value": nodes * T / (t2 - t0), "unit": "node-steps/s (forward + adjoint)",
+            "grad_norm": float(np.linalg.norm(g))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -106,7 +203,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-per-rod", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="only the batched step (for profiling)")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES bytes device to device once (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); independent rod batches "
@@ -119,13 +220,29 @@ def main():
     import paper_2311_18126_amd as dm
     import workloads as W
 
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        n = args.copy_calibration // 8
+        a = torch.ones(n, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": 8 * n}), flush=True)
+        return
     desc = W.rod_batch(1024)
     n_nodes = np.array([r["x0"].shape[0] for r in desc["rods"]])
     stream = torch.cuda.current_stream()
     sim = dm.sim_from_description(desc, stream=stream.cuda_stream, block_size=args.block)
     dt = desc["dt"]
+    tuned = None
+    if not args.no_autotune and args.block == 0:
+        tuned = sim.autotune(dt, trial_steps=2)
+        log(f"autotuned workgroup size {tuned}")
     if args.warmup > 0:
         sim.step(dt, args.warmup)
     torch.cuda.synchronize()
@@ -158,7 +275,7 @@ def main():
                                "E=10^U(6,8) Pa, kbar~N(0,2^2)/m, gravity, dt=1e-3 s, Newton tol 1e-9",
                    "rods": int(len(n_nodes)), "nodes": int(n_nodes.sum()), "dt": dt,
                    "launch": "one persistent launch per call, one workgroup per rod",
-                   "block_size": sim.block_size},
+                   "block_size": sim.block_size, "autotuned": tuned is not None},
         "newton_iters_per_step": float(iters.sum() / len(iters) / args.steps),
         "floor_steps": int(stats["floor_steps"].sum()),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
@@ -166,6 +283,11 @@ def main():
                      "kernel": "dm_step_kernel", "kernel_ms": 1e3 * kernel_s,
                      "algorithmic_flops": flops},
     }
+    sim.close()
+    if not args.no_extras:
+        out["warm_start"] = warm_start_section(dm, args.steps, log)
+        out["stars"] = star_section(dm, max(args.steps // 5, 5))
+        out["adjoint"] = adjoint_section(dm)
     if not args.no_per_rod:
         out["per_rod_plain_value"] = per_rod_baseline(dm, desc, min(args.steps, 20))
     if not args.no_cpu_baseline:
