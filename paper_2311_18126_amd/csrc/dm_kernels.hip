@@ -477,37 +477,42 @@ __device__ __noinline__ double assemble_border(ArgsP Ap, int sid, double DM_L* B
 // banded elimination of one arm by one wavefront
 // ---------------------------------------------------------------------------
 
+// Band, right-hand side and factor records of one arm.  Entry indices are formed in 32-bit
+// arithmetic with out-of-range entries redirected to the arm's first entry (always valid) by
+// multiplying with the in-range flag, so a load never sits behind a branch.
 struct ArmView {
   const double DM_G* band; const double DM_G* R; double DM_G* fac;
   int dof_off, n, first, dir, count, fac_off;
   __device__ __forceinline__ int cd(int l) const { return first + dir * l; }
-  // address of band entry (l, l2) in arm-local numbering; ok = false outside the band
-  __device__ __forceinline__ const double DM_G* ap(int l, int l2, bool& ok) const {
-    const int r = cd(l), r2 = cd(l2);
-    const int o = r2 - r + DM_HALF_BAND;
-    ok = (r >= 0) & (r < n) & (r2 >= 0) & (r2 < n) & (o >= 0) & (o < DM_NDIAG);
-    return band + (ok ? (size_t)(dof_off + r) * DM_NDIAG + o : (size_t)dof_off * DM_NDIAG);
-  }
-  // address of the right-hand side of local row l; ok = false for the border rows
-  __device__ __forceinline__ const double DM_G* rp(int l, bool& ok) const {
-    ok = l < count;
-    return R + (ok ? dof_off + cd(l) : dof_off);
+  // index of band entry (l, l2) in arm-local numbering; ok = 0 outside the band
+  __device__ __forceinline__ int aidx(int l, int l2, int& ok) const {
+    const int r = cd(l), r2 = cd(l2), o = r2 - r + DM_HALF_BAND;
+    ok = ((unsigned)r < (unsigned)n) & ((unsigned)r2 < (unsigned)n) & ((unsigned)o < (unsigned)DM_NDIAG);
+    return dof_off * DM_NDIAG + ok * (r * DM_NDIAG + o);
   }
   __device__ __forceinline__ double a(int l, int l2) const {
-    bool ok;
-    const double v = *ap(l, l2, ok);
+    int ok;
+    const double v = band[aidx(l, l2, ok)];
     return ok ? v : 0.0;
   }
 };
 
+// Pointer select by bit masks (no branch around the load that follows).
+__device__ __forceinline__ const double DM_G* sel_ptr(bool c, const double DM_G* a, const double DM_G* b) {
+  const unsigned long long ia = (unsigned long long)a, ib = (unsigned long long)b;
+  const unsigned long long m = 0ull - (unsigned long long)c;
+  return (const double DM_G*)((ia & ~m) | (ib & m));
+}
+
 // One window entry for lane `lane`: band entry (l, l2) for lanes 0..10, the right-hand side of
-// row l for lane 11; a single load whose address depends on the lane, with no branch.
+// row l for lane 11 (zero for the border rows l >= count); one load per lane.
 __device__ __forceinline__ double window_entry(const ArmView& V, int l, int l2, int lane) {
-  bool oka, okr;
-  const double DM_G* pa = V.ap(l, l2, oka);
-  const double DM_G* pr = V.rp(l, okr);
+  int oka;
+  const int ia = V.aidx(l, l2, oka);
+  const int okr = l < V.count;
+  const int ir = V.dof_off + okr * V.cd(l);
   const bool rhs = (lane == DM_WIN);
-  const double v = *(rhs ? pr : pa);
+  const double v = *sel_ptr(rhs, V.band + ia, V.R + ir);
   return (rhs ? okr : (oka & (lane < DM_WIN))) ? v : 0.0;
 }
 
@@ -522,35 +527,47 @@ __device__ __forceinline__ void load_window_block(double (&buf)[2 * DM_WIN], int
   for (int i = 1; i <= DM_WIN; ++i) buf[i - 1] = V.a(kp + i, kp + DM_WIN);
 #pragma unroll
   for (int T = 0; T < DM_WIN; ++T) {
-    const int k = k0 + T;
-    buf[DM_WIN + T] = window_entry(V, k + DM_WIN, k + 1 + ((s - T - 1 + 2 * DM_WIN) % DM_WIN), lane);
+    const int l = k0 + T + DM_WIN;                 // the row entering the window at step T
+    int t = s - T - 1;
+    t += t < 0 ? DM_WIN : 0;                       // (s - T - 1) mod 11: this lane's column
+    buf[DM_WIN + T] = window_entry(V, l, l + t - DM_HALF_BAND, lane);
   }
 }
 
 // Eliminate window position k (k % 11 == T).  Lane s < 11 holds the column congruent to s
 // (mod 11) in register slots indexed by row mod 11; lane 11 holds the right-hand side.
+// 1/p from the hardware estimate refined by two Newton corrections (each squares the relative
+// error; the result is within a few ulp of the correctly rounded quotient).
+__device__ __forceinline__ double recip(double p) {
+  double r = __builtin_amdgcn_rcp(p);
+  double e = fma(-p, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-p, r, 1.0);
+  return fma(r, e, r);
+}
+
 template <int T>
 __device__ __forceinline__ void elim_step(double (&w)[DM_WIN], const double (&cur)[2 * DM_WIN], int k, int lane,
                                           const ArmView& V, int& bad) {
   const double piv = readlane_d(w[T], T);
   if (!(fabs(piv) > 1e-300) || !isfinite(piv)) bad = 1;
-  const double inv = 1.0 / piv;
+  const double inv = recip(piv);
   double cv[DM_WIN];
 #pragma unroll
   for (int i = 1; i < DM_WIN; ++i) cv[i] = readlane_d(w[(T + i) % DM_WIN], T);
   const double u = w[T];
-  // factor record of row k: [1/pivot, U(k, k+1..k+10), modified rhs]
-  if (lane <= DM_WIN) {
-    const int j = lane == DM_WIN ? DM_WIN : (lane - T + DM_WIN) % DM_WIN;
-    V.fac[(size_t)(V.fac_off + k) * DM_FAC + j] = (lane == T) ? inv : u;
-  }
-  const double us = u * inv;
   const bool piv_lane = (lane == T);
+  // factor record of row k: [1/pivot, U(k, k+1..k+10), modified rhs]; every lane stores (no
+  // branch), lanes beyond the window into the record's padding
+  const int j = lane < DM_WIN ? (lane - T + DM_WIN) % DM_WIN : (lane == DM_WIN ? DM_WIN : DM_FAC);
+  V.fac[(V.fac_off + k) * DM_FAC_STRIDE + j] = piv_lane ? inv : u;
+  // the pivot lane's scale is exactly 1, so its own column becomes exactly zero and the new
+  // column k + 11 it takes over is added in exactly
+  const double us = piv_lane ? 1.0 : u * inv;
+  const double take = piv_lane ? 1.0 : 0.0;
 #pragma unroll
-  for (int i = 1; i < DM_WIN; ++i) {
-    const double upd = w[(T + i) % DM_WIN] - cv[i] * us;
-    w[(T + i) % DM_WIN] = piv_lane ? cur[i - 1] : upd;   // pivot lane takes over column k + 11
-  }
+  for (int i = 1; i < DM_WIN; ++i)
+    w[(T + i) % DM_WIN] = fma(take, cur[i - 1], fma(-cv[i], us, w[(T + i) % DM_WIN]));
   w[T] = piv_lane ? cur[DM_WIN - 1] : cur[DM_WIN + T];     // entries of the new row k + 11
 }
 
@@ -568,17 +585,13 @@ __device__ __noinline__ void sweep_arm(ArgsP Ap, int ai, double DM_L* delta_lds,
   for (int r = 0; r < DM_WIN; ++r) w[r] = window_entry(V, r, lane < DM_WIN ? lane : 0, lane);
   load_window_block(cur, 0, lane, V);
   int bad = 0;
-  for (int k0 = 0; k0 < arm.count; k0 += DM_WIN) {
+  const int cnt = arm.count;
+  for (int k0 = 0; k0 < cnt; k0 += DM_WIN) {
     load_window_block(nxt, k0 + DM_WIN, lane, V);
-    if (k0 + DM_WIN <= arm.count) {
-#define DM_E(T) elim_step<T>(w, cur, k0 + T, lane, V, bad);
-      DM_UNROLL11(DM_E)
+    // one unrolled block; the last block of an arm stops early on a uniform branch
+#define DM_E(T) if (k0 + T < cnt) elim_step<T>(w, cur, k0 + T, lane, V, bad);
+    DM_UNROLL11(DM_E)
 #undef DM_E
-    } else {
-#define DM_E(T) if (k0 + T < arm.count) elim_step<T>(w, cur, k0 + T, lane, V, bad);
-      DM_UNROLL11(DM_E)
-#undef DM_E
-    }
 #pragma unroll
     for (int q = 0; q < 2 * DM_WIN; ++q) cur[q] = nxt[q];
   }
@@ -603,15 +616,16 @@ __device__ __noinline__ void sweep_arm(ArgsP Ap, int ai, double DM_L* delta_lds,
   if (bad && lane == 0) *bad_flag = 1;
 }
 
-// Back substitution of one 11-row block.  The block's factor records (11 x 12 doubles,
-// contiguous) are spread over the wavefront, three doubles per lane, and broadcast with
+// Back substitution of one 11-row block.  The block's factor records (11 records of 16
+// doubles, contiguous) are spread over the wavefront, three doubles per lane, and broadcast with
 // readlane; the next block's records are loaded while this one is solved.
 template <int T>
 __device__ __forceinline__ void back_step(double (&xv)[DM_WIN], const double (&cur)[3], int l, const ArmView& V,
                                           double DM_G* out, int lane) {
   double rec[DM_FAC];
 #pragma unroll
-  for (int j = 0; j < DM_FAC; ++j) rec[j] = readlane_d(cur[(DM_FAC * T + j) / 64], (DM_FAC * T + j) % 64);
+  for (int j = 0; j < DM_FAC; ++j)
+    rec[j] = readlane_d(cur[(DM_FAC_STRIDE * T + j) / 64], (DM_FAC_STRIDE * T + j) % 64);
   double s = rec[DM_WIN];
 #pragma unroll
   for (int j = 1; j < DM_WIN; ++j) s -= rec[j] * xv[(T + j) % DM_WIN];
@@ -624,9 +638,9 @@ __device__ __forceinline__ void load_block(double (&buf)[3], const ArmView& V, i
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     const int f = lane + 64 * q;
-    const int row = lb + f / DM_FAC;
-    const bool ok = (lb >= 0) & (f < DM_WIN * DM_FAC) & (row < V.count);
-    const double v = V.fac[ok ? (size_t)(V.fac_off + lb) * DM_FAC + f : (size_t)V.fac_off * DM_FAC];
+    const int row = lb + f / DM_FAC_STRIDE;
+    const int ok = (lb >= 0) & (f < DM_WIN * DM_FAC_STRIDE) & (row < V.count);
+    const double v = V.fac[V.fac_off * DM_FAC_STRIDE + ok * (lb * DM_FAC_STRIDE + f)];
     buf[q] = ok ? v : 0.0;
   }
 }
@@ -1095,12 +1109,17 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
         res_prev = res;
         alpha = 1.0;
         halvings = 0;
+        // the arm sweeps, the border solve and the back-substitutions are serial chains on the
+        // critical path of the system: their wavefronts take issue priority over the other
+        // workgroups' element and assembly work sharing the SIMDs
+        __builtin_amdgcn_s_setprio(3);
         for (int a = wave; a < S.n_arms; a += nwaves) sweep_arm(Ap, S.arm0 + a, deltas + a * 110, flags);
         __syncthreads();
         DM_TP(3);
         border_solve(Ap, sid, Bt, ld, deltas, xB, red + 34, flags);
         DM_TP(4);
         for (int a = wave; a < S.n_arms; a += nwaves) backsub_arm(Ap, S.arm0 + a, xB);
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         DM_TP(5);
         if (flags[0]) break;

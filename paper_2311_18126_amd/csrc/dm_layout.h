@@ -33,6 +33,7 @@
 #define DM_NDIAG 21          // band storage: row r holds columns r-10 .. r+10
 #define DM_WIN 11            // elimination window (pivot + 10)
 #define DM_FAC 12            // per eliminated row: 1/pivot, 10 upper entries, modified rhs
+#define DM_FAC_STRIDE 16     // doubles per factor record (entries 12..15: write-only padding)
 #define DM_MAX_CHAINS 8
 #define DM_MAX_BORDER 40
 #define DM_MAX_BSRC 8
@@ -59,7 +60,7 @@ struct DmArm {
   int first;       // first chain DOF eliminated
   int count;       // DOFs eliminated; the next n_trail DOFs along dir are border DOFs
   int n_trail;     // trailing border DOFs in the elimination window (<= 10)
-  int fac_off;     // offset (in DM_FAC records) of local row 0's factor record
+  int fac_off;     // offset (in records of DM_FAC_STRIDE doubles) of local row 0's record
 };
 
 struct DmSystem {
