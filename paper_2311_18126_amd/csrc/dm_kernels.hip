@@ -332,6 +332,15 @@ __device__ __forceinline__ double band_row(const DmStepArgs DM_C& A, const DmCha
   for (int o = 0; o < DM_NDIAG; ++o) acc[o] = 0.0;
   auto emit = [&](int rel, double v) { acc[rel - COMP + 10] += v; };
   double Rr = row_contrib<COMP>(A, ch, k, emit);
+  if (rowb && !rowfix) {
+    // the border-block part of a border row goes to the dense border (assemble_border)
+    double DM_G* bp = A.d.bpr + (size_t)(ch.bmap_off + r - ch.b_lo) * DM_NDIAG;
+#pragma unroll
+    for (int o = 0; o < DM_NDIAG; ++o) {
+      const unsigned bit = 1u << (COMP + 2 + o);
+      bp[o] = ((bmask & bit) && !(fixmask & bit)) ? acc[o] : 0.0;
+    }
+  }
   const unsigned drop = fixmask | (rowb ? bmask : 0u);
 #pragma unroll
   for (int o = 0; o < DM_NDIAG; ++o) {
@@ -388,19 +397,13 @@ __device__ __forceinline__ double border_row(const DmStepArgs DM_C& A, const DmS
     const int r = D.bsrc[2 * (S.bsrc_off + b * DM_MAX_BSRC + q) + 1];
     const DmChain ch = D.chain[ci];
     rhs += D.R[ch.dof_off + r];
-    const int k = r >> 2;
-    auto emit = [&](int rel, double v) {
-      const int col = 4 * k + rel;
-      if (col < ch.b_lo || col >= ch.b_hi) return;
-      const int bc = D.bmap[ch.bmap_off + col - ch.b_lo];
-      if (D.bfix[S.bfix_off + bc]) return;
-      row[bc] += v;
-    };
-    switch (r & 3) {
-      case 0: row_contrib<0>(A, ch, k, emit); break;
-      case 1: row_contrib<1>(A, ch, k, emit); break;
-      case 2: row_contrib<2>(A, ch, k, emit); break;
-      default: row_contrib<3>(A, ch, k, emit); break;
+    // border-column entries of this chain row, written by the band assembly
+    const double DM_G* bp = D.bpr + (size_t)(ch.bmap_off + r - ch.b_lo) * DM_NDIAG;
+    for (int o = 0; o < DM_NDIAG; ++o) {
+      const double v = bp[o];
+      if (v == 0.0) continue;
+      const int col = r - DM_HALF_BAND + o;
+      row[D.bmap[ch.bmap_off + col - ch.b_lo]] += v;
     }
   }
   for (int js = 0; js < S.n_jst; ++js) {
@@ -620,18 +623,21 @@ __device__ __noinline__ void sweep_arm(ArgsP Ap, int ai, double DM_L* delta_lds,
 // doubles, contiguous) are spread over the wavefront, three doubles per lane, and broadcast with
 // readlane; the next block's records are loaded while this one is solved.
 template <int T>
-__device__ __forceinline__ void back_step(double (&xv)[DM_WIN], const double (&cur)[3], int l, const ArmView& V,
-                                          double DM_G* out, int lane) {
+__device__ __forceinline__ void back_step(double (&xv)[DM_WIN], const double (&cur)[3], double& xs, int lane) {
   double rec[DM_FAC];
 #pragma unroll
   for (int j = 0; j < DM_FAC; ++j)
     rec[j] = readlane_d(cur[(DM_FAC_STRIDE * T + j) / 64], (DM_FAC_STRIDE * T + j) % 64);
-  double s = rec[DM_WIN];
+  // y_k - sum_j U(k, k+j) x_{k+j} as two interleaved partial sums (half the dependent chain)
+  double s0 = rec[DM_WIN], s1 = 0.0;
 #pragma unroll
-  for (int j = 1; j < DM_WIN; ++j) s -= rec[j] * xv[(T + j) % DM_WIN];
-  const double xl = s * rec[0];
+  for (int j = 1; j < DM_WIN; ++j) {
+    if (j & 1) s0 = fma(-rec[j], xv[(T + j) % DM_WIN], s0);
+    else s1 = fma(-rec[j], xv[(T + j) % DM_WIN], s1);
+  }
+  const double xl = (s0 + s1) * rec[0];
   xv[T] = xl;
-  if (lane == 0) out[V.dof_off + V.cd(l)] = xl;
+  xs = (lane == T) ? xl : xs;          // lane T keeps the solution of row k0 + T
 }
 
 __device__ __forceinline__ void load_block(double (&buf)[3], const ArmView& V, int lb, int lane) {
@@ -667,9 +673,11 @@ __device__ __noinline__ void backsub_arm(ArgsP Ap, int ai, const double DM_L* xB
   load_block(cur, V, lb, lane);
   for (; lb >= 0; lb -= DM_WIN) {
     load_block(nxt, V, lb - DM_WIN, lane);
-#define DM_B(T) if (lb + (10 - T) < arm.count) back_step<10 - T>(xv, cur, lb + (10 - T), V, D.delta, lane);
+    double xs = 0.0;
+#define DM_B(T) if (lb + (10 - T) < arm.count) back_step<10 - T>(xv, cur, xs, lane);
     DM_UNROLL11(DM_B)
 #undef DM_B
+    if ((lane < DM_WIN) & (lb + lane < arm.count)) D.delta[V.dof_off + V.cd(lb + lane)] = xs;
 #pragma unroll
     for (int q = 0; q < 3; ++q) cur[q] = nxt[q];
   }

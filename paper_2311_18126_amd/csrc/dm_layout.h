@@ -128,6 +128,7 @@ struct DmDev {
   double DM_G* ed;     // [9][n_edges]
   double DM_G* nd;     // [12][n_nodes]
   double DM_G* band;   // [n_dof_total][21]
+  double DM_G* bpr;    // [bmap entries][21]: border-column part of each chain's border rows
   double DM_G* R;      // [n_dof_total]
   double DM_G* fac;    // [n_dof_total][12]
   double DM_G* delta;  // [n_dof_total]

@@ -555,6 +555,7 @@ dm_status do_finalize(dm_sim* s) {
   if ((st = alloc(s, (size_t)DM_ED * NE, &D.ed)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)DM_ND * NN, &D.nd)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)DM_NDIAG * dof_total, &D.band)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)DM_NDIAG * bmap.size(), &D.bpr)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)dof_total, &D.R)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)DM_FAC_STRIDE * std::max(fac_total, 1), &D.fac)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)dof_total, &D.delta)) != DM_OK) return st;
