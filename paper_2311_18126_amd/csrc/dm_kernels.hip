@@ -549,15 +549,22 @@ __device__ __forceinline__ double recip(double p) {
   return fma(r, e, r);
 }
 
+// Value of lane T of each 16-lane row, in every lane of that row (v_mov_b64 with DPP
+// row_newbcast); the elimination window lives in lanes 0..11, all in the first row.
+template <int T>
+__device__ __forceinline__ double row_bcast(double v) {
+  return __builtin_amdgcn_mov_dpp(v, 0x150 + T, 0xF, 0xF, false);
+}
+
 template <int T>
 __device__ __forceinline__ void elim_step(double (&w)[DM_WIN], const double (&cur)[2 * DM_WIN], int k, int lane,
                                           const ArmView& V, int& bad) {
-  const double piv = readlane_d(w[T], T);
+  const double piv = row_bcast<T>(w[T]);
   if (!(fabs(piv) > 1e-300) || !isfinite(piv)) bad = 1;
   const double inv = recip(piv);
   double cv[DM_WIN];
 #pragma unroll
-  for (int i = 1; i < DM_WIN; ++i) cv[i] = readlane_d(w[(T + i) % DM_WIN], T);
+  for (int i = 1; i < DM_WIN; ++i) cv[i] = row_bcast<T>(w[(T + i) % DM_WIN]);
   const double u = w[T];
   const bool piv_lane = (lane == T);
   // factor record of row k: [1/pivot, U(k, k+1..k+10), modified rhs]; every lane stores (no
