@@ -87,14 +87,16 @@ __device__ double block_sum(double v, double DM_L* red) {
 // element evaluation
 // ---------------------------------------------------------------------------
 
-// One lane of a stencil pair.  Pass 0 evaluates the stencil as stored with derivatives
-// seeded on its f edge; pass 1 evaluates the same stencil with its orientation reversed
-// (nodes and edges swapped, edges reversed), which leaves the energy unchanged once the
-// second natural-curvature component changes sign, so that both lanes run the same code.
-// Pass 1's Hessian columns are the e-edge columns of the stored stencil, reached through the
-// signed permutation e_f <-> -e_e, theta_f <-> -theta_e (an even number of sign flips per
-// Hessian entry, so only the indices move).
-__device__ __forceinline__ void eval_stencil(const DmStepArgs DM_C& A, int s, int pass, double t_end) {
+// One lane-task of a stencil.  rev = 0 evaluates the stencil as stored, rev = 1 with its
+// orientation reversed (nodes and edges swapped, edges reversed), which leaves the energy
+// unchanged once the second natural-curvature component changes sign, so both run the same
+// code; SUB selects the two f-edge variables the derivatives are seeded on (0: e_f.x, e_f.y;
+// 1: e_f.z, theta_f).  The reversed stencil's f edge is the stored e edge, so its Hessian
+// columns are the stored stencil's e-edge columns, reached through the signed permutation
+// e_f <-> -e_e, theta_f <-> -theta_e (an even number of sign flips per Hessian entry, so only
+// the indices move).  Two tangents per lane keep the pass within the register file.
+template <int SUB>
+__device__ __forceinline__ void eval_stencil(const DmStepArgs DM_C& A, int s, int rev, double t_end) {
   const DmDev DM_C& D = A.d;
   const int NS = D.n_st_tot, NE = D.n_edges_tot, NN = D.n_nodes_tot;
   int np = D.sn[s], nc = D.sn[NS + s], nn = D.sn[2 * NS + s];
@@ -107,29 +109,30 @@ __device__ __forceinline__ void eval_stencil(const DmStepArgs DM_C& A, int s, in
     k1b = amp * sin(6.283185307179586476925286766559 * D.act[NS + s] * t_end + D.act[2 * NS + s]) * D.Vbar[s];
     k2b = 0.0;
   }
-  if (pass) {
+  if (rev) {
     const int tn = np; np = nn; nn = tn;
     const int te = ef; ef = ee; ee = te;
     const double ts = sf; sf = -se; se = -ts;
     k2b = -k2b;
   }
   const v3 xc = ld3(D.x, NN, nc);
-  double g8[8], H8f[8][4];
-  stencil_pass(xc - ld3(D.x, NN, np), ld3(D.x, NN, nn) - xc, sf * D.th[ef], se * D.th[ee],
-               sf * ld3(D.tref, NE, ef), ld3(D.d1ref, NE, ef), se * ld3(D.tref, NE, ee), ld3(D.d1ref, NE, ee),
-               D.bref[s], k1b, k2b, D.tbar[s], D.kbend[s], D.ktwist[s], g8, H8f);
-  if (!pass) {
+  double g8[8], Hf[8][2];
+  stencil_pass_n<2, 2 * SUB>(xc - ld3(D.x, NN, np), ld3(D.x, NN, nn) - xc, sf * D.th[ef], se * D.th[ee],
+                             sf * ld3(D.tref, NE, ef), ld3(D.d1ref, NE, ef), se * ld3(D.tref, NE, ee),
+                             ld3(D.d1ref, NE, ee), D.bref[s], k1b, k2b, D.tbar[s], D.kbend[s], D.ktwist[s], g8, Hf);
+  if (SUB == 0 && !rev) {
 #pragma unroll
     for (int a = 0; a < 8; ++a) D.st_g[a * NS + s] = g8[a];
   }
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
-    // pass 1 maps variable a of the reversed stencil to its stored-stencil variable
-    const int ra = pass ? (a < 3 ? a + 3 : (a < 6 ? a - 3 : 13 - a)) : a;
+    // the reversed stencil's variable a is the stored stencil's variable ra
+    const int ra = rev ? (a < 3 ? a + 3 : (a < 6 ? a - 3 : 13 - a)) : a;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int w = (k < 3 ? k : 6) + (pass ? (k < 3 ? 3 : 1) : 0);
-      D.st_H[(ra * 8 + w) * NS + s] = H8f[a][k];
+    for (int k = 0; k < 2; ++k) {
+      const int var = 2 * SUB + k;
+      const int w = (var < 3 ? var : 6) + (rev ? (var < 3 ? 3 : 1) : 0);
+      D.st_H[(ra * 8 + w) * NS + s] = Hf[a][k];
     }
   }
 }
@@ -435,14 +438,18 @@ __device__ __forceinline__ double border_row(const DmStepArgs DM_C& A, const DmS
 // Phase drivers: each loops over its items with the whole workgroup, so that the cost of a
 // call is paid once per phase.
 
-// Stencil pairs: 64 consecutive stencils per wavefront and pass, so that a wavefront never
-// mixes the two passes.
+// Stencil tasks: 64 consecutive stencils per wavefront and task kind (two orientations x two
+// tangent halves), so that a wavefront never mixes kinds.
 __device__ __noinline__ void eval_stencils(ArgsP Ap, int sid, double t_end) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmSystem DM_C& S = A.d.sys[uniform(sid)];
-  for (int i = threadIdx.x; i < 128 * ((S.n_st + 63) >> 6); i += blockDim.x) {
-    const int st = ((i >> 7) << 6) + (i & 63);
-    if (st < S.n_st) eval_stencil(A, S.st0 + st, (i >> 6) & 1, t_end);
+  for (int i = threadIdx.x; i < 256 * ((S.n_st + 63) >> 6); i += blockDim.x) {
+    const int st = ((i >> 8) << 6) + (i & 63);
+    const int p = (i >> 6) & 3;          // orientation p >> 1, tangent half p & 1
+    if (st < S.n_st) {
+      if (p & 1) eval_stencil<1>(A, S.st0 + st, p >> 1, t_end);
+      else eval_stencil<0>(A, S.st0 + st, p >> 1, t_end);
+    }
   }
 }
 

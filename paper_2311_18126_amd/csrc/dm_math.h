@@ -124,70 +124,87 @@ DM_HD void edge_frame(const Vec<S>& e, const S& th, v3 tn, v3 d1n, EdgeFrame<S>&
 }
 
 typedef Dual<4> D4;
+typedef Dual<2> D2;
 
 // One pass of the bend/twist stencil energy
 //   E = kbend/2 |kappa - kappa_bar|^2 + ktwist/2 (tau - tau_bar)^2        (Eq. 4-8)
-// with derivatives seeded on the f edge (e_f: tangents 0..2, theta_f: tangent 3).  Outputs the
-// exact gradient g8 with respect to v = (e_f, e_e, theta_f, theta_e) (closed-form strain
-// gradients: classical DER terms plus the holonomy term (d strain/d theta) w), whose tangents
-// are the Hessian columns d g8 / d (e_f, theta_f).  Frames are in the stencil's orientation.
-// Returns the reference twist beta.
-DM_HD double stencil_pass(v3 ef_v, v3 ee_v, double thf_s, double the_s, v3 tnf, v3 d1nf, v3 tne, v3 d1ne,
-                          double bref, double k1bar, double k2bar, double tbar, double kbend, double ktw,
-                          double* g8, double (*H8f)[4]) {
-  Vec<D4> ef;
-  {
-    D4 z; z.v = 0.0;
+// with N derivatives seeded on the f-edge variables S0 .. S0+N-1 of (e_f.x, e_f.y, e_f.z,
+// theta_f).  Outputs the exact gradient g8 with respect to v = (e_f, e_e, theta_f, theta_e)
+// (closed-form strain gradients: classical DER terms plus the holonomy term (d strain/d theta)
+// w), whose tangents are the Hessian columns d g8 / d (seeded variables).  Frames are in the
+// stencil's orientation.  Returns the reference twist beta.
+template <int N, int S0>
+DM_HD double stencil_pass_n(v3 ef_v, v3 ee_v, double thf_s, double the_s, v3 tnf, v3 d1nf, v3 tne, v3 d1ne,
+                            double bref, double k1bar, double k2bar, double tbar, double kbend, double ktw,
+                            double* g8, double (*Hf)[N]) {
+  typedef Dual<N> DN;
+  DN z;
+  z.v = 0.0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) z.d[k] = 0.0;
-    ef.x = z; ef.y = z; ef.z = z;
-    ef.x.v = ef_v.x; ef.y.v = ef_v.y; ef.z.v = ef_v.z;
-    ef.x.d[0] = 1.0; ef.y.d[1] = 1.0; ef.z.d[2] = 1.0;
-  }
-  D4 thf;
+  for (int k = 0; k < N; ++k) z.d[k] = 0.0;
+  Vec<DN> ef;
+  ef.x = z; ef.y = z; ef.z = z;
+  ef.x.v = ef_v.x; ef.y.v = ef_v.y; ef.z.v = ef_v.z;
+  DN thf = z;
   thf.v = thf_s;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) thf.d[k] = (k == 3) ? 1.0 : 0.0;
-  EdgeFrame<D4> F;
+  for (int k = 0; k < N; ++k) {
+    const int var = S0 + k;
+    if (var == 0) ef.x.d[k] = 1.0;
+    if (var == 1) ef.y.d[k] = 1.0;
+    if (var == 2) ef.z.d[k] = 1.0;
+    if (var == 3) thf.d[k] = 1.0;
+  }
+  EdgeFrame<DN> F;
   EdgeFrame<double> G;
   edge_frame(ef, thf, tnf, d1nf, F);
   edge_frame(tov(ee_v), the_s, tne, d1ne, G);
   const double beta = ref_twist(vval(F.t), F.d1v, vval(G.t), G.d1v, bref, false);
   const double tau = the_s - thf_s + beta;                       // Eq. 7
-  D4 ichi = dinv(vdot(F.t, G.t) + 1.0);
-  Vec<D4> kb = vscale(2.0 * ichi, vcross(F.t, G.t));            // Eq. 4
+  DN ichi = dinv(vdot(F.t, G.t) + 1.0);
+  Vec<DN> kb = vscale(2.0 * ichi, vcross(F.t, G.t));            // Eq. 4
   // c_i = kbend (kappa_i - kappa_bar_i), kappa from Eq. 5; a_f, a_e = sum_i c_i d kappa_i / d theta
-  D4 k1 = 0.5 * (vdot(kb, F.m2) + vdot(kb, G.m2));
-  D4 k2 = -0.5 * (vdot(kb, F.m1) + vdot(kb, G.m1));
-  D4 c1 = kbend * (k1 - k1bar);
-  D4 c2 = kbend * (k2 - k2bar);
-  D4 af = -0.5 * (c1 * vdot(kb, F.m1) + c2 * vdot(kb, F.m2));
-  D4 ae = -0.5 * (c1 * vdot(kb, G.m1) + c2 * vdot(kb, G.m2));
+  DN k1 = 0.5 * (vdot(kb, F.m2) + vdot(kb, G.m2));
+  DN k2 = -0.5 * (vdot(kb, F.m1) + vdot(kb, G.m1));
+  DN c1 = kbend * (k1 - k1bar);
+  DN c2 = kbend * (k2 - k2bar);
+  DN af = -0.5 * (c1 * vdot(kb, F.m1) + c2 * vdot(kb, F.m2));
+  DN ae = -0.5 * (c1 * vdot(kb, G.m1) + c2 * vdot(kb, G.m2));
   // ct = ktwist (tau - tau_bar); its tangent is ktwist d tau, with d tau/d e_f = kb/(2|e_f|) - w_f
   // and d tau / d theta_f = -1
-  D4 ct;
+  DN ct;
   {
     const v3 gt = 0.5 * val(F.il) * vval(kb) - vval(F.w);
+    const double gv[4] = {gt.x, gt.y, gt.z, -1.0};
     ct.v = ktw * (tau - tbar);
-    ct.d[0] = ktw * gt.x; ct.d[1] = ktw * gt.y; ct.d[2] = ktw * gt.z; ct.d[3] = -ktw;
+#pragma unroll
+    for (int k = 0; k < N; ++k) ct.d[k] = ktw * gv[S0 + k];
   }
   // the kappa terms of the edge gradients share M = (c1 (m2f + m2e) - c2 (m1f + m1e)) / chi
   // and c_k = c1 kappa1 + c2 kappa2 (classical DER gradients, grouped)
-  D4 ck = c1 * k1 + c2 * k2;
-  Vec<D4> M = vscale(ichi, vsub(vscale(c1, vadd(F.m2, G.m2)), vscale(c2, vadd(F.m1, G.m1))));
-  Vec<D4> V = vadd(vscale(-(ck * ichi), vadd(F.t, G.t)), vscale(0.5 * ct, kb));
-  Vec<D4> gf = vadd(vscale(F.il, vadd(vcross(G.t, M), V)), vscale(af - ct, F.w));
-  Vec<D4> ge = vadd(vscale(G.il, vsub(V, vcross(F.t, M))), vscale(ae + ct, G.w));
-  D4 gthf = af - ct;
-  D4 gthe = ae + ct;
-  const D4* out[8] = {&gf.x, &gf.y, &gf.z, &ge.x, &ge.y, &ge.z, &gthf, &gthe};
+  DN ck = c1 * k1 + c2 * k2;
+  Vec<DN> M = vscale(ichi, vsub(vscale(c1, vadd(F.m2, G.m2)), vscale(c2, vadd(F.m1, G.m1))));
+  Vec<DN> V = vadd(vscale(-(ck * ichi), vadd(F.t, G.t)), vscale(0.5 * ct, kb));
+  Vec<DN> gf = vadd(vscale(F.il, vadd(vcross(G.t, M), V)), vscale(af - ct, F.w));
+  Vec<DN> ge = vadd(vscale(G.il, vsub(V, vcross(F.t, M))), vscale(ae + ct, G.w));
+  DN gthf = af - ct;
+  DN gthe = ae + ct;
+  const DN* out[8] = {&gf.x, &gf.y, &gf.z, &ge.x, &ge.y, &ge.z, &gthf, &gthe};
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
     g8[a] = out[a]->v;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) H8f[a][k] = out[a]->d[k];
+    for (int k = 0; k < N; ++k) Hf[a][k] = out[a]->d[k];
   }
   return beta;
+}
+
+// All four f-edge tangents in one pass.
+DM_HD double stencil_pass(v3 ef_v, v3 ee_v, double thf_s, double the_s, v3 tnf, v3 d1nf, v3 tne, v3 d1ne,
+                          double bref, double k1bar, double k2bar, double tbar, double kbend, double ktw,
+                          double* g8, double (*H8f)[4]) {
+  return stencil_pass_n<4, 0>(ef_v, ee_v, thf_s, the_s, tnf, d1nf, tne, d1ne, bref, k1bar, k2bar, tbar, kbend, ktw,
+                              g8, H8f);
 }
 
 // Local DOF l of a stencil as a signed combination of the 8 stencil variables
