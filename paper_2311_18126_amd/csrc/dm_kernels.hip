@@ -484,28 +484,49 @@ __device__ __noinline__ double assemble_border(ArgsP Ap, int sid, double DM_L* B
 }
 
 // ---------------------------------------------------------------------------
-// banded elimination of one arm by one wavefront
+// banded elimination of up to four arms by one wavefront, one arm per 16-lane row
 // ---------------------------------------------------------------------------
 
-// Band, right-hand side and factor records of one arm.  Entry indices are formed in 32-bit
-// arithmetic with out-of-range entries redirected to the arm's first entry (always valid) by
-// multiplying with the in-range flag, so a load never sits behind a branch.
+// Lane roles: row = lane / 16 selects the arm (rows beyond the group's arm count mirror its
+// last arm: they compute the same values and store them to the same places), l = lane % 16
+// the role within the row: l < 11 a window column, l == 11 the right-hand side, l > 11 idle.
+// Every value that crosses lanes moves by DPP row broadcasts, which stay inside a row.
+
+// Band, right-hand side and factor records of one arm (per lane: the lane's arm), in
+// arm-local numbering: local row l is chain DOF first + dir * l, and lmax local rows exist.
+// Band entry (l, l2) sits at band index b0() + d21() * l + dir * (l2 - l).  Out-of-range
+// entries are redirected to the chain's first band entry (always valid) and zeroed after the
+// load, so a load never sits behind a branch.
 struct ArmView {
-  const double DM_G* band; const double DM_G* R; double DM_G* fac;
-  int dof_off, n, first, dir, count, fac_off;
+  const double DM_G* band; const double DM_G* R; double DM_G* fac; const double DM_G* zpad;
+  int dof_off, first, dir, count, fac_off, lmax;
   __device__ __forceinline__ int cd(int l) const { return first + dir * l; }
-  // index of band entry (l, l2) in arm-local numbering; ok = 0 outside the band
-  __device__ __forceinline__ int aidx(int l, int l2, int& ok) const {
-    const int r = cd(l), r2 = cd(l2), o = r2 - r + DM_HALF_BAND;
-    ok = ((unsigned)r < (unsigned)n) & ((unsigned)r2 < (unsigned)n) & ((unsigned)o < (unsigned)DM_NDIAG);
-    return dof_off * DM_NDIAG + ok * (r * DM_NDIAG + o);
-  }
-  __device__ __forceinline__ double a(int l, int l2) const {
-    int ok;
-    const double v = band[aidx(l, l2, ok)];
-    return ok ? v : 0.0;
-  }
+  __device__ __forceinline__ int b0() const { return (dof_off + first) * DM_NDIAG + DM_HALF_BAND; }
+  __device__ __forceinline__ int d21() const { return DM_NDIAG * dir; }
 };
+
+// The lane's arm within a group of na arms starting at global arm ai0.
+__device__ __forceinline__ int lane_arm(int ai0, int na, int lane) {
+  const int r = lane >> 4;
+  return ai0 + (r < na ? r : na - 1);
+}
+
+__device__ __forceinline__ ArmView arm_view(const DmDev DM_C& D, const DmArm& arm) {
+  const DmChain ch = D.chain[arm.chain];
+  const int n = 4 * ch.n_nodes - 1;
+  return ArmView{D.band, D.R, D.fac, D.zpad, ch.dof_off, arm.first, arm.dir, arm.count, arm.fac_off,
+                 arm.dir > 0 ? n - arm.first : arm.first + 1};
+}
+
+// Smallest and largest arm length of a group (uniform).
+__device__ __forceinline__ void group_counts(const DmDev DM_C& D, int ai0, int na, int& cmin, int& cmax) {
+  cmin = 0x7fffffff; cmax = 0;
+  for (int r = 0; r < na; ++r) {
+    const int c = D.arm[ai0 + r].count;
+    cmin = c < cmin ? c : cmin;
+    cmax = c > cmax ? c : cmax;
+  }
+}
 
 // Pointer select by bit masks (no branch around the load that follows).
 __device__ __forceinline__ const double DM_G* sel_ptr(bool c, const double DM_G* a, const double DM_G* b) {
@@ -514,38 +535,48 @@ __device__ __forceinline__ const double DM_G* sel_ptr(bool c, const double DM_G*
   return (const double DM_G*)((ia & ~m) | (ib & m));
 }
 
-// One window entry for lane `lane`: band entry (l, l2) for lanes 0..10, the right-hand side of
-// row l for lane 11 (zero for the border rows l >= count); one load per lane.
-__device__ __forceinline__ double window_entry(const ArmView& V, int l, int l2, int lane) {
-  int oka;
-  const int ia = V.aidx(l, l2, oka);
-  const int okr = l < V.count;
-  const int ir = V.dof_off + okr * V.cd(l);
-  const bool rhs = (lane == DM_WIN);
-  const double v = *sel_ptr(rhs, V.band + ia, V.R + ir);
-  return (rhs ? okr : (oka & (lane < DM_WIN))) ? v : 0.0;
+// Entry of local row r in the column of role s (s < 11: column r + t - 10, the column
+// congruent to s mod 11 among r-10 .. r, with t = (s - r - 1) mod 11 given by the caller;
+// s == 11: the right-hand side of row r, zero for the border rows r >= count).  One load per
+// lane; a missing entry is read from the zero pad, so the loaded value needs no masking
+// (which would wait for the load).
+__device__ __forceinline__ double row_entry(const ArmView& V, int r, int s, int t) {
+  const int rhs = s == DM_WIN;
+  const int ok = (rhs & (r < V.count)) | ((r < V.lmax) & (s < DM_WIN));
+  const int ib = V.b0() + V.d21() * r + V.dir * (t - DM_HALF_BAND);
+  const int ir = V.dof_off + V.cd(r);
+  return *sel_ptr(ok, V.zpad, sel_ptr(rhs, V.band + ib, V.R + ir));
 }
 
-// Loads of block k0 .. k0+10 for one lane s: buf[0..10] = the column this lane takes over at
-// its pivot step k0 + s (rows k+1 .. k+11 of column k+11); buf[11 + T] = the entry of the row
-// entering at step k0 + T in this lane's column (lane 11: that row's right-hand side).  The
-// band is not modified during elimination, so these are loaded one block ahead.
-__device__ __forceinline__ void load_window_block(double (&buf)[2 * DM_WIN], int k0, int lane, const ArmView& V) {
-  const int s = lane < DM_WIN ? lane : 0;
-  const int kp = k0 + s;
-#pragma unroll
-  for (int i = 1; i <= DM_WIN; ++i) buf[i - 1] = V.a(kp + i, kp + DM_WIN);
-#pragma unroll
-  for (int T = 0; T < DM_WIN; ++T) {
-    const int l = k0 + T + DM_WIN;                 // the row entering the window at step T
-    int t = s - T - 1;
-    t += t < 0 ? DM_WIN : 0;                       // (s - T - 1) mod 11: this lane's column
-    buf[DM_WIN + T] = window_entry(V, l, l + t - DM_HALF_BAND, lane);
-  }
+// (s - T - 1) mod 11 for 0 <= s, T <= 11.
+__device__ __forceinline__ int wrap11(int s, int T) {
+  const int t = s - T - 1;
+  return t < 0 ? t + DM_WIN : t;
 }
 
-// Eliminate window position k (k % 11 == T).  Lane s < 11 holds the column congruent to s
-// (mod 11) in register slots indexed by row mod 11; lane 11 holds the right-hand side.
+// Initial window entry of role s: band entry (r, s) for s < 11, the right-hand side of row r
+// for s == 11 (r, s <= 10, so the entry is inside the band when both rows exist).
+__device__ __forceinline__ double init_entry(const ArmView& V, int r, int s) {
+  const int rhs = s == DM_WIN;
+  const int ok = (rhs & (r < V.count)) | ((r < V.lmax) & (s < V.lmax) & (s < DM_WIN));
+  const int ib = V.b0() + V.d21() * r + V.dir * (s - r);
+  const int ir = V.dof_off + V.cd(r);
+  return *sel_ptr(ok, V.zpad, sel_ptr(rhs, V.band + ib, V.R + ir));
+}
+
+// The column role s takes over at its pivot step kp = k0 + s: rows kp+1 .. kp+11 of column
+// kp + 11 (all in the band; all zero once column kp + 11 is past the chain end, read from the
+// zero pad).  Roles >= 11 load role 0's column, which they never take.
+__device__ __forceinline__ void load_new_column(double (&col)[DM_WIN], int k0, int s, const ArmView& V) {
+  const int kp = k0 + (s < DM_WIN ? s : 0);
+  const bool ok = kp + DM_WIN < V.lmax;
+  // entry (kp + i, kp + 11) at b0 + d21 (kp + i) + dir (11 - i) = x + i * 20 dir
+  const double DM_G* p = sel_ptr(ok, V.zpad, V.band + (V.b0() + V.d21() * kp + DM_WIN * V.dir));
+  const int st = ok ? V.d21() - V.dir : 0;
+#pragma unroll
+  for (int i = 1; i <= DM_WIN; ++i) col[i - 1] = p[i * st];
+}
+
 // 1/p from the hardware estimate refined by two Newton corrections (each squares the relative
 // error; the result is within a few ulp of the correctly rounded quotient).
 __device__ __forceinline__ double recip(double p) {
@@ -557,91 +588,113 @@ __device__ __forceinline__ double recip(double p) {
 }
 
 // Value of lane T of each 16-lane row, in every lane of that row (v_mov_b64 with DPP
-// row_newbcast); the elimination window lives in lanes 0..11, all in the first row.
+// row_newbcast).
 template <int T>
 __device__ __forceinline__ double row_bcast(double v) {
   return __builtin_amdgcn_mov_dpp(v, 0x150 + T, 0xF, 0xF, false);
 }
 
+// Eliminate window position k (k % 11 == T).  Role s < 11 holds the column congruent to s
+// (mod 11) in register slots indexed by row mod 11; role 11 holds the right-hand side.  col:
+// the column the pivot role takes over; ent: the entry of row k + 11 in this role's column.
+// Rows whose arm ends before k leave their window untouched and park their store in the
+// padding of their first record.
 template <int T>
-__device__ __forceinline__ void elim_step(double (&w)[DM_WIN], const double (&cur)[2 * DM_WIN], int k, int lane,
+__device__ __forceinline__ void elim_step(double (&w)[DM_WIN], const double (&col)[DM_WIN], double ent, int k, int l,
                                           const ArmView& V, int& bad) {
+  const bool act = k < V.count;
   const double piv = row_bcast<T>(w[T]);
-  if (!(fabs(piv) > 1e-300) || !isfinite(piv)) bad = 1;
+  if (act && (!(fabs(piv) > 1e-300) || !isfinite(piv))) bad = 1;
   const double inv = recip(piv);
   double cv[DM_WIN];
 #pragma unroll
   for (int i = 1; i < DM_WIN; ++i) cv[i] = row_bcast<T>(w[(T + i) % DM_WIN]);
   const double u = w[T];
-  const bool piv_lane = (lane == T);
+  const bool piv_lane = (l == T);
   // factor record of row k: [1/pivot, U(k, k+1..k+10), modified rhs]; every lane stores (no
-  // branch), lanes beyond the window into the record's padding
-  const int j = lane < DM_WIN ? (lane - T + DM_WIN) % DM_WIN : (lane == DM_WIN ? DM_WIN : DM_FAC);
-  V.fac[(V.fac_off + k) * DM_FAC_STRIDE + j] = piv_lane ? inv : u;
+  // branch), idle roles into the record's padding
+  const int j = l < DM_WIN ? (l - T + DM_WIN) % DM_WIN : (l == DM_WIN ? DM_WIN : DM_FAC);
+  const int rec = act ? (V.fac_off + k) * DM_FAC_STRIDE + j : V.fac_off * DM_FAC_STRIDE + DM_FAC;
+  V.fac[rec] = piv_lane ? inv : u;
   // the pivot lane's scale is exactly 1, so its own column becomes exactly zero and the new
-  // column k + 11 it takes over is added in exactly
-  const double us = piv_lane ? 1.0 : u * inv;
-  const double take = piv_lane ? 1.0 : 0.0;
+  // column k + 11 it takes over is added in exactly; a parked row scales by zero
+  const double us = !act ? 0.0 : (piv_lane ? 1.0 : u * inv);
+  const double take = (act && piv_lane) ? 1.0 : 0.0;
 #pragma unroll
   for (int i = 1; i < DM_WIN; ++i)
-    w[(T + i) % DM_WIN] = fma(take, cur[i - 1], fma(-cv[i], us, w[(T + i) % DM_WIN]));
-  w[T] = piv_lane ? cur[DM_WIN - 1] : cur[DM_WIN + T];     // entries of the new row k + 11
+    w[(T + i) % DM_WIN] = fma(take, col[i - 1], fma(-cv[i], us, w[(T + i) % DM_WIN]));
+  const double wn = piv_lane ? col[DM_WIN - 1] : ent;     // entries of the new row k + 11
+  w[T] = act ? wn : w[T];
 }
 
 #define DM_UNROLL11(M) M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10)
 
-__device__ __noinline__ void sweep_arm(ArgsP Ap, int ai, double DM_L* delta_lds, int DM_L* bad_flag) {
+// Forward elimination of the na (<= 4) arms ai0 .. ai0+na-1; deltas: the Schur-complement
+// slots (110 doubles per arm) of arm ai0.  The new columns of a block are loaded one block
+// ahead; the entering row of step T is loaded right after step T of the previous block, into
+// the register that step has just freed.
+__device__ __noinline__ void sweep_arms(ArgsP Ap, int ai0, int na, double DM_L* deltas, int DM_L* bad_flag) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmDev DM_C& D = A.d;
-  const DmArm DM_C& arm = D.arm[uniform(ai)];
-  const DmChain ch = D.chain[arm.chain];
-  ArmView V{D.band, D.R, D.fac, ch.dof_off, 4 * ch.n_nodes - 1, arm.first, arm.dir, arm.count, arm.fac_off};
-  const int lane = threadIdx.x & 63;
-  double w[DM_WIN], cur[2 * DM_WIN], nxt[2 * DM_WIN];
+  ai0 = uniform(ai0);
+  na = uniform(na);
+  const int lane = threadIdx.x & 63, l = lane & 15;
+  const int ai = lane_arm(ai0, na, lane);
+  const DmArm arm = D.arm[ai];
+  const ArmView V = arm_view(D, arm);
+  int cmin, cmax;
+  group_counts(D, ai0, na, cmin, cmax);
+  double w[DM_WIN], col[DM_WIN], ncol[DM_WIN], ent[DM_WIN];
 #pragma unroll
-  for (int r = 0; r < DM_WIN; ++r) w[r] = window_entry(V, r, lane < DM_WIN ? lane : 0, lane);
-  load_window_block(cur, 0, lane, V);
+  for (int r = 0; r < DM_WIN; ++r) w[r] = init_entry(V, r, l);
+  load_new_column(col, 0, l, V);
+#pragma unroll
+  for (int T = 0; T < DM_WIN; ++T) ent[T] = row_entry(V, T + DM_WIN, l, wrap11(l, T));
   int bad = 0;
-  const int cnt = arm.count;
-  for (int k0 = 0; k0 < cnt; k0 += DM_WIN) {
-    load_window_block(nxt, k0 + DM_WIN, lane, V);
-    // one unrolled block; the last block of an arm stops early on a uniform branch
-#define DM_E(T) if (k0 + T < cnt) elim_step<T>(w, cur, k0 + T, lane, V, bad);
+  for (int k0 = 0; k0 < cmax; k0 += DM_WIN) {
+    load_new_column(ncol, k0 + DM_WIN, l, V);
+    // rows whose arm ends inside the block are masked per step; the group stops on a
+    // uniform branch
+#define DM_E(T) \
+  if (k0 + T < cmax) elim_step<T>(w, col, ent[T], k0 + T, l, V, bad); \
+  ent[T] = row_entry(V, k0 + T + 2 * DM_WIN, l, wrap11(l, T));
     DM_UNROLL11(DM_E)
 #undef DM_E
 #pragma unroll
-    for (int q = 0; q < 2 * DM_WIN; ++q) cur[q] = nxt[q];
+    for (int q = 0; q < DM_WIN; ++q) col[q] = ncol[q];
   }
   // trailing (border) block of the window = this arm's Schur complement contribution
+  double DM_L* dl = deltas + (ai - ai0) * 110;
   const int c0 = arm.count % DM_WIN, nt = arm.n_trail;
-  if (lane < DM_WIN) {
-    const int j = (lane - c0 + DM_WIN) % DM_WIN;
+  if (l < DM_WIN) {
+    const int j = (l - c0 + DM_WIN) % DM_WIN;
     if (j < nt) {
 #pragma unroll
       for (int q = 0; q < DM_WIN; ++q) {
         const int i = (q - c0 + DM_WIN) % DM_WIN;
-        if (i < nt) delta_lds[i * 10 + j] = w[q];
+        if (i < nt) dl[i * 10 + j] = w[q];
       }
     }
-  } else if (lane == DM_WIN) {
+  } else if (l == DM_WIN) {
 #pragma unroll
     for (int q = 0; q < DM_WIN; ++q) {
       const int i = (q - c0 + DM_WIN) % DM_WIN;
-      if (i < nt) delta_lds[100 + i] = w[q];
+      if (i < nt) dl[100 + i] = w[q];
     }
   }
-  if (bad && lane == 0) *bad_flag = 1;
+  if (bad) *bad_flag = 1;
 }
 
-// Back substitution of one 11-row block.  The block's factor records (11 records of 16
-// doubles, contiguous) are spread over the wavefront, three doubles per lane, and broadcast with
-// readlane; the next block's records are loaded while this one is solved.
-template <int T>
-__device__ __forceinline__ void back_step(double (&xv)[DM_WIN], const double (&cur)[3], double& xs, int lane) {
+// Back substitution of one 11-row block.  Role s < 11 of a row holds the factor record of the
+// block's row s of its arm; step T takes record T from the row by DPP broadcasts.  xv: the
+// solution window (slots by row mod 11), the same in every lane of a row.  MASK: rows whose
+// arm ends below the block's row T keep their window (it holds the trailing border values).
+template <int T, bool MASK>
+__device__ __forceinline__ void back_step(double (&xv)[DM_WIN], const double (&cur)[DM_FAC], double& xs, int l,
+                                          bool act) {
   double rec[DM_FAC];
 #pragma unroll
-  for (int j = 0; j < DM_FAC; ++j)
-    rec[j] = readlane_d(cur[(DM_FAC_STRIDE * T + j) / 64], (DM_FAC_STRIDE * T + j) % 64);
+  for (int j = 0; j < DM_FAC; ++j) rec[j] = row_bcast<T>(cur[j]);
   // y_k - sum_j U(k, k+j) x_{k+j} as two interleaved partial sums (half the dependent chain)
   double s0 = rec[DM_WIN], s1 = 0.0;
 #pragma unroll
@@ -650,28 +703,34 @@ __device__ __forceinline__ void back_step(double (&xv)[DM_WIN], const double (&c
     else s1 = fma(-rec[j], xv[(T + j) % DM_WIN], s1);
   }
   const double xl = (s0 + s1) * rec[0];
-  xv[T] = xl;
-  xs = (lane == T) ? xl : xs;          // lane T keeps the solution of row k0 + T
+  xv[T] = (!MASK || act) ? xl : xv[T];
+  xs = (l == T) ? xl : xs;             // role T keeps the solution of row k0 + T
 }
 
-__device__ __forceinline__ void load_block(double (&buf)[3], const ArmView& V, int lb, int lane) {
+// Factor records of block rows lb .. lb+10: role s < 11 loads record lb + s (12 doubles from a
+// 128-byte aligned record, as six 16-byte loads); missing records read the arm's first record.
+__device__ __forceinline__ void load_records(double (&buf)[DM_FAC], const ArmView& V, int lb, int l) {
+  const int ok = (lb >= 0) & (l < DM_WIN) & (lb + l < V.count);
+  const double2 DM_G* p = (const double2 DM_G*)(V.fac + (size_t)(V.fac_off + ok * (lb + l)) * DM_FAC_STRIDE);
 #pragma unroll
-  for (int q = 0; q < 3; ++q) {
-    const int f = lane + 64 * q;
-    const int row = lb + f / DM_FAC_STRIDE;
-    const int ok = (lb >= 0) & (f < DM_WIN * DM_FAC_STRIDE) & (row < V.count);
-    const double v = V.fac[V.fac_off * DM_FAC_STRIDE + ok * (lb * DM_FAC_STRIDE + f)];
-    buf[q] = ok ? v : 0.0;
+  for (int q = 0; q < DM_FAC / 2; ++q) {
+    const double2 v = p[q];
+    buf[2 * q] = v.x;
+    buf[2 * q + 1] = v.y;
   }
 }
 
-__device__ __noinline__ void backsub_arm(ArgsP Ap, int ai, const double DM_L* xB) {
+__device__ __noinline__ void backsub_arms(ArgsP Ap, int ai0, int na, const double DM_L* xB) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmDev DM_C& D = A.d;
-  const DmArm DM_C& arm = D.arm[uniform(ai)];
+  ai0 = uniform(ai0);
+  na = uniform(na);
+  const int lane = threadIdx.x & 63, l = lane & 15;
+  const DmArm arm = D.arm[lane_arm(ai0, na, lane)];
   const DmChain ch = D.chain[arm.chain];
-  ArmView V{D.band, D.R, D.fac, ch.dof_off, 4 * ch.n_nodes - 1, arm.first, arm.dir, arm.count, arm.fac_off};
-  const int lane = threadIdx.x & 63;
+  const ArmView V = arm_view(D, arm);
+  int cmin, cmax;
+  group_counts(D, ai0, na, cmin, cmax);
   const int c0 = arm.count % DM_WIN;
   double xv[DM_WIN];
 #pragma unroll
@@ -681,20 +740,38 @@ __device__ __noinline__ void backsub_arm(ArgsP Ap, int ai, const double DM_L* xB
     if (i < arm.n_trail) val = xB[D.bmap[ch.bmap_off + V.cd(arm.count + i) - ch.b_lo]];
     xv[q] = val;
   }
-  if (arm.count == 0) return;
-  double cur[3], nxt[3];
-  int lb = ((arm.count - 1) / DM_WIN) * DM_WIN;
-  load_block(cur, V, lb, lane);
+  if (cmax == 0) return;
+  double cur[DM_FAC], nxt[DM_FAC];
+  int lb = ((cmax - 1) / DM_WIN) * DM_WIN;
+  load_records(cur, V, lb, l);
   for (; lb >= 0; lb -= DM_WIN) {
-    load_block(nxt, V, lb - DM_WIN, lane);
+    load_records(nxt, V, lb - DM_WIN, l);
     double xs = 0.0;
-#define DM_B(T) if (lb + (10 - T) < arm.count) back_step<10 - T>(xv, cur, xs, lane);
-    DM_UNROLL11(DM_B)
+    if (lb + DM_WIN <= cmin) {
+#define DM_B(T) back_step<10 - T, false>(xv, cur, xs, l, true);
+      DM_UNROLL11(DM_B)
 #undef DM_B
-    if ((lane < DM_WIN) & (lb + lane < arm.count)) D.delta[V.dof_off + V.cd(lb + lane)] = xs;
+    } else {
+#define DM_B(T) if (lb + (10 - T) < cmax) back_step<10 - T, true>(xv, cur, xs, l, lb + (10 - T) < V.count);
+      DM_UNROLL11(DM_B)
+#undef DM_B
+    }
+    if ((l < DM_WIN) & (lb + l < V.count)) D.delta[V.dof_off + V.cd(lb + l)] = xs;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) cur[q] = nxt[q];
+    for (int q = 0; q < DM_FAC; ++q) cur[q] = nxt[q];
   }
+}
+
+// Arms of a system in groups of four, one group per wavefront.
+__device__ __forceinline__ void sweep_all(ArgsP Ap, const DmSystem DM_C& S, int wave, int nwaves,
+                                          double DM_L* deltas, int DM_L* flags) {
+  for (int g = 4 * wave; g < S.n_arms; g += 4 * nwaves)
+    sweep_arms(Ap, S.arm0 + g, min(4, S.n_arms - g), deltas + g * 110, flags);
+}
+
+__device__ __forceinline__ void backsub_all(ArgsP Ap, const DmSystem DM_C& S, int wave, int nwaves,
+                                            const double DM_L* xB) {
+  for (int g = 4 * wave; g < S.n_arms; g += 4 * nwaves) backsub_arms(Ap, S.arm0 + g, min(4, S.n_arms - g), xB);
 }
 
 // Dense border: add the arms' Schur contributions (fixed order), then Gaussian elimination
@@ -1135,12 +1212,12 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
         // critical path of the system: their wavefronts take issue priority over the other
         // workgroups' element and assembly work sharing the SIMDs
         __builtin_amdgcn_s_setprio(3);
-        for (int a = wave; a < S.n_arms; a += nwaves) sweep_arm(Ap, S.arm0 + a, deltas + a * 110, flags);
+        sweep_all(Ap, S, wave, nwaves, deltas, flags);
         __syncthreads();
         DM_TP(3);
         border_solve(Ap, sid, Bt, ld, deltas, xB, red + 34, flags);
         DM_TP(4);
-        for (int a = wave; a < S.n_arms; a += nwaves) backsub_arm(Ap, S.arm0 + a, xB);
+        backsub_all(Ap, S, wave, nwaves, xB);
         __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         DM_TP(5);
@@ -1221,10 +1298,10 @@ __global__ void __launch_bounds__(512) dm_adjoint_kernel(DmAdjArgs) {
     __syncthreads();
     adj_rhs(Pp, sid, Bt, ld);
     __syncthreads();
-    for (int a = wave; a < S.n_arms; a += nwaves) sweep_arm(Ap, S.arm0 + a, deltas + a * 110, flags);
+    sweep_all(Ap, S, wave, nwaves, deltas, flags);
     __syncthreads();
     border_solve(Ap, sid, Bt, ld, deltas, xB, red + 34, flags);
-    for (int a = wave; a < S.n_arms; a += nwaves) backsub_arm(Ap, S.arm0 + a, xB);
+    backsub_all(Ap, S, wave, nwaves, xB);
     __syncthreads();
     if (flags[0]) { status = DM_STATUS_SINGULAR; break; }
     adj_store_lambda(Pp, sid, xB);

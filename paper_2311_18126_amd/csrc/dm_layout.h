@@ -132,6 +132,7 @@ struct DmDev {
   double DM_G* R;      // [n_dof_total]
   double DM_G* fac;    // [n_dof_total][12]
   double DM_G* delta;  // [n_dof_total]
+  double DM_G* zpad;   // [16] zeros, never written: where out-of-range solver loads are sent
   // statistics
   int DM_G* s_steps; int DM_G* s_iters; int DM_G* s_status; double DM_G* s_res; int DM_G* s_floor;
   int DM_G* s_fallback;  // warm-started attempts that had to restart from the step start

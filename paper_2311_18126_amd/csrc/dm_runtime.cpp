@@ -559,6 +559,7 @@ dm_status do_finalize(dm_sim* s) {
   if ((st = alloc(s, (size_t)dof_total, &D.R)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)DM_FAC_STRIDE * std::max(fac_total, 1), &D.fac)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)dof_total, &D.delta)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)16, &D.zpad)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)s->n_sys, &D.s_steps)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)s->n_sys, &D.s_iters)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)s->n_sys, &D.s_status)) != DM_OK) return st;
