@@ -70,8 +70,10 @@ typedef struct {
                              a multiple of 64 */
   int warm_max_iter;      /* Newton iterations allowed to a warm-started solve before it is
                              redone from the step-start state (0 = max_iter) */
-  int use_graphs;         /* 1 (default): warm-started stepping replays one captured HIP graph
-                             per step instead of launching its kernels one by one */
+  int use_graphs;         /* 1 (default): dm_rollout and the adjoint's recomputation replay one
+                             captured HIP graph per checkpoint segment (its one-step launches
+                             and tip gathers or state saves) instead of launching them one by
+                             one; 0: eager launches */
 } dm_config;
 
 /* Per-system counters accumulated over the last dm_step call. */
@@ -234,11 +236,18 @@ dm_status dm_ws_features(dm_sim* sim, double* F);
  * with v_n and a_n taken from the step-start features F_prev. */
 dm_status dm_ws_targets(dm_sim* sim, const double* F_prev, double dt, double* T);
 /* Warm start of dm_step: mode 0 off (Newton from x_n), 1 explicit predictor x_n + dt v_n,
- * 2 the network on top of the second-order extrapolation x_n + dt (v_n + a_n) (net must have
- * max_rows >= dm_ws_rows), 3 that extrapolation alone.  With mode 1..3 dm_step launches one
- * step at a time and reports fallbacks in dm_stats.  The sim keeps a reference to net.
- * After dm_set_state or dm_load_checkpoint the last-step velocity change a is zero. */
+ * 2 the network on top of the second-order extrapolation x_n + dt (v_n + a_n), 3 that
+ * extrapolation alone.  Each system guesses at the start of every step inside the same
+ * persistent launch (the network runs there on the matrix cores); a guess whose Newton solve
+ * fails within warm_max_iter iterations is redone from x_n and counted in dm_stats.fallbacks.
+ * The sim keeps a reference to net, which must outlive its use.  After dm_set_state or
+ * dm_load_checkpoint the last-step velocity change a is zero. */
 dm_status dm_set_warm_start(dm_sim* sim, dm_mlp* net, int mode);
+/* The guessed displacement x^(0) - x_n of every feature row for a step of dt from the
+ * current state under the current warm mode (not 0), into dx [rows][3] (device memory if
+ * on_device, else host); the state is not changed.  Rows of clamped or shared nodes are
+ * reported too (the step leaves clamped DOFs alone and uses the owning rod's row). */
+dm_status dm_ws_predict(dm_sim* sim, double dt, double* dx, int on_device);
 
 /* Autotuner: times the step kernel at each workgroup size (64, 128, 256, 512 threads) over
  * trial_steps steps of size dt from the current state, keeps the fastest, and restores the

@@ -87,6 +87,7 @@ _SIGS = {
     "dm_ws_features": (c_int, [c_void_p, c_void_p]),
     "dm_ws_targets": (c_int, [c_void_p, c_void_p, c_double, c_void_p]),
     "dm_set_warm_start": (c_int, [c_void_p, c_void_p, c_int]),
+    "dm_ws_predict": (c_int, [c_void_p, c_double, c_void_p, c_int]),
     "dm_autotune": (c_int, [c_void_p, c_double, c_int, c_char_p, POINTER(c_int)]),
     "dm_time": (c_double, [c_void_p]),
     "dm_last_kernel_ms": (c_double, [c_void_p]),
@@ -337,8 +338,19 @@ class Sim:
         _check(lib().dm_ws_targets(self._h, features_prev.data_ptr(), dt, out.data_ptr()), "dm_ws_targets")
         return out
 
+    def ws_predict(self, dt, out=None):
+        """Guessed displacement of every feature row for a step of `dt` under the current warm
+        mode, into `out` (float64 device tensor (ws_rows, 3)), or returned as a numpy array."""
+        if out is not None:
+            _check(lib().dm_ws_predict(self._h, dt, out.data_ptr(), 1), "dm_ws_predict")
+            return out
+        h = np.zeros((self.ws_rows, 3))
+        _check(lib().dm_ws_predict(self._h, dt, h.ctypes.data, 0), "dm_ws_predict")
+        return h
+
     def set_warm_start(self, net=None, mode=None):
-        """Warm start of step(): None/0 off, 1 explicit predictor, 2 the network `net`."""
+        """Warm start of step(): None/0 off, 1 explicit predictor x_n + dt v_n, 2 the network
+        `net` on top of the second-order extrapolation, 3 that extrapolation alone."""
         if mode is None:
             mode = 0 if net is None else 2
         _check(lib().dm_set_warm_start(self._h, net._h if net is not None else None, mode), "dm_set_warm_start")

@@ -33,6 +33,11 @@
 #define DM_TSAVE(sid)
 #endif
 
+// tangents per stencil task: the stencil Hessian takes 2 x 4 / DM_STENCIL_TANGENTS tasks
+#ifndef DM_STENCIL_TANGENTS
+#define DM_STENCIL_TANGENTS 2
+#endif
+
 #define DM_STATUS_OK 0
 #define DM_STATUS_NOT_CONVERGED 1
 #define DM_STATUS_SINGULAR (-5)
@@ -95,7 +100,7 @@ __device__ double block_sum(double v, double DM_L* red) {
 // columns are the stored stencil's e-edge columns, reached through the signed permutation
 // e_f <-> -e_e, theta_f <-> -theta_e (an even number of sign flips per Hessian entry, so only
 // the indices move).  Two tangents per lane keep the pass within the register file.
-template <int SUB>
+template <int NT, int SUB>
 __device__ __forceinline__ void eval_stencil(const DmStepArgs DM_C& A, int s, int rev, double t_end) {
   const DmDev DM_C& D = A.d;
   const int NS = D.n_st_tot, NE = D.n_edges_tot, NN = D.n_nodes_tot;
@@ -116,8 +121,8 @@ __device__ __forceinline__ void eval_stencil(const DmStepArgs DM_C& A, int s, in
     k2b = -k2b;
   }
   const v3 xc = ld3(D.x, NN, nc);
-  double g8[8], Hf[8][2];
-  stencil_pass_n<2, 2 * SUB>(xc - ld3(D.x, NN, np), ld3(D.x, NN, nn) - xc, sf * D.th[ef], se * D.th[ee],
+  double g8[8], Hf[8][NT];
+  stencil_pass_n<NT, NT * SUB>(xc - ld3(D.x, NN, np), ld3(D.x, NN, nn) - xc, sf * D.th[ef], se * D.th[ee],
                              sf * ld3(D.tref, NE, ef), ld3(D.d1ref, NE, ef), se * ld3(D.tref, NE, ee),
                              ld3(D.d1ref, NE, ee), D.bref[s], k1b, k2b, D.tbar[s], D.kbend[s], D.ktwist[s], g8, Hf);
   if (SUB == 0 && !rev) {
@@ -129,8 +134,8 @@ __device__ __forceinline__ void eval_stencil(const DmStepArgs DM_C& A, int s, in
     // the reversed stencil's variable a is the stored stencil's variable ra
     const int ra = rev ? (a < 3 ? a + 3 : (a < 6 ? a - 3 : 13 - a)) : a;
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int var = 2 * SUB + k;
+    for (int k = 0; k < NT; ++k) {
+      const int var = NT * SUB + k;
       const int w = (var < 3 ? var : 6) + (rev ? (var < 3 ? 3 : 1) : 0);
       D.st_H[(ra * 8 + w) * NS + s] = Hf[a][k];
     }
@@ -435,6 +440,8 @@ __device__ __forceinline__ double border_row(const DmStepArgs DM_C& A, const DmS
   return rhs * rhs;
 }
 
+#include "dm_warm.h"
+
 // Phase drivers: each loops over its items with the whole workgroup, so that the cost of a
 // call is paid once per phase.
 
@@ -443,12 +450,17 @@ __device__ __forceinline__ double border_row(const DmStepArgs DM_C& A, const DmS
 __device__ __noinline__ void eval_stencils(ArgsP Ap, int sid, double t_end) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmSystem DM_C& S = A.d.sys[uniform(sid)];
-  for (int i = threadIdx.x; i < 256 * ((S.n_st + 63) >> 6); i += blockDim.x) {
-    const int st = ((i >> 8) << 6) + (i & 63);
-    const int p = (i >> 6) & 3;          // orientation p >> 1, tangent half p & 1
+  constexpr int NT = DM_STENCIL_TANGENTS, NSUB = 4 / NT, NTASK = 2 * NSUB;
+  for (int i = threadIdx.x; i < 64 * NTASK * ((S.n_st + 63) >> 6); i += blockDim.x) {
+    const int st = (i / (64 * NTASK)) * 64 + (i & 63);
+    const int p = (i >> 6) % NTASK;      // orientation p / NSUB, tangent group p % NSUB
     if (st < S.n_st) {
-      if (p & 1) eval_stencil<1>(A, S.st0 + st, p >> 1, t_end);
-      else eval_stencil<0>(A, S.st0 + st, p >> 1, t_end);
+      const int rev = p / NSUB, sub = p % NSUB;
+      if (NSUB == 1) eval_stencil<NT, 0>(A, S.st0 + st, rev, t_end);
+      else if (sub == 0) eval_stencil<NT, 0>(A, S.st0 + st, rev, t_end);
+      else if (NSUB == 2 || sub == 1) eval_stencil<NT, (NSUB > 1 ? 1 : 0)>(A, S.st0 + st, rev, t_end);
+      else if (sub == 2) eval_stencil<NT, (NSUB > 2 ? 2 : 0)>(A, S.st0 + st, rev, t_end);
+      else eval_stencil<NT, (NSUB > 3 ? 3 : 0)>(A, S.st0 + st, rev, t_end);
     }
   }
 }
@@ -1156,6 +1168,7 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
   double DM_L* xB = deltas + A.max_arms * 110;             // [max_nb]
   double DM_L* red = xB + A.max_nb;                        // [40]
   int DM_L* flags = (int DM_L*)(red + 40);      // [4]
+  unsigned short DM_L* hbuf = (unsigned short DM_L*)((char DM_L*)lds_raw + A.net_lds);   // network (warm == 2)
   const int tid = threadIdx.x, wave = tid >> 6, nwaves = blockDim.x >> 6;
   if (tid == 0) flags[0] = 0;
   int status = DM_STATUS_OK, iters = 0, steps = 0, floor_hits = 0, fallbacks = 0;
@@ -1169,6 +1182,10 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
     const double t_end = t + A.dt;
     bool conv = false;
     int newton = 0;
+    if (A.warm) {
+      warm_guess(Ap, sid, hbuf, nullptr);
+      __syncthreads();
+    }
     // attempt 0 starts from the current positions (the step start, or a warm-start guess);
     // with a warm start, a failed attempt is repeated from the step start
     for (int attempt = 0; attempt < (A.warm ? 2 : 1) && !conv; ++attempt) {
@@ -1261,6 +1278,21 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
 
 extern "C" hipError_t dm_launch_step(const DmStepArgs* args, int block, size_t lds_bytes, hipStream_t stream) {
   hipLaunchKernelGGL(dm_step_kernel, dim3(args->n_systems), dim3(block), lds_bytes, stream, *args);
+  return hipGetLastError();
+}
+
+// Step-start guess of every system without stepping: out[row][3] = predicted displacement of
+// each chain-node row for the warm mode in the arguments.  One workgroup per system.
+__global__ void __launch_bounds__(512) dm_predict_kernel(DmStepArgs, double* out) {
+  extern __shared__ double lds_raw[];
+  const ArgsP Ap = (ArgsP)__builtin_amdgcn_kernarg_segment_ptr();
+  unsigned short DM_L* hbuf = (unsigned short DM_L*)((char DM_L*)lds_raw + Ap->net_lds);
+  warm_guess(Ap, blockIdx.x, hbuf, (double DM_G*)out);
+}
+
+extern "C" hipError_t dm_launch_predict(const DmStepArgs* args, int block, size_t lds_bytes, double* out,
+                                        hipStream_t stream) {
+  hipLaunchKernelGGL(dm_predict_kernel, dim3(args->n_systems), dim3(block), lds_bytes, stream, *args, out);
   return hipGetLastError();
 }
 

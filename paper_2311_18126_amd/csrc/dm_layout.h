@@ -115,6 +115,8 @@ struct DmDev {
   const double DM_C* kbar;      // [2][n_st] static integrated natural curvature
   const double DM_C* tbar;
   const double DM_C* act;       // [3][n_st] A (1/m), f, phi; A is NaN when not actuated
+  // warm-start network inputs per chain-node row (rows: chains in order, nodes in chain order)
+  const double DM_C* nconst;    // [rows][3] log10 E, radius, mean rest length of the node's edges
   // state
   double DM_G* x;  double DM_G* x0;  double DM_G* v;      // [3][n_nodes]
   double DM_G* vprev;                           // [3][n_nodes] velocity before the last step
@@ -140,17 +142,38 @@ struct DmDev {
   int n_nodes_tot, n_edges_tot, n_st_tot;
 };
 
+// Warm-start network of the step kernel, 20 -> 256 -> 256 -> 3 with ReLU: bfloat16 bit
+// patterns of W1 [256][32], W2 [256][256] and W3 [16][256] (zero padded, reduction index
+// contiguous), float32 biases, and the float64 input standardisation and output scales.
+#define DM_NET_IN 20
+#define DM_NET_HID 256
+#define DM_NET_OUT 3
+#define DM_NET_KX 32          // input width padded to one matrix-core reduction step
+#define DM_NET_OUTP 16        // output width padded to one matrix-core tile
+#define DM_NET_WAVES 4        // wavefronts of a workgroup that run the network
+#define DM_NET_LDS_ROW 264    // bfloat16 per activation row in LDS (256 + 8 padding)
+#define DM_NET_RT 3           // 16-row tiles per network block of the step kernel
+#define DM_NET_LDS_BYTES (2 * 16 * DM_NET_RT * DM_NET_LDS_ROW * 2)   // two activation buffers
+struct DmNetView {
+  const unsigned short DM_C* w1; const unsigned short DM_C* w2; const unsigned short DM_C* w3;
+  const float DM_C* b1; const float DM_C* b2; const float DM_C* b3;
+  const double DM_C* mean; const double DM_C* sd; const double DM_C* ystd;
+};
+
 struct DmStepArgs {
   DmDev d;
+  DmNetView net;
   double dt, tol, stag_tol;
   double g[3];
   double damping;
   double floor_z, delta, nu, mu, kc;
   int floor_on;
   int max_iter, nsteps, line_search;
-  int warm;        // 1: the current positions are a warm-start guess; on failure restart from x_n
+  int warm;        // step-start guess: 0 none (x_n), 1 x_n + dt v_n, 3 + dt (v_n - v_prev),
+                   // 2 that plus the network's correction; a failed guess restarts from x_n
   int warm_max_iter;   // Newton iterations allowed to the warm-started attempt
   int accum;       // 1: add to the statistics (one-step launches) and skip systems that failed
+  int net_lds;     // byte offset of the network's LDS activations (warm == 2)
   int n_systems;
   int max_nb, max_arms;
 };
@@ -177,3 +200,7 @@ struct DmAdjArgs {
   DmStepArgs s;                 // first member: the step arguments at offset 0
   DmAdjDev a;
 };
+
+struct dm_mlp;
+// Device operands of a network for the step kernel (host function of dm_mlp.hip).
+void dm_mlp_view(const dm_mlp* m, DmNetView* v);

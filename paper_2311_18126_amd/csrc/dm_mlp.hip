@@ -16,32 +16,27 @@
 
 #define DM_KERNEL_TU
 #include "dm_layout.h"
+#include "dm_bf16.h"
 #include "dmrod.h"
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef dm_bf16x8 bf16x8;
+typedef dm_f32x4 f32x4;
 typedef uint16_t u16;
 
 namespace {
 
-constexpr int NI = 20, NH = 256, NO = 3;
-constexpr int KX = 32;                    // input width padded to one MFMA reduction step
-constexpr int NOP = 16;                   // output width padded to one MFMA tile
+constexpr int NI = DM_NET_IN, NH = DM_NET_HID, NO = DM_NET_OUT;
+constexpr int KX = DM_NET_KX;             // input width padded to one MFMA reduction step
+constexpr int NOP = DM_NET_OUTP;          // output width padded to one MFMA tile
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NI, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH;
 constexpr int OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NO * NH, NPARAM = OFF_B3 + NO;
 constexpr int ROWS_WG = 64;               // batch rows per workgroup of the row GEMM (4 waves x 16)
 constexpr int WG_CHUNK = 4096;            // batch rows per split of the weight-gradient GEMM
 
-__device__ __forceinline__ u16 bf16_bits(float v) {
-  const uint32_t b = __float_as_uint(v);
-  if (v != v) return 0x7FC0;
-  return (u16)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
-}
+__device__ __forceinline__ u16 bf16_bits(float v) { return dm_bf16_bits(v); }
 __device__ __forceinline__ float bf16_val(u16 h) { return __uint_as_float((uint32_t)h << 16); }
 
-__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
-  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
-}
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) { return dm_mfma_bf16(a, b, c); }
 __device__ __forceinline__ bf16x8 ld8(const u16* p) { return *reinterpret_cast<const bf16x8*>(p); }
 
 enum { EPI_HIDDEN = 0, EPI_OUTPUT = 1, EPI_DGRAD = 2 };
@@ -289,29 +284,6 @@ __global__ void node_features(DmDev D, int rows, const int* __restrict__ cn_chai
     f[19] = D.kbar[NS + s] / D.Vbar[s];
   } else {
     f[18] = f[19] = 0.0;
-  }
-}
-
-// Initial Newton guess on free position DOFs, written by the chain that owns the node:
-// x = x_n + dt v_n (explicit predictor), + dt (v_n - v_prev) (second-order extrapolation), and
-// with the network + scale * y.
-__global__ void apply_guess(DmDev D, int rows, const int* __restrict__ cn_chain, double dt, int second_order,
-                            const float* __restrict__ Y, const double* __restrict__ scale) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= rows) return;
-  const int NN = D.n_nodes_tot;
-  const int c = cn_chain[i];
-  const DmChain ch = D.chain[c];
-  const int k = i - ch.node_tab;
-  const int n0 = D.chain_node[ch.node_tab + k];
-  if (D.node_owner[n0] != c) return;
-  for (int q = 0; q < 3; ++q) {
-    if (D.cfix[ch.dof_off + 4 * k + q]) continue;
-    const double v = D.v[q * NN + n0];
-    double d = dt * v;
-    if (second_order) d += dt * (v - D.vprev[q * NN + n0]);
-    if (Y) d += scale[q] * (double)Y[(size_t)i * NO + q];
-    D.x[q * NN + n0] = D.x0[q * NN + n0] + d;
   }
 }
 
@@ -594,21 +566,10 @@ hipError_t dm_ws_launch_targets(const DmDev* D, int rows, const int* cn_chain, c
   return hipGetLastError();
 }
 
-// Guess for the next step: explicit predictor, + second-order term if second_order, + the
-// network's correction if m is given (F must then hold the step-start features of every row).
-hipError_t dm_ws_launch_guess(const DmDev* D, int rows, const int* cn_chain, double dt, int second_order, dm_mlp* m,
-                              const double* F, hipStream_t st) {
-  const float* Y = nullptr;
-  const double* scale = nullptr;
-  if (m) {
-    m->stream = st;
-    if (forward_rows(m, F, rows, rup(rows, ROWS_WG)) != DM_OK) return hipErrorUnknown;
-    Y = m->Y;
-    scale = m->ystd;
-  }
-  hipLaunchKernelGGL(apply_guess, dim3((rows + 255) / 256), dim3(256), 0, st, *D, rows, cn_chain, dt, second_order, Y,
-                     scale);
-  return hipGetLastError();
-}
-
 }  // extern "C"
+
+#ifndef __HIP_DEVICE_COMPILE__
+void dm_mlp_view(const dm_mlp* m, DmNetView* v) {
+  *v = DmNetView{m->W1b, m->W2b, m->W3b, m->P + OFF_B1, m->P + OFF_B2, m->P + OFF_B3, m->mean, m->sd, m->ystd};
+}
+#endif

@@ -25,13 +25,12 @@ extern "C" hipError_t dm_launch_step(const DmStepArgs* args, int block, size_t l
 extern "C" hipError_t dm_launch_adjoint(const DmAdjArgs* args, int block, size_t lds_bytes, hipStream_t stream);
 extern "C" hipError_t dm_launch_gather_tips(const double* x, int nn, const int* tip, int n, double* out,
                                             hipStream_t stream);
-extern "C" int dm_mlp_capacity(const dm_mlp* m);
+extern "C" hipError_t dm_launch_predict(const DmStepArgs* args, int block, size_t lds_bytes, double* out,
+                                        hipStream_t stream);
 extern "C" hipError_t dm_ws_launch_features(const DmDev* D, int rows, const int* cn_chain, const double* nconst,
                                             double* F, hipStream_t st);
 extern "C" hipError_t dm_ws_launch_targets(const DmDev* D, int rows, const int* cn_chain, const double* Fprev,
                                            double dt, double* T, hipStream_t st);
-extern "C" hipError_t dm_ws_launch_guess(const DmDev* D, int rows, const int* cn_chain, double dt, int second_order,
-                                         dm_mlp* m, const double* F, hipStream_t st);
 
 namespace {
 
@@ -65,6 +64,18 @@ struct DevBuf {
 };
 
 }  // namespace
+
+// One captured trajectory segment: len one-step launches, each followed by the tip gather or
+// the state save; replayed while the step arguments, length and destinations are the same.
+struct SegGraph {
+  DmStepArgs args{};
+  int len = 0, block = 0;
+  size_t lds = 0;
+  const double* tips = nullptr;
+  const double* states = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
 
 struct dm_sim {
   dm_config cfg{};
@@ -100,13 +111,10 @@ struct dm_sim {
   double* ws_F = nullptr; size_t ws_F_n = 0;
   dm_mlp* ws_net = nullptr;
   int ws_mode = 0;
-  // captured warm-started step (rebuilt when dt, mode, network or block size change)
+  // captured step sequences of trajectory segments (dm_rollout, the adjoint's recomputation)
   hipStream_t cap_stream = nullptr;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
-  double g_dt = 0.0;
-  int g_mode = -1, g_block = 0;
-  dm_mlp* g_net = nullptr;
+  std::vector<SegGraph> seg_graphs;
+  double* tips_stage = nullptr; size_t tips_stage_n = 0;
   double* tune_ck = nullptr; size_t tune_ck_n = 0;
   int roll_steps = 0, roll_ckpt = 0;
   double roll_dt = 0.0;
@@ -586,6 +594,7 @@ dm_status do_finalize(dm_sim* s) {
     s->ws_rows = (int)chain_node.size();
     if ((st = upload(s, cnc, &s->cn_chain)) != DM_OK) return st;
     if ((st = upload(s, nc, &s->nconst)) != DM_OK) return st;
+    D.nconst = s->nconst;
   }
 #ifdef DM_PHASE_TIMING
   if ((st = alloc(s, (size_t)s->n_sys * 8, &D.dbg)) != DM_OK) return st;
@@ -622,7 +631,7 @@ size_t state_doubles(const dm_sim* s) { return 3 * (size_t)s->n_nodes * 3 + 3 * 
 
 // Step arguments and LDS size of a launch.
 void fill_step_args(const dm_sim* s, double dt, int nsteps, DmStepArgs& A) {
-  A = DmStepArgs{};
+  std::memset(&A, 0, sizeof(A));       // padding too: captured segments are keyed by these bytes
   A.d = s->dev;
   A.dt = dt;
   A.tol = s->cfg.newton_tol;
@@ -638,10 +647,18 @@ void fill_step_args(const dm_sim* s, double dt, int nsteps, DmStepArgs& A) {
   A.n_systems = s->n_sys;
   A.max_nb = std::max(s->max_nb, 1);
   A.max_arms = std::max(s->max_arms, 1);
+  A.warm = s->ws_mode;
+  if (s->ws_mode == 2) dm_mlp_view(s->ws_net, &A.net);
 }
 
-size_t step_lds(const DmStepArgs& A) {
-  return sizeof(double) * ((size_t)A.max_nb * (A.max_nb + 1) + (size_t)A.max_arms * 110 + A.max_nb + 40 + 2);
+// LDS bytes of a step launch; places the network's activations (warm mode 2) after the
+// solver's arrays, 16-byte aligned.
+size_t step_lds(DmStepArgs& A) {
+  const size_t base =
+      sizeof(double) * ((size_t)A.max_nb * (A.max_nb + 1) + (size_t)A.max_arms * 110 + A.max_nb + 40 + 2);
+  if (A.warm != 2) return base;
+  A.net_lds = (int)((base + 15) / 16 * 16);
+  return (size_t)A.net_lds + DM_NET_LDS_BYTES;
 }
 
 // Device buffer of at least n doubles (contents not kept when it grows).
@@ -662,18 +679,23 @@ size_t traj_stride(const dm_sim* s) {
   return 6 * (size_t)s->n_nodes + 8 * (size_t)s->n_edges + (size_t)s->n_st + (size_t)s->n_sys;
 }
 
-dm_status save_state(dm_sim* s, double* dst) {
+hipError_t save_state_on(const dm_sim* s, double* dst, hipStream_t q) {
   const size_t NN = s->n_nodes, NE = s->n_edges;
   const hipMemcpyKind k = hipMemcpyDeviceToDevice;
   double* p = dst;
-  DM_HIP(hipMemcpyAsync(p, s->dev.x, sizeof(double) * 3 * NN, k, s->stream)); p += 3 * NN;
-  DM_HIP(hipMemcpyAsync(p, s->dev.v, sizeof(double) * 3 * NN, k, s->stream)); p += 3 * NN;
-  DM_HIP(hipMemcpyAsync(p, s->dev.th, sizeof(double) * NE, k, s->stream)); p += NE;
-  DM_HIP(hipMemcpyAsync(p, s->dev.om, sizeof(double) * NE, k, s->stream)); p += NE;
-  DM_HIP(hipMemcpyAsync(p, s->dev.tref, sizeof(double) * 3 * NE, k, s->stream)); p += 3 * NE;
-  DM_HIP(hipMemcpyAsync(p, s->dev.d1ref, sizeof(double) * 3 * NE, k, s->stream)); p += 3 * NE;
-  DM_HIP(hipMemcpyAsync(p, s->dev.bref, sizeof(double) * s->n_st, k, s->stream)); p += s->n_st;
-  DM_HIP(hipMemcpyAsync(p, s->dev.time, sizeof(double) * s->n_sys, k, s->stream));
+  hipError_t e = hipMemcpyAsync(p, s->dev.x, sizeof(double) * 3 * NN, k, q); p += 3 * NN;
+  if (e == hipSuccess) e = hipMemcpyAsync(p, s->dev.v, sizeof(double) * 3 * NN, k, q); p += 3 * NN;
+  if (e == hipSuccess) e = hipMemcpyAsync(p, s->dev.th, sizeof(double) * NE, k, q); p += NE;
+  if (e == hipSuccess) e = hipMemcpyAsync(p, s->dev.om, sizeof(double) * NE, k, q); p += NE;
+  if (e == hipSuccess) e = hipMemcpyAsync(p, s->dev.tref, sizeof(double) * 3 * NE, k, q); p += 3 * NE;
+  if (e == hipSuccess) e = hipMemcpyAsync(p, s->dev.d1ref, sizeof(double) * 3 * NE, k, q); p += 3 * NE;
+  if (e == hipSuccess) e = hipMemcpyAsync(p, s->dev.bref, sizeof(double) * s->n_st, k, q); p += s->n_st;
+  if (e == hipSuccess) e = hipMemcpyAsync(p, s->dev.time, sizeof(double) * s->n_sys, k, q);
+  return e;
+}
+
+dm_status save_state(dm_sim* s, double* dst) {
+  DM_HIP(save_state_on(s, dst, s->stream));
   return DM_OK;
 }
 
@@ -693,6 +715,106 @@ dm_status load_state(dm_sim* s, const double* src) {
   DM_HIP(hipMemcpyAsync(s->dev.bref, p, sizeof(double) * s->n_st, k, s->stream)); p += s->n_st;
   DM_HIP(hipMemcpyAsync(s->dev.time, p, sizeof(double) * s->n_sys, k, s->stream));
   return DM_OK;
+}
+
+// Runs the enclosing call on the capture stream when graphs are on and the sim has no
+// stream (capture needs a stream other than the null stream); device synchronisation fences
+// the call against earlier null-stream work, and the stream is drained on exit.
+struct CaptureStream {
+  dm_sim* s;
+  bool swapped = false;
+  explicit CaptureStream(dm_sim* s_) : s(s_) {
+    if (!s->cfg.use_graphs || s->stream) return;
+    if (!s->cap_stream && hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking) != hipSuccess) return;
+    (void)hipDeviceSynchronize();
+    s->stream = s->cap_stream;
+    swapped = true;
+  }
+  ~CaptureStream() {
+    if (!swapped) return;
+    (void)hipStreamSynchronize(s->stream);
+    s->stream = nullptr;
+  }
+};
+
+// len one-step launches of A; after step i the rod tips go to tips + 3 i n_rods (if tips) and
+// the state to states + (i + 1) W (if states).
+hipError_t seg_sequence(dm_sim* s, const DmStepArgs& A, size_t lds, int len, double* tips, double* states) {
+  const int nr = (int)s->rods.size();
+  const size_t W = traj_stride(s);
+  for (int i = 0; i < len; ++i) {
+    hipError_t e = dm_launch_step(&A, s->block, lds, s->stream);
+    if (e == hipSuccess && tips)
+      e = dm_launch_gather_tips(s->dev.x, s->n_nodes, s->tip_nodes, nr, tips + (size_t)i * nr * 3, s->stream);
+    if (e == hipSuccess && states) e = save_state_on(s, states + (size_t)(i + 1) * W, s->stream);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+// One trajectory segment of len steps (statistics accumulate; a failed system sits out the
+// rest).  With graphs on, the sequence is captured once per step configuration, length and
+// destination and replayed afterwards.
+dm_status run_segment(dm_sim* s, double dt, int len, double* tips, double* states) {
+  DmStepArgs A;
+  fill_step_args(s, dt, 1, A);
+  A.accum = 1;
+  const size_t lds = step_lds(A);
+  if (!s->cfg.use_graphs) {
+    DM_HIP(seg_sequence(s, A, lds, len, tips, states));
+    return DM_OK;
+  }
+  SegGraph* g = nullptr;
+  for (SegGraph& c : s->seg_graphs)
+    if (c.len == len && c.tips == tips && c.states == states && c.block == s->block && c.lds == lds &&
+        std::memcmp(&c.args, &A, sizeof(A)) == 0)
+      g = &c;
+  if (!g) {
+    if (s->seg_graphs.size() >= 8) {
+      for (SegGraph& c : s->seg_graphs) { (void)hipGraphExecDestroy(c.exec); (void)hipGraphDestroy(c.graph); }
+      s->seg_graphs.clear();
+    }
+    SegGraph c;
+    c.args = A; c.len = len; c.tips = tips; c.states = states; c.block = s->block; c.lds = lds;
+    DM_HIP(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    const hipError_t ce = seg_sequence(s, A, lds, len, tips, states);
+    const hipError_t ee = hipStreamEndCapture(s->stream, &c.graph);
+    if (ce != hipSuccess) {
+      if (c.graph) (void)hipGraphDestroy(c.graph);
+      DM_HIP(ce);
+    }
+    DM_HIP(ee);
+    const hipError_t ie = hipGraphInstantiate(&c.exec, c.graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(c.graph);
+      DM_HIP(ie);
+    }
+    s->seg_graphs.push_back(c);
+    g = &s->seg_graphs.back();
+  }
+  DM_HIP(hipGraphLaunch(g->exec, s->stream));
+  return DM_OK;
+}
+
+// Zero the per-system statistics (before accumulating launches).
+dm_status zero_stats(dm_sim* s) {
+  for (int* p : {s->dev.s_steps, s->dev.s_iters, s->dev.s_status, s->dev.s_floor, s->dev.s_fallback})
+    DM_HIP(hipMemsetAsync(p, 0, sizeof(int) * s->n_sys, s->stream));
+  return DM_OK;
+}
+
+// Worst status over the systems after accumulating launches (DM_OK, DM_NOT_CONVERGED or
+// DM_ERR_SINGULAR); synchronises the stream.
+dm_status worst_status(dm_sim* s) {
+  std::vector<int> status(s->n_sys);
+  DM_HIP(hipMemcpyAsync(status.data(), s->dev.s_status, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost, s->stream));
+  DM_HIP(hipStreamSynchronize(s->stream));
+  dm_status w = DM_OK;
+  for (int v : status) {
+    if (v == DM_ERR_SINGULAR) w = DM_ERR_SINGULAR;
+    else if (v == DM_NOT_CONVERGED && w == DM_OK) w = DM_NOT_CONVERGED;
+  }
+  return w;
 }
 
 // The adjoint covers independent rods without contact or time-dependent actuation.
@@ -868,56 +990,10 @@ dm_status dm_step(dm_sim* s, double dt, int nsteps, dm_stats* stats) {
   fill_step_args(s, dt, nsteps, A);
   const size_t lds = step_lds(A);
   if (!s->ev0) { DM_HIP(hipEventCreate(&s->ev0)); DM_HIP(hipEventCreate(&s->ev1)); }
-  if (s->ws_mode == 0) {
-    DM_HIP(hipEventRecord(s->ev0, s->stream));
-    DM_HIP(dm_launch_step(&A, s->block, lds, s->stream));
-    DM_HIP(hipEventRecord(s->ev1, s->stream));
-  } else {
-    // one step at a time: guess, then the step with restart-on-failure, statistics summed;
-    // replayed from a captured graph unless graphs are off
-    dm_status st;
-    if (s->ws_mode == 2 && (st = grow(&s->ws_F, &s->ws_F_n, (size_t)s->ws_rows * 20)) != DM_OK) return st;
-    hipStream_t rs = s->stream;
-    if (s->cfg.use_graphs && !rs) {       // capture needs a stream other than the null stream
-      if (!s->cap_stream) DM_HIP(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
-      DM_HIP(hipDeviceSynchronize());
-      rs = s->cap_stream;
-    }
-    for (int* p : {s->dev.s_steps, s->dev.s_iters, s->dev.s_status, s->dev.s_floor, s->dev.s_fallback})
-      DM_HIP(hipMemsetAsync(p, 0, sizeof(int) * s->n_sys, rs));
-    A.nsteps = 1;
-    A.warm = 1;
-    A.accum = 1;
-    dm_mlp* net = s->ws_mode == 2 ? s->ws_net : nullptr;
-    auto one_step = [&](hipStream_t q) -> hipError_t {
-      hipError_t e = hipSuccess;
-      if (s->ws_mode == 2) e = dm_ws_launch_features(&s->dev, s->ws_rows, s->cn_chain, s->nconst, s->ws_F, q);
-      if (e == hipSuccess) e = dm_ws_launch_guess(&s->dev, s->ws_rows, s->cn_chain, dt, s->ws_mode >= 2, net, s->ws_F, q);
-      if (e == hipSuccess) e = dm_launch_step(&A, s->block, lds, q);
-      return e;
-    };
-    if (s->cfg.use_graphs &&
-        (!s->gexec || s->g_dt != dt || s->g_mode != s->ws_mode || s->g_net != net || s->g_block != s->block)) {
-      if (s->gexec) { DM_HIP(hipGraphExecDestroy(s->gexec)); s->gexec = nullptr; }
-      if (s->graph) { DM_HIP(hipGraphDestroy(s->graph)); s->graph = nullptr; }
-      DM_HIP(hipStreamBeginCapture(rs, hipStreamCaptureModeThreadLocal));
-      hipError_t ce = one_step(rs);
-      hipGraph_t g = nullptr;
-      hipError_t ee = hipStreamEndCapture(rs, &g);
-      if (ce != hipSuccess) { if (g) (void)hipGraphDestroy(g); DM_HIP(ce); }
-      DM_HIP(ee);
-      s->graph = g;
-      DM_HIP(hipGraphInstantiate(&s->gexec, s->graph, nullptr, nullptr, 0));
-      s->g_dt = dt; s->g_mode = s->ws_mode; s->g_net = net; s->g_block = s->block;
-    }
-    DM_HIP(hipEventRecord(s->ev0, rs));
-    for (int k = 0; k < nsteps; ++k) {
-      if (s->cfg.use_graphs) DM_HIP(hipGraphLaunch(s->gexec, rs));
-      else DM_HIP(one_step(rs));
-    }
-    DM_HIP(hipEventRecord(s->ev1, rs));
-    DM_HIP(hipStreamSynchronize(rs));
-  }
+  // one persistent launch for all steps; a warm start guesses inside it at every step start
+  DM_HIP(hipEventRecord(s->ev0, s->stream));
+  DM_HIP(dm_launch_step(&A, s->block, lds, s->stream));
+  DM_HIP(hipEventRecord(s->ev1, s->stream));
   DM_HIP(hipStreamSynchronize(s->stream));
   DM_HIP(hipEventElapsedTime(&s->last_kernel_ms, s->ev0, s->ev1));
   std::vector<int> steps(s->n_sys), iters(s->n_sys), status(s->n_sys), floors(s->n_sys), falls(s->n_sys);
@@ -997,10 +1073,31 @@ dm_status dm_set_warm_start(dm_sim* s, dm_mlp* net, int mode) {
   if (!s) return fail(DM_ERR_INVALID_ARG, "null sim");
   if (!s->finalized) return fail(DM_ERR_STATE, "dm_set_warm_start before dm_finalize");
   if (mode < 0 || mode > 3) return fail(DM_ERR_INVALID_ARG, "dm_set_warm_start: mode must be 0, 1, 2 or 3");
-  if (mode == 2 && (!net || dm_mlp_capacity(net) < s->ws_rows))
-    return fail(DM_ERR_INVALID_ARG, "dm_set_warm_start: network missing or max_rows below dm_ws_rows");
+  if (mode == 2 && !net) return fail(DM_ERR_INVALID_ARG, "dm_set_warm_start: mode 2 needs a network");
   s->ws_mode = mode;
   s->ws_net = mode == 2 ? net : nullptr;
+  return DM_OK;
+}
+
+dm_status dm_ws_predict(dm_sim* s, double dt, double* dx, int on_device) {
+  if (!s || !dx) return fail(DM_ERR_INVALID_ARG, "dm_ws_predict: null argument");
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_ws_predict before dm_finalize");
+  if (s->ws_mode == 0) return fail(DM_ERR_STATE, "dm_ws_predict: no warm start set");
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(DM_ERR_INVALID_ARG, "dm_ws_predict: bad dt");
+  DM_HIP(hipSetDevice(s->cfg.device));
+  DmStepArgs A;
+  fill_step_args(s, dt, 0, A);
+  const size_t lds = step_lds(A);
+  const size_t n = (size_t)s->ws_rows * 3;
+  double* out = dx;
+  dm_status st;
+  if (!on_device) {
+    if ((st = grow(&s->ws_F, &s->ws_F_n, n)) != DM_OK) return st;
+    out = s->ws_F;
+  }
+  DM_HIP(dm_launch_predict(&A, s->block, lds, out, s->stream));
+  if (!on_device) DM_HIP(hipMemcpyAsync(dx, out, sizeof(double) * n, hipMemcpyDeviceToHost, s->stream));
+  DM_HIP(hipStreamSynchronize(s->stream));
   return DM_OK;
 }
 
@@ -1029,15 +1126,26 @@ dm_status dm_rollout(dm_sim* s, double dt, int nsteps, int ckpt_every, double* t
     if ((st = grow(&s->tips_dev, &s->tips_n, (size_t)nsteps * nr * 3)) != DM_OK) return st;
     tdev = s->tips_dev;
   }
-  for (int k = 0; k < nsteps; ++k) {
-    if (k % ckpt_every == 0 && (st = save_state(s, s->ck + (size_t)(k / ckpt_every) * W)) != DM_OK) return st;
-    st = dm_step(s, dt, 1, nullptr);
-    if (st != DM_OK) return fail(st, "dm_rollout: step " + std::to_string(k) + " failed: " + g_err);
-    DM_HIP(dm_launch_gather_tips(s->dev.x, s->n_nodes, s->tip_nodes, nr, tdev + (size_t)k * nr * 3, s->stream));
+  // captured segments gather the tips into a fixed staging buffer, copied out per segment
+  if (s->cfg.use_graphs &&
+      (st = grow(&s->tips_stage, &s->tips_stage_n, (size_t)std::min(ckpt_every, nsteps) * nr * 3)) != DM_OK)
+    return st;
+  CaptureStream cs(s);
+  if ((st = zero_stats(s)) != DM_OK) return st;
+  for (int k0 = 0; k0 < nsteps; k0 += ckpt_every) {
+    const int len = std::min(ckpt_every, nsteps - k0);
+    DM_HIP(save_state_on(s, s->ck + (size_t)(k0 / ckpt_every) * W, s->stream));
+    double* out = tdev + (size_t)k0 * nr * 3;
+    if ((st = run_segment(s, dt, len, s->cfg.use_graphs ? s->tips_stage : out, nullptr)) != DM_OK) return st;
+    if (s->cfg.use_graphs)
+      DM_HIP(hipMemcpyAsync(out, s->tips_stage, sizeof(double) * (size_t)len * nr * 3, hipMemcpyDeviceToDevice,
+                            s->stream));
   }
   if (!on_device)
     DM_HIP(hipMemcpyAsync(tips, tdev, sizeof(double) * (size_t)nsteps * nr * 3, hipMemcpyDeviceToHost, s->stream));
-  DM_HIP(hipStreamSynchronize(s->stream));
+  st = worst_status(s);
+  s->time += dt * nsteps;
+  if (st != DM_OK) return fail(st, "dm_rollout: a step failed in some system (state rolled back to that step)");
   s->roll_steps = nsteps;
   s->roll_ckpt = ckpt_every;
   s->roll_dt = dt;
@@ -1051,6 +1159,7 @@ dm_status dm_adjoint(dm_sim* s, const double* dL_dtips, int in_on_device, double
   dm_status st;
   if ((st = adjoint_supported(s)) != DM_OK) return st;
   DM_HIP(hipSetDevice(s->cfg.device));
+  CaptureStream cs(s);
   const size_t NN = s->n_nodes, NE = s->n_edges, NS = s->n_st, W = traj_stride(s);
   const int T = s->roll_steps, C = s->roll_ckpt, nr = (int)s->rods.size();
   const int nck = (T + C - 1) / C;
@@ -1094,11 +1203,10 @@ dm_status dm_adjoint(dm_sim* s, const double* dL_dtips, int in_on_device, double
     const int g0 = j * C, len = std::min(C, T - g0);
     if ((st = load_state(s, s->ck + (size_t)j * W)) != DM_OK) return st;
     if ((st = save_state(s, s->seg)) != DM_OK) return st;
-    for (int i = 0; i < len; ++i) {
-      st = dm_step(s, dt, 1, nullptr);
-      if (st != DM_OK) return fail(st, "dm_adjoint: recomputed step " + std::to_string(g0 + i) + " failed: " + g_err);
-      if ((st = save_state(s, s->seg + (size_t)(i + 1) * W)) != DM_OK) return st;
-    }
+    if ((st = zero_stats(s)) != DM_OK) return st;
+    if ((st = run_segment(s, dt, len, nullptr, s->seg)) != DM_OK) return st;
+    if ((st = worst_status(s)) != DM_OK)
+      return fail(st, "dm_adjoint: a recomputed step of segment " + std::to_string(j) + " failed");
     P.a.seg_len = len;
     P.a.step0 = g0;
     DM_HIP(dm_launch_adjoint(&P, s->block, lds, s->stream));
@@ -1354,8 +1462,7 @@ void dm_destroy(dm_sim* s) {
     for (void* p : s->allocs) (void)hipFree(p);
     for (double* p : {s->ck, s->seg, s->adj, s->tips_dev, s->dl_dev}) if (p) (void)hipFree(p);
   }
-  if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
-  if (s->graph) (void)hipGraphDestroy(s->graph);
+  for (SegGraph& c : s->seg_graphs) { (void)hipGraphExecDestroy(c.exec); (void)hipGraphDestroy(c.graph); }
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
   if (s->tune_ck) (void)hipFree(s->tune_ck);
   if (s->ev0) { (void)hipEventDestroy(s->ev0); (void)hipEventDestroy(s->ev1); }

@@ -1,6 +1,6 @@
-"""Batching machinery on the GPU: the captured per-step graph of warm-started stepping
-(checked replay by replay against eager launches, with the program's own work and
-synchronisation between replays) and the workgroup-size autotuner."""
+"""Batching machinery on the GPU: trajectory segments captured as HIP graphs (rollout and the
+adjoint's recomputation; checked replay by replay against eager launches, with the program's
+own work and synchronisation between replays) and the workgroup-size autotuner."""
 import os
 
 import numpy as np
@@ -24,45 +24,61 @@ def say(msg):
     print(msg, flush=True)
 
 
-def trajectories(dm, d, use_graphs, mode, net=None, stream=None, calls=(3, 1, 4)):
+def rollouts(dm, d, use_graphs, mode=0, net=None, stream=None, calls=((7, 3), (5, 5), (6, 4))):
+    """Rollouts (nsteps, ckpt_every) in a row from the same sim; each returns its tips and the
+    state after it, with the program's own eager work (a state round trip) in between."""
     sim = dm.sim_from_description(d, use_graphs=use_graphs, stream=stream)
     sim.set_warm_start(net, mode)
     out = []
-    for k in calls:
-        st = sim.step(d["dt"], k)
-        assert (st["status"] == 0).all()
-        out.append((sim.state(), st["iters"].copy(), st["fallbacks"].copy()))
+    for n, c in calls:
+        tips = sim.rollout(d["dt"], n, ckpt_every=c)
+        out.append((tips.copy(), sim.state()))
         x, th, v, om = sim.state()            # eager work between replays
         sim.set_state(x=x, theta=th, v=v, theta_dot=om)
     return out
 
 
-@pytest.mark.parametrize("mode", [1, 3])
-def test_graph_replays_match_eager_launches(dm, mode):
-    d = W.warm_start_eval(24, steps=8)
-    say(f"case: warm mode {mode}, 24 rods, 3 calls")
-    a = trajectories(dm, d, False, mode)
-    b = trajectories(dm, d, True, mode)
-    for (sa, ia, fa), (sb, ib, fb) in zip(a, b):
+@pytest.mark.parametrize("mode", [0, 3])
+def test_captured_segments_match_eager_launches(dm, mode):
+    """Rollout segments replayed from captured graphs (each segment length captured once and
+    replayed for every later segment of that length) against eager launches, bit for bit."""
+    d = W.adjoint_rods(12, 30, steps=20)[0]
+    say(f"case: rollout segments, warm mode {mode}, 12 rods")
+    a = rollouts(dm, d, False, mode)
+    b = rollouts(dm, d, True, mode)
+    for (ta, sa), (tb, sb) in zip(a, b):
+        assert np.array_equal(ta, tb)
         for u, w in zip(sa, sb):
             assert np.array_equal(u, w)
-        assert np.array_equal(ia, ib) and np.array_equal(fa, fb)
 
 
-def test_graph_with_the_network_on_a_torch_stream(dm):
+def test_captured_segments_with_the_network_on_a_torch_stream(dm):
     import torch
     from paper_2311_18126_amd import warm_start as WS
-    d = W.warm_start_eval(16, steps=6)
-    net = dm.Mlp(max_rows=10_000)
+    d = W.adjoint_rods(8, 40, steps=12)[0]
+    net = dm.Mlp(max_rows=64)
     net.set_params(WS.init_params(3) * np.float32(1e-3))     # small corrections
     net.set_normalisation(np.zeros(20), np.ones(20), np.full(3, 1e-6))
     s = torch.cuda.Stream()
-    a = trajectories(dm, d, False, 2, net=net, stream=s.cuda_stream)
-    b = trajectories(dm, d, True, 2, net=net, stream=s.cuda_stream)
-    for (sa, ia, _), (sb, ib, _) in zip(a, b):
+    a = rollouts(dm, d, False, 2, net=net, stream=s.cuda_stream)
+    b = rollouts(dm, d, True, 2, net=net, stream=s.cuda_stream)
+    for (ta, sa), (tb, sb) in zip(a, b):
+        assert np.array_equal(ta, tb)
         for u, w in zip(sa, sb):
             assert np.array_equal(u, w)
-        assert np.array_equal(ia, ib)
+
+
+def test_adjoint_recomputation_from_captured_segments_matches_eager(dm):
+    d, kstar = W.adjoint_rods(6, 30, steps=25)
+    grads = []
+    for graphs in (False, True):
+        sim = dm.sim_from_description(d, use_graphs=graphs)
+        tips = sim.rollout(d["dt"], 25, ckpt_every=10)
+        g1 = sim.adjoint(2.0 * tips)
+        g2 = sim.adjoint(2.0 * tips)             # second pass replays the captured segments
+        assert np.array_equal(g1, g2)
+        grads.append(g1)
+    assert np.array_equal(grads[0], grads[1])
 
 
 def test_autotuner_picks_a_size_restores_the_state_and_caches(dm, tmp_path):
