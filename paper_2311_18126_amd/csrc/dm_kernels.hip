@@ -255,10 +255,13 @@ __device__ __forceinline__ void eval_node(const DmStepArgs DM_C& A, int n) {
 
 // Row L (compile-time local DOF) of a chain stencil's gradient and Hessian, expanded from the
 // 8-variable form: local DOF l = sum of coef * variable (loc_terms, orientation +1 in a chain).
-// emit(rel0 + b, H_local[L][b]) for b = 0..10; returns g_local[L].
+// emit(rel0 + b, H_local[L][b]) for b = 0..10; returns g_local[L].  A stencil that does not
+// exist (ok false) contributes zero: its loads read stencil 0 (always allocated) and the values
+// are dropped by selection, so no load sits behind a branch.
 template <int L, class Emit>
-__device__ __forceinline__ double stencil_row(const DmDev DM_C& D, int s, int rel0, Emit& emit) {
+__device__ __forceinline__ double stencil_row(const DmDev DM_C& D, int s, bool ok, int rel0, Emit& emit) {
   const int NS = D.n_st_tot;
+  s = ok ? s : 0;
   int va[2], vb[2];
   double ca[2], cb[2];
   const int na = loc_terms(L, 1.0, 1.0, va, ca);
@@ -279,49 +282,57 @@ __device__ __forceinline__ double stencil_row(const DmDev DM_C& D, int s, int re
     const int nb = loc_terms(b, 1.0, 1.0, vb, cb);
     double v = cb[0] * r8[vb[0]];
     if (nb > 1) v += cb[1] * r8[vb[1]];
-    emit(rel0 + b, v);
+    emit(rel0 + b, ok ? v : 0.0);
   }
-  return gl;
+  return ok ? gl : 0.0;
 }
 
 // Contributions of chain elements to chain row 4k + COMP; emit(rel, value) receives the
-// column as rel = column - 4k.  Returns the residual entry.
+// column as rel = column - 4k.  Returns the residual entry.  Every term is loaded (from a valid
+// index) and kept or dropped by selection: the terms present depend only on where node k sits
+// in its chain and on whether the chain owns the node.
 template <int COMP, class Emit>
-__device__ __forceinline__ double row_contrib(const DmStepArgs DM_C& A, const DmChain& ch, int k, Emit& emit) {
+__device__ __forceinline__ double row_contrib(const DmStepArgs DM_C& A, const DmChain& ch, int k, bool own,
+                                              Emit& emit) {
   const DmDev DM_C& D = A.d;
-  const int NS = D.n_st_tot, NE = D.n_edges_tot, NN = D.n_nodes_tot;
+  const int NE = D.n_edges_tot, NN = D.n_nodes_tot;
   const int N = ch.n_nodes;
+  // stencil centred on chain node m (1 <= m <= N-2) is st_off + m - 1
+  auto sok = [&](int m) { return (m >= 1) & (m <= N - 2); };
   double Rr = 0.0;
   if (COMP < 3) {
     const int node = D.chain_node[ch.node_tab + k];
-    if (D.node_owner[node] == ch.global_id) {
-      Rr += D.nd[COMP * NN + node];
+    const bool tail = k <= N - 2, head = k >= 1;      // node k is the tail of edge k, head of edge k-1
+    const int et = D.chain_edge[ch.edge_tab + (tail ? k : N - 2)];
+    const int eh = D.chain_edge[ch.edge_tab + (head ? k - 1 : 0)];
+    const double rn = D.nd[COMP * NN + node];
+    Rr += own ? rn : 0.0;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) emit(c, D.nd[(3 + 3 * COMP + c) * NN + node]);
+    for (int c = 0; c < 3; ++c) {
+      const double v = D.nd[(3 + 3 * COMP + c) * NN + node];
+      emit(c, own ? v : 0.0);
     }
-    if (k <= N - 2) {   // edge k: node k is its tail
-      const int e = D.chain_edge[ch.edge_tab + k];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) { double K = edge_K(D, NE, e, COMP, c); emit(c, K); emit(4 + c, -K); }
-      Rr -= D.ed[COMP * NE + e];
+    for (int c = 0; c < 3; ++c) {
+      const double Kt = edge_K(D, NE, et, COMP, c), Kh = edge_K(D, NE, eh, COMP, c);
+      const double kt = tail ? Kt : 0.0, kh = head ? Kh : 0.0;
+      emit(c, kt + kh);
+      emit(4 + c, -kt);
+      emit(-4 + c, -kh);
     }
-    if (k >= 1) {       // edge k-1: node k is its head
-      const int e = D.chain_edge[ch.edge_tab + k - 1];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) { double K = edge_K(D, NE, e, COMP, c); emit(-4 + c, -K); emit(c, K); }
-      Rr += D.ed[COMP * NE + e];
-    }
+    const double ft = D.ed[COMP * NE + et], fh = D.ed[COMP * NE + eh];
+    Rr += (head ? fh : 0.0) - (tail ? ft : 0.0);
     // stencils centred on nodes k-1, k, k+1 (node k is their next, centre, previous node)
-    if (k - 1 >= 1 && k - 1 <= N - 2) Rr += stencil_row<8 + COMP>(D, ch.st_off + k - 2, -8, emit);
-    if (k >= 1 && k <= N - 2) Rr += stencil_row<4 + COMP>(D, ch.st_off + k - 1, -4, emit);
-    if (k + 1 >= 1 && k + 1 <= N - 2) Rr += stencil_row<COMP>(D, ch.st_off + k, 0, emit);
+    Rr += stencil_row<8 + COMP>(D, ch.st_off + k - 2, sok(k - 1), -8, emit);
+    Rr += stencil_row<4 + COMP>(D, ch.st_off + k - 1, sok(k), -4, emit);
+    Rr += stencil_row<COMP>(D, ch.st_off + k, sok(k + 1), 0, emit);
   } else {
     const int e = D.chain_edge[ch.edge_tab + k];
     const double I = D.Ith[e] / (A.dt * A.dt);
     emit(3, I);
     Rr += I * (D.th[e] - D.th0[e] - A.dt * D.om[e]) - D.moment[e];
-    if (k >= 1 && k <= N - 2) Rr += stencil_row<7>(D, ch.st_off + k - 1, -4, emit);
-    if (k + 1 >= 1 && k + 1 <= N - 2) Rr += stencil_row<3>(D, ch.st_off + k, 0, emit);
+    Rr += stencil_row<7>(D, ch.st_off + k - 1, sok(k), -4, emit);
+    Rr += stencil_row<3>(D, ch.st_off + k, sok(k + 1), 0, emit);
   }
   return Rr;
 }
@@ -331,7 +342,7 @@ __device__ __forceinline__ double row_contrib(const DmStepArgs DM_C& A, const Dm
 // afterwards.  fixmask / bmask: bit i describes chain DOF 4k - 12 + i.
 template <int COMP>
 __device__ __forceinline__ double band_row(const DmStepArgs DM_C& A, const DmChain& ch, int k,
-                                           unsigned fixmask, unsigned bmask) {
+                                           unsigned fixmask, unsigned bmask, bool own) {
   const int r = 4 * k + COMP;
   const bool rowb = (bmask >> (12 + COMP)) & 1u;
   const bool rowfix = (fixmask >> (12 + COMP)) & 1u;
@@ -339,7 +350,7 @@ __device__ __forceinline__ double band_row(const DmStepArgs DM_C& A, const DmCha
 #pragma unroll
   for (int o = 0; o < DM_NDIAG; ++o) acc[o] = 0.0;
   auto emit = [&](int rel, double v) { acc[rel - COMP + 10] += v; };
-  double Rr = row_contrib<COMP>(A, ch, k, emit);
+  double Rr = row_contrib<COMP>(A, ch, k, own, emit);
   if (rowb && !rowfix) {
     // the border-block part of a border row goes to the dense border (assemble_border)
     double DM_G* bp = A.d.bpr + (size_t)(ch.bmap_off + r - ch.b_lo) * DM_NDIAG;
@@ -372,20 +383,12 @@ __device__ __forceinline__ double band_row(const DmStepArgs DM_C& A, const DmCha
 __device__ __forceinline__ double band_node(const DmStepArgs DM_C& A, int ci, int k) {
   const DmDev DM_C& D = A.d;
   const DmChain ch = D.chain[ci];
-  const int n = 4 * ch.n_nodes - 1;
-  unsigned fixmask = 0u, bmask = 0u;
-#pragma unroll
-  for (int i = 0; i < 32; ++i) {
-    const int r = 4 * k - 12 + i;
-    if (r >= 0 && r < n) {
-      fixmask |= (unsigned)(D.cfix[ch.dof_off + r] != 0) << i;
-      bmask |= (unsigned)(r >= ch.b_lo && r < ch.b_hi) << i;
-    }
-  }
-  double s = band_row<0>(A, ch, k, fixmask, bmask);
-  s += band_row<1>(A, ch, k, fixmask, bmask);
-  s += band_row<2>(A, ch, k, fixmask, bmask);
-  if (k < ch.n_nodes - 1) s += band_row<3>(A, ch, k, fixmask, bmask);
+  const uint4 m = *(const uint4 DM_C*)(D.nmask + 4 * (size_t)(ch.node_tab + k));
+  const bool own = m.z & 1u;
+  double s = band_row<0>(A, ch, k, m.x, m.y, own);
+  s += band_row<1>(A, ch, k, m.x, m.y, own);
+  s += band_row<2>(A, ch, k, m.x, m.y, own);
+  if (k < ch.n_nodes - 1) s += band_row<3>(A, ch, k, m.x, m.y, own);
   return s;
 }
 

@@ -92,6 +92,8 @@ struct DmDev {
   const int DM_C* bjst;
   const unsigned char DM_C* bfix;
   const unsigned char DM_C* cfix;   // per chain DOF: 1 if clamped
+  const unsigned DM_C* nmask;   // [chain-node rows][4]: clamped and border bits of chain DOFs
+                                // 4k-12 .. 4k+19 (bit i: DOF 4k-12+i), owner flag, padding
   // nodes
   const double DM_C* mass;
   const double DM_C* radius;

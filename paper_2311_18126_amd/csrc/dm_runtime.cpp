@@ -531,6 +531,22 @@ dm_status do_finalize(dm_sim* s) {
     se[i] = sef[i]; se[s->n_st + i] = see[i];
   }
   for (int c = 0; c < 3; ++c) for (int n = 0; n < NN; ++n) nh[c * NN + n] = node_home_c[c][n];
+  // band-assembly masks per chain-node row: clamped and border bits of chain DOFs
+  // 4k - 12 .. 4k + 19, and whether the chain owns the node
+  std::vector<unsigned> nmask(4 * chain_node.size(), 0u);
+  for (const DmChain& C : chains) {
+    const int n = 4 * C.n_nodes - 1;
+    for (int k = 0; k < C.n_nodes; ++k) {
+      unsigned* m = &nmask[4 * (size_t)(C.node_tab + k)];
+      for (int i = 0; i < 32; ++i) {
+        const int r = 4 * k - 12 + i;
+        if (r < 0 || r >= n) continue;
+        m[0] |= (unsigned)(cfix[C.dof_off + r] != 0) << i;
+        m[1] |= (unsigned)(r >= C.b_lo && r < C.b_hi) << i;
+      }
+      m[2] = node_owner[chain_node[C.node_tab + k]] == C.global_id ? 1u : 0u;
+    }
+  }
   DmDev& D = s->dev;
   dm_status st;
   auto up = [&](const auto& vec, auto& field) -> dm_status {
@@ -542,7 +558,7 @@ dm_status do_finalize(dm_sim* s) {
   };
 #define UP(vec, field) if ((st = up(vec, D.field)) != DM_OK) return st;
   UP(systems, sys) UP(chains, chain) UP(arms, arm) UP(order, order) UP(chain_node, chain_node) UP(chain_edge, chain_edge)
-  UP(bmap, bmap) UP(bsrc, bsrc) UP(bjst, bjst) UP(bfix, bfix) UP(cfix, cfix)
+  UP(bmap, bmap) UP(bsrc, bsrc) UP(bjst, bjst) UP(bfix, bfix) UP(cfix, cfix) UP(nmask, nmask)
   UP(mass, mass) UP(radius, radius)
   std::vector<double> forceS = soa3(force);
   UP(forceS, force) UP(node_owner, node_owner) UP(nh, node_home)
