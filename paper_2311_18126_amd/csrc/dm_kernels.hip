@@ -592,14 +592,13 @@ __device__ __forceinline__ void load_new_column(double (&col)[DM_WIN], int k0, i
   for (int i = 1; i <= DM_WIN; ++i) col[i - 1] = p[i * st];
 }
 
-// 1/p from the hardware estimate refined by two Newton corrections (each squares the relative
-// error; the result is within a few ulp of the correctly rounded quotient).
+// 1/p from the hardware estimate (about 24 correct bits) refined by one third-order
+// correction r (1 + e + e^2), e = 1 - p r, which leaves a relative error of order e^3 (below
+// the float64 rounding of the result).
 __device__ __forceinline__ double recip(double p) {
-  double r = __builtin_amdgcn_rcp(p);
-  double e = fma(-p, r, 1.0);
-  r = fma(r, e, r);
-  e = fma(-p, r, 1.0);
-  return fma(r, e, r);
+  const double r = __builtin_amdgcn_rcp(p);
+  const double e = fma(-p, r, 1.0);
+  return fma(r, fma(e, e, e), r);
 }
 
 // Value of lane T of each 16-lane row, in every lane of that row (v_mov_b64 with DPP
@@ -612,14 +611,14 @@ __device__ __forceinline__ double row_bcast(double v) {
 // Eliminate window position k (k % 11 == T).  Role s < 11 holds the column congruent to s
 // (mod 11) in register slots indexed by row mod 11; role 11 holds the right-hand side.  col:
 // the column the pivot role takes over; ent: the entry of row k + 11 in this role's column.
-// Rows whose arm ends before k leave their window untouched and park their store in the
+// MASK: rows whose arm ends before k leave their window untouched and park their store in the
 // padding of their first record.
-template <int T>
+template <int T, bool MASK>
 __device__ __forceinline__ void elim_step(double (&w)[DM_WIN], const double (&col)[DM_WIN], double ent, int k, int l,
                                           const ArmView& V, int& bad) {
-  const bool act = k < V.count;
+  const bool act = MASK ? k < V.count : true;
   const double piv = row_bcast<T>(w[T]);
-  if (act && (!(fabs(piv) > 1e-300) || !isfinite(piv))) bad = 1;
+  if (act && !__builtin_isnormal(piv)) bad = 1;       // zero, subnormal, infinite or NaN
   const double inv = recip(piv);
   double cv[DM_WIN];
 #pragma unroll
@@ -668,13 +667,21 @@ __device__ __noinline__ void sweep_arms(ArgsP Ap, int ai0, int na, double DM_L* 
   int bad = 0;
   for (int k0 = 0; k0 < cmax; k0 += DM_WIN) {
     load_new_column(ncol, k0 + DM_WIN, l, V);
-    // rows whose arm ends inside the block are masked per step; the group stops on a
-    // uniform branch
+    // a block inside every arm of the group runs unmasked; in the last block of some arm the
+    // rows whose arm has ended are masked per step and the group stops on a uniform branch
+    if (k0 + DM_WIN <= cmin) {
 #define DM_E(T) \
-  if (k0 + T < cmax) elim_step<T>(w, col, ent[T], k0 + T, l, V, bad); \
+  elim_step<T, false>(w, col, ent[T], k0 + T, l, V, bad); \
   ent[T] = row_entry(V, k0 + T + 2 * DM_WIN, l, wrap11(l, T));
-    DM_UNROLL11(DM_E)
+      DM_UNROLL11(DM_E)
 #undef DM_E
+    } else {
+#define DM_E(T) \
+  if (k0 + T < cmax) elim_step<T, true>(w, col, ent[T], k0 + T, l, V, bad); \
+  ent[T] = row_entry(V, k0 + T + 2 * DM_WIN, l, wrap11(l, T));
+      DM_UNROLL11(DM_E)
+#undef DM_E
+    }
 #pragma unroll
     for (int q = 0; q < DM_WIN; ++q) col[q] = ncol[q];
   }
@@ -710,14 +717,16 @@ __device__ __forceinline__ void back_step(double (&xv)[DM_WIN], const double (&c
   double rec[DM_FAC];
 #pragma unroll
   for (int j = 0; j < DM_FAC; ++j) rec[j] = row_bcast<T>(cur[j]);
-  // y_k - sum_j U(k, k+j) x_{k+j} as two interleaved partial sums (half the dependent chain)
+  // y_k - sum_j U(k, k+j) x_{k+j}: the older solutions first, in two interleaved partial sums
+  // each ending with its most recent term, and x_{k+1} (solved by the previous step) last, so
+  // that only two dependent operations separate x_{k+1} from x_k
   double s0 = rec[DM_WIN], s1 = 0.0;
 #pragma unroll
-  for (int j = 1; j < DM_WIN; ++j) {
+  for (int j = DM_WIN - 1; j >= 2; --j) {
     if (j & 1) s0 = fma(-rec[j], xv[(T + j) % DM_WIN], s0);
     else s1 = fma(-rec[j], xv[(T + j) % DM_WIN], s1);
   }
-  const double xl = (s0 + s1) * rec[0];
+  const double xl = fma(-rec[1], xv[(T + 1) % DM_WIN], s0 + s1) * rec[0];
   xv[T] = (!MASK || act) ? xl : xv[T];
   xs = (l == T) ? xl : xs;             // role T keeps the solution of row k0 + T
 }
