@@ -28,7 +28,8 @@ METRIC = "node-steps/s, batched implicit DER at 1e-9 residual; plain vs warm-sta
 FLOPS_PER_NODE_ITER = 4.0e3
 PEAK_FP64_VALU_TFLOPS = 78.6          # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 KERNEL_SOURCES = ["paper_2311_18126_amd/csrc/dm_kernels.hip", "paper_2311_18126_amd/csrc/dm_math.h",
-                  "paper_2311_18126_amd/csrc/dm_layout.h"]
+                  "paper_2311_18126_amd/csrc/dm_layout.h", "paper_2311_18126_amd/csrc/dm_warm.h",
+                  "paper_2311_18126_amd/csrc/dm_bf16.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dm_step_kernel_rod_batch_traffic.json")
 
 
