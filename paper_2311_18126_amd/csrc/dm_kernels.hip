@@ -392,57 +392,6 @@ __device__ __forceinline__ double band_node(const DmStepArgs DM_C& A, int ci, in
   return s;
 }
 
-// Dense border row b: pristine border-border entries of every chain touching it plus the
-// joint stencils; right-hand side in column nb.  Returns its squared residual if free.
-__device__ __forceinline__ double border_row(const DmStepArgs DM_C& A, const DmSystem DM_C& S, int b,
-                                             double DM_L* Bt, int ld) {
-  const DmDev DM_C& D = A.d;
-  const int NS = D.n_st_tot;
-  double DM_L* row = Bt + b * ld;
-  for (int j = 0; j <= S.nb; ++j) row[j] = 0.0;
-  if (D.bfix[S.bfix_off + b]) { row[b] = 1.0; return 0.0; }
-  double rhs = 0.0;
-  for (int q = 0; q < DM_MAX_BSRC; ++q) {
-    const int ci = D.bsrc[2 * (S.bsrc_off + b * DM_MAX_BSRC + q)];
-    if (ci < 0) break;
-    const int r = D.bsrc[2 * (S.bsrc_off + b * DM_MAX_BSRC + q) + 1];
-    const DmChain ch = D.chain[ci];
-    rhs += D.R[ch.dof_off + r];
-    // border-column entries of this chain row, written by the band assembly
-    const double DM_G* bp = D.bpr + (size_t)(ch.bmap_off + r - ch.b_lo) * DM_NDIAG;
-    for (int o = 0; o < DM_NDIAG; ++o) {
-      const double v = bp[o];
-      if (v == 0.0) continue;
-      const int col = r - DM_HALF_BAND + o;
-      row[D.bmap[ch.bmap_off + col - ch.b_lo]] += v;
-    }
-  }
-  for (int js = 0; js < S.n_jst; ++js) {
-    const int DM_C* bj = D.bjst + S.bjst_off + js * 11;
-    const int s = S.jst0 + js;
-    const int sg = D.ssign[s];
-    const double sf = (sg & 1) ? -1.0 : 1.0, se = (sg & 2) ? -1.0 : 1.0;
-    for (int a = 0; a < 11; ++a) {
-      if (bj[a] != b) continue;
-      int va[2], vc[2];
-      double ca[2], cc[2];
-      const int na = loc_terms(a, sf, se, va, ca);
-      for (int t = 0; t < na; ++t) rhs += ca[t] * D.st_g[va[t] * NS + s];
-      for (int c = 0; c < 11; ++c) {
-        const int bc = bj[c];
-        if (bc < 0 || D.bfix[S.bfix_off + bc]) continue;
-        const int nc = loc_terms(c, sf, se, vc, cc);
-        double h = 0.0;
-        for (int t = 0; t < na; ++t)
-          for (int u = 0; u < nc; ++u) h += ca[t] * cc[u] * D.st_H[(va[t] * 8 + vc[u]) * NS + s];
-        row[bc] += h;
-      }
-    }
-  }
-  row[S.nb] = rhs;
-  return rhs * rhs;
-}
-
 #include "dm_warm.h"
 
 // Phase drivers: each loops over its items with the whole workgroup, so that the cost of a
@@ -490,11 +439,40 @@ __device__ __noinline__ double assemble_band(ArgsP Ap, int sid) {
   return r2;
 }
 
+// Dense border with one lane per entry: the sum of the entry's terms (built once at finalize)
+// in their stored order; a clamped border row is the identity row with a zero right-hand
+// side.  Returns this lane's share of the squared residual of free border rows.
 __device__ __noinline__ double assemble_border(ArgsP Ap, int sid, double DM_L* Bt, int ld) {
   const DmStepArgs DM_C& A = *uniform(Ap);
-  const DmSystem DM_C& S = A.d.sys[uniform(sid)];
+  const DmDev DM_C& D = A.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
+  const int nb = S.nb, W = nb + 1;
   double r2 = 0.0;
-  for (int b = threadIdx.x; b < S.nb; b += blockDim.x) r2 += border_row(A, S, b, Bt, ld);
+  for (int e = threadIdx.x; e < nb * W; e += blockDim.x) {
+    const int b = e / W, col = e - b * W;
+    double v = 0.0;
+    if (D.bfix[S.bfix_off + b]) {
+      v = col == b ? 1.0 : 0.0;
+    } else {
+      // terms in batches of eight: every load of a batch is issued before the sums
+      int i = D.bent[S.bent_off + e];
+      const int i1 = D.bent[S.bent_off + e + 1];
+      for (; i < i1; i += 8) {
+        double c[8], x[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const DmBItem it = D.bitem[i + j < i1 ? i + j : i];
+          const double DM_G* src = it.kind == 0 ? D.bpr : (it.kind == 1 ? D.st_H : (it.kind == 2 ? D.R : D.st_g));
+          c[j] = i + j < i1 ? it.coef : 0.0;
+          x[j] = src[it.idx];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v = fma(c[j], x[j], v);
+      }
+      if (col == nb) r2 += v * v;
+    }
+    Bt[b * ld + col] = v;
+  }
   return r2;
 }
 
@@ -798,56 +776,88 @@ __device__ __forceinline__ void backsub_all(ArgsP Ap, const DmSystem DM_C& S, in
   for (int g = 4 * wave; g < S.n_arms; g += 4 * nwaves) backsub_arms(Ap, S.arm0 + g, min(4, S.n_arms - g), xB);
 }
 
-// Dense border: add the arms' Schur contributions (fixed order), then Gaussian elimination
-// with partial pivoting and back substitution.  All threads take part.
+// LDS operations of a wavefront stay in program order: this keeps the compiler from moving
+// them across (the hardware runs one wavefront's LDS instructions in order).
+__device__ __forceinline__ void lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Dense border solve by wavefront 0, without workgroup barriers (the workgroup meets once at
+// the end): the arms' Schur contributions are added in arm order, then Gaussian elimination
+// with partial pivoting (the largest magnitude, the first row among equals; one lane per
+// candidate row, a butterfly for the maximum) and back substitution with one lane per column
+// (two for borders of more than 64 DOFs) and a butterfly sum per row.
 __device__ __noinline__ void border_solve(ArgsP Ap, int sid, double DM_L* Bt, int ld,
                              const double DM_L* deltas, double DM_L* xB, double DM_L* scal, int DM_L* bad_flag) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmDev DM_C& D = A.d;
   const DmSystem DM_C& S = D.sys[uniform(sid)];
-  const int nb = S.nb, tid = threadIdx.x, nt = blockDim.x;
-  for (int a = 0; a < S.n_arms; ++a) {
-    const DmArm arm = D.arm[S.arm0 + a];
-    const DmChain ch = D.chain[arm.chain];
-    const double DM_L* dl = deltas + a * 110;
-    const int ntr = arm.n_trail;
-    for (int p = tid; p < ntr * (ntr + 1); p += nt) {
-      const int i = p / (ntr + 1), j = p % (ntr + 1);
-      const int bi = D.bmap[ch.bmap_off + (arm.first + arm.dir * (arm.count + i)) - ch.b_lo];
-      if (D.bfix[S.bfix_off + bi]) continue;
-      if (j < ntr) {
-        const int bj = D.bmap[ch.bmap_off + (arm.first + arm.dir * (arm.count + j)) - ch.b_lo];
-        if (!D.bfix[S.bfix_off + bj]) Bt[bi * ld + bj] += dl[i * 10 + j];
-      } else {
-        Bt[bi * ld + nb] += dl[100 + i];
+  (void)scal;
+  const int nb = S.nb, lane = threadIdx.x;
+  if (threadIdx.x < 64) {
+    for (int a = 0; a < S.n_arms; ++a) {
+      const DmArm arm = D.arm[S.arm0 + a];
+      const DmChain ch = D.chain[arm.chain];
+      const double DM_L* dl = deltas + a * 110;
+      const int ntr = arm.n_trail;
+      for (int p = lane; p < ntr * (ntr + 1); p += 64) {
+        const int i = p / (ntr + 1), j = p % (ntr + 1);
+        const int bi = D.bmap[ch.bmap_off + (arm.first + arm.dir * (arm.count + i)) - ch.b_lo];
+        if (D.bfix[S.bfix_off + bi]) continue;
+        if (j < ntr) {
+          const int bj = D.bmap[ch.bmap_off + (arm.first + arm.dir * (arm.count + j)) - ch.b_lo];
+          if (!D.bfix[S.bfix_off + bj]) Bt[bi * ld + bj] += dl[i * 10 + j];
+        } else {
+          Bt[bi * ld + nb] += dl[100 + i];
+        }
       }
+      lds_order();
     }
-    __syncthreads();
-  }
-  for (int p = 0; p < nb; ++p) {
-    if (tid == 0) {
-      int im = p;
-      double vm = fabs(Bt[p * ld + p]);
-      for (int i = p + 1; i < nb; ++i) { double v = fabs(Bt[i * ld + p]); if (v > vm) { vm = v; im = i; } }
+    int bad = 0;
+    for (int p = 0; p < nb; ++p) {
+      double vm = (lane >= p && lane < nb) ? fabs(Bt[lane * ld + p]) : -1.0;
+      int im = lane;
+      for (int p2 = lane + 64; p2 < nb; p2 += 64) {
+        const double v2 = fabs(Bt[p2 * ld + p]);
+        if (p2 >= p && v2 > vm) { vm = v2; im = p2; }
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(vm, o, 64);
+        const int oi = __shfl_xor(im, o, 64);
+        if (ov > vm || (ov == vm && oi < im)) { vm = ov; im = oi; }
+      }
+      im = uniform(im);
+      if (!(vm > 1e-300) || !isfinite(vm)) bad = 1;
       if (im != p)
-        for (int j = 0; j <= nb; ++j) { double t = Bt[p * ld + j]; Bt[p * ld + j] = Bt[im * ld + j]; Bt[im * ld + j] = t; }
-      if (!(vm > 1e-300) || !isfinite(vm)) *bad_flag = 1;
-      scal[0] = 1.0 / Bt[p * ld + p];
+        for (int j = lane; j <= nb; j += 64) {
+          const double t = Bt[p * ld + j];
+          Bt[p * ld + j] = Bt[im * ld + j];
+          Bt[im * ld + j] = t;
+        }
+      lds_order();
+      const double inv = 1.0 / Bt[p * ld + p];
+      const int w = nb - p;   // columns p+1 .. nb
+      for (int q = lane; q < (nb - p - 1) * w; q += 64) {
+        const int i = p + 1 + q / w, j = p + 1 + q % w;
+        Bt[i * ld + j] -= Bt[i * ld + p] * inv * Bt[p * ld + j];
+      }
+      lds_order();
     }
-    __syncthreads();
-    const int w = nb - p;   // columns p+1 .. nb
-    for (int q = tid; q < (nb - p - 1) * w; q += nt) {
-      const int i = p + 1 + q / w, j = p + 1 + q % w;
-      Bt[i * ld + j] -= Bt[i * ld + p] * scal[0] * Bt[p * ld + j];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
+    double x0 = 0.0, x1 = 0.0;      // solutions of columns lane and lane + 64
     for (int i = nb - 1; i >= 0; --i) {
-      double s = Bt[i * ld + nb];
-      for (int j = i + 1; j < nb; ++j) s -= Bt[i * ld + j] * xB[j];
-      xB[i] = s / Bt[i * ld + i];
+      double part = 0.0;
+      if (lane > i && lane < nb) part = Bt[i * ld + lane] * x0;
+      if (lane + 64 > i && lane + 64 < nb) part += Bt[i * ld + lane + 64] * x1;
+      const double xi = (Bt[i * ld + nb] - wave_sum(part)) / Bt[i * ld + i];
+      if (lane == i) x0 = xi;
+      if (lane + 64 == i) x1 = xi;
     }
+    if (lane < nb) xB[lane] = x0;
+    if (lane + 64 < nb) xB[lane + 64] = x1;
+    if (bad && lane == 0) *bad_flag = 1;
   }
   __syncthreads();
 }

@@ -63,6 +63,13 @@ struct DmArm {
   int fac_off;     // offset (in records of DM_FAC_STRIDE doubles) of local row 0's record
 };
 
+// One term of a dense border entry: coef * (array kind)[idx], kinds 0 bpr, 1 st_H, 2 R,
+// 3 st_g (the right-hand side column holds R and st_g terms).
+struct DmBItem {
+  int kind, idx;
+  double coef;
+};
+
 struct DmSystem {
   int chain0, n_chains;
   int arm0, n_arms;
@@ -75,6 +82,7 @@ struct DmSystem {
   int bjst_off;          // n_jst * 11 border indices of joint-stencil local DOFs
   int bfix_off;          // nb fixed flags
   int chain_nodes;       // sum of chain node counts (band-assembly work items)
+  int bent_off;          // nb (nb + 1) + 1 offsets into the border items, entry b (nb + 1) + col
   int n_dof;             // sum of chain DOFs
 };
 
@@ -90,6 +98,8 @@ struct DmDev {
   const int DM_C* bmap;
   const int DM_C* bsrc;         // pairs (chain global index, chain DOF)
   const int DM_C* bjst;
+  const int DM_C* bent;         // border entry -> first item (per system from bent_off)
+  const DmBItem DM_C* bitem;    // border entry terms, summed in their stored order
   const unsigned char DM_C* bfix;
   const unsigned char DM_C* cfix;   // per chain DOF: 1 if clamped
   const unsigned DM_C* nmask;   // [chain-node rows][4]: clamped and border bits of chain DOFs

@@ -480,6 +480,60 @@ dm_status do_finalize(dm_sim* s) {
     s->max_arms = std::max(s->max_arms, S.n_arms);
     systems.push_back(S);
   }
+  // ---- terms of every dense border entry (entry b (nb + 1) + col, col = nb: right-hand side),
+  // in the order the assembly sums them: each source chain row's residual and border-column
+  // band entries, then the joint stencils' gradient and Hessian terms
+  std::vector<int> bent;
+  std::vector<DmBItem> bitem;
+  const int NST = (int)Vbar.size();      // every stencil is placed by now
+  for (DmSystem& S : systems) {
+    const int W = S.nb + 1;
+    std::vector<std::vector<DmBItem>> ent((size_t)S.nb * W);
+    for (int b = 0; b < S.nb; ++b) {
+      if (bfix[S.bfix_off + b]) continue;
+      for (int q = 0; q < DM_MAX_BSRC; ++q) {
+        const int ci = bsrc[2 * (S.bsrc_off + b * DM_MAX_BSRC + q)];
+        if (ci < 0) break;
+        const int r = bsrc[2 * (S.bsrc_off + b * DM_MAX_BSRC + q) + 1];
+        const DmChain& C = chains[ci];
+        ent[(size_t)b * W + S.nb].push_back(DmBItem{2, C.dof_off + r, 1.0});
+        for (int o = 0; o < DM_NDIAG; ++o) {
+          const int col = r - DM_HALF_BAND + o;
+          if (col < C.b_lo || col >= C.b_hi) continue;
+          const int bc = bmap[C.bmap_off + col - C.b_lo];
+          if (bfix[S.bfix_off + bc]) continue;
+          ent[(size_t)b * W + bc].push_back(DmBItem{0, (C.bmap_off + r - C.b_lo) * DM_NDIAG + o, 1.0});
+        }
+      }
+    }
+    for (int js = 0; js < S.n_jst; ++js) {
+      const int* bj = &bjst[S.bjst_off + js * 11];
+      const int st = S.jst0 + js;
+      const double sf = (ssign[st] & 1) ? -1.0 : 1.0, se = (ssign[st] & 2) ? -1.0 : 1.0;
+      for (int a = 0; a < 11; ++a) {
+        const int b = bj[a];
+        if (bfix[S.bfix_off + b]) continue;
+        int va[2], vc[2];
+        double ca[2], cc[2];
+        const int na = loc_terms(a, sf, se, va, ca);
+        for (int t = 0; t < na; ++t) ent[(size_t)b * W + S.nb].push_back(DmBItem{3, va[t] * NST + st, ca[t]});
+        for (int c = 0; c < 11; ++c) {
+          const int bc = bj[c];
+          if (bc < 0 || bfix[S.bfix_off + bc]) continue;
+          const int nc = loc_terms(c, sf, se, vc, cc);
+          for (int t = 0; t < na; ++t)
+            for (int u = 0; u < nc; ++u)
+              ent[(size_t)b * W + bc].push_back(DmBItem{1, (va[t] * 8 + vc[u]) * NST + st, ca[t] * cc[u]});
+        }
+      }
+    }
+    S.bent_off = (int)bent.size();
+    for (const auto& e : ent) {
+      bent.push_back((int)bitem.size());
+      bitem.insert(bitem.end(), e.begin(), e.end());
+    }
+    bent.push_back((int)bitem.size());
+  }
   // ---- homes of every DOF (delta index or border)
   const int NN = (int)mass.size(), NE = (int)ebar.size();
   for (int c = 0; c < 3; ++c) node_home_c[c].assign(NN, 0);
@@ -559,6 +613,7 @@ dm_status do_finalize(dm_sim* s) {
 #define UP(vec, field) if ((st = up(vec, D.field)) != DM_OK) return st;
   UP(systems, sys) UP(chains, chain) UP(arms, arm) UP(order, order) UP(chain_node, chain_node) UP(chain_edge, chain_edge)
   UP(bmap, bmap) UP(bsrc, bsrc) UP(bjst, bjst) UP(bfix, bfix) UP(cfix, cfix) UP(nmask, nmask)
+  UP(bent, bent) UP(bitem, bitem)
   UP(mass, mass) UP(radius, radius)
   std::vector<double> forceS = soa3(force);
   UP(forceS, force) UP(node_owner, node_owner) UP(nh, node_home)
@@ -621,11 +676,7 @@ dm_status do_finalize(dm_sim* s) {
   // natural curvature and actuation may be set again later; keep a copy of stencil->rod
   s->finalized = true;
   int blk = s->cfg.block_size;
-  if (blk <= 0) {
-    blk = 128;
-    while (blk < 64 * s->max_arms && blk < 1024) blk *= 2;
-    if (s->max_arms > 2) blk = std::max(blk, 512);
-  }
+  if (blk <= 0) blk = 256;   // four wavefronts: element work in parallel, up to 16 arms per sweep
   s->block = blk;
   return DM_OK;
 }
