@@ -557,17 +557,38 @@ __device__ __forceinline__ double init_entry(const ArmView& V, int r, int s) {
   return *sel_ptr(ok, V.zpad, sel_ptr(rhs, V.band + ib, V.R + ir));
 }
 
-// The column role s takes over at its pivot step kp = k0 + s: rows kp+1 .. kp+11 of column
-// kp + 11 (all in the band; all zero once column kp + 11 is past the chain end, read from the
+// Window halves: an arm's window rows (slots 0..10, a row's slot being its index mod 11) are
+// split over the two 16-lane rows of a row pair, the even row holding slots 0..5 and the odd
+// row slots 6..10 (its sixth register unused), so each lane updates half a column per step.
+#define DM_HS 6
+
+// The column role s takes over at its pivot step kp = k0 + s, as this lane's half of it:
+// slot g = 6h + j holds row kp + i of column kp + 11 with i = (g - s) mod 11 (i = 11, the new
+// diagonal, in slot s).  All zero once column kp + 11 is past the chain end (read from the
 // zero pad).  Roles >= 11 load role 0's column, which they never take.
-__device__ __forceinline__ void load_new_column(double (&col)[DM_WIN], int k0, int s, const ArmView& V) {
-  const int kp = k0 + (s < DM_WIN ? s : 0);
+__device__ __forceinline__ void load_new_column(double (&col)[DM_HS], int k0, int s, int h, const ArmView& V) {
+  const int sr = s < DM_WIN ? s : 0;
+  const int kp = k0 + sr;
   const bool ok = kp + DM_WIN < V.lmax;
   // entry (kp + i, kp + 11) at b0 + d21 (kp + i) + dir (11 - i) = x + i * 20 dir
   const double DM_G* p = sel_ptr(ok, V.zpad, V.band + (V.b0() + V.d21() * kp + DM_WIN * V.dir));
   const int st = ok ? V.d21() - V.dir : 0;
 #pragma unroll
-  for (int i = 1; i <= DM_WIN; ++i) col[i - 1] = p[i * st];
+  for (int j = 0; j < DM_HS; ++j) {
+    int i = DM_HS * h + j - sr;
+    i += i <= 0 ? DM_WIN : 0;             // 1 .. 11 for the slots 0..10 (slot 11 of the odd row: unused)
+    col[j] = p[(i < DM_WIN + 1 ? i : DM_WIN) * st];
+  }
+}
+
+// The value of the even (odd) row of each row pair, in both rows of the pair
+// (v_permlane16_swap_b32).
+__device__ __forceinline__ double from_half(double v, int half) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)b, (unsigned)b, false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
+  const unsigned l32 = half ? lo[1] : lo[0], h32 = half ? hi[1] : hi[0];
+  return __longlong_as_double((long long)(((unsigned long long)h32 << 32) | l32));
 }
 
 // 1/p from the hardware estimate (about 24 correct bits) refined by one third-order
@@ -587,24 +608,27 @@ __device__ __forceinline__ double row_bcast(double v) {
 }
 
 // Eliminate window position k (k % 11 == T).  Role s < 11 holds the column congruent to s
-// (mod 11) in register slots indexed by row mod 11; role 11 holds the right-hand side.  col:
-// the column the pivot role takes over; ent: the entry of row k + 11 in this role's column.
+// (mod 11), role 11 the right-hand side; row half h holds slots 6h .. 6h+5.  The pivot row's
+// entries (slot T, in half T / 6) reach the other half by one row-pair swap; the pivot column
+// is broadcast within each row.  col: this lane's half of the column the pivot role takes
+// over; ent: the entry of row k + 11 in this role's column (used by the half owning slot T).
 // MASK: rows whose arm ends before k leave their window untouched and park their store in the
 // padding of their first record.
 template <int T, bool MASK>
-__device__ __forceinline__ void elim_step(double (&w)[DM_WIN], const double (&col)[DM_WIN], double ent, int k, int l,
-                                          const ArmView& V, int& bad) {
+__device__ __forceinline__ void elim_step(double (&w)[DM_HS], const double (&col)[DM_HS], double ent, int k, int l,
+                                          int h, const ArmView& V, int& bad) {
+  constexpr int hT = T >= DM_HS ? 1 : 0, tT = T - DM_HS * hT;
   const bool act = MASK ? k < V.count : true;
-  const double piv = row_bcast<T>(w[T]);
+  const double u = from_half(w[tT], hT);              // row k's entry in this lane's column
+  const double piv = row_bcast<T>(u);
   if (act && !__builtin_isnormal(piv)) bad = 1;       // zero, subnormal, infinite or NaN
   const double inv = recip(piv);
-  double cv[DM_WIN];
+  double cv[DM_HS];
 #pragma unroll
-  for (int i = 1; i < DM_WIN; ++i) cv[i] = row_bcast<T>(w[(T + i) % DM_WIN]);
-  const double u = w[T];
+  for (int j = 0; j < DM_HS; ++j) cv[j] = row_bcast<T>(w[j]);
   const bool piv_lane = (l == T);
   // factor record of row k: [1/pivot, U(k, k+1..k+10), modified rhs]; every lane stores (no
-  // branch), idle roles into the record's padding
+  // branch; both halves store the same values), idle roles into the record's padding
   const int j = l < DM_WIN ? (l - T + DM_WIN) % DM_WIN : (l == DM_WIN ? DM_WIN : DM_FAC);
   const int rec = act ? (V.fac_off + k) * DM_FAC_STRIDE + j : V.fac_off * DM_FAC_STRIDE + DM_FAC;
   V.fac[rec] = piv_lane ? inv : u;
@@ -613,73 +637,78 @@ __device__ __forceinline__ void elim_step(double (&w)[DM_WIN], const double (&co
   const double us = !act ? 0.0 : (piv_lane ? 1.0 : u * inv);
   const double take = (act && piv_lane) ? 1.0 : 0.0;
 #pragma unroll
-  for (int i = 1; i < DM_WIN; ++i)
-    w[(T + i) % DM_WIN] = fma(take, col[i - 1], fma(-cv[i], us, w[(T + i) % DM_WIN]));
-  const double wn = piv_lane ? col[DM_WIN - 1] : ent;     // entries of the new row k + 11
-  w[T] = act ? wn : w[T];
+  for (int q = 0; q < DM_HS; ++q) w[q] = fma(take, col[q], fma(-cv[q], us, w[q]));
+  // slot T now holds row k + 11 (the pivot lane: the new diagonal)
+  const double wn = piv_lane ? col[tT] : ent;
+  w[tT] = (act && h == hT) ? wn : w[tT];
 }
 
 #define DM_UNROLL11(M) M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10)
 
-// Forward elimination of the na (<= 4) arms ai0 .. ai0+na-1; deltas: the Schur-complement
-// slots (110 doubles per arm) of arm ai0.  The new columns of a block are loaded one block
-// ahead; the entering row of step T is loaded right after step T of the previous block, into
-// the register that step has just freed.
+// Forward elimination of the na (<= 2) arms ai0 .. ai0+na-1, one per row pair; deltas: the
+// Schur-complement slots (110 doubles per arm) of arm ai0.  The new columns of a block are
+// loaded one block ahead; the entering row of step T is loaded right after step T of the
+// previous block, into the register that step has just freed.
 __device__ __noinline__ void sweep_arms(ArgsP Ap, int ai0, int na, double DM_L* deltas, int DM_L* bad_flag) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmDev DM_C& D = A.d;
   ai0 = uniform(ai0);
   na = uniform(na);
-  const int lane = threadIdx.x & 63, l = lane & 15;
-  const int ai = lane_arm(ai0, na, lane);
+  const int lane = threadIdx.x & 63, l = lane & 15, h = (lane >> 4) & 1, pr = lane >> 5;
+  const int ai = ai0 + (pr < na ? pr : na - 1);
   const DmArm arm = D.arm[ai];
   const ArmView V = arm_view(D, arm);
   int cmin, cmax;
   group_counts(D, ai0, na, cmin, cmax);
-  double w[DM_WIN], col[DM_WIN], ncol[DM_WIN], ent[DM_WIN];
+  double w[DM_HS], col[DM_HS], ncol[DM_HS], ent[DM_WIN];
 #pragma unroll
-  for (int r = 0; r < DM_WIN; ++r) w[r] = init_entry(V, r, l);
-  load_new_column(col, 0, l, V);
+  for (int j = 0; j < DM_HS; ++j) {
+    const int g = DM_HS * h + j;
+    w[j] = init_entry(V, g < DM_WIN ? g : 0, l);
+  }
+  load_new_column(col, 0, l, h, V);
 #pragma unroll
   for (int T = 0; T < DM_WIN; ++T) ent[T] = row_entry(V, T + DM_WIN, l, wrap11(l, T));
   int bad = 0;
   for (int k0 = 0; k0 < cmax; k0 += DM_WIN) {
-    load_new_column(ncol, k0 + DM_WIN, l, V);
+    load_new_column(ncol, k0 + DM_WIN, l, h, V);
     // a block inside every arm of the group runs unmasked; in the last block of some arm the
     // rows whose arm has ended are masked per step and the group stops on a uniform branch
     if (k0 + DM_WIN <= cmin) {
 #define DM_E(T) \
-  elim_step<T, false>(w, col, ent[T], k0 + T, l, V, bad); \
+  elim_step<T, false>(w, col, ent[T], k0 + T, l, h, V, bad); \
   ent[T] = row_entry(V, k0 + T + 2 * DM_WIN, l, wrap11(l, T));
       DM_UNROLL11(DM_E)
 #undef DM_E
     } else {
 #define DM_E(T) \
-  if (k0 + T < cmax) elim_step<T, true>(w, col, ent[T], k0 + T, l, V, bad); \
+  if (k0 + T < cmax) elim_step<T, true>(w, col, ent[T], k0 + T, l, h, V, bad); \
   ent[T] = row_entry(V, k0 + T + 2 * DM_WIN, l, wrap11(l, T));
       DM_UNROLL11(DM_E)
 #undef DM_E
     }
 #pragma unroll
-    for (int q = 0; q < DM_WIN; ++q) col[q] = ncol[q];
+    for (int q = 0; q < DM_HS; ++q) col[q] = ncol[q];
   }
   // trailing (border) block of the window = this arm's Schur complement contribution
   double DM_L* dl = deltas + (ai - ai0) * 110;
   const int c0 = arm.count % DM_WIN, nt = arm.n_trail;
   if (l < DM_WIN) {
-    const int j = (l - c0 + DM_WIN) % DM_WIN;
-    if (j < nt) {
+    const int jc = (l - c0 + DM_WIN) % DM_WIN;
+    if (jc < nt) {
 #pragma unroll
-      for (int q = 0; q < DM_WIN; ++q) {
-        const int i = (q - c0 + DM_WIN) % DM_WIN;
-        if (i < nt) dl[i * 10 + j] = w[q];
+      for (int q = 0; q < DM_HS; ++q) {
+        const int g = DM_HS * h + q;
+        const int i = (g - c0 + DM_WIN) % DM_WIN;
+        if (g < DM_WIN && i < nt) dl[i * 10 + jc] = w[q];
       }
     }
   } else if (l == DM_WIN) {
 #pragma unroll
-    for (int q = 0; q < DM_WIN; ++q) {
-      const int i = (q - c0 + DM_WIN) % DM_WIN;
-      if (i < nt) dl[100 + i] = w[q];
+    for (int q = 0; q < DM_HS; ++q) {
+      const int g = DM_HS * h + q;
+      const int i = (g - c0 + DM_WIN) % DM_WIN;
+      if (g < DM_WIN && i < nt) dl[100 + i] = w[q];
     }
   }
   if (bad) *bad_flag = 1;
@@ -764,11 +793,12 @@ __device__ __noinline__ void backsub_arms(ArgsP Ap, int ai0, int na, const doubl
   }
 }
 
-// Arms of a system in groups of four, one group per wavefront.
+// The sweep takes a system's arms in groups of two (one per row pair), the back-substitution
+// in groups of four (one per row), one group per wavefront.
 __device__ __forceinline__ void sweep_all(ArgsP Ap, const DmSystem DM_C& S, int wave, int nwaves,
                                           double DM_L* deltas, int DM_L* flags) {
-  for (int g = 4 * wave; g < S.n_arms; g += 4 * nwaves)
-    sweep_arms(Ap, S.arm0 + g, min(4, S.n_arms - g), deltas + g * 110, flags);
+  for (int g = 2 * wave; g < S.n_arms; g += 2 * nwaves)
+    sweep_arms(Ap, S.arm0 + g, min(2, S.n_arms - g), deltas + g * 110, flags);
 }
 
 __device__ __forceinline__ void backsub_all(ArgsP Ap, const DmSystem DM_C& S, int wave, int nwaves,
