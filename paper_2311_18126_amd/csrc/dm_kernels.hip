@@ -33,9 +33,10 @@
 #define DM_TSAVE(sid)
 #endif
 
-// tangents per stencil task: the stencil Hessian takes 2 x 4 / DM_STENCIL_TANGENTS tasks
+// tangents per stencil task: the stencil Hessian takes 2 x 4 / DM_STENCIL_TANGENTS tasks (one
+// tangent per task: the most tasks and the fewest live values per lane)
 #ifndef DM_STENCIL_TANGENTS
-#define DM_STENCIL_TANGENTS 2
+#define DM_STENCIL_TANGENTS 1
 #endif
 
 #define DM_STATUS_OK 0
@@ -95,11 +96,11 @@ __device__ double block_sum(double v, double DM_L* red) {
 // One lane-task of a stencil.  rev = 0 evaluates the stencil as stored, rev = 1 with its
 // orientation reversed (nodes and edges swapped, edges reversed), which leaves the energy
 // unchanged once the second natural-curvature component changes sign, so both run the same
-// code; SUB selects the two f-edge variables the derivatives are seeded on (0: e_f.x, e_f.y;
-// 1: e_f.z, theta_f).  The reversed stencil's f edge is the stored e edge, so its Hessian
+// code; the task seeds NT of the four f-edge variables (e_f.x, e_f.y, e_f.z, theta_f), from
+// variable NT * SUB on.  The reversed stencil's f edge is the stored e edge, so its Hessian
 // columns are the stored stencil's e-edge columns, reached through the signed permutation
 // e_f <-> -e_e, theta_f <-> -theta_e (an even number of sign flips per Hessian entry, so only
-// the indices move).  Two tangents per lane keep the pass within the register file.
+// the indices move).  Few tangents per lane keep the pass within the register file.
 template <int NT, int SUB>
 __device__ __forceinline__ void eval_stencil(const DmStepArgs DM_C& A, int s, int rev, double t_end) {
   const DmDev DM_C& D = A.d;
@@ -397,8 +398,8 @@ __device__ __forceinline__ double band_node(const DmStepArgs DM_C& A, int ci, in
 // Phase drivers: each loops over its items with the whole workgroup, so that the cost of a
 // call is paid once per phase.
 
-// Stencil tasks: 64 consecutive stencils per wavefront and task kind (two orientations x two
-// tangent halves), so that a wavefront never mixes kinds.
+// Stencil tasks: 64 consecutive stencils per wavefront and task kind (two orientations x
+// 4 / DM_STENCIL_TANGENTS tangent groups), so that a wavefront never mixes kinds.
 __device__ __noinline__ void eval_stencils(ArgsP Ap, int sid, double t_end) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmSystem DM_C& S = A.d.sys[uniform(sid)];
