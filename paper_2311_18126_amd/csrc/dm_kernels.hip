@@ -1111,47 +1111,53 @@ __device__ __noinline__ void adj_store_lambda(AdjP Pp, int sid, const double DM_
 }
 
 // Per stencil: derivatives of psi = lambda_loc . g_loc with respect to the step-start frames
-// of both edges and the natural curvature, in four passes of four tangents:
-// (t_f, kbar1), (d1_f, kbar2), (t_e), (d1_e), stored as pst[4 pass + tangent].
+// of both edges and the natural curvature, stored as pst[q] for the 16 parameters
+// q = (t_f.x, t_f.y, t_f.z, kbar1, d1_f.x, d1_f.y, d1_f.z, kbar2, t_e.x, t_e.y, t_e.z, -,
+// d1_e.x, d1_e.y, d1_e.z, -) (the two unused slots hold zero).  One lane-task per stencil and
+// parameter, a 1-tangent dual pass seeded on that parameter (seeds selected by value); 64
+// consecutive stencils per wavefront and parameter.
+__device__ __forceinline__ void adj_stencil_task(const DmAdjArgs DM_C& P, int s, int q) {
+  typedef Dual<1> D1;
+  const DmDev DM_C& D = P.s.d;
+  const int NS = D.n_st_tot, NE = D.n_edges_tot, NN = D.n_nodes_tot;
+  if ((q & 3) == 3 && q >= 8) {            // no parameter
+    P.a.pst[q * NS + s] = 0.0;
+    return;
+  }
+  const int np = D.sn[s], nc = D.sn[NS + s], nn = D.sn[2 * NS + s];
+  const int ef = D.se[s], ee = D.se[NS + s];
+  const int sg = D.ssign[s];
+  const double sf = (sg & 1) ? -1.0 : 1.0, se = (sg & 2) ? -1.0 : 1.0;
+  const v3 xc = ld3(D.x, NN, nc);
+  const v3 efv = xc - ld3(D.x, NN, np), eev = ld3(D.x, NN, nn) - xc;
+  const v3 lp = ld3(P.a.lam, NN, np), lc = ld3(P.a.lam, NN, nc), ln = ld3(P.a.lam, NN, nn);
+  const v3 l0 = lc - lp, l1 = ln - lc;
+  const double l8[8] = {l0.x, l0.y, l0.z, l1.x, l1.y, l1.z, sf * P.a.lam[3 * NN + ef], se * P.a.lam[3 * NN + ee]};
+  const v3 tnf = sf * ld3(D.tref, NE, ef), d1nf = ld3(D.d1ref, NE, ef);
+  const v3 tne = se * ld3(D.tref, NE, ee), d1ne = ld3(D.d1ref, NE, ee);
+  auto seed = [&](int p) { return q == p ? 1.0 : 0.0; };
+  Vec<D1> TNF = liftv<D1>(tnf), D1NF = liftv<D1>(d1nf), TNE = liftv<D1>(tne), D1NE = liftv<D1>(d1ne);
+  D1 K1 = lift<D1>(D.kbar[s]), K2 = lift<D1>(D.kbar[NS + s]);
+  TNF.x.d[0] = seed(0); TNF.y.d[0] = seed(1); TNF.z.d[0] = seed(2); K1.d[0] = seed(3);
+  D1NF.x.d[0] = seed(4); D1NF.y.d[0] = seed(5); D1NF.z.d[0] = seed(6); K2.d[0] = seed(7);
+  TNE.x.d[0] = seed(8); TNE.y.d[0] = seed(9); TNE.z.d[0] = seed(10);
+  D1NE.x.d[0] = seed(12); D1NE.y.d[0] = seed(13); D1NE.z.d[0] = seed(14);
+  D1 g8[8];
+  stencil_grad_g(liftv<D1>(efv), liftv<D1>(eev), lift<D1>(sf * D.th[ef]), lift<D1>(se * D.th[ee]), TNF, D1NF, TNE,
+                 D1NE, D.bref[s], K1, K2, D.tbar[s], D.kbend[s], D.ktwist[s], g8);
+  double acc = 0.0;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) acc += l8[a] * g8[a].d[0];
+  P.a.pst[q * NS + s] = acc;
+}
+
 __device__ __noinline__ void adj_stencils(AdjP Pp, int sid) {
   const DmAdjArgs DM_C& P = *uniform(Pp);
-  const DmDev DM_C& D = P.s.d;
-  const DmSystem DM_C& S = D.sys[uniform(sid)];
-  const int NS = D.n_st_tot, NE = D.n_edges_tot, NN = D.n_nodes_tot;
-  for (int i = threadIdx.x; i < S.n_st; i += blockDim.x) {
-    const int s = S.st0 + i;
-    const int np = D.sn[s], nc = D.sn[NS + s], nn = D.sn[2 * NS + s];
-    const int ef = D.se[s], ee = D.se[NS + s];
-    const int sg = D.ssign[s];
-    const double sf = (sg & 1) ? -1.0 : 1.0, se = (sg & 2) ? -1.0 : 1.0;
-    const v3 xc = ld3(D.x, NN, nc);
-    const v3 efv = xc - ld3(D.x, NN, np), eev = ld3(D.x, NN, nn) - xc;
-    const v3 lp = ld3(P.a.lam, NN, np), lc = ld3(P.a.lam, NN, nc), ln = ld3(P.a.lam, NN, nn);
-    const v3 l0 = lc - lp, l1 = ln - lc;
-    const double l8[8] = {l0.x, l0.y, l0.z, l1.x, l1.y, l1.z, sf * P.a.lam[3 * NN + ef], se * P.a.lam[3 * NN + ee]};
-    const v3 tnf = sf * ld3(D.tref, NE, ef), d1nf = ld3(D.d1ref, NE, ef);
-    const v3 tne = se * ld3(D.tref, NE, ee), d1ne = ld3(D.d1ref, NE, ee);
-    for (int pass = 0; pass < 4; ++pass) {
-      // seeds selected by value (tangent k of pass p is 1 on that pass's parameter)
-      const double w0 = pass == 0 ? 1.0 : 0.0, w1 = pass == 1 ? 1.0 : 0.0;
-      const double w2 = pass == 2 ? 1.0 : 0.0, w3 = pass == 3 ? 1.0 : 0.0;
-      Vec<D4> TNF = liftv<D4>(tnf), D1NF = liftv<D4>(d1nf), TNE = liftv<D4>(tne), D1NE = liftv<D4>(d1ne);
-      D4 K1 = lift<D4>(D.kbar[s]), K2 = lift<D4>(D.kbar[NS + s]);
-      TNF.x.d[0] = w0; TNF.y.d[1] = w0; TNF.z.d[2] = w0; K1.d[3] = w0;
-      D1NF.x.d[0] = w1; D1NF.y.d[1] = w1; D1NF.z.d[2] = w1; K2.d[3] = w1;
-      TNE.x.d[0] = w2; TNE.y.d[1] = w2; TNE.z.d[2] = w2;
-      D1NE.x.d[0] = w3; D1NE.y.d[1] = w3; D1NE.z.d[2] = w3;
-      D4 g8[8];
-      stencil_grad_g(liftv<D4>(efv), liftv<D4>(eev), lift<D4>(sf * D.th[ef]), lift<D4>(se * D.th[ee]), TNF, D1NF,
-                     TNE, D1NE, D.bref[s], K1, K2, D.tbar[s], D.kbend[s], D.ktwist[s], g8);
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        double acc = 0.0;
-#pragma unroll
-        for (int a = 0; a < 8; ++a) acc += l8[a] * g8[a].d[k];
-        P.a.pst[(4 * pass + k) * NS + s] = acc;
-      }
-    }
+  const DmSystem DM_C& S = P.s.d.sys[uniform(sid)];
+  for (int i = threadIdx.x; i < 1024 * ((S.n_st + 63) >> 6); i += blockDim.x) {
+    const int st = ((i >> 10) << 6) + (i & 63);
+    const int q = (i >> 6) & 15;
+    if (st < S.n_st) adj_stencil_task(P, S.st0 + st, q);
   }
 }
 
