@@ -815,79 +815,181 @@ __device__ __forceinline__ void lds_order() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// 32-bit halves of a double through a DPP row rotation (row_ror:N), and the partner row's
+// value of a row pair (v_permlane16_swap_b32).
+template <int N>
+__device__ __forceinline__ double row_ror_d(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_mov_dpp((int)(unsigned)b, 0x120 + N, 0xF, 0xF, false);
+  const unsigned hi = __builtin_amdgcn_mov_dpp((int)(unsigned)(b >> 32), 0x120 + N, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+template <int N>
+__device__ __forceinline__ int row_ror_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x120 + N, 0xF, 0xF, false); }
+__device__ __forceinline__ unsigned partner_row(unsigned v, int odd) {
+  const auto r = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return odd ? r[0] : r[1];
+}
+
+// Largest v over the lanes of each 16-lane row (NBX <= 16) or row pair (NBX <= 32), the
+// smallest lane among equals, as (value, lane) in every lane of the row (pair).
+__device__ __forceinline__ void argmax_step(double& v, int& i, double ov, int oi) {
+  const bool take = (ov > v) | ((ov == v) & (oi < i));
+  v = take ? ov : v;
+  i = take ? oi : i;
+}
+template <int NBX>
+__device__ __forceinline__ void row_argmax(double& v, int& i) {
+  argmax_step(v, i, row_ror_d<8>(v), row_ror_i<8>(i));
+  argmax_step(v, i, row_ror_d<4>(v), row_ror_i<4>(i));
+  argmax_step(v, i, row_ror_d<2>(v), row_ror_i<2>(i));
+  argmax_step(v, i, row_ror_d<1>(v), row_ror_i<1>(i));
+  if (NBX > 16) {
+    const int odd = (threadIdx.x >> 4) & 1;
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = partner_row((unsigned)b, odd), hi = partner_row((unsigned)(b >> 32), odd);
+    const double ov = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    argmax_step(v, i, ov, (int)partner_row((unsigned)i, odd));
+  }
+}
+
+// Gaussian elimination with partial pivoting of a border of nb <= NBX DOFs held in registers:
+// lane i holds row i (columns in r[0..NBX), the right-hand side in rhs).  Rows are not
+// exchanged: step p picks the not yet pivotal row with the largest |entry| in column p (the
+// first such row among equals), broadcasts it by lane reads, and eliminates column p from the
+// other open rows; back substitution runs over the pivots in reverse, every lane keeping its
+// row's partial sum.  The solution of border DOF j ends in lane j.
+template <int NBX>
+__device__ __forceinline__ double border_lu_regs(const double DM_L* Bt, int ld, int nb, int& bad) {
+  const int lane = threadIdx.x & 63;
+  const bool row = lane < nb;
+  const double DM_L* br = Bt + (row ? lane : 0) * ld;
+  double r[NBX];
+#pragma unroll
+  for (int c = 0; c < NBX; ++c) r[c] = (row && c < nb) ? br[c < nb ? c : 0] : 0.0;
+  double rhs = row ? br[nb] : 0.0;
+  bool open = row;
+  int piv[NBX];
+  double pinv[NBX];
+#pragma unroll
+  for (int p = 0; p < NBX; ++p) {
+    piv[p] = 0;
+    pinv[p] = 0.0;
+    if (p < nb) {
+      double v = open ? fabs(r[p]) : -1.0;
+      int im = lane;
+      row_argmax<NBX>(v, im);
+      im = uniform(im);
+      const double pv = readlane_d(r[p], im);
+      bad |= !(fabs(pv) > 1e-300) | !isfinite(pv);
+      const double inv = 1.0 / pv;
+      piv[p] = im;
+      pinv[p] = inv;
+      open = open && lane != im;
+      const double l = open ? r[p] * inv : 0.0;
+#pragma unroll
+      for (int c = p + 1; c < NBX; ++c) r[c] = fma(-l, readlane_d(r[c], im), r[c]);
+      rhs = fma(-l, readlane_d(rhs, im), rhs);
+    }
+  }
+  double x = 0.0;
+#pragma unroll
+  for (int p = NBX - 1; p >= 0; --p) {
+    if (p < nb) {
+      const double xp = readlane_d(rhs, piv[p]) * pinv[p];
+      rhs = fma(-r[p], xp, rhs);
+      x = lane == p ? xp : x;
+    }
+  }
+  return x;
+}
+
+// The same elimination on the border in LDS, for borders of more than 32 DOFs: rows are
+// exchanged, one lane per candidate row and a butterfly for the maximum; back substitution
+// with one lane per column (two for borders of more than 64 DOFs) and a butterfly sum per row.
+__device__ __forceinline__ void border_lu_lds(double DM_L* Bt, int ld, int nb, double DM_L* xB, int& bad) {
+  const int lane = threadIdx.x;
+  for (int p = 0; p < nb; ++p) {
+    double vm = (lane >= p && lane < nb) ? fabs(Bt[lane * ld + p]) : -1.0;
+    int im = lane;
+    for (int p2 = lane + 64; p2 < nb; p2 += 64) {
+      const double v2 = fabs(Bt[p2 * ld + p]);
+      if (p2 >= p && v2 > vm) { vm = v2; im = p2; }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(vm, o, 64);
+      const int oi = __shfl_xor(im, o, 64);
+      if (ov > vm || (ov == vm && oi < im)) { vm = ov; im = oi; }
+    }
+    im = uniform(im);
+    if (!(vm > 1e-300) || !isfinite(vm)) bad = 1;
+    if (im != p)
+      for (int j = lane; j <= nb; j += 64) {
+        const double t = Bt[p * ld + j];
+        Bt[p * ld + j] = Bt[im * ld + j];
+        Bt[im * ld + j] = t;
+      }
+    lds_order();
+    const double inv = 1.0 / Bt[p * ld + p];
+    const int w = nb - p;   // columns p+1 .. nb
+    for (int q = lane; q < (nb - p - 1) * w; q += 64) {
+      const int i = p + 1 + q / w, j = p + 1 + q % w;
+      Bt[i * ld + j] -= Bt[i * ld + p] * inv * Bt[p * ld + j];
+    }
+    lds_order();
+  }
+  double x0 = 0.0, x1 = 0.0;      // solutions of columns lane and lane + 64
+  for (int i = nb - 1; i >= 0; --i) {
+    double part = 0.0;
+    if (lane > i && lane < nb) part = Bt[i * ld + lane] * x0;
+    if (lane + 64 > i && lane + 64 < nb) part += Bt[i * ld + lane + 64] * x1;
+    const double xi = (Bt[i * ld + nb] - wave_sum(part)) / Bt[i * ld + i];
+    if (lane == i) x0 = xi;
+    if (lane + 64 == i) x1 = xi;
+  }
+  if (lane < nb) xB[lane] = x0;
+  if (lane + 64 < nb) xB[lane + 64] = x1;
+}
+
 // Dense border solve by wavefront 0, without workgroup barriers (the workgroup meets once at
-// the end): the arms' Schur contributions are added in arm order, then Gaussian elimination
-// with partial pivoting (the largest magnitude, the first row among equals; one lane per
-// candidate row, a butterfly for the maximum) and back substitution with one lane per column
-// (two for borders of more than 64 DOFs) and a butterfly sum per row.
+// the end): the arms' Schur contributions are added in arm order (each lane adds the slots the
+// arm's table assigns it), then Gaussian elimination with partial pivoting.
 __device__ __noinline__ void border_solve(ArgsP Ap, int sid, double DM_L* Bt, int ld,
                              const double DM_L* deltas, double DM_L* xB, double DM_L* scal, int DM_L* bad_flag) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmDev DM_C& D = A.d;
   const DmSystem DM_C& S = D.sys[uniform(sid)];
   (void)scal;
-  const int nb = S.nb, lane = threadIdx.x;
+  const int nb = S.nb, lane = threadIdx.x, na = S.n_arms;
   if (threadIdx.x < 64) {
-    for (int a = 0; a < S.n_arms; ++a) {
-      const DmArm arm = D.arm[S.arm0 + a];
-      const DmChain ch = D.chain[arm.chain];
-      const double DM_L* dl = deltas + a * 110;
-      const int ntr = arm.n_trail;
-      for (int p = lane; p < ntr * (ntr + 1); p += 64) {
-        const int i = p / (ntr + 1), j = p % (ntr + 1);
-        const int bi = D.bmap[ch.bmap_off + (arm.first + arm.dir * (arm.count + i)) - ch.b_lo];
-        if (D.bfix[S.bfix_off + bi]) continue;
-        if (j < ntr) {
-          const int bj = D.bmap[ch.bmap_off + (arm.first + arm.dir * (arm.count + j)) - ch.b_lo];
-          if (!D.bfix[S.bfix_off + bj]) Bt[bi * ld + bj] += dl[i * 10 + j];
-        } else {
-          Bt[bi * ld + nb] += dl[100 + i];
-        }
-      }
-      lds_order();
-    }
-    int bad = 0;
-    for (int p = 0; p < nb; ++p) {
-      double vm = (lane >= p && lane < nb) ? fabs(Bt[lane * ld + p]) : -1.0;
-      int im = lane;
-      for (int p2 = lane + 64; p2 < nb; p2 += 64) {
-        const double v2 = fabs(Bt[p2 * ld + p]);
-        if (p2 >= p && v2 > vm) { vm = v2; im = p2; }
+    for (int a0 = 0; a0 < na; a0 += 4) {
+      int c0[4], c1[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {        // the table entries of four arms, loaded together
+        const int* t = D.bsch + (size_t)(S.arm0 + (a0 + q < na ? a0 + q : 0)) * 110;
+        c0[q] = t[lane];
+        c1[q] = t[lane + 64 < 110 ? lane + 64 : 109];
+        c1[q] = lane + 64 < 110 ? c1[q] : -1;
       }
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(vm, o, 64);
-        const int oi = __shfl_xor(im, o, 64);
-        if (ov > vm || (ov == vm && oi < im)) { vm = ov; im = oi; }
-      }
-      im = uniform(im);
-      if (!(vm > 1e-300) || !isfinite(vm)) bad = 1;
-      if (im != p)
-        for (int j = lane; j <= nb; j += 64) {
-          const double t = Bt[p * ld + j];
-          Bt[p * ld + j] = Bt[im * ld + j];
-          Bt[im * ld + j] = t;
+      for (int q = 0; q < 4; ++q) {
+        if (a0 + q < na) {
+          const double DM_L* dl = deltas + (a0 + q) * 110;
+          if (c0[q] >= 0) Bt[(c0[q] >> 16) * ld + ((c0[q] >> 8) & 255)] += dl[c0[q] & 255];
+          if (c1[q] >= 0) Bt[(c1[q] >> 16) * ld + ((c1[q] >> 8) & 255)] += dl[c1[q] & 255];
+          lds_order();
         }
-      lds_order();
-      const double inv = 1.0 / Bt[p * ld + p];
-      const int w = nb - p;   // columns p+1 .. nb
-      for (int q = lane; q < (nb - p - 1) * w; q += 64) {
-        const int i = p + 1 + q / w, j = p + 1 + q % w;
-        Bt[i * ld + j] -= Bt[i * ld + p] * inv * Bt[p * ld + j];
       }
-      lds_order();
     }
-    double x0 = 0.0, x1 = 0.0;      // solutions of columns lane and lane + 64
-    for (int i = nb - 1; i >= 0; --i) {
-      double part = 0.0;
-      if (lane > i && lane < nb) part = Bt[i * ld + lane] * x0;
-      if (lane + 64 > i && lane + 64 < nb) part += Bt[i * ld + lane + 64] * x1;
-      const double xi = (Bt[i * ld + nb] - wave_sum(part)) / Bt[i * ld + i];
-      if (lane == i) x0 = xi;
-      if (lane + 64 == i) x1 = xi;
+    int bad = 0;
+    if (nb <= 32) {
+      const double x = nb <= 10 ? border_lu_regs<10>(Bt, ld, nb, bad)
+                     : nb <= 16 ? border_lu_regs<16>(Bt, ld, nb, bad) : border_lu_regs<32>(Bt, ld, nb, bad);
+      if (lane < nb) xB[lane] = x;
+    } else {
+      border_lu_lds(Bt, ld, nb, xB, bad);
     }
-    if (lane < nb) xB[lane] = x0;
-    if (lane + 64 < nb) xB[lane + 64] = x1;
     if (bad && lane == 0) *bad_flag = 1;
   }
   __syncthreads();

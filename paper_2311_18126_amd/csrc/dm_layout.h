@@ -100,6 +100,8 @@ struct DmDev {
   const int DM_C* bjst;
   const int DM_C* bent;         // border entry -> first item (per system from bent_off)
   const DmBItem DM_C* bitem;    // border entry terms, summed in their stored order
+  const int DM_C* bsch;         // [arms][110]: where each Schur slot of an arm adds into the
+                                // border, (row << 16) | (col << 8) | slot, or -1 (none or clamped)
   const unsigned char DM_C* bfix;
   const unsigned char DM_C* cfix;   // per chain DOF: 1 if clamped
   const unsigned DM_C* nmask;   // [chain-node rows][4]: clamped and border bits of chain DOFs

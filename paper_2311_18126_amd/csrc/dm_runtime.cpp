@@ -534,6 +534,27 @@ dm_status do_finalize(dm_sim* s) {
     }
     bent.push_back((int)bitem.size());
   }
+  // ---- per arm, the border entry each of its Schur-complement slots adds to: slot i * 10 + j
+  // (trailing DOFs i, j) or 100 + i (right-hand side of trailing DOF i)
+  std::vector<int> bsch(arms.size() * 110, -1);
+  for (const DmSystem& S : systems) {
+    if (S.nb > 255) return fail(DM_ERR_UNSUPPORTED, "border larger than 255 DOFs");
+    for (int a = S.arm0; a < S.arm0 + S.n_arms; ++a) {
+      const DmArm& A = arms[a];
+      const DmChain& C = chains[A.chain];
+      const int ntr = A.n_trail;
+      auto bidx = [&](int i) { return bmap[C.bmap_off + (A.first + A.dir * (A.count + i)) - C.b_lo]; };
+      for (int i = 0; i < ntr; ++i) {
+        const int bi = bidx(i);
+        if (bfix[S.bfix_off + bi]) continue;
+        for (int j = 0; j < ntr; ++j) {
+          const int bj = bidx(j);
+          if (!bfix[S.bfix_off + bj]) bsch[(size_t)a * 110 + i * (ntr + 1) + j] = (bi << 16) | (bj << 8) | (i * 10 + j);
+        }
+        bsch[(size_t)a * 110 + i * (ntr + 1) + ntr] = (bi << 16) | (S.nb << 8) | (100 + i);
+      }
+    }
+  }
   // ---- homes of every DOF (delta index or border)
   const int NN = (int)mass.size(), NE = (int)ebar.size();
   for (int c = 0; c < 3; ++c) node_home_c[c].assign(NN, 0);
@@ -613,7 +634,7 @@ dm_status do_finalize(dm_sim* s) {
 #define UP(vec, field) if ((st = up(vec, D.field)) != DM_OK) return st;
   UP(systems, sys) UP(chains, chain) UP(arms, arm) UP(order, order) UP(chain_node, chain_node) UP(chain_edge, chain_edge)
   UP(bmap, bmap) UP(bsrc, bsrc) UP(bjst, bjst) UP(bfix, bfix) UP(cfix, cfix) UP(nmask, nmask)
-  UP(bent, bent) UP(bitem, bitem)
+  UP(bent, bent) UP(bitem, bitem) UP(bsch, bsch)
   UP(mass, mass) UP(radius, radius)
   std::vector<double> forceS = soa3(force);
   UP(forceS, force) UP(node_owner, node_owner) UP(nh, node_home)

@@ -87,3 +87,24 @@ def test_star_stored_with_reversed_limbs_matches(dm):
     xa = star_positions(a, 0)
     xb = np.concatenate([b.rod_state(k)[0][::-1] for k in range(6)])
     assert rel(xb, xa) < 1e-9
+
+
+@pytest.mark.parametrize("limbs", [7, 8])
+def test_many_limb_star_matches_oracle(dm, limbs):
+    """Hub borders of 3 + 4 * limbs DOFs: 31 (seven limbs) is solved in registers, 35 (eight
+    limbs, the most rods one joint may hold) by the elimination in shared memory.  Both
+    against the oracle stepped here: 1e-9 after one step, 1e-8 after two."""
+    from oracle import der
+    d = W.star_robots(n_instances=1, steps=2, limbs=limbs)
+    print(f"case: one {limbs}-limb star, 2 steps", flush=True)
+    sim = dm.sim_from_description(d)
+    osys, ost = der.build(d, list(range(limbs)))
+    for k, tol in ((1, 1e-9), (2, 1e-8)):
+        st = sim.step(d["dt"], 1)
+        assert st["status"][0] == 0
+        ost, info = der.step(osys, ost, d["dt"], d["tol"], d["max_iter"], polish=1,
+                             line_search=d.get("line_search", False))
+        assert info.converged
+        ref = np.concatenate([der.rod_positions(osys, ost, a).numpy() for a in range(limbs)])
+        got = np.concatenate([sim.rod_state(a)[0] for a in range(limbs)])
+        assert rel(got, ref) < tol, (limbs, k, rel(got, ref))
