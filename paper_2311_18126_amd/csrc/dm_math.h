@@ -69,21 +69,34 @@ template <int N> DM_HD Dual<N> operator+(const Dual<N>& a, double s) { Dual<N> r
 template <int N> DM_HD Dual<N> operator+(double s, const Dual<N>& a) { Dual<N> r = a; r.v += s; return r; }
 template <int N> DM_HD Dual<N> operator-(const Dual<N>& a, double s) { Dual<N> r = a; r.v -= s; return r; }
 template <int N> DM_HD Dual<N> operator-(double s, const Dual<N>& a) { Dual<N> r = -a; r.v += s; return r; }
-template <int N> DM_HD Dual<N> dinv(const Dual<N>& a) { Dual<N> r; double i = 1.0 / a.v; double m = -i * i; r.v = i;
+// 1/a: on the device the hardware estimate (about 24 correct bits) refined by one third-order
+// correction r (1 + e + e^2), e = 1 - a r (relative error of order e^3, below the float64
+// rounding of the result; not correctly rounded), in four operations instead of a division.
+DM_HD double frcp(double a) {
+#ifdef __HIP_DEVICE_COMPILE__
+  const double r = __builtin_amdgcn_rcp(a);
+  const double e = fma(-a, r, 1.0);
+  return fma(r, fma(e, e, e), r);
+#else
+  return 1.0 / a;
+#endif
+}
+template <int N> DM_HD Dual<N> dinv(const Dual<N>& a) { Dual<N> r; double i = frcp(a.v); double m = -i * i; r.v = i;
 #pragma unroll
   for (int k = 0; k < N; ++k) r.d[k] = m * a.d[k]; return r; }
-template <int N> DM_HD Dual<N> dsqrt(const Dual<N>& a) { Dual<N> r; double s = sqrt(a.v); double h = 0.5 / s; r.v = s;
+template <int N> DM_HD Dual<N> dsqrt(const Dual<N>& a) { Dual<N> r; double s = sqrt(a.v); double h = 0.5 * frcp(s); r.v = s;
 #pragma unroll
   for (int k = 0; k < N; ++k) r.d[k] = h * a.d[k]; return r; }
 template <int N> DM_HD void dsincos(const Dual<N>& a, Dual<N>& s, Dual<N>& c) {
-  double sv = sin(a.v), cv = cos(a.v);
+  double sv, cv;
+  sincos(a.v, &sv, &cv);      // one argument reduction for both
   s.v = sv; c.v = cv;
 #pragma unroll
   for (int k = 0; k < N; ++k) { s.d[k] = cv * a.d[k]; c.d[k] = -sv * a.d[k]; }
 }
-DM_HD double dinv(double a) { return 1.0 / a; }
+DM_HD double dinv(double a) { return frcp(a); }
 DM_HD double dsqrt(double a) { return sqrt(a); }
-DM_HD void dsincos(double a, double& s, double& c) { s = sin(a); c = cos(a); }
+DM_HD void dsincos(double a, double& s, double& c) { sincos(a, &s, &c); }
 template <int N> DM_HD double val(const Dual<N>& a) { return a.v; }
 DM_HD double val(double a) { return a; }
 
@@ -241,7 +254,7 @@ DM_HD void stencil_strains(v3 tf, v3 d1f, double thf, v3 te, v3 d1e, double the,
 template <int N> DM_HD Dual<N> datan2(const Dual<N>& y, const Dual<N>& x) {
   Dual<N> r;
   r.v = atan2(y.v, x.v);
-  const double q = 1.0 / (x.v * x.v + y.v * y.v);
+  const double q = frcp(x.v * x.v + y.v * y.v);
 #pragma unroll
   for (int k = 0; k < N; ++k) r.d[k] = (x.v * y.d[k] - y.v * x.d[k]) * q;
   return r;
@@ -283,7 +296,7 @@ DM_HD void stencil_grad_g(const Vec<S>& ef, const Vec<S>& ee, const S& thf, cons
   Vec<S> u = vsub(d1f, vscale(vdot(G.t, d1f) * dinv(vdot(F.t, G.t) + 1.0), vadd(F.t, G.t)));
   S beta = datan2(vdot(vcross(u, d1e), G.t), vdot(u, d1e));
   const double two_pi = 6.283185307179586476925286766559;
-  beta = beta + two_pi * rint((bref - val(beta)) / two_pi);
+  beta = beta + two_pi * rint((bref - val(beta)) * (1.0 / two_pi));
   S tau = the - thf + beta;
   S ichi = dinv(vdot(F.t, G.t) + 1.0);
   Vec<S> kb = vscale(2.0 * ichi, vcross(F.t, G.t));
