@@ -617,7 +617,7 @@ __device__ __forceinline__ double row_bcast(double v) {
 // padding of their first record.
 template <int T, bool MASK>
 __device__ __forceinline__ void elim_step(double (&w)[DM_HS], const double (&col)[DM_HS], double ent, int k, int l,
-                                          int h, const ArmView& V, int& bad) {
+                                          int h, const ArmView& V, double DM_G* recp, int& bad) {
   constexpr int hT = T >= DM_HS ? 1 : 0, tT = T - DM_HS * hT;
   const bool act = MASK ? k < V.count : true;
   const double u = from_half(w[tT], hT);              // row k's entry in this lane's column
@@ -630,9 +630,7 @@ __device__ __forceinline__ void elim_step(double (&w)[DM_HS], const double (&col
   const bool piv_lane = (l == T);
   // factor record of row k: [1/pivot, U(k, k+1..k+10), modified rhs]; every lane stores (no
   // branch; both halves store the same values), idle roles into the record's padding
-  const int j = l < DM_WIN ? (l - T + DM_WIN) % DM_WIN : (l == DM_WIN ? DM_WIN : DM_FAC);
-  const int rec = act ? (V.fac_off + k) * DM_FAC_STRIDE + j : V.fac_off * DM_FAC_STRIDE + DM_FAC;
-  V.fac[rec] = piv_lane ? inv : u;
+  *recp = piv_lane ? inv : u;
   // the pivot lane's scale is exactly 1, so its own column becomes exactly zero and the new
   // column k + 11 it takes over is added in exactly; a parked row scales by zero
   const double us = !act ? 0.0 : (piv_lane ? 1.0 : u * inv);
@@ -645,6 +643,15 @@ __device__ __forceinline__ void elim_step(double (&w)[DM_HS], const double (&col
 }
 
 #define DM_UNROLL11(M) M(0) M(1) M(2) M(3) M(4) M(5) M(6) M(7) M(8) M(9) M(10)
+
+// Where role l stores in the factor record of row k (k % 11 == T): slot (l - T) mod 11 of the
+// window columns, 11 for the right-hand side, the padding for idle roles and parked rows.
+template <int T>
+__device__ __forceinline__ double DM_G* rec_ptr(const ArmView& V, int k, int l, bool act) {
+  const int j = l < DM_WIN ? (l - T + DM_WIN) % DM_WIN : (l == DM_WIN ? DM_WIN : DM_FAC);
+  const int rec = act ? (V.fac_off + k) * DM_FAC_STRIDE + j : V.fac_off * DM_FAC_STRIDE + DM_FAC;
+  return V.fac + rec;
+}
 
 // Forward elimination of the na (<= 2) arms ai0 .. ai0+na-1, one per row pair; deltas: the
 // Schur-complement slots (110 doubles per arm) of arm ai0.  The new columns of a block are
@@ -671,23 +678,40 @@ __device__ __noinline__ void sweep_arms(ArgsP Ap, int ai0, int na, double DM_L* 
 #pragma unroll
   for (int T = 0; T < DM_WIN; ++T) ent[T] = row_entry(V, T + DM_WIN, l, wrap11(l, T));
   int bad = 0;
+  // Deep blocks (k0 + 33 <= every arm's count: the block's rows and the entering rows it loads,
+  // k0 + 22 .. k0 + 32, are inside every arm) address by fixed per-lane strides from one
+  // pointer per block.  Entering row of step T: the right-hand side role (and the idle roles,
+  // which load the same row's right-hand side and never use it) reads R at T dir past the
+  // block's base, the column roles read band entry (r, r + t - 10), t = (l - T - 1) mod 11,
+  // at 20 dir T past the base plus 11 dir once T >= l.  Record of step T: 15 T past the base
+  // for the column roles (16 T for the others) plus 11 once T > l.
+  const bool side = l >= DM_WIN;
+  const int e_step = side ? V.dir : (DM_NDIAG - 1) * V.dir, e_jump = side ? 0 : DM_WIN * V.dir;
+  const int e_adv = DM_WIN * (side ? V.dir : V.d21());
+  const int r_step = side ? DM_FAC_STRIDE : DM_FAC_STRIDE - 1;
+  const int r_base = l < DM_WIN ? l : (l == DM_WIN ? DM_WIN : DM_FAC);
+  const double DM_G* ep = side ? V.R + (V.dof_off + V.cd(2 * DM_WIN)) : V.band + (V.b0() + V.d21() * (2 * DM_WIN) + V.dir * (l - DM_WIN));
+  double DM_G* rp = V.fac + (size_t)V.fac_off * DM_FAC_STRIDE + r_base;
   for (int k0 = 0; k0 < cmax; k0 += DM_WIN) {
     load_new_column(ncol, k0 + DM_WIN, l, h, V);
-    // a block inside every arm of the group runs unmasked; in the last block of some arm the
-    // rows whose arm has ended are masked per step and the group stops on a uniform branch
-    if (k0 + DM_WIN <= cmin) {
+    // a deep block runs unmasked; in the last blocks the rows whose arm has ended are masked
+    // per step, the loads of rows past an arm's end read the zero pad, and the group stops
+    // on a uniform branch
+    if (k0 + 3 * DM_WIN <= cmin) {
 #define DM_E(T) \
-  elim_step<T, false>(w, col, ent[T], k0 + T, l, h, V, bad); \
-  ent[T] = row_entry(V, k0 + T + 2 * DM_WIN, l, wrap11(l, T));
+  elim_step<T, false>(w, col, ent[T], k0 + T, l, h, V, rp + (T * r_step + (T > l && !side ? DM_WIN : 0)), bad); \
+  ent[T] = ep[T * e_step + (T >= l ? e_jump : 0)];
       DM_UNROLL11(DM_E)
 #undef DM_E
     } else {
 #define DM_E(T) \
-  if (k0 + T < cmax) elim_step<T, true>(w, col, ent[T], k0 + T, l, h, V, bad); \
+  if (k0 + T < cmax) elim_step<T, true>(w, col, ent[T], k0 + T, l, h, V, rec_ptr<T>(V, k0 + T, l, k0 + T < V.count), bad); \
   ent[T] = row_entry(V, k0 + T + 2 * DM_WIN, l, wrap11(l, T));
       DM_UNROLL11(DM_E)
 #undef DM_E
     }
+    ep += e_adv;
+    rp += DM_WIN * DM_FAC_STRIDE;
 #pragma unroll
     for (int q = 0; q < DM_HS; ++q) col[q] = ncol[q];
   }
