@@ -22,6 +22,10 @@ What it computes, in the paper's order and notation (DisMech, Methodology):
   gravity and optional viscous damping (miscellaneous forces).
 * Backward Euler (Eq. 14-15) solved by Newton's method; the Jacobian (Eq. 16)
   is the automatic Jacobian of the residual.  Velocity update after Eq. 16.
+* Implicit midpoint (named as the alternative implicit scheme in the time-stepping
+  subsection, without formulas): the textbook rule for M qddot = F,
+  q_{n+1} = q_n + dt (qdot_n + qdot_{n+1}) / 2 and M (qdot_{n+1} - qdot_n) = dt F(q_m)
+  at q_m = (q_n + q_{n+1}) / 2, solved by Newton's method for q_{n+1}.
 * Elastic joints (Elastic Joints subsection): nodes shared by several rods;
   bend and twist for every pair of edges meeting at the joint.
 * Actuation through natural curvature (Actuation subsection).
@@ -468,6 +472,28 @@ def residual(sys, q, st, dt, kappa_bar):
     return pack(Mx - F, Mt - sys.moment) + gE
 
 
+def residual_midpoint(sys, q, st, dt, kappa_bar):
+    """Implicit-midpoint residual in the unknown q = q_{n+1}: eliminating qdot_{n+1} =
+    2 (q_{n+1} - q_n) / dt - qdot_n from M (qdot_{n+1} - qdot_n) = dt F(q_m) gives
+        2 M / dt^2 (q_{n+1} - q_n - dt qdot_n) + dE/dq (q_m) - F_ext(q_m) = 0,
+    q_m = (q_n + q_{n+1}) / 2.  The elastic energy at q_m uses frames carried by time-parallel
+    transport from the step-start frames to q_m; damping and friction see the midpoint
+    velocity (q_{n+1} - q_n) / dt = (x_m - x_n) / (dt / 2)."""
+    qn = pack(st.x, st.theta)
+    qm = 0.5 * (qn + q)
+
+    def energy(qq):
+        xx, tt = unpack(sys, qq)
+        return elastic_energy(sys, xx, tt, st, kappa_bar)
+    gE = torch.func.grad(energy)(qm)
+    x1, th1 = unpack(sys, q)
+    xm, _ = unpack(sys, qm)
+    Mx = 2.0 * sys.mass[:, None] * (x1 - st.x - dt * st.v) / (dt * dt)
+    Mt = 2.0 * sys.Itheta * (th1 - st.theta - dt * st.omega) / (dt * dt)
+    F = external_force(sys, xm, st, 0.5 * dt)
+    return pack(Mx - F, Mt - sys.moment) + gE
+
+
 @dataclass
 class StepInfo:
     iters: int
@@ -477,21 +503,21 @@ class StepInfo:
 
 
 def newton_solve(sys, st, dt, kappa_bar, tol=1e-9, max_iter=50, q0=None, polish=0, line_search=False,
-                 stag_tol=1e-6):
+                 stag_tol=1e-6, res=residual):
     """Newton's method on the residual.  Initial guess q_n unless q0 is given.
     Stops when the 2-norm of the residual over free DOFs is <= tol, or when the residual
     was already <= stag_tol and the last iteration failed to halve it (the FP64 rounding
     floor of a stiff rod can lie above tol); `polish` extra iterations may follow (used
     to reach the rounding floor in tests).
     With line_search (the paper's optional globalisation), the Newton step is halved
-    (at most 10 times) until the residual norm decreases."""
+    (at most 10 times) until the residual norm decreases.  `res` is the scheme's residual."""
     free = ~sys.fixed
     q = pack(st.x, st.theta).clone() if q0 is None else q0.clone()
-    jac = torch.func.jacfwd(lambda qq: residual(sys, qq, st, dt, kappa_bar))
+    jac = torch.func.jacfwd(lambda qq: res(sys, qq, st, dt, kappa_bar))
     hist = []
     it = 0
     extra = 0
-    R = residual(sys, q, st, dt, kappa_bar)
+    R = res(sys, q, st, dt, kappa_bar)
     while True:
         r = float(torch.linalg.norm(R[free]))
         hist.append(r)
@@ -509,7 +535,7 @@ def newton_solve(sys, st, dt, kappa_bar, tol=1e-9, max_iter=50, q0=None, polish=
         for _ in range(11 if line_search else 1):
             qn = q.clone()
             qn[free] = q[free] - alpha * dq
-            Rn = residual(sys, qn, st, dt, kappa_bar)
+            Rn = res(sys, qn, st, dt, kappa_bar)
             if not line_search or float(torch.linalg.norm(Rn[free])) < r:
                 break
             alpha *= 0.5
@@ -526,8 +552,25 @@ def commit(sys, st, q, dt):
                  t.clone(), d1.clone(), beta.clone(), st.time + dt)
 
 
-def step(sys, st, dt, tol=1e-9, max_iter=50, kbar_rods=None, polish=0, q0=None, line_search=False):
-    """One backward-Euler time step.  Natural curvature is evaluated at the end-of-step time."""
+def commit_midpoint(sys, st, q, dt):
+    """Implicit-midpoint velocity update qdot_{n+1} = 2 (q_{n+1} - q_n) / dt - qdot_n and the
+    step-end frames for the next step."""
+    x, theta = unpack(sys, q)
+    t, ell, d1, d2, m1, m2 = frames(sys, x, theta, st)
+    _, _, beta = strains(sys, x, theta, st)
+    return State(x.clone(), theta.clone(), 2.0 * (x - st.x) / dt - st.v, 2.0 * (theta - st.theta) / dt - st.omega,
+                 t.clone(), d1.clone(), beta.clone(), st.time + dt)
+
+
+def step(sys, st, dt, tol=1e-9, max_iter=50, kbar_rods=None, polish=0, q0=None, line_search=False,
+         scheme="euler"):
+    """One time step: backward Euler ("euler", natural curvature at the end-of-step time) or
+    implicit midpoint ("midpoint", natural curvature at the midpoint time t + dt / 2)."""
+    if scheme == "midpoint":
+        kap = natural_curvature(sys, st.time + 0.5 * dt, kbar_rods)
+        q, info = newton_solve(sys, st, dt, kap, tol, max_iter, q0=q0, polish=polish, line_search=line_search,
+                               res=residual_midpoint)
+        return (commit_midpoint(sys, st, q, dt) if info.converged else st), info
     kap = natural_curvature(sys, st.time + dt, kbar_rods)
     q, info = newton_solve(sys, st, dt, kap, tol, max_iter, q0=q0, polish=polish, line_search=line_search)
     if not info.converged:
@@ -535,7 +578,7 @@ def step(sys, st, dt, tol=1e-9, max_iter=50, kbar_rods=None, polish=0, q0=None, 
     return commit(sys, st, q, dt), info
 
 
-def simulate(desc, steps=None, rod_ids=None, tol=None, polish=0, record=False, line_search=None):
+def simulate(desc, steps=None, rod_ids=None, tol=None, polish=0, record=False, line_search=None, scheme="euler"):
     """Step the rods `rod_ids` (closed under joints) for `steps` steps."""
     sys, st = build(desc, rod_ids)
     n = desc["steps"] if steps is None else steps
@@ -543,7 +586,7 @@ def simulate(desc, steps=None, rod_ids=None, tol=None, polish=0, record=False, l
     ls = desc.get("line_search", False) if line_search is None else line_search
     traj, infos = [], []
     for _ in range(n):
-        st, info = step(sys, st, desc["dt"], tol, desc["max_iter"], polish=polish, line_search=ls)
+        st, info = step(sys, st, desc["dt"], tol, desc["max_iter"], polish=polish, line_search=ls, scheme=scheme)
         infos.append(info)
         if not info.converged:
             break
