@@ -170,6 +170,24 @@ def star_section(dm, steps):
             "block_size": sim.block_size}
 
 
+def midpoint_section(dm, steps):
+    """The 1024-rod batch stepped with the implicit-midpoint integrator (same rods, residual
+    and launch as the headline figure)."""
+    import workloads as W
+    d = W.rod_batch(1024)
+    sim = dm.sim_from_description(d)
+    sim.set_integrator("midpoint")
+    sim.step(d["dt"], 1)
+    st, wall = timed_steps(sim, d["dt"], steps)
+    assert (st["status"] == 0).all()
+    nodes = float(sim.num_nodes)
+    out = {"workload": "1024-rod batch (seed 0) as above, implicit midpoint", "steps": steps,
+           "value": nodes * steps / wall, "unit": "node-steps/s",
+           "newton_iters_per_step": float(st["iters"].mean() / steps), "block_size": sim.block_size}
+    sim.close()
+    return out
+
+
 def adjoint_section(dm):
     """Gradient of the tip-trajectory loss with respect to natural curvature: 256 rods x 100
     nodes x 200 steps, checkpoint every 20 (forward rollout + recompute + backward), timed after
@@ -292,6 +310,7 @@ def main():
     if not args.no_extras:
         out["warm_start"] = warm_start_section(dm, args.steps, log)
         out["stars"] = star_section(dm, max(args.steps // 5, 5))
+        out["midpoint"] = midpoint_section(dm, args.steps)
         out["adjoint"] = adjoint_section(dm)
     if not args.no_per_rod:
         out["per_rod_plain_value"] = per_rod_baseline(dm, desc, min(args.steps, 20))

@@ -132,6 +132,20 @@ dm_status dm_finalize(dm_sim* sim);
  * or DM_ERR_SINGULAR (the worst over systems), or an error. */
 dm_status dm_step(dm_sim* sim, double dt, int nsteps, dm_stats* stats);
 
+/* Time integrator of dm_step and dm_autotune (Time Stepping subsection, which offers
+ * backward Euler and implicit midpoint).  DM_BACKWARD_EULER (default): the residual of Eq. 15
+ * at the step end.  DM_IMPLICIT_MIDPOINT: q_{n+1} = q_n + dt (qdot_n + qdot_{n+1}) / 2 with
+ * M (qdot_{n+1} - qdot_n) = dt F(q_m), q_m = (q_n + q_{n+1}) / 2; solved as the backward-Euler
+ * residual over dt / 2 for q_m (the same function values, so newton_tol means the same), then
+ * q_{n+1} = 2 q_m - q_n, qdot_{n+1} = 2 (q_{n+1} - q_n) / dt - qdot_n; frames are carried from
+ * the step start to q_m for the forces and to q_{n+1} for the commit; damping and friction see
+ * (q_{n+1} - q_n) / dt; actuation is evaluated at t + dt / 2.  Applies to later calls; the
+ * adjoint (dm_rollout, dm_adjoint) returns DM_ERR_UNSUPPORTED under midpoint.  Unknown
+ * scheme: DM_ERR_INVALID_ARG. */
+#define DM_BACKWARD_EULER 0
+#define DM_IMPLICIT_MIDPOINT 1
+dm_status dm_set_integrator(dm_sim* sim, int scheme);
+
 /* Number of independent systems (connected rod sets) and the system holding a rod. */
 int dm_num_systems(const dm_sim* sim);
 int dm_rod_system(const dm_sim* sim, int rod);
@@ -182,8 +196,8 @@ dm_status dm_set_natural_curvature_all(dm_sim* sim, const double* kbar, int on_d
  * device).  It recomputes each checkpoint interval forward, then runs the implicit-function
  * adjoint of every step backward (transposed Newton system, step-start frames and natural
  * curvature differentiated exactly); the sim is back at the rollout's final state after the
- * call.  Both return DM_ERR_UNSUPPORTED for joined rods, floor contact or actuated rods, and
- * DM_ERR_STATE if dm_adjoint has no completed rollout. */
+ * call.  Both return DM_ERR_UNSUPPORTED for joined rods, floor contact, actuated rods or the
+ * implicit-midpoint integrator, and DM_ERR_STATE if dm_adjoint has no completed rollout. */
 dm_status dm_rollout(dm_sim* sim, double dt, int nsteps, int ckpt_every, double* tips, int on_device);
 dm_status dm_adjoint(dm_sim* sim, const double* dL_dtips, int in_on_device, double* dL_dkbar,
                      int out_on_device);

@@ -87,6 +87,7 @@ _SIGS = {
     "dm_ws_features": (c_int, [c_void_p, c_void_p]),
     "dm_ws_targets": (c_int, [c_void_p, c_void_p, c_double, c_void_p]),
     "dm_set_warm_start": (c_int, [c_void_p, c_void_p, c_int]),
+    "dm_set_integrator": (c_int, [c_void_p, c_int]),
     "dm_ws_predict": (c_int, [c_void_p, c_double, c_void_p, c_int]),
     "dm_autotune": (c_int, [c_void_p, c_double, c_int, c_char_p, POINTER(c_int)]),
     "dm_time": (c_double, [c_void_p]),
@@ -232,6 +233,14 @@ class Sim:
             out[i] = (st[i].steps_done, st[i].newton_iters, st[i].status, st[i].floor_steps, st[i].fallbacks,
                       st[i].residual)
         return out
+
+    def set_integrator(self, scheme):
+        """Time integrator of step(): "euler" (backward Euler, the default) or "midpoint"
+        (implicit midpoint); see dm_set_integrator."""
+        code = {"euler": 0, "midpoint": 1}.get(scheme)
+        if code is None:
+            raise ValueError(f"unknown integrator {scheme!r}")
+        _check(lib().dm_set_integrator(self._h, code), "dm_set_integrator")
 
     # -- state --------------------------------------------------------------
     @property

@@ -1059,6 +1059,18 @@ __device__ __noinline__ void commit(ArgsP Ap, int sid) {
   const DmDev DM_C& D = A.d;
   const DmSystem DM_C& S = D.sys[uniform(sid)];
   const int NN = D.n_nodes_tot, NE = D.n_edges_tot, NS = D.n_st_tot;
+  if (A.midpoint) {
+    // implicit midpoint: the Newton solve (a backward-Euler solve over half the step) gave the
+    // midpoint state q_m; the step ends at q_{n+1} = 2 q_m - q_n (clamped DOFs stay put)
+    for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const int k = c * NN + S.node0 + i;
+        D.x[k] = 2.0 * D.x[k] - D.x0[k];
+      }
+    for (int i = threadIdx.x; i < S.n_edges; i += blockDim.x) D.th[S.edge0 + i] = 2.0 * D.th[S.edge0 + i] - D.th0[S.edge0 + i];
+    __syncthreads();
+  }
   for (int i = threadIdx.x; i < S.n_st; i += blockDim.x) {
     const int s = S.st0 + i;
     const int np = D.sn[s], nc = D.sn[NS + s], nn = D.sn[2 * NS + s];
@@ -1079,15 +1091,19 @@ __device__ __noinline__ void commit(ArgsP Ap, int sid) {
     v3 d1 = transport_perp(ld3(D.tref, NE, e), t, ld3(D.d1ref, NE, e));
     st3(D.tref, NE, e, t);
     st3(D.d1ref, NE, e, d1);
-    D.om[e] = (D.th[e] - D.th0[e]) / A.dt;
+    // backward Euler: (q_{n+1} - q_n) / dt; midpoint (A.dt = half the step):
+    // 2 (q_{n+1} - q_n) / step - qdot_n
+    const double om = (D.th[e] - D.th0[e]) / A.dt;
+    D.om[e] = A.midpoint ? om - D.om[e] : om;
     D.th0[e] = D.th[e];
   }
   for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x) {
     const int n = S.node0 + i;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      D.vprev[c * NN + n] = D.v[c * NN + n];
-      D.v[c * NN + n] = (D.x[c * NN + n] - D.x0[c * NN + n]) / A.dt;
+      const double v0 = D.v[c * NN + n], v = (D.x[c * NN + n] - D.x0[c * NN + n]) / A.dt;
+      D.vprev[c * NN + n] = v0;
+      D.v[c * NN + n] = A.midpoint ? v - v0 : v;
       D.x0[c * NN + n] = D.x[c * NN + n];
     }
   }
@@ -1439,7 +1455,7 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
     }
     commit(Ap, sid);
     DM_TP(7);
-    t = t_end;
+    t += A.midpoint ? 2.0 * A.dt : A.dt;
     ++steps;
   }
   DM_TSAVE(sid);

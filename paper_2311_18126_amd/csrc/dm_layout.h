@@ -177,7 +177,7 @@ struct DmNetView {
 struct DmStepArgs {
   DmDev d;
   DmNetView net;
-  double dt, tol, stag_tol;
+  double dt, tol, stag_tol;   // dt: the Newton solve's step (half the time step under midpoint)
   double g[3];
   double damping;
   double floor_z, delta, nu, mu, kc;
@@ -188,6 +188,8 @@ struct DmStepArgs {
   int warm_max_iter;   // Newton iterations allowed to the warm-started attempt
   int accum;       // 1: add to the statistics (one-step launches) and skip systems that failed
   int net_lds;     // byte offset of the network's LDS activations (warm == 2)
+  int midpoint;    // 1: implicit midpoint; dt is then half the time step (the Newton solve is
+                   // backward Euler to the midpoint) and the commit extrapolates to the step end
   int n_systems;
   int max_nb, max_arms;
 };

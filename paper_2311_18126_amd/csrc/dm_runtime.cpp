@@ -111,6 +111,7 @@ struct dm_sim {
   double* ws_F = nullptr; size_t ws_F_n = 0;
   dm_mlp* ws_net = nullptr;
   int ws_mode = 0;
+  int scheme = DM_BACKWARD_EULER;   // time integrator of dm_step and dm_rollout
   // captured step sequences of trajectory segments (dm_rollout, the adjoint's recomputation)
   hipStream_t cap_stream = nullptr;
   std::vector<SegGraph> seg_graphs;
@@ -721,7 +722,8 @@ size_t state_doubles(const dm_sim* s) { return 3 * (size_t)s->n_nodes * 3 + 3 * 
 void fill_step_args(const dm_sim* s, double dt, int nsteps, DmStepArgs& A) {
   std::memset(&A, 0, sizeof(A));       // padding too: captured segments are keyed by these bytes
   A.d = s->dev;
-  A.dt = dt;
+  A.midpoint = s->scheme == DM_IMPLICIT_MIDPOINT;
+  A.dt = A.midpoint ? 0.5 * dt : dt;
   A.tol = s->cfg.newton_tol;
   A.stag_tol = s->cfg.stagnation_tol;
   for (int c = 0; c < 3; ++c) A.g[c] = s->cfg.gravity[c];
@@ -907,6 +909,7 @@ dm_status worst_status(dm_sim* s) {
 
 // The adjoint covers independent rods without contact or time-dependent actuation.
 dm_status adjoint_supported(const dm_sim* s) {
+  if (s->scheme != DM_BACKWARD_EULER) return fail(DM_ERR_UNSUPPORTED, "adjoint: only the backward-Euler step");
   if (s->cfg.floor_contact) return fail(DM_ERR_UNSUPPORTED, "adjoint: floor contact is not supported");
   for (const DmSystem& S : s->sys)
     if (S.n_chains != 1 || S.n_jst != 0) return fail(DM_ERR_UNSUPPORTED, "adjoint: joined rods are not supported");
@@ -1154,6 +1157,14 @@ dm_status dm_ws_targets(dm_sim* s, const double* F_prev, double dt, double* T) {
   DM_HIP(hipSetDevice(s->cfg.device));
   DM_HIP(dm_ws_launch_targets(&s->dev, s->ws_rows, s->cn_chain, F_prev, dt, T, s->stream));
   DM_HIP(hipStreamSynchronize(s->stream));
+  return DM_OK;
+}
+
+dm_status dm_set_integrator(dm_sim* s, int scheme) {
+  if (!s) return fail(DM_ERR_INVALID_ARG, "dm_set_integrator: null sim");
+  if (scheme != DM_BACKWARD_EULER && scheme != DM_IMPLICIT_MIDPOINT)
+    return fail(DM_ERR_INVALID_ARG, "dm_set_integrator: unknown scheme " + std::to_string(scheme));
+  s->scheme = scheme;
   return DM_OK;
 }
 

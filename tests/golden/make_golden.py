@@ -33,14 +33,15 @@ def batch_sample_ids(desc):
     return sorted(set(pick))
 
 
-def run(desc, rod_ids, checkpoints, polish=1):
+def run(desc, rod_ids, checkpoints, polish=1, scheme="euler"):
     """Step the system holding rod_ids and record rod states at the given step counts."""
     sys_, st = der.build(desc, rod_ids)
     out, iters = {}, []
     n = max(checkpoints)
     ls = desc.get("line_search", False)
     for k in range(1, n + 1):
-        st, info = der.step(sys_, st, desc["dt"], desc["tol"], desc["max_iter"], polish=polish, line_search=ls)
+        st, info = der.step(sys_, st, desc["dt"], desc["tol"], desc["max_iter"], polish=polish, line_search=ls,
+                            scheme=scheme)
         if not info.converged:
             raise RuntimeError(f"oracle did not converge at step {k}: {info.history}")
         iters.append(info.iters)
@@ -57,6 +58,19 @@ def run(desc, rod_ids, checkpoints, polish=1):
 def golden_cantilever():
     d = W.cantilever()
     return run(d, [0], {1, 10, 100})
+
+
+def golden_cantilever_midpoint():
+    # the undamped swing of this soft cantilever at dt = 1e-2 stays within reach of Newton for
+    # about 90 steps under the midpoint rule (its step 94 already needs 36 iterations and step
+    # 95 does not converge, with or without line search); the record ends at step 50
+    d = W.cantilever()
+    return run(d, [0], {1, 10, 50}, scheme="midpoint")
+
+
+def golden_star_midpoint():
+    d = W.star_robots(n_instances=1, steps=5)
+    return run(d, list(range(6)), {1, 5}, scheme="midpoint")
 
 
 def golden_batch():
@@ -109,7 +123,8 @@ def golden_adjoint():
 
 
 GOLDEN = {"cantilever": golden_cantilever, "batch": golden_batch, "helix": golden_helix, "star": golden_star,
-          "adjoint": golden_adjoint}
+          "adjoint": golden_adjoint, "cantilever_midpoint": golden_cantilever_midpoint,
+          "star_midpoint": golden_star_midpoint}
 
 
 if __name__ == "__main__":

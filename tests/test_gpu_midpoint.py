@@ -1,0 +1,139 @@
+"""GPU parity of the implicit-midpoint integrator (dm_set_integrator) against the oracle's
+midpoint step: the cantilever against stored oracle trajectories (1e-9 after one step, 1e-6
+after 50: the undamped swing outruns Newton near step 95 at this dt), a star with contact, friction and actuation at the midpoint time, uneven small
+rods, a free damped rod with loads and sampled rods of the full 1024-rod batch against the
+oracle stepped here, and the rejected uses."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def dm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2311_18126_amd as m
+    assert os.path.exists(m.LIB_PATH), "libdmrod.so is not built"
+    return m
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def test_cantilever_matches_golden(dm):
+    g = np.load(os.path.join(GOLD, "cantilever_midpoint.npz"))
+    d = W.cantilever()
+    say("case: cantilever, implicit midpoint, 50 steps")
+    sim = dm.sim_from_description(d)
+    sim.set_integrator("midpoint")
+    done, iters = 0, []
+    for k, tol in ((1, 1e-9), (10, 1e-8), (50, 1e-6)):
+        st = sim.step(d["dt"], k - done)
+        done = k
+        assert st["status"][0] == 0
+        iters.append(int(st["iters"][0]))
+        x, th, _, _ = sim.rod_state(0)
+        assert rel(x, g[f"x_{k}_0"]) < tol, (k, rel(x, g[f"x_{k}_0"]))
+        assert np.abs(th - g[f"th_{k}_0"]).max() < 1e3 * tol
+    # Newton on the midpoint residual and on the half-step residual take the same iterates
+    assert sum(iters) <= int(g["iters"].sum()) + 3
+
+
+def test_star_with_contact_and_actuation_matches_golden(dm):
+    g = np.load(os.path.join(GOLD, "star_midpoint.npz"))
+    d = W.star_robots(n_instances=1, steps=5)
+    say("case: one six-limb star, implicit midpoint, 5 steps")
+    sim = dm.sim_from_description(d)
+    sim.set_integrator("midpoint")
+    done = 0
+    for k, tol in ((1, 1e-9), (5, 1e-8)):
+        st = sim.step(d["dt"], k - done)
+        done = k
+        assert st["status"][0] == 0
+        x = np.concatenate([sim.rod_state(a)[0] for a in range(6)])
+        ref = np.concatenate([g[f"x_{k}_{a}"] for a in range(6)])
+        assert rel(x, ref) < tol, (k, rel(x, ref))
+
+
+def test_uneven_small_rods_match_live_oracle(dm):
+    from oracle import der
+    rng = np.random.Generator(np.random.PCG64(17))
+    rods = []
+    for n in (2, 3, 5, 9, 13, 40):
+        kb = rng.normal(0, 2.0, size=(max(n - 2, 0), 2))
+        rods.append(W.rod(W.straight_nodes(n, 0.3 + 0.01 * n), 2e-3, 1e6, kbar=kb if n > 2 else None))
+    d = W.desc(rods, dt=1e-3, steps=3)
+    say("case: uneven small rods, implicit midpoint, 3 steps")
+    sim = dm.sim_from_description(d)
+    sim.set_integrator("midpoint")
+    sim.step(d["dt"], 3)
+    for r in range(len(rods)):
+        _, ost, _, _ = der.simulate(W.subset(d, [r]), steps=3, polish=1, scheme="midpoint")
+        x, _, v, _ = sim.rod_state(r)
+        assert rel(x, ost.x.numpy()) < 1e-9, (r, rel(x, ost.x.numpy()))
+        assert np.abs(v - ost.v.numpy()).max() <= 1e-6 * max(np.abs(ost.v.numpy()).max(), 1e-3), r
+
+
+def test_free_rod_with_damping_and_loads_matches_live_oracle(dm):
+    from oracle import der
+    rng = np.random.Generator(np.random.PCG64(18))
+    n = 17
+    force = rng.normal(0, 1e-3, size=(n, 3))
+    mom = rng.normal(0, 1e-6, size=n - 1)
+    kb = rng.normal(0, 3.0, size=(n - 2, 2))
+    r = W.rod(W.helix_nodes(n, 0.03, 0.04, 0.3), 1.5e-3, 5e6, kbar=kb, fixed_nodes=(), fixed_edges=(),
+              force=force, moment=mom)
+    d = W.desc([r], dt=2e-3, steps=4, damping=3.0)
+    say("case: free helix with damping and loads, implicit midpoint, 4 steps")
+    sim = dm.sim_from_description(d)
+    sim.set_integrator("midpoint")
+    sim.step(d["dt"], 4)
+    x, th, v, om = sim.rod_state(0)
+    _, ost, _, _ = der.simulate(d, steps=4, polish=1, scheme="midpoint")
+    assert rel(x, ost.x.numpy()) < 1e-9
+    assert np.abs(th - ost.theta.numpy()).max() < 1e-8
+    assert rel(om, ost.omega.numpy()) < 1e-6
+
+
+def test_full_batch_sampled_rods_match_live_oracle(dm):
+    """The 1024-rod batch in one launch (256 threads per rod, as timed), two midpoint steps;
+    the shortest rod and two seeded rods of at most 150 nodes against the oracle."""
+    from oracle import der
+    d = W.rod_batch(1024, steps=2)
+    ns = np.array([r["x0"].shape[0] for r in d["rods"]])
+    rng = np.random.Generator(np.random.PCG64(21))
+    pick = [int(np.argmin(ns))] + [int(i) for i in rng.choice(np.nonzero(ns <= 150)[0], 2, replace=False)]
+    say(f"case: 1024-rod batch, implicit midpoint, 2 steps; rods {pick} (N = {ns[pick].tolist()})")
+    sim = dm.sim_from_description(d, block_size=256)
+    sim.set_integrator("midpoint")
+    st = sim.step(d["dt"], 2)
+    assert (st["status"] == 0).all()
+    for r in pick:
+        _, ost, _, _ = der.simulate(W.subset(d, [r]), steps=2, polish=1, scheme="midpoint")
+        x, _, _, _ = sim.rod_state(r)
+        assert rel(x, ost.x.numpy()) < 1e-9, (r, rel(x, ost.x.numpy()))
+
+
+def test_bad_scheme_and_adjoint_under_midpoint_are_rejected(dm):
+    d = W.cantilever(steps=1)
+    sim = dm.sim_from_description(d)
+    with pytest.raises(ValueError):
+        sim.set_integrator("verlet")
+    assert dm.lib().dm_set_integrator(sim._h, 7) != 0
+    sim.set_integrator("midpoint")
+    with pytest.raises(dm.DmError):
+        sim.rollout(d["dt"], 2, 1)
+    sim.set_integrator("euler")
+    sim.step(d["dt"], 1)
