@@ -84,6 +84,8 @@ typedef struct {
   int floor_steps;        /* steps that ended by the stagnation rule, not newton_tol */
   int fallbacks;          /* warm-started steps whose Newton solve failed and was redone
                              from the step-start state (see dm_set_warm_start) */
+  int halvings;           /* (sub)steps whose Newton solve failed and were redone as two
+                             halves (see dm_set_adaptive) */
   double residual;        /* residual norm at the last Newton iterate */
 } dm_stats;
 
@@ -146,6 +148,16 @@ dm_status dm_step(dm_sim* sim, double dt, int nsteps, dm_stats* stats);
 #define DM_IMPLICIT_MIDPOINT 1
 dm_status dm_set_integrator(dm_sim* sim, int scheme);
 
+/* Adaptive time stepping of dm_step (offered as an option in the Time Stepping subsection; the
+ * rule is not given there).  With max_halvings = L > 0 a step whose Newton solve does not
+ * converge (or meets a zero pivot) is redone as two steps of half the size, each of them
+ * adaptive in the same way, down to dt / 2^L; a system only fails when a step of dt / 2^L
+ * fails, and then stays at the end of its last converged substep.  Substeps are counted in
+ * dm_stats.halvings; steps_done counts whole steps.  0 (default) turns it off; values outside
+ * 0..20 return DM_ERR_INVALID_ARG.  Applies to later calls; the adjoint (dm_rollout,
+ * dm_adjoint) returns DM_ERR_UNSUPPORTED while it is on. */
+dm_status dm_set_adaptive(dm_sim* sim, int max_halvings);
+
 /* Number of independent systems (connected rod sets) and the system holding a rod. */
 int dm_num_systems(const dm_sim* sim);
 int dm_rod_system(const dm_sim* sim, int rod);
@@ -196,8 +208,9 @@ dm_status dm_set_natural_curvature_all(dm_sim* sim, const double* kbar, int on_d
  * device).  It recomputes each checkpoint interval forward, then runs the implicit-function
  * adjoint of every step backward (transposed Newton system, step-start frames and natural
  * curvature differentiated exactly); the sim is back at the rollout's final state after the
- * call.  Both return DM_ERR_UNSUPPORTED for joined rods, floor contact, actuated rods or the
- * implicit-midpoint integrator, and DM_ERR_STATE if dm_adjoint has no completed rollout. */
+ * call.  Both return DM_ERR_UNSUPPORTED for joined rods, floor contact, actuated rods, the
+ * implicit-midpoint integrator or adaptive time stepping, and DM_ERR_STATE if dm_adjoint has
+ * no completed rollout. */
 dm_status dm_rollout(dm_sim* sim, double dt, int nsteps, int ckpt_every, double* tips, int on_device);
 dm_status dm_adjoint(dm_sim* sim, const double* dL_dtips, int in_on_device, double* dL_dkbar,
                      int out_on_device);

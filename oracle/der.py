@@ -22,6 +22,8 @@ What it computes, in the paper's order and notation (DisMech, Methodology):
   gravity and optional viscous damping (miscellaneous forces).
 * Backward Euler (Eq. 14-15) solved by Newton's method; the Jacobian (Eq. 16)
   is the automatic Jacobian of the residual.  Velocity update after Eq. 16.
+* Adaptive time stepping (named as an option in the same subsection): a step whose Newton
+  solve fails is covered by two half steps, recursively.
 * Implicit midpoint (named as the alternative implicit scheme in the time-stepping
   subsection, without formulas): the textbook rule for M qddot = F,
   q_{n+1} = q_n + dt (qdot_n + qdot_{n+1}) / 2 and M (qdot_{n+1} - qdot_n) = dt F(q_m)
@@ -576,6 +578,31 @@ def step(sys, st, dt, tol=1e-9, max_iter=50, kbar_rods=None, polish=0, q0=None, 
     if not info.converged:
         return st, info
     return commit(sys, st, q, dt), info
+
+
+def step_adaptive(sys, st, dt, tol=1e-9, max_iter=50, max_halvings=0, polish=0, line_search=False,
+                  scheme="euler"):
+    """One time step with adaptive step halving (the paper offers adaptive time stepping as an
+    option without stating a rule; this is the plain recursive one): try the step; if Newton
+    does not converge, cover the same interval by two steps of half the size, each of them
+    adaptive in the same way, down to dt / 2^max_halvings.  Returns the new state, whether it
+    succeeded, the Newton iterations spent (failed attempts included) and the halvings made."""
+    tot = {"iters": 0, "halvings": 0}
+
+    def advance(s, h, level):
+        s1, info = step(sys, s, h, tol, max_iter, polish=polish, line_search=line_search, scheme=scheme)
+        tot["iters"] += info.iters
+        if info.converged:
+            return s1, True
+        if level == max_halvings:
+            return s, False
+        tot["halvings"] += 1
+        sm, ok = advance(s, 0.5 * h, level + 1)
+        if not ok:
+            return s, False
+        return advance(sm, 0.5 * h, level + 1)
+    out, ok = advance(st, dt, 0)
+    return out, ok, tot["iters"], tot["halvings"]
 
 
 def simulate(desc, steps=None, rod_ids=None, tol=None, polish=0, record=False, line_search=None, scheme="euler"):

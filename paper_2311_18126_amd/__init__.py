@@ -36,7 +36,7 @@ class DmConfig(ctypes.Structure):
 
 class DmStats(ctypes.Structure):
     _fields_ = [("steps_done", c_int), ("newton_iters", c_int), ("status", c_int), ("floor_steps", c_int),
-                ("fallbacks", c_int), ("residual", c_double)]
+                ("fallbacks", c_int), ("halvings", c_int), ("residual", c_double)]
 
 
 _DP = POINTER(c_double)
@@ -88,6 +88,7 @@ _SIGS = {
     "dm_ws_targets": (c_int, [c_void_p, c_void_p, c_double, c_void_p]),
     "dm_set_warm_start": (c_int, [c_void_p, c_void_p, c_int]),
     "dm_set_integrator": (c_int, [c_void_p, c_int]),
+    "dm_set_adaptive": (c_int, [c_void_p, c_int]),
     "dm_ws_predict": (c_int, [c_void_p, c_double, c_void_p, c_int]),
     "dm_autotune": (c_int, [c_void_p, c_double, c_int, c_char_p, POINTER(c_int)]),
     "dm_time": (c_double, [c_void_p]),
@@ -228,9 +229,11 @@ class Sim:
             _check(s, "dm_step")
         self.last_status = s
         out = np.zeros(n, dtype=[("steps", np.int32), ("iters", np.int32), ("status", np.int32),
-                                 ("floor_steps", np.int32), ("fallbacks", np.int32), ("residual", np.float64)])
+                                 ("floor_steps", np.int32), ("fallbacks", np.int32), ("halvings", np.int32),
+                                 ("residual", np.float64)])
         for i in range(n):
             out[i] = (st[i].steps_done, st[i].newton_iters, st[i].status, st[i].floor_steps, st[i].fallbacks,
+                      st[i].halvings,
                       st[i].residual)
         return out
 
@@ -241,6 +244,11 @@ class Sim:
         if code is None:
             raise ValueError(f"unknown integrator {scheme!r}")
         _check(lib().dm_set_integrator(self._h, code), "dm_set_integrator")
+
+    def set_adaptive(self, max_halvings):
+        """Adaptive time stepping of step(): a step whose Newton solve fails is redone as two
+        half steps, recursively, at most max_halvings levels deep (0: off); see dm_set_adaptive."""
+        _check(lib().dm_set_adaptive(self._h, int(max_halvings)), "dm_set_adaptive")
 
     # -- state --------------------------------------------------------------
     @property

@@ -204,10 +204,10 @@ __device__ __forceinline__ void friction_ratio(double s, double K2, double* g, d
 
 // Node terms of the residual (Eq. 15) and Jacobian: inertia, gravity, constant load,
 // damping, floor contact (Eq. 10-11) and friction (Eq. 12-13).
-__device__ __forceinline__ void eval_node(const DmStepArgs DM_C& A, int n) {
+__device__ __forceinline__ void eval_node(const DmStepArgs DM_C& A, int n, double dt) {
   const DmDev DM_C& D = A.d;
   const int NN = D.n_nodes_tot;
-  const double dt = A.dt, m = D.mass[n];
+  const double m = D.mass[n];
   v3 x = ld3(D.x, NN, n), x0 = ld3(D.x0, NN, n), v = ld3(D.v, NN, n), F = ld3(D.force, NN, n);
   const double im = m / (dt * dt);
   double R[3], J[9];
@@ -293,8 +293,8 @@ __device__ __forceinline__ double stencil_row(const DmDev DM_C& D, int s, bool o
 // index) and kept or dropped by selection: the terms present depend only on where node k sits
 // in its chain and on whether the chain owns the node.
 template <int COMP, class Emit>
-__device__ __forceinline__ double row_contrib(const DmStepArgs DM_C& A, const DmChain& ch, int k, bool own,
-                                              Emit& emit) {
+__device__ __forceinline__ double row_contrib(const DmStepArgs DM_C& A, double dt, const DmChain& ch, int k,
+                                              bool own, Emit& emit) {
   const DmDev DM_C& D = A.d;
   const int NE = D.n_edges_tot, NN = D.n_nodes_tot;
   const int N = ch.n_nodes;
@@ -329,9 +329,9 @@ __device__ __forceinline__ double row_contrib(const DmStepArgs DM_C& A, const Dm
     Rr += stencil_row<COMP>(D, ch.st_off + k, sok(k + 1), 0, emit);
   } else {
     const int e = D.chain_edge[ch.edge_tab + k];
-    const double I = D.Ith[e] / (A.dt * A.dt);
+    const double I = D.Ith[e] / (dt * dt);
     emit(3, I);
-    Rr += I * (D.th[e] - D.th0[e] - A.dt * D.om[e]) - D.moment[e];
+    Rr += I * (D.th[e] - D.th0[e] - dt * D.om[e]) - D.moment[e];
     Rr += stencil_row<7>(D, ch.st_off + k - 1, sok(k), -4, emit);
     Rr += stencil_row<3>(D, ch.st_off + k, sok(k + 1), 0, emit);
   }
@@ -342,7 +342,7 @@ __device__ __forceinline__ double row_contrib(const DmStepArgs DM_C& A, const Dm
 // border columns of a border row (those couplings live in the dense border), are zeroed
 // afterwards.  fixmask / bmask: bit i describes chain DOF 4k - 12 + i.
 template <int COMP>
-__device__ __forceinline__ double band_row(const DmStepArgs DM_C& A, const DmChain& ch, int k,
+__device__ __forceinline__ double band_row(const DmStepArgs DM_C& A, double dt, const DmChain& ch, int k,
                                            unsigned fixmask, unsigned bmask, bool own) {
   const int r = 4 * k + COMP;
   const bool rowb = (bmask >> (12 + COMP)) & 1u;
@@ -351,7 +351,7 @@ __device__ __forceinline__ double band_row(const DmStepArgs DM_C& A, const DmCha
 #pragma unroll
   for (int o = 0; o < DM_NDIAG; ++o) acc[o] = 0.0;
   auto emit = [&](int rel, double v) { acc[rel - COMP + 10] += v; };
-  double Rr = row_contrib<COMP>(A, ch, k, own, emit);
+  double Rr = row_contrib<COMP>(A, dt, ch, k, own, emit);
   if (rowb && !rowfix) {
     // the border-block part of a border row goes to the dense border (assemble_border)
     double DM_G* bp = A.d.bpr + (size_t)(ch.bmap_off + r - ch.b_lo) * DM_NDIAG;
@@ -381,15 +381,15 @@ __device__ __forceinline__ double band_row(const DmStepArgs DM_C& A, const DmCha
 
 // Band rows of chain node k (4 rows; 3 for the last node).  Returns the squared residual of
 // its free, non-border rows.
-__device__ __forceinline__ double band_node(const DmStepArgs DM_C& A, int ci, int k) {
+__device__ __forceinline__ double band_node(const DmStepArgs DM_C& A, double dt, int ci, int k) {
   const DmDev DM_C& D = A.d;
   const DmChain ch = D.chain[ci];
   const uint4 m = *(const uint4 DM_C*)(D.nmask + 4 * (size_t)(ch.node_tab + k));
   const bool own = m.z & 1u;
-  double s = band_row<0>(A, ch, k, m.x, m.y, own);
-  s += band_row<1>(A, ch, k, m.x, m.y, own);
-  s += band_row<2>(A, ch, k, m.x, m.y, own);
-  if (k < ch.n_nodes - 1) s += band_row<3>(A, ch, k, m.x, m.y, own);
+  double s = band_row<0>(A, dt, ch, k, m.x, m.y, own);
+  s += band_row<1>(A, dt, ch, k, m.x, m.y, own);
+  s += band_row<2>(A, dt, ch, k, m.x, m.y, own);
+  if (k < ch.n_nodes - 1) s += band_row<3>(A, dt, ch, k, m.x, m.y, own);
   return s;
 }
 
@@ -418,16 +418,17 @@ __device__ __noinline__ void eval_stencils(ArgsP Ap, int sid, double t_end) {
   }
 }
 
-__device__ __noinline__ void eval_edges_nodes(ArgsP Ap, int sid) {
+// dt: the Newton step of the (sub)step being solved.
+__device__ __noinline__ void eval_edges_nodes(ArgsP Ap, int sid, double dt) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmSystem DM_C& S = A.d.sys[uniform(sid)];
   for (int i = threadIdx.x; i < S.n_edges; i += blockDim.x) eval_edge(A, S.edge0 + i);
-  for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x) eval_node(A, S.node0 + i);
+  for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x) eval_node(A, S.node0 + i, dt);
 }
 
 // Band rows of every chain node of the system; returns this lane's share of the squared
 // residual of free, non-border rows.
-__device__ __noinline__ double assemble_band(ArgsP Ap, int sid) {
+__device__ __noinline__ double assemble_band(ArgsP Ap, int sid, double dt) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmDev DM_C& D = A.d;
   const DmSystem DM_C& S = D.sys[uniform(sid)];
@@ -435,7 +436,7 @@ __device__ __noinline__ double assemble_band(ArgsP Ap, int sid) {
   for (int i = threadIdx.x; i < S.chain_nodes; i += blockDim.x) {
     int c = S.chain0, k = i;
     while (k >= D.chain[c].n_nodes) { k -= D.chain[c].n_nodes; ++c; }
-    r2 += band_node(A, c, k);
+    r2 += band_node(A, dt, c, k);
   }
   return r2;
 }
@@ -1054,7 +1055,8 @@ __device__ __noinline__ void rollback(ArgsP Ap, int sid) {
 }
 
 // Velocity update (after Eq. 16) and the step-end reference frames.
-__device__ __noinline__ void commit(ArgsP Ap, int sid) {
+// dt: the Newton step of the (sub)step just solved (half of it under midpoint).
+__device__ __noinline__ void commit(ArgsP Ap, int sid, double dt) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmDev DM_C& D = A.d;
   const DmSystem DM_C& S = D.sys[uniform(sid)];
@@ -1091,9 +1093,9 @@ __device__ __noinline__ void commit(ArgsP Ap, int sid) {
     v3 d1 = transport_perp(ld3(D.tref, NE, e), t, ld3(D.d1ref, NE, e));
     st3(D.tref, NE, e, t);
     st3(D.d1ref, NE, e, d1);
-    // backward Euler: (q_{n+1} - q_n) / dt; midpoint (A.dt = half the step):
+    // backward Euler: (q_{n+1} - q_n) / dt; midpoint (dt = half the step):
     // 2 (q_{n+1} - q_n) / step - qdot_n
-    const double om = (D.th[e] - D.th0[e]) / A.dt;
+    const double om = (D.th[e] - D.th0[e]) / dt;
     D.om[e] = A.midpoint ? om - D.om[e] : om;
     D.th0[e] = D.th[e];
   }
@@ -1101,7 +1103,7 @@ __device__ __noinline__ void commit(ArgsP Ap, int sid) {
     const int n = S.node0 + i;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      const double v0 = D.v[c * NN + n], v = (D.x[c * NN + n] - D.x0[c * NN + n]) / A.dt;
+      const double v0 = D.v[c * NN + n], v = (D.x[c * NN + n] - D.x0[c * NN + n]) / dt;
       D.vprev[c * NN + n] = v0;
       D.v[c * NN + n] = A.midpoint ? v - v0 : v;
       D.x0[c * NN + n] = D.x[c * NN + n];
@@ -1372,7 +1374,7 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
   unsigned short DM_L* hbuf = (unsigned short DM_L*)((char DM_L*)lds_raw + A.net_lds);   // network (warm == 2)
   const int tid = threadIdx.x, wave = tid >> 6, nwaves = blockDim.x >> 6;
   if (tid == 0) flags[0] = 0;
-  int status = DM_STATUS_OK, iters = 0, steps = 0, floor_hits = 0, fallbacks = 0;
+  int status = DM_STATUS_OK, iters = 0, steps = 0, floor_hits = 0, fallbacks = 0, halved = 0;
   double res = 0.0;
   double t = D.time[sid];
   // accumulating launches (one step each) leave a system alone once it has failed
@@ -1380,82 +1382,106 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
   __syncthreads();
   DM_T0();
   for (int step = 0; step < nsteps; ++step) {
-    const double t_end = t + A.dt;
-    bool conv = false;
-    int newton = 0;
-    if (A.warm) {
-      warm_guess(Ap, sid, hbuf, nullptr);
-      __syncthreads();
-    }
-    // attempt 0 starts from the current positions (the step start, or a warm-start guess);
-    // with a warm start, a failed attempt is repeated from the step start
-    for (int attempt = 0; attempt < (A.warm ? 2 : 1) && !conv; ++attempt) {
-      if (attempt == 1) {
-        rollback(Ap, sid);
-        if (tid == 0) flags[0] = 0;
-        ++fallbacks;
+    // adaptive halving: substep (lev, idx) covers [idx, idx + 1) dt / 2^lev of the step; a
+    // substep whose Newton solve fails is covered by its two halves, down to level
+    // A.max_halvings; after a converged substep the next is the following sibling in that
+    // binary tree (a right child completes its parent)
+    int lev = 0, idx = 0;
+    bool failed = false;
+    while (true) {
+      const double hn = ldexp(A.dt, -lev);        // the substep's Newton step
+      const double t_end = t + hn;
+      bool conv = false;
+      int newton = 0;
+      if (A.warm) {
+        warm_guess(Ap, sid, hbuf, nullptr, hn);
         __syncthreads();
       }
-      int it = 0, halvings = 0;
-      double alpha = 1.0, res_prev = 0.0;
-      while (true) {
-        eval_stencils(Ap, sid, t_end);
-        eval_edges_nodes(Ap, sid);
-        __syncthreads();
-        DM_TP(0);
-        double r2 = assemble_band(Ap, sid);
-        __syncthreads();
-        DM_TP(1);
-        r2 += assemble_border(Ap, sid, Bt, ld);
-        res = sqrt(block_sum(r2, red));
-        DM_TP(2);
-        if (res > A.tol && it > 0 && res_prev <= A.stag_tol && res > 0.5 * res_prev) {
-          conv = true;    // stagnation at the FP64 rounding floor of the residual
-          ++floor_hits;
-          break;
+      // attempt 0 starts from the current positions (the substep start, or a warm-start
+      // guess); with a warm start, a failed attempt is repeated from the substep start
+      for (int attempt = 0; attempt < (A.warm ? 2 : 1) && !conv; ++attempt) {
+        if (attempt == 1) {
+          rollback(Ap, sid);
+          if (tid == 0) flags[0] = 0;
+          ++fallbacks;
+          __syncthreads();
         }
-        if (A.line_search && it > 0 && res >= res_prev && halvings < 10) {
-          apply_update(Ap, sid, xB, -0.5 * alpha);      // back off to half of the current step
-          alpha *= 0.5;
-          ++halvings;
+        int it = 0, halvings = 0;
+        double alpha = 1.0, res_prev = 0.0;
+        while (true) {
+          eval_stencils(Ap, sid, t_end);
+          eval_edges_nodes(Ap, sid, hn);
+          __syncthreads();
+          DM_TP(0);
+          double r2 = assemble_band(Ap, sid, hn);
+          __syncthreads();
+          DM_TP(1);
+          r2 += assemble_border(Ap, sid, Bt, ld);
+          res = sqrt(block_sum(r2, red));
+          DM_TP(2);
+          if (res > A.tol && it > 0 && res_prev <= A.stag_tol && res > 0.5 * res_prev) {
+            conv = true;    // stagnation at the FP64 rounding floor of the residual
+            ++floor_hits;
+            break;
+          }
+          if (A.line_search && it > 0 && res >= res_prev && halvings < 10) {
+            apply_update(Ap, sid, xB, -0.5 * alpha);      // back off to half of the current step
+            alpha *= 0.5;
+            ++halvings;
+            __syncthreads();
+            continue;
+          }
+          if (res <= A.tol) { conv = true; break; }
+          if (it >= (A.warm && attempt == 0 ? A.warm_max_iter : A.max_iter) || !isfinite(res)) break;
+          res_prev = res;
+          alpha = 1.0;
+          halvings = 0;
+          // the arm sweeps, the border solve and the back-substitutions are serial chains on
+          // the critical path of the system: their wavefronts take issue priority over the
+          // other workgroups' element and assembly work sharing the SIMDs
+          __builtin_amdgcn_s_setprio(3);
+          sweep_all(Ap, S, wave, nwaves, deltas, flags);
+          __syncthreads();
+          DM_TP(3);
+          border_solve(Ap, sid, Bt, ld, deltas, xB, red + 34, flags);
+          DM_TP(4);
+          backsub_all(Ap, S, wave, nwaves, xB);
+          __builtin_amdgcn_s_setprio(0);
+          __syncthreads();
+          DM_TP(5);
+          if (flags[0]) break;
+          apply_update(Ap, sid, xB, 1.0);
+          ++it;
+          ++newton;
+          __syncthreads();
+          DM_TP(6);
+        }
+      }
+      iters += newton;
+      if (!conv) {
+        const bool singular = flags[0] != 0;
+        rollback(Ap, sid);
+        if (lev < A.max_halvings) {
+          ++lev;
+          idx *= 2;
+          ++halved;
+          if (tid == 0) flags[0] = 0;
           __syncthreads();
           continue;
         }
-        if (res <= A.tol) { conv = true; break; }
-        if (it >= (A.warm && attempt == 0 ? A.warm_max_iter : A.max_iter) || !isfinite(res)) break;
-        res_prev = res;
-        alpha = 1.0;
-        halvings = 0;
-        // the arm sweeps, the border solve and the back-substitutions are serial chains on the
-        // critical path of the system: their wavefronts take issue priority over the other
-        // workgroups' element and assembly work sharing the SIMDs
-        __builtin_amdgcn_s_setprio(3);
-        sweep_all(Ap, S, wave, nwaves, deltas, flags);
-        __syncthreads();
-        DM_TP(3);
-        border_solve(Ap, sid, Bt, ld, deltas, xB, red + 34, flags);
-        DM_TP(4);
-        backsub_all(Ap, S, wave, nwaves, xB);
-        __builtin_amdgcn_s_setprio(0);
-        __syncthreads();
-        DM_TP(5);
-        if (flags[0]) break;
-        apply_update(Ap, sid, xB, 1.0);
-        ++it;
-        ++newton;
-        __syncthreads();
-        DM_TP(6);
+        // the system stays at the end of its last converged substep
+        status = singular ? DM_STATUS_SINGULAR : DM_STATUS_NOT_CONVERGED;
+        failed = true;
+        break;
       }
+      commit(Ap, sid, hn);
+      DM_TP(7);
+      t += A.midpoint ? 2.0 * hn : hn;
+      while (lev > 0 && (idx & 1)) { --lev; idx >>= 1; }
+      if (lev == 0) break;
+      ++idx;
     }
-    iters += newton;
-    if (!conv) {
-      status = flags[0] ? DM_STATUS_SINGULAR : DM_STATUS_NOT_CONVERGED;
-      rollback(Ap, sid);
-      break;
-    }
-    commit(Ap, sid);
-    DM_TP(7);
-    t += A.midpoint ? 2.0 * A.dt : A.dt;
+    if (failed) break;
     ++steps;
   }
   DM_TSAVE(sid);
@@ -1468,11 +1494,13 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
       D.s_iters[sid] += iters;
       D.s_floor[sid] += floor_hits;
       D.s_fallback[sid] += fallbacks;
+      D.s_halved[sid] += halved;
     } else {
       D.s_steps[sid] = steps;
       D.s_iters[sid] = iters;
       D.s_floor[sid] = floor_hits;
       D.s_fallback[sid] = fallbacks;
+      D.s_halved[sid] = halved;
     }
   }
 }
@@ -1488,7 +1516,7 @@ __global__ void __launch_bounds__(512) dm_predict_kernel(DmStepArgs, double* out
   extern __shared__ double lds_raw[];
   const ArgsP Ap = (ArgsP)__builtin_amdgcn_kernarg_segment_ptr();
   unsigned short DM_L* hbuf = (unsigned short DM_L*)((char DM_L*)lds_raw + Ap->net_lds);
-  warm_guess(Ap, blockIdx.x, hbuf, (double DM_G*)out);
+  warm_guess(Ap, blockIdx.x, hbuf, (double DM_G*)out, Ap->dt);
 }
 
 extern "C" hipError_t dm_launch_predict(const DmStepArgs* args, int block, size_t lds_bytes, double* out,
@@ -1523,9 +1551,9 @@ __global__ void __launch_bounds__(512) dm_adjoint_kernel(DmAdjArgs) {
     __syncthreads();
     adj_commit_vjp(Pp, sid, P.a.step0 + i);
     eval_stencils(Ap, sid, 0.0);
-    eval_edges_nodes(Ap, sid);
+    eval_edges_nodes(Ap, sid, A.dt);
     __syncthreads();
-    assemble_band(Ap, sid);
+    assemble_band(Ap, sid, A.dt);
     __syncthreads();
     assemble_border(Ap, sid, Bt, ld);
     __syncthreads();

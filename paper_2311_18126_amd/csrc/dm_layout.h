@@ -152,6 +152,7 @@ struct DmDev {
   // statistics
   int DM_G* s_steps; int DM_G* s_iters; int DM_G* s_status; double DM_G* s_res; int DM_G* s_floor;
   int DM_G* s_fallback;  // warm-started attempts that had to restart from the step start
+  int DM_G* s_halved;    // substeps whose failed Newton solve was redone as two halves
   double DM_G* dbg;     // [n_systems][8] phase timers in diagnosis builds; null otherwise
   int n_nodes_tot, n_edges_tot, n_st_tot;
 };
@@ -190,6 +191,8 @@ struct DmStepArgs {
   int net_lds;     // byte offset of the network's LDS activations (warm == 2)
   int midpoint;    // 1: implicit midpoint; dt is then half the time step (the Newton solve is
                    // backward Euler to the midpoint) and the commit extrapolates to the step end
+  int max_halvings;  // adaptive time stepping: a failed (sub)step is redone as two halves, at
+                     // most this many levels deep (0: off)
   int n_systems;
   int max_nb, max_arms;
 };

@@ -111,7 +111,8 @@ struct dm_sim {
   double* ws_F = nullptr; size_t ws_F_n = 0;
   dm_mlp* ws_net = nullptr;
   int ws_mode = 0;
-  int scheme = DM_BACKWARD_EULER;   // time integrator of dm_step and dm_rollout
+  int scheme = DM_BACKWARD_EULER;   // time integrator of dm_step
+  int max_halvings = 0;             // adaptive step halving depth of dm_step (0: off)
   // captured step sequences of trajectory segments (dm_rollout, the adjoint's recomputation)
   hipStream_t cap_stream = nullptr;
   std::vector<SegGraph> seg_graphs;
@@ -667,6 +668,7 @@ dm_status do_finalize(dm_sim* s) {
   if ((st = alloc(s, (size_t)s->n_sys, &D.s_res)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)s->n_sys, &D.s_floor)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)s->n_sys, &D.s_fallback)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)s->n_sys, &D.s_halved)) != DM_OK) return st;
   {
     // warm-start feature rows: one per chain node
     std::vector<int> cnc(chain_node.size());
@@ -723,6 +725,7 @@ void fill_step_args(const dm_sim* s, double dt, int nsteps, DmStepArgs& A) {
   std::memset(&A, 0, sizeof(A));       // padding too: captured segments are keyed by these bytes
   A.d = s->dev;
   A.midpoint = s->scheme == DM_IMPLICIT_MIDPOINT;
+  A.max_halvings = s->max_halvings;
   A.dt = A.midpoint ? 0.5 * dt : dt;
   A.tol = s->cfg.newton_tol;
   A.stag_tol = s->cfg.stagnation_tol;
@@ -888,7 +891,8 @@ dm_status run_segment(dm_sim* s, double dt, int len, double* tips, double* state
 
 // Zero the per-system statistics (before accumulating launches).
 dm_status zero_stats(dm_sim* s) {
-  for (int* p : {s->dev.s_steps, s->dev.s_iters, s->dev.s_status, s->dev.s_floor, s->dev.s_fallback})
+  for (int* p : {s->dev.s_steps, s->dev.s_iters, s->dev.s_status, s->dev.s_floor, s->dev.s_fallback,
+                 s->dev.s_halved})
     DM_HIP(hipMemsetAsync(p, 0, sizeof(int) * s->n_sys, s->stream));
   return DM_OK;
 }
@@ -910,6 +914,7 @@ dm_status worst_status(dm_sim* s) {
 // The adjoint covers independent rods without contact or time-dependent actuation.
 dm_status adjoint_supported(const dm_sim* s) {
   if (s->scheme != DM_BACKWARD_EULER) return fail(DM_ERR_UNSUPPORTED, "adjoint: only the backward-Euler step");
+  if (s->max_halvings != 0) return fail(DM_ERR_UNSUPPORTED, "adjoint: adaptive time stepping is not supported");
   if (s->cfg.floor_contact) return fail(DM_ERR_UNSUPPORTED, "adjoint: floor contact is not supported");
   for (const DmSystem& S : s->sys)
     if (S.n_chains != 1 || S.n_jst != 0) return fail(DM_ERR_UNSUPPORTED, "adjoint: joined rods are not supported");
@@ -1087,8 +1092,10 @@ dm_status dm_step(dm_sim* s, double dt, int nsteps, dm_stats* stats) {
   DM_HIP(hipEventRecord(s->ev1, s->stream));
   DM_HIP(hipStreamSynchronize(s->stream));
   DM_HIP(hipEventElapsedTime(&s->last_kernel_ms, s->ev0, s->ev1));
-  std::vector<int> steps(s->n_sys), iters(s->n_sys), status(s->n_sys), floors(s->n_sys), falls(s->n_sys);
+  std::vector<int> steps(s->n_sys), iters(s->n_sys), status(s->n_sys), floors(s->n_sys), falls(s->n_sys),
+      halved(s->n_sys);
   DM_HIP(hipMemcpy(falls.data(), s->dev.s_fallback, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
+  DM_HIP(hipMemcpy(halved.data(), s->dev.s_halved, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
   std::vector<double> res(s->n_sys);
   DM_HIP(hipMemcpy(steps.data(), s->dev.s_steps, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
   DM_HIP(hipMemcpy(iters.data(), s->dev.s_iters, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
@@ -1100,6 +1107,7 @@ dm_status dm_step(dm_sim* s, double dt, int nsteps, dm_stats* stats) {
     if (stats) {
       stats[i].steps_done = steps[i]; stats[i].newton_iters = iters[i]; stats[i].status = status[i];
       stats[i].floor_steps = floors[i]; stats[i].residual = res[i]; stats[i].fallbacks = falls[i];
+      stats[i].halvings = halved[i];
     }
     if (status[i] == DM_ERR_SINGULAR) worst = DM_ERR_SINGULAR;
     else if (status[i] == DM_NOT_CONVERGED && worst == DM_OK) worst = DM_NOT_CONVERGED;
@@ -1165,6 +1173,14 @@ dm_status dm_set_integrator(dm_sim* s, int scheme) {
   if (scheme != DM_BACKWARD_EULER && scheme != DM_IMPLICIT_MIDPOINT)
     return fail(DM_ERR_INVALID_ARG, "dm_set_integrator: unknown scheme " + std::to_string(scheme));
   s->scheme = scheme;
+  return DM_OK;
+}
+
+dm_status dm_set_adaptive(dm_sim* s, int max_halvings) {
+  if (!s) return fail(DM_ERR_INVALID_ARG, "dm_set_adaptive: null sim");
+  if (max_halvings < 0 || max_halvings > 20)
+    return fail(DM_ERR_INVALID_ARG, "dm_set_adaptive: max_halvings must be 0..20");
+  s->max_halvings = max_halvings;
   return DM_OK;
 }
 

@@ -48,14 +48,15 @@ __device__ __forceinline__ void row_features(const DmDev DM_C& D, const DmChain&
   }
 }
 
-// Displacement component q of node k of chain ch without the network: dt v_n (+ dt a_n).
-__device__ __forceinline__ double base_guess(const DmStepArgs DM_C& A, const DmChain& ch, int k, int q) {
+// Displacement component q of node k of chain ch without the network: dt v_n (+ dt a_n), dt the
+// Newton step of the (sub)step.
+__device__ __forceinline__ double base_guess(const DmStepArgs DM_C& A, double dt, const DmChain& ch, int k, int q) {
   const DmDev DM_C& D = A.d;
   const int NN = D.n_nodes_tot;
   const int n0 = D.chain_node[ch.node_tab + k];
   const double v = D.v[q * NN + n0];
-  double d = A.dt * v;
-  if (A.warm >= 2) d += A.dt * (v - D.vprev[q * NN + n0]);
+  double d = dt * v;
+  if (A.warm >= 2) d += dt * (v - D.vprev[q * NN + n0]);
   return d;
 }
 
@@ -138,7 +139,7 @@ __device__ __forceinline__ void layer2_step(dm_f32x4 (&acc)[DM_NET_RT][4], const
 // are dealt to the first DM_NET_WAVES wavefronts; each output accumulates over the reduction
 // index in ascending order, one matrix-core chain per tile, as in the batch kernels.
 // LDS: P holds layer 1's activations, Q the inputs and then layer 2's activations.
-__device__ __forceinline__ void network_block(const DmStepArgs DM_C& A, const DmSystem DM_C& S, int row0,
+__device__ __forceinline__ void network_block(const DmStepArgs DM_C& A, double dt, const DmSystem DM_C& S, int row0,
                                               unsigned short DM_L* P, unsigned short DM_L* Q, double DM_G* out) {
   const DmDev DM_C& D = A.d;
   const DmNetView DM_C& W = A.net;
@@ -212,7 +213,7 @@ __device__ __forceinline__ void network_block(const DmStepArgs DM_C& A, const Dm
             system_row(D, S, i, c, k);
             const DmChain ch = D.chain[c];
             const float yv = y[j] + bb;
-            put_guess(A, ch, k, lr, base_guess(A, ch, k, lr) + sc * (double)yv, out);
+            put_guess(A, ch, k, lr, base_guess(A, dt, ch, k, lr) + sc * (double)yv, out);
           }
         }
       }
@@ -223,20 +224,20 @@ __device__ __forceinline__ void network_block(const DmStepArgs DM_C& A, const Dm
 // Step-start guess of system sid for the current warm mode (no-op for mode 0).  net: the
 // network's LDS activations (two buffers of 16 DM_NET_RT rows).  out == null: written to the positions;
 // else every row's displacement goes to out[row][3] and the positions stay.
-__device__ __noinline__ void warm_guess(ArgsP Ap, int sid, unsigned short DM_L* net, double DM_G* out) {
+__device__ __noinline__ void warm_guess(ArgsP Ap, int sid, unsigned short DM_L* net, double DM_G* out, double dt) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmDev DM_C& D = A.d;
   const DmSystem DM_C& S = D.sys[uniform(sid)];
   if (A.warm == 2) {
     for (int row0 = 0; row0 < S.chain_nodes; row0 += 16 * DM_NET_RT)
-      network_block(A, S, row0, net, net + 16 * DM_NET_RT * DM_NET_LDS_ROW, out);
+      network_block(A, dt, S, row0, net, net + 16 * DM_NET_RT * DM_NET_LDS_ROW, out);
   } else if (A.warm != 0) {
     for (int i = threadIdx.x; i < S.chain_nodes; i += blockDim.x) {
       int c, k;
       system_row(D, S, i, c, k);
       const DmChain ch = D.chain[c];
 #pragma unroll
-      for (int q = 0; q < 3; ++q) put_guess(A, ch, k, q, base_guess(A, ch, k, q), out);
+      for (int q = 0; q < 3; ++q) put_guess(A, ch, k, q, base_guess(A, dt, ch, k, q), out);
     }
   }
 }
