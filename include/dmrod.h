@@ -215,6 +215,22 @@ dm_status dm_rollout(dm_sim* sim, double dt, int nsteps, int ckpt_every, double*
 dm_status dm_adjoint(dm_sim* sim, const double* dL_dtips, int in_on_device, double* dL_dkbar,
                      int out_on_device);
 
+/* Gradient descent on the natural curvature in the control flow of the Real2Sim algorithm
+ * (Alg. 1): per iterate, the sim is reset to its state at the call, the curvature set, the
+ * trajectory rolled out (dm_rollout with dt, nsteps, ckpt_every) and the loss
+ * L = sum |tip - target|^2 formed on the device; the loop stops when L < tol or after max_iter
+ * gradient steps; the step size (alpha0 at first) is halved whenever L rose since the previous
+ * iterate; the step is kbar <- kbar - alpha dL/dkbar (Eq. 21) with the gradient from dm_adjoint
+ * in place of the forward differences of Eq. 20.  target_tips: [nsteps][n_rods][3] (host or
+ * device).  kbar: in the start value, out the fitted one, layout of
+ * dm_set_natural_curvature_all (host or device).  losses: NULL or host array of max_iter + 1
+ * receiving the loss of every evaluated iterate; n_eval: NULL or their count.  On return the
+ * sim holds its starting state and the fitted curvature.  Same restrictions as dm_adjoint;
+ * bad step size, tolerance or counts return DM_ERR_INVALID_ARG. */
+dm_status dm_fit_natural_curvature(dm_sim* sim, double dt, int nsteps, int ckpt_every, const double* target_tips,
+                                   int target_on_device, double alpha0, double tol, int max_iter, double* kbar,
+                                   int kbar_on_device, double* losses, int* n_eval);
+
 /* ---- Learned warm start of the Newton solve ----------------------------------------------
  * Not part of the paper's method: a small network predicts each node's displacement over a
  * step and the prediction is Newton's initial guess (Eq. 16 is still iterated to newton_tol,

@@ -131,3 +131,28 @@ def loss_and_grad(desc, kbar, target_tips, steps=None, polish=2):
     sys, states, tips = rollout(desc, kbar, steps, polish=polish)
     L, dL = tip_loss(tips, torch.as_tensor(target_tips, dtype=der.DT))
     return L, adjoint(sys, states, kbar, desc["dt"], dL), tips
+
+
+def fit_natural_curvature(desc, target_tips, kbar0, alpha0, tol, max_iter, polish=2):
+    """Gradient descent on the natural curvature in the control flow of the paper's Real2Sim
+    algorithm (Alg. 1): evaluate the loss of the current kbar; stop below tol; halve the step
+    size when the loss rose since the previous iterate; step kbar <- kbar - alpha grad
+    (Eq. 21), the gradient here being the discrete adjoint of the tip loss instead of the
+    forward differences of Eq. 20.  At most max_iter gradient steps.  Returns the kbar after
+    every step (first entry kbar0), the loss of every evaluated iterate and the step size of
+    every step."""
+    kbar = [torch.as_tensor(k, dtype=der.DT).clone() for k in kbar0]
+    alpha, prev = alpha0, float("inf")
+    ks, losses, alphas = [[k.clone() for k in kbar]], [], []
+    for _ in range(max_iter + 1):
+        L, g, _ = loss_and_grad(desc, kbar, target_tips, polish=polish)
+        losses.append(L)
+        if L < tol or len(losses) == max_iter + 1:
+            break
+        if L > prev:
+            alpha *= 0.5
+        prev = L
+        kbar = [k - alpha * gi for k, gi in zip(kbar, g)]
+        ks.append([k.clone() for k in kbar])
+        alphas.append(alpha)
+    return ks, losses, alphas

@@ -71,6 +71,8 @@ _SIGS = {
     "dm_set_natural_curvature_all": (c_int, [c_void_p, c_void_p, c_int]),
     "dm_rollout": (c_int, [c_void_p, c_double, c_int, c_int, c_void_p, c_int]),
     "dm_adjoint": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int]),
+    "dm_fit_natural_curvature": (c_int, [c_void_p, c_double, c_int, c_int, c_void_p, c_int, c_double, c_double,
+                                         c_int, c_void_p, c_int, _DP, POINTER(c_int)]),
     "dm_mlp_num_params": (c_size_t, []),
     "dm_mlp_create": (c_int, [c_int, c_void_p, c_int, POINTER(c_void_p)]),
     "dm_mlp_set_params": (c_int, [c_void_p, c_void_p, c_int]),
@@ -422,6 +424,20 @@ class Sim:
         res = np.zeros(self.kbar_size)
         _check(lib().dm_adjoint(self._h, src, on_dev, res.ctypes.data, 0), "dm_adjoint")
         return res
+
+    def fit_natural_curvature(self, dt, nsteps, target_tips, kbar0=None, alpha0=0.1, tol=0.0, max_iter=10,
+                              ckpt_every=20):
+        """Real2Sim-style gradient descent (dm_fit_natural_curvature): returns the fitted
+        concatenated natural curvature and the loss of every evaluated iterate (host arrays)."""
+        tgt = _f64(target_tips)
+        kb = np.zeros(self.kbar_size) if kbar0 is None else _f64(kbar0).copy()
+        losses = np.zeros(max_iter + 1)
+        n = ctypes.c_int(0)
+        _check(lib().dm_fit_natural_curvature(self._h, float(dt), int(nsteps), int(ckpt_every), tgt.ctypes.data, 0,
+                                              float(alpha0), float(tol), int(max_iter), kb.ctypes.data, 0,
+                                              losses.ctypes.data_as(_DP), ctypes.byref(n)),
+               "dm_fit_natural_curvature")
+        return kb, losses[:n.value]
 
     @property
     def time(self):

@@ -1586,6 +1586,44 @@ extern "C" hipError_t dm_launch_adjoint(const DmAdjArgs* args, int block, size_t
   return hipGetLastError();
 }
 
+// Tip loss of one fitting iterate: loss = sum over the n entries of (tips - target)^2 and
+// dL = 2 (tips - target); one 1024-thread workgroup, summed in a fixed order.
+__global__ void __launch_bounds__(1024) dm_fit_loss_kernel(const double* tips, const double* target, int n,
+                                                          double* dL, double* loss) {
+  __shared__ double part[1024];
+  double sum = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const double d = tips[i] - target[i];
+    dL[i] = 2.0 * d;
+    sum = fma(d, d, sum);
+  }
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = part[0];
+}
+
+// y <- y + a x over n entries.
+__global__ void dm_axpy_kernel(double* y, const double* x, double a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = fma(a, x[i], y[i]);
+}
+
+extern "C" hipError_t dm_launch_fit_loss(const double* tips, const double* target, int n, double* dL, double* loss,
+                                         hipStream_t stream) {
+  hipLaunchKernelGGL(dm_fit_loss_kernel, dim3(1), dim3(1024), 0, stream, tips, target, n, dL, loss);
+  return hipGetLastError();
+}
+
+extern "C" hipError_t dm_launch_axpy(double* y, const double* x, double a, int n, hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dm_axpy_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, y, x, a, n);
+  return hipGetLastError();
+}
+
 extern "C" hipError_t dm_launch_gather_tips(const double* x, int nn, const int* tip, int n, double* out,
                                             hipStream_t stream) {
   if (n <= 0) return hipSuccess;

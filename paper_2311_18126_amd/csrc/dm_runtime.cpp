@@ -12,6 +12,7 @@
 #include <cstring>
 #include <map>
 #include <numeric>
+#include <limits>
 #include <string>
 #include <type_traits>
 #include <fstream>
@@ -25,6 +26,9 @@ extern "C" hipError_t dm_launch_step(const DmStepArgs* args, int block, size_t l
 extern "C" hipError_t dm_launch_adjoint(const DmAdjArgs* args, int block, size_t lds_bytes, hipStream_t stream);
 extern "C" hipError_t dm_launch_gather_tips(const double* x, int nn, const int* tip, int n, double* out,
                                             hipStream_t stream);
+extern "C" hipError_t dm_launch_fit_loss(const double* tips, const double* target, int n, double* dL, double* loss,
+                                         hipStream_t stream);
+extern "C" hipError_t dm_launch_axpy(double* y, const double* x, double a, int n, hipStream_t stream);
 extern "C" hipError_t dm_launch_predict(const DmStepArgs* args, int block, size_t lds_bytes, double* out,
                                         hipStream_t stream);
 extern "C" hipError_t dm_ws_launch_features(const DmDev* D, int rows, const int* cn_chain, const double* nconst,
@@ -1350,6 +1354,61 @@ dm_status dm_adjoint(dm_sim* s, const double* dL_dtips, int in_on_device, double
   } else {
     std::copy(out.begin(), out.end(), dL_dkbar);
   }
+  return DM_OK;
+}
+
+dm_status dm_fit_natural_curvature(dm_sim* s, double dt, int nsteps, int ckpt_every, const double* target_tips,
+                                   int target_on_device, double alpha0, double tol, int max_iter, double* kbar,
+                                   int kbar_on_device, double* losses, int* n_eval) {
+  if (!s || !target_tips || !kbar) return fail(DM_ERR_INVALID_ARG, "dm_fit_natural_curvature: null argument");
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_fit_natural_curvature before dm_finalize");
+  if (!(alpha0 > 0) || !std::isfinite(alpha0) || !(tol >= 0) || max_iter < 0 || nsteps <= 0 || ckpt_every <= 0)
+    return fail(DM_ERR_INVALID_ARG, "dm_fit_natural_curvature: bad alpha0, tol, max_iter, nsteps or ckpt_every");
+  dm_status st;
+  if ((st = adjoint_supported(s)) != DM_OK) return st;
+  DM_HIP(hipSetDevice(s->cfg.device));
+  const size_t nk = kbar_total(s), nt = (size_t)nsteps * s->rods.size() * 3, nc = dm_checkpoint_size(s);
+  // device work buffers of this call: kbar, its gradient, tips, target, dL/dtips, loss, start state
+  std::vector<double*> bufs;
+  struct Guard { std::vector<double*>& b; ~Guard() { for (double* p : b) (void)hipFree(p); } } guard{bufs};
+  auto get = [&](size_t n, double** p) -> dm_status {
+    if (hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(double)) != hipSuccess)
+      return fail(DM_ERR_OOM, "dm_fit_natural_curvature: hipMalloc failed");
+    bufs.push_back(*p);
+    return DM_OK;
+  };
+  double *kb, *g, *tips, *tgt, *dl, *loss, *ck0;
+  for (auto pr : {std::make_pair(nk, &kb), std::make_pair(nk, &g), std::make_pair(nt, &tips), std::make_pair(nt, &tgt),
+                  std::make_pair(nt, &dl), std::make_pair((size_t)1, &loss), std::make_pair(nc, &ck0)})
+    if ((st = get(pr.first, pr.second)) != DM_OK) return st;
+  DM_HIP(hipMemcpy(kb, kbar, nk * sizeof(double), kbar_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+  DM_HIP(hipMemcpy(tgt, target_tips, nt * sizeof(double),
+                   target_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice));
+  if ((st = dm_save_checkpoint(s, ck0, 1)) != DM_OK) return st;
+  double alpha = alpha0, prev = std::numeric_limits<double>::infinity();
+  int evals = 0;
+  for (int it = 0; it <= max_iter; ++it) {
+    if ((st = dm_load_checkpoint(s, ck0, 1)) != DM_OK) return st;
+    if ((st = dm_set_natural_curvature_all(s, kb, 1)) != DM_OK) return st;
+    if ((st = dm_rollout(s, dt, nsteps, ckpt_every, tips, 1)) != DM_OK) return st;
+    DM_HIP(dm_launch_fit_loss(tips, tgt, (int)nt, dl, loss, s->stream));
+    double L = 0.0;
+    DM_HIP(hipMemcpyAsync(&L, loss, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    DM_HIP(hipStreamSynchronize(s->stream));
+    if (losses) losses[evals] = L;
+    ++evals;
+    if (L < tol || it == max_iter) break;
+    if (L > prev) alpha *= 0.5;
+    prev = L;
+    if ((st = dm_adjoint(s, dl, 1, g, 1)) != DM_OK) return st;
+    DM_HIP(dm_launch_axpy(kb, g, -alpha, (int)nk, s->stream));
+  }
+  // the sim ends at its starting state with the fitted natural curvature
+  if ((st = dm_load_checkpoint(s, ck0, 1)) != DM_OK) return st;
+  if ((st = dm_set_natural_curvature_all(s, kb, 1)) != DM_OK) return st;
+  DM_HIP(hipStreamSynchronize(s->stream));
+  DM_HIP(hipMemcpy(kbar, kb, nk * sizeof(double), kbar_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+  if (n_eval) *n_eval = evals;
   return DM_OK;
 }
 

@@ -122,9 +122,26 @@ def golden_adjoint():
     return out
 
 
+# Real2Sim-style fit (Alg. 1 control flow, adjoint gradient) on the adjoint case, from zero
+# natural curvature; step size 5e4 (the loss is in m^2, its gradient ~1e-5 per 1/m)
+FIT_ALPHA, FIT_ITERS = 5e4, 4
+
+
+def golden_fit():
+    d, kstar = adjoint_case()
+    _, _, target = AD.rollout(d, kstar)
+    k0 = [np.zeros((ADJ_NODES - 2, 2)) for _ in range(ADJ_RODS)]
+    ks, losses, alphas = AD.fit_natural_curvature(d, target.numpy(), k0, FIT_ALPHA, 1e-12, FIT_ITERS)
+    out = {"target_tips": target.numpy(), "losses": np.array(losses), "alphas": np.array(alphas),
+           "alpha": np.array(FIT_ALPHA), "iters": np.array(FIT_ITERS)}
+    for i, k in enumerate(ks):
+        out[f"kbar_{i}"] = np.stack([ki.numpy() for ki in k])
+    return out
+
+
 GOLDEN = {"cantilever": golden_cantilever, "batch": golden_batch, "helix": golden_helix, "star": golden_star,
           "adjoint": golden_adjoint, "cantilever_midpoint": golden_cantilever_midpoint,
-          "star_midpoint": golden_star_midpoint}
+          "star_midpoint": golden_star_midpoint, "fit": golden_fit}
 
 
 if __name__ == "__main__":

@@ -66,3 +66,26 @@ def test_adjoint_gradient_vanishes_at_the_target():
     L, g, _ = AD.loss_and_grad(d, ks, tgt)
     assert L == 0.0
     assert float(g[0].abs().max()) == 0.0
+
+
+# ---------------------------------------------------------------------------
+# Real2Sim-style fit (Alg. 1 control flow with the adjoint gradient)
+# ---------------------------------------------------------------------------
+
+def test_fit_stops_at_once_on_the_target_and_halves_the_step_after_a_rise():
+    d, kstar = W.adjoint_rods(n_rods=1, n_nodes=8, steps=6)
+    _, _, target = AD.rollout(d, [kstar[0]])
+    ks, losses, alphas = AD.fit_natural_curvature(d, target.numpy(), [kstar[0]], 1.0, 1e-20, 5)
+    assert losses == [0.0] and alphas == [] and len(ks) == 1
+    # an oversized first step overshoots: the loss rises and the step size halves from then on
+    k0 = [np.zeros((6, 2))]
+    ks, losses, alphas = AD.fit_natural_curvature(d, target.numpy(), k0, 2.5e10, 0.0, 6)
+    assert len(losses) == 7 and len(alphas) == 6
+    assert alphas[0] == 2.5e10
+    for i in range(1, 6):
+        assert alphas[i] == alphas[i - 1] * (0.5 if losses[i] > losses[i - 1] else 1.0)
+    assert any(losses[i] > losses[i - 1] for i in range(1, 6))
+    # every step is kbar <- kbar - alpha grad at the evaluated iterate
+    for i in range(6):
+        _, g, _ = AD.loss_and_grad(d, ks[i], target.numpy())
+        assert np.allclose(ks[i + 1][0].numpy(), ks[i][0].numpy() - alphas[i] * g[0].numpy(), rtol=0, atol=1e-12)
