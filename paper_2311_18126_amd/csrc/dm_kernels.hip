@@ -741,27 +741,26 @@ __device__ __noinline__ void sweep_arms(ArgsP Ap, int ai0, int na, double DM_L* 
 }
 
 // Back substitution of one 11-row block.  Role s < 11 of a row holds the factor record of the
-// block's row s of its arm; step T takes record T from the row by DPP broadcasts.  xv: the
-// solution window (slots by row mod 11), the same in every lane of a row.  MASK: rows whose
-// arm ends below the block's row T keep their window (it holds the trailing border values).
+// block's row s of its arm; at step T every lane evaluates row k0 + T's equation with its own
+// record and the common solution window, role T's value (the one whose record is row k0 + T's)
+// is broadcast in the row by DPP, and every lane enters it into its window.  xv: the solution
+// window (slots by row mod 11), the same in every lane of a row.  MASK: rows whose arm ends
+// below the block's row T keep their window (it holds the trailing border values).
 template <int T, bool MASK>
 __device__ __forceinline__ void back_step(double (&xv)[DM_WIN], const double (&cur)[DM_FAC], double& xs, int l,
                                           bool act) {
-  double rec[DM_FAC];
-#pragma unroll
-  for (int j = 0; j < DM_FAC; ++j) rec[j] = row_bcast<T>(cur[j]);
   // y_k - sum_j U(k, k+j) x_{k+j}: the older solutions first, in two interleaved partial sums
-  // each ending with its most recent term, and x_{k+1} (solved by the previous step) last, so
-  // that only two dependent operations separate x_{k+1} from x_k
-  double s0 = rec[DM_WIN], s1 = 0.0;
+  // each ending with its most recent term, and x_{k+1} (solved by the previous step) last
+  double s0 = cur[DM_WIN], s1 = 0.0;
 #pragma unroll
   for (int j = DM_WIN - 1; j >= 2; --j) {
-    if (j & 1) s0 = fma(-rec[j], xv[(T + j) % DM_WIN], s0);
-    else s1 = fma(-rec[j], xv[(T + j) % DM_WIN], s1);
+    if (j & 1) s0 = fma(-cur[j], xv[(T + j) % DM_WIN], s0);
+    else s1 = fma(-cur[j], xv[(T + j) % DM_WIN], s1);
   }
-  const double xl = fma(-rec[1], xv[(T + 1) % DM_WIN], s0 + s1) * rec[0];
+  const double xo = fma(-cur[1], xv[(T + 1) % DM_WIN], s0 + s1) * cur[0];
+  const double xl = row_bcast<T>(xo);
   xv[T] = (!MASK || act) ? xl : xv[T];
-  xs = (l == T) ? xl : xs;             // role T keeps the solution of row k0 + T
+  xs = (l == T) ? xo : xs;             // role T keeps the solution of row k0 + T
 }
 
 // Factor records of block rows lb .. lb+10: role s < 11 loads record lb + s (12 doubles from a
