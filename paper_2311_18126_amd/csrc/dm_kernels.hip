@@ -456,18 +456,28 @@ __device__ __noinline__ double assemble_border(ArgsP Ap, int sid, double DM_L* B
     if (D.bfix[S.bfix_off + b]) {
       v = col == b ? 1.0 : 0.0;
     } else {
-      // terms in batches of eight: every load of a batch is issued before the sums
+      // terms in batches of eight: every load of a batch is issued before the sums, and the
+      // next batch's items are fetched while this batch's values are (one round trip to memory
+      // per batch instead of two)
       int i = D.bent[S.bent_off + e];
       const int i1 = D.bent[S.bent_off + e + 1];
+      DmBItem it[8];
+      if (i < i1) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) it[j] = D.bitem[i + j < i1 ? i + j : i];
+      }
       for (; i < i1; i += 8) {
         double c[8], x[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
-          const DmBItem it = D.bitem[i + j < i1 ? i + j : i];
-          const double DM_G* src = it.kind == 0 ? D.bpr : (it.kind == 1 ? D.st_H : (it.kind == 2 ? D.R : D.st_g));
-          c[j] = i + j < i1 ? it.coef : 0.0;
-          x[j] = src[it.idx];
+          const double DM_G* src =
+              it[j].kind == 0 ? D.bpr : (it[j].kind == 1 ? D.st_H : (it[j].kind == 2 ? D.R : D.st_g));
+          c[j] = i + j < i1 ? it[j].coef : 0.0;
+          x[j] = src[it[j].idx];
         }
+        const int n = i + 8;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) it[j] = D.bitem[n + j < i1 ? n + j : i];
 #pragma unroll
         for (int j = 0; j < 8; ++j) v = fma(c[j], x[j], v);
       }
