@@ -233,8 +233,8 @@ def main():
                     help="only copy BYTES bytes device to device once (calibrates the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); independent rod batches "
-              "shard by rods across GPUs with no communication, which this build does not launch.",
+        print(f"bench.py measures one GPU (asked for --gpus {args.gpus}); independent rod batches "
+              "would shard by rods across GPUs with no communication, and no multi-GPU launch is made.",
               file=sys.stderr)
         sys.exit(2)
 

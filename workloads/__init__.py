@@ -27,7 +27,7 @@ import math
 
 import numpy as np
 
-G_BASELINE = (0.0, 0.0, -9.81)
+G_EARTH = (0.0, 0.0, -9.81)
 
 
 def straight_nodes(n: int, length: float, origin=(0.0, 0.0, 0.0), direction=(1.0, 0.0, 0.0)) -> np.ndarray:
@@ -66,7 +66,7 @@ def desc(rods, dt, steps, **kw):
     return _desc(rods, dt, steps, **kw)
 
 
-def _desc(rods, dt, steps, gravity=G_BASELINE, joints=(), floor=None, damping=0.0, tol=1e-9, max_iter=50):
+def _desc(rods, dt, steps, gravity=G_EARTH, joints=(), floor=None, damping=0.0, tol=1e-9, max_iter=50):
     return {"rods": list(rods), "joints": list(joints), "gravity": tuple(float(g) for g in gravity),
             "dt": float(dt), "steps": int(steps), "tol": float(tol), "max_iter": int(max_iter),
             "floor": floor, "damping": float(damping)}
