@@ -441,14 +441,71 @@ __device__ __noinline__ double assemble_band(ArgsP Ap, int sid, double dt) {
   return r2;
 }
 
-// Dense border with one lane per entry: the sum of the entry's terms (built once at finalize)
-// in their stored order; a clamped border row is the identity row with a zero right-hand
-// side.  Returns this lane's share of the squared residual of free border rows.
-__device__ __noinline__ double assemble_border(ArgsP Ap, int sid, double DM_L* Bt, int ld) {
+// Value of a border term (kind 4: the zero pad).
+__device__ __forceinline__ double bterm(const DmDev DM_C& D, const DmBItem& it) {
+  const double DM_G* src = it.kind == 0 ? D.bpr
+                         : it.kind == 1 ? D.st_H
+                         : it.kind == 2 ? D.R
+                         : it.kind == 3 ? D.st_g : D.zpad;
+  return it.coef * src[it.idx];
+}
+
+// Dense border from the entries' term segments of DM_SEG terms (built once at finalize),
+// summed in their stored order; a clamped border row is the identity row with a zero
+// right-hand side.  When every entry has at most one segment (a rod's separator), one lane per
+// entry sums its segment.  Otherwise (a hub's entries have dozens of terms) it takes two
+// passes: one lane per segment into segsum (two segments per lane at a time, so that every
+// item and value load of both is in flight together), then one lane per entry adds its
+// segments in order.  Called by the whole workgroup.  Returns this lane's share of the
+// squared residual of free border rows.
+__device__ __noinline__ double assemble_border(ArgsP Ap, int sid, double DM_L* Bt, int ld, double DM_L* segsum) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmDev DM_C& D = A.d;
   const DmSystem DM_C& S = D.sys[uniform(sid)];
-  const int nb = S.nb, W = nb + 1;
+  const int nb = S.nb, W = nb + 1, ns = S.n_seg;
+  if (!S.seg_long) {
+    double r2 = 0.0;
+    for (int e = threadIdx.x; e < nb * W; e += blockDim.x) {
+      const int b = e / W, col = e - b * W;
+      double v = 0.0;
+      if (D.bfix[S.bfix_off + b]) {
+        v = col == b ? 1.0 : 0.0;
+      } else {
+        const int s0 = D.bent[S.bent_off + e];
+        if (D.bent[S.bent_off + e + 1] > s0) {
+          const DmBItem DM_C* p = D.bitem + (size_t)s0 * DM_SEG;
+          DmBItem it[DM_SEG];
+          double x[DM_SEG];
+#pragma unroll
+          for (int j = 0; j < DM_SEG; ++j) it[j] = p[j];
+#pragma unroll
+          for (int j = 0; j < DM_SEG; ++j) x[j] = bterm(D, it[j]);
+#pragma unroll
+          for (int j = 0; j < DM_SEG; ++j) v += x[j];
+        }
+        if (col == nb) r2 += v * v;
+      }
+      Bt[b * ld + col] = v;
+    }
+    return r2;
+  }
+  for (int g = threadIdx.x; g < ns; g += 2 * blockDim.x) {
+    const int g2 = g + blockDim.x;
+    const bool two = g2 < ns;
+    const DmBItem DM_C* p1 = D.bitem + (size_t)(S.seg0 + g) * DM_SEG;
+    const DmBItem DM_C* p2 = D.bitem + (size_t)(S.seg0 + (two ? g2 : g)) * DM_SEG;
+    DmBItem i1[DM_SEG], i2[DM_SEG];
+#pragma unroll
+    for (int j = 0; j < DM_SEG; ++j) { i1[j] = p1[j]; i2[j] = p2[j]; }
+    double v1 = 0.0, v2 = 0.0, x1[DM_SEG], x2[DM_SEG];
+#pragma unroll
+    for (int j = 0; j < DM_SEG; ++j) { x1[j] = bterm(D, i1[j]); x2[j] = bterm(D, i2[j]); }
+#pragma unroll
+    for (int j = 0; j < DM_SEG; ++j) { v1 += x1[j]; v2 += x2[j]; }
+    segsum[g] = v1;
+    if (two) segsum[g2] = v2;
+  }
+  __syncthreads();
   double r2 = 0.0;
   for (int e = threadIdx.x; e < nb * W; e += blockDim.x) {
     const int b = e / W, col = e - b * W;
@@ -456,31 +513,8 @@ __device__ __noinline__ double assemble_border(ArgsP Ap, int sid, double DM_L* B
     if (D.bfix[S.bfix_off + b]) {
       v = col == b ? 1.0 : 0.0;
     } else {
-      // terms in batches of eight: every load of a batch is issued before the sums, and the
-      // next batch's items are fetched while this batch's values are (one round trip to memory
-      // per batch instead of two)
-      int i = D.bent[S.bent_off + e];
-      const int i1 = D.bent[S.bent_off + e + 1];
-      DmBItem it[8];
-      if (i < i1) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) it[j] = D.bitem[i + j < i1 ? i + j : i];
-      }
-      for (; i < i1; i += 8) {
-        double c[8], x[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const double DM_G* src =
-              it[j].kind == 0 ? D.bpr : (it[j].kind == 1 ? D.st_H : (it[j].kind == 2 ? D.R : D.st_g));
-          c[j] = i + j < i1 ? it[j].coef : 0.0;
-          x[j] = src[it[j].idx];
-        }
-        const int n = i + 8;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) it[j] = D.bitem[n + j < i1 ? n + j : i];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) v = fma(c[j], x[j], v);
-      }
+      const int s0 = D.bent[S.bent_off + e] - S.seg0, s1 = D.bent[S.bent_off + e + 1] - S.seg0;
+      for (int q = s0; q < s1; ++q) v += segsum[q];
       if (col == nb) r2 += v * v;
     }
     Bt[b * ld + col] = v;
@@ -1379,7 +1413,7 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
   double DM_L* deltas = Bt + A.max_nb * ld;                // [max_arms][110]
   double DM_L* xB = deltas + A.max_arms * 110;             // [max_nb]
   double DM_L* red = xB + A.max_nb;                        // [40]
-  int DM_L* flags = (int DM_L*)(red + 40);      // [4]
+  int DM_L* flags = (int DM_L*)(red + 40);      // [4]; then border term segment sums at red + 42
   unsigned short DM_L* hbuf = (unsigned short DM_L*)((char DM_L*)lds_raw + A.net_lds);   // network (warm == 2)
   const int tid = threadIdx.x, wave = tid >> 6, nwaves = blockDim.x >> 6;
   if (tid == 0) flags[0] = 0;
@@ -1425,7 +1459,7 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
           double r2 = assemble_band(Ap, sid, hn);
           __syncthreads();
           DM_TP(1);
-          r2 += assemble_border(Ap, sid, Bt, ld);
+          r2 += assemble_border(Ap, sid, Bt, ld, red + 42);
           res = sqrt(block_sum(r2, red));
           DM_TP(2);
           if (res > A.tol && it > 0 && res_prev <= A.stag_tol && res > 0.5 * res_prev) {
@@ -1564,7 +1598,7 @@ __global__ void __launch_bounds__(512) dm_adjoint_kernel(DmAdjArgs) {
     __syncthreads();
     assemble_band(Ap, sid, A.dt);
     __syncthreads();
-    assemble_border(Ap, sid, Bt, ld);
+    assemble_border(Ap, sid, Bt, ld, red + 42);
     __syncthreads();
     adj_rhs(Pp, sid, Bt, ld);
     __syncthreads();

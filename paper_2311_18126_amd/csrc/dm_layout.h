@@ -37,6 +37,7 @@
 #define DM_MAX_CHAINS 8
 #define DM_MAX_BORDER 40
 #define DM_MAX_BSRC 8
+#define DM_SEG 8             // terms per border term segment (padded with zero-pad terms)
 #define DM_ST_G 8            // stencil gradient in (e_f, e_e, theta_f, theta_e)
 #define DM_ST_H 64           // stencil Hessian in the same 8 variables, row-major
 #define DM_ED 9              // edge: stretch gradient (3) + stiffness block (6, symmetric)
@@ -64,7 +65,8 @@ struct DmArm {
 };
 
 // One term of a dense border entry: coef * (array kind)[idx], kinds 0 bpr, 1 st_H, 2 R,
-// 3 st_g (the right-hand side column holds R and st_g terms).
+// 3 st_g (the right-hand side column holds R and st_g terms), 4 the zero pad (padding of a
+// segment: every segment holds DM_SEG terms).
 struct DmBItem {
   int kind, idx;
   double coef;
@@ -82,7 +84,10 @@ struct DmSystem {
   int bjst_off;          // n_jst * 11 border indices of joint-stencil local DOFs
   int bfix_off;          // nb fixed flags
   int chain_nodes;       // sum of chain node counts (band-assembly work items)
-  int bent_off;          // nb (nb + 1) + 1 offsets into the border items, entry b (nb + 1) + col
+  int bent_off;          // nb (nb + 1) + 1 offsets into bent: entry b (nb + 1) + col sums the
+                         // term segments bent[bent_off + e] .. bent[bent_off + e + 1] - 1
+  int seg0, n_seg;       // the system's term segments (global segment indices)
+  int seg_long;          // 1 if some entry has more than one segment
   int n_dof;             // sum of chain DOFs
 };
 
@@ -98,8 +103,8 @@ struct DmDev {
   const int DM_C* bmap;
   const int DM_C* bsrc;         // pairs (chain global index, chain DOF)
   const int DM_C* bjst;
-  const int DM_C* bent;         // border entry -> first item (per system from bent_off)
-  const DmBItem DM_C* bitem;    // border entry terms, summed in their stored order
+  const int DM_C* bent;         // border entry -> first term segment (per system from bent_off)
+  const DmBItem DM_C* bitem;    // border entry terms in segments of DM_SEG, in entry order
   const int DM_C* bsch;         // [arms][110]: where each Schur slot of an arm adds into the
                                 // border, (row << 16) | (col << 8) | slot, or -1 (none or clamped)
   const unsigned char DM_C* bfix;
@@ -195,6 +200,7 @@ struct DmStepArgs {
                      // most this many levels deep (0: off)
   int n_systems;
   int max_nb, max_arms;
+  int max_seg;     // largest number of border term segments of a system (LDS partial sums)
 };
 
 // Discrete adjoint of a stored trajectory segment (single-rod systems without contact).

@@ -89,7 +89,7 @@ struct dm_sim {
   hipStream_t stream = nullptr;
   // layout
   int n_nodes = 0, n_edges = 0, n_st = 0, n_sys = 0, n_chains = 0, n_arms = 0, n_dof = 0;
-  int max_nb = 0, max_arms = 0, block = 0;
+  int max_nb = 0, max_arms = 0, max_seg = 0, block = 0;
   std::vector<int> rod_sys;
   std::vector<std::vector<int>> rod_node, rod_edge;   // global ids per rod node / edge
   std::vector<int> rod_st0;                            // global stencil id of rod node 1
@@ -533,12 +533,20 @@ dm_status do_finalize(dm_sim* s) {
         }
       }
     }
+    // each entry's terms in segments of DM_SEG (the last one padded with zero-pad terms);
+    // bent holds the global index of every entry's first segment
     S.bent_off = (int)bent.size();
+    S.seg0 = (int)(bitem.size() / DM_SEG);
+    S.seg_long = 0;
     for (const auto& e : ent) {
-      bent.push_back((int)bitem.size());
-      bitem.insert(bitem.end(), e.begin(), e.end());
+      if (e.size() > DM_SEG) S.seg_long = 1;
+      bent.push_back((int)(bitem.size() / DM_SEG));
+      for (size_t i = 0; i < e.size(); i += DM_SEG)
+        for (size_t j = i; j < i + DM_SEG; ++j) bitem.push_back(j < e.size() ? e[j] : DmBItem{4, 0, 0.0});
     }
-    bent.push_back((int)bitem.size());
+    bent.push_back((int)(bitem.size() / DM_SEG));
+    S.n_seg = (int)(bitem.size() / DM_SEG) - S.seg0;
+    s->max_seg = std::max(s->max_seg, S.n_seg);
   }
   // ---- per arm, the border entry each of its Schur-complement slots adds to: slot i * 10 + j
   // (trailing DOFs i, j) or 100 + i (right-hand side of trailing DOF i)
@@ -744,6 +752,7 @@ void fill_step_args(const dm_sim* s, double dt, int nsteps, DmStepArgs& A) {
   A.n_systems = s->n_sys;
   A.max_nb = std::max(s->max_nb, 1);
   A.max_arms = std::max(s->max_arms, 1);
+  A.max_seg = std::max(s->max_seg, 1);
   A.warm = s->ws_mode;
   if (s->ws_mode == 2) dm_mlp_view(s->ws_net, &A.net);
 }
@@ -751,8 +760,8 @@ void fill_step_args(const dm_sim* s, double dt, int nsteps, DmStepArgs& A) {
 // LDS bytes of a step launch; places the network's activations (warm mode 2) after the
 // solver's arrays, 16-byte aligned.
 size_t step_lds(DmStepArgs& A) {
-  const size_t base =
-      sizeof(double) * ((size_t)A.max_nb * (A.max_nb + 1) + (size_t)A.max_arms * 110 + A.max_nb + 40 + 2);
+  const size_t base = sizeof(double) * ((size_t)A.max_nb * (A.max_nb + 1) + (size_t)A.max_arms * 110 + A.max_nb +
+                                         40 + 2 + (size_t)A.max_seg);
   if (A.warm != 2) return base;
   A.net_lds = (int)((base + 15) / 16 * 16);
   return (size_t)A.net_lds + DM_NET_LDS_BYTES;
