@@ -53,29 +53,39 @@ def measured_traffic(n_launch_steps):
     return t["bytes_per_step"] * n_launch_steps
 
 
-def cpu_baseline(desc, budget_s=20.0):
+def cpu_baseline(desc, budget_s=20.0, single_budget_s=8.0):
     """The CPU oracle, as is, on a bounded sample of the same workload: seeded rods of the
-    batch, one step each, until the time budget is used (rank 0, one GPU only)."""
+    batch, one step each, until the time budget is used (rank 0, one GPU only); then the same
+    rods in the same order on one thread for a shorter budget."""
     import torch
 
     import workloads as W
     from oracle import der
     threads = min(os.cpu_count() or 1, 16)
-    torch.set_num_threads(threads)
     rng = np.random.Generator(np.random.PCG64(123))
     order = rng.permutation(len(desc["rods"]))
-    nodes, t_used, rods = 0, 0.0, 0
-    for r in order:
-        sub = W.subset(desc, [int(r)])
-        t0 = time.perf_counter()
-        der.simulate(sub, steps=1)
-        t_used += time.perf_counter() - t0
-        nodes += sub["rods"][0]["x0"].shape[0]
-        rods += 1
-        if t_used > budget_s:
-            break
-    return {"value": nodes / t_used, "unit": "node-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{rods} seeded rods of the 1024-rod batch, 1 step each, {t_used:.1f} s"}
+
+    def run(budget):
+        nodes, t_used, rods = 0, 0.0, 0
+        for r in order:
+            sub = W.subset(desc, [int(r)])
+            t0 = time.perf_counter()
+            der.simulate(sub, steps=1)
+            t_used += time.perf_counter() - t0
+            nodes += sub["rods"][0]["x0"].shape[0]
+            rods += 1
+            if t_used > budget:
+                break
+        return nodes / t_used, rods, t_used
+    torch.set_num_threads(threads)
+    value, rods, t_used = run(budget_s)
+    torch.set_num_threads(1)
+    v1, rods1, t1 = run(single_budget_s)
+    torch.set_num_threads(threads)
+    return {"value": value, "unit": "node-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{rods} seeded rods of the 1024-rod batch, 1 step each, {t_used:.1f} s",
+            "single_thread_value": v1,
+            "single_thread_sample": f"the first {rods1} of those rods on 1 thread, {t1:.1f} s"}
 
 
 def per_rod_baseline(dm, desc, steps, n=16):
