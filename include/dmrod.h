@@ -226,7 +226,9 @@ dm_status dm_adjoint(dm_sim* sim, const double* dL_dtips, int in_on_device, doub
  * dm_set_natural_curvature_all (host or device).  losses: NULL or host array of max_iter + 1
  * receiving the loss of every evaluated iterate; n_eval: NULL or their count.  On return the
  * sim holds its starting state and the fitted curvature.  Same restrictions as dm_adjoint;
- * bad step size, tolerance or counts return DM_ERR_INVALID_ARG. */
+ * bad step size, tolerance or counts return DM_ERR_INVALID_ARG; a rollout whose Newton solve
+ * fails returns its status and leaves the sim's state and curvature unspecified (reload a
+ * checkpoint).  The caller's arrays must hold the sizes stated (not checked). */
 dm_status dm_fit_natural_curvature(dm_sim* sim, double dt, int nsteps, int ckpt_every, const double* target_tips,
                                    int target_on_device, double alpha0, double tol, int max_iter, double* kbar,
                                    int kbar_on_device, double* losses, int* n_eval);

@@ -430,7 +430,11 @@ class Sim:
         """Real2Sim-style gradient descent (dm_fit_natural_curvature): returns the fitted
         concatenated natural curvature and the loss of every evaluated iterate (host arrays)."""
         tgt = _f64(target_tips)
+        if tgt.size != int(nsteps) * self.num_rods * 3:
+            raise ValueError(f"target_tips must hold nsteps x n_rods x 3 = {int(nsteps) * self.num_rods * 3} values")
         kb = np.zeros(self.kbar_size) if kbar0 is None else _f64(kbar0).copy()
+        if kb.size != self.kbar_size:
+            raise ValueError(f"kbar0 must hold {self.kbar_size} values")
         losses = np.zeros(max_iter + 1)
         n = ctypes.c_int(0)
         _check(lib().dm_fit_natural_curvature(self._h, float(dt), int(nsteps), int(ckpt_every), tgt.ctypes.data, 0,

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -61,3 +62,20 @@ def test_missing_device_is_an_error_not_a_fallback(library):
     with pytest.raises(dm.DmError) as e:
         dm.Sim()
     assert e.value.status == dm.DM_ERR_HIP
+
+
+def test_fit_checks_array_sizes_before_the_library_call():
+    """The binding refuses a target or start curvature of the wrong size (the C entry point
+    reads the sizes it is told); no GPU is touched before the check."""
+    import paper_2311_18126_amd as dm
+
+    class Probe(dm.Sim):
+        def __init__(self):     # no library call: only the size checks run
+            pass
+        num_rods = 2
+        kbar_size = 12
+    p = Probe()
+    with pytest.raises(ValueError):
+        p.fit_natural_curvature(1e-3, 4, np.zeros((4, 1, 3)))
+    with pytest.raises(ValueError):
+        p.fit_natural_curvature(1e-3, 4, np.zeros((4, 2, 3)), kbar0=np.zeros(5))
