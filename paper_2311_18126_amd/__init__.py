@@ -142,6 +142,23 @@ def _f64(a, shape=None):
     return a
 
 
+def _sized(a, n, what):
+    """float64 contiguous host copy of a, which must hold exactly n values (the library reads
+    the sizes it is told, so a short array is refused here)."""
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.size != n:
+        raise ValueError(f"{what} must hold {n} values, got {a.size}")
+    return a
+
+
+def _device_sized(t, n, what):
+    """A float64 contiguous device tensor of at least n values."""
+    import torch
+    if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() < n:
+        raise ValueError(f"{what} must be a contiguous float64 device tensor of at least {n} values")
+    return t
+
+
 class Sim:
     """One dm_sim.  Build with add_rod / add_joint / ..., then finalize() and step()."""
 
@@ -189,6 +206,8 @@ class Sim:
     # -- construction -------------------------------------------------------
     def add_rod(self, x0, radius, E, poisson=0.5, density=1000.0):
         x0 = _f64(x0)
+        if x0.ndim != 2 or x0.shape[1] != 3:
+            raise ValueError("x0 must have shape (n_nodes, 3)")
         rid = c_int()
         _check(lib().dm_add_rod(self._h, x0.shape[0], _dp(x0), radius, E, poisson, density, ctypes.byref(rid)),
                "dm_add_rod")
@@ -206,15 +225,16 @@ class Sim:
         _check(lib().dm_fix_edges(self._h, rod, a.ctypes.data_as(_IP), a.size), "dm_fix_edges")
 
     def set_natural_curvature(self, rod, kbar):
-        k = _f64(kbar)
+        k = _sized(kbar, 2 * max(lib().dm_rod_nodes(self._h, rod) - 2, 0), "kbar")
         _check(lib().dm_set_natural_curvature(self._h, rod, _dp(k)), "dm_set_natural_curvature")
 
     def set_actuation_sine(self, rod, A, f, phi):
         _check(lib().dm_set_actuation_sine(self._h, rod, A, f, phi), "dm_set_actuation_sine")
 
     def set_external_load(self, rod, force=None, moment=None):
-        fp = _f64(force) if force is not None else None
-        mp = _f64(moment) if moment is not None else None
+        n = lib().dm_rod_nodes(self._h, rod)
+        fp = _sized(force, 3 * n, "force") if force is not None else None
+        mp = _sized(moment, max(n - 1, 0), "moment") if moment is not None else None
         _check(lib().dm_set_external_load(self._h, rod, _dp(fp) if fp is not None else None,
                                           _dp(mp) if mp is not None else None), "dm_set_external_load")
 
@@ -276,7 +296,10 @@ class Sim:
         return x, th, v, om
 
     def set_rod_state(self, rod, x=None, theta=None, v=None, theta_dot=None):
-        args = [(_dp(_f64(a)) if a is not None else None) for a in (x, theta, v, theta_dot)]
+        n = lib().dm_rod_nodes(self._h, rod)
+        arrs = [None if a is None else _sized(a, m, w) for a, m, w in
+                ((x, 3 * n, "x"), (theta, n - 1, "theta"), (v, 3 * n, "v"), (theta_dot, n - 1, "theta_dot"))]
+        args = [(_dp(a) if a is not None else None) for a in arrs]
         _check(lib().dm_set_rod_state(self._h, rod, *args), "dm_set_rod_state")
 
     def state(self):
@@ -321,10 +344,12 @@ class Sim:
 
     def restore(self, buf):
         """Load a checkpoint from a host array or a device tensor (checkpoint_torch)."""
+        n = lib().dm_checkpoint_size(self._h)
         if _is_cuda_tensor(buf):
+            _device_sized(buf, n, "checkpoint")
             _check(lib().dm_load_checkpoint(self._h, buf.data_ptr(), 1), "dm_load_checkpoint")
             return
-        buf = _f64(buf)
+        buf = _sized(buf, n, "checkpoint")
         _check(lib().dm_load_checkpoint(self._h, buf.ctypes.data, 0), "dm_load_checkpoint")
 
     def checkpoint_torch(self, device="cuda"):
@@ -391,10 +416,10 @@ class Sim:
         """Every rod's natural curvature [N_r-2][2] (1/m), concatenated in rod order; a host
         array or a float64 device tensor."""
         if _is_cuda_tensor(kbar):
-            k = kbar.detach().contiguous()
+            k = _device_sized(kbar.detach().contiguous(), self.kbar_size, "kbar")
             _check(lib().dm_set_natural_curvature_all(self._h, k.data_ptr(), 1), "dm_set_natural_curvature_all")
         else:
-            k = _f64(kbar).reshape(-1)
+            k = _sized(kbar, self.kbar_size, "kbar")
             _check(lib().dm_set_natural_curvature_all(self._h, k.ctypes.data, 0), "dm_set_natural_curvature_all")
 
     def rollout(self, dt, nsteps, ckpt_every=20, out=None):
@@ -402,23 +427,33 @@ class Sim:
         (last node) of every rod after every step, (nsteps, n_rods, 3), into `out` (a float64
         device tensor) or a new host array."""
         if out is not None:
+            _device_sized(out, int(nsteps) * self.num_rods * 3, "out")
             _check(lib().dm_rollout(self._h, dt, nsteps, ckpt_every, out.data_ptr(), 1), "dm_rollout")
+            self._roll_steps = int(nsteps)
             return out
         tips = np.zeros((nsteps, self.num_rods, 3))
         _check(lib().dm_rollout(self._h, dt, nsteps, ckpt_every, tips.ctypes.data, 0), "dm_rollout")
+        self._roll_steps = int(nsteps)
         return tips
 
     def adjoint(self, dL_dtips, out=None):
         """Gradient of a tip-trajectory loss with respect to the concatenated natural curvature,
         from dL/dtips of the last rollout (host array or device tensor); into `out` (float64
         device tensor) or a new host array."""
+        # sizes are checked against the last rollout; without one the library reports the
+        # missing rollout (DM_ERR_STATE) before reading anything
+        steps = getattr(self, "_roll_steps", None)
+        n = (steps or 0) * self.num_rods * 3
         if _is_cuda_tensor(dL_dtips):
             g = dL_dtips.detach().contiguous()
+            if steps is not None:
+                _device_sized(g, n, "dL_dtips")
             src, on_dev = g.data_ptr(), 1
         else:
-            g = _f64(dL_dtips)
+            g = _f64(dL_dtips) if steps is None else _sized(dL_dtips, n, "dL_dtips")
             src, on_dev = g.ctypes.data, 0
         if out is not None:
+            _device_sized(out, self.kbar_size, "out")
             _check(lib().dm_adjoint(self._h, src, on_dev, out.data_ptr(), 1), "dm_adjoint")
             return out
         res = np.zeros(self.kbar_size)
@@ -494,7 +529,7 @@ class Mlp:
         return p
 
     def set_normalisation(self, mean, std, scale):
-        m, sd, sc = _f64(mean), _f64(std), _f64(scale)
+        m, sd, sc = _sized(mean, 20, "mean"), _sized(std, 20, "std"), _sized(scale, 3, "scale")
         _check(lib().dm_mlp_set_normalisation(self._h, _dp(m), _dp(sd), _dp(sc)), "dm_mlp_set_normalisation")
 
     def get_normalisation(self):
