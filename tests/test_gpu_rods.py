@@ -205,3 +205,47 @@ def test_unsupported_topology_is_rejected(dm):
     with pytest.raises(dm.DmError) as e:
         sim.finalize()
     assert e.value.status == dm.DM_ERR_UNSUPPORTED
+
+
+def test_degenerate_inputs(dm):
+    """An empty simulation cannot be finalized; a straight rod with no load is already at rest
+    (zero Newton iterations, state unchanged bit for bit); a rod clamped everywhere does not
+    move under gravity."""
+    with pytest.raises(dm.DmError) as e:
+        dm.Sim().finalize()
+    assert e.value.status == dm.DM_ERR_STATE
+    d = W.desc([W.rod(W.straight_nodes(30, 0.6), 2e-3, 1e6)], dt=1e-3, steps=3, gravity=(0.0, 0.0, 0.0))
+    sim = dm.sim_from_description(d)
+    x0 = sim.state()[0].copy()
+    st = sim.step(d["dt"], 3)
+    assert st["status"][0] == 0 and st["iters"][0] == 0
+    assert np.array_equal(sim.state()[0], x0)
+    n = 25
+    d = W.desc([W.rod(W.straight_nodes(n, 0.5), 2e-3, 1e6, fixed_nodes=range(n), fixed_edges=range(n - 1))],
+               dt=1e-3, steps=3)
+    sim = dm.sim_from_description(d)
+    x0 = sim.state()[0].copy()
+    st = sim.step(d["dt"], 3)
+    assert st["status"][0] == 0
+    assert np.array_equal(sim.state()[0], x0)
+
+
+def test_long_rod_under_axial_tip_load_reaches_uniform_strain(dm):
+    """A 3000-node rod (12,000 DOFs, far above the batch's longest) clamped at one end and
+    pulled at the other, without gravity: with steps of 10 s the implicit step lands on the
+    static state, whose every free edge carries the strain P / EA (Eq. 2-3), at any size."""
+    n, L, h, E, P = 3000, 3.0, 2e-3, 1e7, 0.5
+    force = np.zeros((n, 3))
+    force[-1, 0] = P
+    d = W.desc([W.rod(W.straight_nodes(n, L), h, E, force=force)], dt=10.0, steps=4, gravity=(0.0, 0.0, 0.0))
+    say("case: 3000-node rod, axial tip load, 4 steps of 10 s")
+    sim = dm.sim_from_description(d)
+    st = sim.step(d["dt"], 4)
+    assert st["status"][0] == 0
+    x = sim.rod_state(0)[0]
+    ell = np.linalg.norm(np.diff(x, axis=0), axis=1)
+    strain = ell / (L / (n - 1)) - 1.0
+    expect = P / (E * np.pi * h * h)
+    assert strain[0] == 0.0                      # between the two clamped nodes
+    assert np.abs(strain[1:] - expect).max() <= 1e-6 * expect, (strain[1:].min(), strain[1:].max(), expect)
+    assert np.abs(x[:, 1:]).max() < 1e-12
