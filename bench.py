@@ -232,6 +232,126 @@ def adjoint_section(dm):
             "grad_norm": float(np.linalg.norm(g))}
 
 
+def oracle_rate(make, threads, budget_s):
+    """Node-steps/s of the CPU oracle, as is, on `threads` threads: calls make() -> (fn, nodes)
+    repeatedly (each call one oracle unit of work over `nodes` node-steps) until the budget."""
+    import torch
+    torch.set_num_threads(threads)
+    done, used = 0.0, 0.0
+    while used < budget_s:
+        fn, nodes = make()
+        t0 = time.perf_counter()
+        fn()
+        used += time.perf_counter() - t0
+        done += nodes
+    return done / used
+
+
+def config_table(dm, log):
+    """One line per benchmark configuration: the plain per-system GPU step, the batched launch,
+    the warm-started (second-order extrapolation) launch, the CPU oracle on one thread and on
+    all cores (bounded samples), FP64 and HBM roofline fractions and Newton iterations per step.
+    Each figure is node-steps/s at the 1e-9 residual."""
+    import torch
+
+    import workloads as W
+    from oracle import adjoint as AD
+    from oracle import der
+    threads = min(os.cpu_count() or 1, 16)
+    rows = []
+
+    def gpu_run(desc, steps, warm=0, block=0):
+        sim = dm.sim_from_description(desc, block_size=block)
+        sim.set_warm_start(None, warm)
+        sim.step(desc["dt"], 1)
+        st, wall = timed_steps(sim, desc["dt"], steps)
+        assert (st["status"] == 0).all()
+        nodes = float(sim.num_nodes)
+        kernel_s = sim.last_kernel_ms / 1e3
+        iters = float(st["iters"].sum())
+        sim.close()
+        return nodes * steps / wall, iters / st["iters"].size / steps, kernel_s, nodes, iters
+
+    def fp64_frac(nodes_per_sys_iters, kernel_s):
+        return FLOPS_PER_NODE_ITER * nodes_per_sys_iters / kernel_s / (PEAK_FP64_VALU_TFLOPS * 1e12)
+
+    # cfg1: single cantilever
+    d = W.cantilever(steps=100)
+    v, it, ks, nodes, iters = gpu_run(d, 100)
+    vw, itw, _, _, _ = gpu_run(d, 100, warm=3)
+    one = lambda: (lambda: der.simulate(d, steps=2), 2 * 51)
+    rows.append({"config": "cfg1 cantilever N=51, dt 1e-2, 100 steps", "plain_per_rod_gpu": v, "batched_gpu": None,
+                 "warm_started_gpu": vw, "cpu_oracle_1_thread": oracle_rate(one, 1, 4.0),
+                 "cpu_oracle_all_cores": oracle_rate(one, threads, 4.0), "cores": threads,
+                 "fp64_roof_fraction": fp64_frac(nodes * iters, ks), "hbm_roof_fraction": None,
+                 "newton_iters_plain": it, "newton_iters_warm": itw})
+    log(f"configs: {rows[-1]}")
+    # cfg2: 1024-rod batch
+    d = W.rod_batch(1024)
+    n_r = np.array([r["x0"].shape[0] for r in d["rods"]], dtype=float)
+    sim = dm.sim_from_description(d)
+    sim.step(d["dt"], 1)
+    st, wall = timed_steps(sim, d["dt"], 20)
+    ks = sim.last_kernel_ms / 1e3
+    sim.close()
+    v = n_r.sum() * 20 / wall
+    it = float(st["iters"].mean() / 20)
+    vw, itw, _, _, _ = gpu_run(d, 20, warm=3)
+    traffic = measured_traffic(20)
+    rng = np.random.Generator(np.random.PCG64(123))
+    order = iter(rng.permutation(len(d["rods"])))
+
+    def one_rod():
+        r = int(next(order))
+        sub = W.subset(d, [r])
+        return (lambda: der.simulate(sub, steps=1)), sub["rods"][0]["x0"].shape[0]
+    c1 = oracle_rate(one_rod, 1, 6.0)
+    call = oracle_rate(one_rod, threads, 6.0)
+    rows.append({"config": "cfg2 1024 rods N~U{20..400}, dt 1e-3", "plain_per_rod_gpu": per_rod_baseline(dm, d, 20),
+                 "batched_gpu": v, "warm_started_gpu": vw, "cpu_oracle_1_thread": c1, "cpu_oracle_all_cores": call,
+                 "cores": threads, "fp64_roof_fraction": fp64_frac(float((n_r * st["iters"]).sum()), ks),
+                 "hbm_roof_fraction": None if traffic is None else traffic / ks / 8e12,
+                 "newton_iters_plain": it, "newton_iters_warm": itw})
+    log(f"configs: {rows[-1]}")
+    # cfg3: six-limb stars
+    d1 = W.star_robots(1, steps=10)
+    v1, _, _, _, _ = gpu_run(d1, 10)
+    d = W.star_robots(4096)
+    v, it, ks, nodes, iters = gpu_run(d, 10)
+    vw, itw, _, _, _ = gpu_run(d, 10, warm=3)
+    star = lambda: (lambda: der.simulate(d1, steps=1), 6 * 30 + 1)
+    rows.append({"config": "cfg3 4096 six-limb stars, floor contact, actuation", "plain_per_rod_gpu": v1,
+                 "batched_gpu": v, "warm_started_gpu": vw, "cpu_oracle_1_thread": oracle_rate(star, 1, 6.0),
+                 "cpu_oracle_all_cores": oracle_rate(star, threads, 6.0), "cores": threads,
+                 "fp64_roof_fraction": fp64_frac(iters / 4096.0 * nodes, ks),
+                 "hbm_roof_fraction": None, "newton_iters_plain": it, "newton_iters_warm": itw})
+    log(f"configs: {rows[-1]}")
+    # cfg4: learned warm start (network) on fresh rods
+    ws = warm_start_section(dm, 20, log)
+    rows.append({"config": "cfg4 learned warm start, 1024 fresh rods N~U{50..400}", "plain_per_rod_gpu": None,
+                 "batched_gpu": ws["plain_value"], "warm_started_gpu": ws["network_value"],
+                 "warm_started_gpu_extrapolation": ws["extrapolation_value"], "cpu_oracle_1_thread": None,
+                 "cpu_oracle_all_cores": None, "cores": threads, "fp64_roof_fraction": None, "hbm_roof_fraction": None,
+                 "newton_iters_plain": ws["plain_iters_per_step"], "newton_iters_warm": ws["network_iters_per_step"]})
+    log(f"configs: {rows[-1]}")
+    # cfg5: adjoint
+    adj = adjoint_section(dm)
+    da, kstar = W.adjoint_rods(n_rods=1, n_nodes=100, steps=5)
+    _, _, target = AD.rollout(da, [kstar[0]])
+    k0 = [np.zeros((98, 2))]
+
+    def adj_unit():
+        return (lambda: AD.loss_and_grad(da, k0, target.numpy())), 100 * 5
+    rows.append({"config": "cfg5 adjoint 256 rods x 100 nodes x 200 steps (forward + backward)",
+                 "plain_per_rod_gpu": None, "batched_gpu": adj["value"], "warm_started_gpu": None,
+                 "cpu_oracle_1_thread": oracle_rate(adj_unit, 1, 8.0),
+                 "cpu_oracle_all_cores": oracle_rate(adj_unit, threads, 8.0), "cores": threads,
+                 "fp64_roof_fraction": None, "hbm_roof_fraction": None, "newton_iters_plain": None,
+                 "newton_iters_warm": None})
+    for r in rows:
+        print(json.dumps(r), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -242,6 +362,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the batched step (for profiling)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--configs", action="store_true",
+                    help="instead of the headline line, one line per benchmark configuration")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES bytes device to device once (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -269,6 +391,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": 8 * n}), flush=True)
+        return
+    if args.configs:
+        config_table(dm, log)
         return
     desc = W.rod_batch(1024)
     n_nodes = np.array([r["x0"].shape[0] for r in desc["rods"]])
