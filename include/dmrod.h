@@ -269,6 +269,14 @@ dm_status dm_mlp_forward(dm_mlp* net, const double* F, int n, float* Y);
 dm_status dm_mlp_gradients(dm_mlp* net, const double* F, const double* T, int n, float* grads, double* loss);
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8, learning rate lr) on that loss. */
 dm_status dm_mlp_train_step(dm_mlp* net, const double* F, const double* T, int n, float lr, double* loss);
+/* One epoch of such steps without a host wait per step: mini-batches of `batch` rows taken in
+ * the order of perm (device int32 [n], indices into the n rows of F [n][20] and T [n][3], both
+ * device float64); the last n % batch entries of perm are not used.  mean_loss (host, may be
+ * NULL) receives the mean of the batch losses.  1 <= batch <= min(n, max_rows); an index of
+ * perm outside 0..n-1 gives DM_ERR_INVALID_ARG (that batch's row is replaced by row 0 and the
+ * epoch's steps have still been applied).  Waits for the network's stream before returning. */
+dm_status dm_mlp_train_epoch(dm_mlp* net, const double* F, const double* T, const int* perm, int n, int batch,
+                             float lr, double* mean_loss);
 const char* dm_mlp_last_error(void);
 void dm_mlp_destroy(dm_mlp* net);
 

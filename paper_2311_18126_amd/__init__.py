@@ -83,6 +83,7 @@ _SIGS = {
     "dm_mlp_forward": (c_int, [c_void_p, c_void_p, c_int, c_void_p]),
     "dm_mlp_gradients": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, _DP]),
     "dm_mlp_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_float, _DP]),
+    "dm_mlp_train_epoch": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_float, _DP]),
     "dm_mlp_last_error": (c_char_p, []),
     "dm_mlp_destroy": (None, [c_void_p]),
     "dm_ws_rows": (c_int, [c_void_p]),
@@ -500,6 +501,7 @@ class Mlp:
         _check(lib().dm_mlp_create(device, stream, int(max_rows), ctypes.byref(h)), "dm_mlp_create")
         self._h = h
         self.max_rows = int(max_rows)
+        self.stream = stream
 
     @staticmethod
     def num_params():
@@ -550,10 +552,27 @@ class Mlp:
                                       ctypes.byref(loss)), "dm_mlp_gradients")
         return loss.value
 
-    def train_step(self, F, T, lr=1e-3):
+    def train_step(self, F, T, lr=1e-3, want_loss=True):
+        """One Adam step; returns the batch loss, or None without waiting for the stream when
+        want_loss is False."""
         loss = c_double()
-        _check(lib().dm_mlp_train_step(self._h, F.data_ptr(), T.data_ptr(), F.shape[0], lr, ctypes.byref(loss)),
-               "dm_mlp_train_step")
+        _check(lib().dm_mlp_train_step(self._h, F.data_ptr(), T.data_ptr(), F.shape[0], lr,
+                                       ctypes.byref(loss) if want_loss else None), "dm_mlp_train_step")
+        return loss.value if want_loss else None
+
+    def train_epoch(self, F, T, perm, batch, lr=1e-3):
+        """Adam over the mini-batches perm[0:batch], perm[batch:2 batch], ... of device features
+        F [n, 20] and targets T [n, 3] (float64); perm is a device int32 [n].  Returns the mean
+        batch loss."""
+        import torch
+        n = F.shape[0]
+        if (F.dtype != torch.float64 or T.dtype != torch.float64 or perm.dtype != torch.int32
+                or tuple(F.shape) != (n, 20) or tuple(T.shape) != (n, 3) or tuple(perm.shape) != (n,)
+                or not (F.is_contiguous() and T.is_contiguous() and perm.is_contiguous())):
+            raise ValueError("train_epoch: F [n, 20] and T [n, 3] float64, perm [n] int32, contiguous")
+        loss = c_double()
+        _check(lib().dm_mlp_train_epoch(self._h, F.data_ptr(), T.data_ptr(), perm.data_ptr(), n, int(batch), lr,
+                                        ctypes.byref(loss)), "dm_mlp_train_epoch")
         return loss.value
 
 

@@ -10,6 +10,8 @@
 // accumulators, master weights and Adam moments are float32.
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <algorithm>
 #include <stdint.h>
 #include <string>
 #include <vector>
@@ -30,8 +32,9 @@ constexpr int KX = DM_NET_KX;             // input width padded to one MFMA redu
 constexpr int NOP = DM_NET_OUTP;          // output width padded to one MFMA tile
 constexpr int OFF_W1 = 0, OFF_B1 = OFF_W1 + NH * NI, OFF_W2 = OFF_B1 + NH, OFF_B2 = OFF_W2 + NH * NH;
 constexpr int OFF_W3 = OFF_B2 + NH, OFF_B3 = OFF_W3 + NO * NH, NPARAM = OFF_B3 + NO;
-constexpr int ROWS_WG = 64;               // batch rows per workgroup of the row GEMM (4 waves x 16)
-constexpr int WG_CHUNK = 4096;            // batch rows per split of the weight-gradient GEMM
+constexpr int ROWS_PAD = 64;              // batch rows are padded to a multiple of this
+constexpr int NS_MAX = 64;                // most splits of the weight-gradient batch reduction
+constexpr int WG_WAVES = 2048;            // wavefronts aimed at per weight-gradient launch (8 per CU)
 
 __device__ __forceinline__ u16 bf16_bits(float v) { return dm_bf16_bits(v); }
 __device__ __forceinline__ float bf16_val(u16 h) { return __uint_as_float((uint32_t)h << 16); }
@@ -41,9 +44,19 @@ __device__ __forceinline__ bf16x8 ld8(const u16* p) { return *reinterpret_cast<c
 
 enum { EPI_HIDDEN = 0, EPI_OUTPUT = 1, EPI_DGRAD = 2 };
 
-// out = epilogue(A[rows][K] . Bm[N][K]^T).  One wavefront per 16 rows; lane l supplies
-// A[l % 16][8 (l / 16) + 0..7] and, per 16-column tile t, Bm[16 t + l % 16][8 (l / 16) + 0..7],
-// and receives C[4 (l / 16) + j][16 t + l % 16], j = 0..3.
+// Wavefronts of a row-GEMM workgroup that share one 16-row block, each taking a quarter of the
+// column tiles (four when N has at least four tiles, else one wavefront per block).
+template <int N>
+constexpr int row_wpr() { return N / 16 >= 4 ? 4 : 1; }
+
+// Workgroups of 256 threads covering `rows` (a multiple of ROWS_PAD) for a product of width N.
+template <int N>
+inline int row_grid(int rows) { return rows / (16 * (4 / row_wpr<N>())); }
+
+// out = epilogue(A[rows][K] . Bm[N][K]^T).  A wavefront computes one 16-row block over
+// N / 16 / row_wpr column tiles; lane l supplies A[l % 16][8 (l / 16) + 0..7] and, per
+// 16-column tile t, Bm[16 t + l % 16][8 (l / 16) + 0..7], and receives
+// C[4 (l / 16) + j][16 t + l % 16], j = 0..3.
 //   EPI_HIDDEN: + bias, ReLU, bfloat16 to out [rows][N] and outT [N][rows];
 //   EPI_OUTPUT: + bias, float32 to outF [rows][3] (columns 0..2);
 //   EPI_DGRAD : times the ReLU mask (mask [rows][N] > 0), bfloat16 to out (if given) and outT.
@@ -52,23 +65,26 @@ __global__ void __launch_bounds__(256) row_gemm(const u16* __restrict__ A, const
                                                 const float* __restrict__ bias, const u16* __restrict__ mask,
                                                 int rows, u16* __restrict__ out, u16* __restrict__ outT,
                                                 float* __restrict__ outF) {
-  const int l = threadIdx.x & 63;
-  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+  constexpr int WPR = row_wpr<N>(), TPW = N / 16 / WPR;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int row0 = (blockIdx.x * (4 / WPR) + w / WPR) * 16;
+  const int tb = (w % WPR) * TPW;
   if (row0 >= rows) return;
   const int lr = l & 15, lk = 8 * (l >> 4);
-  f32x4 acc[N / 16];
+  f32x4 acc[TPW];
 #pragma unroll
-  for (int t = 0; t < N / 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int k0 = 0; k0 < K; k0 += 32) {
     const bf16x8 a = ld8(A + (size_t)(row0 + lr) * K + k0 + lk);
 #pragma unroll
-    for (int t = 0; t < N / 16; ++t) acc[t] = mfma(a, ld8(Bm + (size_t)(16 * t + lr) * K + k0 + lk), acc[t]);
+    for (int t = 0; t < TPW; ++t)
+      acc[t] = mfma(a, ld8(Bm + (size_t)(16 * (tb + t) + lr) * K + k0 + lk), acc[t]);
   }
   const int r0 = row0 + 4 * (l >> 4);
 #pragma unroll
-  for (int t = 0; t < N / 16; ++t) {
-    const int n = 16 * t + lr;
+  for (int t = 0; t < TPW; ++t) {
+    const int n = 16 * (tb + t) + lr;
     if (EPI == EPI_OUTPUT) {
       if (n < NO)
 #pragma unroll
@@ -94,22 +110,32 @@ __global__ void __launch_bounds__(256) row_gemm(const u16* __restrict__ A, const
   }
 }
 
+// Split of the batch reduction of a weight-gradient product with `tiles` output blocks: about
+// WG_WAVES wavefronts in all, at most NS_MAX splits, each split a multiple of 32 rows (one
+// MFMA reduction step).  ns <= want follows from chunk >= rows / want.
+inline void split_plan(int rows, int tiles, int* chunk, int* ns) {
+  const int want = std::min(NS_MAX, std::max(1, WG_WAVES / tiles));
+  *chunk = ((rows + want - 1) / want + 31) / 32 * 32;
+  *ns = (rows + *chunk - 1) / *chunk;
+}
+
 // Partial weight gradients over one split of the batch: part[s][m][n] = sum_k At[m][k] Bt[n][k]
-// over k in split s, and (for the first column block) bpart[s][m] = sum_k At[m][k].  One
-// wavefront per 16 x NT output block.
+// over k in split s (rows s * chunk .. min((s + 1) * chunk, ld) - 1), and (for the first
+// column block) bpart[s][m] = sum_k At[m][k].  One wavefront per 16 x NT output block.
 template <int M, int N>
 __global__ void __launch_bounds__(64) wgrad_gemm(const u16* __restrict__ At, const u16* __restrict__ Bt, int ld,
-                                                 float* __restrict__ part, float* __restrict__ bpart) {
+                                                 int chunk, float* __restrict__ part, float* __restrict__ bpart) {
   constexpr int NT = N < 64 ? N : 64;
   const int l = threadIdx.x;
   const int mt = blockIdx.x / (N / NT), nt = blockIdx.x % (N / NT);
   const int m0 = 16 * mt, n0 = NT * nt, s = blockIdx.y;
-  const int kb = s * WG_CHUNK, ke = min(kb + WG_CHUNK, ld);
+  const int kb = s * chunk, ke = min(kb + chunk, ld);
   const int lr = l & 15, lk = 8 * (l >> 4);
   f32x4 acc[NT / 16];
 #pragma unroll
   for (int t = 0; t < NT / 16; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
   float bs = 0.0f;
+#pragma unroll 4
   for (int k0 = kb; k0 < ke; k0 += 32) {
     const bf16x8 a = ld8(At + (size_t)(m0 + lr) * ld + k0 + lk);
     if (nt == 0) {
@@ -132,20 +158,36 @@ __global__ void __launch_bounds__(64) wgrad_gemm(const u16* __restrict__ At, con
 }
 
 // Sum of the splits into the parameter-shaped gradient: rows x cols of the padded product,
-// keeping rows < keep_r and columns < keep_c, row-major at dst; bias sums to dst_b.
-__global__ void reduce_splits(const float* __restrict__ part, const float* __restrict__ bpart, int ns, int M, int N,
-                              int keep_r, int keep_c, float* __restrict__ dst, float* __restrict__ dst_b) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < keep_r * keep_c) {
-    const int r = i / keep_c, c = i % keep_c;
-    double s = 0.0;
-    for (int k = 0; k < ns; ++k) s += part[(size_t)k * M * N + (size_t)r * N + c];
-    dst[i] = (float)s;
+// keeping rows < keep_r and columns < keep_c, row-major at dst; bias sums to dst_b.  Outputs
+// are numbered weights first (keep_r * keep_c), then biases (keep_r); a workgroup takes 64 of
+// them, its four wavefronts sum every fourth split in double, and the four sums are added in
+// a fixed order, so the result does not depend on scheduling.
+__global__ void __launch_bounds__(256) reduce_splits(const float* __restrict__ part, const float* __restrict__ bpart,
+                                                     int ns, int M, int N, int keep_r, int keep_c,
+                                                     float* __restrict__ dst, float* __restrict__ dst_b) {
+  __shared__ double red[4][64];
+  const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + l, nw = keep_r * keep_c;
+  const float* src = nullptr;
+  size_t stride = 0;
+  if (i < nw) {
+    src = part + (size_t)(i / keep_c) * N + i % keep_c;
+    stride = (size_t)M * N;
+  } else if (i < nw + keep_r) {
+    src = bpart + (i - nw);
+    stride = M;
   }
-  if (i < keep_r) {
-    double s = 0.0;
-    for (int k = 0; k < ns; ++k) s += bpart[(size_t)k * M + i];
-    dst_b[i] = (float)s;
+  double acc = 0.0;
+  if (src) {
+#pragma unroll 4
+    for (int k = g; k < ns; k += 4) acc += src[(size_t)k * stride];
+  }
+  red[g][l] = acc;
+  __syncthreads();
+  if (g == 0 && src) {
+    const double t = (red[0][l] + red[1][l]) + (red[2][l] + red[3][l]);
+    if (i < nw) dst[i] = (float)t;
+    else dst_b[i - nw] = (float)t;
   }
 }
 
@@ -191,6 +233,31 @@ __global__ void __launch_bounds__(256) loss_grad(const float* __restrict__ Y, co
     __syncthreads();
   }
   if (threadIdx.x == 0) lpart[blockIdx.x] = red[0];
+}
+
+// Rows of a mini-batch: Fb[r] = F[perm[b0 + r]], Tb[r] = T[perm[b0 + r]], r < nb.  An index
+// outside 0..n-1 raises *bad and reads row 0 instead.
+__global__ void gather_batch(const double* __restrict__ F, const double* __restrict__ T, const int* __restrict__ perm,
+                             int n, int b0, int nb, double* __restrict__ Fb, double* __restrict__ Tb,
+                             int* __restrict__ bad) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb * (NI + NO)) return;
+  const int r = i / (NI + NO), c = i % (NI + NO);
+  int p = perm[b0 + r];
+  if (p < 0 || p >= n) {
+    *bad = 1;
+    p = 0;
+  }
+  if (c < NI) Fb[(size_t)r * NI + c] = F[(size_t)p * NI + c];
+  else Tb[(size_t)r * NO + (c - NI)] = T[(size_t)p * NO + (c - NI)];
+}
+
+// acc += (block loss sums added in block order) / n: one batch's loss, kept on the device.
+__global__ void add_loss(const double* __restrict__ lpart, int nblk, int n, double* __restrict__ acc) {
+  if (threadIdx.x != 0) return;
+  double L = 0.0;
+  for (int k = 0; k < nblk; ++k) L += lpart[k];
+  acc[0] += L / n;
 }
 
 // Adam on the float32 master weights (bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t).
@@ -327,6 +394,8 @@ struct dm_mlp {
   u16 *X = nullptr, *XT = nullptr, *H1 = nullptr, *H1T = nullptr, *H2 = nullptr, *H2T = nullptr;
   u16 *dY = nullptr, *dYT = nullptr, *dH2 = nullptr, *dH2T = nullptr, *dH1T = nullptr;
   double *mean = nullptr, *sd = nullptr, *ystd = nullptr, *lpart = nullptr, *moments = nullptr;
+  double *Fb = nullptr, *Tb = nullptr, *lacc = nullptr;   // gathered mini-batch, epoch loss sum
+  int* bad = nullptr;                                      // raised by an out-of-range batch index
   int t = 0;
 };
 
@@ -352,13 +421,13 @@ dm_status check_rows(const dm_mlp* m, int n) {
 dm_status forward_rows(dm_mlp* m, const double* F, int n, int rows) {
   hipStream_t st = m->stream;
   hipLaunchKernelGGL(standardise, dim3((rows + 255) / 256), dim3(256), 0, st, F, n, rows, m->mean, m->sd, m->X, m->XT);
-  const dim3 g(rows / ROWS_WG), b(256);
-  hipLaunchKernelGGL((row_gemm<KX, NH, EPI_HIDDEN>), g, b, 0, st, m->X, m->W1b, m->P + OFF_B1, nullptr, rows, m->H1,
-                     m->H1T, nullptr);
-  hipLaunchKernelGGL((row_gemm<NH, NH, EPI_HIDDEN>), g, b, 0, st, m->H1, m->W2b, m->P + OFF_B2, nullptr, rows, m->H2,
-                     m->H2T, nullptr);
-  hipLaunchKernelGGL((row_gemm<NH, NOP, EPI_OUTPUT>), g, b, 0, st, m->H2, m->W3b, m->P + OFF_B3, nullptr, rows,
-                     nullptr, nullptr, m->Y);
+  const dim3 b(256);
+  hipLaunchKernelGGL((row_gemm<KX, NH, EPI_HIDDEN>), dim3(row_grid<NH>(rows)), b, 0, st, m->X, m->W1b, m->P + OFF_B1,
+                     nullptr, rows, m->H1, m->H1T, nullptr);
+  hipLaunchKernelGGL((row_gemm<NH, NH, EPI_HIDDEN>), dim3(row_grid<NH>(rows)), b, 0, st, m->H1, m->W2b, m->P + OFF_B2,
+                     nullptr, rows, m->H2, m->H2T, nullptr);
+  hipLaunchKernelGGL((row_gemm<NH, NOP, EPI_OUTPUT>), dim3(row_grid<NOP>(rows)), b, 0, st, m->H2, m->W3b,
+                     m->P + OFF_B3, nullptr, rows, nullptr, nullptr, m->Y);
   MH(hipGetLastError());
   return DM_OK;
 }
@@ -370,34 +439,42 @@ dm_status prepare(dm_mlp* m) {
   return DM_OK;
 }
 
+// Adam step on m->G (bias corrections from the step count), then the bfloat16 weight copies.
+dm_status adam_step(dm_mlp* m, float lr) {
+  m->t += 1;
+  const float c1 = (float)(1.0 - std::pow(0.9, m->t)), c2 = (float)(1.0 - std::pow(0.999, m->t));
+  hipLaunchKernelGGL(adam, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->P, m->M, m->V, m->G, NPARAM, lr,
+                     0.9f, 0.999f, 1e-8f, c1, c2);
+  MH(hipGetLastError());
+  return prepare(m);
+}
+
 // Loss and gradients into m->G for rows 0..n-1 of raw features F and raw targets T.
 dm_status gradients(dm_mlp* m, const double* F, const double* T, int n, double* loss) {
-  const int rows = rup(n, ROWS_WG);
+  const int rows = rup(n, ROWS_PAD);
   dm_status s;
   if ((s = forward_rows(m, F, n, rows)) != DM_OK) return s;
   hipStream_t st = m->stream;
   const int nb = (rows + 255) / 256;
   hipLaunchKernelGGL(loss_grad, dim3(nb), dim3(256), 0, st, m->Y, T, m->ystd, n, rows, m->dY, m->dYT, m->lpart);
-  const dim3 g(rows / ROWS_WG), b(256);
-  hipLaunchKernelGGL((row_gemm<KX, NH, EPI_DGRAD>), g, b, 0, st, m->dY, m->W3tb, nullptr, m->H2, rows, m->dH2,
-                     m->dH2T, nullptr);
-  hipLaunchKernelGGL((row_gemm<NH, NH, EPI_DGRAD>), g, b, 0, st, m->dH2, m->W2tb, nullptr, m->H1, rows, nullptr,
-                     m->dH1T, nullptr);
-  const int ns = (rows + WG_CHUNK - 1) / WG_CHUNK;
+  const dim3 b(256);
+  hipLaunchKernelGGL((row_gemm<KX, NH, EPI_DGRAD>), dim3(row_grid<NH>(rows)), b, 0, st, m->dY, m->W3tb, nullptr,
+                     m->H2, rows, m->dH2, m->dH2T, nullptr);
+  hipLaunchKernelGGL((row_gemm<NH, NH, EPI_DGRAD>), dim3(row_grid<NH>(rows)), b, 0, st, m->dH2, m->W2tb, nullptr,
+                     m->H1, rows, nullptr, m->dH1T, nullptr);
   float* G = m->G;
-  auto red = [&](int M_, int N_, int kr, int kc, float* dst, float* dstb) {
-    hipLaunchKernelGGL(reduce_splits, dim3((kr * kc + 255) / 256), dim3(256), 0, st, m->part, m->bpart, ns, M_, N_, kr,
-                       kc, dst, dstb);
+  // One weight-gradient product: tiles = (M / 16) x (N / min(N, 64)) output blocks.
+  auto wgrad = [&](auto kern, int tiles, const u16* At, const u16* Bt, int M_, int N_, int kr, int kc, float* dst,
+                   float* dstb) {
+    int chunk, ns;
+    split_plan(rows, tiles, &chunk, &ns);
+    hipLaunchKernelGGL(kern, dim3(tiles, ns), dim3(64), 0, st, At, Bt, rows, chunk, m->part, m->bpart);
+    hipLaunchKernelGGL(reduce_splits, dim3((kr * kc + kr + 63) / 64), dim3(256), 0, st, m->part, m->bpart, ns, M_, N_,
+                       kr, kc, dst, dstb);
   };
-  hipLaunchKernelGGL((wgrad_gemm<NH, NH>), dim3((NH / 16) * (NH / 64), ns), dim3(64), 0, st, m->dH2T, m->H1T, rows,
-                     m->part, m->bpart);
-  red(NH, NH, NH, NH, G + OFF_W2, G + OFF_B2);
-  hipLaunchKernelGGL((wgrad_gemm<NH, KX>), dim3((NH / 16) * 1, ns), dim3(64), 0, st, m->dH1T, m->XT, rows, m->part,
-                     m->bpart);
-  red(NH, KX, NH, NI, G + OFF_W1, G + OFF_B1);
-  hipLaunchKernelGGL((wgrad_gemm<NOP, NH>), dim3(1 * (NH / 64), ns), dim3(64), 0, st, m->dYT, m->H2T, rows, m->part,
-                     m->bpart);
-  red(NOP, NH, NO, NH, G + OFF_W3, G + OFF_B3);
+  wgrad(wgrad_gemm<NH, NH>, (NH / 16) * (NH / 64), m->dH2T, m->H1T, NH, NH, NH, NH, G + OFF_W2, G + OFF_B2);
+  wgrad(wgrad_gemm<NH, KX>, (NH / 16) * 1, m->dH1T, m->XT, NH, KX, NH, NI, G + OFF_W1, G + OFF_B1);
+  wgrad(wgrad_gemm<NOP, NH>, 1 * (NH / 64), m->dYT, m->H2T, NOP, NH, NO, NH, G + OFF_W3, G + OFF_B3);
   MH(hipGetLastError());
   if (loss) {
     std::vector<double> lp(nb);
@@ -423,17 +500,17 @@ dm_status dm_mlp_create(int device, void* stream, int max_rows, dm_mlp** out) {
   dm_mlp* m = new dm_mlp();
   m->device = device;
   m->stream = (hipStream_t)stream;
-  m->max_rows = rup(max_rows, ROWS_WG);
+  m->max_rows = rup(max_rows, ROWS_PAD);
   const size_t R = m->max_rows;
-  const int ns = (m->max_rows + WG_CHUNK - 1) / WG_CHUNK;
   dm_status s = DM_OK;
   auto A = [&](auto** p, size_t n) { if (s == DM_OK) s = malloc_n(m, p, n); };
   A(&m->P, NPARAM); A(&m->M, NPARAM); A(&m->V, NPARAM); A(&m->G, NPARAM); A(&m->Y, R * NO);
-  A(&m->part, (size_t)ns * NH * NH); A(&m->bpart, (size_t)ns * NH);
+  A(&m->part, (size_t)NS_MAX * NH * NH); A(&m->bpart, (size_t)NS_MAX * NH);
   A(&m->W1b, NH * KX); A(&m->W2b, NH * NH); A(&m->W2tb, NH * NH); A(&m->W3b, NOP * NH); A(&m->W3tb, NH * KX);
   A(&m->X, R * KX); A(&m->XT, R * KX); A(&m->H1, R * NH); A(&m->H1T, R * NH); A(&m->H2, R * NH); A(&m->H2T, R * NH);
   A(&m->dY, R * KX); A(&m->dYT, R * NOP); A(&m->dH2, R * NH); A(&m->dH2T, R * NH); A(&m->dH1T, R * NH);
   A(&m->mean, NI); A(&m->sd, NI); A(&m->ystd, NO); A(&m->lpart, R / 256 + 1); A(&m->moments, 2 * (NI + NO));
+  A(&m->Fb, R * NI); A(&m->Tb, R * NO); A(&m->lacc, 1); A(&m->bad, 1);
   if (s != DM_OK) { dm_mlp_destroy(m); return s; }
   std::vector<double> one(NI, 1.0);
   if (hipMemcpy(m->sd, one.data(), sizeof(double) * NI, hipMemcpyHostToDevice) != hipSuccess ||
@@ -510,7 +587,7 @@ dm_status dm_mlp_forward(dm_mlp* m, const double* F, int n, float* Y) {
   if ((s = check_rows(m, n)) != DM_OK) return s;
   if (!F || !Y) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_forward: null argument");
   MH(hipSetDevice(m->device));
-  if ((s = forward_rows(m, F, n, rup(n, ROWS_WG))) != DM_OK) return s;
+  if ((s = forward_rows(m, F, n, rup(n, ROWS_PAD))) != DM_OK) return s;
   MH(hipMemcpyAsync(Y, m->Y, sizeof(float) * NO * (size_t)n, hipMemcpyDeviceToDevice, m->stream));
   MH(hipStreamSynchronize(m->stream));
   return DM_OK;
@@ -533,12 +610,35 @@ dm_status dm_mlp_train_step(dm_mlp* m, const double* F, const double* T, int n, 
   if (!F || !T || !(lr > 0)) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_train_step: bad arguments");
   MH(hipSetDevice(m->device));
   if ((s = gradients(m, F, T, n, loss)) != DM_OK) return s;
-  m->t += 1;
-  const float c1 = (float)(1.0 - std::pow(0.9, m->t)), c2 = (float)(1.0 - std::pow(0.999, m->t));
-  hipLaunchKernelGGL(adam, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->P, m->M, m->V, m->G, NPARAM, lr,
-                     0.9f, 0.999f, 1e-8f, c1, c2);
-  MH(hipGetLastError());
-  return prepare(m);
+  return adam_step(m, lr);
+}
+
+dm_status dm_mlp_train_epoch(dm_mlp* m, const double* F, const double* T, const int* perm, int n, int batch,
+                             float lr, double* mean_loss) {
+  dm_status s;
+  if ((s = check_rows(m, batch)) != DM_OK) return s;
+  if (!F || !T || !perm || batch > n || !(lr > 0)) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_train_epoch: bad arguments");
+  MH(hipSetDevice(m->device));
+  hipStream_t st = m->stream;
+  MH(hipMemsetAsync(m->lacc, 0, sizeof(double), st));
+  MH(hipMemsetAsync(m->bad, 0, sizeof(int), st));
+  const int nbatch = n / batch, nblk = (rup(batch, ROWS_PAD) + 255) / 256;
+  const int items = batch * (NI + NO);
+  for (int k = 0; k < nbatch; ++k) {
+    hipLaunchKernelGGL(gather_batch, dim3((items + 255) / 256), dim3(256), 0, st, F, T, perm, n, k * batch, batch,
+                       m->Fb, m->Tb, m->bad);
+    if ((s = gradients(m, m->Fb, m->Tb, batch, nullptr)) != DM_OK) return s;
+    hipLaunchKernelGGL(add_loss, dim3(1), dim3(64), 0, st, m->lpart, nblk, batch, m->lacc);
+    if ((s = adam_step(m, lr)) != DM_OK) return s;
+  }
+  double L = 0.0;
+  int bad = 0;
+  MH(hipMemcpyAsync(&L, m->lacc, sizeof(double), hipMemcpyDeviceToHost, st));
+  MH(hipMemcpyAsync(&bad, m->bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  MH(hipStreamSynchronize(st));
+  if (bad) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_train_epoch: perm holds an index outside 0..n-1");
+  if (mean_loss) *mean_loss = L / nbatch;
+  return DM_OK;
 }
 
 void dm_mlp_destroy(dm_mlp* m) {

@@ -45,24 +45,19 @@ def collect(sim, dt, steps, every=1):
 
 
 def train(net: Mlp, F, T, epochs=2, batch=8192, lr=1e-3, seed=0, log=None):
-    """Fit the standardisation on (F, T), then Adam over shuffled mini-batches.  Returns the
-    mean loss of each epoch."""
+    """Fit the standardisation on (F, T), then Adam over shuffled mini-batches (one library
+    call per epoch; the shuffle is torch's seeded randperm).  Returns the mean loss of each
+    epoch."""
     import torch
     net.fit_normalisation(F, T)
     g = torch.Generator(device=F.device)
     g.manual_seed(seed)
     n = F.shape[0]
+    F, T = F.contiguous(), T.contiguous()
     hist = []
     for e in range(epochs):
-        perm = torch.randperm(n, generator=g, device=F.device)
-        tot, cnt = 0.0, 0
-        for b in range(0, n - batch + 1, batch):
-            idx = perm[b:b + batch]
-            Fb = F.index_select(0, idx).contiguous()
-            Tb = T.index_select(0, idx).contiguous()
-            tot += net.train_step(Fb, Tb, lr)
-            cnt += 1
-        hist.append(tot / max(cnt, 1))
+        perm = torch.randperm(n, generator=g, device=F.device).to(torch.int32)
+        hist.append(net.train_epoch(F, T, perm, batch, lr))
         if log:
             log(f"epoch {e}: loss {hist[-1]:.4e}")
     return hist

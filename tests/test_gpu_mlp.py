@@ -116,6 +116,37 @@ def test_adam_step_applies_the_update_rule(dm):
             assert np.abs(got[k] - cur[k]).max() <= 1e-6 * max(1.0, np.abs(cur[k]).max()), (t, k)
 
 
+def test_train_epoch_equals_its_steps(dm):
+    """One library call per epoch gives the same weights, bit for bit, as the same mini-batches
+    fed to train_step one at a time, and the mean of their losses; an index outside 0..n-1 in
+    the order is reported as an error."""
+    import torch
+    n, batch = 5000, 1024                      # four batches; the last 904 entries are unused
+    F, T, mean, std, scale = raw_case(n, 7)
+    p = OM.init_params(14)
+    Fd, Td = torch.tensor(F, device="cuda"), torch.tensor(T, device="cuda")
+    order = np.random.Generator(np.random.PCG64(8)).permutation(n)
+    perm = torch.tensor(order, dtype=torch.int32, device="cuda")
+    a, b = dm.Mlp(batch), dm.Mlp(batch)
+    for net in (a, b):
+        net.set_params(flat(p))
+        net.set_normalisation(mean, std, scale)
+    La = a.train_epoch(Fd, Td, perm, batch, 1e-3)
+    losses = []
+    for k in range(n // batch):
+        idx = torch.tensor(order[k * batch:(k + 1) * batch], device="cuda")
+        losses.append(b.train_step(Fd[idx].contiguous(), Td[idx].contiguous(), 1e-3))
+    say(f"epoch loss {La:.6e}, mean of steps {np.mean(losses):.6e}")
+    assert np.array_equal(a.get_params(), b.get_params())
+    assert abs(La - np.mean(losses)) <= 1e-12 * abs(La)
+    bad = perm.clone()
+    bad[3] = n
+    with pytest.raises(dm.DmError):
+        a.train_epoch(Fd, Td, bad, batch, 1e-3)
+    with pytest.raises(dm.DmError):
+        a.train_epoch(Fd, Td, perm, 2 * batch, 1e-3)   # batch above the network's row capacity
+
+
 def test_features_and_targets_match_oracle(dm):
     import torch
     d = W.rod_batch(6, seed=4, nmin=3, nmax=40)
