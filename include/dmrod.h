@@ -260,7 +260,8 @@ dm_status dm_mlp_get_params(dm_mlp* net, float* params, int on_device);
 dm_status dm_mlp_set_normalisation(dm_mlp* net, const double* mean, const double* std, const double* scale);
 dm_status dm_mlp_get_normalisation(dm_mlp* net, double* mean, double* std, double* scale);
 /* Mean and standard deviation of each feature and the root-mean-square of each target
- * component over n rows of raw features F and targets T. */
+ * component over n >= 2 rows of raw features F [n][20] (device, 16-byte aligned) and targets
+ * T [n][3] (device). */
 dm_status dm_mlp_fit_normalisation(dm_mlp* net, const double* F, const double* T, int n);
 /* Y [n][3] (float32): the network's standardised output for raw features F [n][20]. */
 dm_status dm_mlp_forward(dm_mlp* net, const double* F, int n, float* Y);

@@ -294,25 +294,71 @@ __global__ void prepare_weights(const float* __restrict__ P, u16* __restrict__ W
   }
 }
 
-// Sums and sums of squares of features and targets over a data set, one block per column.
-__global__ void column_moments(const double* __restrict__ F, const double* __restrict__ T, int n,
-                               double* __restrict__ out /*[23][2]*/) {
-  __shared__ double s1[256], s2[256];
-  const int c = blockIdx.x;
-  double a = 0.0, b = 0.0;
-  for (int r = threadIdx.x; r < n; r += blockDim.x) {
-    const double x = c < NI ? F[(size_t)r * NI + c] : T[(size_t)r * NO + c - NI];
-    a += x;
-    b += x * x;
+// Sums and sums of squares of the 23 feature and target columns over a data set, in two
+// passes: each of MOM_BLOCKS workgroups reads whole rows in a grid-stride loop (so the rows
+// are read once, in order) and writes its partial sums part[b][c][0..1]; then one workgroup
+// adds the partials.
+constexpr int MOM_BLOCKS = 1024, NC = NI + NO;
+
+__global__ void __launch_bounds__(256) column_moments(const double* __restrict__ F, const double* __restrict__ T,
+                                                      int n, double* __restrict__ part) {
+  __shared__ double red[4][NC][2];
+  double a[NC], q[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) a[c] = q[c] = 0.0;
+  for (size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x; r < (size_t)n; r += (size_t)gridDim.x * blockDim.x) {
+    const double2* f = reinterpret_cast<const double2*>(F + r * NI);   // rows of 160 bytes
+#pragma unroll
+    for (int c = 0; c < NI / 2; ++c) {
+      const double2 x = f[c];
+      a[2 * c] += x.x;
+      q[2 * c] += x.x * x.x;
+      a[2 * c + 1] += x.y;
+      q[2 * c + 1] += x.y * x.y;
+    }
+#pragma unroll
+    for (int c = 0; c < NO; ++c) {
+      const double x = T[r * NO + c];
+      a[NI + c] += x;
+      q[NI + c] += x * x;
+    }
   }
-  s1[threadIdx.x] = a;
-  s2[threadIdx.x] = b;
+  const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    double x = a[c], y = q[c];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      x += __shfl_xor(x, o, 64);
+      y += __shfl_xor(y, o, 64);
+    }
+    if (l == 0) {
+      red[w][c][0] = x;
+      red[w][c][1] = y;
+    }
+  }
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) { s1[threadIdx.x] += s1[threadIdx.x + o]; s2[threadIdx.x] += s2[threadIdx.x + o]; }
-    __syncthreads();
+  if (threadIdx.x < 2 * NC) {
+    const int c = threadIdx.x >> 1, k = threadIdx.x & 1;
+    part[((size_t)blockIdx.x * NC + c) * 2 + k] = (red[0][c][k] + red[1][c][k]) + (red[2][c][k] + red[3][c][k]);
   }
-  if (threadIdx.x == 0) { out[2 * c] = s1[0]; out[2 * c + 1] = s2[0]; }
+}
+
+// Total of the partials: eight wavefronts each add every eighth block's partials, and the
+// eight sums are added in a fixed order.
+__global__ void __launch_bounds__(512) moments_total(const double* __restrict__ part, int nblk,
+                                                     double* __restrict__ out /*[23][2]*/) {
+  __shared__ double red[8][2 * NC];
+  const int i = threadIdx.x & 63, g = threadIdx.x >> 6;
+  double s = 0.0;
+  if (i < 2 * NC) {
+#pragma unroll 8
+    for (int b = g; b < nblk; b += 8) s += part[(size_t)b * 2 * NC + i];
+    red[g][i] = s;
+  }
+  __syncthreads();
+  if (g == 0 && i < 2 * NC)
+    out[i] = ((red[0][i] + red[1][i]) + (red[2][i] + red[3][i])) + ((red[4][i] + red[5][i]) + (red[6][i] + red[7][i]));
 }
 
 // ---------------------------------------------------------------------------
@@ -396,6 +442,7 @@ struct dm_mlp {
   double *mean = nullptr, *sd = nullptr, *ystd = nullptr, *lpart = nullptr, *moments = nullptr;
   double *Fb = nullptr, *Tb = nullptr, *lacc = nullptr;   // gathered mini-batch, epoch loss sum
   int* bad = nullptr;                                      // raised by an out-of-range batch index
+  double* mpart = nullptr;                                 // per-workgroup column moments
   int t = 0;
 };
 
@@ -511,6 +558,7 @@ dm_status dm_mlp_create(int device, void* stream, int max_rows, dm_mlp** out) {
   A(&m->dY, R * KX); A(&m->dYT, R * NOP); A(&m->dH2, R * NH); A(&m->dH2T, R * NH); A(&m->dH1T, R * NH);
   A(&m->mean, NI); A(&m->sd, NI); A(&m->ystd, NO); A(&m->lpart, R / 256 + 1); A(&m->moments, 2 * (NI + NO));
   A(&m->Fb, R * NI); A(&m->Tb, R * NO); A(&m->lacc, 1); A(&m->bad, 1);
+  A(&m->mpart, (size_t)MOM_BLOCKS * 2 * (NI + NO));
   if (s != DM_OK) { dm_mlp_destroy(m); return s; }
   std::vector<double> one(NI, 1.0);
   if (hipMemcpy(m->sd, one.data(), sizeof(double) * NI, hipMemcpyHostToDevice) != hipSuccess ||
@@ -565,8 +613,11 @@ dm_status dm_mlp_get_normalisation(dm_mlp* m, double* mean, double* sd, double* 
 
 dm_status dm_mlp_fit_normalisation(dm_mlp* m, const double* F, const double* T, int n) {
   if (!m || !F || !T || n < 2) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_fit_normalisation: bad arguments");
+  if (reinterpret_cast<uintptr_t>(F) % 16 != 0)
+    return mfail(DM_ERR_INVALID_ARG, "dm_mlp_fit_normalisation: F is not 16-byte aligned");
   MH(hipSetDevice(m->device));
-  hipLaunchKernelGGL(column_moments, dim3(NI + NO), dim3(256), 0, m->stream, F, T, n, m->moments);
+  hipLaunchKernelGGL(column_moments, dim3(MOM_BLOCKS), dim3(256), 0, m->stream, F, T, n, m->mpart);
+  hipLaunchKernelGGL(moments_total, dim3(1), dim3(512), 0, m->stream, m->mpart, MOM_BLOCKS, m->moments);
   MH(hipGetLastError());
   std::vector<double> mo(2 * (NI + NO));
   MH(hipMemcpyAsync(mo.data(), m->moments, sizeof(double) * mo.size(), hipMemcpyDeviceToHost, m->stream));
