@@ -1,4 +1,5 @@
-"""Build libdmrod.so (the HIP kernels and the C++ host runtime) for gfx950 with hipcc."""
+"""Build libdmrod.so (the HIP kernels and the C++ host runtime) and the dm_peaks measurement
+program for gfx950 with hipcc."""
 from __future__ import annotations
 
 import os
@@ -8,6 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdmrod.so")
+PEAKS = os.path.join(HERE, "dm_peaks")
 SOURCES = ["dm_kernels.hip", "dm_mlp.hip", "dm_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -28,7 +30,23 @@ def build(verbose: bool = False) -> str:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building libdmrod.so")
     os.replace(tmp, LIB)
+    build_peaks(verbose)
     return LIB
+
+
+def build_peaks(verbose: bool = False) -> str:
+    """Compile the standalone ceiling-measurement program (FP64 FMA, HBM copy, BF16 MFMA)."""
+    flags = [f for f in FLAGS if f not in ("-fPIC", "-shared")]
+    tmp = PEAKS + ".tmp"
+    cmd = [HIPCC, *flags, os.path.join(CSRC, "dm_peaks.hip"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building dm_peaks")
+    os.replace(tmp, PEAKS)
+    return PEAKS
 
 
 if __name__ == "__main__":
