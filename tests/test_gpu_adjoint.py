@@ -134,9 +134,9 @@ def test_autograd_function_and_a_descent_step(dm, golden_desc):
     assert np.linalg.norm(got - ref) / np.linalg.norm(ref) < 1e-6
     # one gradient step along -grad lowers the loss
     with torch.no_grad():
-        k2 = k - (0.1 * float(loss) / float((k.grad ** 2).sum())) * k.grad
+        k2 = k - (0.1 * loss.item() / (k.grad ** 2).sum().item()) * k.grad
     loss2 = ((dm.tip_trajectory(k2, sim, start, d["dt"], T, ckpt_every=10) - target) ** 2).sum()
-    assert float(loss2) < float(loss)
+    assert loss2.item() < loss.item()
 
 
 def test_adjoint_rejects_unsupported_and_out_of_order_calls(dm):
