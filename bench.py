@@ -27,6 +27,10 @@ METRIC = "node-steps/s, batched implicit DER at 1e-9 residual; plain vs warm-sta
 # operation count of the method).
 FLOPS_PER_NODE_ITER = 4.0e3
 PEAK_FP64_VALU_TFLOPS = 78.6          # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
+PEAK_BF16_MFMA_TFLOPS = 2500.0        # dense BF16 matrix-core peak, published
+# 20-256-256-3 network, per row of a training step: forward 2 (20*256 + 256*256 + 256*3),
+# input gradients of layers 3 and 2: 2 (256*3 + 256*256), weight gradients 2 (20*256 + 256*256 + 3*256)
+TRAIN_FLOPS_PER_ROW = 2 * (20 * 256 + 256 * 256 + 256 * 3) * 2 + 2 * (256 * 3 + 256 * 256)
 KERNEL_SOURCES = ["paper_2311_18126_amd/csrc/dm_kernels.hip", "paper_2311_18126_amd/csrc/dm_math.h",
                   "paper_2311_18126_amd/csrc/dm_layout.h", "paper_2311_18126_amd/csrc/dm_warm.h",
                   "paper_2311_18126_amd/csrc/dm_bf16.h"]
@@ -141,8 +145,9 @@ def warm_start_section(dm, steps, log):
     net = dm.Mlp(max_rows=max(rows, 65536))
     net.set_params(WS.init_params(0))
     t0 = time.perf_counter()
-    hist = WS.train(net, F, T, epochs=3, batch=8192, lr=1e-3)
-    hist += WS.train(net, F, T, epochs=2, batch=8192, lr=3e-4)
+    batch, epochs = 8192, (3, 2)
+    hist = WS.train(net, F, T, epochs=epochs[0], batch=batch, lr=1e-3)
+    hist += WS.train(net, F, T, epochs=epochs[1], batch=batch, lr=3e-4)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     log(f"warm start: {F.shape[0]} training rows, collect {t_collect:.1f} s, train {t_train:.1f} s, "
@@ -153,6 +158,11 @@ def warm_start_section(dm, steps, log):
            "steps": steps, "training": "1024-rod batch (seed 0), steps 101..200, every second step",
            "training_rows": n_train, "train_s": t_train,
            "final_training_loss": hist[-1]}
+    # matrix-core throughput of training (whole batches only)
+    train_flops = TRAIN_FLOPS_PER_ROW * (n_train // batch) * batch * sum(epochs)
+    out["training_mfma"] = {"bound": "mfma", "achieved": train_flops / t_train / 1e12, "peak": PEAK_BF16_MFMA_TFLOPS,
+                            "unit": "TFLOP/s", "frac": train_flops / t_train / 1e12 / PEAK_BF16_MFMA_TFLOPS,
+                            "algorithmic_flops": float(train_flops)}
     for name, mode in (("plain", 0), ("explicit_predictor", 1), ("extrapolation", 3), ("network", 2)):
         sim = dm.sim_from_description(ev)
         sim.set_warm_start(net if mode == 2 else None, mode)
