@@ -30,7 +30,8 @@ PEAK_FP64_VALU_TFLOPS = 78.6          # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2
 PEAK_BF16_MFMA_TFLOPS = 2500.0        # dense BF16 matrix-core peak, published
 # 20-256-256-3 network, per row of a training step: forward 2 (20*256 + 256*256 + 256*3),
 # input gradients of layers 3 and 2: 2 (256*3 + 256*256), weight gradients 2 (20*256 + 256*256 + 3*256)
-TRAIN_FLOPS_PER_ROW = 2 * (20 * 256 + 256 * 256 + 256 * 3) * 2 + 2 * (256 * 3 + 256 * 256)
+INFER_FLOPS_PER_ROW = 2 * (20 * 256 + 256 * 256 + 256 * 3)
+TRAIN_FLOPS_PER_ROW = 2 * INFER_FLOPS_PER_ROW + 2 * (256 * 3 + 256 * 256)
 KERNEL_SOURCES = ["paper_2311_18126_amd/csrc/dm_kernels.hip", "paper_2311_18126_amd/csrc/dm_math.h",
                   "paper_2311_18126_amd/csrc/dm_layout.h", "paper_2311_18126_amd/csrc/dm_warm.h",
                   "paper_2311_18126_amd/csrc/dm_bf16.h"]
@@ -123,6 +124,29 @@ def timed_steps(sim, dt, steps):
     return st, time.perf_counter() - t0
 
 
+def inference_rate(sim, dt, reps=10):
+    """Matrix-core throughput of the network's guess for every node of the batch, run by
+    dm_ws_predict with the step kernel's own device code (features, three layers, output).
+    Each call is bracketed by events on the simulation's stream (torch's default stream); the
+    shortest call is kept, and it still includes one launch latency."""
+    import torch
+    rows = sim.ws_rows
+    buf = torch.empty((rows, 3), dtype=torch.float64, device="cuda")
+    sim.ws_predict(dt, buf)
+    best = float("inf")
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sim.ws_predict(dt, buf)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) / 1e3)
+    flops = INFER_FLOPS_PER_ROW * rows
+    return {"bound": "mfma", "achieved": flops / best / 1e12, "peak": PEAK_BF16_MFMA_TFLOPS, "unit": "TFLOP/s",
+            "frac": flops / best / 1e12 / PEAK_BF16_MFMA_TFLOPS, "algorithmic_flops": float(flops),
+            "rows": int(rows), "ms_per_call": best * 1e3}
+
+
 def warm_start_section(dm, steps, log):
     """Learned warm start: a network trained on the 1024-rod batch's own trajectories (seed 0,
     steps 101..200, every second one: past the start-up transient, whose large targets would
@@ -173,6 +197,7 @@ def warm_start_section(dm, steps, log):
         out[f"{name}_iters_per_step"] = float(st["iters"].sum() / st["iters"].size / steps)
         if mode == 2:
             out["network_fallbacks"] = int(st["fallbacks"].sum())
+            out["inference_mfma"] = inference_rate(sim, ev["dt"])
         sim.close()
     net.close()
     return out
