@@ -1,8 +1,9 @@
 """GPU parity of the implicit-midpoint integrator (dm_set_integrator) against the oracle's
 midpoint step: the cantilever against stored oracle trajectories (1e-9 after one step, 1e-6
 after 50: the undamped swing outruns Newton near step 95 at this dt), a star with contact, friction and actuation at the midpoint time, uneven small
-rods, a free damped rod with loads and sampled rods of the full 1024-rod batch against the
-oracle stepped here, and the rejected uses."""
+rods, a free damped rod with loads, the paper's validation workloads at its time steps and
+sampled rods of the full 1024-rod batch against the oracle stepped here, and the rejected
+uses."""
 import os
 
 import numpy as np
@@ -105,6 +106,35 @@ def test_free_rod_with_damping_and_loads_matches_live_oracle(dm):
     assert rel(x, ost.x.numpy()) < 1e-9
     assert np.abs(th - ost.theta.numpy()).max() < 1e-8
     assert rel(om, ost.omega.numpy()) < 1e-6
+
+
+@pytest.mark.parametrize("case", ["a1", "b2", "c"])
+def test_paper_workloads_match_live_oracle(dm, case):
+    """The paper's validation workloads at its own time steps: the N = 201 cantilever at
+    dt = 0.5 s (a1), the stiff thin helix (b2) and three of the 44 friction rods (c: the two
+    extreme pushes and one below the sliding threshold), a few midpoint steps against the
+    oracle.  Displacements are compared too, since the cantilever moves millimetres."""
+    from oracle import der
+    if case == "a1":
+        d, steps = W.paper_cantilever(E=1e5, dt=0.5, steps=4), 4
+    elif case == "b2":
+        d, steps = W.paper_helix(E=1e9, h=1e-3, dt=3e-3, steps=6), 6
+    else:
+        steps = 6
+        d = W.paper_friction(push=-10.6, steps=steps)
+        d["rods"] = [W.paper_friction(push=p, steps=steps)["rods"][0] for p in (-10.6, 2.0, 10.5)]
+    say(f"case: paper workload {case}, implicit midpoint, {steps} steps, {len(d['rods'])} rods")
+    sim = dm.sim_from_description(d)
+    sim.set_integrator("midpoint")
+    sim.step(d["dt"], steps)
+    for r in range(len(d["rods"])):
+        _, ost, infos, _ = der.simulate(W.subset(d, [r]), steps=steps, polish=1, scheme="midpoint")
+        assert all(i.converged for i in infos), r
+        x, _, _, _ = sim.rod_state(r)
+        ox, x0 = ost.x.numpy(), d["rods"][r]["x0"]
+        say(f"  rod {r}: position {rel(x, ox):.2e}, displacement {rel(x - x0, ox - x0):.2e}")
+        assert rel(x, ox) < 1e-9, (r, rel(x, ox))
+        assert rel(x - x0, ox - x0) < 1e-6, (r, rel(x - x0, ox - x0))
 
 
 def test_full_batch_sampled_rods_match_live_oracle(dm):
