@@ -287,7 +287,8 @@ def paper_table(dm, log):
     midpoint, at its time steps and end times, each timed as one whole simulation in one
     launch, beside the paper's wall times on an 8-core desktop CPU.  Context only: other
     hardware, and the paper states no Newton tolerance (here 1e-9).  A step whose Newton solve
-    fails is redone as two half steps (up to 8 levels); halvings are reported."""
+    fails is redone as two half steps (up to 8 levels); halvings are reported.  The same runs
+    under backward Euler are reported beside them."""
     import torch
 
     import workloads as W
@@ -301,9 +302,9 @@ def paper_table(dm, log):
         ("b2 helix N=100, h=1 mm, E=1e9 Pa, dt=3e-3 s, T=2 s", W.paper_helix(E=1e9, h=1e-3, dt=3e-3, steps=667), 3.18),
         ("c axial friction N=26, 44 pushes in [-10.6, 10.5] N, dt=5e-3 s, T=1.5 s", fr, 1.59),
     ]
-    for name, d, paper_s in cases:
+    def run(d, scheme):
         sim = dm.sim_from_description(d)
-        sim.set_integrator("midpoint")
+        sim.set_integrator(scheme)
         sim.set_adaptive(8)
         start = sim.checkpoint()
         sim.step(d["dt"], 2, allow_failure=True)
@@ -314,14 +315,22 @@ def paper_table(dm, log):
         st = sim.step(d["dt"], steps, allow_failure=True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        sim.close()
+        return wall, float(st["iters"].sum() / st["iters"].size / steps), int(st["halvings"].sum()), \
+            int((st["status"] != 0).sum())
+
+    for name, d, paper_s in cases:
+        steps = int(d["steps"])
+        wall, iters, halv, failed = run(d, "midpoint")
+        e_wall, e_iters, e_halv, e_failed = run(d, "euler")
         nodes = sum(r["x0"].shape[0] for r in d["rods"])
         row = {"workload": name, "integrator": "implicit midpoint", "systems": len(d["rods"]), "steps": steps,
                "wall_s": wall, "paper_wall_s": paper_s, "paper_over_this": paper_s / wall,
-               "node_steps_per_s": nodes * steps / wall,
-               "newton_iters_per_step": float(st["iters"].sum() / st["iters"].size / steps),
-               "halvings": int(st["halvings"].sum()), "failed_systems": int((st["status"] != 0).sum())}
-        sim.close()
-        log(f"paper: {name}: {wall:.3f} s (paper {paper_s} s)")
+               "node_steps_per_s": nodes * steps / wall, "newton_iters_per_step": iters,
+               "halvings": halv, "failed_systems": failed,
+               "backward_euler": {"wall_s": e_wall, "newton_iters_per_step": e_iters, "halvings": e_halv,
+                                  "failed_systems": e_failed}}
+        log(f"paper: {name}: midpoint {wall:.3f} s, backward Euler {e_wall:.3f} s (paper {paper_s} s)")
         print(json.dumps(row), flush=True)
 
 
