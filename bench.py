@@ -3,9 +3,14 @@
 Workload: 1024 independent clamped rods, N ~ U{20..400} nodes (seed 0), L ~ U(0.5, 2) m,
 h ~ U(1e-3, 5e-3) m, E = 10^U(6, 8) Pa, natural curvature ~ N(0, 2^2) 1/m, gravity,
 dt = 1e-3 s, FP64, all rods in one persistent launch.  A "step" is one backward-Euler time
-step of the whole batch.  Prints one JSON line (see the design doc for every field).
+step of the whole batch.  Prints one JSON line: the batch's rate and its FP64 roofline
+(kernel time from HIP events on the launch's stream; HBM bytes from the committed counter
+summary of the same kernel source, else null), the CPU oracle on a bounded sample, and the
+warm start, star, midpoint, adjoint and per-rod figures.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --configs    # one line per benchmark configuration
+    python bench.py --paper      # the paper's validation workloads against its wall times
 """
 from __future__ import annotations
 
@@ -22,9 +27,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "node-steps/s, batched implicit DER at 1e-9 residual; plain vs warm-started"
-# Algorithmic FP64 work of one Newton iteration per rod node: frames, strains, stretch and
-# bend/twist gradients and Hessians, assembly, banded LU and solves, update (closed-form
-# operation count of the method).
+# Algorithmic FP64 work of one Newton iteration per rod node (closed-form operation count of
+# the method): frames ~100, strains ~110, stretch ~100, bend Hessian ~1750, twist ~400, node
+# terms ~20, assembly ~280, banded LU and solves ~1160, update ~10.
 FLOPS_PER_NODE_ITER = 4.0e3
 PEAK_FP64_VALU_TFLOPS = 78.6          # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_BF16_MFMA_TFLOPS = 2500.0        # dense BF16 matrix-core peak, published
