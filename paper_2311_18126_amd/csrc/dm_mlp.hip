@@ -121,14 +121,14 @@ inline void split_plan(int rows, int tiles, int* chunk, int* ns) {
 
 // Partial weight gradients over one split of the batch: part[s][m][n] = sum_k At[m][k] Bt[n][k]
 // over k in split s (rows s * chunk .. min((s + 1) * chunk, ld) - 1), and (for the first
-// column block) bpart[s][m] = sum_k At[m][k].  One wavefront per 16 x NT output block.
+// column block) bpart[s][m] = sum_k At[m][k].  One wavefront per 16 x NT output block `tile`.
 template <int M, int N>
-__global__ void __launch_bounds__(64) wgrad_gemm(const u16* __restrict__ At, const u16* __restrict__ Bt, int ld,
-                                                 int chunk, float* __restrict__ part, float* __restrict__ bpart) {
+__device__ __forceinline__ void wgrad_block(const u16* __restrict__ At, const u16* __restrict__ Bt, int ld, int chunk,
+                                            int tile, int s, float* __restrict__ part, float* __restrict__ bpart) {
   constexpr int NT = N < 64 ? N : 64;
   const int l = threadIdx.x;
-  const int mt = blockIdx.x / (N / NT), nt = blockIdx.x % (N / NT);
-  const int m0 = 16 * mt, n0 = NT * nt, s = blockIdx.y;
+  const int mt = tile / (N / NT), nt = tile % (N / NT);
+  const int m0 = 16 * mt, n0 = NT * nt;
   const int kb = s * chunk, ke = min(kb + chunk, ld);
   const int lr = l & 15, lk = 8 * (l >> 4);
   f32x4 acc[NT / 16];
@@ -157,17 +157,66 @@ __global__ void __launch_bounds__(64) wgrad_gemm(const u16* __restrict__ At, con
   }
 }
 
+// The three weight-gradient products of one backward pass in one launch.  Product p has
+// tiles[p] output blocks and ns[p] splits of chunk[p] rows; its blocks are numbered
+// (split, tile) after those of the products before it.
+struct WgradSet {
+  const u16* At[3];
+  const u16* Bt[3];
+  float* part[3];
+  float* bpart[3];
+  int chunk[3], tiles[3], ns[3];
+};
+
+__global__ void __launch_bounds__(64) wgrad_all(WgradSet w, int ld) {
+  int b = blockIdx.x;
+  if (b < w.tiles[0] * w.ns[0]) {
+    wgrad_block<NH, NH>(w.At[0], w.Bt[0], ld, w.chunk[0], b % w.tiles[0], b / w.tiles[0], w.part[0], w.bpart[0]);
+    return;
+  }
+  b -= w.tiles[0] * w.ns[0];
+  if (b < w.tiles[1] * w.ns[1]) {
+    wgrad_block<NH, KX>(w.At[1], w.Bt[1], ld, w.chunk[1], b % w.tiles[1], b / w.tiles[1], w.part[1], w.bpart[1]);
+    return;
+  }
+  b -= w.tiles[1] * w.ns[1];
+  wgrad_block<NOP, NH>(w.At[2], w.Bt[2], ld, w.chunk[2], b % w.tiles[2], b / w.tiles[2], w.part[2], w.bpart[2]);
+}
+
 // Sum of the splits into the parameter-shaped gradient: rows x cols of the padded product,
 // keeping rows < keep_r and columns < keep_c, row-major at dst; bias sums to dst_b.  Outputs
 // are numbered weights first (keep_r * keep_c), then biases (keep_r); a workgroup takes 64 of
 // them, its four wavefronts sum every fourth split in double, and the four sums are added in
 // a fixed order, so the result does not depend on scheduling.
-__global__ void __launch_bounds__(256) reduce_splits(const float* __restrict__ part, const float* __restrict__ bpart,
-                                                     int ns, int M, int N, int keep_r, int keep_c,
-                                                     float* __restrict__ dst, float* __restrict__ dst_b) {
+struct ReduceJob {
+  const float* part;
+  const float* bpart;
+  int ns, M, N, keep_r, keep_c;
+  float* dst;
+  float* dst_b;
+};
+
+// Workgroups a reduction job needs: 64 outputs each.
+__host__ __device__ inline int reduce_wgs(const ReduceJob& j) { return (j.keep_r * j.keep_c + j.keep_r + 63) / 64; }
+
+// The split sums of the three products in one launch: the workgroups of job p follow those of
+// the jobs before it.
+struct ReduceSet {
+  ReduceJob j[3];
+};
+
+__global__ void __launch_bounds__(256) reduce_all(ReduceSet r) {
   __shared__ double red[4][64];
+  int b = blockIdx.x, p = 0;
+  while (p < 2 && b >= reduce_wgs(r.j[p])) b -= reduce_wgs(r.j[p++]);
+  const ReduceJob& J = r.j[p];
+  const float* __restrict__ part = J.part;
+  const float* __restrict__ bpart = J.bpart;
+  const int ns = J.ns, M = J.M, N = J.N, keep_r = J.keep_r, keep_c = J.keep_c;
+  float* __restrict__ dst = J.dst;
+  float* __restrict__ dst_b = J.dst_b;
   const int l = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + l, nw = keep_r * keep_c;
+  const int i = b * 64 + l, nw = keep_r * keep_c;
   const float* src = nullptr;
   size_t stride = 0;
   if (i < nw) {
@@ -252,25 +301,44 @@ __global__ void gather_batch(const double* __restrict__ F, const double* __restr
   else Tb[(size_t)r * NO + (c - NI)] = T[(size_t)p * NO + (c - NI)];
 }
 
-// acc += (block loss sums added in block order) / n: one batch's loss, kept on the device.
-__global__ void add_loss(const double* __restrict__ lpart, int nblk, int n, double* __restrict__ acc) {
-  if (threadIdx.x != 0) return;
-  double L = 0.0;
-  for (int k = 0; k < nblk; ++k) L += lpart[k];
-  acc[0] += L / n;
-}
+// bfloat16 operand copies of the master weights, as prepare_weights writes them.
+struct WeightCopies {
+  u16 *W1b, *W2b, *W2tb, *W3b, *W3tb;
+};
 
-// Adam on the float32 master weights (bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t).
+// Adam on the float32 master weights (bias corrections c1 = 1 - beta1^t, c2 = 1 - beta2^t),
+// writing each updated weight's bfloat16 copies (the zero padding of the copies is left as
+// prepare_weights wrote it).  If lacc is given, thread 0 also adds the batch loss, the block
+// sums lpart[0..nblk) in block order over nrows, to *lacc.
 __global__ void adam(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v, const float* __restrict__ g,
-                     int n, float lr, float b1, float b2, float eps, float c1, float c2) {
+                     int n, float lr, float b1, float b2, float eps, float c1, float c2, WeightCopies wc,
+                     const double* __restrict__ lpart, int nblk, int nrows, double* __restrict__ lacc) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (lacc && i == 0) {
+    double L = 0.0;
+    for (int k = 0; k < nblk; ++k) L += lpart[k];
+    lacc[0] += L / nrows;
+  }
   if (i >= n) return;
   const float gi = g[i];
   const float mi = b1 * m[i] + (1.0f - b1) * gi;
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  p[i] = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  const float pn = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  p[i] = pn;
+  const u16 h = bf16_bits(pn);
+  if (i < OFF_B1) {
+    wc.W1b[(i / NI) * KX + i % NI] = h;
+  } else if (i >= OFF_W2 && i < OFF_B2) {
+    const int k = i - OFF_W2;
+    wc.W2b[k] = h;
+    wc.W2tb[(k % NH) * NH + k / NH] = h;
+  } else if (i >= OFF_W3 && i < OFF_B3) {
+    const int k = i - OFF_W3;
+    wc.W3b[k] = h;
+    wc.W3tb[(k % NH) * KX + k / NH] = h;
+  }
 }
 
 // bfloat16 operand copies of the master weights: W1 [256][32], W2 [256][256], W2^T, W3 [16][256],
@@ -486,14 +554,17 @@ dm_status prepare(dm_mlp* m) {
   return DM_OK;
 }
 
-// Adam step on m->G (bias corrections from the step count), then the bfloat16 weight copies.
-dm_status adam_step(dm_mlp* m, float lr) {
+// Adam step on m->G (bias corrections from the step count) with the bfloat16 weight copies;
+// with lacc, the batch loss of the last gradient pass (nrows rows) is added to *lacc.
+dm_status adam_step(dm_mlp* m, float lr, int nrows = 0, double* lacc = nullptr) {
   m->t += 1;
   const float c1 = (float)(1.0 - std::pow(0.9, m->t)), c2 = (float)(1.0 - std::pow(0.999, m->t));
+  const WeightCopies wc{m->W1b, m->W2b, m->W2tb, m->W3b, m->W3tb};
+  const int nblk = (rup(std::max(nrows, 1), ROWS_PAD) + 255) / 256;
   hipLaunchKernelGGL(adam, dim3((NPARAM + 255) / 256), dim3(256), 0, m->stream, m->P, m->M, m->V, m->G, NPARAM, lr,
-                     0.9f, 0.999f, 1e-8f, c1, c2);
+                     0.9f, 0.999f, 1e-8f, c1, c2, wc, m->lpart, nblk, nrows, lacc);
   MH(hipGetLastError());
-  return prepare(m);
+  return DM_OK;
 }
 
 // Loss and gradients into m->G for rows 0..n-1 of raw features F and raw targets T.
@@ -510,18 +581,34 @@ dm_status gradients(dm_mlp* m, const double* F, const double* T, int n, double* 
   hipLaunchKernelGGL((row_gemm<NH, NH, EPI_DGRAD>), dim3(row_grid<NH>(rows)), b, 0, st, m->dH2, m->W2tb, nullptr,
                      m->H1, rows, nullptr, m->dH1T, nullptr);
   float* G = m->G;
-  // One weight-gradient product: tiles = (M / 16) x (N / min(N, 64)) output blocks.
-  auto wgrad = [&](auto kern, int tiles, const u16* At, const u16* Bt, int M_, int N_, int kr, int kc, float* dst,
-                   float* dstb) {
-    int chunk, ns;
-    split_plan(rows, tiles, &chunk, &ns);
-    hipLaunchKernelGGL(kern, dim3(tiles, ns), dim3(64), 0, st, At, Bt, rows, chunk, m->part, m->bpart);
-    hipLaunchKernelGGL(reduce_splits, dim3((kr * kc + kr + 63) / 64), dim3(256), 0, st, m->part, m->bpart, ns, M_, N_,
-                       kr, kc, dst, dstb);
-  };
-  wgrad(wgrad_gemm<NH, NH>, (NH / 16) * (NH / 64), m->dH2T, m->H1T, NH, NH, NH, NH, G + OFF_W2, G + OFF_B2);
-  wgrad(wgrad_gemm<NH, KX>, (NH / 16) * 1, m->dH1T, m->XT, NH, KX, NH, NI, G + OFF_W1, G + OFF_B1);
-  wgrad(wgrad_gemm<NOP, NH>, 1 * (NH / 64), m->dYT, m->H2T, NOP, NH, NO, NH, G + OFF_W3, G + OFF_B3);
+  // The three weight-gradient products (W2, W1, W3; tiles = (M / 16) x (N / min(N, 64))), each
+  // with its own split plan and partial-sum region, then their split sums.
+  WgradSet w;
+  ReduceSet r;
+  const u16* At[3] = {m->dH2T, m->dH1T, m->dYT};
+  const u16* Bt[3] = {m->H1T, m->XT, m->H2T};
+  const int Ms[3] = {NH, NH, NOP}, Ns[3] = {NH, KX, NH}, tiles[3] = {(NH / 16) * (NH / 64), NH / 16, NH / 64};
+  const int kr[3] = {NH, NH, NO}, kc[3] = {NH, NI, NH};
+  float* dst[3] = {G + OFF_W2, G + OFF_W1, G + OFF_W3};
+  float* dstb[3] = {G + OFF_B2, G + OFF_B1, G + OFF_B3};
+  float* part = m->part;
+  float* bpart = m->bpart;
+  int wblocks = 0, rblocks = 0;
+  for (int q = 0; q < 3; ++q) {
+    w.At[q] = At[q];
+    w.Bt[q] = Bt[q];
+    w.part[q] = part;
+    w.bpart[q] = bpart;
+    w.tiles[q] = tiles[q];
+    split_plan(rows, tiles[q], &w.chunk[q], &w.ns[q]);
+    r.j[q] = ReduceJob{part, bpart, w.ns[q], Ms[q], Ns[q], kr[q], kc[q], dst[q], dstb[q]};
+    part += (size_t)NS_MAX * Ms[q] * Ns[q];
+    bpart += (size_t)NS_MAX * Ms[q];
+    wblocks += tiles[q] * w.ns[q];
+    rblocks += reduce_wgs(r.j[q]);
+  }
+  hipLaunchKernelGGL(wgrad_all, dim3(wblocks), dim3(64), 0, st, w, rows);
+  hipLaunchKernelGGL(reduce_all, dim3(rblocks), dim3(256), 0, st, r);
   MH(hipGetLastError());
   if (loss) {
     std::vector<double> lp(nb);
@@ -552,7 +639,7 @@ dm_status dm_mlp_create(int device, void* stream, int max_rows, dm_mlp** out) {
   dm_status s = DM_OK;
   auto A = [&](auto** p, size_t n) { if (s == DM_OK) s = malloc_n(m, p, n); };
   A(&m->P, NPARAM); A(&m->M, NPARAM); A(&m->V, NPARAM); A(&m->G, NPARAM); A(&m->Y, R * NO);
-  A(&m->part, (size_t)NS_MAX * NH * NH); A(&m->bpart, (size_t)NS_MAX * NH);
+  A(&m->part, (size_t)NS_MAX * (NH * NH + NH * KX + NOP * NH)); A(&m->bpart, (size_t)NS_MAX * (2 * NH + NOP));
   A(&m->W1b, NH * KX); A(&m->W2b, NH * NH); A(&m->W2tb, NH * NH); A(&m->W3b, NOP * NH); A(&m->W3tb, NH * KX);
   A(&m->X, R * KX); A(&m->XT, R * KX); A(&m->H1, R * NH); A(&m->H1T, R * NH); A(&m->H2, R * NH); A(&m->H2T, R * NH);
   A(&m->dY, R * KX); A(&m->dYT, R * NOP); A(&m->dH2, R * NH); A(&m->dH2T, R * NH); A(&m->dH1T, R * NH);
@@ -673,14 +760,13 @@ dm_status dm_mlp_train_epoch(dm_mlp* m, const double* F, const double* T, const 
   hipStream_t st = m->stream;
   MH(hipMemsetAsync(m->lacc, 0, sizeof(double), st));
   MH(hipMemsetAsync(m->bad, 0, sizeof(int), st));
-  const int nbatch = n / batch, nblk = (rup(batch, ROWS_PAD) + 255) / 256;
+  const int nbatch = n / batch;
   const int items = batch * (NI + NO);
   for (int k = 0; k < nbatch; ++k) {
     hipLaunchKernelGGL(gather_batch, dim3((items + 255) / 256), dim3(256), 0, st, F, T, perm, n, k * batch, batch,
                        m->Fb, m->Tb, m->bad);
     if ((s = gradients(m, m->Fb, m->Tb, batch, nullptr)) != DM_OK) return s;
-    hipLaunchKernelGGL(add_loss, dim3(1), dim3(64), 0, st, m->lpart, nblk, batch, m->lacc);
-    if ((s = adam_step(m, lr)) != DM_OK) return s;
+    if ((s = adam_step(m, lr, batch, m->lacc)) != DM_OK) return s;
   }
   double L = 0.0;
   int bad = 0;
