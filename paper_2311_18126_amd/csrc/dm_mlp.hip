@@ -240,18 +240,29 @@ __global__ void __launch_bounds__(256) reduce_all(ReduceSet r) {
   }
 }
 
+// One 32-entry bfloat16 row (64 bytes, 16-byte aligned) from packed pairs, as four 16-byte stores.
+__device__ __forceinline__ void store_row(u16* row, const uint32_t (&w)[KX / 2]) {
+  uint4* q = reinterpret_cast<uint4*>(row);
+#pragma unroll
+  for (int k = 0; k < KX / 8; ++k) q[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+}
+
 // Standardised, bfloat16-rounded input rows (and their transpose) from raw float64 features;
 // rows >= n are zero.
 __global__ void standardise(const double* __restrict__ F, int n, int rows, const double* __restrict__ mean,
                             const double* __restrict__ sd, u16* __restrict__ X, u16* __restrict__ XT) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= rows) return;
+  uint32_t w[KX / 2];
+#pragma unroll
   for (int c = 0; c < KX; ++c) {
     u16 h = 0;
     if (r < n && c < NI) h = bf16_bits((float)((F[(size_t)r * NI + c] - mean[c]) / sd[c]));
-    X[(size_t)r * KX + c] = h;
     XT[(size_t)c * rows + r] = h;
+    if (c & 1) w[c / 2] |= (uint32_t)h << 16;
+    else w[c / 2] = h;
   }
+  store_row(X + (size_t)r * KX, w);
 }
 
 // Squared-error loss against standardised targets T/ystd and its gradient 2 (y - t)/n, rounded
@@ -263,6 +274,8 @@ __global__ void __launch_bounds__(256) loss_grad(const float* __restrict__ Y, co
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   double ls = 0.0;
   if (r < rows) {
+    uint32_t w[KX / 2];
+#pragma unroll
     for (int c = 0; c < KX; ++c) {
       u16 h = 0;
       if (r < n && c < NO) {
@@ -271,9 +284,11 @@ __global__ void __launch_bounds__(256) loss_grad(const float* __restrict__ Y, co
         ls += d * d;
         h = bf16_bits((float)(2.0 * d / n));
       }
-      dY[(size_t)r * KX + c] = h;
       if (c < NOP) dYT[(size_t)c * rows + r] = h;
+      if (c & 1) w[c / 2] |= (uint32_t)h << 16;
+      else w[c / 2] = h;
     }
+    store_row(dY + (size_t)r * KX, w);
   }
   red[threadIdx.x] = ls;
   __syncthreads();
