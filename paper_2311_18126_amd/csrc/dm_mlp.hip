@@ -49,11 +49,17 @@ enum { EPI_HIDDEN = 0, EPI_OUTPUT = 1, EPI_DGRAD = 2 };
 template <int N>
 constexpr int row_wpr() { return N / 16 >= 4 ? 4 : 1; }
 
-// Workgroups of 256 threads covering `rows` (a multiple of ROWS_PAD) for a product of width N.
-template <int N>
-inline int row_grid(int rows) { return rows / (16 * (4 / row_wpr<N>())); }
+// 16-row blocks per wavefront: two where the column tiles are shared out and the reduction is
+// long (K >= 64), so each weight fragment loaded serves two MFMAs (half the re-reads of the
+// weights over the batch); for K = 32 the weights are small and the wavefronts count more.
+template <int K, int N>
+constexpr int row_rb() { return row_wpr<N>() == 4 && K >= 64 ? 2 : 1; }
 
-// out = epilogue(A[rows][K] . Bm[N][K]^T).  A wavefront computes one 16-row block over
+// Workgroups of 256 threads covering `rows` (a multiple of ROWS_PAD) for a K x N product.
+template <int K, int N>
+inline int row_grid(int rows) { return rows / (16 * row_rb<K, N>() * (4 / row_wpr<N>())); }
+
+// out = epilogue(A[rows][K] . Bm[N][K]^T).  A wavefront computes row_rb 16-row blocks over
 // N / 16 / row_wpr column tiles; lane l supplies A[l % 16][8 (l / 16) + 0..7] and, per
 // 16-column tile t, Bm[16 t + l % 16][8 (l / 16) + 0..7], and receives
 // C[4 (l / 16) + j][16 t + l % 16], j = 0..3.
@@ -65,35 +71,43 @@ __global__ void __launch_bounds__(256) row_gemm(const u16* __restrict__ A, const
                                                 const float* __restrict__ bias, const u16* __restrict__ mask,
                                                 int rows, u16* __restrict__ out, u16* __restrict__ outT,
                                                 float* __restrict__ outF) {
-  constexpr int WPR = row_wpr<N>(), TPW = N / 16 / WPR;
+  constexpr int WPR = row_wpr<N>(), RB = row_rb<K, N>(), TPW = N / 16 / WPR;
   const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int row0 = (blockIdx.x * (4 / WPR) + w / WPR) * 16;
+  const int row0 = (blockIdx.x * (4 / WPR) + w / WPR) * 16 * RB;
   const int tb = (w % WPR) * TPW;
   if (row0 >= rows) return;
   const int lr = l & 15, lk = 8 * (l >> 4);
-  f32x4 acc[TPW];
+  f32x4 acc[RB][TPW];
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int b = 0; b < RB; ++b)
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) acc[b][t] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int k0 = 0; k0 < K; k0 += 32) {
-    const bf16x8 a = ld8(A + (size_t)(row0 + lr) * K + k0 + lk);
+    bf16x8 a[RB];
 #pragma unroll
-    for (int t = 0; t < TPW; ++t)
-      acc[t] = mfma(a, ld8(Bm + (size_t)(16 * (tb + t) + lr) * K + k0 + lk), acc[t]);
+    for (int b = 0; b < RB; ++b) a[b] = ld8(A + (size_t)(row0 + 16 * b + lr) * K + k0 + lk);
+#pragma unroll
+    for (int t = 0; t < TPW; ++t) {
+      const bf16x8 wt = ld8(Bm + (size_t)(16 * (tb + t) + lr) * K + k0 + lk);
+#pragma unroll
+      for (int b = 0; b < RB; ++b) acc[b][t] = mfma(a[b], wt, acc[b][t]);
+    }
   }
-  const int r0 = row0 + 4 * (l >> 4);
 #pragma unroll
-  for (int t = 0; t < TPW; ++t) {
+  for (int rb = 0; rb < RB * TPW; ++rb) {
+    const int b = rb / TPW, t = rb % TPW;
+    const int r0 = row0 + 16 * b + 4 * (l >> 4);
     const int n = 16 * (tb + t) + lr;
     if (EPI == EPI_OUTPUT) {
       if (n < NO)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) outF[(size_t)(r0 + j) * NO + n] = acc[t][j] + bias[n];
+        for (int j = 0; j < 4; ++j) outF[(size_t)(r0 + j) * NO + n] = acc[b][t][j] + bias[n];
     } else {
       u16 h[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        float v = acc[t][j];
+        float v = acc[b][t][j];
         if (EPI == EPI_HIDDEN) v = fmaxf(v + bias[n], 0.0f);
         else {
           const u16 m = mask[(size_t)(r0 + j) * N + n];
@@ -552,11 +566,11 @@ dm_status forward_rows(dm_mlp* m, const double* F, int n, int rows) {
   hipStream_t st = m->stream;
   hipLaunchKernelGGL(standardise, dim3((rows + 255) / 256), dim3(256), 0, st, F, n, rows, m->mean, m->sd, m->X, m->XT);
   const dim3 b(256);
-  hipLaunchKernelGGL((row_gemm<KX, NH, EPI_HIDDEN>), dim3(row_grid<NH>(rows)), b, 0, st, m->X, m->W1b, m->P + OFF_B1,
+  hipLaunchKernelGGL((row_gemm<KX, NH, EPI_HIDDEN>), dim3(row_grid<KX, NH>(rows)), b, 0, st, m->X, m->W1b, m->P + OFF_B1,
                      nullptr, rows, m->H1, m->H1T, nullptr);
-  hipLaunchKernelGGL((row_gemm<NH, NH, EPI_HIDDEN>), dim3(row_grid<NH>(rows)), b, 0, st, m->H1, m->W2b, m->P + OFF_B2,
+  hipLaunchKernelGGL((row_gemm<NH, NH, EPI_HIDDEN>), dim3(row_grid<NH, NH>(rows)), b, 0, st, m->H1, m->W2b, m->P + OFF_B2,
                      nullptr, rows, m->H2, m->H2T, nullptr);
-  hipLaunchKernelGGL((row_gemm<NH, NOP, EPI_OUTPUT>), dim3(row_grid<NOP>(rows)), b, 0, st, m->H2, m->W3b,
+  hipLaunchKernelGGL((row_gemm<NH, NOP, EPI_OUTPUT>), dim3(row_grid<NH, NOP>(rows)), b, 0, st, m->H2, m->W3b,
                      m->P + OFF_B3, nullptr, rows, nullptr, nullptr, m->Y);
   MH(hipGetLastError());
   return DM_OK;
@@ -591,9 +605,9 @@ dm_status gradients(dm_mlp* m, const double* F, const double* T, int n, double* 
   const int nb = (rows + 255) / 256;
   hipLaunchKernelGGL(loss_grad, dim3(nb), dim3(256), 0, st, m->Y, T, m->ystd, n, rows, m->dY, m->dYT, m->lpart);
   const dim3 b(256);
-  hipLaunchKernelGGL((row_gemm<KX, NH, EPI_DGRAD>), dim3(row_grid<NH>(rows)), b, 0, st, m->dY, m->W3tb, nullptr,
+  hipLaunchKernelGGL((row_gemm<KX, NH, EPI_DGRAD>), dim3(row_grid<KX, NH>(rows)), b, 0, st, m->dY, m->W3tb, nullptr,
                      m->H2, rows, m->dH2, m->dH2T, nullptr);
-  hipLaunchKernelGGL((row_gemm<NH, NH, EPI_DGRAD>), dim3(row_grid<NH>(rows)), b, 0, st, m->dH2, m->W2tb, nullptr,
+  hipLaunchKernelGGL((row_gemm<NH, NH, EPI_DGRAD>), dim3(row_grid<NH, NH>(rows)), b, 0, st, m->dH2, m->W2tb, nullptr,
                      m->H1, rows, nullptr, m->dH1T, nullptr);
   float* G = m->G;
   // The three weight-gradient products (W2, W1, W3; tiles = (M / 16) x (N / min(N, 64))), each
