@@ -191,3 +191,14 @@ def test_normalisation_fit_matches_numpy(dm):
     assert np.allclose(mean, F.mean(0), rtol=1e-10, atol=1e-12)
     assert np.allclose(std, F.std(0), rtol=1e-8)
     assert np.allclose(scale, np.sqrt((T * T).mean(0)), rtol=1e-10)
+    # more rows than the fit's threads (1024 x 256): the grid-stride loop comes round again
+    F2, T2, _, _, _ = raw_case(300_000, 9)
+    net.fit_normalisation(torch.tensor(F2, device="cuda"), torch.tensor(T2, device="cuda"))
+    mean, std, scale = net.get_normalisation()
+    assert np.allclose(mean, F2.mean(0), rtol=1e-10, atol=1e-12)
+    assert np.allclose(std, F2.std(0), rtol=1e-8)
+    assert np.allclose(scale, np.sqrt((T2 * T2).mean(0)), rtol=1e-10)
+    # features that do not start on a 16-byte boundary are refused
+    flat = torch.zeros(5000 * 20 + 1, dtype=torch.float64, device="cuda")
+    with pytest.raises(dm.DmError):
+        net.fit_normalisation(flat[1:].view(5000, 20), torch.tensor(T, device="cuda"))
