@@ -39,7 +39,8 @@ INFER_FLOPS_PER_ROW = 2 * (20 * 256 + 256 * 256 + 256 * 3)
 TRAIN_FLOPS_PER_ROW = 2 * INFER_FLOPS_PER_ROW + 2 * (256 * 3 + 256 * 256)
 KERNEL_SOURCES = ["paper_2311_18126_amd/csrc/dm_kernels.hip", "paper_2311_18126_amd/csrc/dm_math.h",
                   "paper_2311_18126_amd/csrc/dm_layout.h", "paper_2311_18126_amd/csrc/dm_warm.h",
-                  "paper_2311_18126_amd/csrc/dm_bf16.h"]
+                  "paper_2311_18126_amd/csrc/dm_bf16.h",
+                  "paper_2311_18126_amd/build.py"]      # the compiler flags shape the kernel too
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dm_step_kernel_rod_batch_traffic.json")
 
 
