@@ -502,46 +502,80 @@ class StepInfo:
     residual: float
     converged: bool
     history: list
+    at_floor: bool = False       # ended by the rounding-floor rule, not the tolerance
+    floor: float = 0.0           # rounding-floor estimate of the last iterate
+
+
+EPS = 2.0 ** -52
+
+
+def floor_scales(sys, st):
+    """Magnitude of each DOF kind at the step start: the largest |coordinate| of the node
+    positions for position DOFs, the largest |theta| plus pi for twist DOFs (the reference
+    twist in (-pi, pi] enters every twist strain)."""
+    s = torch.empty(sys.n_dof, dtype=DT)
+    s[:3 * sys.n_nodes] = float(st.x.abs().max())
+    s[3 * sys.n_nodes:] = (float(st.theta.abs().max()) if sys.n_edges else 0.0) + math.pi
+    return s
+
+
+def rounding_floor(J_ff, s_f, factor):
+    """Estimate of the FP64 rounding floor of the residual norm: a free DOF cannot be placed
+    closer than eps |q_k| to the root, so row i of the residual cannot be resolved below
+    eps sum_k |J_ik| |q_k|; with |q_k| bounded by its kind's step-start magnitude the floor is
+    factor * eps * || |J| s ||_2 over free rows and columns."""
+    return factor * EPS * float(torch.linalg.norm(J_ff.abs() @ s_f))
 
 
 def newton_solve(sys, st, dt, kappa_bar, tol=1e-9, max_iter=50, q0=None, polish=0, line_search=False,
-                 stag_tol=1e-6, res=residual):
+                 floor_factor=1.0, res=residual, floor_jac_scale=1.0):
     """Newton's method on the residual.  Initial guess q_n unless q0 is given.
-    Stops when the 2-norm of the residual over free DOFs is <= tol, or when the residual
-    was already <= stag_tol and the last iteration failed to halve it (the FP64 rounding
-    floor of a stiff rod can lie above tol); `polish` extra iterations may follow (used
-    to reach the rounding floor in tests).
-    With line_search (the paper's optional globalisation), the Newton step is halved
-    (at most 10 times) until the residual norm decreases.  `res` is the scheme's residual."""
+    Stops when the 2-norm of the residual over free DOFs is <= tol, or, after at least one
+    Newton step, when the residual is at or below its computed rounding floor
+    (`rounding_floor`, floor_factor 0 turns the rule off) and the last step failed to halve
+    it: the FP64 floor of a stiff rod can lie above tol.  `polish` extra iterations may follow
+    the tolerance (used to reach the rounding floor in tests); the last one is returned.
+    With line_search (the paper's optional globalisation), the Newton step is halved (at most
+    10 times) until the residual norm decreases; a step taken from an iterate already at its
+    rounding floor is not judged by the residual and is kept whole.  `res` is the scheme's
+    residual; floor_jac_scale multiplies the Jacobian in the floor estimate (2 when the
+    unknown is the step end but the rounding acts on the midpoint state)."""
     free = ~sys.fixed
     q = pack(st.x, st.theta).clone() if q0 is None else q0.clone()
     jac = torch.func.jacfwd(lambda qq: res(sys, qq, st, dt, kappa_bar))
+    sc = floor_scales(sys, st)[free]
     hist = []
     it = 0
     extra = 0
     R = res(sys, q, st, dt, kappa_bar)
+    J = jac(q)
     while True:
         r = float(torch.linalg.norm(R[free]))
+        Jff = J[free][:, free]
+        fl = rounding_floor(floor_jac_scale * Jff, sc, floor_factor)
         hist.append(r)
-        if r > tol and len(hist) >= 2 and hist[-2] <= stag_tol and r > 0.5 * hist[-2] and extra == 0:
-            return q, StepInfo(it, r, True, hist)
-        if r <= tol:
+        if r <= tol or extra > 0:
+            # converged; polishing iterations (at the rounding floor, where the residual is
+            # noise and may sit a hair above tol) end after their count whatever it reads
             if extra >= polish:
-                return q, StepInfo(it, r, True, hist)
+                return q, StepInfo(it, r, True, hist, False, fl)
             extra += 1
+        elif it > 0 and r <= fl and r > 0.5 * hist[-2]:
+            return q, StepInfo(it, r, True, hist, True, fl)
         if it >= max_iter + polish:
-            return q, StepInfo(it, r, False, hist)
-        J = jac(q)
-        dq = torch.linalg.solve(J[free][:, free], R[free])
+            return q, StepInfo(it, r, False, hist, False, fl)
+        dq = torch.linalg.solve(Jff, R[free])
         alpha = 1.0
-        for _ in range(11 if line_search else 1):
+        ls = line_search and r > fl
+        for _ in range(11 if ls else 1):
             qn = q.clone()
             qn[free] = q[free] - alpha * dq
             Rn = res(sys, qn, st, dt, kappa_bar)
-            if not line_search or float(torch.linalg.norm(Rn[free])) < r:
+            if not ls or float(torch.linalg.norm(Rn[free])) < r:
                 break
             alpha *= 0.5
         q, R = qn, Rn
+        J = jac(q)
         it += 1
 
 
@@ -571,7 +605,7 @@ def step(sys, st, dt, tol=1e-9, max_iter=50, kbar_rods=None, polish=0, q0=None, 
     if scheme == "midpoint":
         kap = natural_curvature(sys, st.time + 0.5 * dt, kbar_rods)
         q, info = newton_solve(sys, st, dt, kap, tol, max_iter, q0=q0, polish=polish, line_search=line_search,
-                               res=residual_midpoint)
+                               res=residual_midpoint, floor_jac_scale=2.0)
         return (commit_midpoint(sys, st, q, dt) if info.converged else st), info
     kap = natural_curvature(sys, st.time + dt, kbar_rods)
     q, info = newton_solve(sys, st, dt, kap, tol, max_iter, q0=q0, polish=polish, line_search=line_search)
