@@ -537,6 +537,10 @@ def main():
                    "block_size": sim.block_size, "autotuned": tuned is not None},
         "newton_iters_per_step": float(iters.sum() / len(iters) / args.steps),
         "floor_steps": int(stats["floor_steps"].sum()),
+        # largest residual among the steps accepted at their rounding floor, and that step's
+        # computed floor (every floor-ended step has residual <= its floor by construction)
+        "floor_residual_max": float(stats["floor_residual_max"].max()),
+        "floor_estimate_at_max": float(stats["floor_estimate"][int(np.argmax(stats["floor_residual_max"]))]),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": traffic,
                      "kernel": "dm_step_kernel", "kernel_ms": 1e3 * kernel_s,

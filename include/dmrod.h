@@ -50,9 +50,13 @@ typedef struct {
   double gravity[3];      /* m/s^2, acts on node positions as m_i g (misc. force, Eq. 13 text) */
   double newton_tol;      /* Newton stops when the 2-norm of the residual of Eq. 15 over
                              free DOFs is <= newton_tol (absolute, N and N m mixed) */
-  double stagnation_tol;  /* ...or when the residual was already <= stagnation_tol and the
-                             last Newton iteration failed to halve it: the FP64 rounding
-                             floor of stiff systems can lie above newton_tol.  0 disables. */
+  double floor_factor;    /* ...or, after at least one Newton step, when the residual is at or
+                             below its FP64 rounding floor and the last step failed to halve
+                             it (the floor of stiff or distant systems lies above newton_tol).
+                             The floor is floor_factor * eps * || |J| s ||_2 over free rows and
+                             columns of the Newton matrix J of the iterate, s_k the step-start
+                             magnitude of DOF k's kind (largest |position coordinate| of the
+                             system; largest |theta| + pi).  Default 1; 0 disables the rule. */
   int max_iter;           /* Newton iterations per step before DM_NOT_CONVERGED */
   int line_search;        /* 1: halve the Newton step (at most 10 times) until the residual
                              norm decreases (the paper's optional line search) */
@@ -74,6 +78,18 @@ typedef struct {
                              captured HIP graph per checkpoint segment (its one-step launches
                              and tip gathers or state saves) instead of launching them one by
                              one; 0: eager launches */
+  /* Device-memory hook (the caller's allocator owns the pages, e.g. a framework's caching
+     allocator): when alloc is non-NULL every device buffer of the simulation (its state,
+     topology, scratch, checkpoints and trajectory buffers) is obtained by
+     alloc(bytes, alloc_ctx), which returns device memory on cfg->device, at least 256-byte
+     aligned, or NULL on failure (the call then returns DM_ERR_OOM), and is released by
+     free_(ptr, alloc_ctx) (required with alloc) after the simulation's stream has drained:
+     when a buffer grows and in dm_destroy.  Both are called on the thread that called the
+     library.  NULL (default): hipMalloc / hipFree.  The dm_mlp network keeps its own hipMalloc
+     buffers. */
+  void* (*alloc)(size_t bytes, void* ctx);
+  void (*free_)(void* ptr, void* ctx);
+  void* alloc_ctx;
 } dm_config;
 
 /* Per-system counters accumulated over the last dm_step call. */
@@ -81,12 +97,15 @@ typedef struct {
   int steps_done;         /* time steps completed */
   int newton_iters;       /* Newton iterations summed over those steps */
   int status;             /* dm_status of this system for the call */
-  int floor_steps;        /* steps that ended by the stagnation rule, not newton_tol */
+  int floor_steps;        /* (sub)steps that ended at the rounding floor (floor_factor), not
+                             newton_tol */
   int fallbacks;          /* warm-started steps whose Newton solve failed and was redone
                              from the step-start state (see dm_set_warm_start) */
   int halvings;           /* (sub)steps whose Newton solve failed and were redone as two
                              halves (see dm_set_adaptive) */
   double residual;        /* residual norm at the last Newton iterate */
+  double floor_residual_max;  /* largest residual among the floor-ended (sub)steps (0: none) */
+  double floor_estimate;      /* the rounding-floor estimate of that (sub)step */
 } dm_stats;
 
 void dm_config_default(dm_config* cfg);

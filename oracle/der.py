@@ -536,8 +536,8 @@ def newton_solve(sys, st, dt, kappa_bar, tol=1e-9, max_iter=50, q0=None, polish=
     it: the FP64 floor of a stiff rod can lie above tol.  `polish` extra iterations may follow
     the tolerance (used to reach the rounding floor in tests); the last one is returned.
     With line_search (the paper's optional globalisation), the Newton step is halved (at most
-    10 times) until the residual norm decreases; a step taken from an iterate already at its
-    rounding floor is not judged by the residual and is kept whole.  `res` is the scheme's
+    10 times) until the residual norm decreases, unless the trial's residual lies within its
+    own rounding floor (a rise there is rounding noise) and is kept.  `res` is the scheme's
     residual; floor_jac_scale multiplies the Jacobian in the floor estimate (2 when the
     unknown is the step end but the rounding acts on the midpoint state)."""
     free = ~sys.fixed
@@ -566,16 +566,21 @@ def newton_solve(sys, st, dt, kappa_bar, tol=1e-9, max_iter=50, q0=None, polish=
             return q, StepInfo(it, r, False, hist, False, fl)
         dq = torch.linalg.solve(Jff, R[free])
         alpha = 1.0
-        ls = line_search and r > fl
-        for _ in range(11 if ls else 1):
+        Jn = None
+        for _ in range(11 if line_search else 1):
             qn = q.clone()
             qn[free] = q[free] - alpha * dq
             Rn = res(sys, qn, st, dt, kappa_bar)
-            if not ls or float(torch.linalg.norm(Rn[free])) < r:
+            Jn = None
+            if not line_search or float(torch.linalg.norm(Rn[free])) < r:
                 break
+            Jn = jac(qn)
+            if float(torch.linalg.norm(Rn[free])) <= rounding_floor(floor_jac_scale * Jn[free][:, free], sc,
+                                                                     floor_factor):
+                break           # a rise within the trial's own rounding floor is noise, not a bad step
             alpha *= 0.5
         q, R = qn, Rn
-        J = jac(q)
+        J = Jn if Jn is not None else jac(q)
         it += 1
 
 

@@ -26,17 +26,23 @@ DM_ERR_SINGULAR = -5
 DM_ERR_UNSUPPORTED = -6
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
+
+
 class DmConfig(ctypes.Structure):
-    _fields_ = [("gravity", c_double * 3), ("newton_tol", c_double), ("stagnation_tol", c_double), ("max_iter", c_int),
+    _fields_ = [("gravity", c_double * 3), ("newton_tol", c_double), ("floor_factor", c_double), ("max_iter", c_int),
                 ("line_search", c_int), ("floor_contact", c_int), ("floor_z", c_double),
                 ("delta", c_double), ("nu", c_double), ("mu", c_double), ("k_contact", c_double),
                 ("damping", c_double), ("device", c_int), ("stream", c_void_p), ("block_size", c_int),
-                ("warm_max_iter", c_int), ("use_graphs", c_int)]
+                ("warm_max_iter", c_int), ("use_graphs", c_int), ("alloc", ALLOC_FN), ("free_", FREE_FN),
+                ("alloc_ctx", c_void_p)]
 
 
 class DmStats(ctypes.Structure):
     _fields_ = [("steps_done", c_int), ("newton_iters", c_int), ("status", c_int), ("floor_steps", c_int),
-                ("fallbacks", c_int), ("halvings", c_int), ("residual", c_double)]
+                ("fallbacks", c_int), ("halvings", c_int), ("residual", c_double), ("floor_residual_max", c_double),
+                ("floor_estimate", c_double)]
 
 
 _DP = POINTER(c_double)
@@ -160,19 +166,50 @@ def _device_sized(t, n, what):
     return t
 
 
+def _torch_cuda():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except ImportError:
+        return False
+
+
+def _torch_hooks(device, stream):
+    """Allocator callbacks of dm_config backed by PyTorch's caching allocator on the given
+    device and stream (an int hipStream_t or None for the null stream).  Returns the two ctypes
+    callbacks; the caller keeps them alive while the simulation exists."""
+    import torch
+    sptr = int(stream) if stream else 0
+
+    def alloc(nbytes, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, sptr)
+        except Exception:          # out of memory: the library reports DM_ERR_OOM
+            return None
+
+    def free(ptr, ctx):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:          # interpreter shutdown: nothing left to return the pages to
+            pass
+    return ALLOC_FN(alloc), FREE_FN(free)
+
+
 class Sim:
     """One dm_sim.  Build with add_rod / add_joint / ..., then finalize() and step()."""
 
     def __init__(self, gravity=(0.0, 0.0, -9.81), newton_tol=1e-9, max_iter=50, line_search=False,
-                 floor=None, damping=0.0, device=0, stream=None, block_size=0, stagnation_tol=1e-6,
-                 warm_max_iter=0, use_graphs=True):
+                 floor=None, damping=0.0, device=0, stream=None, block_size=0, floor_factor=1.0,
+                 warm_max_iter=0, use_graphs=True, torch_memory=True):
+        """torch_memory: obtain every device buffer of the simulation from PyTorch's caching
+        allocator (dm_config.alloc / free_) instead of hipMalloc."""
         L = lib()
         cfg = DmConfig()
         L.dm_config_default(ctypes.byref(cfg))
         for i in range(3):
             cfg.gravity[i] = float(gravity[i])
         cfg.newton_tol = float(newton_tol)
-        cfg.stagnation_tol = float(stagnation_tol)
+        cfg.floor_factor = float(floor_factor)
         cfg.max_iter = int(max_iter)
         cfg.line_search = int(bool(line_search))
         if floor is not None:
@@ -188,6 +225,11 @@ class Sim:
         cfg.block_size = int(block_size)
         cfg.warm_max_iter = int(warm_max_iter)
         cfg.use_graphs = int(bool(use_graphs))
+        self._hooks = None
+        if torch_memory and _torch_cuda():
+            # without a visible GPU no hook is set and dm_create itself reports DM_ERR_HIP
+            self._hooks = _torch_hooks(int(device), stream)
+            cfg.alloc, cfg.free_ = self._hooks
         h = c_void_p()
         _check(L.dm_create(ctypes.byref(cfg), ctypes.byref(h)), "dm_create")
         self._h = h
@@ -253,11 +295,11 @@ class Sim:
         self.last_status = s
         out = np.zeros(n, dtype=[("steps", np.int32), ("iters", np.int32), ("status", np.int32),
                                  ("floor_steps", np.int32), ("fallbacks", np.int32), ("halvings", np.int32),
-                                 ("residual", np.float64)])
+                                 ("residual", np.float64), ("floor_residual_max", np.float64),
+                                 ("floor_estimate", np.float64)])
         for i in range(n):
             out[i] = (st[i].steps_done, st[i].newton_iters, st[i].status, st[i].floor_steps, st[i].fallbacks,
-                      st[i].halvings,
-                      st[i].residual)
+                      st[i].halvings, st[i].residual, st[i].floor_residual_max, st[i].floor_estimate)
         return out
 
     def set_integrator(self, scheme):

@@ -441,6 +441,76 @@ __device__ __noinline__ double assemble_band(ArgsP Ap, int sid, double dt) {
   return r2;
 }
 
+// FP64 rounding floor of the residual norm of the iterate whose Newton matrix J is assembled
+// (band, border rows' band parts and the dense border Bt): a free DOF cannot be placed closer
+// than eps |q_k| to the root, so row i cannot be resolved below eps sum_k |J_ik| |q_k|; with
+// |q_k| bounded by its kind's magnitude at the (sub)step start (largest |position coordinate|;
+// largest |theta| plus pi, the reference twist's range) the floor is
+// floor_factor * eps * || |J| s ||_2 over free rows and columns.  Called by the whole
+// workgroup, only when a stopping or line-search decision needs it; the same value in every
+// lane.
+__device__ __noinline__ double residual_floor(ArgsP Ap, int sid, const double DM_L* Bt, int ld, double DM_L* red) {
+  const DmStepArgs DM_C& A = *uniform(Ap);
+  const DmDev DM_C& D = A.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
+  const int NN = D.n_nodes_tot, w = threadIdx.x >> 6;
+  // magnitudes of the (sub)step start
+  double mx = 0.0, mt = 0.0;
+  for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mx = fmax(mx, fabs(D.x0[c * NN + S.node0 + i]));
+  for (int i = threadIdx.x; i < S.n_edges; i += blockDim.x) mt = fmax(mt, fabs(D.th0[S.edge0 + i]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, o, 64));
+    mt = fmax(mt, __shfl_xor(mt, o, 64));
+  }
+  if ((threadIdx.x & 63) == 0) { red[16 + w] = mx; red[24 + w] = mt; }
+  __syncthreads();
+  double xs = 0.0, ts = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) { xs = fmax(xs, red[16 + i]); ts = fmax(ts, red[24 + i]); }
+  ts += 3.141592653589793238462643383279;
+  // band rows: row sums of free rows (a border row's band part goes to babs)
+  double f2 = 0.0;
+  for (int a = 0; a < S.n_chains; ++a) {
+    const DmChain DM_C& C = D.chain[S.chain0 + a];
+    const int n = 4 * C.n_nodes - 1;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+      if (D.cfix[C.dof_off + r]) continue;
+      const double DM_G* row = D.band + (size_t)(C.dof_off + r) * DM_NDIAG;
+      double fa = 0.0;
+      for (int o = 0; o < DM_NDIAG; ++o) fa = fma(fabs(row[o]), ((r - DM_HALF_BAND + o) & 3) == 3 ? ts : xs, fa);
+      if (r >= C.b_lo && r < C.b_hi) D.babs[C.bmap_off + r - C.b_lo] = fa;
+      else f2 = fma(fa, fa, f2);
+    }
+  }
+  __syncthreads();
+  // border rows (nb <= 64: wavefront 0): each source chain's band part plus the dense border row
+  const int nb = S.nb, b = threadIdx.x;
+  if (b < nb && !D.bfix[S.bfix_off + b]) {
+    double fa = 0.0;
+    for (int q = 0; q < DM_MAX_BSRC; ++q) {
+      const int slot = 2 * ((S.bsrc_off + b * DM_MAX_BSRC) + q);
+      const int ci = D.bsrc[slot];
+      if (ci < 0) break;
+      const DmChain DM_C& C = D.chain[ci];
+      fa += D.babs[C.bmap_off + D.bsrc[slot + 1] - C.b_lo];
+    }
+    for (int c = 0; c < nb; ++c) {
+      const int r0 = D.bsrc[2 * (S.bsrc_off + c * DM_MAX_BSRC) + 1];     // a chain DOF of border DOF c
+      fa = fma(fabs(Bt[b * ld + c]), (r0 & 3) == 3 ? ts : xs, fa);
+    }
+    f2 = fma(fa, fa, f2);
+  }
+  f2 = wave_sum(f2);
+  if ((threadIdx.x & 63) == 0) red[8 + w] = f2;
+  __syncthreads();
+  double tot = 0.0;
+  for (int i = 0; i < (int)(blockDim.x >> 6); ++i) tot += red[8 + i];
+  __syncthreads();
+  return A.floor_factor * 2.220446049250313080847263336181640625e-16 * sqrt(tot);   // eps = 2^-52
+}
+
 // Value of a border term (kind 4: the zero pad).
 __device__ __forceinline__ double bterm(const DmDev DM_C& D, const DmBItem& it) {
   const double DM_G* src = it.kind == 0 ? D.bpr
@@ -660,14 +730,22 @@ __device__ __forceinline__ double row_bcast(double v) {
 // over; ent: the entry of row k + 11 in this role's column (used by the half owning slot T).
 // MASK: rows whose arm ends before k leave their window untouched and park their store in the
 // padding of their first record.
+// A pivot below this fraction of its row's diagonal in the assembled band marks the system's
+// Newton matrix as numerically singular (the elimination does not pivot).
+#define DM_PIVOT_TAU 1e-12
+
 template <int T, bool MASK>
 __device__ __forceinline__ void elim_step(double (&w)[DM_HS], const double (&col)[DM_HS], double ent, int k, int l,
-                                          int h, const ArmView& V, double DM_G* recp, int& bad) {
+                                          int h, const ArmView& V, double DM_G* recp, int& bad, double& dg) {
   constexpr int hT = T >= DM_HS ? 1 : 0, tT = T - DM_HS * hT;
   const bool act = MASK ? k < V.count : true;
   const double u = from_half(w[tT], hT);              // row k's entry in this lane's column
   const double piv = row_bcast<T>(u);
   if (act && !__builtin_isnormal(piv)) bad = 1;       // zero, subnormal, infinite or NaN
+  // the lane holding slot T of role T keeps the assembled diagonal of the row it pivots next
+  const bool dlane = (l == T) & (h == hT);
+  if (act && dlane && !(fabs(piv) >= DM_PIVOT_TAU * fabs(dg))) bad = 1;
+  dg = dlane ? col[tT] : dg;                          // the diagonal of row k + 11
   const double inv = recip(piv);
   double cv[DM_HS];
 #pragma unroll
@@ -714,10 +792,12 @@ __device__ __noinline__ void sweep_arms(ArgsP Ap, int ai0, int na, double DM_L* 
   int cmin, cmax;
   group_counts(D, ai0, na, cmin, cmax);
   double w[DM_HS], col[DM_HS], ncol[DM_HS], ent[DM_WIN];
+  double dg = 0.0;        // role l's next pivot row's assembled diagonal (lane of slot l only)
 #pragma unroll
   for (int j = 0; j < DM_HS; ++j) {
     const int g = DM_HS * h + j;
     w[j] = init_entry(V, g < DM_WIN ? g : 0, l);
+    dg = (g == l) ? w[j] : dg;
   }
   load_new_column(col, 0, l, h, V);
 #pragma unroll
@@ -744,13 +824,13 @@ __device__ __noinline__ void sweep_arms(ArgsP Ap, int ai0, int na, double DM_L* 
     // on a uniform branch
     if (k0 + 3 * DM_WIN <= cmin) {
 #define DM_E(T) \
-  elim_step<T, false>(w, col, ent[T], k0 + T, l, h, V, rp + (T * r_step + (T > l && !side ? DM_WIN : 0)), bad); \
+  elim_step<T, false>(w, col, ent[T], k0 + T, l, h, V, rp + (T * r_step + (T > l && !side ? DM_WIN : 0)), bad, dg); \
   ent[T] = ep[T * e_step + (T >= l ? e_jump : 0)];
       DM_UNROLL11(DM_E)
 #undef DM_E
     } else {
 #define DM_E(T) \
-  if (k0 + T < cmax) elim_step<T, true>(w, col, ent[T], k0 + T, l, h, V, rec_ptr<T>(V, k0 + T, l, k0 + T < V.count), bad); \
+  if (k0 + T < cmax) elim_step<T, true>(w, col, ent[T], k0 + T, l, h, V, rec_ptr<T>(V, k0 + T, l, k0 + T < V.count), bad, dg); \
   ent[T] = row_entry(V, k0 + T + 2 * DM_WIN, l, wrap11(l, T));
       DM_UNROLL11(DM_E)
 #undef DM_E
@@ -939,6 +1019,13 @@ __device__ __forceinline__ double border_lu_regs(const double DM_L* Bt, int ld, 
   bool open = row;
   int piv[NBX];
   double pinv[NBX];
+  // largest assembled entry of the border: a pivot below DM_PIVOT_TAU of it marks the border
+  // numerically singular
+  double amax = 0.0;
+#pragma unroll
+  for (int c = 0; c < NBX; ++c) amax = fmax(amax, fabs(r[c]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
 #pragma unroll
   for (int p = 0; p < NBX; ++p) {
     piv[p] = 0;
@@ -949,7 +1036,7 @@ __device__ __forceinline__ double border_lu_regs(const double DM_L* Bt, int ld, 
       row_argmax<NBX>(v, im);
       im = uniform(im);
       const double pv = readlane_d(r[p], im);
-      bad |= !(fabs(pv) > 1e-300) | !isfinite(pv);
+      bad |= !(fabs(pv) > 1e-300) | !isfinite(pv) | !(fabs(pv) >= DM_PIVOT_TAU * amax);
       const double inv = 1.0 / pv;
       piv[p] = im;
       pinv[p] = inv;
@@ -977,6 +1064,10 @@ __device__ __forceinline__ double border_lu_regs(const double DM_L* Bt, int ld, 
 // with one lane per column (two for borders of more than 64 DOFs) and a butterfly sum per row.
 __device__ __forceinline__ void border_lu_lds(double DM_L* Bt, int ld, int nb, double DM_L* xB, int& bad) {
   const int lane = threadIdx.x;
+  double amax = 0.0;           // largest assembled entry (see border_lu_regs)
+  for (int q = lane; q < nb * nb; q += 64) amax = fmax(amax, fabs(Bt[(q / nb) * ld + q % nb]));
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) amax = fmax(amax, __shfl_xor(amax, o, 64));
   for (int p = 0; p < nb; ++p) {
     double vm = (lane >= p && lane < nb) ? fabs(Bt[lane * ld + p]) : -1.0;
     int im = lane;
@@ -991,7 +1082,7 @@ __device__ __forceinline__ void border_lu_lds(double DM_L* Bt, int ld, int nb, d
       if (ov > vm || (ov == vm && oi < im)) { vm = ov; im = oi; }
     }
     im = uniform(im);
-    if (!(vm > 1e-300) || !isfinite(vm)) bad = 1;
+    if (!(vm > 1e-300) || !isfinite(vm) || !(vm >= DM_PIVOT_TAU * amax)) bad = 1;
     if (im != p)
       for (int j = lane; j <= nb; j += 64) {
         const double t = Bt[p * ld + j];
@@ -1416,7 +1507,11 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
   int DM_L* flags = (int DM_L*)(red + 40);      // [4]; then border term segment sums at red + 42
   unsigned short DM_L* hbuf = (unsigned short DM_L*)((char DM_L*)lds_raw + A.net_lds);   // network (warm == 2)
   const int tid = threadIdx.x, wave = tid >> 6, nwaves = blockDim.x >> 6;
-  if (tid == 0) flags[0] = 0;
+  if (tid == 0) {
+    flags[0] = 0;
+    red[37] = 0.0;      // largest floor-ended residual of this launch and its floor estimate
+    red[38] = 0.0;
+  }
   int status = DM_STATUS_OK, iters = 0, steps = 0, floor_hits = 0, fallbacks = 0, halved = 0;
   double res = 0.0;
   double t = D.time[sid];
@@ -1462,12 +1557,14 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
           r2 += assemble_border(Ap, sid, Bt, ld, red + 42);
           res = sqrt(block_sum(r2, red));
           DM_TP(2);
-          if (res > A.tol && it > 0 && res_prev <= A.stag_tol && res > 0.5 * res_prev) {
-            conv = true;    // stagnation at the FP64 rounding floor of the residual
-            ++floor_hits;
-            break;
-          }
-          if (A.line_search && it > 0 && res >= res_prev && halvings < 10) {
+          // the rounding floor is needed only where a decision reads it: a residual that rose
+          // under line search, or one that stopped halving above the tolerance
+          const bool rise = A.line_search && it > 0 && res >= res_prev;
+          const bool stall = it > 0 && res > A.tol && res > 0.5 * res_prev && A.floor_factor > 0.0;
+          const double flo = (rise || stall) ? residual_floor(Ap, sid, Bt, ld, red) : 0.0;
+          // line search: a step whose residual did not decrease is halved (at most 10 times),
+          // unless its residual is within the iterate's rounding floor (noise, not a bad step)
+          if (rise && res > flo && halvings < 10) {
             apply_update(Ap, sid, xB, -0.5 * alpha);      // back off to half of the current step
             alpha *= 0.5;
             ++halvings;
@@ -1475,6 +1572,12 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
             continue;
           }
           if (res <= A.tol) { conv = true; break; }
+          if (stall && res <= flo) {
+            conv = true;    // the step stopped improving at or below its FP64 rounding floor
+            ++floor_hits;
+            if (tid == 0 && res > red[37]) { red[37] = res; red[38] = flo; }   // kept in LDS
+            break;
+          }
           if (it >= (A.warm && attempt == 0 ? A.warm_max_iter : A.max_iter) || !isfinite(res)) break;
           res_prev = res;
           alpha = 1.0;
@@ -1538,12 +1641,15 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
       D.s_floor[sid] += floor_hits;
       D.s_fallback[sid] += fallbacks;
       D.s_halved[sid] += halved;
+      if (red[37] > D.s_floor_res[sid]) { D.s_floor_res[sid] = red[37]; D.s_floor_est[sid] = red[38]; }
     } else {
       D.s_steps[sid] = steps;
       D.s_iters[sid] = iters;
       D.s_floor[sid] = floor_hits;
       D.s_fallback[sid] = fallbacks;
       D.s_halved[sid] = halved;
+      D.s_floor_res[sid] = red[37];
+      D.s_floor_est[sid] = red[38];
     }
   }
 }

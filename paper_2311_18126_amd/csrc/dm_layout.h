@@ -153,11 +153,15 @@ struct DmDev {
   double DM_G* R;      // [n_dof_total]
   double DM_G* fac;    // [n_dof_total][12]
   double DM_G* delta;  // [n_dof_total]
+  double DM_G* babs;   // [bmap entries]: sum_k |J_rk| s_k over the band columns of a border row r
+                       // (the part of its rounding-floor row sum held by one chain)
   double DM_G* zpad;   // [16] zeros, never written: where out-of-range solver loads are sent
   // statistics
   int DM_G* s_steps; int DM_G* s_iters; int DM_G* s_status; double DM_G* s_res; int DM_G* s_floor;
   int DM_G* s_fallback;  // warm-started attempts that had to restart from the step start
   int DM_G* s_halved;    // substeps whose failed Newton solve was redone as two halves
+  double DM_G* s_floor_res;  // largest residual among (sub)steps ended at the rounding floor
+  double DM_G* s_floor_est;  // the floor estimate of that (sub)step
   double DM_G* dbg;     // [n_systems][8] phase timers in diagnosis builds; null otherwise
   int n_nodes_tot, n_edges_tot, n_st_tot;
 };
@@ -183,7 +187,8 @@ struct DmNetView {
 struct DmStepArgs {
   DmDev d;
   DmNetView net;
-  double dt, tol, stag_tol;   // dt: the Newton solve's step (half the time step under midpoint)
+  double dt, tol;      // dt: the Newton solve's step (half the time step under midpoint)
+  double floor_factor; // rounding-floor estimate factor * eps * || |J| s ||_2 (0: no floor rule)
   double g[3];
   double damping;
   double floor_z, delta, nu, mu, kc;

@@ -129,11 +129,29 @@ struct dm_sim {
 
 namespace {
 
+// Device memory of a simulation: the caller's allocator hook when one is set (dm_config.alloc),
+// else hipMalloc; nullptr on failure.
+void* dev_malloc(const dm_sim* s, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 1);
+  if (s->cfg.alloc) return s->cfg.alloc(bytes, s->cfg.alloc_ctx);
+  void* p = nullptr;
+  return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+
+// Release a buffer of dev_malloc once the simulation's stream has drained (a hook's allocator
+// may hand the pages out again at once).
+void dev_free(const dm_sim* s, void* p) {
+  if (!p) return;
+  (void)hipStreamSynchronize(s->stream);
+  if (s->cfg.alloc) s->cfg.free_(p, s->cfg.alloc_ctx);
+  else (void)hipFree(p);
+}
+
 template <class T>
 dm_status upload(dm_sim* s, const std::vector<T>& h, T** out) {
   size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(T);
-  void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return fail(DM_ERR_OOM, "hipMalloc failed (" + std::to_string(bytes) + " bytes)");
+  void* p = dev_malloc(s, bytes);
+  if (!p) return fail(DM_ERR_OOM, "device allocation failed (" + std::to_string(bytes) + " bytes)");
   s->allocs.push_back(p);
   if (!h.empty()) DM_HIP(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
   *out = static_cast<T*>(p);
@@ -143,8 +161,8 @@ dm_status upload(dm_sim* s, const std::vector<T>& h, T** out) {
 template <class T>
 dm_status alloc(dm_sim* s, size_t n, T** out) {
   size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
-  void* p = nullptr;
-  if (hipMalloc(&p, bytes) != hipSuccess) return fail(DM_ERR_OOM, "hipMalloc failed (" + std::to_string(bytes) + " bytes)");
+  void* p = dev_malloc(s, bytes);
+  if (!p) return fail(DM_ERR_OOM, "device allocation failed (" + std::to_string(bytes) + " bytes)");
   s->allocs.push_back(p);
   DM_HIP(hipMemset(p, 0, bytes));
   *out = static_cast<T*>(p);
@@ -673,6 +691,9 @@ dm_status do_finalize(dm_sim* s) {
   if ((st = alloc(s, (size_t)dof_total, &D.R)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)DM_FAC_STRIDE * std::max(fac_total, 1), &D.fac)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)dof_total, &D.delta)) != DM_OK) return st;
+  if ((st = alloc(s, bmap.size(), &D.babs)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)s->n_sys, &D.s_floor_res)) != DM_OK) return st;
+  if ((st = alloc(s, (size_t)s->n_sys, &D.s_floor_est)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)16, &D.zpad)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)s->n_sys, &D.s_steps)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)s->n_sys, &D.s_iters)) != DM_OK) return st;
@@ -740,7 +761,7 @@ void fill_step_args(const dm_sim* s, double dt, int nsteps, DmStepArgs& A) {
   A.max_halvings = s->max_halvings;
   A.dt = A.midpoint ? 0.5 * dt : dt;
   A.tol = s->cfg.newton_tol;
-  A.stag_tol = s->cfg.stagnation_tol;
+  A.floor_factor = s->cfg.floor_factor;
   for (int c = 0; c < 3; ++c) A.g[c] = s->cfg.gravity[c];
   A.damping = s->cfg.damping;
   A.floor_on = s->cfg.floor_contact;
@@ -768,12 +789,11 @@ size_t step_lds(DmStepArgs& A) {
 }
 
 // Device buffer of at least n doubles (contents not kept when it grows).
-dm_status grow(double** p, size_t* cap, size_t n) {
+dm_status grow(dm_sim* s, double** p, size_t* cap, size_t n) {
   if (*cap >= n && *p) return DM_OK;
-  if (*p) { DM_HIP(hipFree(*p)); *p = nullptr; *cap = 0; }
-  void* q = nullptr;
-  if (hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(double)) != hipSuccess)
-    return fail(DM_ERR_OOM, "hipMalloc failed (" + std::to_string(n * sizeof(double)) + " bytes)");
+  if (*p) { dev_free(s, *p); *p = nullptr; *cap = 0; }
+  void* q = dev_malloc(s, std::max<size_t>(n, 1) * sizeof(double));
+  if (!q) return fail(DM_ERR_OOM, "device allocation failed (" + std::to_string(n * sizeof(double)) + " bytes)");
   *p = static_cast<double*>(q);
   *cap = n;
   return DM_OK;
@@ -907,6 +927,8 @@ dm_status zero_stats(dm_sim* s) {
   for (int* p : {s->dev.s_steps, s->dev.s_iters, s->dev.s_status, s->dev.s_floor, s->dev.s_fallback,
                  s->dev.s_halved})
     DM_HIP(hipMemsetAsync(p, 0, sizeof(int) * s->n_sys, s->stream));
+  for (double* p : {s->dev.s_floor_res, s->dev.s_floor_est})
+    DM_HIP(hipMemsetAsync(p, 0, sizeof(double) * s->n_sys, s->stream));
   return DM_OK;
 }
 
@@ -950,7 +972,7 @@ void dm_config_default(dm_config* c) {
   std::memset(c, 0, sizeof(*c));
   c->gravity[2] = -9.81;
   c->newton_tol = 1e-9;
-  c->stagnation_tol = 1e-6;
+  c->floor_factor = 1.0;
   c->max_iter = 50;
   c->use_graphs = 1;
   c->delta = 5e-4;
@@ -961,8 +983,10 @@ void dm_config_default(dm_config* c) {
 
 dm_status dm_create(const dm_config* cfg, dm_sim** out) {
   if (!cfg || !out) return fail(DM_ERR_INVALID_ARG, "dm_create: null argument");
-  if (!(cfg->newton_tol >= 0.0) || !(cfg->stagnation_tol >= 0.0) || cfg->max_iter < 1 || cfg->warm_max_iter < 0)
+  if (!(cfg->newton_tol >= 0.0) || !(cfg->floor_factor >= 0.0) || !std::isfinite(cfg->floor_factor) ||
+      cfg->max_iter < 1 || cfg->warm_max_iter < 0)
     return fail(DM_ERR_INVALID_ARG, "dm_create: bad Newton settings");
+  if (cfg->alloc && !cfg->free_) return fail(DM_ERR_INVALID_ARG, "dm_create: an allocator hook needs free_");
   if (cfg->block_size != 0 && (cfg->block_size < 64 || cfg->block_size > 512 || cfg->block_size % 64))
     return fail(DM_ERR_INVALID_ARG, "dm_create: block_size must be 0 or a multiple of 64 in [64, 512]");
   if (cfg->floor_contact && (!(cfg->delta > 0) || !(cfg->nu > 0) || !(cfg->k_contact >= 0) || !(cfg->mu >= 0)))
@@ -1081,8 +1105,7 @@ dm_status dm_finalize(dm_sim* s) {
   DM_HIP(hipSetDevice(s->cfg.device));
   dm_status st = do_finalize(s);
   if (st != DM_OK) {
-    for (void* p : s->allocs) (void)hipFree(p);
-    for (double* p : {s->ck, s->seg, s->adj, s->tips_dev, s->dl_dev}) if (p) (void)hipFree(p);
+    for (void* p : s->allocs) dev_free(s, p);
     s->allocs.clear();
     s->finalized = false;
   }
@@ -1109,7 +1132,9 @@ dm_status dm_step(dm_sim* s, double dt, int nsteps, dm_stats* stats) {
       halved(s->n_sys);
   DM_HIP(hipMemcpy(falls.data(), s->dev.s_fallback, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
   DM_HIP(hipMemcpy(halved.data(), s->dev.s_halved, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
-  std::vector<double> res(s->n_sys);
+  std::vector<double> res(s->n_sys), fres(s->n_sys), fest(s->n_sys);
+  DM_HIP(hipMemcpy(fres.data(), s->dev.s_floor_res, sizeof(double) * s->n_sys, hipMemcpyDeviceToHost));
+  DM_HIP(hipMemcpy(fest.data(), s->dev.s_floor_est, sizeof(double) * s->n_sys, hipMemcpyDeviceToHost));
   DM_HIP(hipMemcpy(steps.data(), s->dev.s_steps, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
   DM_HIP(hipMemcpy(iters.data(), s->dev.s_iters, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
   DM_HIP(hipMemcpy(status.data(), s->dev.s_status, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
@@ -1121,6 +1146,7 @@ dm_status dm_step(dm_sim* s, double dt, int nsteps, dm_stats* stats) {
       stats[i].steps_done = steps[i]; stats[i].newton_iters = iters[i]; stats[i].status = status[i];
       stats[i].floor_steps = floors[i]; stats[i].residual = res[i]; stats[i].fallbacks = falls[i];
       stats[i].halvings = halved[i];
+      stats[i].floor_residual_max = fres[i]; stats[i].floor_estimate = fest[i];
     }
     if (status[i] == DM_ERR_SINGULAR) worst = DM_ERR_SINGULAR;
     else if (status[i] == DM_NOT_CONVERGED && worst == DM_OK) worst = DM_NOT_CONVERGED;
@@ -1220,7 +1246,7 @@ dm_status dm_ws_predict(dm_sim* s, double dt, double* dx, int on_device) {
   double* out = dx;
   dm_status st;
   if (!on_device) {
-    if ((st = grow(&s->ws_F, &s->ws_F_n, n)) != DM_OK) return st;
+    if ((st = grow(s, &s->ws_F, &s->ws_F_n, n)) != DM_OK) return st;
     out = s->ws_F;
   }
   DM_HIP(dm_launch_predict(&A, s->block, lds, out, s->stream));
@@ -1241,7 +1267,7 @@ dm_status dm_rollout(dm_sim* s, double dt, int nsteps, int ckpt_every, double* t
   const size_t W = traj_stride(s);
   const int nck = (nsteps + ckpt_every - 1) / ckpt_every;
   const int nr = (int)s->rods.size();
-  if ((st = grow(&s->ck, &s->ck_n, (size_t)nck * W)) != DM_OK) return st;
+  if ((st = grow(s, &s->ck, &s->ck_n, (size_t)nck * W)) != DM_OK) return st;
   if (!s->tip_nodes) {
     std::vector<int> tn(nr);
     for (int r = 0; r < nr; ++r) tn[r] = s->rod_node[r].back();
@@ -1251,12 +1277,12 @@ dm_status dm_rollout(dm_sim* s, double dt, int nsteps, int ckpt_every, double* t
   }
   double* tdev = tips;
   if (!on_device) {
-    if ((st = grow(&s->tips_dev, &s->tips_n, (size_t)nsteps * nr * 3)) != DM_OK) return st;
+    if ((st = grow(s, &s->tips_dev, &s->tips_n, (size_t)nsteps * nr * 3)) != DM_OK) return st;
     tdev = s->tips_dev;
   }
   // captured segments gather the tips into a fixed staging buffer, copied out per segment
   if (s->cfg.use_graphs &&
-      (st = grow(&s->tips_stage, &s->tips_stage_n, (size_t)std::min(ckpt_every, nsteps) * nr * 3)) != DM_OK)
+      (st = grow(s, &s->tips_stage, &s->tips_stage_n, (size_t)std::min(ckpt_every, nsteps) * nr * 3)) != DM_OK)
     return st;
   CaptureStream cs(s);
   if ((st = zero_stats(s)) != DM_OK) return st;
@@ -1294,16 +1320,16 @@ dm_status dm_adjoint(dm_sim* s, const double* dL_dtips, int in_on_device, double
   const double dt = s->roll_dt;
   const double* dl = dL_dtips;
   if (!in_on_device) {
-    if ((st = grow(&s->dl_dev, &s->dl_n, (size_t)T * nr * 3)) != DM_OK) return st;
+    if ((st = grow(s, &s->dl_dev, &s->dl_n, (size_t)T * nr * 3)) != DM_OK) return st;
     DM_HIP(hipMemcpyAsync(s->dl_dev, dL_dtips, sizeof(double) * (size_t)T * nr * 3, hipMemcpyHostToDevice, s->stream));
     dl = s->dl_dev;
   }
   // adjoint arrays: ax, av [3NN]; ath, aom [NE]; atref, ad1 [3NE]; akap [2NS]; lam [3NN+NE];
   // pst [16NS]; pe [3NE]
   const size_t na = 9 * NN + 12 * NE + 18 * NS;
-  if ((st = grow(&s->adj, &s->adj_n, na)) != DM_OK) return st;
+  if ((st = grow(s, &s->adj, &s->adj_n, na)) != DM_OK) return st;
   DM_HIP(hipMemsetAsync(s->adj, 0, sizeof(double) * na, s->stream));
-  if ((st = grow(&s->seg, &s->seg_n, (size_t)(C + 2) * W)) != DM_OK) return st;
+  if ((st = grow(s, &s->seg, &s->seg_n, (size_t)(C + 2) * W)) != DM_OK) return st;
   double* fin = s->seg + (size_t)(C + 1) * W;
   if ((st = save_state(s, fin)) != DM_OK) return st;
   const double t_end = s->time;
@@ -1379,10 +1405,10 @@ dm_status dm_fit_natural_curvature(dm_sim* s, double dt, int nsteps, int ckpt_ev
   const size_t nk = kbar_total(s), nt = (size_t)nsteps * s->rods.size() * 3, nc = dm_checkpoint_size(s);
   // device work buffers of this call: kbar, its gradient, tips, target, dL/dtips, loss, start state
   std::vector<double*> bufs;
-  struct Guard { std::vector<double*>& b; ~Guard() { for (double* p : b) (void)hipFree(p); } } guard{bufs};
+  struct Guard { dm_sim* s; std::vector<double*>& b; ~Guard() { for (double* p : b) dev_free(s, p); } } guard{s, bufs};
   auto get = [&](size_t n, double** p) -> dm_status {
-    if (hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(double)) != hipSuccess)
-      return fail(DM_ERR_OOM, "dm_fit_natural_curvature: hipMalloc failed");
+    *p = static_cast<double*>(dev_malloc(s, std::max<size_t>(n, 1) * sizeof(double)));
+    if (!*p) return fail(DM_ERR_OOM, "dm_fit_natural_curvature: device allocation failed");
     bufs.push_back(*p);
     return DM_OK;
   };
@@ -1451,7 +1477,7 @@ dm_status dm_autotune(dm_sim* s, double dt, int trial_steps, const char* cache_p
   }
   dm_status st;
   const size_t n = state_doubles(s);
-  if ((st = grow(&s->tune_ck, &s->tune_ck_n, n)) != DM_OK) return st;
+  if ((st = grow(s, &s->tune_ck, &s->tune_ck_n, n)) != DM_OK) return st;
   if ((st = dm_save_checkpoint(s, s->tune_ck, 1)) != DM_OK) return st;
   const double t0 = s->time;
   const int old = s->block;
@@ -1639,15 +1665,13 @@ const char* dm_last_error(void) { return g_err.c_str(); }
 
 void dm_destroy(dm_sim* s) {
   if (!s) return;
-  if (s->finalized || !s->allocs.empty()) {
-    (void)hipSetDevice(s->cfg.device);
-    (void)hipStreamSynchronize(s->stream);
-    for (void* p : s->allocs) (void)hipFree(p);
-    for (double* p : {s->ck, s->seg, s->adj, s->tips_dev, s->dl_dev}) if (p) (void)hipFree(p);
-  }
+  (void)hipSetDevice(s->cfg.device);
+  (void)hipStreamSynchronize(s->stream);
+  for (void* p : s->allocs) dev_free(s, p);
+  for (double* p : {s->ck, s->seg, s->adj, s->tips_dev, s->dl_dev, s->ws_F, s->tips_stage, s->tune_ck})
+    dev_free(s, p);
   for (SegGraph& c : s->seg_graphs) { (void)hipGraphExecDestroy(c.exec); (void)hipGraphDestroy(c.graph); }
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
-  if (s->tune_ck) (void)hipFree(s->tune_ck);
   if (s->ev0) { (void)hipEventDestroy(s->ev0); (void)hipEventDestroy(s->ev1); }
   delete s;
 }

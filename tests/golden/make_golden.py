@@ -85,6 +85,46 @@ def golden_batch():
     return outs
 
 
+def golden_batch100():
+    """The sampled batch rods (the longest, N = 400, included) over 100 steps, with their
+    initial shapes, for displacement-relative parity at steps 1, 10 and 100."""
+    d = W.rod_batch(1024)
+    ids = batch_sample_ids(d)
+    outs = {}
+    for j, r in enumerate(ids):
+        o = run(d, [r], {1, 10, 100})
+        for k, v in o.items():
+            outs[f"{k}_r{j}"] = v
+        outs[f"x0_r{j}"] = d["rods"][r]["x0"]
+        print(f"  batch100: rod {r} done", flush=True)
+    outs["rods"] = np.array(ids)
+    return outs
+
+
+def golden_star100():
+    d = W.star_robots(n_instances=1, steps=100)
+    out = run(d, list(range(6)), {1, 10, 100})
+    for a in range(6):
+        out[f"x0_{a}"] = d["rods"][a]["x0"]
+    return out
+
+
+# the adjoint workload at its full rod size and length (100 nodes, 200 steps, checkpoints every
+# 20), for its first two rods, from zero natural curvature toward the seeded target
+ADJ_FULL_RODS = 2
+
+
+def golden_adjoint_full():
+    d, target_kbar = W.adjoint_rods(n_rods=ADJ_FULL_RODS)
+    kstar = [target_kbar[r] for r in range(ADJ_FULL_RODS)]
+    _, _, target = AD.rollout(d, kstar)
+    n = d["rods"][0]["x0"].shape[0]
+    k0 = [np.zeros((n - 2, 2)) for _ in range(ADJ_FULL_RODS)]
+    L, g, tips = AD.loss_and_grad(d, k0, target)
+    return {"target_tips": target.numpy(), "loss": np.array(L), "grad": np.stack([gi.numpy() for gi in g]),
+            "tips": tips.numpy()}
+
+
 def golden_helix():
     d = W.paper_helix(steps=20)
     return run(d, [0], {1, 20})
@@ -141,7 +181,8 @@ def golden_fit():
 
 GOLDEN = {"cantilever": golden_cantilever, "batch": golden_batch, "helix": golden_helix, "star": golden_star,
           "adjoint": golden_adjoint, "cantilever_midpoint": golden_cantilever_midpoint,
-          "star_midpoint": golden_star_midpoint, "fit": golden_fit}
+          "star_midpoint": golden_star_midpoint, "fit": golden_fit, "batch100": golden_batch100,
+          "star100": golden_star100, "adjoint_full": golden_adjoint_full}
 
 
 if __name__ == "__main__":

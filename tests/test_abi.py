@@ -49,7 +49,8 @@ def test_config_struct_matches_header_defaults(library):
     cfg = dm.DmConfig()
     dm.lib().dm_config_default(ctypes.byref(cfg))
     assert cfg.newton_tol == 1e-9 and cfg.max_iter == 50 and cfg.gravity[2] == -9.81
-    assert cfg.block_size == 0 and cfg.floor_contact == 0
+    assert cfg.block_size == 0 and cfg.floor_contact == 0 and cfg.floor_factor == 1.0
+    assert not cfg.alloc and not cfg.free_ and not cfg.alloc_ctx
 
 
 def test_missing_device_is_an_error_not_a_fallback(library):

@@ -64,6 +64,31 @@ def test_adjoint_matches_oracle_gradient(dm, golden_desc, case):
     assert np.allclose(x[-1], tips[-1, 1], rtol=0, atol=0)
 
 
+def test_full_size_adjoint_matches_oracle_gradient(dm):
+    """The adjoint workload at its full size in one launch (256 rods of 100 nodes, 200 steps,
+    checkpoints every 20), from zero natural curvature toward the seeded target: the gradients
+    of its first two rods against the oracle's adjoint of the same two rods (rods do not
+    interact, so the oracle runs them alone), 1e-7 relative."""
+    g = np.load(os.path.join(GOLD, "adjoint_full.npz"))
+    d, kstar = W.adjoint_rods()
+    T = d["steps"]
+    say(f"case: full adjoint workload, 256 rods x 100 nodes, {T} steps, checkpoint every 20")
+    sim = dm.sim_from_description(d)
+    sim.set_natural_curvature_all(kstar.reshape(-1))
+    target = sim.rollout(d["dt"], T, ckpt_every=20)
+    assert np.linalg.norm(target[:, :2] - g["target_tips"]) <= 1e-9 * np.linalg.norm(g["target_tips"])
+    sim.close()
+    sim = dm.sim_from_description(d)
+    tips = sim.rollout(d["dt"], T, ckpt_every=20)
+    assert np.linalg.norm(tips[:, :2] - g["tips"]) <= 1e-9 * np.linalg.norm(g["tips"])
+    grad = sim.adjoint(2.0 * (tips - target)).reshape(256, -1)
+    for r in range(2):
+        ref = g["grad"][r].reshape(-1)
+        rel = np.linalg.norm(grad[r] - ref) / np.linalg.norm(ref)
+        say(f"  rod {r}: relative gradient error vs oracle {rel:.3e}")
+        assert rel < 1e-7
+
+
 def test_adjoint_checkpoint_interval_does_not_change_the_gradient(dm, golden_desc):
     g = np.load(os.path.join(GOLD, "adjoint.npz"))
     d, T = golden_desc

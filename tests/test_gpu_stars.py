@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from parity import assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -41,12 +42,30 @@ def test_one_star_matches_golden(dm):
     sim = dm.sim_from_description(d)
     assert sim.num_systems == 1
     done = 0
+    x0 = np.concatenate([d["rods"][a]["x0"] for a in range(6)])
     for k in (1, 5, 20):
         st = sim.step(d["dt"], k - done)
         done = k
         assert st["status"][0] == 0
         tol = 1e-9 if k == 1 else 1e-7
-        assert rel(star_positions(sim, 0), golden_positions(g, k)) < tol, (k, rel(star_positions(sim, 0), golden_positions(g, k)))
+        assert_parity(star_positions(sim, 0), golden_positions(g, k), x0, tol, 1e-6, f"star step {k}")
+
+
+def test_one_star_matches_golden_over_100_steps(dm):
+    """One actuated star on the floor over 100 steps against the oracle: 1e-6 of the positions
+    and of the displacement at steps 1, 10 and 100."""
+    g = np.load(os.path.join(GOLD, "star100.npz"))
+    d = W.star_robots(n_instances=1, steps=100)
+    print("case: one six-limb star, 100 steps", flush=True)
+    sim = dm.sim_from_description(d)
+    x0 = np.concatenate([g[f"x0_{a}"] for a in range(6)])
+    done = 0
+    for k in (1, 10, 100):
+        st = sim.step(d["dt"], k - done)
+        done = k
+        assert st["status"][0] == 0
+        assert_parity(star_positions(sim, 0), golden_positions(g, k), x0, 1e-9 if k == 1 else 1e-6, 1e-6,
+                      f"star step {k}")
 
 
 def test_full_star_batch_instance_matches_golden(dm):
@@ -58,7 +77,8 @@ def test_full_star_batch_instance_matches_golden(dm):
     assert sim.num_systems == 4096
     st = sim.step(d["dt"], 5)
     assert (st["status"] == 0).all(), np.unique(st["status"], return_counts=True)
-    assert rel(star_positions(sim, 0), golden_positions(g, 5)) < 1e-7
+    x0 = np.concatenate([d["rods"][a]["x0"] for a in range(6)])
+    assert_parity(star_positions(sim, 0), golden_positions(g, 5), x0, 1e-7, 1e-6, "star 0 of 4096, step 5")
 
 
 def test_hub_is_one_node(dm):
@@ -107,4 +127,5 @@ def test_many_limb_star_matches_oracle(dm, limbs):
         assert info.converged
         ref = np.concatenate([der.rod_positions(osys, ost, a).numpy() for a in range(limbs)])
         got = np.concatenate([sim.rod_state(a)[0] for a in range(limbs)])
-        assert rel(got, ref) < tol, (limbs, k, rel(got, ref))
+        x0 = np.concatenate([d["rods"][a]["x0"] for a in range(limbs)])
+        assert_parity(got, ref, x0, tol, 1e-6, f"{limbs} limbs, step {k}")
