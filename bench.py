@@ -27,10 +27,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "node-steps/s, batched implicit DER at 1e-9 residual; plain vs warm-started"
-# Algorithmic FP64 work of one Newton iteration per rod node (closed-form operation count of
-# the method): frames ~100, strains ~110, stretch ~100, bend Hessian ~1750, twist ~400, node
-# terms ~20, assembly ~280, banded LU and solves ~1160, update ~10.
-FLOPS_PER_NODE_ITER = 4.0e3
+# Algorithmic FP64 work of one Newton iteration per item, counted by the host program
+# paper_2311_18126_amd/dm_flops over the step's own element math (csrc/dm_flops.cpp states the
+# counting rules); the committed output is read here and checked against the program by the
+# CPU tests.
+FLOP_COUNT_FILE = os.path.join(ROOT, "profiles", "flop_count.json")
 PEAK_FP64_VALU_TFLOPS = 78.6          # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_BF16_MFMA_TFLOPS = 2500.0        # dense BF16 matrix-core peak, published
 # 20-256-256-3 network, per row of a training step: forward 2 (20*256 + 256*256 + 256*3),
@@ -42,6 +43,46 @@ KERNEL_SOURCES = ["paper_2311_18126_amd/csrc/dm_kernels.hip", "paper_2311_18126_
                   "paper_2311_18126_amd/csrc/dm_bf16.h",
                   "paper_2311_18126_amd/build.py"]      # the compiler flags shape the kernel too
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dm_step_kernel_rod_batch_traffic.json")
+
+
+def rod_iteration_flops(n_nodes, count=None):
+    """Counted FP64 operations of one Newton iteration of a clamped single rod of n nodes:
+    stencils, stretch and twist inertia of the edges, node terms, their assembly into the band,
+    the banded LU of the two arms with back substitution, the 10-DOF separator's dense LU and
+    the arms' Schur blocks added into it, the update and the residual norm."""
+    if count is None:
+        with open(FLOP_COUNT_FILE) as f:
+            count = json.load(f)
+    n = np.asarray(n_nodes, dtype=np.float64)
+    if np.any(n < 4):
+        raise ValueError("the per-rod count assumes a 10-DOF separator and two arms (rods of 4 nodes or more)")
+    dof = 4 * n - 1
+    return ((n - 2) * (count["stencil"] + count["assembly_stencil"])
+            + (n - 1) * (count["stretch"] + count["edge_inertia"] + count["assembly_edge"])
+            + n * (count["node"] + count["assembly_node"])
+            + (dof - 10) * (count["lu_row"] + count["backsub_row"]) + count["border_lu_10"] + 2 * count["schur_per_arm"]
+            + dof * count["dof"])
+
+
+def star_iteration_flops(limbs=6, limb_nodes=30, count=None):
+    """Counted FP64 operations of one Newton iteration of a star of `limbs` rods of
+    limb_nodes + 1 nodes joined at a hub: limb and hub stencils (every pair of hub edges),
+    edges, nodes (contact and friction terms not counted: a lower bound), each limb's arm
+    eliminated toward the 3 + 4 limbs border, the border's dense LU and the Schur blocks."""
+    if count is None:
+        with open(FLOP_COUNT_FILE) as f:
+            count = json.load(f)
+    assert limbs == 6, "the committed count holds the six-limb hub's border"
+    n = limb_nodes + 1
+    stencils = limbs * (n - 2) + limbs * (limbs - 1) // 2
+    edges, nodes = limbs * (n - 1), limbs * (n - 1) + 1
+    dof = limbs * (4 * n - 1) - 3 * (limbs - 1)
+    eliminated = limbs * (4 * n - 1 - 7)
+    return (stencils * (count["stencil"] + count["assembly_stencil"])
+            + edges * (count["stretch"] + count["edge_inertia"] + count["assembly_edge"])
+            + nodes * (count["node"] + count["assembly_node"])
+            + eliminated * (count["lu_row"] + count["backsub_row"]) + count["border_lu_27"]
+            + limbs * count["schur_per_arm"] + dof * count["dof"])
 
 
 def kernel_hash():
@@ -365,8 +406,8 @@ def config_table(dm, log):
         sim.close()
         return nodes * steps / wall, iters / st["iters"].size / steps, kernel_s, nodes, iters
 
-    def fp64_frac(nodes_per_sys_iters, kernel_s):
-        return FLOPS_PER_NODE_ITER * nodes_per_sys_iters / kernel_s / (PEAK_FP64_VALU_TFLOPS * 1e12)
+    def fp64_frac(flops, kernel_s):
+        return flops / kernel_s / (PEAK_FP64_VALU_TFLOPS * 1e12)
 
     # cfg1: single cantilever
     d = W.cantilever(steps=100)
@@ -376,7 +417,7 @@ def config_table(dm, log):
     rows.append({"config": "cfg1 cantilever N=51, dt 1e-2, 100 steps", "plain_per_rod_gpu": v, "batched_gpu": None,
                  "warm_started_gpu": vw, "cpu_oracle_1_thread": oracle_rate(one, 1, 4.0),
                  "cpu_oracle_all_cores": oracle_rate(one, threads, 4.0), "cores": threads,
-                 "fp64_roof_fraction": fp64_frac(nodes * iters, ks), "hbm_roof_fraction": None,
+                 "fp64_roof_fraction": fp64_frac(float(rod_iteration_flops(51)) * iters, ks), "hbm_roof_fraction": None,
                  "newton_iters_plain": it, "newton_iters_warm": itw})
     log(f"configs: {rows[-1]}")
     # cfg2: 1024-rod batch
@@ -402,7 +443,7 @@ def config_table(dm, log):
     call = oracle_rate(one_rod, threads, 6.0)
     rows.append({"config": "cfg2 1024 rods N~U{20..400}, dt 1e-3", "plain_per_rod_gpu": per_rod_baseline(dm, d, 20),
                  "batched_gpu": v, "warm_started_gpu": vw, "cpu_oracle_1_thread": c1, "cpu_oracle_all_cores": call,
-                 "cores": threads, "fp64_roof_fraction": fp64_frac(float((n_r * st["iters"]).sum()), ks),
+                 "cores": threads, "fp64_roof_fraction": fp64_frac(float((rod_iteration_flops(n_r) * st["iters"]).sum()), ks),
                  "hbm_roof_fraction": None if traffic is None else traffic / ks / 8e12,
                  "newton_iters_plain": it, "newton_iters_warm": itw})
     log(f"configs: {rows[-1]}")
@@ -416,7 +457,7 @@ def config_table(dm, log):
     rows.append({"config": "cfg3 4096 six-limb stars, floor contact, actuation", "plain_per_rod_gpu": v1,
                  "batched_gpu": v, "warm_started_gpu": vw, "cpu_oracle_1_thread": oracle_rate(star, 1, 6.0),
                  "cpu_oracle_all_cores": oracle_rate(star, threads, 6.0), "cores": threads,
-                 "fp64_roof_fraction": fp64_frac(iters / 4096.0 * nodes, ks),
+                 "fp64_roof_fraction": fp64_frac(star_iteration_flops() * iters, ks),
                  "hbm_roof_fraction": None, "newton_iters_plain": it, "newton_iters_warm": itw})
     log(f"configs: {rows[-1]}")
     # cfg4: learned warm start (network) on fresh rods
@@ -514,7 +555,7 @@ def main():
     # systems are rods here, in order
     iters = stats["iters"].astype(np.float64)
     node_steps = float(n_nodes.sum()) * args.steps
-    flops = FLOPS_PER_NODE_ITER * float((n_nodes * iters).sum())
+    flops = float((rod_iteration_flops(n_nodes) * iters).sum())
     achieved = flops / kernel_s / 1e12
     traffic = measured_traffic(args.steps)
     out = {
@@ -544,7 +585,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP64_VALU_TFLOPS, "traffic": traffic,
                      "kernel": "dm_step_kernel", "kernel_ms": 1e3 * kernel_s,
-                     "algorithmic_flops": flops},
+                     "algorithmic_flops": flops, "flops_from": "profiles/flop_count.json (dm_flops)",
+                     "flops_per_node_iteration": flops / float((n_nodes * iters).sum())},
     }
     sim.close()
     if not args.no_extras:

@@ -10,6 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdmrod.so")
 PEAKS = os.path.join(HERE, "dm_peaks")
+FLOPS = os.path.join(HERE, "dm_flops")
 SOURCES = ["dm_kernels.hip", "dm_mlp.hip", "dm_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -34,7 +35,22 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed building libdmrod.so")
     os.replace(tmp, LIB)
     build_peaks(verbose)
+    build_flops(verbose)
     return LIB
+
+
+def build_flops(verbose: bool = False) -> str:
+    """Compile the operation counter of the element math (a host program, no GPU code)."""
+    tmp = FLOPS + ".tmp"
+    cmd = [HIPCC, "--cuda-host-only", "-O2", "-std=c++17", os.path.join(CSRC, "dm_flops.cpp"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building dm_flops")
+    os.replace(tmp, FLOPS)
+    return FLOPS
 
 
 def build_peaks(verbose: bool = False) -> str:
@@ -50,6 +66,21 @@ def build_peaks(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed building dm_peaks")
     os.replace(tmp, PEAKS)
     return PEAKS
+
+
+def build_hostcheck(out: str, verbose: bool = False) -> str:
+    """Compile the host check of the element math (csrc/dm_hostcheck.cpp) with AddressSanitizer
+    and UndefinedBehaviorSanitizer on the host code (the program has no GPU code)."""
+    cmd = [HIPCC, "--cuda-host-only", "-O1", "-g", "-std=c++17",
+           "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=all", os.path.join(CSRC, "dm_hostcheck.cpp"), "-o", out]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("hipcc failed building dm_hostcheck")
+    return out
 
 
 if __name__ == "__main__":

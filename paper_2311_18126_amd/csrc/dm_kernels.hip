@@ -143,26 +143,14 @@ __device__ __forceinline__ void eval_stencil(const DmStepArgs DM_C& A, int s, in
   }
 }
 
-// Stretch (Eq. 2-3): gradient EA (|e|/ebar - 1) t with respect to the edge vector and its
-// Hessian (EA/ebar) t t^T + EA (1/ebar - 1/|e|)(I - t t^T).
+// Stretch of one edge (stretch_terms, Eq. 2-3) into the edge scratch.
 __device__ __forceinline__ void eval_edge(const DmStepArgs DM_C& A, int e) {
   const DmDev DM_C& D = A.d;
   const int NE = D.n_edges_tot, NN = D.n_nodes_tot;
-  v3 d = ld3(D.x, NN, D.en[NE + e]) - ld3(D.x, NN, D.en[e]);
-  double l = sqrt(dot(d, d));
-  v3 t = (1.0 / l) * d;
-  double EA = D.EA[e], eb = D.ebar[e];
-  double f = EA * (l / eb - 1.0);
-  double c1 = EA / eb, c2 = EA * (1.0 / eb - 1.0 / l);
-  double tt[3] = {t.x, t.y, t.z};
-  D.ed[0 * NE + e] = f * t.x;
-  D.ed[1 * NE + e] = f * t.y;
-  D.ed[2 * NE + e] = f * t.z;
-  int k = 3;
+  double out[9];
+  stretch_terms(ld3(D.x, NN, D.en[NE + e]) - ld3(D.x, NN, D.en[e]), D.EA[e], D.ebar[e], out);
 #pragma unroll
-  for (int i = 0; i < 3; ++i)
-#pragma unroll
-    for (int j = i; j < 3; ++j) D.ed[(k++) * NE + e] = (c1 - c2) * tt[i] * tt[j] + (i == j ? c2 : 0.0);
+  for (int k = 0; k < 9; ++k) D.ed[k * NE + e] = out[k];
 }
 
 __device__ __forceinline__ double edge_K(const DmDev DM_C& D, int NE, int e, int i, int j) {
