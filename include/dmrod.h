@@ -284,6 +284,17 @@ dm_status dm_mlp_get_normalisation(dm_mlp* net, double* mean, double* std, doubl
 dm_status dm_mlp_fit_normalisation(dm_mlp* net, const double* F, const double* T, int n);
 /* Y [n][3] (float32): the network's standardised output for raw features F [n][20]. */
 dm_status dm_mlp_forward(dm_mlp* net, const double* F, int n, float* Y);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same forward pass as dm_mlp_forward, bit for
+ * bit, with its activations (standardised inputs, both hidden layers, outputs) in a static
+ * device array of the library instead of the network's buffers, so the call allocates
+ * nothing.  n is limited to DM_MLP_NOALLOC_MAX_ROWS (the array holds that many rows, about
+ * 4.5 MB on each GPU the library runs on, kept until the process ends); a larger n returns
+ * DM_ERR_INVALID_ARG.  F [n][20] float64 and Y [n][3] float32 are device memory.  Every call
+ * on a GPU uses that GPU's one array: calls that overlap on one GPU (other threads, other
+ * streams) race.  The array's device address is looked up once per device on the first call. */
+#define DM_MLP_NOALLOC_MAX_ROWS 2048
+dm_status dm_mlp_forward_noalloc(dm_mlp* net, const double* F, int n, float* Y);
 /* Loss = (1/n) sum |y - T/scale|^2 and its gradient with respect to every parameter
  * (float32 [dm_mlp_num_params()], device); loss is a host pointer (may be NULL). */
 dm_status dm_mlp_gradients(dm_mlp* net, const double* F, const double* T, int n, float* grads, double* loss);

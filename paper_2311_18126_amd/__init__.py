@@ -24,6 +24,7 @@ DM_ERR_HIP = -3
 DM_ERR_OOM = -4
 DM_ERR_SINGULAR = -5
 DM_ERR_UNSUPPORTED = -6
+DM_MLP_NOALLOC_MAX_ROWS = 2048     # rows of dm_mlp_forward_noalloc's static activation buffer
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p)
@@ -87,6 +88,7 @@ _SIGS = {
     "dm_mlp_get_normalisation": (c_int, [c_void_p, _DP, _DP, _DP]),
     "dm_mlp_fit_normalisation": (c_int, [c_void_p, c_void_p, c_void_p, c_int]),
     "dm_mlp_forward": (c_int, [c_void_p, c_void_p, c_int, c_void_p]),
+    "dm_mlp_forward_noalloc": (c_int, [c_void_p, c_void_p, c_int, c_void_p]),
     "dm_mlp_gradients": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_void_p, _DP]),
     "dm_mlp_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_float, _DP]),
     "dm_mlp_train_epoch": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_float, _DP]),
@@ -583,6 +585,13 @@ class Mlp:
 
     def fit_normalisation(self, F, T):
         _check(lib().dm_mlp_fit_normalisation(self._h, F.data_ptr(), T.data_ptr(), F.shape[0]), "dm_mlp_fit_normalisation")
+
+    def forward_noalloc(self, F, out):
+        """forward() through dm_mlp_forward_noalloc (static activations, at most
+        DM_MLP_NOALLOC_MAX_ROWS rows)."""
+        _check(lib().dm_mlp_forward_noalloc(self._h, F.data_ptr(), F.shape[0], out.data_ptr()),
+               "dm_mlp_forward_noalloc")
+        return out
 
     def forward(self, F, out):
         _check(lib().dm_mlp_forward(self._h, F.data_ptr(), F.shape[0], out.data_ptr()), "dm_mlp_forward")

@@ -12,6 +12,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 #include <stdint.h>
 #include <string>
 #include <vector>
@@ -560,19 +561,64 @@ dm_status check_rows(const dm_mlp* m, int n) {
   return DM_OK;
 }
 
-// Forward pass on raw features F (device, [n][20]); leaves Y [rows][3] (standardised outputs)
-// and every activation needed by the backward pass.
-dm_status forward_rows(dm_mlp* m, const double* F, int n, int rows) {
+// Activations of a forward pass: standardised inputs, both hidden layers (row-major and
+// transposed), outputs.
+struct FwdBufs {
+  u16 *X, *XT, *H1, *H1T, *H2, *H2T;
+  float* Y;
+};
+
+// Forward pass on raw features F (device, [n][20]) into the activation buffers b (rows padded
+// to ROWS_PAD): leaves Y [rows][3] (standardised outputs) and every activation needed by the
+// backward pass.
+dm_status forward_into(dm_mlp* m, const FwdBufs& b, const double* F, int n, int rows) {
   hipStream_t st = m->stream;
-  hipLaunchKernelGGL(standardise, dim3((rows + 255) / 256), dim3(256), 0, st, F, n, rows, m->mean, m->sd, m->X, m->XT);
-  const dim3 b(256);
-  hipLaunchKernelGGL((row_gemm<KX, NH, EPI_HIDDEN>), dim3(row_grid<KX, NH>(rows)), b, 0, st, m->X, m->W1b, m->P + OFF_B1,
-                     nullptr, rows, m->H1, m->H1T, nullptr);
-  hipLaunchKernelGGL((row_gemm<NH, NH, EPI_HIDDEN>), dim3(row_grid<NH, NH>(rows)), b, 0, st, m->H1, m->W2b, m->P + OFF_B2,
-                     nullptr, rows, m->H2, m->H2T, nullptr);
-  hipLaunchKernelGGL((row_gemm<NH, NOP, EPI_OUTPUT>), dim3(row_grid<NH, NOP>(rows)), b, 0, st, m->H2, m->W3b,
-                     m->P + OFF_B3, nullptr, rows, nullptr, nullptr, m->Y);
+  hipLaunchKernelGGL(standardise, dim3((rows + 255) / 256), dim3(256), 0, st, F, n, rows, m->mean, m->sd, b.X, b.XT);
+  const dim3 blk(256);
+  hipLaunchKernelGGL((row_gemm<KX, NH, EPI_HIDDEN>), dim3(row_grid<KX, NH>(rows)), blk, 0, st, b.X, m->W1b,
+                     m->P + OFF_B1, nullptr, rows, b.H1, b.H1T, nullptr);
+  hipLaunchKernelGGL((row_gemm<NH, NH, EPI_HIDDEN>), dim3(row_grid<NH, NH>(rows)), blk, 0, st, b.H1, m->W2b,
+                     m->P + OFF_B2, nullptr, rows, b.H2, b.H2T, nullptr);
+  hipLaunchKernelGGL((row_gemm<NH, NOP, EPI_OUTPUT>), dim3(row_grid<NH, NOP>(rows)), blk, 0, st, b.H2, m->W3b,
+                     m->P + OFF_B3, nullptr, rows, nullptr, nullptr, b.Y);
   MH(hipGetLastError());
+  return DM_OK;
+}
+
+// The same into the network's own buffers.
+dm_status forward_rows(dm_mlp* m, const double* F, int n, int rows) {
+  return forward_into(m, FwdBufs{m->X, m->XT, m->H1, m->H1T, m->H2, m->H2T, m->Y}, F, n, rows);
+}
+
+// ---- activations of dm_mlp_forward_noalloc: a file-scope device array, one copy per GPU ----
+// Byte offsets of the buffers for DM_MLP_NOALLOC_MAX_ROWS rows (each a multiple of 256).
+constexpr size_t NA_ROWS = DM_MLP_NOALLOC_MAX_ROWS;
+constexpr size_t NA_X = 0, NA_XT = NA_X + NA_ROWS * KX * 2, NA_H1 = NA_XT + NA_ROWS * KX * 2;
+constexpr size_t NA_H1T = NA_H1 + NA_ROWS * NH * 2, NA_H2 = NA_H1T + NA_ROWS * NH * 2;
+constexpr size_t NA_H2T = NA_H2 + NA_ROWS * NH * 2, NA_Y = NA_H2T + NA_ROWS * NH * 2;
+constexpr size_t NA_BYTES = NA_Y + NA_ROWS * NO * 4;
+static_assert(NA_ROWS % ROWS_PAD == 0 && NA_Y % 256 == 0, "scratch layout");
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+namespace {
+// Device address of `scratch` on each device, taken once per device (with that device
+// current) by hipGetSymbolAddress; host code uses only these addresses.
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+dm_status scratch_address(int device, void** out) {
+  if (device < 0 || device >= 64) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_forward_noalloc: device ordinal above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return mfail(DM_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
   return DM_OK;
 }
 
@@ -747,6 +793,26 @@ dm_status dm_mlp_fit_normalisation(dm_mlp* m, const double* F, const double* T, 
     else ys[c - NI] = std::sqrt(mo[2 * c + 1] / n) > 0 ? std::sqrt(mo[2 * c + 1] / n) : 1.0;
   }
   return dm_mlp_set_normalisation(m, mean, sd, ys);
+}
+
+dm_status dm_mlp_forward_noalloc(dm_mlp* m, const double* F, int n, float* Y) {
+  if (!m || !F || !Y) return mfail(DM_ERR_INVALID_ARG, "dm_mlp_forward_noalloc: null argument");
+  if (n <= 0 || n > DM_MLP_NOALLOC_MAX_ROWS)
+    return mfail(DM_ERR_INVALID_ARG, "dm_mlp_forward_noalloc: row count outside 1.." +
+                                         std::to_string(DM_MLP_NOALLOC_MAX_ROWS) + " (the static activation buffer)");
+  MH(hipSetDevice(m->device));
+  void* base = nullptr;
+  dm_status s;
+  if ((s = scratch_address(m->device, &base)) != DM_OK) return s;
+  unsigned char* p = static_cast<unsigned char*>(base);
+  const FwdBufs b{reinterpret_cast<u16*>(p + NA_X), reinterpret_cast<u16*>(p + NA_XT),
+                  reinterpret_cast<u16*>(p + NA_H1), reinterpret_cast<u16*>(p + NA_H1T),
+                  reinterpret_cast<u16*>(p + NA_H2), reinterpret_cast<u16*>(p + NA_H2T),
+                  reinterpret_cast<float*>(p + NA_Y)};
+  if ((s = forward_into(m, b, F, n, rup(n, ROWS_PAD))) != DM_OK) return s;
+  MH(hipMemcpyAsync(Y, b.Y, sizeof(float) * NO * (size_t)n, hipMemcpyDeviceToDevice, m->stream));
+  MH(hipStreamSynchronize(m->stream));
+  return DM_OK;
 }
 
 dm_status dm_mlp_forward(dm_mlp* m, const double* F, int n, float* Y) {
