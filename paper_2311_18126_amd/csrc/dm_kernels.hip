@@ -101,7 +101,9 @@ __device__ double block_sum(double v, double DM_L* red) {
 // columns are the stored stencil's e-edge columns, reached through the signed permutation
 // e_f <-> -e_e, theta_f <-> -theta_e (an even number of sign flips per Hessian entry, so only
 // the indices move).  Few tangents per lane keep the pass within the register file.
-template <int NT, int SUB>
+// WG: the task that seeds the first tangent of the stored orientation also writes the gradient
+// (off when a residual pass has already written it).
+template <int NT, int SUB, bool WG>
 __device__ __forceinline__ void eval_stencil(const DmStepArgs DM_C& A, int s, int rev, double t_end) {
   const DmDev DM_C& D = A.d;
   const int NS = D.n_st_tot, NE = D.n_edges_tot, NN = D.n_nodes_tot;
@@ -126,7 +128,7 @@ __device__ __forceinline__ void eval_stencil(const DmStepArgs DM_C& A, int s, in
   stencil_pass_n<NT, NT * SUB>(xc - ld3(D.x, NN, np), ld3(D.x, NN, nn) - xc, sf * D.th[ef], se * D.th[ee],
                              sf * ld3(D.tref, NE, ef), ld3(D.d1ref, NE, ef), se * ld3(D.tref, NE, ee),
                              ld3(D.d1ref, NE, ee), D.bref[s], k1b, k2b, D.tbar[s], D.kbend[s], D.ktwist[s], g8, Hf);
-  if (SUB == 0 && !rev) {
+  if (WG && SUB == 0 && !rev) {
 #pragma unroll
     for (int a = 0; a < 8; ++a) D.st_g[a * NS + s] = g8[a];
   }
@@ -141,6 +143,29 @@ __device__ __forceinline__ void eval_stencil(const DmStepArgs DM_C& A, int s, in
       D.st_H[(ra * 8 + w) * NS + s] = Hf[a][k];
     }
   }
+}
+
+// Gradient only of a stencil (the residual pass): the same closed form without tangents.
+__device__ __forceinline__ void eval_stencil_grad(const DmStepArgs DM_C& A, int s, double t_end) {
+  const DmDev DM_C& D = A.d;
+  const int NS = D.n_st_tot, NE = D.n_edges_tot, NN = D.n_nodes_tot;
+  const int np = D.sn[s], nc = D.sn[NS + s], nn = D.sn[2 * NS + s];
+  const int ef = D.se[s], ee = D.se[NS + s];
+  const int sg = D.ssign[s];
+  const double sf = (sg & 1) ? -1.0 : 1.0, se = (sg & 2) ? -1.0 : 1.0;
+  double k1b = D.kbar[s], k2b = D.kbar[NS + s];
+  const double amp = D.act[s];
+  if (!isnan(amp)) {   // actuation: kappa1 = A sin(2 pi f t + phi), integrated over Vbar
+    k1b = amp * sin(6.283185307179586476925286766559 * D.act[NS + s] * t_end + D.act[2 * NS + s]) * D.Vbar[s];
+    k2b = 0.0;
+  }
+  const v3 xc = ld3(D.x, NN, nc);
+  double g8[8];
+  stencil_grad_g<double>(tov(xc - ld3(D.x, NN, np)), tov(ld3(D.x, NN, nn) - xc), sf * D.th[ef], se * D.th[ee],
+                         tov(sf * ld3(D.tref, NE, ef)), tov(ld3(D.d1ref, NE, ef)), tov(se * ld3(D.tref, NE, ee)),
+                         tov(ld3(D.d1ref, NE, ee)), D.bref[s], k1b, k2b, D.tbar[s], D.kbend[s], D.ktwist[s], g8);
+#pragma unroll
+  for (int a = 0; a < 8; ++a) D.st_g[a * NS + s] = g8[a];
 }
 
 // Stretch of one edge (stretch_terms, Eq. 2-3) into the edge scratch.
@@ -329,7 +354,9 @@ __device__ __forceinline__ double row_contrib(const DmStepArgs DM_C& A, double d
 // Band row 4k + COMP.  Contributions are summed per diagonal first; clamped columns, and
 // border columns of a border row (those couplings live in the dense border), are zeroed
 // afterwards.  fixmask / bmask: bit i describes chain DOF 4k - 12 + i.
-template <int COMP>
+// MODE 0: matrix row and residual entry; 1: the residual entry only (the element terms not
+// read are never loaded); 2: the matrix row only.
+template <int COMP, int MODE>
 __device__ __forceinline__ double band_row(const DmStepArgs DM_C& A, double dt, const DmChain& ch, int k,
                                            unsigned fixmask, unsigned bmask, bool own) {
   const int r = 4 * k + COMP;
@@ -340,7 +367,7 @@ __device__ __forceinline__ double band_row(const DmStepArgs DM_C& A, double dt, 
   for (int o = 0; o < DM_NDIAG; ++o) acc[o] = 0.0;
   auto emit = [&](int rel, double v) { acc[rel - COMP + 10] += v; };
   double Rr = row_contrib<COMP>(A, dt, ch, k, own, emit);
-  if (rowb && !rowfix) {
+  if (MODE != 1 && rowb && !rowfix) {
     // the border-block part of a border row goes to the dense border (assemble_border)
     double DM_G* bp = A.d.bpr + (size_t)(ch.bmap_off + r - ch.b_lo) * DM_NDIAG;
 #pragma unroll
@@ -360,24 +387,28 @@ __device__ __forceinline__ double band_row(const DmStepArgs DM_C& A, double dt, 
     for (int o = 0; o < DM_NDIAG; ++o) acc[o] = (o == 10) ? 1.0 : 0.0;
     Rr = 0.0;
   }
-  double DM_G* out = A.d.band + (size_t)(ch.dof_off + r) * DM_NDIAG;
+  if (MODE != 1) {
+    double DM_G* out = A.d.band + (size_t)(ch.dof_off + r) * DM_NDIAG;
 #pragma unroll
-  for (int o = 0; o < DM_NDIAG; ++o) out[o] = acc[o];
+    for (int o = 0; o < DM_NDIAG; ++o) out[o] = acc[o];
+  }
+  if (MODE == 2) return 0.0;
   A.d.R[ch.dof_off + r] = Rr;
   return (rowfix || rowb) ? 0.0 : Rr * Rr;
 }
 
 // Band rows of chain node k (4 rows; 3 for the last node).  Returns the squared residual of
 // its free, non-border rows.
+template <int MODE>
 __device__ __forceinline__ double band_node(const DmStepArgs DM_C& A, double dt, int ci, int k) {
   const DmDev DM_C& D = A.d;
   const DmChain ch = D.chain[ci];
   const uint4 m = *(const uint4 DM_C*)(D.nmask + 4 * (size_t)(ch.node_tab + k));
   const bool own = m.z & 1u;
-  double s = band_row<0>(A, dt, ch, k, m.x, m.y, own);
-  s += band_row<1>(A, dt, ch, k, m.x, m.y, own);
-  s += band_row<2>(A, dt, ch, k, m.x, m.y, own);
-  if (k < ch.n_nodes - 1) s += band_row<3>(A, dt, ch, k, m.x, m.y, own);
+  double s = band_row<0, MODE>(A, dt, ch, k, m.x, m.y, own);
+  s += band_row<1, MODE>(A, dt, ch, k, m.x, m.y, own);
+  s += band_row<2, MODE>(A, dt, ch, k, m.x, m.y, own);
+  if (k < ch.n_nodes - 1) s += band_row<3, MODE>(A, dt, ch, k, m.x, m.y, own);
   return s;
 }
 
@@ -388,6 +419,7 @@ __device__ __forceinline__ double band_node(const DmStepArgs DM_C& A, double dt,
 
 // Stencil tasks: 64 consecutive stencils per wavefront and task kind (two orientations x
 // 4 / DM_STENCIL_TANGENTS tangent groups), so that a wavefront never mixes kinds.
+template <bool WG>
 __device__ __noinline__ void eval_stencils(ArgsP Ap, int sid, double t_end) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmSystem DM_C& S = A.d.sys[uniform(sid)];
@@ -397,13 +429,20 @@ __device__ __noinline__ void eval_stencils(ArgsP Ap, int sid, double t_end) {
     const int p = (i >> 6) % NTASK;      // orientation p / NSUB, tangent group p % NSUB
     if (st < S.n_st) {
       const int rev = p / NSUB, sub = p % NSUB;
-      if (NSUB == 1) eval_stencil<NT, 0>(A, S.st0 + st, rev, t_end);
-      else if (sub == 0) eval_stencil<NT, 0>(A, S.st0 + st, rev, t_end);
-      else if (NSUB == 2 || sub == 1) eval_stencil<NT, (NSUB > 1 ? 1 : 0)>(A, S.st0 + st, rev, t_end);
-      else if (sub == 2) eval_stencil<NT, (NSUB > 2 ? 2 : 0)>(A, S.st0 + st, rev, t_end);
-      else eval_stencil<NT, (NSUB > 3 ? 3 : 0)>(A, S.st0 + st, rev, t_end);
+      if (NSUB == 1) eval_stencil<NT, 0, WG>(A, S.st0 + st, rev, t_end);
+      else if (sub == 0) eval_stencil<NT, 0, WG>(A, S.st0 + st, rev, t_end);
+      else if (NSUB == 2 || sub == 1) eval_stencil<NT, (NSUB > 1 ? 1 : 0), WG>(A, S.st0 + st, rev, t_end);
+      else if (sub == 2) eval_stencil<NT, (NSUB > 2 ? 2 : 0), WG>(A, S.st0 + st, rev, t_end);
+      else eval_stencil<NT, (NSUB > 3 ? 3 : 0), WG>(A, S.st0 + st, rev, t_end);
     }
   }
+}
+
+// Stencil gradients only (the residual pass), one lane per stencil.
+__device__ __noinline__ void eval_stencil_grads(ArgsP Ap, int sid, double t_end) {
+  const DmStepArgs DM_C& A = *uniform(Ap);
+  const DmSystem DM_C& S = A.d.sys[uniform(sid)];
+  for (int i = threadIdx.x; i < S.n_st; i += blockDim.x) eval_stencil_grad(A, S.st0 + i, t_end);
 }
 
 // dt: the Newton step of the (sub)step being solved.
@@ -416,6 +455,7 @@ __device__ __noinline__ void eval_edges_nodes(ArgsP Ap, int sid, double dt) {
 
 // Band rows of every chain node of the system; returns this lane's share of the squared
 // residual of free, non-border rows.
+template <int MODE>
 __device__ __noinline__ double assemble_band(ArgsP Ap, int sid, double dt) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmDev DM_C& D = A.d;
@@ -424,7 +464,7 @@ __device__ __noinline__ double assemble_band(ArgsP Ap, int sid, double dt) {
   for (int i = threadIdx.x; i < S.chain_nodes; i += blockDim.x) {
     int c = S.chain0, k = i;
     while (k >= D.chain[c].n_nodes) { k -= D.chain[c].n_nodes; ++c; }
-    r2 += band_node(A, dt, c, k);
+    r2 += band_node<MODE>(A, dt, c, k);
   }
   return r2;
 }
@@ -516,15 +556,46 @@ __device__ __forceinline__ double bterm(const DmDev DM_C& D, const DmBItem& it) 
 // item and value load of both is in flight together), then one lane per entry adds its
 // segments in order.  Called by the whole workgroup.  Returns this lane's share of the
 // squared residual of free border rows.
+// MODE 0: every entry; 1: the right-hand side column only, one lane per row summing its
+// segments in the same order; 2: the matrix entries only (the right-hand side column is left
+// as the residual pass wrote it).
+template <int MODE>
 __device__ __noinline__ double assemble_border(ArgsP Ap, int sid, double DM_L* Bt, int ld, double DM_L* segsum) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmDev DM_C& D = A.d;
   const DmSystem DM_C& S = D.sys[uniform(sid)];
   const int nb = S.nb, W = nb + 1, ns = S.n_seg;
+  if (MODE == 1) {
+    double r2 = 0.0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+      const int e = b * W + nb;
+      double v = 0.0;
+      if (!D.bfix[S.bfix_off + b]) {
+        const int s1 = D.bent[S.bent_off + e + 1];
+        for (int q = D.bent[S.bent_off + e]; q < s1; ++q) {
+          const DmBItem DM_C* p = D.bitem + (size_t)q * DM_SEG;
+          DmBItem it[DM_SEG];
+          double x[DM_SEG];
+#pragma unroll
+          for (int j = 0; j < DM_SEG; ++j) it[j] = p[j];
+#pragma unroll
+          for (int j = 0; j < DM_SEG; ++j) x[j] = bterm(D, it[j]);
+          double sg = 0.0;
+#pragma unroll
+          for (int j = 0; j < DM_SEG; ++j) sg += x[j];
+          v += sg;
+        }
+        r2 += v * v;
+      }
+      Bt[b * ld + nb] = v;
+    }
+    return r2;
+  }
   if (!S.seg_long) {
     double r2 = 0.0;
     for (int e = threadIdx.x; e < nb * W; e += blockDim.x) {
       const int b = e / W, col = e - b * W;
+      if (MODE == 2 && col == nb) continue;
       double v = 0.0;
       if (D.bfix[S.bfix_off + b]) {
         v = col == b ? 1.0 : 0.0;
@@ -567,6 +638,7 @@ __device__ __noinline__ double assemble_border(ArgsP Ap, int sid, double DM_L* B
   double r2 = 0.0;
   for (int e = threadIdx.x; e < nb * W; e += blockDim.x) {
     const int b = e / W, col = e - b * W;
+    if (MODE == 2 && col == nb) continue;
     double v = 0.0;
     if (D.bfix[S.bfix_off + b]) {
       v = col == b ? 1.0 : 0.0;
@@ -1535,20 +1607,32 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
         int it = 0, halvings = 0;
         double alpha = 1.0, res_prev = 0.0;
         while (true) {
-          eval_stencils(Ap, sid, t_end);
+          // residual pass: stencil gradients, edge and node terms, the residual of every row
+          eval_stencil_grads(Ap, sid, t_end);
           eval_edges_nodes(Ap, sid, hn);
           __syncthreads();
           DM_TP(0);
-          double r2 = assemble_band(Ap, sid, hn);
+          double r2 = assemble_band<1>(Ap, sid, hn);
           __syncthreads();
-          DM_TP(1);
-          r2 += assemble_border(Ap, sid, Bt, ld, red + 42);
+          r2 += assemble_border<1>(Ap, sid, Bt, ld, red + 42);
           res = sqrt(block_sum(r2, red));
+          DM_TP(1);
+          if (res <= A.tol) { conv = true; break; }   // (a rise under line search is above tol)
+          const bool rise = A.line_search && it > 0 && res >= res_prev;
+          const bool stall = it > 0 && res > 0.5 * res_prev && A.floor_factor > 0.0;
+          const bool give_up = it >= (A.warm && attempt == 0 ? A.warm_max_iter : A.max_iter) || !isfinite(res);
+          if (give_up && !rise && !stall) break;
+          // matrix pass, only when a decision or a solve follows: stencil Hessians, the band and
+          // the dense border's matrix part
+          eval_stencils<false>(Ap, sid, t_end);
+          __syncthreads();
+          assemble_band<2>(Ap, sid, hn);
+          __syncthreads();
+          assemble_border<2>(Ap, sid, Bt, ld, red + 42);
+          __syncthreads();
           DM_TP(2);
           // the rounding floor is needed only where a decision reads it: a residual that rose
           // under line search, or one that stopped halving above the tolerance
-          const bool rise = A.line_search && it > 0 && res >= res_prev;
-          const bool stall = it > 0 && res > A.tol && res > 0.5 * res_prev && A.floor_factor > 0.0;
           const double flo = (rise || stall) ? residual_floor(Ap, sid, Bt, ld, red) : 0.0;
           // line search: a step whose residual did not decrease is halved (at most 10 times),
           // unless its residual is within the iterate's rounding floor (noise, not a bad step)
@@ -1559,14 +1643,13 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
             __syncthreads();
             continue;
           }
-          if (res <= A.tol) { conv = true; break; }
           if (stall && res <= flo) {
             conv = true;    // the step stopped improving at or below its FP64 rounding floor
             ++floor_hits;
             if (tid == 0 && res > red[37]) { red[37] = res; red[38] = flo; }   // kept in LDS
             break;
           }
-          if (it >= (A.warm && attempt == 0 ? A.warm_max_iter : A.max_iter) || !isfinite(res)) break;
+          if (give_up) break;
           res_prev = res;
           alpha = 1.0;
           halvings = 0;
@@ -1687,12 +1770,12 @@ __global__ void __launch_bounds__(512) dm_adjoint_kernel(DmAdjArgs) {
     adj_load_states(Pp, sid, i);
     __syncthreads();
     adj_commit_vjp(Pp, sid, P.a.step0 + i);
-    eval_stencils(Ap, sid, 0.0);
+    eval_stencils<true>(Ap, sid, 0.0);
     eval_edges_nodes(Ap, sid, A.dt);
     __syncthreads();
-    assemble_band(Ap, sid, A.dt);
+    assemble_band<0>(Ap, sid, A.dt);
     __syncthreads();
-    assemble_border(Ap, sid, Bt, ld, red + 42);
+    assemble_border<0>(Ap, sid, Bt, ld, red + 42);
     __syncthreads();
     adj_rhs(Pp, sid, Bt, ld);
     __syncthreads();
