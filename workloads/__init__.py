@@ -146,6 +146,40 @@ def adjoint_rods(n_rods: int = 256, n_nodes: int = 100, seed: int = 2, steps: in
     return _desc(rods, dt=1e-3, steps=steps), target
 
 
+def two_limb_manipulator(n_robots: int = 1, limb_nodes: int = 12, limb_length: float = 0.076,
+                         radius: float = 0.1, spacing: float = 1.0) -> dict:
+    """The real2sim dual soft limb manipulator (Real2Sim section): per robot two limbs of
+    silicone (rho = 1240, E = 1.793 MPa, Poisson 0.5, the printed rod radius of 10 cm by
+    default), each `limb_nodes` nodes over `limb_length` (76 mm, the limbs' length), joined
+    end to start by an elastic joint and hanging from a base clamped at its first two nodes
+    and first twist, along -z under gravity -9.8 z.  Rods 2r and 2r + 1 are robot r's limbs;
+    robots are offset along x.  The limbs' natural curvature is set by the caller.  dt = 1e4 s,
+    one step: a quasi-static configuration is one implicit step so long that inertia is
+    negligible."""
+    rods, joints = [], []
+    for k in range(n_robots):
+        o = np.array([spacing * k, 0.0, 0.0])
+        a = _rod(straight_nodes(limb_nodes, limb_length, o, (0.0, 0.0, -1.0)), radius, 1.793e6, 0.5, 1240.0,
+                 kbar=np.zeros((limb_nodes - 2, 2)))
+        b = _rod(straight_nodes(limb_nodes, limb_length, o + np.array([0.0, 0.0, -limb_length]), (0.0, 0.0, -1.0)),
+                 radius, 1.793e6, 0.5, 1240.0, kbar=np.zeros((limb_nodes - 2, 2)), fixed_nodes=(), fixed_edges=())
+        rods += [a, b]
+        joints.append((2 * k, limb_nodes - 1, 2 * k + 1, 0))
+    return _desc(rods, dt=1e4, steps=1, gravity=(0.0, 0.0, -9.8), joints=joints)
+
+
+def limb_curvature_targets(n_configs: int = 8, seed: int = 5, n_robots: int = 1, scale: float = 1.0) -> np.ndarray:
+    """Natural curvatures (1/m, first material direction) of a sequence of quasi-static
+    configurations of two-limb robots, (n_configs, n_robots, 2): a slow seeded drift per robot
+    and limb, as a hardware actuation sweep would give.  The target curvatures of the fit are
+    the curvatures the simulated robot shows at these natural curvatures."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    start = rng.uniform(-2.0, 2.0, size=(n_robots, 2))
+    drift = rng.uniform(-1.0, 1.0, size=(n_robots, 2))
+    s = np.arange(n_configs)[:, None, None]
+    return scale * (start[None] + drift[None] * s + 0.3 * np.sin(0.9 * s + rng.uniform(0, 6.3, size=(n_robots, 2))[None]))
+
+
 # ---------------------------------------------------------------------------
 # Paper-shape workloads (validation section parameters)
 # ---------------------------------------------------------------------------
