@@ -486,6 +486,44 @@ def config_table(dm, log):
         print(json.dumps(r), flush=True)
 
 
+def real2sim_section(dm, n_robots=1024, n_configs=8, tol=1e-3, max_iter=200):
+    """Alg. 1 (Real2Sim section) on a batch of two-limb manipulators with the paper's
+    parameters: the target limb curvatures of each configuration are those the simulated
+    robots show at seeded natural curvatures (a forward solve on the GPU), then every robot's
+    natural curvatures are fitted to them from zero, configuration after configuration."""
+    import torch
+
+    import workloads as W
+    d = W.two_limb_manipulator(n_robots=n_robots)
+    kstar = W.limb_curvature_targets(n_configs=n_configs, n_robots=n_robots)
+    sizes = [r["x0"].shape[0] - 2 for r in d["rods"]]
+
+    def kbar_all(kv):
+        return np.concatenate([np.stack([np.full(n, k), np.zeros(n)], 1).reshape(-1) for n, k in zip(sizes, kv)])
+    stream = torch.cuda.current_stream().cuda_stream
+    sim = dm.sim_from_description(d, line_search=True, stream=stream)
+    targets = []
+    for c in range(n_configs):
+        sim.set_natural_curvature_all(kbar_all(kstar[c].reshape(-1)))
+        sim.step(d["dt"], d["steps"])
+        targets.append(sim.limb_curvatures())
+    sim.close()
+    targets = np.array(targets)
+    sim = dm.sim_from_description(d, line_search=True, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    traj, steps, losses = sim.fit_limb_curvatures(d["dt"], d["steps"], targets, alpha0=0.1, tol=tol, max_iter=max_iter)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sim.close()
+    return {"workload": f"{n_robots} two-limb manipulators (limbs of 76 mm, 12 nodes, radius 10 cm, silicone), "
+                        f"{n_configs} target configurations from seeded natural curvatures",
+            "tol": tol, "alpha0": 0.1, "wall_s": wall, "gradient_steps": int(steps.sum()),
+            "configurations_per_s": n_robots * n_configs / wall,
+            "converged_fraction": float((losses < tol).mean()),
+            "max_kbar_error": float(np.abs(traj - kstar.reshape(n_configs, -1)).max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -594,6 +632,7 @@ def main():
         out["stars"] = star_section(dm, max(args.steps // 5, 5))
         out["midpoint"] = midpoint_section(dm, args.steps)
         out["adjoint"] = adjoint_section(dm)
+        out["real2sim"] = real2sim_section(dm)
     if not args.no_per_rod:
         out["per_rod_plain_value"] = per_rod_baseline(dm, desc, min(args.steps, 20))
     if not args.no_cpu_baseline:

@@ -252,6 +252,35 @@ dm_status dm_fit_natural_curvature(dm_sim* sim, double dt, int nsteps, int ckpt_
                                    int target_on_device, double alpha0, double tol, int max_iter, double* kbar,
                                    int kbar_on_device, double* losses, int* n_eval);
 
+/* ---- Real2Sim: limb curvatures of quasi-static configurations (Real2Sim section) ----------
+ * Limb curvature of a rod: the mean over its interior stencils of the first integrated
+ * curvature of Eq. 5 divided by the rest Voronoi length (1/m), at the current state.
+ * dm_limb_curvatures: kappa (host [n_rods]) of every rod; 0 for rods of fewer than 3 nodes. */
+dm_status dm_limb_curvatures(dm_sim* sim, double* kappa);
+/* Gradient of sum_r w[r] kappa_r with respect to each rod's uniform natural curvature (1/m,
+ * first material direction, on all its interior stencils) at the current state taken as an
+ * equilibrium: the implicit-function adjoint of one more backward-Euler step of dt from it
+ * (inertia negligible for a long dt).  w and grad: host [n_rods].  DM_ERR_UNSUPPORTED with floor
+ * contact, actuated rods or the midpoint integrator; DM_ERR_SINGULAR for a singular matrix. */
+dm_status dm_limb_curvature_gradient(dm_sim* sim, double dt, const double* w, double* grad);
+/* Alg. 1 of the Real2Sim section for every system at once, each system's rods being its limbs:
+ * for each of n_configs target configurations (targets: host [n_configs][n_rods], limb
+ * curvatures in 1/m), alpha = alpha0 and lambda_prev = infinity per system; repeat: set each
+ * rod's uniform natural curvature kbar_r, reach the quasi-static configuration by n_settle
+ * backward-Euler steps of dt from the current state, lambda = sum over the system's rods of
+ * |kappa*_r - kappa_r| (Eq. 19); stop below tol or after max_iter gradient steps; halve alpha if
+ * lambda rose; kbar <- kbar - alpha d lambda/d kbar (Eq. 21) with the gradient of
+ * dm_limb_curvature_gradient in place of the forward differences of Eq. 20.  kbar starts at 0
+ * and carries over between configurations; a system that has stopped is not stepped until the
+ * next configuration.  kbar_traj: host [n_configs][n_rods], the fitted kbar after each
+ * configuration; steps (host int [n_configs][n_systems]) and losses (host
+ * [n_configs][n_systems], the last lambda) may be NULL.  The sim ends in the last configuration
+ * with its natural curvature set to the fit.  Same restrictions as the gradient; a failing
+ * quasi-static solve returns its status. */
+dm_status dm_fit_limb_curvatures(dm_sim* sim, double dt, int n_settle, int n_configs, const double* targets,
+                                 double alpha0, double tol, int max_iter, double* kbar_traj, int* steps,
+                                 double* losses);
+
 /* ---- Learned warm start of the Newton solve ----------------------------------------------
  * Not part of the paper's method: a small network predicts each node's displacement over a
  * step and the prediction is Newton's initial guess (Eq. 16 is still iterated to newton_tol,

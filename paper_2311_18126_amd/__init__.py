@@ -80,6 +80,10 @@ _SIGS = {
     "dm_adjoint": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int]),
     "dm_fit_natural_curvature": (c_int, [c_void_p, c_double, c_int, c_int, c_void_p, c_int, c_double, c_double,
                                          c_int, c_void_p, c_int, _DP, POINTER(c_int)]),
+    "dm_limb_curvatures": (c_int, [c_void_p, _DP]),
+    "dm_limb_curvature_gradient": (c_int, [c_void_p, c_double, _DP, _DP]),
+    "dm_fit_limb_curvatures": (c_int, [c_void_p, c_double, c_int, c_int, _DP, c_double, c_double, c_int, _DP,
+                                       _IP, _DP]),
     "dm_mlp_num_params": (c_size_t, []),
     "dm_mlp_create": (c_int, [c_int, c_void_p, c_int, POINTER(c_void_p)]),
     "dm_mlp_set_params": (c_int, [c_void_p, c_void_p, c_int]),
@@ -466,6 +470,35 @@ class Sim:
         else:
             k = _sized(kbar, self.kbar_size, "kbar")
             _check(lib().dm_set_natural_curvature_all(self._h, k.ctypes.data, 0), "dm_set_natural_curvature_all")
+
+    def limb_curvatures(self):
+        """Every rod's limb curvature (1/m): see dm_limb_curvatures."""
+        k = np.zeros(self.num_rods)
+        _check(lib().dm_limb_curvatures(self._h, _dp(k)), "dm_limb_curvatures")
+        return k
+
+    def limb_curvature_gradient(self, dt, weights):
+        """d(sum w kappa)/d kbar per rod at the current state: see dm_limb_curvature_gradient."""
+        w = _sized(weights, self.num_rods, "weights")
+        g = np.zeros(self.num_rods)
+        _check(lib().dm_limb_curvature_gradient(self._h, float(dt), _dp(w), _dp(g)), "dm_limb_curvature_gradient")
+        return g
+
+    def fit_limb_curvatures(self, dt, n_settle, targets, alpha0=0.1, tol=1e-3, max_iter=200):
+        """Alg. 1 over target limb curvatures (n_configs, n_rods); returns the fitted natural
+        curvature after each configuration (n_configs, n_rods), the gradient steps and the last
+        loss of each configuration and system (n_configs, n_systems)."""
+        t = _f64(targets)
+        if t.ndim != 2 or t.shape[1] != self.num_rods:
+            raise ValueError(f"targets must have shape (n_configs, {self.num_rods})")
+        nc, ns = t.shape[0], self.num_systems
+        traj = np.zeros((nc, self.num_rods))
+        steps = np.zeros((nc, ns), dtype=np.int32)
+        losses = np.zeros((nc, ns))
+        _check(lib().dm_fit_limb_curvatures(self._h, float(dt), int(n_settle), nc, _dp(t), float(alpha0), float(tol),
+                                            int(max_iter), _dp(traj), steps.ctypes.data_as(_IP), _dp(losses)),
+               "dm_fit_limb_curvatures")
+        return traj, steps, losses
 
     def rollout(self, dt, nsteps, ckpt_every=20, out=None):
         """nsteps steps with a checkpoint every ckpt_every steps, for adjoint(); returns the tip

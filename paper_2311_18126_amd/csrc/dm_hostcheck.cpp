@@ -7,7 +7,9 @@
 //  * the reversed orientation gives the e-edge columns through the signed permutation the
 //    kernels use (e_f <-> -e_e, theta_f <-> -theta_e, second curvature component negated);
 //  * the stretch gradient and Hessian match central differences of Eq. 3's energy;
-//  * parallel transport keeps a director unit and perpendicular to the new tangent.
+//  * parallel transport keeps a director unit and perpendicular to the new tangent;
+//  * the closed-form gradient of the first curvature matches central differences of Eq. 5's
+//    value (with the frames carried from the step start).
 // Prints one summary line and exits non-zero on a failed check.
 #include <cmath>
 #include <cstdio>
@@ -67,6 +69,7 @@ double rel(double a, double b, double scale) { return std::fabs(a - b) / scale; 
 int main() {
   int fail = 0;
   double worst_g = 0.0, worst_fd = 0.0, worst_one = 0.0, worst_rev = 0.0, worst_st = 0.0, worst_tr = 0.0;
+  double worst_k = 0.0;
   for (int trial = 0; trial < 400; ++trial) {
     const Stencil s = random_stencil();
     double g8[8], H[8][4];
@@ -130,11 +133,35 @@ int main() {
     // transport of the step-start director onto the current tangent
     const v3 t = unitv(s.ef), d1 = transport_perp(s.tnf, t, s.d1nf);
     worst_tr = std::fmax(worst_tr, std::fmax(std::fabs(dot(d1, d1) - 1.0), std::fabs(dot(d1, t))));
+    // first curvature and its closed-form gradient
+    auto kappa1 = [&](v3 ef, v3 ee, double thf, double the) {
+      const v3 tf = unitv(ef), te = unitv(ee);
+      double k1, k2, b;
+      stencil_strains(tf, transport_perp(s.tnf, tf, s.d1nf), thf, te, transport_perp(s.tne, te, s.d1ne), the, 0.0, true,
+                      &k1, &k2, &b);
+      return k1;
+    };
+    double gk[8];
+    stencil_kappa1_grad_g<double>(tov(s.ef), tov(s.ee), s.thf, s.the, tov(s.tnf), tov(s.d1nf), tov(s.tne), tov(s.d1ne),
+                                  gk);
+    double ks = 0.0;
+    for (int a = 0; a < 8; ++a) ks = std::fmax(ks, std::fabs(gk[a]));
+    for (int a = 0; a < 8; ++a) {
+      const int e = a < 3 ? 0 : (a < 6 ? 1 : (a == 6 ? 2 : 3));
+      const int c = a < 6 ? a % 3 : 0;
+      const double hh = e < 2 ? 1e-7 * 0.01 : 1e-6;
+      v3 dv = mk3(c == 0 ? hh : 0.0, c == 1 ? hh : 0.0, c == 2 ? hh : 0.0);
+      const double kp = kappa1(e == 0 ? s.ef + dv : s.ef, e == 1 ? s.ee + dv : s.ee, s.thf + (e == 2 ? hh : 0.0),
+                               s.the + (e == 3 ? hh : 0.0));
+      const double km = kappa1(e == 0 ? s.ef - dv : s.ef, e == 1 ? s.ee - dv : s.ee, s.thf - (e == 2 ? hh : 0.0),
+                               s.the - (e == 3 ? hh : 0.0));
+      worst_k = std::fmax(worst_k, rel((kp - km) / (2 * hh), gk[a], ks));
+    }
   }
   fail |= !(worst_g < 1e-12) | !(worst_fd < 1e-6) | !(worst_one < 1e-12) | !(worst_rev < 1e-6) |
-          !(worst_st < 1e-5) | !(worst_tr < 1e-14);
+          !(worst_st < 1e-5) | !(worst_tr < 1e-14) | !(worst_k < 1e-6);
   std::printf("dm_hostcheck: gradient %.2e, Hessian vs differences %.2e, one-tangent %.2e, reversed %.2e, "
-              "stretch %.2e, transport %.2e: %s\n",
-              worst_g, worst_fd, worst_one, worst_rev, worst_st, worst_tr, fail ? "FAIL" : "ok");
+              "stretch %.2e, transport %.2e, curvature gradient %.2e: %s\n",
+              worst_g, worst_fd, worst_one, worst_rev, worst_st, worst_tr, worst_k, fail ? "FAIL" : "ok");
   return fail ? 1 : 0;
 }

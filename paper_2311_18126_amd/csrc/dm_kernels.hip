@@ -305,7 +305,8 @@ __device__ __forceinline__ double stencil_row(const DmDev DM_C& D, int s, bool o
 // column as rel = column - 4k.  Returns the residual entry.  Every term is loaded (from a valid
 // index) and kept or dropped by selection: the terms present depend only on where node k sits
 // in its chain and on whether the chain owns the node.
-template <int COMP, class Emit>
+// NE_RES: the residual includes the node and edge terms (off: stencil gradients only).
+template <int COMP, bool NE_RES, class Emit>
 __device__ __forceinline__ double row_contrib(const DmStepArgs DM_C& A, double dt, const DmChain& ch, int k,
                                               bool own, Emit& emit) {
   const DmDev DM_C& D = A.d;
@@ -320,7 +321,7 @@ __device__ __forceinline__ double row_contrib(const DmStepArgs DM_C& A, double d
     const int et = D.chain_edge[ch.edge_tab + (tail ? k : N - 2)];
     const int eh = D.chain_edge[ch.edge_tab + (head ? k - 1 : 0)];
     const double rn = D.nd[COMP * NN + node];
-    Rr += own ? rn : 0.0;
+    if (NE_RES) Rr += own ? rn : 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const double v = D.nd[(3 + 3 * COMP + c) * NN + node];
@@ -335,7 +336,7 @@ __device__ __forceinline__ double row_contrib(const DmStepArgs DM_C& A, double d
       emit(-4 + c, -kh);
     }
     const double ft = D.ed[COMP * NE + et], fh = D.ed[COMP * NE + eh];
-    Rr += (head ? fh : 0.0) - (tail ? ft : 0.0);
+    if (NE_RES) Rr += (head ? fh : 0.0) - (tail ? ft : 0.0);
     // stencils centred on nodes k-1, k, k+1 (node k is their next, centre, previous node)
     Rr += stencil_row<8 + COMP>(D, ch.st_off + k - 2, sok(k - 1), -8, emit);
     Rr += stencil_row<4 + COMP>(D, ch.st_off + k - 1, sok(k), -4, emit);
@@ -344,7 +345,7 @@ __device__ __forceinline__ double row_contrib(const DmStepArgs DM_C& A, double d
     const int e = D.chain_edge[ch.edge_tab + k];
     const double I = D.Ith[e] / (dt * dt);
     emit(3, I);
-    Rr += I * (D.th[e] - D.th0[e] - dt * D.om[e]) - D.moment[e];
+    if (NE_RES) Rr += I * (D.th[e] - D.th0[e] - dt * D.om[e]) - D.moment[e];
     Rr += stencil_row<7>(D, ch.st_off + k - 1, sok(k), -4, emit);
     Rr += stencil_row<3>(D, ch.st_off + k, sok(k + 1), 0, emit);
   }
@@ -355,7 +356,8 @@ __device__ __forceinline__ double row_contrib(const DmStepArgs DM_C& A, double d
 // border columns of a border row (those couplings live in the dense border), are zeroed
 // afterwards.  fixmask / bmask: bit i describes chain DOF 4k - 12 + i.
 // MODE 0: matrix row and residual entry; 1: the residual entry only (the element terms not
-// read are never loaded); 2: the matrix row only.
+// read are never loaded); 2: the matrix row only; 3: the residual entry from the stencil
+// gradients alone (a right-hand side built from per-stencil vectors in st_g).
 template <int COMP, int MODE>
 __device__ __forceinline__ double band_row(const DmStepArgs DM_C& A, double dt, const DmChain& ch, int k,
                                            unsigned fixmask, unsigned bmask, bool own) {
@@ -366,8 +368,8 @@ __device__ __forceinline__ double band_row(const DmStepArgs DM_C& A, double dt, 
 #pragma unroll
   for (int o = 0; o < DM_NDIAG; ++o) acc[o] = 0.0;
   auto emit = [&](int rel, double v) { acc[rel - COMP + 10] += v; };
-  double Rr = row_contrib<COMP>(A, dt, ch, k, own, emit);
-  if (MODE != 1 && rowb && !rowfix) {
+  double Rr = row_contrib<COMP, MODE != 3>(A, dt, ch, k, own, emit);
+  if (MODE != 1 && MODE != 3 && rowb && !rowfix) {
     // the border-block part of a border row goes to the dense border (assemble_border)
     double DM_G* bp = A.d.bpr + (size_t)(ch.bmap_off + r - ch.b_lo) * DM_NDIAG;
 #pragma unroll
@@ -387,7 +389,7 @@ __device__ __forceinline__ double band_row(const DmStepArgs DM_C& A, double dt, 
     for (int o = 0; o < DM_NDIAG; ++o) acc[o] = (o == 10) ? 1.0 : 0.0;
     Rr = 0.0;
   }
-  if (MODE != 1) {
+  if (MODE != 1 && MODE != 3) {
     double DM_G* out = A.d.band + (size_t)(ch.dof_off + r) * DM_NDIAG;
 #pragma unroll
     for (int o = 0; o < DM_NDIAG; ++o) out[o] = acc[o];
@@ -1548,7 +1550,185 @@ __device__ __noinline__ void adj_update(AdjP Pp, int sid) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// limb curvature of an equilibrium and its gradient with respect to natural curvature
+//
+// At a settled state (the committed state, its own step start) the residual of one more step
+// of dt, R(q; kbar), vanishes; d/dkbar of sum_s w_s kappa1_s (Eq. 5's first curvature) is then
+// -mu^T dR/dkbar with J mu = d(sum w kappa1)/dq (J symmetric without friction), and
+// dR/dkbar_s (the stencil's natural curvature in 1/m, first component) = -kbend_s Vbar_s
+// d kappa1_s / dq, so the derivative is kbend_s Vbar_s mu . d kappa1_s / dq per stencil.
+// ---------------------------------------------------------------------------
+using CurvP = const DmCurvArgs DM_C*;
+
+__device__ __forceinline__ CurvP uniform(CurvP p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (CurvP)(((unsigned long long)hi << 32) | lo);
+}
+
+// d kappa1 / d(e_f, e_e, theta_f, theta_e) of stencil s at the committed state (frames carried
+// from the step start, which is the committed state itself).
+__device__ __forceinline__ void kappa1_grad(const DmDev DM_C& D, int s, double* g8) {
+  const int NS = D.n_st_tot, NE = D.n_edges_tot, NN = D.n_nodes_tot;
+  const int np = D.sn[s], nc = D.sn[NS + s], nn = D.sn[2 * NS + s];
+  const int ef = D.se[s], ee = D.se[NS + s];
+  const int sg = D.ssign[s];
+  const double sf = (sg & 1) ? -1.0 : 1.0, se = (sg & 2) ? -1.0 : 1.0;
+  const v3 xc = ld3(D.x, NN, nc);
+  stencil_kappa1_grad_g<double>(tov(xc - ld3(D.x, NN, np)), tov(ld3(D.x, NN, nn) - xc), sf * D.th[ef],
+                                se * D.th[ee], tov(sf * ld3(D.tref, NE, ef)), tov(ld3(D.d1ref, NE, ef)),
+                                tov(se * ld3(D.tref, NE, ee)), tov(ld3(D.d1ref, NE, ee)), g8);
+}
+
+// Right-hand side vectors: st_g = w_s d kappa1_s / dv (zero where w_s is zero, joint stencils
+// included); the unweighted gradient is kept in st_H's first 8 rows for curv_params.
+__device__ __noinline__ void curv_rhs(CurvP Cp, int sid) {
+  const DmCurvArgs DM_C& C = *uniform(Cp);
+  const DmDev DM_C& D = C.s.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
+  const int NS = D.n_st_tot;
+  for (int i = threadIdx.x; i < S.n_st; i += blockDim.x) {
+    const int s = S.st0 + i;
+    const double w = C.c.wst[s];
+    double g8[8];
+    kappa1_grad(D, s, g8);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      D.st_g[a * NS + s] = w * g8[a];
+      D.st_H[a * NS + s] = g8[a];
+    }
+  }
+}
+
+// mu of every node position and edge twist from the solve (band rows or the border).
+__device__ __noinline__ void curv_store_mu(CurvP Cp, int sid, const double DM_L* xB) {
+  const DmCurvArgs DM_C& C = *uniform(Cp);
+  const DmDev DM_C& D = C.s.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
+  const int NN = D.n_nodes_tot;
+  for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x) {
+    const int n = S.node0 + i;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int h = D.node_home[c * NN + n];
+      C.c.mu[c * NN + n] = h >= 0 ? D.delta[h] : xB[-1 - h];
+    }
+  }
+  for (int i = threadIdx.x; i < S.n_edges; i += blockDim.x) {
+    const int e = S.edge0 + i;
+    const int h = D.edge_home[e];
+    C.c.mu[3 * NN + e] = h >= 0 ? D.delta[h] : xB[-1 - h];
+  }
+}
+
+// Per stencil: kbend Vbar (mu_loc . d kappa1 / dq_loc), mu_loc mapped to the stencil variables
+// (x_c - x_p, x_n - x_c, and the signed twists).
+__device__ __noinline__ void curv_params(CurvP Cp, int sid) {
+  const DmCurvArgs DM_C& C = *uniform(Cp);
+  const DmDev DM_C& D = C.s.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
+  const int NS = D.n_st_tot, NN = D.n_nodes_tot;
+  for (int i = threadIdx.x; i < S.n_st; i += blockDim.x) {
+    const int s = S.st0 + i;
+    const int np = D.sn[s], nc = D.sn[NS + s], nn = D.sn[2 * NS + s];
+    const int ef = D.se[s], ee = D.se[NS + s];
+    const int sg = D.ssign[s];
+    const double sf = (sg & 1) ? -1.0 : 1.0, se = (sg & 2) ? -1.0 : 1.0;
+    const v3 lp = ld3(C.c.mu, NN, np), lc = ld3(C.c.mu, NN, nc), ln = ld3(C.c.mu, NN, nn);
+    const v3 l0 = lc - lp, l1 = ln - lc;
+    const double l8[8] = {l0.x, l0.y, l0.z, l1.x, l1.y, l1.z, sf * C.c.mu[3 * NN + ef], se * C.c.mu[3 * NN + ee]};
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < 8; ++a) acc = fma(l8[a], D.st_H[a * NS + s], acc);
+    C.c.pst[s] = D.kbend[s] * D.Vbar[s] * acc;
+  }
+}
+
+// kappa1 / Vbar of stencil s at the committed state, the frames being the step-start ones.
+__device__ __forceinline__ double stencil_curvature(const DmDev DM_C& D, int s) {
+  const int NS = D.n_st_tot, NE = D.n_edges_tot;
+  const int ef = D.se[s], ee = D.se[NS + s];
+  const int sg = D.ssign[s];
+  const double sf = (sg & 1) ? -1.0 : 1.0, se = (sg & 2) ? -1.0 : 1.0;
+  double k1, k2, b;
+  stencil_strains(sf * ld3(D.tref, NE, ef), ld3(D.d1ref, NE, ef), sf * D.th[ef], se * ld3(D.tref, NE, ee),
+                  ld3(D.d1ref, NE, ee), se * D.th[ee], D.bref[s], true, &k1, &k2, &b);
+  return k1 / D.Vbar[s];
+}
+
 }  // namespace
+
+// First curvature over the rest Voronoi length (1/m) of every stencil at the committed state.
+__global__ void dm_stencil_curvature_kernel(DmStepArgs, double* out) {
+  const ArgsP Ap = (ArgsP)__builtin_amdgcn_kernarg_segment_ptr();   // the by-value argument
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s < Ap->d.n_st_tot) out[s] = stencil_curvature(Ap->d, s);
+}
+
+extern "C" hipError_t dm_launch_stencil_curvature(const DmStepArgs* args, double* out, hipStream_t stream) {
+  const int n = args->d.n_st_tot;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(dm_stencil_curvature_kernel, dim3((n + 255) / 256), dim3(256), 0, stream, *args, out);
+  return hipGetLastError();
+}
+
+// Gradient of sum_s w_s kappa1_s of an equilibrium with respect to the stencils' natural
+// curvature; one workgroup per system (systems marked in skip are left alone).
+__global__ void __launch_bounds__(512) dm_curvature_adjoint_kernel(DmCurvArgs) {
+  extern __shared__ double lds_raw[];
+  double DM_L* lds = (double DM_L*)lds_raw;
+  const CurvP Cp = (CurvP)__builtin_amdgcn_kernarg_segment_ptr();
+  const ArgsP Ap = (ArgsP)__builtin_amdgcn_kernarg_segment_ptr();   // the step arguments lead
+  const DmCurvArgs DM_C& C = *Cp;
+  const DmStepArgs DM_C& A = C.s;
+  const DmDev DM_C& D = A.d;
+  const int sid = D.order[blockIdx.x];
+  if (C.c.skip && C.c.skip[sid]) return;           // the whole workgroup, before any barrier
+  const DmSystem DM_C& S = D.sys[sid];
+  const int ld = A.max_nb + 1;
+  double DM_L* Bt = lds;
+  double DM_L* deltas = Bt + A.max_nb * ld;
+  double DM_L* xB = deltas + A.max_arms * 110;
+  double DM_L* red = xB + A.max_nb;
+  int DM_L* flags = (int DM_L*)(red + 40);
+  const int tid = threadIdx.x, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  if (tid == 0) flags[0] = 0;
+  __syncthreads();
+  const double t_end = D.time[sid] + A.dt;
+  eval_stencils<true>(Ap, sid, t_end);
+  eval_edges_nodes(Ap, sid, A.dt);
+  __syncthreads();
+  assemble_band<2>(Ap, sid, A.dt);
+  __syncthreads();
+  assemble_border<2>(Ap, sid, Bt, ld, red + 42);
+  __syncthreads();
+  curv_rhs(Cp, sid);
+  __syncthreads();
+  assemble_band<3>(Ap, sid, A.dt);
+  __syncthreads();
+  assemble_border<1>(Ap, sid, Bt, ld, red + 42);
+  __syncthreads();
+  sweep_all(Ap, S, wave, nwaves, deltas, flags);
+  __syncthreads();
+  border_solve(Ap, sid, Bt, ld, deltas, xB, red + 34, flags);
+  backsub_all(Ap, S, wave, nwaves, xB);
+  __syncthreads();
+  const bool bad = flags[0] != 0;
+  if (!bad) {
+    curv_store_mu(Cp, sid, xB);
+    __syncthreads();
+    curv_params(Cp, sid);
+  }
+  if (tid == 0) D.s_status[sid] = bad ? DM_STATUS_SINGULAR : DM_STATUS_OK;
+}
+
+extern "C" hipError_t dm_launch_curvature_adjoint(const DmCurvArgs* args, int block, size_t lds_bytes,
+                                                  hipStream_t stream) {
+  hipLaunchKernelGGL(dm_curvature_adjoint_kernel, dim3(args->s.n_systems), dim3(block), lds_bytes, stream, *args);
+  return hipGetLastError();
+}
 
 __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
   extern __shared__ double lds_raw[];
@@ -1576,7 +1756,7 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
   double res = 0.0;
   double t = D.time[sid];
   // accumulating launches (one step each) leave a system alone once it has failed
-  const int nsteps = (A.accum && D.s_status[sid] != DM_STATUS_OK) ? 0 : A.nsteps;
+  const int nsteps = ((A.accum && D.s_status[sid] != DM_STATUS_OK) || (A.skip && A.skip[sid])) ? 0 : A.nsteps;
   __syncthreads();
   DM_T0();
   for (int step = 0; step < nsteps; ++step) {

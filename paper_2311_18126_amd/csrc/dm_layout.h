@@ -203,6 +203,7 @@ struct DmStepArgs {
                    // backward Euler to the midpoint) and the commit extrapolates to the step end
   int max_halvings;  // adaptive time stepping: a failed (sub)step is redone as two halves, at
                      // most this many levels deep (0: off)
+  const int DM_C* skip;   // [n_systems] nonzero: the system takes no step in this launch (or null)
   int n_systems;
   int max_nb, max_arms;
   int max_seg;     // largest number of border term segments of a system (LDS partial sums)
@@ -229,6 +230,19 @@ struct DmAdjDev {
 struct DmAdjArgs {
   DmStepArgs s;                 // first member: the step arguments at offset 0
   DmAdjDev a;
+};
+
+// Gradient of a weighted sum of stencil curvatures of an equilibrium (dm_curvature_adjoint_kernel).
+struct DmCurvAdj {
+  const double DM_C* wst;   // [n_st] weight of each stencil's kappa_1 (zero: not in the sum)
+  double DM_G* mu;          // [3 NN + NE] solution of J mu = d(sum w kappa1)/dq
+  double DM_G* pst;         // [n_st] derivative with respect to the stencil's natural curvature (1/m)
+  const int DM_C* skip;     // [n_systems] nonzero: the system is left alone (or null)
+};
+
+struct DmCurvArgs {
+  DmStepArgs s;             // first member: the step arguments at offset 0
+  DmCurvAdj c;
 };
 
 struct dm_mlp;

@@ -342,3 +342,27 @@ DM_HD void stencil_grad_g(const Vec<S>& ef, const Vec<S>& ee, const S& thf, cons
   g8[3] = ge.x; g8[4] = ge.y; g8[5] = ge.z;
   g8[6] = af - ct; g8[7] = ae + ct;
 }
+
+// Gradient of the first integrated curvature kappa_1 of a stencil (Eq. 5) with respect to
+// (e_f, e_e, theta_f, theta_e), frames carried by time-parallel transport from (tn, d1n): the
+// bending part of stencil_grad_g's closed form with c1 = 1, c2 = 0 and no twist term.
+template <class S>
+DM_HD void stencil_kappa1_grad_g(const Vec<S>& ef, const Vec<S>& ee, const S& thf, const S& the, const Vec<S>& tnf,
+                                 const Vec<S>& d1nf, const Vec<S>& tne, const Vec<S>& d1ne, S* g8) {
+  EdgeFrame<S> F, G;
+  Vec<S> d1f, d1e;
+  edge_frame_g(ef, thf, tnf, d1nf, F, d1f);
+  edge_frame_g(ee, the, tne, d1ne, G, d1e);
+  S ichi = dinv(vdot(F.t, G.t) + 1.0);
+  Vec<S> kb = vscale(2.0 * ichi, vcross(F.t, G.t));
+  S k1 = 0.5 * (vdot(kb, F.m2) + vdot(kb, G.m2));
+  S af = -0.5 * vdot(kb, F.m1);
+  S ae = -0.5 * vdot(kb, G.m1);
+  Vec<S> M = vscale(ichi, vadd(F.m2, G.m2));
+  Vec<S> V = vscale(-(k1 * ichi), vadd(F.t, G.t));
+  Vec<S> gf = vadd(vscale(F.il, vadd(vcross(G.t, M), V)), vscale(af, F.w));
+  Vec<S> ge = vadd(vscale(G.il, vsub(V, vcross(F.t, M))), vscale(ae, G.w));
+  g8[0] = gf.x; g8[1] = gf.y; g8[2] = gf.z;
+  g8[3] = ge.x; g8[4] = ge.y; g8[5] = ge.z;
+  g8[6] = af; g8[7] = ae;
+}

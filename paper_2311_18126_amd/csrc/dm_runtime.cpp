@@ -29,6 +29,9 @@ extern "C" hipError_t dm_launch_gather_tips(const double* x, int nn, const int* 
 extern "C" hipError_t dm_launch_fit_loss(const double* tips, const double* target, int n, double* dL, double* loss,
                                          hipStream_t stream);
 extern "C" hipError_t dm_launch_axpy(double* y, const double* x, double a, int n, hipStream_t stream);
+extern "C" hipError_t dm_launch_stencil_curvature(const DmStepArgs* args, double* out, hipStream_t stream);
+extern "C" hipError_t dm_launch_curvature_adjoint(const DmCurvArgs* args, int block, size_t lds_bytes,
+                                                  hipStream_t stream);
 extern "C" hipError_t dm_launch_predict(const DmStepArgs* args, int block, size_t lds_bytes, double* out,
                                         hipStream_t stream);
 extern "C" hipError_t dm_ws_launch_features(const DmDev* D, int rows, const int* cn_chain, const double* nconst,
@@ -122,6 +125,13 @@ struct dm_sim {
   std::vector<SegGraph> seg_graphs;
   double* tips_stage = nullptr; size_t tips_stage_n = 0;
   double* tune_ck = nullptr; size_t tune_ck_n = 0;
+  // limb curvatures and their gradient (Real2Sim fit): per-stencil curvature, weights, adjoint
+  // solution, per-stencil derivatives, and the per-system skip mask of the fit's launches
+  double* curv_st = nullptr; size_t curv_st_n = 0;
+  double* curv_w = nullptr; size_t curv_w_n = 0;
+  double* curv_mu = nullptr; size_t curv_mu_n = 0;
+  double* curv_p = nullptr; size_t curv_p_n = 0;
+  double* skip_buf = nullptr; size_t skip_n = 0;   // int flags, sized in doubles
   int roll_steps = 0, roll_ckpt = 0;
   double roll_dt = 0.0;
   bool roll_valid = false;
@@ -963,6 +973,88 @@ size_t kbar_total(const dm_sim* s) {
   for (const Rod& R : s->rods) n += 2 * (size_t)std::max(R.n - 2, 0);
   return n;
 }
+
+// ---- limb curvatures of an equilibrium and their gradient (Real2Sim) ----
+
+dm_status curvature_supported(const dm_sim* s, const char* who) {
+  if (!s->finalized) return fail(DM_ERR_STATE, std::string(who) + " before dm_finalize");
+  if (s->scheme != DM_BACKWARD_EULER) return fail(DM_ERR_UNSUPPORTED, std::string(who) + ": only the backward-Euler step");
+  if (s->cfg.floor_contact) return fail(DM_ERR_UNSUPPORTED, std::string(who) + ": floor contact is not supported");
+  for (const Rod& R : s->rods)
+    if (R.act) return fail(DM_ERR_UNSUPPORTED, std::string(who) + ": actuated rods are not supported");
+  return DM_OK;
+}
+
+// Mean over each rod's interior stencils of kappa1 / Vbar at the committed state (0 for rods of
+// fewer than 3 nodes), summed in stencil order.
+dm_status read_limb_curvatures(dm_sim* s, std::vector<double>& kappa) {
+  dm_status st;
+  if ((st = grow(s, &s->curv_st, &s->curv_st_n, (size_t)s->n_st)) != DM_OK) return st;
+  DmStepArgs A;
+  fill_step_args(s, 1.0, 0, A);
+  DM_HIP(dm_launch_stencil_curvature(&A, s->curv_st, s->stream));
+  std::vector<double> h(s->n_st);
+  DM_HIP(hipMemcpyAsync(h.data(), s->curv_st, sizeof(double) * s->n_st, hipMemcpyDeviceToHost, s->stream));
+  DM_HIP(hipStreamSynchronize(s->stream));
+  kappa.assign(s->rods.size(), 0.0);
+  for (size_t r = 0; r < s->rods.size(); ++r) {
+    const int m = s->rods[r].n - 2;
+    if (m <= 0) continue;
+    double sum = 0.0;
+    for (int i = 0; i < m; ++i) sum += h[s->rod_st0[r] + i];
+    kappa[r] = sum / m;
+  }
+  return DM_OK;
+}
+
+// d (sum_r w_r kappa_r) / d kbar_r at the committed (settled) state, kbar_r a rod's uniform
+// natural curvature (1/m, first component), by the equilibrium adjoint with a step of dt;
+// systems whose flag in skip_dev (device ints, or null) is set are left out (their entries 0).
+dm_status limb_curvature_gradient(dm_sim* s, double dt, const double* w, std::vector<double>& g, const int* skip_dev) {
+  dm_status st;
+  const size_t NN = s->n_nodes, NE = s->n_edges, NS = s->n_st;
+  std::vector<double> wst(NS, 0.0);
+  for (size_t r = 0; r < s->rods.size(); ++r) {
+    const int m = s->rods[r].n - 2;
+    for (int i = 0; i < m; ++i) {
+      const int k = s->rod_st0[r] + i;
+      wst[k] = w[r] / (m * s->h_Vbar[k]);
+    }
+  }
+  if ((st = grow(s, &s->curv_w, &s->curv_w_n, NS)) != DM_OK) return st;
+  if ((st = grow(s, &s->curv_mu, &s->curv_mu_n, 3 * NN + NE)) != DM_OK) return st;
+  if ((st = grow(s, &s->curv_p, &s->curv_p_n, NS)) != DM_OK) return st;
+  DM_HIP(hipMemcpyAsync(s->curv_w, wst.data(), sizeof(double) * NS, hipMemcpyHostToDevice, s->stream));
+  DM_HIP(hipMemsetAsync(s->curv_p, 0, sizeof(double) * NS, s->stream));
+  DmCurvArgs C;
+  std::memset(&C, 0, sizeof(C));
+  fill_step_args(s, dt, 0, C.s);
+  C.s.warm = 0;
+  C.c.wst = s->curv_w;
+  C.c.mu = s->curv_mu;
+  C.c.pst = s->curv_p;
+  C.c.skip = skip_dev;
+  const size_t lds = step_lds(C.s);
+  DM_HIP(dm_launch_curvature_adjoint(&C, s->block, lds, s->stream));
+  std::vector<double> p(NS);
+  std::vector<int> status(s->n_sys);
+  DM_HIP(hipMemcpyAsync(p.data(), s->curv_p, sizeof(double) * NS, hipMemcpyDeviceToHost, s->stream));
+  DM_HIP(hipMemcpyAsync(status.data(), s->dev.s_status, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost, s->stream));
+  DM_HIP(hipStreamSynchronize(s->stream));
+  std::vector<int> skip(s->n_sys, 0);
+  if (skip_dev) DM_HIP(hipMemcpy(skip.data(), skip_dev, sizeof(int) * s->n_sys, hipMemcpyDeviceToHost));
+  for (int k = 0; k < s->n_sys; ++k)
+    if (!skip[k] && status[k] == DM_ERR_SINGULAR)
+      return fail(DM_ERR_SINGULAR, "limb curvature gradient: singular Newton matrix in some system");
+  g.assign(s->rods.size(), 0.0);
+  for (size_t r = 0; r < s->rods.size(); ++r) {
+    const int m = s->rods[r].n - 2;
+    double sum = 0.0;
+    for (int i = 0; i < m; ++i) sum += p[s->rod_st0[r] + i];
+    g[r] = sum;
+  }
+  return DM_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -1392,6 +1484,115 @@ dm_status dm_adjoint(dm_sim* s, const double* dL_dtips, int in_on_device, double
   return DM_OK;
 }
 
+dm_status dm_limb_curvatures(dm_sim* s, double* kappa) {
+  if (!s || !kappa) return fail(DM_ERR_INVALID_ARG, "dm_limb_curvatures: null argument");
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_limb_curvatures before dm_finalize");
+  DM_HIP(hipSetDevice(s->cfg.device));
+  std::vector<double> k;
+  dm_status st;
+  if ((st = read_limb_curvatures(s, k)) != DM_OK) return st;
+  std::copy(k.begin(), k.end(), kappa);
+  return DM_OK;
+}
+
+dm_status dm_limb_curvature_gradient(dm_sim* s, double dt, const double* w, double* grad) {
+  if (!s || !w || !grad) return fail(DM_ERR_INVALID_ARG, "dm_limb_curvature_gradient: null argument");
+  dm_status st;
+  if ((st = curvature_supported(s, "dm_limb_curvature_gradient")) != DM_OK) return st;
+  if (!(dt > 0) || !std::isfinite(dt)) return fail(DM_ERR_INVALID_ARG, "dm_limb_curvature_gradient: bad dt");
+  if (!finite_all(w, s->rods.size())) return fail(DM_ERR_INVALID_ARG, "dm_limb_curvature_gradient: non-finite weight");
+  DM_HIP(hipSetDevice(s->cfg.device));
+  std::vector<double> g;
+  if ((st = limb_curvature_gradient(s, dt, w, g, nullptr)) != DM_OK) return st;
+  std::copy(g.begin(), g.end(), grad);
+  return DM_OK;
+}
+
+dm_status dm_fit_limb_curvatures(dm_sim* s, double dt, int n_settle, int n_configs, const double* targets,
+                                 double alpha0, double tol, int max_iter, double* kbar_traj, int* steps,
+                                 double* losses) {
+  if (!s || !targets || !kbar_traj) return fail(DM_ERR_INVALID_ARG, "dm_fit_limb_curvatures: null argument");
+  dm_status st;
+  if ((st = curvature_supported(s, "dm_fit_limb_curvatures")) != DM_OK) return st;
+  if (!(dt > 0) || !std::isfinite(dt) || n_settle < 1 || n_configs < 0 || !(alpha0 > 0) || !std::isfinite(alpha0) ||
+      !(tol >= 0) || max_iter < 0)
+    return fail(DM_ERR_INVALID_ARG, "dm_fit_limb_curvatures: bad dt, n_settle, n_configs, alpha0, tol or max_iter");
+  const int nr = (int)s->rods.size(), ns = s->n_sys;
+  if (!finite_all(targets, (size_t)n_configs * nr)) return fail(DM_ERR_INVALID_ARG, "dm_fit_limb_curvatures: non-finite target");
+  DM_HIP(hipSetDevice(s->cfg.device));
+  if ((st = grow(s, &s->skip_buf, &s->skip_n, ((size_t)ns + 1) / 2)) != DM_OK) return st;
+  int* skip_dev = reinterpret_cast<int*>(s->skip_buf);
+  std::vector<double> kv(nr, 0.0), kappa, g, w(nr);
+  std::vector<int> skip(ns);
+  for (int c = 0; c < n_configs; ++c) {
+    const double* tgt = targets + (size_t)c * nr;
+    std::vector<double> alpha(ns, alpha0), prev(ns, std::numeric_limits<double>::infinity()), lam(ns, 0.0);
+    std::vector<int> it(ns, 0), active(ns, 1);
+    while (true) {
+      // F(kbar): the natural curvature of every rod's interior stencils, then n_settle steps of
+      // the systems still fitting
+      for (int r = 0; r < nr; ++r) {
+        Rod& R = s->rods[r];
+        R.kbar.assign(2 * (size_t)std::max(R.n - 2, 0), 0.0);
+        R.has_kbar = true;
+        for (int i = 0; i + 2 < R.n; ++i) {
+          const int k = s->rod_st0[r] + i;
+          R.kbar[2 * i] = kv[r];
+          s->h_kbar[k] = kv[r] * s->h_Vbar[k];
+          s->h_kbar[s->n_st + k] = 0.0;
+        }
+      }
+      if ((st = upload_kbar(s)) != DM_OK) return st;
+      for (int k = 0; k < ns; ++k) skip[k] = !active[k];
+      DM_HIP(hipMemcpyAsync(skip_dev, skip.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s->stream));
+      DmStepArgs A;
+      fill_step_args(s, dt, n_settle, A);
+      A.skip = skip_dev;
+      const size_t lds = step_lds(A);
+      DM_HIP(dm_launch_step(&A, s->block, lds, s->stream));
+      std::vector<int> status(ns);
+      DM_HIP(hipMemcpyAsync(status.data(), s->dev.s_status, sizeof(int) * ns, hipMemcpyDeviceToHost, s->stream));
+      DM_HIP(hipStreamSynchronize(s->stream));
+      for (int k = 0; k < ns; ++k)
+        if (active[k] && status[k] != DM_OK)
+          return fail(status[k] == DM_ERR_SINGULAR ? DM_ERR_SINGULAR : DM_NOT_CONVERGED,
+                      "dm_fit_limb_curvatures: the quasi-static solve failed in system " + std::to_string(k));
+      s->time += dt * n_settle;
+      if ((st = read_limb_curvatures(s, kappa)) != DM_OK) return st;
+      // Eq. 19 per system, then Alg. 1's stopping test and step-size rule
+      std::fill(lam.begin(), lam.end(), 0.0);
+      for (int r = 0; r < nr; ++r) lam[s->rod_sys[r]] += std::fabs(tgt[r] - kappa[r]);
+      bool any = false;
+      for (int k = 0; k < ns; ++k) {
+        if (!active[k]) continue;
+        if (lam[k] < tol || it[k] >= max_iter) { active[k] = 0; continue; }
+        if (lam[k] > prev[k]) alpha[k] *= 0.5;
+        prev[k] = lam[k];
+        any = true;
+      }
+      if (!any) break;
+      for (int r = 0; r < nr; ++r) {
+        const double d = kappa[r] - tgt[r];
+        w[r] = active[s->rod_sys[r]] ? (double)((d > 0) - (d < 0)) : 0.0;
+      }
+      for (int k = 0; k < ns; ++k) skip[k] = !active[k];
+      DM_HIP(hipMemcpyAsync(skip_dev, skip.data(), sizeof(int) * ns, hipMemcpyHostToDevice, s->stream));
+      if ((st = limb_curvature_gradient(s, dt, w.data(), g, skip_dev)) != DM_OK) return st;
+      for (int r = 0; r < nr; ++r) {
+        const int k = s->rod_sys[r];
+        if (active[k]) kv[r] -= alpha[k] * g[r];
+      }
+      for (int k = 0; k < ns; ++k) it[k] += active[k];
+    }
+    for (int r = 0; r < nr; ++r) kbar_traj[(size_t)c * nr + r] = kv[r];
+    for (int k = 0; k < ns; ++k) {
+      if (steps) steps[(size_t)c * ns + k] = it[k];
+      if (losses) losses[(size_t)c * ns + k] = lam[k];
+    }
+  }
+  return DM_OK;
+}
+
 dm_status dm_fit_natural_curvature(dm_sim* s, double dt, int nsteps, int ckpt_every, const double* target_tips,
                                    int target_on_device, double alpha0, double tol, int max_iter, double* kbar,
                                    int kbar_on_device, double* losses, int* n_eval) {
@@ -1668,7 +1869,8 @@ void dm_destroy(dm_sim* s) {
   (void)hipSetDevice(s->cfg.device);
   (void)hipStreamSynchronize(s->stream);
   for (void* p : s->allocs) dev_free(s, p);
-  for (double* p : {s->ck, s->seg, s->adj, s->tips_dev, s->dl_dev, s->ws_F, s->tips_stage, s->tune_ck})
+  for (double* p : {s->ck, s->seg, s->adj, s->tips_dev, s->dl_dev, s->ws_F, s->tips_stage, s->tune_ck, s->curv_st,
+                    s->curv_w, s->curv_mu, s->curv_p, s->skip_buf})
     dev_free(s, p);
   for (SegGraph& c : s->seg_graphs) { (void)hipGraphExecDestroy(c.exec); (void)hipGraphDestroy(c.graph); }
   if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);

@@ -125,6 +125,29 @@ def golden_adjoint_full():
             "tips": tips.numpy()}
 
 
+# Real2Sim fit (Alg. 1, Eq. 19-21) of the two-limb manipulator (1 cm radius, so that gravity
+# bends the limbs visibly), three target configurations produced by known natural curvatures
+R2S_KSTAR = [[0.6, -0.4], [0.75, -0.25], [0.8, 0.0]]
+R2S_TOL, R2S_MAXIT = 1e-5, 150
+
+
+def golden_real2sim():
+    from oracle import real2sim as RS
+    import torch
+    d = W.two_limb_manipulator(limb_nodes=8, radius=0.01)
+    sys_, st = der.build(d)
+    kv = torch.tensor([1.7, -0.8], dtype=der.DT)
+    st = RS.settle(sys_, st, kv, d["dt"], d["steps"])
+    out = {"settled_kbar": kv.numpy(), "settled_kappa": RS.limb_curvatures(sys_, st.x, st.theta, st).numpy()}
+    for i, w in enumerate(([1.0, 0.0], [0.0, 1.0])):
+        out[f"grad_{i}"] = RS.curvature_gradient(sys_, st, kv, torch.tensor(w, dtype=der.DT), d["dt"]).numpy()
+    targets = RS.curvatures_at(d, np.array(R2S_KSTAR)).numpy()
+    traj, losses, steps, _ = RS.solve_natural_curvatures(d, targets, tol=R2S_TOL, max_iter=R2S_MAXIT)
+    out.update({"targets": targets, "kstar": np.array(R2S_KSTAR), "traj": traj.numpy(), "losses": np.array(losses),
+                "steps": np.array(steps), "tol": np.array(R2S_TOL), "max_iter": np.array(R2S_MAXIT)})
+    return out
+
+
 def golden_helix():
     d = W.paper_helix(steps=20)
     return run(d, [0], {1, 20})
@@ -182,7 +205,7 @@ def golden_fit():
 GOLDEN = {"cantilever": golden_cantilever, "batch": golden_batch, "helix": golden_helix, "star": golden_star,
           "adjoint": golden_adjoint, "cantilever_midpoint": golden_cantilever_midpoint,
           "star_midpoint": golden_star_midpoint, "fit": golden_fit, "batch100": golden_batch100,
-          "star100": golden_star100, "adjoint_full": golden_adjoint_full}
+          "star100": golden_star100, "adjoint_full": golden_adjoint_full, "real2sim": golden_real2sim}
 
 
 if __name__ == "__main__":

@@ -154,8 +154,8 @@ def two_limb_manipulator(n_robots: int = 1, limb_nodes: int = 12, limb_length: f
     end to start by an elastic joint and hanging from a base clamped at its first two nodes
     and first twist, along -z under gravity -9.8 z.  Rods 2r and 2r + 1 are robot r's limbs;
     robots are offset along x.  The limbs' natural curvature is set by the caller.  dt = 1e4 s,
-    one step: a quasi-static configuration is one implicit step so long that inertia is
-    negligible."""
+    one step with line search: a quasi-static configuration is one implicit step so long that
+    inertia is negligible."""
     rods, joints = [], []
     for k in range(n_robots):
         o = np.array([spacing * k, 0.0, 0.0])
@@ -165,7 +165,9 @@ def two_limb_manipulator(n_robots: int = 1, limb_nodes: int = 12, limb_length: f
                  radius, 1.793e6, 0.5, 1240.0, kbar=np.zeros((limb_nodes - 2, 2)), fixed_nodes=(), fixed_edges=())
         rods += [a, b]
         joints.append((2 * k, limb_nodes - 1, 2 * k + 1, 0))
-    return _desc(rods, dt=1e4, steps=1, gravity=(0.0, 0.0, -9.8), joints=joints)
+    d = _desc(rods, dt=1e4, steps=1, gravity=(0.0, 0.0, -9.8), joints=joints)
+    d["line_search"] = True
+    return d
 
 
 def limb_curvature_targets(n_configs: int = 8, seed: int = 5, n_robots: int = 1, scale: float = 1.0) -> np.ndarray:
