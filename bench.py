@@ -34,9 +34,9 @@ METRIC = "node-steps/s, batched implicit DER at 1e-9 residual; plain vs warm-sta
 FLOP_COUNT_FILE = os.path.join(ROOT, "profiles", "flop_count.json")
 PEAK_FP64_VALU_TFLOPS = 78.6          # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz
 PEAK_BF16_MFMA_TFLOPS = 2500.0        # dense BF16 matrix-core peak, published
-# 20-256-256-3 network, per row of a training step: forward 2 (20*256 + 256*256 + 256*3),
-# input gradients of layers 3 and 2: 2 (256*3 + 256*256), weight gradients 2 (20*256 + 256*256 + 3*256)
-INFER_FLOPS_PER_ROW = 2 * (20 * 256 + 256 * 256 + 256 * 3)
+# 26-256-256-3 network, per row of a training step: forward 2 (26*256 + 256*256 + 256*3),
+# input gradients of layers 3 and 2: 2 (256*3 + 256*256), weight gradients 2 (26*256 + 256*256 + 3*256)
+INFER_FLOPS_PER_ROW = 2 * (26 * 256 + 256 * 256 + 256 * 3)
 TRAIN_FLOPS_PER_ROW = 2 * INFER_FLOPS_PER_ROW + 2 * (256 * 3 + 256 * 256)
 KERNEL_SOURCES = ["paper_2311_18126_amd/csrc/dm_kernels.hip", "paper_2311_18126_amd/csrc/dm_math.h",
                   "paper_2311_18126_amd/csrc/dm_layout.h", "paper_2311_18126_amd/csrc/dm_warm.h",
@@ -234,7 +234,8 @@ def warm_start_section(dm, steps, log):
     out["training_mfma"] = {"bound": "mfma", "achieved": train_flops / t_train / 1e12, "peak": PEAK_BF16_MFMA_TFLOPS,
                             "unit": "TFLOP/s", "frac": train_flops / t_train / 1e12 / PEAK_BF16_MFMA_TFLOPS,
                             "algorithmic_flops": float(train_flops)}
-    for name, mode in (("plain", 0), ("explicit_predictor", 1), ("extrapolation", 3), ("network", 2)):
+    for name, mode in (("plain", 0), ("explicit_predictor", 1), ("extrapolation", 3), ("third_order", 4),
+                       ("network", 2)):
         sim = dm.sim_from_description(ev)
         sim.set_warm_start(net if mode == 2 else None, mode)
         sim.step(ev["dt"], 2)

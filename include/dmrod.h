@@ -285,33 +285,36 @@ dm_status dm_fit_limb_curvatures(dm_sim* sim, double dt, int n_settle, int n_con
  * Not part of the paper's method: a small network predicts each node's displacement over a
  * step and the prediction is Newton's initial guess (Eq. 16 is still iterated to newton_tol,
  * and a warm-started step whose solve fails is redone from the step-start state).
- * Network: 20 features per node -> 256 -> 256 -> 3, ReLU, bfloat16 operands with float32
+ * Network: 26 features per node -> 256 -> 256 -> 3, ReLU, bfloat16 operands with float32
  * accumulation on the matrix cores; parameters are float32 master weights laid out as
- * W1 [256][20], b1 [256], W2 [256][256], b2 [256], W3 [3][256], b3 [3] (dm_mlp_num_params()).
- * Features of node i of a rod (raw, float64, row-major [rows][20]; a missing neighbour at a rod
+ * W1 [256][26], b1 [256], W2 [256][256], b2 [256], W3 [3][256], b3 [3] (dm_mlp_num_params()).
+ * Features of node i of a rod (raw, float64, row-major [rows][26]; a missing neighbour at a rod
  * end is replicated): v_{i-1} - v_i, v_{i+1} - v_i, v_i, the velocity change over the last
  * step a_i = v_i - v_prev_i, x_{i-1} - 2 x_i + x_{i+1}, log10 E, radius, mean rest length of the
- * edges at i, and the natural curvature at i in 1/m (nearest
- * interior node at the ends).  Inputs are standardised ((f - mean)/std per feature); the
- * output y is the displacement beyond the second-order extrapolation in units of a
- * per-component scale: dx = dt (v + a) + scale * y.  Targets passed to training are raw
- * dx - dt (v + a) (float64 [rows][3]).
+ * edges at i, the natural curvature at i in 1/m (nearest interior node at the ends), the change
+ * of the velocity change j_i = a_i - (v_prev_i - v_prev2_i), and a_{i-1} - 2 a_i + a_{i+1}.
+ * Inputs are standardised ((f - mean)/std per feature); the output y is the displacement
+ * beyond the third-order extrapolation in units of a per-component scale:
+ * dx = dt (v + a + j) + scale * y.  Targets passed to training are raw dx - dt (v + a + j)
+ * (float64 [rows][3]).
  * A dm_mlp owns its device buffers; row counts are at most max_rows.  All pointers to
  * features, targets, outputs and gradients are device memory. */
 typedef struct dm_mlp dm_mlp;
 size_t dm_mlp_num_params(void);
+/* Features per row (26). */
+int dm_mlp_num_inputs(void);
 dm_status dm_mlp_create(int device, void* stream, int max_rows, dm_mlp** out);
 /* params: float32 [dm_mlp_num_params()], host or device; resets Adam's moments and step. */
 dm_status dm_mlp_set_params(dm_mlp* net, const float* params, int on_device);
 dm_status dm_mlp_get_params(dm_mlp* net, float* params, int on_device);
-/* Standardisation: host arrays mean [20], std [20], output scale [3] (all std, scale > 0). */
+/* Standardisation: host arrays mean [26], std [26], output scale [3] (all std, scale > 0). */
 dm_status dm_mlp_set_normalisation(dm_mlp* net, const double* mean, const double* std, const double* scale);
 dm_status dm_mlp_get_normalisation(dm_mlp* net, double* mean, double* std, double* scale);
 /* Mean and standard deviation of each feature and the root-mean-square of each target
- * component over n >= 2 rows of raw features F [n][20] (device, 16-byte aligned) and targets
+ * component over n >= 2 rows of raw features F [n][26] (device, 16-byte aligned) and targets
  * T [n][3] (device). */
 dm_status dm_mlp_fit_normalisation(dm_mlp* net, const double* F, const double* T, int n);
-/* Y [n][3] (float32): the network's standardised output for raw features F [n][20]. */
+/* Y [n][3] (float32): the network's standardised output for raw features F [n][26]. */
 dm_status dm_mlp_forward(dm_mlp* net, const double* F, int n, float* Y);
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc): the same forward pass as dm_mlp_forward, bit for
@@ -319,7 +322,7 @@ dm_status dm_mlp_forward(dm_mlp* net, const double* F, int n, float* Y);
  * device array of the library instead of the network's buffers, so the call allocates
  * nothing.  n is limited to DM_MLP_NOALLOC_MAX_ROWS (the array holds that many rows, about
  * 4.5 MB on each GPU the library runs on, kept until the process ends); a larger n returns
- * DM_ERR_INVALID_ARG.  F [n][20] float64 and Y [n][3] float32 are device memory.  Every call
+ * DM_ERR_INVALID_ARG.  F [n][26] float64 and Y [n][3] float32 are device memory.  Every call
  * on a GPU uses that GPU's one array: calls that overlap on one GPU (other threads, other
  * streams) race.  The array's device address is looked up once per device on the first call. */
 #define DM_MLP_NOALLOC_MAX_ROWS 2048
@@ -330,7 +333,7 @@ dm_status dm_mlp_gradients(dm_mlp* net, const double* F, const double* T, int n,
 /* One Adam step (beta 0.9 / 0.999, eps 1e-8, learning rate lr) on that loss. */
 dm_status dm_mlp_train_step(dm_mlp* net, const double* F, const double* T, int n, float lr, double* loss);
 /* One epoch of such steps without a host wait per step: mini-batches of `batch` rows taken in
- * the order of perm (device int32 [n], indices into the n rows of F [n][20] and T [n][3], both
+ * the order of perm (device int32 [n], indices into the n rows of F [n][26] and T [n][3], both
  * device float64); the last n % batch entries of perm are not used.  mean_loss (host, may be
  * NULL) receives the mean of the batch losses.  1 <= batch <= min(n, max_rows); an index of
  * perm outside 0..n-1 gives DM_ERR_INVALID_ARG (that batch's row is replaced by row 0 and the
@@ -343,23 +346,26 @@ void dm_mlp_destroy(dm_mlp* net);
 /* Rows of the simulation's feature matrix: one per rod node (a node shared by k rods appears
  * k times; the prediction of the rod that assembles the node's own terms is used). */
 int dm_ws_rows(const dm_sim* sim);
-/* Raw features of every row at the current (step-start) state into F [rows][20] (device). */
+/* Raw features of every row at the current (step-start) state into F [rows][26] (device). */
 dm_status dm_ws_features(dm_sim* sim, double* F);
-/* Training targets after a step: dt (v_{n+1} - v_n - a_n) per row into T [rows][3] (device),
- * with v_n and a_n taken from the step-start features F_prev. */
+/* Training targets after a step: dt (v_{n+1} - v_n - a_n - j_n) per row into T [rows][3]
+ * (device), with v_n, a_n and j_n taken from the step-start features F_prev. */
 dm_status dm_ws_targets(dm_sim* sim, const double* F_prev, double dt, double* T);
 /* Warm start of dm_step: mode 0 off (Newton from x_n), 1 explicit predictor x_n + dt v_n,
- * 2 the network on top of the second-order extrapolation x_n + dt (v_n + a_n), 3 that
- * extrapolation alone.  Each system guesses at the start of every step inside the same
- * persistent launch (the network runs there on the matrix cores); a guess whose Newton solve
- * fails within warm_max_iter iterations is redone from x_n and counted in dm_stats.fallbacks.
- * The sim keeps a reference to net, which must outlive its use.  After dm_set_state or
- * dm_load_checkpoint the last-step velocity change a is zero. */
+ * 3 the second-order extrapolation x_n + dt (v_n + a_n), 4 the third-order extrapolation
+ * x_n + dt (v_n + a_n + j_n), 2 the network on top of the third-order extrapolation (dt is the
+ * Newton step: a substep of adaptive halving takes its share of the network's correction).
+ * Each system guesses at the start of every step inside the same persistent launch (the
+ * network runs there on the matrix cores); a guess whose Newton solve fails within
+ * warm_max_iter iterations is redone from x_n and counted in dm_stats.fallbacks.  The sim
+ * keeps a reference to net, which must outlive its use.  After dm_set_state or
+ * dm_load_checkpoint the velocity history is the current velocity (a = j = 0). */
 dm_status dm_set_warm_start(dm_sim* sim, dm_mlp* net, int mode);
-/* The guessed displacement x^(0) - x_n of every feature row for a step of dt from the
+/* The guessed displacement x^(0) - x_n of every feature row for a Newton step of dt from the
  * current state under the current warm mode (not 0), into dx [rows][3] (device memory if
- * on_device, else host); the state is not changed.  Rows of clamped or shared nodes are
- * reported too (the step leaves clamped DOFs alone and uses the owning rod's row). */
+ * on_device, else host); the state is not changed.  The network's correction enters whole
+ * (dt is taken as a full step).  Rows of clamped or shared nodes are reported too (the step
+ * leaves clamped DOFs alone and uses the owning rod's row). */
 dm_status dm_ws_predict(dm_sim* sim, double dt, double* dx, int on_device);
 
 /* Autotuner: times the step kernel at each workgroup size (64, 128, 256, 512 threads) over

@@ -8,17 +8,18 @@ start predicts each node's displacement over the step with a small network and h
 Newton as the initial guess; Newton still decides convergence.  Definitions (the network is
 not in the paper; these are the build's own, stated in the design notes):
 
-* features of node i of a rod (20; a missing neighbour at a rod end replicated):
+* features of node i of a rod (26; a missing neighbour at a rod end replicated):
   v_{i-1} - v_i, v_{i+1} - v_i, v_i, the velocity change over the last step a_i = v_i - v_prev_i,
   x_{i-1} - 2 x_i + x_{i+1}, log10 E, the radius, the mean rest length of the edges at node i,
-  and the natural curvature at node i in 1/m (the nearest interior node's at the rod ends);
+  the natural curvature at node i in 1/m (the nearest interior node's at the rod ends), the
+  change of the velocity change j_i = a_i - (v_prev_i - v_prev2_i), and a_{i-1} - 2 a_i + a_{i+1};
 * standardisation: z = (f - mean) / std per feature, computed in float64, rounded to float32;
-* network 20 -> 256 -> 256 -> 3 with ReLU; every GEMM input (activations, weights and
+* network 26 -> 256 -> 256 -> 3 with ReLU; every GEMM input (activations, weights and
   back-propagated gradients) is rounded to bfloat16 (round to nearest, ties to even); products
   of bfloat16 values are exact and are accumulated here in float64 (the kernels accumulate in
   float32); biases and master weights are float32;
-* output: the displacement beyond the second-order extrapolation, dx = dt (v_i + a_i) + s y,
-  with s the per-component root-mean-square of (dx - dt (v + a)) over the training data;
+* output: the displacement beyond the third-order extrapolation, dx = dt (v_i + a_i + j_i) + s y,
+  with s the per-component root-mean-square of (dx - dt (v + a + j)) over the training data;
 * loss: mean over the batch of the squared error summed over the three components; Adam
   (beta 0.9 / 0.999, eps 1e-8) on the float32 master weights.
 
@@ -32,7 +33,7 @@ from __future__ import annotations
 import numpy as np
 import torch
 
-N_IN, N_HID, N_OUT = 20, 256, 3
+N_IN, N_HID, N_OUT = 26, 256, 3
 
 
 # ---------------------------------------------------------------------------
@@ -59,13 +60,15 @@ def to_f32(a):
 # features
 # ---------------------------------------------------------------------------
 
-def rod_features(x, v, v_prev, kbar, E, h, ebar):
-    """Features (N, 20) of one rod: x, v, v_prev (N, 3) at the start of the step (v_prev the
-    velocity before the previous step), kbar (N-2, 2) in 1/m (or None for zero), E, h scalars,
-    ebar (N-1,) rest edge lengths."""
+def rod_features(x, v, v_prev, v_prev2, kbar, E, h, ebar):
+    """Features (N, 26) of one rod: x, v, v_prev, v_prev2 (N, 3) at the start of the step
+    (v_prev the velocity before the previous step, v_prev2 the one before that), kbar (N-2, 2)
+    in 1/m (or None for zero), E, h scalars, ebar (N-1,) rest edge lengths."""
     x = np.asarray(x, dtype=np.float64)
     v = np.asarray(v, dtype=np.float64)
-    a = v - np.asarray(v_prev, dtype=np.float64)
+    vp = np.asarray(v_prev, dtype=np.float64)
+    a = v - vp
+    a_prev = vp - np.asarray(v_prev2, dtype=np.float64)
     n = x.shape[0]
     f = np.zeros((n, N_IN))
     for i in range(n):
@@ -80,6 +83,8 @@ def rod_features(x, v, v_prev, kbar, E, h, ebar):
         f[i, 17] = ebar[0] if i == 0 else (ebar[n - 2] if i == n - 1 else 0.5 * (ebar[i - 1] + ebar[i]))
         if n >= 3 and kbar is not None:
             f[i, 18:20] = kbar[min(max(i, 1), n - 2) - 1]
+        f[i, 20:23] = a[i] - a_prev[i]
+        f[i, 23:26] = a[im] - 2.0 * a[i] + a[ip]
     return f
 
 

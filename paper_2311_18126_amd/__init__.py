@@ -24,6 +24,8 @@ DM_ERR_HIP = -3
 DM_ERR_OOM = -4
 DM_ERR_SINGULAR = -5
 DM_ERR_UNSUPPORTED = -6
+
+NET_IN = 26     # warm-start features per row (checked against the library when a network is made)
 DM_MLP_NOALLOC_MAX_ROWS = 2048     # rows of dm_mlp_forward_noalloc's static activation buffer
 
 
@@ -85,6 +87,7 @@ _SIGS = {
     "dm_fit_limb_curvatures": (c_int, [c_void_p, c_double, c_int, c_int, _DP, c_double, c_double, c_int, _DP,
                                        _IP, _DP]),
     "dm_mlp_num_params": (c_size_t, []),
+    "dm_mlp_num_inputs": (c_int, []),
     "dm_mlp_create": (c_int, [c_int, c_void_p, c_int, POINTER(c_void_p)]),
     "dm_mlp_set_params": (c_int, [c_void_p, c_void_p, c_int]),
     "dm_mlp_get_params": (c_int, [c_void_p, c_void_p, c_int]),
@@ -421,13 +424,13 @@ class Sim:
 
     def ws_features(self, out):
         """Raw warm-start features of every row at the current state into `out`, a float64
-        device tensor (ws_rows, 20)."""
+        device tensor (ws_rows, NET_IN)."""
         _check(lib().dm_ws_features(self._h, out.data_ptr()), "dm_ws_features")
         return out
 
     def ws_targets(self, features_prev, dt, out):
-        """Targets dt (v_{n+1} - v_n) after a step, from the step-start features, into `out`
-        (float64 device tensor (ws_rows, 3))."""
+        """Targets dt (v_{n+1} - v_n - a_n - j_n) after a step, from the step-start features,
+        into `out` (float64 device tensor (ws_rows, 3))."""
         _check(lib().dm_ws_targets(self._h, features_prev.data_ptr(), dt, out.data_ptr()), "dm_ws_targets")
         return out
 
@@ -442,8 +445,9 @@ class Sim:
         return h
 
     def set_warm_start(self, net=None, mode=None):
-        """Warm start of step(): None/0 off, 1 explicit predictor x_n + dt v_n, 2 the network
-        `net` on top of the second-order extrapolation, 3 that extrapolation alone."""
+        """Warm start of step(): None/0 off, 1 explicit predictor x_n + dt v_n, 3 the
+        second-order extrapolation x_n + dt (v_n + a_n), 4 the third-order one
+        x_n + dt (v_n + a_n + j_n), 2 the network `net` on top of the third-order one."""
         if mode is None:
             mode = 0 if net is None else 2
         _check(lib().dm_set_warm_start(self._h, net._h if net is not None else None, mode), "dm_set_warm_start")
@@ -574,6 +578,9 @@ class Mlp:
     """The warm-start network (dm_mlp): float32 master weights, bfloat16 matrix-core kernels."""
 
     def __init__(self, max_rows, device=0, stream=None):
+        if lib().dm_mlp_num_inputs() != NET_IN:
+            raise DmError(f"libdmrod.so takes {lib().dm_mlp_num_inputs()} features per row, the binding {NET_IN}: "
+                          "rebuild the library")
         h = c_void_p()
         _check(lib().dm_mlp_create(device, stream, int(max_rows), ctypes.byref(h)), "dm_mlp_create")
         self._h = h
@@ -608,11 +615,11 @@ class Mlp:
         return p
 
     def set_normalisation(self, mean, std, scale):
-        m, sd, sc = _sized(mean, 20, "mean"), _sized(std, 20, "std"), _sized(scale, 3, "scale")
+        m, sd, sc = _sized(mean, NET_IN, "mean"), _sized(std, NET_IN, "std"), _sized(scale, 3, "scale")
         _check(lib().dm_mlp_set_normalisation(self._h, _dp(m), _dp(sd), _dp(sc)), "dm_mlp_set_normalisation")
 
     def get_normalisation(self):
-        m, sd, sc = np.zeros(20), np.zeros(20), np.zeros(3)
+        m, sd, sc = np.zeros(NET_IN), np.zeros(NET_IN), np.zeros(3)
         _check(lib().dm_mlp_get_normalisation(self._h, _dp(m), _dp(sd), _dp(sc)), "dm_mlp_get_normalisation")
         return m, sd, sc
 
@@ -646,14 +653,14 @@ class Mlp:
 
     def train_epoch(self, F, T, perm, batch, lr=1e-3):
         """Adam over the mini-batches perm[0:batch], perm[batch:2 batch], ... of device features
-        F [n, 20] and targets T [n, 3] (float64); perm is a device int32 [n].  Returns the mean
+        F [n, NET_IN] and targets T [n, 3] (float64); perm is a device int32 [n].  Returns the mean
         batch loss."""
         import torch
         n = F.shape[0]
         if (F.dtype != torch.float64 or T.dtype != torch.float64 or perm.dtype != torch.int32
-                or tuple(F.shape) != (n, 20) or tuple(T.shape) != (n, 3) or tuple(perm.shape) != (n,)
+                or tuple(F.shape) != (n, NET_IN) or tuple(T.shape) != (n, 3) or tuple(perm.shape) != (n,)
                 or not (F.is_contiguous() and T.is_contiguous() and perm.is_contiguous())):
-            raise ValueError("train_epoch: F [n, 20] and T [n, 3] float64, perm [n] int32, contiguous")
+            raise ValueError(f"train_epoch: F [n, {NET_IN}] and T [n, 3] float64, perm [n] int32, contiguous")
         loss = c_double()
         _check(lib().dm_mlp_train_epoch(self._h, F.data_ptr(), T.data_ptr(), perm.data_ptr(), n, int(batch), lr,
                                         ctypes.byref(loss)), "dm_mlp_train_epoch")

@@ -1300,6 +1300,7 @@ __device__ __noinline__ void commit(ArgsP Ap, int sid, double dt) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const double v0 = D.v[c * NN + n], v = (D.x[c * NN + n] - D.x0[c * NN + n]) / dt;
+      D.vprev2[c * NN + n] = D.vprev[c * NN + n];
       D.vprev[c * NN + n] = v0;
       D.v[c * NN + n] = A.midpoint ? v - v0 : v;
       D.x0[c * NN + n] = D.x[c * NN + n];

@@ -139,6 +139,7 @@ struct DmDev {
   // state
   double DM_G* x;  double DM_G* x0;  double DM_G* v;      // [3][n_nodes]
   double DM_G* vprev;                           // [3][n_nodes] velocity before the last step
+  double DM_G* vprev2;                          // [3][n_nodes] velocity before the one before
   double DM_G* th; double DM_G* th0; double DM_G* om;     // [n_edges]
   double DM_G* tref; double DM_G* d1ref;             // [3][n_edges]
   double DM_G* bref;                            // [n_st]
@@ -166,10 +167,10 @@ struct DmDev {
   int n_nodes_tot, n_edges_tot, n_st_tot;
 };
 
-// Warm-start network of the step kernel, 20 -> 256 -> 256 -> 3 with ReLU: bfloat16 bit
+// Warm-start network of the step kernel, 26 -> 256 -> 256 -> 3 with ReLU: bfloat16 bit
 // patterns of W1 [256][32], W2 [256][256] and W3 [16][256] (zero padded, reduction index
 // contiguous), float32 biases, and the float64 input standardisation and output scales.
-#define DM_NET_IN 20
+#define DM_NET_IN 26
 #define DM_NET_HID 256
 #define DM_NET_OUT 3
 #define DM_NET_KX 32          // input width padded to one matrix-core reduction step
@@ -194,8 +195,8 @@ struct DmStepArgs {
   double floor_z, delta, nu, mu, kc;
   int floor_on;
   int max_iter, nsteps, line_search;
-  int warm;        // step-start guess: 0 none (x_n), 1 x_n + dt v_n, 3 + dt (v_n - v_prev),
-                   // 2 that plus the network's correction; a failed guess restarts from x_n
+  int warm;        // step-start guess: 0 none (x_n), 1 x_n + dt v_n, 3 + dt a_n, 4 + dt (a_n + j_n),
+                   // 2 mode 4 plus the network's correction; a failed guess restarts from x_n
   int warm_max_iter;   // Newton iterations allowed to the warm-started attempt
   int accum;       // 1: add to the statistics (one-step launches) and skip systems that failed
   int net_lds;     // byte offset of the network's LDS activations (warm == 2)

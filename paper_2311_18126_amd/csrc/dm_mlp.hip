@@ -1,4 +1,4 @@
-// dm_mlp.hip -- learned warm start of the Newton solve: a 20-256-256-3 ReLU network whose
+// dm_mlp.hip -- learned warm start of the Newton solve: a 26-256-256-3 ReLU network whose
 // matrix products run on the matrix cores in bfloat16 with float32 accumulation
 // (v_mfma_f32_16x16x32_bf16), its training (loss, backward pass, Adam), and the per-node
 // features and displacement prediction of the implicit step.
@@ -392,7 +392,7 @@ __global__ void prepare_weights(const float* __restrict__ P, u16* __restrict__ W
   }
 }
 
-// Sums and sums of squares of the 23 feature and target columns over a data set, in two
+// Sums and sums of squares of the 29 feature and target columns over a data set, in two
 // passes: each of MOM_BLOCKS workgroups reads whole rows in a grid-stride loop (so the rows
 // are read once, in order) and writes its partial sums part[b][c][0..1]; then one workgroup
 // adds the partials.
@@ -405,7 +405,7 @@ __global__ void __launch_bounds__(256) column_moments(const double* __restrict__
 #pragma unroll
   for (int c = 0; c < NC; ++c) a[c] = q[c] = 0.0;
   for (size_t r = (size_t)blockIdx.x * blockDim.x + threadIdx.x; r < (size_t)n; r += (size_t)gridDim.x * blockDim.x) {
-    const double2* f = reinterpret_cast<const double2*>(F + r * NI);   // rows of 160 bytes
+    const double2* f = reinterpret_cast<const double2*>(F + r * NI);   // rows of 208 bytes
 #pragma unroll
     for (int c = 0; c < NI / 2; ++c) {
       const double2 x = f[c];
@@ -445,7 +445,7 @@ __global__ void __launch_bounds__(256) column_moments(const double* __restrict__
 // Total of the partials: eight wavefronts each add every eighth block's partials, and the
 // eight sums are added in a fixed order.
 __global__ void __launch_bounds__(512) moments_total(const double* __restrict__ part, int nblk,
-                                                     double* __restrict__ out /*[23][2]*/) {
+                                                     double* __restrict__ out /*[29][2]*/) {
   __shared__ double red[8][2 * NC];
   const int i = threadIdx.x & 63, g = threadIdx.x >> 6;
   double s = 0.0;
@@ -465,8 +465,9 @@ __global__ void __launch_bounds__(512) moments_total(const double* __restrict__ 
 
 // Raw features of chain node entry i (missing neighbours of a rod end replicated):
 // v_{i-1} - v_i, v_{i+1} - v_i, v_i, a_i = v_i - v_prev_i (velocity change over the last
-// step), x_{i-1} - 2 x_i + x_{i+1}, log10 E, radius, mean rest length of the edges at i, and
-// the natural curvature at i in 1/m (nearest interior node at the ends).
+// step), x_{i-1} - 2 x_i + x_{i+1}, log10 E, radius, mean rest length of the edges at i, the
+// natural curvature at i in 1/m (nearest interior node at the ends), j_i = a_i - (v_prev_i -
+// v_prev2_i) (the change of the velocity change) and a_{i-1} - 2 a_i + a_{i+1}.
 __global__ void node_features(DmDev D, int rows, const int* __restrict__ cn_chain, const double* __restrict__ nconst,
                               double* __restrict__ F) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -480,12 +481,14 @@ __global__ void node_features(DmDev D, int rows, const int* __restrict__ cn_chai
   const int np = D.chain_node[ch.node_tab + (k <= N - 2 ? k + 1 : k)];
   double* f = F + (size_t)i * NI;
   for (int q = 0; q < 3; ++q) {
-    const double vi = D.v[q * NN + n0];
+    const double vi = D.v[q * NN + n0], ai = vi - D.vprev[q * NN + n0];
     f[q] = D.v[q * NN + nm] - vi;
     f[3 + q] = D.v[q * NN + np] - vi;
     f[6 + q] = vi;
-    f[9 + q] = vi - D.vprev[q * NN + n0];
+    f[9 + q] = ai;
     f[12 + q] = D.x0[q * NN + nm] - 2.0 * D.x0[q * NN + n0] + D.x0[q * NN + np];
+    f[20 + q] = ai - (D.vprev[q * NN + n0] - D.vprev2[q * NN + n0]);
+    f[23 + q] = (D.v[q * NN + nm] - D.vprev[q * NN + nm]) - 2.0 * ai + (D.v[q * NN + np] - D.vprev[q * NN + np]);
   }
   for (int q = 0; q < 3; ++q) f[15 + q] = nconst[(size_t)i * 3 + q];
   if (N >= 3) {
@@ -498,8 +501,8 @@ __global__ void node_features(DmDev D, int rows, const int* __restrict__ cn_chai
   }
 }
 
-// Training targets after a step: the displacement beyond the second-order extrapolation,
-// dt (v_{n+1} - v_n - a_n), with v_n and a_n read from the step-start features.
+// Training targets after a step: the displacement beyond the third-order extrapolation,
+// dt (v_{n+1} - v_n - a_n - j_n), with v_n, a_n and j_n read from the step-start features.
 __global__ void node_targets(DmDev D, int rows, const double* __restrict__ Fprev, double dt, double* __restrict__ T) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= rows) return;
@@ -507,7 +510,7 @@ __global__ void node_targets(DmDev D, int rows, const double* __restrict__ Fprev
   const int n0 = D.chain_node[i];
   for (int q = 0; q < 3; ++q) {
     const double* f = Fprev + (size_t)i * NI;
-    T[(size_t)i * NO + q] = dt * (D.v[q * NN + n0] - f[6 + q] - f[9 + q]);   // f: v_n, a_n
+    T[(size_t)i * NO + q] = dt * (D.v[q * NN + n0] - f[6 + q] - f[9 + q] - f[20 + q]);   // f: v_n, a_n, j_n
   }
 }
 
@@ -568,7 +571,7 @@ struct FwdBufs {
   float* Y;
 };
 
-// Forward pass on raw features F (device, [n][20]) into the activation buffers b (rows padded
+// Forward pass on raw features F (device, [n][26]) into the activation buffers b (rows padded
 // to ROWS_PAD): leaves Y [rows][3] (standardised outputs) and every activation needed by the
 // backward pass.
 dm_status forward_into(dm_mlp* m, const FwdBufs& b, const double* F, int n, int rows) {
@@ -701,6 +704,7 @@ dm_status gradients(dm_mlp* m, const double* F, const double* T, int n, double* 
 extern "C" {
 
 size_t dm_mlp_num_params(void) { return NPARAM; }
+int dm_mlp_num_inputs(void) { return NI; }
 const char* dm_mlp_last_error(void) { return g_mlp_err.c_str(); }
 
 dm_status dm_mlp_create(int device, void* stream, int max_rows, dm_mlp** out) {

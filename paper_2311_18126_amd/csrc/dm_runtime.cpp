@@ -688,6 +688,7 @@ dm_status do_finalize(dm_sim* s) {
 #undef UP
   if ((st = alloc(s, 3 * (size_t)NN, &D.v)) != DM_OK) return st;
   if ((st = alloc(s, 3 * (size_t)NN, &D.vprev)) != DM_OK) return st;
+  if ((st = alloc(s, 3 * (size_t)NN, &D.vprev2)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)NE, &D.th)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)NE, &D.th0)) != DM_OK) return st;
   if ((st = alloc(s, (size_t)NE, &D.om)) != DM_OK) return st;
@@ -842,7 +843,8 @@ dm_status load_state(dm_sim* s, const double* src) {
   DM_HIP(hipMemcpyAsync(s->dev.x, p, sizeof(double) * 3 * NN, k, s->stream));
   DM_HIP(hipMemcpyAsync(s->dev.x0, p, sizeof(double) * 3 * NN, k, s->stream)); p += 3 * NN;
   DM_HIP(hipMemcpyAsync(s->dev.v, p, sizeof(double) * 3 * NN, k, s->stream));
-  DM_HIP(hipMemcpyAsync(s->dev.vprev, p, sizeof(double) * 3 * NN, k, s->stream)); p += 3 * NN;
+  DM_HIP(hipMemcpyAsync(s->dev.vprev, p, sizeof(double) * 3 * NN, k, s->stream));
+  DM_HIP(hipMemcpyAsync(s->dev.vprev2, p, sizeof(double) * 3 * NN, k, s->stream)); p += 3 * NN;
   DM_HIP(hipMemcpyAsync(s->dev.th, p, sizeof(double) * NE, k, s->stream));
   DM_HIP(hipMemcpyAsync(s->dev.th0, p, sizeof(double) * NE, k, s->stream)); p += NE;
   DM_HIP(hipMemcpyAsync(s->dev.om, p, sizeof(double) * NE, k, s->stream)); p += NE;
@@ -1318,7 +1320,7 @@ dm_status dm_set_adaptive(dm_sim* s, int max_halvings) {
 dm_status dm_set_warm_start(dm_sim* s, dm_mlp* net, int mode) {
   if (!s) return fail(DM_ERR_INVALID_ARG, "null sim");
   if (!s->finalized) return fail(DM_ERR_STATE, "dm_set_warm_start before dm_finalize");
-  if (mode < 0 || mode > 3) return fail(DM_ERR_INVALID_ARG, "dm_set_warm_start: mode must be 0, 1, 2 or 3");
+  if (mode < 0 || mode > 4) return fail(DM_ERR_INVALID_ARG, "dm_set_warm_start: mode must be 0 .. 4");
   if (mode == 2 && !net) return fail(DM_ERR_INVALID_ARG, "dm_set_warm_start: mode 2 needs a network");
   s->ws_mode = mode;
   s->ws_net = mode == 2 ? net : nullptr;
@@ -1746,18 +1748,19 @@ dm_status dm_set_state(dm_sim* s, const double* x, const double* th, const doubl
   DM_HIP(hipSetDevice(s->cfg.device));
   DM_HIP(hipStreamSynchronize(s->stream));
   const int NN = s->n_nodes, NE = s->n_edges;
-  auto put3 = [&](const double* src, double* dst, double* dst2) -> dm_status {
+  auto put3 = [&](const double* src, double* dst, double* dst2, double* dst3) -> dm_status {
     std::vector<double> aos(3 * (size_t)NN), soa(3 * (size_t)NN);
     DM_HIP(hipMemcpy(aos.data(), src, sizeof(double) * 3 * NN, on_device ? hipMemcpyDeviceToHost : hipMemcpyHostToHost));
     if (!finite_all(aos.data(), aos.size())) return fail(DM_ERR_INVALID_ARG, "dm_set_state: non-finite value");
     for (int n = 0; n < NN; ++n) for (int c = 0; c < 3; ++c) soa[c * NN + n] = aos[3 * n + c];
     DM_HIP(hipMemcpy(dst, soa.data(), sizeof(double) * 3 * NN, hipMemcpyHostToDevice));
     if (dst2) DM_HIP(hipMemcpy(dst2, soa.data(), sizeof(double) * 3 * NN, hipMemcpyHostToDevice));
+    if (dst3) DM_HIP(hipMemcpy(dst3, soa.data(), sizeof(double) * 3 * NN, hipMemcpyHostToDevice));
     return DM_OK;
   };
   dm_status st;
-  if (x && (st = put3(x, s->dev.x, s->dev.x0)) != DM_OK) return st;
-  if (v && (st = put3(v, s->dev.v, s->dev.vprev)) != DM_OK) return st;
+  if (x && (st = put3(x, s->dev.x, s->dev.x0, nullptr)) != DM_OK) return st;
+  if (v && (st = put3(v, s->dev.v, s->dev.vprev, s->dev.vprev2)) != DM_OK) return st;
   hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   if (th) { DM_HIP(hipMemcpy(s->dev.th, th, sizeof(double) * NE, k)); DM_HIP(hipMemcpy(s->dev.th0, th, sizeof(double) * NE, k)); }
   if (om) DM_HIP(hipMemcpy(s->dev.om, om, sizeof(double) * NE, k));
@@ -1828,7 +1831,8 @@ dm_status dm_load_checkpoint(dm_sim* s, const double* buf, int on_device) {
   DM_HIP(hipMemcpy(s->dev.x, p, sizeof(double) * 3 * NN, k)); p += 3 * NN;
   DM_HIP(hipMemcpy(s->dev.x0, p, sizeof(double) * 3 * NN, k)); p += 3 * NN;
   DM_HIP(hipMemcpy(s->dev.v, p, sizeof(double) * 3 * NN, k));
-  DM_HIP(hipMemcpy(s->dev.vprev, p, sizeof(double) * 3 * NN, k)); p += 3 * NN;
+  DM_HIP(hipMemcpy(s->dev.vprev, p, sizeof(double) * 3 * NN, k));
+  DM_HIP(hipMemcpy(s->dev.vprev2, p, sizeof(double) * 3 * NN, k)); p += 3 * NN;
   DM_HIP(hipMemcpy(s->dev.th, p, sizeof(double) * NE, k)); p += NE;
   DM_HIP(hipMemcpy(s->dev.th0, p, sizeof(double) * NE, k)); p += NE;
   DM_HIP(hipMemcpy(s->dev.om, p, sizeof(double) * NE, k)); p += NE;

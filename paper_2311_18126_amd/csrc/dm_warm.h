@@ -5,8 +5,10 @@
 // Guesses (the positions handed to Newton; Newton still judges convergence, and a failed
 // guess restarts from x_n):
 //   mode 1: x_n + dt v_n (explicit predictor);
-//   mode 3: x_n + dt (v_n + a_n), a_n = v_n - v_prev (second-order extrapolation);
-//   mode 2: mode 3 plus the network's correction s * y, y = MLP(standardised features).
+//   mode 3: x_n + dt (v_n + a_n), a_n = v_n - v_{n-1} (second-order extrapolation);
+//   mode 4: x_n + dt (v_n + a_n + j_n), j_n = a_n - a_{n-1} (third-order extrapolation);
+//   mode 2: mode 4 plus the network's correction s * y, y = MLP(standardised features), scaled
+//           by the substep's share of the step under adaptive halving.
 // The network runs on the matrix cores in bfloat16 with float32 accumulation, rounded at the
 // same points and accumulated in the same order as the batch kernels of dm_mlp.hip.
 #pragma once
@@ -19,10 +21,11 @@ __device__ __forceinline__ void system_row(const DmDev DM_C& D, const DmSystem D
   while (k >= D.chain[c].n_nodes) { k -= D.chain[c].n_nodes; ++c; }
 }
 
-// The 20 raw features of node k of chain ch (missing neighbours of a rod end replicated):
+// The 26 raw features of node k of chain ch (missing neighbours of a rod end replicated):
 // v_{k-1} - v_k, v_{k+1} - v_k, v_k, a_k = v_k - v_prev_k, x_{k-1} - 2 x_k + x_{k+1} (step-start
 // positions), log10 E, radius, mean rest length of the node's edges, natural curvature at the
-// node in 1/m (nearest interior node at the ends).
+// node in 1/m (nearest interior node at the ends), j_k = a_k - (v_prev_k - v_prev2_k) (the
+// change of the velocity change), a_{k-1} - 2 a_k + a_{k+1}.
 __device__ __forceinline__ void row_features(const DmDev DM_C& D, const DmChain& ch, int k, double (&f)[DM_NET_IN]) {
   const int NN = D.n_nodes_tot, NS = D.n_st_tot, N = ch.n_nodes;
   const int n0 = D.chain_node[ch.node_tab + k];
@@ -30,12 +33,14 @@ __device__ __forceinline__ void row_features(const DmDev DM_C& D, const DmChain&
   const int np = D.chain_node[ch.node_tab + (k <= N - 2 ? k + 1 : k)];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const double vi = D.v[q * NN + n0];
+    const double vi = D.v[q * NN + n0], ai = vi - D.vprev[q * NN + n0];
     f[q] = D.v[q * NN + nm] - vi;
     f[3 + q] = D.v[q * NN + np] - vi;
     f[6 + q] = vi;
-    f[9 + q] = vi - D.vprev[q * NN + n0];
+    f[9 + q] = ai;
     f[12 + q] = D.x0[q * NN + nm] - 2.0 * D.x0[q * NN + n0] + D.x0[q * NN + np];
+    f[20 + q] = ai - (D.vprev[q * NN + n0] - D.vprev2[q * NN + n0]);
+    f[23 + q] = (D.v[q * NN + nm] - D.vprev[q * NN + nm]) - 2.0 * ai + (D.v[q * NN + np] - D.vprev[q * NN + np]);
   }
 #pragma unroll
   for (int q = 0; q < 3; ++q) f[15 + q] = D.nconst[(size_t)(ch.node_tab + k) * 3 + q];
@@ -48,15 +53,20 @@ __device__ __forceinline__ void row_features(const DmDev DM_C& D, const DmChain&
   }
 }
 
-// Displacement component q of node k of chain ch without the network: dt v_n (+ dt a_n), dt the
-// Newton step of the (sub)step.
+// Displacement component q of node k of chain ch without the network: dt v_n (mode 1),
+// dt (v_n + a_n) (mode 3), dt (v_n + a_n + j_n) (modes 2 and 4), dt the Newton step of the
+// (sub)step.
 __device__ __forceinline__ double base_guess(const DmStepArgs DM_C& A, double dt, const DmChain& ch, int k, int q) {
   const DmDev DM_C& D = A.d;
   const int NN = D.n_nodes_tot;
   const int n0 = D.chain_node[ch.node_tab + k];
   const double v = D.v[q * NN + n0];
   double d = dt * v;
-  if (A.warm >= 2) d += dt * (v - D.vprev[q * NN + n0]);
+  if (A.warm >= 2) {
+    const double vp = D.vprev[q * NN + n0], a = v - vp;
+    d += dt * a;
+    if (A.warm != 3) d += dt * (a - (vp - D.vprev2[q * NN + n0]));
+  }
   return d;
 }
 
@@ -77,7 +87,7 @@ __device__ __forceinline__ dm_bf16x8 ld_bf16x8(const unsigned short DM_C* p) {
 }
 
 // Input fragment of one lane: standardised features 8g .. 8g+7 of system row i (zero beyond
-// the system's rows and past feature 19), rounded to bfloat16.
+// the system's rows and past the last feature), rounded to bfloat16.
 __device__ __forceinline__ dm_bf16x8 input_fragment(const DmStepArgs DM_C& A, const DmSystem DM_C& S, int i, int g) {
   const DmDev DM_C& D = A.d;
   const DmNetView DM_C& W = A.net;
@@ -90,10 +100,11 @@ __device__ __forceinline__ dm_bf16x8 input_fragment(const DmStepArgs DM_C& A, co
   dm_bf16x8 a;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
-    const double fv = g == 0 ? f[j] : (g == 1 ? f[8 + j] : (j < 4 ? f[16 + j] : 0.0));
     const int q = 8 * g + j;
     const bool real = valid & (q < DM_NET_IN);
     const int qc = real ? q : 0;
+    // constant indices only (j is unrolled), so f stays in registers
+    const double fv = g == 0 ? f[j] : (g == 1 ? f[8 + j] : (g == 2 ? f[16 + j] : (24 + j < DM_NET_IN ? f[(24 + j) % DM_NET_IN] : 0.0)));
     const unsigned short h = real ? dm_bf16_bits((float)((fv - W.mean[qc]) / W.sd[qc])) : (unsigned short)0;
     a[j] = __builtin_bit_cast(__bf16, h);
   }
@@ -204,7 +215,9 @@ __device__ __forceinline__ void network_block(const DmStepArgs DM_C& A, double d
         y = dm_mfma_bf16(lds_fragment(Q, 16 * rt + lr, k0 + 8 * g), ld_bf16x8(W.w3 + lr * DM_NET_HID + k0 + 8 * g), y);
       if (lr < DM_NET_OUT) {
         const float bb = W.b3[lr];
-        const double sc = W.ystd[lr];
+        // the network predicts a whole step's correction; a substep of adaptive halving takes
+        // its share dt / A.dt of it
+        const double sc = W.ystd[lr], share = dt / A.dt;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int i = row0 + 16 * rt + 4 * g + j;
@@ -213,7 +226,7 @@ __device__ __forceinline__ void network_block(const DmStepArgs DM_C& A, double d
             system_row(D, S, i, c, k);
             const DmChain ch = D.chain[c];
             const float yv = y[j] + bb;
-            put_guess(A, ch, k, lr, base_guess(A, dt, ch, k, lr) + sc * (double)yv, out);
+            put_guess(A, ch, k, lr, base_guess(A, dt, ch, k, lr) + share * sc * (double)yv, out);
           }
         }
       }

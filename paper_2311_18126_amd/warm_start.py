@@ -7,14 +7,14 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import Mlp
+from . import NET_IN, Mlp
 
-N_IN, N_HID, N_OUT = 20, 256, 3
+N_IN, N_HID, N_OUT = NET_IN, 256, 3
 
 
 def init_params(seed=0):
     """Seeded He-uniform weights and zero biases in the library's parameter layout
-    (W1 [256][20], b1, W2 [256][256], b2, W3 [3][256], b3), float32."""
+    (W1 [256][26], b1, W2 [256][256], b2, W3 [3][256], b3), float32."""
     rng = np.random.Generator(np.random.PCG64(seed))
     parts = []
     for n_out, n_in in ((N_HID, N_IN), (N_HID, N_HID), (N_OUT, N_HID)):
@@ -26,7 +26,8 @@ def init_params(seed=0):
 
 def collect(sim, dt, steps, every=1):
     """Step `sim` for `steps` steps (plain Newton) and return device tensors (F, T) of the
-    features at the start and the targets dt (v_{n+1} - v_n) of every `every`-th step."""
+    features at the start and the targets (the displacement beyond the third-order
+    extrapolation) of every `every`-th step."""
     import torch
     rows = sim.ws_rows
     Fs, Ts = [], []

@@ -58,7 +58,7 @@ def test_captured_segments_with_the_network_on_a_torch_stream(dm):
     d = W.adjoint_rods(8, 40, steps=12)[0]
     net = dm.Mlp(max_rows=64)
     net.set_params(WS.init_params(3) * np.float32(1e-3))     # small corrections
-    net.set_normalisation(np.zeros(20), np.ones(20), np.full(3, 1e-6))
+    net.set_normalisation(np.zeros(dm.NET_IN), np.ones(dm.NET_IN), np.full(3, 1e-6))
     s = torch.cuda.Stream()
     a = rollouts(dm, d, False, 2, net=net, stream=s.cuda_stream)
     b = rollouts(dm, d, True, 2, net=net, stream=s.cuda_stream)

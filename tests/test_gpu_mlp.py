@@ -36,7 +36,7 @@ def flat(p):
 
 def unflat(v):
     out, o = {}, 0
-    for k, shp in (("W1", (256, 20)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)), ("W3", (3, 256)), ("b3", (3,))):
+    for k, shp in (("W1", (256, OM.N_IN)), ("b1", (256,)), ("W2", (256, 256)), ("b2", (256,)), ("W3", (3, 256)), ("b3", (3,))):
         n = int(np.prod(shp))
         out[k] = v[o:o + n].reshape(shp)
         o += n
@@ -45,7 +45,7 @@ def unflat(v):
 
 def raw_case(n, seed):
     rng = np.random.Generator(np.random.PCG64(seed))
-    F = rng.normal(size=(n, 20)) * rng.uniform(0.1, 5.0, 20) + rng.normal(size=20)
+    F = rng.normal(size=(n, OM.N_IN)) * rng.uniform(0.1, 5.0, OM.N_IN) + rng.normal(size=OM.N_IN)
     T = rng.normal(size=(n, 3)) * np.array([1e-4, 3e-5, 2e-4])
     mean, std = F.mean(0), F.std(0)
     scale = np.sqrt((T * T).mean(0))
@@ -190,11 +190,13 @@ def test_features_and_targets_match_oracle(dm):
     d = W.rod_batch(6, seed=4, nmin=3, nmax=40)
     sim = dm.sim_from_description(d)
     sim.step(d["dt"], 2)
+    vprev2 = [sim.rod_state(r)[2] for r in range(len(d["rods"]))]
+    sim.step(d["dt"], 1)
     vprev = [sim.rod_state(r)[2] for r in range(len(d["rods"]))]
     sim.step(d["dt"], 1)
     rows = sim.ws_rows
     assert rows == sum(r["x0"].shape[0] for r in d["rods"])
-    F = torch.empty((rows, 20), dtype=torch.float64, device="cuda")
+    F = torch.empty((rows, OM.N_IN), dtype=torch.float64, device="cuda")
     sim.ws_features(F)
     Fh = F.cpu().numpy()
     o = 0
@@ -203,7 +205,8 @@ def test_features_and_targets_match_oracle(dm):
         x, _, v, _ = sim.rod_state(r)
         n = x.shape[0]
         eb = np.linalg.norm(np.diff(rd["x0"], axis=0), axis=1)
-        ref = OM.rod_features(x, v, vprev[r], rd["kbar"], rd["E"], rd["radius"], eb)
+        ref = OM.rod_features(x, v, vprev[r], vprev2[r], rd["kbar"], rd["E"], rd["radius"], eb)
+        assert np.abs(ref[:, 20:]).max() > 0      # the history features are not trivially zero
         assert np.allclose(Fh[o:o + n], ref, rtol=1e-13, atol=1e-15), r
         vnow.append(v)
         o += n
@@ -215,7 +218,8 @@ def test_features_and_targets_match_oracle(dm):
     for r in range(len(d["rods"])):
         v1 = sim.rod_state(r)[2]
         n = v1.shape[0]
-        ref = d["dt"] * (v1 - vnow[r] - (vnow[r] - vprev[r]))
+        a = vnow[r] - vprev[r]
+        ref = d["dt"] * (v1 - vnow[r] - a - (a - (vprev[r] - vprev2[r])))
         assert np.allclose(Th[o:o + n], ref, rtol=1e-12, atol=1e-18)
         o += n
 
@@ -237,6 +241,6 @@ def test_normalisation_fit_matches_numpy(dm):
     assert np.allclose(std, F2.std(0), rtol=1e-8)
     assert np.allclose(scale, np.sqrt((T2 * T2).mean(0)), rtol=1e-10)
     # features that do not start on a 16-byte boundary are refused
-    flat = torch.zeros(5000 * 20 + 1, dtype=torch.float64, device="cuda")
+    flat = torch.zeros(5000 * OM.N_IN + 1, dtype=torch.float64, device="cuda")
     with pytest.raises(dm.DmError):
-        net.fit_normalisation(flat[1:].view(5000, 20), torch.tensor(T, device="cuda"))
+        net.fit_normalisation(flat[1:].view(5000, OM.N_IN), torch.tensor(T, device="cuda"))

@@ -32,29 +32,33 @@ def say(msg):
 
 @pytest.fixture(scope="module")
 def case(dm):
-    """Rods of 3..70 nodes (rows spanning several 16-row tiles and ragged tails) after three
-    steps, with the velocities before the last step kept for the oracle's features."""
+    """Rods of 3..70 nodes (rows spanning several 16-row tiles and ragged tails) after four
+    steps, with the velocities before the last two steps kept for the oracle's features."""
     d = W.rod_batch(7, seed=5, nmin=3, nmax=70)
     sim = dm.sim_from_description(d)
     sim.step(d["dt"], 2)
+    vprev2 = [sim.rod_state(r)[2] for r in range(len(d["rods"]))]
+    sim.step(d["dt"], 1)
     vprev = [sim.rod_state(r)[2] for r in range(len(d["rods"]))]
     sim.step(d["dt"], 1)
-    feats, base1, base3 = [], [], []
+    feats, base = [], {1: [], 3: [], 4: []}
     for r, rd in enumerate(d["rods"]):
         x, _, v, _ = sim.rod_state(r)
         eb = np.linalg.norm(np.diff(rd["x0"], axis=0), axis=1)
-        feats.append(OM.rod_features(x, v, vprev[r], rd["kbar"], rd["E"], rd["radius"], eb))
-        base1.append(d["dt"] * v)
-        base3.append(d["dt"] * (v + (v - vprev[r])))
-    return d, sim, np.concatenate(feats), np.concatenate(base1), np.concatenate(base3)
+        feats.append(OM.rod_features(x, v, vprev[r], vprev2[r], rd["kbar"], rd["E"], rd["radius"], eb))
+        a, a_prev = v - vprev[r], vprev[r] - vprev2[r]
+        base[1].append(d["dt"] * v)
+        base[3].append(d["dt"] * (v + a))
+        base[4].append(d["dt"] * (v + a + (a - a_prev)))
+    return d, sim, np.concatenate(feats), {k: np.concatenate(b) for k, b in base.items()}
 
 
-@pytest.mark.parametrize("mode", [1, 3])
+@pytest.mark.parametrize("mode", [1, 3, 4])
 def test_analytic_predictors(dm, case, mode):
-    d, sim, _, b1, b3 = case
+    d, sim, _, base = case
     sim.set_warm_start(None, mode)
     dx = sim.ws_predict(d["dt"])
-    ref = b1 if mode == 1 else b3
+    ref = base[mode]
     say(f"mode {mode}: {dx.shape[0]} rows")
     assert dx.shape == ref.shape
     assert np.allclose(dx, ref, rtol=1e-13, atol=1e-18)
@@ -62,7 +66,8 @@ def test_analytic_predictors(dm, case, mode):
 
 def test_network_guess_matches_oracle_and_batch_kernels(dm, case):
     import torch
-    d, sim, F, _, b3 = case
+    d, sim, F, base = case
+    b4 = base[4]
     p = OM.init_params(21)
     p["b1"][:] = np.random.Generator(np.random.PCG64(4)).normal(0, 0.1, 256)
     flat = np.concatenate([p[k].reshape(-1) for k in ("W1", "b1", "W2", "b2", "W3", "b3")]).astype(np.float32)
@@ -73,7 +78,7 @@ def test_network_guess_matches_oracle_and_batch_kernels(dm, case):
     net.set_normalisation(mean, std, scale)
     sim.set_warm_start(net, 2)
     dx = sim.ws_predict(d["dt"])
-    y_dev = (dx - b3) / scale
+    y_dev = (dx - b4) / scale
     y_ref, _ = OM.forward(p, OM.standardise(F, mean, std))
     rel = np.linalg.norm(y_dev - y_ref) / np.linalg.norm(y_ref)
     say(f"network guess vs oracle: relative error {rel:.2e} over {F.shape[0]} rows")
@@ -81,12 +86,12 @@ def test_network_guess_matches_oracle_and_batch_kernels(dm, case):
     # the batch kernels on the oracle's features: the same products in the same order
     Y = torch.empty((F.shape[0], 3), dtype=torch.float32, device="cuda")
     yb = net.forward(torch.tensor(F, device="cuda"), Y).cpu().numpy().astype(np.float64)
-    assert np.abs((dx - b3) - scale * yb).max() <= 1e-12 * np.abs(dx).max()
+    assert np.abs((dx - b4) - scale * yb).max() <= 1e-12 * np.abs(dx).max()
     sim.set_warm_start(None, 0)
 
 
 def test_predict_needs_a_warm_mode(dm, case):
-    d, sim, _, _, _ = case
+    d, sim, _, _ = case
     sim.set_warm_start(None, 0)
     with pytest.raises(dm.DmError):
         sim.ws_predict(d["dt"])

@@ -65,20 +65,38 @@ def test_explicit_predictor_gives_the_same_solution(dm):
     say(f"iterations plain {s0['iters'].sum()} explicit predictor {s1['iters'].sum()}")
 
 
-def test_trained_network_cuts_newton_iterations_on_fresh_rods(dm, trained):
+@pytest.fixture(scope="module")
+def iterations(dm, trained):
     """Fresh rods (N ~ U{50..400}, seed 3), 60 steps from rest: Newton iterations per step of
-    the plain step, the analytic predictors, and the network on top of the second-order
-    extrapolation; the network must beat the plain step at the same residual."""
+    the plain step, the analytic predictors and the network on top of the third-order
+    extrapolation, all at the same residual."""
     d = W.warm_start_eval(64, steps=60)
     x0, s0 = run(dm, d, 60)
-    _, s1 = run(dm, d, 60, mode=1)
-    _, s3 = run(dm, d, 60, mode=3)
-    x2, s2 = run(dm, d, 60, net=trained, mode=2)
-    i0, i1, i3, i2 = (s["iters"].sum() / s["iters"].size / 60 for s in (s0, s1, s3, s2))
-    say(f"Newton iterations per step: plain {i0:.3f}, explicit predictor {i1:.3f}, second-order "
-        f"extrapolation {i3:.3f}, network {i2:.3f}; fallbacks {s2['fallbacks'].sum()}")
+    out = {"plain": s0}
+    for name, mode in (("explicit", 1), ("second_order", 3), ("third_order", 4)):
+        out[name] = run(dm, d, 60, mode=mode)[1]
+    x2, out["network"] = run(dm, d, 60, net=trained, mode=2)
     assert rel(x2, x0) < 1e-8
-    assert i2 < 0.95 * i0
+    it = {k: s["iters"].sum() / s["iters"].size / 60 for k, s in out.items()}
+    say("Newton iterations per step: " + ", ".join(f"{k} {v:.3f}" for k, v in it.items())
+        + f"; network fallbacks {out['network']['fallbacks'].sum()}")
+    return it, out
+
+
+def test_trained_network_cuts_newton_iterations_on_fresh_rods(dm, iterations):
+    it, out = iterations
+    assert it["network"] < 0.95 * it["plain"]
+    assert out["network"]["fallbacks"].sum() == 0
+
+
+@pytest.mark.xfail(strict=False, reason=(
+    "measured on MI355X: the network and the analytic extrapolations all take ~2.3 Newton "
+    "iterations per step (second order 2.303, third order 2.324, network 2.321 on 1024 fresh "
+    "rods); in the oracle even the exact end-of-step positions as the guess leave 2 iterations, "
+    "so a position guess cannot cut the count by 10 %"))
+def test_network_beats_the_extrapolation_by_a_tenth(dm, iterations):
+    it, _ = iterations
+    assert it["network"] <= 0.9 * it["second_order"]
 
 
 def test_a_failing_guess_falls_back_to_the_plain_solve(dm):
@@ -88,7 +106,7 @@ def test_a_failing_guess_falls_back_to_the_plain_solve(dm):
     from paper_2311_18126_amd import warm_start as WS
     net = dm.Mlp(max_rows=20_000)
     net.set_params(WS.init_params(1))     # untrained: metre-scale, node-to-node random guesses
-    net.set_normalisation(np.zeros(20), np.ones(20), np.full(3, 1.0))
+    net.set_normalisation(np.zeros(dm.NET_IN), np.ones(dm.NET_IN), np.full(3, 1.0))
     d = W.warm_start_eval(8, steps=3)
     x0, _ = run(dm, d, 3)
     sim = dm.sim_from_description(d, warm_max_iter=2)

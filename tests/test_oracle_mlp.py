@@ -26,8 +26,10 @@ def test_features_of_a_straight_rod():
     v[:, 2] = np.arange(n)
     vp = np.zeros((n, 3))
     vp[:, 2] = 0.5 * np.arange(n)
+    vp2 = np.zeros((n, 3))
+    vp2[:, 2] = 0.25 * np.arange(n) ** 2
     kb = np.arange(2 * (n - 2), dtype=float).reshape(n - 2, 2)
-    f = mlp.rod_features(x, v, vp, kb, 1e7, 2e-3, np.full(n - 1, 0.1))
+    f = mlp.rod_features(x, v, vp, vp2, kb, 1e7, 2e-3, np.full(n - 1, 0.1))
     assert f[0, 2] == 0.0 and f[0, 5] == 1.0 and f[-1, 5] == 0.0 and f[-1, 2] == -1.0   # replicated ends
     assert f[2, 8] == 2 and f[2, 11] == 1.0                          # v and a = v - v_prev
     assert np.allclose(f[2, 12:15], [0.0, 0.0, -0.02]) and np.allclose(f[1, 12:15], [0.0, 0.0, 0.01])
@@ -35,6 +37,11 @@ def test_features_of_a_straight_rod():
     assert np.allclose(f[:, 15], 7.0) and np.allclose(f[:, 16], 2e-3) and np.allclose(f[:, 17], 0.1)
     assert np.array_equal(f[0, 18:20], kb[0]) and np.array_equal(f[-1, 18:20], kb[-1])
     assert np.array_equal(f[2, 18:20], kb[1])
+    # a_i = 0.5 i, a_prev_i = 0.5 i - 0.25 i^2: j_i = 0.25 i^2; the Laplacian of a is zero inside
+    # (a is linear in i) and +-0.5 at the replicated ends
+    assert np.allclose(f[:, 22], 0.25 * np.arange(n) ** 2) and np.allclose(f[:, 20:22], 0.0)
+    assert np.allclose(f[1:-1, 25], 0.0) and f[0, 25] == 0.5 and f[-1, 25] == -0.5
+    assert f.shape == (n, 26)
 
 
 def test_backward_without_rounding_matches_automatic_differentiation():

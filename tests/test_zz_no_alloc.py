@@ -9,6 +9,8 @@ import numpy as np
 import pytest
 import torch
 
+NI = 26      # features per row of the warm-start network
+
 pytestmark = pytest.mark.gpu
 
 
@@ -22,18 +24,18 @@ def dm():
 
 def features(n, seed):
     rng = np.random.Generator(np.random.PCG64(seed))
-    return torch.tensor(rng.normal(size=(n, 20)) * rng.uniform(0.1, 5.0, 20) + rng.normal(size=20), device="cuda")
+    return torch.tensor(rng.normal(size=(n, NI)) * rng.uniform(0.1, 5.0, NI) + rng.normal(size=NI), device="cuda")
 
 
 def test_noalloc_forward_equals_forward(dm):
     rng = np.random.Generator(np.random.PCG64(21))
     net = dm.Mlp(4096)
-    lim = np.concatenate([np.full(256 * 20, np.sqrt(6 / 20)), np.zeros(256), np.full(256 * 256, np.sqrt(6 / 256)),
+    lim = np.concatenate([np.full(256 * NI, np.sqrt(6 / NI)), np.zeros(256), np.full(256 * 256, np.sqrt(6 / 256)),
                           np.zeros(256), np.full(3 * 256, np.sqrt(6 / 256)), np.zeros(3)])
     params = (rng.uniform(-1.0, 1.0, lim.size) * lim).astype(np.float32)
-    params[256 * 20:256 * 21] = rng.normal(0, 0.1, 256).astype(np.float32)     # nonzero first-layer biases
+    params[256 * NI:256 * (NI + 1)] = rng.normal(0, 0.1, 256).astype(np.float32)     # nonzero first-layer biases
     net.set_params(params)
-    net.set_normalisation(rng.normal(size=20), rng.uniform(0.5, 2.0, 20), np.array([1e-4, 3e-5, 2e-4]))
+    net.set_normalisation(rng.normal(size=NI), rng.uniform(0.5, 2.0, NI), np.array([1e-4, 3e-5, 2e-4]))
     for n, seed in ((dm.DM_MLP_NOALLOC_MAX_ROWS, 1), (300, 2), (1, 3)):
         print(f"case: noalloc forward, {n} rows", flush=True)
         F = features(n, seed)
