@@ -40,8 +40,7 @@ INFER_FLOPS_PER_ROW = 2 * (26 * 256 + 256 * 256 + 256 * 3)
 TRAIN_FLOPS_PER_ROW = 2 * INFER_FLOPS_PER_ROW + 2 * (256 * 3 + 256 * 256)
 KERNEL_SOURCES = ["paper_2311_18126_amd/csrc/dm_kernels.hip", "paper_2311_18126_amd/csrc/dm_math.h",
                   "paper_2311_18126_amd/csrc/dm_layout.h", "paper_2311_18126_amd/csrc/dm_warm.h",
-                  "paper_2311_18126_amd/csrc/dm_bf16.h",
-                  "paper_2311_18126_amd/build.py"]      # the compiler flags shape the kernel too
+                  "paper_2311_18126_amd/csrc/dm_bf16.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dm_step_kernel_rod_batch_traffic.json")
 
 
@@ -86,10 +85,13 @@ def star_iteration_flops(limbs=6, limb_nodes=30, count=None):
 
 
 def kernel_hash():
+    """Hash of the step kernel's sources and of the compiler flags they are built with."""
+    from paper_2311_18126_amd import build as B
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
+    h.update(" ".join(f for f in B.FLAGS if not f.startswith(("-I", "/"))).encode())
     return h.hexdigest()[:16]
 
 

@@ -803,10 +803,12 @@ __device__ __forceinline__ void elim_step(double (&w)[DM_HS], const double (&col
   const bool act = MASK ? k < V.count : true;
   const double u = from_half(w[tT], hT);              // row k's entry in this lane's column
   const double piv = row_bcast<T>(u);
-  if (act && !__builtin_isnormal(piv)) bad = 1;       // zero, subnormal, infinite or NaN
-  // the lane holding slot T of role T keeps the assembled diagonal of the row it pivots next
+  // the lane holding slot T of role T keeps the assembled diagonal of the row it pivots next;
+  // a pivot that is zero, subnormal, infinite or NaN, or small against that diagonal, marks
+  // the matrix (bitwise logic: no branch on the serial chain)
   const bool dlane = (l == T) & (h == hT);
-  if (act && dlane && !(fabs(piv) >= DM_PIVOT_TAU * fabs(dg))) bad = 1;
+  const bool small = dlane & !(fabs(piv) >= DM_PIVOT_TAU * fabs(dg));
+  bad |= (int)(act & (!__builtin_isnormal(piv) | small));
   dg = dlane ? col[tT] : dg;                          // the diagonal of row k + 11
   const double inv = recip(piv);
   double cv[DM_HS];
