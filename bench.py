@@ -489,6 +489,46 @@ def config_table(dm, log):
         print(json.dumps(r), flush=True)
 
 
+# per contact pair, the terms kernel's algorithmic traffic: reads the pair (2 int32), the four
+# nodes' positions now and at the step start (4 x 2 x 24 B), their edge tables (2 x (2 int32 +
+# radius)); writes the energy, gradient (12), Hessian (144) and friction forces (12) in float64
+CONTACT_TERMS_BYTES_PER_PAIR = 8 + 192 + 2 * 16 + 8 * (1 + 12 + 144 + 12)
+
+
+def contact_section(dm, reps=10):
+    """Edge-edge contact of the entanglement gripper's scenes (4096 tangles of five 60-node
+    fingers): detection (broad and narrow phase) and the pair terms (energy, gradient, Hessian,
+    friction), each kernel timed by HIP events on the handle's stream."""
+    import torch
+
+    import workloads as W
+    d = W.contact_tangle(4096)
+    c = dm.Contact.from_rods(d["rods"], d["groups"], d["delta"], 1024,
+                             stream=torch.cuda.current_stream().cuda_stream)
+    x = torch.tensor(np.concatenate([r[0] for r in d["rods"]]), device="cuda")
+    xp = torch.tensor(d["x_prev"], device="cuda")
+    edges = sum(r[0].shape[0] - 1 for r in d["rods"])
+    pairs, dst, counts, total = c.find(x)
+    c.terms(x, pairs, counts, d["k_c"], x_prev=xp, dt=d["dt"], mu=d["mu"], nu=d["nu"], friction=True)
+    tf, tt = [], []
+    for _ in range(reps):
+        c.find(x)
+        tf.append(c.last_find_ms)
+        c.terms(x, pairs, counts, d["k_c"], x_prev=xp, dt=d["dt"], mu=d["mu"], nu=d["nu"], friction=True)
+        tt.append(c.last_terms_ms)
+    mf, mt = float(np.mean(tf)), float(np.mean(tt))
+    nbytes = CONTACT_TERMS_BYTES_PER_PAIR * total
+    out = {"workload": "4096 tangles of the entanglement gripper: 5 fingers x 60 nodes, h = 5 mm, delta = 5e-4 m "
+                       "(seed 7)", "edges": int(edges), "pairs": int(total),
+           "detection_ms": mf, "detection_edges_per_s": edges / (mf * 1e-3),
+           "terms_ms": mt, "terms_pairs_per_s": total / (mt * 1e-3),
+           "terms_roofline": {"bound": "hbm", "achieved": nbytes / (mt * 1e-3) / 1e9, "peak": 8000.0,
+                              "unit": "GB/s", "frac": nbytes / (mt * 1e-3) / 1e9 / 8000.0,
+                              "bytes_per_pair": CONTACT_TERMS_BYTES_PER_PAIR}}
+    c.close()
+    return out
+
+
 def real2sim_section(dm, n_robots=1024, n_configs=8, tol=1e-3, max_iter=200):
     """Alg. 1 (Real2Sim section) on a batch of two-limb manipulators with the paper's
     parameters: the target limb curvatures of each configuration are those the simulated
@@ -636,6 +676,7 @@ def main():
         out["midpoint"] = midpoint_section(dm, args.steps)
         out["adjoint"] = adjoint_section(dm)
         out["real2sim"] = real2sim_section(dm)
+        out["contact"] = contact_section(dm)
     if not args.no_per_rod:
         out["per_rod_plain_value"] = per_rod_baseline(dm, desc, min(args.steps, 20))
     if not args.no_cpu_baseline:

@@ -281,6 +281,55 @@ dm_status dm_fit_limb_curvatures(dm_sim* sim, double dt, int n_settle, int n_con
                                  double alpha0, double tol, int max_iter, double* kbar_traj, int* steps,
                                  double* losses);
 
+/* ---- Edge-edge contact (Contact and Friction subsection, Eq. 10-13) ----------------------
+ * The Implicit Contact Model between edges: contact energy k_c E_c(D) (Eq. 10, K1 = 15/delta,
+ * k_c a stiffness the equation leaves out), D the minimum distance between two edges (as
+ * segments), C = h_i + h_j the centreline distance at which contact starts (2h within one rod),
+ * contact force -dE/dx (Eq. 11) and friction (Eq. 12-13).  These entry points detect the pairs
+ * of a set of edges and evaluate each pair's terms; the implicit step does not use them yet
+ * (edge-edge contact couples DOFs outside the banded structure of a rod).
+ *
+ * Edges are grouped: pairs are only sought inside a group (a scene of rods that may touch);
+ * a group holds at most DM_CONTACT_MAX_GROUP_EDGES edges.  Two edges of one rod (same `rod`
+ * value) whose rest arclength gap -- arc0 of the later edge minus arc0 + ebar of the earlier --
+ * is below h_i + h_j + delta never form a pair (they would touch in the rest shape).  A pair is
+ * every other pair of one group with D < h_i + h_j + delta. */
+#define DM_CONTACT_MAX_GROUP_EDGES 2048
+#define DM_CONTACT_MAX_PAIRS_PER_GROUP 2048
+typedef struct dm_contact dm_contact;
+/* Tables (host, copied): edges [n_edges][2] node indices into positions [n_nodes][3], rod id
+ * [n_edges], arc0 [n_edges] rest arclength of the edge's rod at its first node, ebar
+ * [n_edges] rest lengths (> 0), radius [n_edges] (> 0); group_start [n_groups + 1] ascending,
+ * 0 .. n_edges, each group's edges contiguous; delta > 0 (m); pair_capacity: pair slots per
+ * group, 1 .. DM_CONTACT_MAX_PAIRS_PER_GROUP.  The handle works on `device` and `stream`. */
+dm_status dm_contact_create(int device, void* stream, int n_nodes, int n_edges, const int* edges, const int* rod,
+                            const double* arc0, const double* ebar, const double* radius, int n_groups,
+                            const int* group_start, double delta, int pair_capacity, dm_contact** out);
+/* Pairs at positions x [n_nodes][3] (device).  Outputs (device): pairs [n_groups][cap][2] global
+ * edge indices i < j, sorted by (i, j) within a group; dst [n_groups][cap][3] = D, s, t (the
+ * closest points a + s (b - a) on edge i and c + t (d - c) on edge j; for parallel edges one of
+ * the equally close pairs of points); counts [n_groups] pairs per group; total (host, may be
+ * NULL) the sum.  A group with more pairs than cap gives DM_ERR_INVALID_ARG: its count is
+ * exact, its slots hold an unspecified subset. */
+dm_status dm_contact_find(dm_contact* c, const double* x, int* pairs, double* dst, int* counts, int* total);
+/* Per pair of the slots of dm_contact_find (pairs, counts as it wrote them), at positions x:
+ * energy [n_groups][cap] = k_c E_c(D); grad [n_groups][12][cap], the gradient with respect to
+ * the 12 coordinates (edge i's nodes a, b, edge j's c, d, x y z each; component-major per
+ * group, so consecutive pairs are consecutive in memory); hess [n_groups][144][cap] (row-major
+ * 12 x 12 per pair; NULL to skip); friction [n_groups][12][cap] (NULL to skip) the friction
+ * forces of Eq. 12-13 on the four nodes with u the tangential relative velocity of the closest
+ * points over the step from x_prev (device [n_nodes][3], the step start; no friction if
+ * NULL), dt > 0, mu >= 0, nu > 0.  Slots beyond a group's count are not written.  At D = 0
+ * the direction is undefined and the gradient, Hessian and friction are zero. */
+dm_status dm_contact_terms(dm_contact* c, const double* x, const double* x_prev, double dt, double k_c, double mu,
+                           double nu, const int* pairs, const int* counts, double* energy, double* grad, double* hess,
+                           double* friction);
+/* Duration in ms of the last detection (which = 0) or terms (1) kernel, from HIP events on the
+ * handle's stream. */
+double dm_contact_last_ms(const dm_contact* c, int which);
+const char* dm_contact_last_error(void);
+void dm_contact_destroy(dm_contact* c);
+
 /* ---- Learned warm start of the Newton solve ----------------------------------------------
  * Not part of the paper's method: a small network predicts each node's displacement over a
  * step and the prediction is Newton's initial guess (Eq. 16 is still iterated to newton_tol,

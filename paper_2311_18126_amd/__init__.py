@@ -100,6 +100,14 @@ _SIGS = {
     "dm_mlp_train_step": (c_int, [c_void_p, c_void_p, c_void_p, c_int, c_float, _DP]),
     "dm_mlp_train_epoch": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_int, c_int, c_float, _DP]),
     "dm_mlp_last_error": (c_char_p, []),
+    "dm_contact_create": (c_int, [c_int, c_void_p, c_int, c_int, _IP, _IP, _DP, _DP, _DP, c_int, _IP, c_double, c_int,
+                                  POINTER(c_void_p)]),
+    "dm_contact_find": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, POINTER(c_int)]),
+    "dm_contact_terms": (c_int, [c_void_p, c_void_p, c_void_p, c_double, c_double, c_double, c_double, c_void_p,
+                                 c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "dm_contact_last_ms": (c_double, [c_void_p, c_int]),
+    "dm_contact_last_error": (c_char_p, []),
+    "dm_contact_destroy": (None, [c_void_p]),
     "dm_mlp_destroy": (None, [c_void_p]),
     "dm_ws_rows": (c_int, [c_void_p]),
     "dm_ws_features": (c_int, [c_void_p, c_void_p]),
@@ -136,7 +144,10 @@ def lib():
 
 class DmError(RuntimeError):
     def __init__(self, status, where):
-        msg = lib().dm_last_error().decode(errors="replace")
+        # each part of the library keeps its own last message
+        src = (lib().dm_mlp_last_error if where.startswith("dm_mlp")
+               else lib().dm_contact_last_error if where.startswith("dm_contact") else lib().dm_last_error)
+        msg = src().decode(errors="replace")
         super().__init__(f"{where}: status {status}: {msg}")
         self.status = status
 
@@ -665,6 +676,109 @@ class Mlp:
         _check(lib().dm_mlp_train_epoch(self._h, F.data_ptr(), T.data_ptr(), perm.data_ptr(), n, int(batch), lr,
                                         ctypes.byref(loss)), "dm_mlp_train_epoch")
         return loss.value
+
+
+class Contact:
+    """Edge-edge contact (dm_contact_*): pair detection inside groups of edges and each pair's
+    energy k_c E_c(D) (Eq. 10), gradient, Hessian and friction (Eq. 12-13).  Positions are
+    float64 device tensors (n_nodes, 3); outputs are device tensors in the library's layouts."""
+
+    def __init__(self, n_nodes, edges, rod, arc0, ebar, radius, group_start, delta, pair_capacity,
+                 device=0, stream=None):
+        e = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+        ne = e.shape[0]
+        r = np.ascontiguousarray(rod, dtype=np.int32).reshape(ne)
+        a0, eb, rad = (_f64(v, (ne,)) for v in (arc0, ebar, radius))
+        gs = np.ascontiguousarray(group_start, dtype=np.int32)
+        h = c_void_p()
+        _check(lib().dm_contact_create(int(device), stream, int(n_nodes), ne, e.ctypes.data_as(_IP),
+                                       r.ctypes.data_as(_IP), _dp(a0), _dp(eb), _dp(rad), int(gs.size - 1),
+                                       gs.ctypes.data_as(_IP), float(delta), int(pair_capacity), ctypes.byref(h)),
+               "dm_contact_create")
+        self._h = h
+        self.n_nodes, self.n_edges, self.n_groups, self.cap = int(n_nodes), ne, int(gs.size - 1), int(pair_capacity)
+        self.device = device
+
+    @staticmethod
+    def from_rods(rods, groups, delta, pair_capacity, device=0, stream=None):
+        """rods: [(x0 (N, 3), radius), ...] numbered rod after rod (nodes and edges in order);
+        groups: the number of rods in each group, in order.  Rest lengths and arclengths come
+        from x0."""
+        edges, rod, arc0, ebar, radius, gstart = [], [], [], [], [], [0]
+        off, k = 0, 0
+        for gsize in groups:
+            for _ in range(gsize):
+                x0, h = rods[k]
+                x0 = np.asarray(x0, dtype=np.float64)
+                eb = np.linalg.norm(np.diff(x0, axis=0), axis=1)
+                a = np.concatenate([[0.0], np.cumsum(eb)[:-1]])
+                for j in range(x0.shape[0] - 1):
+                    edges.append((off + j, off + j + 1))
+                    rod.append(k)
+                    arc0.append(a[j])
+                    ebar.append(eb[j])
+                    radius.append(h)
+                off += x0.shape[0]
+                k += 1
+            gstart.append(len(edges))
+        return Contact(off, edges, rod, arc0, ebar, radius, gstart, delta, pair_capacity, device, stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().dm_contact_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _x(self, x):
+        import torch
+        if not (x.is_cuda and x.dtype == torch.float64 and x.is_contiguous() and tuple(x.shape) == (self.n_nodes, 3)):
+            raise ValueError(f"positions: contiguous float64 device tensor ({self.n_nodes}, 3)")
+        return x
+
+    def find(self, x):
+        """Pairs at positions x: (pairs [G, cap, 2] int32, dst [G, cap, 3] = D, s, t,
+        counts [G] int32, total).  Raises DmError when a group exceeds the capacity."""
+        import torch
+        x = self._x(x)
+        G, cap = self.n_groups, self.cap
+        pairs = torch.zeros((G, cap, 2), dtype=torch.int32, device=x.device)
+        dst = torch.zeros((G, cap, 3), dtype=torch.float64, device=x.device)
+        counts = torch.zeros((G,), dtype=torch.int32, device=x.device)
+        tot = c_int()
+        _check(lib().dm_contact_find(self._h, x.data_ptr(), pairs.data_ptr(), dst.data_ptr(), counts.data_ptr(),
+                                     ctypes.byref(tot)), "dm_contact_find")
+        return pairs, dst, counts, tot.value
+
+    def terms(self, x, pairs, counts, k_c, x_prev=None, dt=0.0, mu=0.0, nu=1.0, hessian=True, friction=False):
+        """Per pair slot: energy [G, cap], gradient [G, 12, cap], Hessian [G, 144, cap] (or
+        None), friction forces [G, 12, cap] (or None; needs x_prev, dt, mu, nu)."""
+        import torch
+        x = self._x(x)
+        G, cap = self.n_groups, self.cap
+        z = dict(dtype=torch.float64, device=x.device)
+        energy = torch.zeros((G, cap), **z)
+        grad = torch.zeros((G, 12, cap), **z)
+        hess = torch.zeros((G, 144, cap), **z) if hessian else None
+        fric = torch.zeros((G, 12, cap), **z) if friction else None
+        xp = self._x(x_prev).data_ptr() if x_prev is not None else None
+        _check(lib().dm_contact_terms(self._h, x.data_ptr(), xp, float(dt), float(k_c), float(mu), float(nu),
+                                      pairs.data_ptr(), counts.data_ptr(), energy.data_ptr(), grad.data_ptr(),
+                                      hess.data_ptr() if hess is not None else None,
+                                      fric.data_ptr() if fric is not None else None), "dm_contact_terms")
+        return energy, grad, hess, fric
+
+    @property
+    def last_find_ms(self):
+        return lib().dm_contact_last_ms(self._h, 0)
+
+    @property
+    def last_terms_ms(self):
+        return lib().dm_contact_last_ms(self._h, 1)
 
 
 def _is_cuda_tensor(a):

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdmrod.so")
 PEAKS = os.path.join(HERE, "dm_peaks")
 FLOPS = os.path.join(HERE, "dm_flops")
-SOURCES = ["dm_kernels.hip", "dm_mlp.hip", "dm_runtime.cpp"]
+SOURCES = ["dm_kernels.hip", "dm_mlp.hip", "dm_contact.hip", "dm_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          # keep the compiler from forming packed FP32 instructions

@@ -224,6 +224,40 @@ def paper_friction(push: float = 5.0, dt: float = 5e-3, steps: int = 300, n_node
     return d
 
 
+def contact_tangle(n_scenes: int = 4096, seed: int = 7, fingers: int = 5, n_nodes: int = 60,
+                   length: float = 0.3, radius: float = 5e-3, density: float = 1200.0) -> dict:
+    """Scenes of the validation section's entanglement gripper (five fingers of L = 0.3 m,
+    h = 5 mm, rho = 1200, N = 60; delta = 5e-4 m, nu = 1e-3 m/s, mu = 0.5) in a coiled, tangled
+    state: finger k of a scene is a helix about the scene's vertical axis, hanging from height
+    0, pitch ~ U(15, 30) mm, phase 2 pi k / fingers + U(-0.3, 0.3), on nested cylinders whose
+    radii start at U(20, 25) mm and grow by U(9.6, 10.4) mm from finger to finger (so the coils
+    of neighbouring fingers touch where they cross), with N(0, 0.3 mm) jitter on every node;
+    scenes are 1 m apart along x.  The state one
+    step (dt = 1e-3 s) earlier, x_prev, differs by N(0, 1 cm/s) velocities per node.  Contact
+    stiffness k_c = (node mass) g / delta, the floor's choice.  Returns {"rods": [(x (N, 3),
+    radius), ...] scene after scene, "groups": [fingers] * n_scenes, "x_prev": (total nodes, 3),
+    "delta", "nu", "mu", "k_c", "dt"}."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rods, prev = [], []
+    for sc in range(n_scenes):
+        R = rng.uniform(0.020, 0.025)
+        for k in range(fingers):
+            if k > 0:
+                R += rng.uniform(0.0096, 0.0104)
+            p = rng.uniform(0.015, 0.030)
+            ph = 2.0 * math.pi * k / fingers + rng.uniform(-0.3, 0.3)
+            per_turn = math.hypot(2.0 * math.pi * R, p)
+            phi = ph + np.linspace(0.0, 2.0 * math.pi * length / per_turn, n_nodes)
+            x = np.stack([R * np.cos(phi) + 1.0 * sc, R * np.sin(phi), -p * (phi - ph) / (2.0 * math.pi)], 1)
+            x = x + rng.normal(0.0, 3e-4, size=x.shape)
+            rods.append((x, radius))
+            prev.append(x - 1e-3 * rng.normal(0.0, 0.01, size=x.shape))
+    delta = 5e-4
+    m_node = density * math.pi * radius ** 2 * length / (n_nodes - 1)
+    return {"rods": rods, "groups": [fingers] * n_scenes, "x_prev": np.concatenate(prev), "delta": delta,
+            "nu": 1e-3, "mu": 0.5, "k_c": m_node * 9.8 / delta, "dt": 1e-3}
+
+
 def subset(desc: dict, rod_ids) -> dict:
     """A description restricted to the given rods (joints dropped; use for independent rods)."""
     out = dict(desc)
