@@ -64,6 +64,48 @@ def train(net: Mlp, F, T, epochs=2, batch=8192, lr=1e-3, seed=0, log=None):
     return hist
 
 
+def train_streamed(net: Mlp, sim, dt, steps, chunk=100, batch=8192, lr=(1e-3, 3e-4), seed=0, log=None):
+    """Train on the simulation's own trajectory as it is generated, without keeping it.  A
+    calibration pass first steps through the whole horizon once, keeping the features and
+    targets of the first step of every chunk, fits the standardisation on them (so the output
+    scale covers the whole run, not its start) and restores the starting state.  Then `steps`
+    steps (plain Newton) are taken again in chunks of `chunk`; the features and targets of every
+    step of a chunk are collected on the device, trained once (one Adam epoch over its shuffled
+    rows, the learning rate going linearly from lr[0] to lr[1] over the chunks) and dropped.
+    The two steps after the restore are taken without training (see below).  Returns the mean
+    loss per chunk and the number of rows trained on."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    hist, rows_seen = [], 0
+    n_chunks = (steps + chunk - 1) // chunk
+    start = sim.checkpoint_torch()
+    Fs, Ts = [], []
+    for c in range(n_chunks):
+        m = min(chunk, steps - c * chunk)
+        F, T = collect(sim, dt, m, every=m)
+        Fs.append(F)
+        Ts.append(T)
+    net.fit_normalisation(torch.cat(Fs), torch.cat(Ts))
+    del Fs, Ts
+    sim.restore(start)
+    # a restored state has no velocity history (a = j = 0): the first two steps' features are
+    # not those of the trajectory, so they are stepped over
+    sim.step(dt, 2)
+    for c in range(n_chunks):
+        m = min(chunk, steps - c * chunk) - (2 if c == 0 else 0)
+        F, T = collect(sim, dt, m, every=1)
+        n = F.shape[0]
+        perm = torch.randperm(n, generator=g, device="cuda").to(torch.int32)
+        rate = lr[0] + (lr[1] - lr[0]) * (c / max(n_chunks - 1, 1))
+        hist.append(net.train_epoch(F, T, perm, min(batch, n), rate))
+        rows_seen += (n // min(batch, n)) * min(batch, n)
+        if log:
+            log(f"chunk {c}: {n} rows, loss {hist[-1]:.4e}")
+        del F, T, perm
+    return hist, rows_seen
+
+
 def save(net: Mlp, path):
     mean, std, scale = net.get_normalisation()
     np.savez(path, params=net.get_params(), mean=mean, std=std, scale=scale)
