@@ -122,9 +122,14 @@ dm_status dm_add_rod(dm_sim* sim, int n_nodes, const double* x0, double radius, 
                      double poisson, double density, int* rod_id);
 
 /* Elastic joint: node node_b of rod_b becomes the same node as node_a of rod_a.  Bending
- * and twisting act on every pair of edges meeting there (Elastic Joints subsection).
+ * and twisting act on every pair of edges meeting there (Elastic Joints subsection); a rod
+ * passing through the joint keeps its own stencil there (its natural curvature, actuation
+ * and stiffness), and every other pair of edges at the joint gets a joint stencil.
  * Supported topologies: each connected set of rods either is one rod, or meets at a single
- * shared node that is an end node of every rod in the set (at most 8 rods). */
+ * shared node, which may be an end node or an interior node of each rod in the set (a rod
+ * through the joint counts as two branches; at most 8 branches).  Rods joined at two or more
+ * different nodes, and closed loops, give DM_ERR_UNSUPPORTED at dm_finalize; a rod joined to
+ * itself gives it here. */
 dm_status dm_add_joint(dm_sim* sim, int rod_a, int node_a, int rod_b, int node_b);
 
 /* Clamp nodes (all three coordinates) and optionally twist angles of a rod.

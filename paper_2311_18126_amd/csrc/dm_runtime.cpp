@@ -235,6 +235,7 @@ dm_status do_finalize(dm_sim* s) {
   std::vector<int> chain_node, chain_edge, bmap, bsrc, bjst, node_owner;
   std::vector<unsigned char> bfix, cfix;
   std::vector<DmSystem> systems;
+  std::vector<std::vector<int>> sys_bst;   // per system: stencils assembled into the dense border
   std::vector<v3> tref, d1ref;
   std::vector<int> node_home_c[3], edge_home;
   int dof_total = 0, fac_total = 0;
@@ -269,26 +270,38 @@ dm_status do_finalize(dm_sim* s) {
         }
       }
     }
-    // topology check: single rod, or every rod has exactly one end at a single shared node
+    // topology check: a single rod, or rods meeting at one shared node (the hub), which is an
+    // end node or an interior node of each of them.  A rod joined at an interior node k is
+    // solved as two chains, nodes 0..k and k..N-1, that meet at the hub.
     std::map<int, int> mult;
     for (int r : rods) for (int g : s->rod_node[r]) mult[g]++;
     std::vector<int> shared;
     for (auto& kv : mult) if (kv.second > 1) shared.push_back(kv.first);
     int hub = -1;
+    struct ChainSpec { int rod, lo, hi; bool hub_at_start; };
+    std::vector<ChainSpec> specs;
     if (rods.size() == 1) {
       if (!shared.empty()) return fail(DM_ERR_UNSUPPORTED, "rod " + std::to_string(rods[0]) + " is joined to itself");
+      specs.push_back({rods[0], 0, s->rods[rods[0]].n - 1, false});
     } else {
       if (shared.size() != 1) return fail(DM_ERR_UNSUPPORTED, "joined rods must meet at exactly one shared node");
-      if (rods.size() > DM_MAX_CHAINS) return fail(DM_ERR_UNSUPPORTED, "more than 8 rods at one joint");
       hub = shared[0];
       for (int r : rods) {
         const auto& rn = s->rod_node[r];
-        int ends = (rn.front() == hub) + (rn.back() == hub);
-        int inner = 0;
-        for (size_t i = 1; i + 1 < rn.size(); ++i) inner += (rn[i] == hub);
-        if (ends != 1 || inner != 0)
-          return fail(DM_ERR_UNSUPPORTED, "joint node must be an end node of every joined rod (rod " + std::to_string(r) + ")");
+        const int N = (int)rn.size();
+        int at = -1, count = 0;
+        for (int i = 0; i < N; ++i)
+          if (rn[i] == hub) { at = i; ++count; }
+        if (count != 1) return fail(DM_ERR_UNSUPPORTED, "rod " + std::to_string(r) + " meets the joint node more than once");
+        if (at == 0) specs.push_back({r, 0, N - 1, true});
+        else if (at == N - 1) specs.push_back({r, 0, N - 1, false});
+        else {
+          specs.push_back({r, 0, at, false});
+          specs.push_back({r, at, N - 1, true});
+        }
       }
+      if ((int)specs.size() > DM_MAX_CHAINS)
+        return fail(DM_ERR_UNSUPPORTED, "more than 8 rod branches at one joint");
     }
     // edges, masses, rest lengths
     for (int r : rods) {
@@ -364,14 +377,18 @@ dm_status do_finalize(dm_sim* s) {
       }
     }
     S.jst0 = (int)Vbar.size();
+    std::vector<int> bst;       // stencils of this system assembled into the dense border
     std::vector<int> edge_rod(ebar.size(), -1);
     for (int r : rods) for (int e : s->rod_edge[r]) edge_rod[e] = r;
     if (hub >= 0) {
+      // a rod joined at an interior node k keeps its own stencil there (its natural curvature,
+      // actuation and stiffness); that stencil couples the two chains and goes to the border
+      for (const ChainSpec& cs : specs)
+        if (cs.hub_at_start && cs.lo > 0) bst.push_back(s->rod_st0[cs.rod] + cs.lo - 1);
       std::vector<std::pair<int, int>> inc;   // (edge, +1 leaves hub / -1 enters hub), sorted by edge
-      for (int r : rods) {
-        const auto& rn = s->rod_node[r];
-        if (rn.front() == hub) inc.push_back({s->rod_edge[r].front(), +1});
-        else inc.push_back({s->rod_edge[r].back(), -1});
+      for (const ChainSpec& cs : specs) {
+        if (cs.hub_at_start) inc.push_back({s->rod_edge[cs.rod][cs.lo], +1});
+        else inc.push_back({s->rod_edge[cs.rod][cs.hi - 1], -1});
       }
       std::sort(inc.begin(), inc.end());
       for (size_t p = 0; p < inc.size(); ++p)
@@ -382,34 +399,37 @@ dm_status do_finalize(dm_sim* s) {
           else if (db == -1 && da == +1) { f = jb; e = ja; }
           else if (da == +1 && db == +1) { f = ja; e = jb; sfr = 1; }
           else { f = ja; e = jb; ser = 1; }
+          // the two edges of one rod at an interior joint: that rod's own stencil (kept above)
+          if (!sfr && !ser && edge_rod[f] == edge_rod[e] && e == f + 1) continue;
           int np = sfr ? en1[f] : en0[f];
           int nn = ser ? en0[e] : en1[e];
           push_st(np, hub, nn, f, e, sfr | (ser << 1), edge_rod[f], edge_rod[e], -1);
+          bst.push_back((int)Vbar.size() - 1);
         }
     }
-    S.n_jst = (int)Vbar.size() - S.jst0;
+    S.n_jst = (int)bst.size();
     S.n_nodes = (int)mass.size() - S.node0;
     S.n_edges = (int)ebar.size() - S.edge0;
     S.n_st = (int)Vbar.size() - S.st0;
     // ---- chains, border, arms
-    S.n_chains = (int)rods.size();
-    S.nb = (hub >= 0) ? 3 + 4 * (int)rods.size() : 0;
+    S.n_chains = (int)specs.size();
+    S.nb = (hub >= 0) ? 3 + 4 * (int)specs.size() : 0;
     std::vector<std::vector<std::pair<int, int>>> src;   // border index -> (chain, dof)
     int chain_nodes = 0;
-    for (size_t a = 0; a < rods.size(); ++a) {
-      int r = rods[a];
-      const Rod& R = s->rods[r];
+    for (size_t a = 0; a < specs.size(); ++a) {
+      const ChainSpec& cs = specs[a];
+      const int r = cs.rod;
       DmChain C{};
-      C.n_nodes = R.n;
+      C.n_nodes = cs.hi - cs.lo + 1;
       C.node_tab = (int)chain_node.size();
       C.edge_tab = (int)chain_edge.size();
-      C.st_off = s->rod_st0[r];
+      C.st_off = s->rod_st0[r] + cs.lo;     // the stencil of chain node m is the rod's node lo + m
       C.dof_off = dof_total;
       C.global_id = (int)chains.size();
       C.rod = r;
-      for (int g : s->rod_node[r]) chain_node.push_back(g);
-      for (int e : s->rod_edge[r]) chain_edge.push_back(e);
-      const int n = 4 * R.n - 1;
+      for (int k = cs.lo; k <= cs.hi; ++k) chain_node.push_back(s->rod_node[r][k]);
+      for (int k = cs.lo; k < cs.hi; ++k) chain_edge.push_back(s->rod_edge[r][k]);
+      const int n = 4 * C.n_nodes - 1;
       C.bmap_off = (int)bmap.size();
       std::vector<DmArm> ca;
       if (hub < 0) {
@@ -425,7 +445,7 @@ dm_status do_finalize(dm_sim* s) {
         src.assign(S.nb, {});
         for (int i = C.b_lo; i < C.b_hi; ++i) { bmap.push_back(i - C.b_lo); src[i - C.b_lo].push_back({C.global_id, i}); }
       } else {
-        bool at_start = s->rod_node[r].front() == hub;
+        const bool at_start = cs.hub_at_start;
         if (src.empty()) src.assign(S.nb, {});
         const int base = 3 + 4 * (int)a;
         int map7[7];
@@ -451,15 +471,18 @@ dm_status do_finalize(dm_sim* s) {
         arms.push_back(A);
       }
       // clamps per chain DOF
-      for (int k = 0; k < R.n; ++k) {
+      for (int k = cs.lo; k <= cs.hi; ++k) {
         int g = s->rod_node[r][k];
         for (int c = 0; c < 3; ++c) cfix.push_back(nfix[g]);
-        if (k + 1 < R.n) cfix.push_back(efix[s->rod_edge[r][k]]);
+        if (k < cs.hi) cfix.push_back(efix[s->rod_edge[r][k]]);
       }
-      for (int g : s->rod_node[r]) if (node_owner[g] < 0) node_owner[g] = C.global_id;
+      for (int k = cs.lo; k <= cs.hi; ++k) {
+        const int g = s->rod_node[r][k];
+        if (node_owner[g] < 0) node_owner[g] = C.global_id;
+      }
       chains.push_back(C);
       dof_total += n;
-      chain_nodes += R.n;
+      chain_nodes += C.n_nodes;
     }
     S.n_arms = (int)arms.size() - S.arm0;
     S.chain_nodes = chain_nodes;
@@ -481,7 +504,7 @@ dm_status do_finalize(dm_sim* s) {
     // joint stencils: border index of each local DOF
     S.bjst_off = (int)bjst.size();
     for (int js = 0; js < S.n_jst; ++js) {
-      int st = S.jst0 + js;
+      int st = bst[js];
       auto nodeb = [&](int g, int c) -> int {
         if (g == hub) return c;
         for (int a = 0; a < S.n_chains; ++a) {
@@ -513,6 +536,7 @@ dm_status do_finalize(dm_sim* s) {
     s->max_nb = std::max(s->max_nb, S.nb);
     s->max_arms = std::max(s->max_arms, S.n_arms);
     systems.push_back(S);
+    sys_bst.push_back(bst);
   }
   // ---- terms of every dense border entry (entry b (nb + 1) + col, col = nb: right-hand side),
   // in the order the assembly sums them: each source chain row's residual and border-column
@@ -520,7 +544,8 @@ dm_status do_finalize(dm_sim* s) {
   std::vector<int> bent;
   std::vector<DmBItem> bitem;
   const int NST = (int)Vbar.size();      // every stencil is placed by now
-  for (DmSystem& S : systems) {
+  for (size_t si = 0; si < systems.size(); ++si) {
+    DmSystem& S = systems[si];
     const int W = S.nb + 1;
     std::vector<std::vector<DmBItem>> ent((size_t)S.nb * W);
     for (int b = 0; b < S.nb; ++b) {
@@ -542,7 +567,7 @@ dm_status do_finalize(dm_sim* s) {
     }
     for (int js = 0; js < S.n_jst; ++js) {
       const int* bj = &bjst[S.bjst_off + js * 11];
-      const int st = S.jst0 + js;
+      const int st = sys_bst[si][js];
       const double sf = (ssign[st] & 1) ? -1.0 : 1.0, se = (ssign[st] & 2) ? -1.0 : 1.0;
       for (int a = 0; a < 11; ++a) {
         const int b = bj[a];

@@ -219,10 +219,18 @@ def test_invalid_arguments_are_rejected(dm):
 
 
 def test_unsupported_topology_is_rejected(dm):
+    """Closed loops are not a topology the library solves: a rod joined to itself is refused
+    when the joint is added, two rods joined at both ends when the simulation is finalized."""
     sim = dm.Sim()
     a = sim.add_rod(W.straight_nodes(5, 1.0), 1e-3, 1e7)
-    b = sim.add_rod(W.straight_nodes(5, 1.0, (0, 1, 0)), 1e-3, 1e7)
-    sim.add_joint(a, 2, b, 2)      # joint in the middle of both rods
+    with pytest.raises(dm.DmError) as e:
+        sim.add_joint(a, 0, a, 4)
+    assert e.value.status == dm.DM_ERR_UNSUPPORTED
+    sim = dm.Sim()
+    a = sim.add_rod(W.straight_nodes(5, 1.0), 1e-3, 1e7)
+    b = sim.add_rod(W.straight_nodes(5, 1.0, (1.0, 0.0, 0.0), (-1.0, 0.0, 0.0)), 1e-3, 1e7)
+    sim.add_joint(a, 4, b, 0)
+    sim.add_joint(a, 0, b, 4)
     with pytest.raises(dm.DmError) as e:
         sim.finalize()
     assert e.value.status == dm.DM_ERR_UNSUPPORTED
