@@ -91,6 +91,45 @@ def segment_distance(a, b, c, d):
     return cands[k]
 
 
+def branch_of(x12):
+    """Which candidate of `segment_distance` attains the minimum at the coordinates x12
+    (0: the stationary point inside the square, 1..4: end point a, b, c or d against the
+    other segment), decided on plain values."""
+    a, b, c, d = x12[0:3], x12[3:6], x12[6:9], x12[9:12]
+    D, s, t = segment_distance(a, b, c, d)
+    sv, tv = _val(s), _val(t)
+    if 0.0 < sv < 1.0 and 0.0 < tv < 1.0:
+        return 0
+    cands = [(_val(point_segment(a, c, d)[0]), 1), (_val(point_segment(b, c, d)[0]), 2),
+             (_val(point_segment(c, a, b)[0]), 3), (_val(point_segment(d, a, b)[0]), 4)]
+    return min(cands)[1]
+
+
+def closest_on_branch(x12, k):
+    """(D, s, t) by the formula of candidate k alone: no decision on values, so it can be
+    differentiated (and vectorised) at coordinates where k is the minimising candidate."""
+    a, b, c, d = x12[0:3], x12[3:6], x12[6:9], x12[9:12]
+    if k == 0:
+        u, v, w = b - a, d - c, a - c
+        A, B, Cc = torch.dot(u, u), torch.dot(u, v), torch.dot(v, v)
+        Dd, E = torch.dot(u, w), torch.dot(v, w)
+        den = A * Cc - B * B
+        s = (B * E - Cc * Dd) / den
+        t = (A * E - B * Dd) / den
+        return torch.linalg.norm(w + s * u - t * v), s, t
+    if k == 1:
+        D, t = point_segment(a, c, d)
+        return D, torch.zeros_like(D), t
+    if k == 2:
+        D, t = point_segment(b, c, d)
+        return D, torch.ones_like(D), t
+    if k == 3:
+        D, s = point_segment(c, a, b)
+        return D, s, torch.zeros_like(D)
+    D, s = point_segment(d, a, b)
+    return D, s, torch.ones_like(D)
+
+
 def distance_of(x12):
     """D as a function of the 12 stacked coordinates (a, b, c, d)."""
     a, b, c, d = x12[0:3], x12[3:6], x12[6:9], x12[9:12]

@@ -20,6 +20,10 @@ What it computes, in the paper's order and notation (DisMech, Methodology):
   automatic differentiation of the energy exactly as written above.
 * Contact (Eq. 10-11) against a flat floor, smooth Coulomb friction (Eq. 12-13),
   gravity and optional viscous damping (miscellaneous forces).
+* Edge-edge self-contact of a rod (the same Eq. 10-13 on pairs of its edges, with the
+  distance and pairing of `oracle/contact.py`): the contact energy joins the elastic energy
+  and its friction the external force; the pairs, and which closest-point candidate each
+  takes, are found at every Newton iterate.
 * Backward Euler (Eq. 14-15) solved by Newton's method; the Jacobian (Eq. 16)
   is the automatic Jacobian of the residual.  Velocity update after Eq. 16.
 * Adaptive time stepping (named as an option in the same subsection): a step whose Newton
@@ -107,6 +111,8 @@ class System:
     rod_nodes: list = field(default_factory=list)   # per rod: global node id of each rod node
     rod_edges: list = field(default_factory=list)   # per rod: global edge id of each rod edge
     kbar_user: list = field(default_factory=list)   # per rod: (N-2, 2) in 1/m or None
+    self_contact: dict | None = None                # {"delta", "k_c", "mu", "nu"} or None
+    contact_sets: list = field(default_factory=list)  # per rod: its edges (contact.EdgeSet)
 
     @property
     def n_dof(self):
@@ -308,6 +314,16 @@ def build(desc, rod_ids=None):
                  torch.tensor(st_rod), torch.tensor(st_idx), _t(act).reshape(-1, 3), mass, radius_node,
                  fixed, force, moment, _t(desc["gravity"]), desc.get("floor"), float(desc.get("damping", 0.0)),
                  rod_nodes, rod_edges, [rods[r].get("kbar") for r in rod_ids])
+    if desc.get("self_contact"):
+        from . import contact as _contact
+        if any(ra in local or rb in local for (ra, na, rb, nb) in desc["joints"]):
+            raise NotImplementedError("self-contact of joined rods")
+        sys.self_contact = dict(desc["self_contact"])
+        for k, r in enumerate(rod_ids):
+            eids = rod_edges[k]
+            sys.contact_sets.append(_contact.EdgeSet(edge_nodes[eids].tolist(), [0] * len(eids),
+                                                     list(range(len(eids))), [rods[r]["radius"]] * len(eids),
+                                                     ebar[eids].tolist()))
     # --- initial frames, rest curvature and twist of the initial shape
     e = X[edge_nodes[:, 1]] - X[edge_nodes[:, 0]]
     t = e / torch.linalg.norm(e, dim=1, keepdim=True)
@@ -461,16 +477,72 @@ def pack(x, theta):
     return torch.cat([x.reshape(-1), theta])
 
 
-def residual(sys, q, st, dt, kappa_bar):
-    """Backward-Euler residual (Eq. 15):  M/dt^2 (q - q_n - dt qdot_n) + dE/dq - F_ext."""
+def contact_list(sys, q):
+    """The self-contact pairs at q and the closest-point candidate each takes there:
+    [(a, b, c, d, C, branch)] with global node ids of edge (a, b) and edge (c, d)."""
+    if not sys.self_contact:
+        return None
+    from . import contact as _contact
+    x, _ = unpack(sys, q.detach())
+    out = []
+    for es in sys.contact_sets:
+        for (i, j, D, s_, t_) in _contact.contact_pairs(es, x, sys.self_contact["delta"]):
+            a, b = es.edges[i].tolist()
+            c, d = es.edges[j].tolist()
+            br = _contact.branch_of(torch.cat([x[a], x[b], x[c], x[d]]))
+            out.append((a, b, c, d, es.contact_distance(i, j), br))
+    return out
+
+
+def self_contact_energy(sys, x, pairs):
+    """Sum over the pairs of k_c E_c(D) (Eq. 10), D by each pair's fixed candidate."""
+    from . import contact as _contact
+    sc = sys.self_contact
+    tot = torch.zeros((), dtype=DT)
+    for (a, b, c, d, C, br) in pairs:
+        D, _, _ = _contact.closest_on_branch(torch.cat([x[a], x[b], x[c], x[d]]), br)
+        tot = tot + sc["k_c"] * contact_energy_profile(D, C, sc["delta"])
+    return tot
+
+
+def self_contact_friction(sys, x, st, dt, pairs):
+    """Friction (Eq. 12-13) of every pair: u the tangential relative velocity of the closest
+    points over the step at the closest-point parameters of x, |F_con| = k_c |dE_c/dD|; edge
+    (a, b) gets -mu gamma u_hat |F_con| spread by (1 - s, s), edge (c, d) the opposite."""
+    from . import contact as _contact
+    sc = sys.self_contact
+    K2 = 15.0 / sc["nu"]
+    F = torch.zeros_like(x)
+    for (a, b, c, d, C, br) in pairs:
+        D, s, t = _contact.closest_on_branch(torch.cat([x[a], x[b], x[c], x[d]]), br)
+        P, Q = x[a] + s * (x[b] - x[a]), x[c] + t * (x[d] - x[c])
+        Pn, Qn = st.x[a] + s * (st.x[b] - st.x[a]), st.x[c] + t * (st.x[d] - st.x[c])
+        n = (P - Q) / D
+        vrel = (P - Pn - Q + Qn) / dt
+        u = vrel - torch.dot(vrel, n) * n
+        dEdD = torch.func.grad(lambda dd: contact_energy_profile(dd, C, sc["delta"]))(D)
+        ratio = friction_ratio(torch.dot(u, u), K2)          # gamma / |u|, smooth at u = 0
+        f = -sc["mu"] * sc["k_c"] * torch.abs(dEdD) * ratio * u
+        F = F.index_add(0, torch.tensor([a, b, c, d]), torch.stack([(1 - s) * f, s * f, -(1 - t) * f, -t * f]))
+    return F
+
+
+def residual(sys, q, st, dt, kappa_bar, contact=None):
+    """Backward-Euler residual (Eq. 15):  M/dt^2 (q - q_n - dt qdot_n) + dE/dq - F_ext, with
+    the self-contact pairs `contact` (contact_list) in the energy and the external force."""
     def energy(qq):
         xx, tt = unpack(sys, qq)
-        return elastic_energy(sys, xx, tt, st, kappa_bar)
+        e = elastic_energy(sys, xx, tt, st, kappa_bar)
+        if contact:
+            e = e + self_contact_energy(sys, xx, contact)
+        return e
     gE = torch.func.grad(energy)(q)
     x, theta = unpack(sys, q)
     Mx = sys.mass[:, None] * (x - st.x - dt * st.v) / (dt * dt)
     Mt = sys.Itheta * (theta - st.theta - dt * st.omega) / (dt * dt)
     F = external_force(sys, x, st, dt)
+    if contact and sys.self_contact.get("mu", 0.0) > 0.0:
+        F = F + self_contact_friction(sys, x, st, dt, contact)
     return pack(Mx - F, Mt - sys.moment) + gE
 
 
@@ -542,7 +614,22 @@ def newton_solve(sys, st, dt, kappa_bar, tol=1e-9, max_iter=50, q0=None, polish=
     unknown is the step end but the rounding acts on the midpoint state)."""
     free = ~sys.fixed
     q = pack(st.x, st.theta).clone() if q0 is None else q0.clone()
-    jac = torch.func.jacfwd(lambda qq: res(sys, qq, st, dt, kappa_bar))
+    if sys.self_contact and res is not residual:
+        raise NotImplementedError("self-contact under the implicit-midpoint rule")
+    # with self-contact the pairs (and their closest-point candidates) are those of the
+    # iterate being evaluated; the Jacobian at q takes q's pairs
+    res_plain = res
+
+    def res(sys_, qq, st_, dt_, kb_):
+        if not sys_.self_contact:
+            return res_plain(sys_, qq, st_, dt_, kb_)
+        return res_plain(sys_, qq, st_, dt_, kb_, contact_list(sys_, qq))
+
+    def jac(qq):
+        cl = contact_list(sys, qq)
+        if cl is None:
+            return torch.func.jacfwd(lambda z: res_plain(sys, z, st, dt, kappa_bar))(qq)
+        return torch.func.jacfwd(lambda z: res_plain(sys, z, st, dt, kappa_bar, cl))(qq)
     sc = floor_scales(sys, st)[free]
     hist = []
     it = 0

@@ -258,6 +258,34 @@ def contact_tangle(n_scenes: int = 4096, seed: int = 7, fingers: int = 5, n_node
             "nu": 1e-3, "mu": 0.5, "k_c": m_node * 9.8 / delta, "dt": 1e-3}
 
 
+def coiled_springs(n_rods: int = 4, seed: int = 13, nmin: int = 40, nmax: int = 80, radius: float = 4e-3,
+                   steps: int = 10, mu: float = 0.3) -> dict:
+    """Coiled rods standing on their clamped first nodes (a helix rising along +z about a
+    vertical axis), N ~ U{nmin..nmax} nodes over 3 to 4 turns, helix radius U(14, 18) mm, pitch
+    U(8.1, 8.4) mm (the turns sit just inside the contact reach 2h + delta = 8.5 mm of their
+    radius h = 4 mm), E = 10^U(5.5, 6.5) Pa, rho = 1200; gravity -9.81 z presses the turns
+    together; rods 1 m apart along x.  Self-contact: delta = 5e-4 m, k_c = (node mass) g /
+    delta of the first rod, mu as given, nu = 1e-3 m/s; dt = 1e-3 s."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    rods = []
+    m0 = None
+    for k in range(n_rods):
+        n = int(rng.integers(nmin, nmax + 1))
+        R = rng.uniform(0.014, 0.018)
+        p = rng.uniform(0.0081, 0.0084)
+        turns = rng.uniform(3.0, 4.0)
+        phi = np.linspace(0.0, 2.0 * math.pi * turns, n)
+        x0 = np.stack([R * np.cos(phi) + 1.0 * k, R * np.sin(phi), p * phi / (2.0 * math.pi)], 1)
+        E = 10.0 ** rng.uniform(5.5, 6.5)
+        rods.append(_rod(x0, radius, E, 0.5, 1200.0))
+        if m0 is None:
+            m0 = 1200.0 * math.pi * radius ** 2 * float(np.linalg.norm(x0[1] - x0[0]))
+    d = _desc(rods, dt=1e-3, steps=steps)
+    delta = 5e-4
+    d["self_contact"] = {"delta": delta, "k_c": m0 * 9.81 / delta, "mu": float(mu), "nu": 1e-3}
+    return d
+
+
 def subset(desc: dict, rod_ids) -> dict:
     """A description restricted to the given rods (joints dropped; use for independent rods)."""
     out = dict(desc)
