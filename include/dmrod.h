@@ -408,18 +408,21 @@ dm_status dm_ws_targets(dm_sim* sim, const double* F_prev, double dt, double* T)
 /* Warm start of dm_step: mode 0 off (Newton from x_n), 1 explicit predictor x_n + dt v_n,
  * 3 the second-order extrapolation x_n + dt (v_n + a_n), 4 the third-order extrapolation
  * x_n + dt (v_n + a_n + j_n), 2 the network on top of the third-order extrapolation (dt is the
- * Newton step: a substep of adaptive halving takes its share of the network's correction).
+ * Newton step; a substep of adaptive halving, or the midpoint state under the implicit-midpoint
+ * integrator, takes its share of the network's whole-step correction).
  * Each system guesses at the start of every step inside the same persistent launch (the
  * network runs there on the matrix cores); a guess whose Newton solve fails within
  * warm_max_iter iterations is redone from x_n and counted in dm_stats.fallbacks.  The sim
  * keeps a reference to net, which must outlive its use.  After dm_set_state or
  * dm_load_checkpoint the velocity history is the current velocity (a = j = 0). */
 dm_status dm_set_warm_start(dm_sim* sim, dm_mlp* net, int mode);
-/* The guessed displacement x^(0) - x_n of every feature row for a Newton step of dt from the
+/* The guessed displacement x^(0) - x_n of every feature row for a time step dt from the
  * current state under the current warm mode (not 0), into dx [rows][3] (device memory if
- * on_device, else host); the state is not changed.  The network's correction enters whole
- * (dt is taken as a full step).  Rows of clamped or shared nodes are reported too (the step
- * leaves clamped DOFs alone and uses the owning rod's row). */
+ * on_device, else host); the state is not changed.  Under backward Euler that is the guess of
+ * the step's end; under the implicit-midpoint integrator the Newton unknown is the midpoint
+ * state, and the guess is of it (the Newton step dt / 2, half the network's correction).
+ * Rows of clamped or shared nodes are reported too (the step leaves clamped DOFs alone and
+ * uses the owning rod's row). */
 dm_status dm_ws_predict(dm_sim* sim, double dt, double* dx, int on_device);
 
 /* Autotuner: times the step kernel at each workgroup size (64, 128, 256, 512 threads) over

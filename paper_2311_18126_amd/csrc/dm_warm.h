@@ -8,7 +8,8 @@
 //   mode 3: x_n + dt (v_n + a_n), a_n = v_n - v_{n-1} (second-order extrapolation);
 //   mode 4: x_n + dt (v_n + a_n + j_n), j_n = a_n - a_{n-1} (third-order extrapolation);
 //   mode 2: mode 4 plus the network's correction s * y, y = MLP(standardised features), scaled
-//           by the substep's share of the step under adaptive halving.
+//           by the share of the time step that the Newton unknown covers (a substep of adaptive
+//           halving; half the step for the midpoint state of the implicit-midpoint rule).
 // The network runs on the matrix cores in bfloat16 with float32 accumulation, rounded at the
 // same points and accumulated in the same order as the batch kernels of dm_mlp.hip.
 #pragma once
@@ -215,9 +216,10 @@ __device__ __forceinline__ void network_block(const DmStepArgs DM_C& A, double d
         y = dm_mfma_bf16(lds_fragment(Q, 16 * rt + lr, k0 + 8 * g), ld_bf16x8(W.w3 + lr * DM_NET_HID + k0 + 8 * g), y);
       if (lr < DM_NET_OUT) {
         const float bb = W.b3[lr];
-        // the network predicts a whole step's correction; a substep of adaptive halving takes
-        // its share dt / A.dt of it
-        const double sc = W.ystd[lr], share = dt / A.dt;
+        // the network predicts a whole backward-Euler step's correction; the Newton unknown of
+        // a substep of adaptive halving, or the midpoint state of the implicit-midpoint rule,
+        // takes its share: its Newton step over the whole time step
+        const double sc = W.ystd[lr], share = dt / (A.midpoint ? 2.0 * A.dt : A.dt);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           const int i = row0 + 16 * rt + 4 * g + j;

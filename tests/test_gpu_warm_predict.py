@@ -90,6 +90,33 @@ def test_network_guess_matches_oracle_and_batch_kernels(dm, case):
     sim.set_warm_start(None, 0)
 
 
+def test_midpoint_guess_is_of_the_midpoint_state(dm, case):
+    """Under the implicit-midpoint integrator the Newton unknown is the midpoint state: the
+    analytic part is taken over half the step, and so is the network's whole-step correction."""
+    d, sim, F, base = case
+    p = OM.init_params(22)
+    flat = np.concatenate([p[k].reshape(-1) for k in ("W1", "b1", "W2", "b2", "W3", "b3")]).astype(np.float32)
+    mean, std = F.mean(0), F.std(0) + 1e-3
+    scale = np.array([2e-5, 1e-5, 3e-5])
+    net = dm.Mlp(max_rows=F.shape[0])
+    net.set_params(flat)
+    net.set_normalisation(mean, std, scale)
+    y_ref, _ = OM.forward(p, OM.standardise(F, mean, std))
+    sim.set_integrator("midpoint")
+    try:
+        sim.set_warm_start(None, 4)
+        assert np.allclose(sim.ws_predict(d["dt"]), 0.5 * base[4], rtol=1e-13, atol=1e-18)
+        sim.set_warm_start(net, 2)
+        dx = sim.ws_predict(d["dt"])
+        y_dev = (dx - 0.5 * base[4]) / (0.5 * scale)
+        rel = np.linalg.norm(y_dev - y_ref) / np.linalg.norm(y_ref)
+        say(f"midpoint network guess vs oracle: relative error {rel:.2e}")
+        assert rel < 1e-3
+    finally:
+        sim.set_integrator("euler")
+        sim.set_warm_start(None, 0)
+
+
 def test_predict_needs_a_warm_mode(dm, case):
     d, sim, _, _ = case
     sim.set_warm_start(None, 0)
