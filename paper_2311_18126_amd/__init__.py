@@ -114,6 +114,7 @@ _SIGS = {
     "dm_ws_targets": (c_int, [c_void_p, c_void_p, c_double, c_void_p]),
     "dm_set_warm_start": (c_int, [c_void_p, c_void_p, c_int]),
     "dm_set_integrator": (c_int, [c_void_p, c_int]),
+    "dm_set_self_contact": (c_int, [c_void_p, c_double, c_double, c_double, c_double]),
     "dm_set_adaptive": (c_int, [c_void_p, c_int]),
     "dm_ws_predict": (c_int, [c_void_p, c_double, c_void_p, c_int]),
     "dm_autotune": (c_int, [c_void_p, c_double, c_int, c_char_p, POINTER(c_int)]),
@@ -321,6 +322,12 @@ class Sim:
             out[i] = (st[i].steps_done, st[i].newton_iters, st[i].status, st[i].floor_steps, st[i].fallbacks,
                       st[i].halvings, st[i].residual, st[i].floor_residual_max, st[i].floor_estimate)
         return out
+
+    def set_self_contact(self, delta, k_c, mu=0.0, nu=1e-3):
+        """Edge-edge self-contact of every rod inside step() (dm_set_self_contact); k_c = 0
+        turns it off."""
+        _check(lib().dm_set_self_contact(self._h, float(delta), float(k_c), float(mu), float(nu)),
+               "dm_set_self_contact")
 
     def set_integrator(self, scheme):
         """Time integrator of step(): "euler" (backward Euler, the default) or "midpoint"
@@ -832,6 +839,9 @@ def sim_from_description(desc, **overrides):
     for (ra, na, rb, nb) in desc["joints"]:
         sim.add_joint(ra, na, rb, nb)
     sim.finalize()
+    if desc.get("self_contact"):
+        sc = desc["self_contact"]
+        sim.set_self_contact(sc["delta"], sc["k_c"], sc.get("mu", 0.0), sc.get("nu", 1e-3))
     if "initial_tip_velocity" in desc:
         for rid in range(len(desc["rods"])):
             x, th, v, om = sim.rod_state(rid)

@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "dmrod.h"
+#include "dm_segment.h"
 
 namespace {
 
@@ -57,26 +58,12 @@ __device__ __forceinline__ V3 axpy(double s, V3 a, V3 b) { return V3{fma(s, a.x,
 __device__ __forceinline__ double dotv(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 __device__ __forceinline__ double clamp01(double v) { return fmin(fmax(v, 0.0), 1.0); }
 
-// Closest points of segments p1 + s d1 and p2 + t d2, s, t in [0, 1]: the minimiser over s of
-// the line-line problem clamped to [0, 1], t from it, and when t leaves [0, 1], t clamped and
-// s recomputed and clamped.  Parallel (or degenerate) segments take s = 0 (any point of the
-// overlap is a minimiser).  Returns |P - Q|^2.
+// Closest points (dm_segment.h) of segments p1 + s d1 and p2 + t d2; returns |P - Q|^2.
 __device__ double closest(V3 p1, V3 d1, V3 p2, V3 d2, double& s, double& t) {
-  const V3 r = sub(p1, p2);
-  const double a = dotv(d1, d1), e = dotv(d2, d2), f = dotv(d2, r);
-  const double c = dotv(d1, r), b = dotv(d1, d2);
-  const double den = a * e - b * b;
-  s = den > 1e-14 * a * e ? clamp01((b * f - c * e) / den) : 0.0;
-  t = (b * s + f) / e;
-  if (t < 0.0) {
-    t = 0.0;
-    s = clamp01(-c / a);
-  } else if (t > 1.0) {
-    t = 1.0;
-    s = clamp01((b - c) / a);
-  }
-  const V3 w = sub(axpy(s, d1, p1), axpy(t, d2, p2));
-  return dotv(w, w);
+  const double a1[3] = {p1.x, p1.y, p1.z}, b1[3] = {d1.x, d1.y, d1.z};
+  const double a2[3] = {p2.x, p2.y, p2.z}, b2[3] = {d2.x, d2.y, d2.z};
+  double r[3];
+  return seg_closest(a1, b1, a2, b2, s, t, r);
 }
 
 // Edges i and j of one rod that lie within C + delta of each other in the rest shape (their
@@ -386,10 +373,10 @@ const char* dm_contact_last_error(void) { return g_ct_err.c_str(); }
 
 void dm_contact_destroy(dm_contact* c) {
   if (!c) return;
-  hipSetDevice(c->device);
+  (void)hipSetDevice(c->device);
   for (hipEvent_t e : c->ev)
-    if (e) hipEventDestroy(e);
-  for (void* p : c->bufs) hipFree(p);
+    if (e) (void)hipEventDestroy(e);
+  for (void* p : c->bufs) (void)hipFree(p);
   delete c;
 }
 

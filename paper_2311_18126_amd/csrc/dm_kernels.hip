@@ -20,6 +20,7 @@
 #define DM_KERNEL_TU
 #include "dm_layout.h"
 #include "dm_math.h"
+#include "dm_segment.h"
 
 #ifdef DM_PHASE_TIMING
 // Per-phase wall-clock accumulation (100 MHz counter) for diagnosis builds only; every phase
@@ -42,6 +43,7 @@
 #define DM_STATUS_OK 0
 #define DM_STATUS_NOT_CONVERGED 1
 #define DM_STATUS_SINGULAR (-5)
+#define DM_STATUS_CONTACT_OVERFLOW (-6)   // more self-contact pairs than the per-system list holds
 
 namespace {
 
@@ -453,6 +455,196 @@ __device__ __noinline__ void eval_edges_nodes(ArgsP Ap, int sid, double dt) {
   const DmSystem DM_C& S = A.d.sys[uniform(sid)];
   for (int i = threadIdx.x; i < S.n_edges; i += blockDim.x) eval_edge(A, S.edge0 + i);
   for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x) eval_node(A, S.node0 + i, dt);
+}
+
+// ---------------------------------------------------------------------------
+// edge-edge self-contact of a single rod (Contact and Friction subsection: Eq. 10-13 applied
+// to pairs of the rod's edges)
+// ---------------------------------------------------------------------------
+
+// E_c'(D) and E_c''(D) of Eq. 10 (K1 = 15 / delta).
+__device__ __forceinline__ void sc_profile(double D, double C, double delta, double& E1, double& E2) {
+  if (D <= C - delta) {
+    E1 = -2.0 * (C - D);
+    E2 = 2.0;
+  } else if (D < C + delta) {
+    const double K1 = 15.0 / delta, z = K1 * (C - D);
+    const double L = log1p(exp(z)), sg = 1.0 / (1.0 + exp(-z));
+    E1 = -2.0 * L * sg / K1;
+    E2 = 2.0 * (sg * sg + L * sg * (1.0 - sg));
+  } else {
+    E1 = E2 = 0.0;
+  }
+}
+
+__device__ __forceinline__ float sc_down(double v) {
+  const float f = (float)v;
+  return (double)f > v ? nextafterf(f, -INFINITY) : f;
+}
+__device__ __forceinline__ float sc_up(double v) {
+  const float f = (float)v;
+  return (double)f < v ? nextafterf(f, INFINITY) : f;
+}
+
+// Self-contact of the rod of system sid at the current iterate.  The pairs of its edges within
+// reach, D < h_i + h_j + delta, are found over all pairs i < j by a test of boxes inflated by
+// h + delta / 2 (rounded outward to float32 in LDS), the rest-arclength exclusion (edges closer
+// than h_i + h_j + delta along the rest rod are never a pair) and the exact segment distance,
+// and sorted in LDS.  Then each node adds, over its pairs, the contact energy's gradient minus
+// the friction force to its residual terms, and its own 3 x 3 block of the contact Hessian to
+// its Jacobian block.  The couplings between different nodes of a pair are off the rod's band
+// and are left out of the Newton matrix: the residual is exact, the Newton matrix approximate.
+// LDS: box [6][sc_max_edges] floats, keys [sc_cap] ints, the pair count and the overflow flag.
+__device__ __noinline__ void self_contact(ArgsP Ap, int sid, double dt, char DM_L* sc_lds) {
+  const DmStepArgs DM_C& A = *uniform(Ap);
+  const DmDev DM_C& D = A.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
+  const DmChain ch = D.chain[S.chain0];
+  const int N = ch.n_nodes, E = N - 1, NN = D.n_nodes_tot, ME = A.sc_max_edges, cap = A.sc_cap;
+  float DM_L* box = (float DM_L*)sc_lds;
+  int DM_L* keys = (int DM_L*)(box + 6 * ME);
+  int DM_L* cnt = keys + cap;            // [0] pair count, [1] overflow flag
+  const double delta = A.sc_delta;
+  const int tid = threadIdx.x, bd = blockDim.x;
+  if (tid == 0) cnt[0] = 0;
+  for (int e = tid; e < E; e += bd) {
+    const int a = D.chain_node[ch.node_tab + e], b = D.chain_node[ch.node_tab + e + 1];
+    const v3 pa = ld3(D.x, NN, a), pb = ld3(D.x, NN, b);
+    const double inf = D.radius[a] + 0.5 * delta;
+    box[e] = sc_down(fmin(pa.x, pb.x) - inf);
+    box[ME + e] = sc_down(fmin(pa.y, pb.y) - inf);
+    box[2 * ME + e] = sc_down(fmin(pa.z, pb.z) - inf);
+    box[3 * ME + e] = sc_up(fmax(pa.x, pb.x) + inf);
+    box[4 * ME + e] = sc_up(fmax(pa.y, pb.y) + inf);
+    box[5 * ME + e] = sc_up(fmax(pa.z, pb.z) + inf);
+  }
+  __syncthreads();
+  for (int p = tid; p < E * E; p += bd) {
+    const int i = p / E, j = p - i * E;
+    if (j <= i) continue;
+    if (box[j] > box[3 * ME + i] || box[i] > box[3 * ME + j] || box[ME + j] > box[4 * ME + i] ||
+        box[ME + i] > box[4 * ME + j] || box[2 * ME + j] > box[5 * ME + i] || box[2 * ME + i] > box[5 * ME + j])
+      continue;
+    const int ei = D.chain_edge[ch.edge_tab + i], ej = D.chain_edge[ch.edge_tab + j];
+    const int a = D.chain_node[ch.node_tab + i], c = D.chain_node[ch.node_tab + j];
+    const double reach = D.radius[a] + D.radius[c] + delta;
+    if (D.arc0[ej] - D.arc0[ei] - D.ebar[ei] < reach) continue;      // near along the rest rod
+    const int b = D.chain_node[ch.node_tab + i + 1], d = D.chain_node[ch.node_tab + j + 1];
+    const v3 pa = ld3(D.x, NN, a), pb = ld3(D.x, NN, b), pc = ld3(D.x, NN, c), pd = ld3(D.x, NN, d);
+    const double p1[3] = {pa.x, pa.y, pa.z}, d1[3] = {pb.x - pa.x, pb.y - pa.y, pb.z - pa.z};
+    const double p2[3] = {pc.x, pc.y, pc.z}, d2[3] = {pd.x - pc.x, pd.y - pc.y, pd.z - pc.z};
+    double sv, tv, r[3];
+    if (seg_closest(p1, d1, p2, d2, sv, tv, r) < reach * reach) {
+      const int k = atomicAdd(cnt, 1);
+      if (k < cap) keys[k] = (i << 16) | j;
+    }
+  }
+  __syncthreads();
+  int np = cnt[0];
+  if (np > cap) {
+    if (tid == 0) cnt[1] = 1;
+    np = cap;
+  }
+  int n2 = 1;
+  while (n2 < np) n2 <<= 1;
+  for (int k = np + tid; k < n2; k += bd) keys[k] = 0x7fffffff;
+  __syncthreads();
+  // bitonic sort of the keys (fixed order, so the node sums below do not depend on timing)
+  for (int k = 2; k <= n2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = tid; i < n2; i += bd) {
+        const int q = i ^ j;
+        if (q > i) {
+          const int u = keys[i], w = keys[q];
+          if (((i & k) == 0) ? (u > w) : (u < w)) {
+            keys[i] = w;
+            keys[q] = u;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  const double kc = A.sc_kc, mu = A.sc_mu, K2 = 15.0 / A.sc_nu;
+  for (int k = tid; k < N; k += bd) {
+    double g[3] = {0.0, 0.0, 0.0}, H[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    for (int q = 0; q < np; ++q) {
+      const int key = keys[q], i = key >> 16, j = key & 0xffff;
+      const int role = k == i ? 0 : (k == i + 1 ? 1 : (k == j ? 2 : (k == j + 1 ? 3 : -1)));
+      if (role < 0) continue;
+      const int a = D.chain_node[ch.node_tab + i], b = D.chain_node[ch.node_tab + i + 1];
+      const int c = D.chain_node[ch.node_tab + j], d = D.chain_node[ch.node_tab + j + 1];
+      const v3 pa = ld3(D.x, NN, a), pb = ld3(D.x, NN, b), pc = ld3(D.x, NN, c), pd = ld3(D.x, NN, d);
+      const double p1[3] = {pa.x, pa.y, pa.z}, u[3] = {pb.x - pa.x, pb.y - pa.y, pb.z - pa.z};
+      const double p2[3] = {pc.x, pc.y, pc.z}, v[3] = {pd.x - pc.x, pd.y - pc.y, pd.z - pc.z};
+      double s, t, r[3];
+      const double Dd = sqrt(seg_closest(p1, u, p2, v, s, t, r));
+      double E1, E2;
+      sc_profile(Dd, D.radius[a] + D.radius[c], delta, E1, E2);
+      const double cw[4] = {1.0 - s, s, -(1.0 - t), -t};
+      const double w = cw[role], invD = Dd > 0.0 ? 1.0 / Dd : 0.0;
+      // this node's block of D_x, of f_xs and f_xt (closed forms of the pair terms)
+      double gD[3], Gs[3], Gt[3];
+#pragma unroll
+      for (int al = 0; al < 3; ++al) {
+        gD[al] = w * r[al] * invD;
+        Gs[al] = (role == 0 ? -r[al] : (role == 1 ? r[al] : 0.0)) + w * u[al];
+        Gt[al] = (role == 2 ? r[al] : (role == 3 ? -r[al] : 0.0)) - w * v[al];
+      }
+      const bool fs = s > 0.0 && s < 1.0, ft = t > 0.0 && t < 1.0;
+      const double zss = seg_dot(u, u), ztt = seg_dot(v, v), zst = -seg_dot(u, v);
+      double M00 = 0.0, M01 = 0.0, M11 = 0.0;
+      if (fs && ft) {
+        const double det = zss * ztt - zst * zst;
+        M00 = ztt / det;
+        M11 = zss / det;
+        M01 = -zst / det;
+      } else if (fs) {
+        M00 = 1.0 / zss;
+      } else if (ft) {
+        M11 = 1.0 / ztt;
+      }
+#pragma unroll
+      for (int al = 0; al < 3; ++al) {
+        g[al] += kc * E1 * gD[al];
+        const double Ws = Gs[al] * M00 + Gt[al] * M01, Wt = Gs[al] * M01 + Gt[al] * M11;
+#pragma unroll
+        for (int be = 0; be < 3; ++be) {
+          const double fxx = al == be ? w * w : 0.0;
+          H[al][be] += kc * E2 * gD[al] * gD[be] + kc * E1 * invD * (fxx - (Ws * Gs[be] + Wt * Gt[be]) - gD[al] * gD[be]);
+        }
+      }
+      if (mu > 0.0 && E1 != 0.0 && Dd > 0.0) {
+        // friction on edge i (Eq. 12-13): u_t the tangential relative velocity of the closest
+        // points over the step at (s, t); edge j takes the opposite force
+        const v3 qa = ld3(D.x0, NN, a), qb = ld3(D.x0, NN, b), qc = ld3(D.x0, NN, c), qd = ld3(D.x0, NN, d);
+        double vr[3];
+        const double pn[3][4] = {{qa.x, qb.x, qc.x, qd.x}, {qa.y, qb.y, qc.y, qd.y}, {qa.z, qb.z, qc.z, qd.z}};
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+          const double Pn = pn[al][0] + s * (pn[al][1] - pn[al][0]), Qn = pn[al][2] + t * (pn[al][3] - pn[al][2]);
+          vr[al] = (r[al] - (Pn - Qn)) / dt;
+        }
+        const double vn = seg_dot(vr, r) * invD * invD;
+        double ut[3];
+#pragma unroll
+        for (int al = 0; al < 3; ++al) ut[al] = vr[al] - vn * r[al];
+        const double un = sqrt(seg_dot(ut, ut));
+        if (un > 0.0) {
+          const double gamma = 2.0 / (1.0 + exp(-K2 * un)) - 1.0;
+          const double m = -mu * gamma * kc * fabs(E1) / un;
+#pragma unroll
+          for (int al = 0; al < 3; ++al) g[al] -= w * m * ut[al];      // residual: minus the force
+        }
+      }
+    }
+    const int n0 = D.chain_node[ch.node_tab + k];
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+      D.nd[al * NN + n0] += g[al];
+#pragma unroll
+      for (int be = 0; be < 3; ++be) D.nd[(3 + 3 * al + be) * NN + n0] += H[al][be];
+    }
+  }
 }
 
 // Band rows of every chain node of the system; returns this lane's share of the squared
@@ -1750,10 +1942,14 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
   int DM_L* flags = (int DM_L*)(red + 40);      // [4]; then border term segment sums at red + 42
   unsigned short DM_L* hbuf = (unsigned short DM_L*)((char DM_L*)lds_raw + A.net_lds);   // network (warm == 2)
   const int tid = threadIdx.x, wave = tid >> 6, nwaves = blockDim.x >> 6;
+  // self-contact pair list (LDS) and its overflow flag
+  char DM_L* sc_lds = (char DM_L*)lds_raw + A.sc_lds;
+  int DM_L* sc_over = (int DM_L*)(sc_lds + 24 * (size_t)A.sc_max_edges + 4 * (size_t)A.sc_cap) + 1;
   if (tid == 0) {
     flags[0] = 0;
     red[37] = 0.0;      // largest floor-ended residual of this launch and its floor estimate
     red[38] = 0.0;
+    if (A.sc_on) *sc_over = 0;
   }
   int status = DM_STATUS_OK, iters = 0, steps = 0, floor_hits = 0, fallbacks = 0, halved = 0;
   double res = 0.0;
@@ -1794,6 +1990,11 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
           eval_stencil_grads(Ap, sid, t_end);
           eval_edges_nodes(Ap, sid, hn);
           __syncthreads();
+          if (A.sc_on) {
+            self_contact(Ap, sid, hn, sc_lds);
+            __syncthreads();
+            if (*sc_over) break;        // more pairs than the list holds: the system fails
+          }
           DM_TP(0);
           double r2 = assemble_band<1>(Ap, sid, hn);
           __syncthreads();
@@ -1860,8 +2061,9 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
       iters += newton;
       if (!conv) {
         const bool singular = flags[0] != 0;
+        const bool overflow = A.sc_on && *sc_over;
         rollback(Ap, sid);
-        if (lev < A.max_halvings) {
+        if (lev < A.max_halvings && !overflow) {
           ++lev;
           idx *= 2;
           ++halved;
@@ -1870,7 +2072,7 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
           continue;
         }
         // the system stays at the end of its last converged substep
-        status = singular ? DM_STATUS_SINGULAR : DM_STATUS_NOT_CONVERGED;
+        status = overflow ? DM_STATUS_CONTACT_OVERFLOW : (singular ? DM_STATUS_SINGULAR : DM_STATUS_NOT_CONVERGED);
         failed = true;
         break;
       }

@@ -120,6 +120,7 @@ struct DmDev {
   // edges
   const int DM_C* en;           // [2][n_edges] tail, head
   const double DM_C* ebar;
+  const double DM_C* arc0;      // rest arclength of the edge's rod at its first node
   const double DM_C* EA;
   const double DM_C* Ith;
   const double DM_C* moment;
@@ -208,6 +209,9 @@ struct DmStepArgs {
   int n_systems;
   int max_nb, max_arms;
   int max_seg;     // largest number of border term segments of a system (LDS partial sums)
+  // edge-edge self-contact of single-rod systems (off: sc_on = 0)
+  int sc_on, sc_cap, sc_max_edges, sc_lds;   // pair slots per system (a power of two), LDS offset
+  double sc_delta, sc_kc, sc_mu, sc_nu;
 };
 
 // Discrete adjoint of a stored trajectory segment (single-rod systems without contact).

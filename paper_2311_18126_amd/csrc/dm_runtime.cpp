@@ -93,6 +93,9 @@ struct dm_sim {
   // layout
   int n_nodes = 0, n_edges = 0, n_st = 0, n_sys = 0, n_chains = 0, n_arms = 0, n_dof = 0;
   int max_nb = 0, max_arms = 0, max_seg = 0, block = 0;
+  // edge-edge self-contact of single-rod systems (dm_set_self_contact)
+  int sc_on = 0, sc_max_edges = 0;
+  double sc_delta = 0.0, sc_kc = 0.0, sc_mu = 0.0, sc_nu = 1.0;
   std::vector<int> rod_sys;
   std::vector<std::vector<int>> rod_node, rod_edge;   // global ids per rod node / edge
   std::vector<int> rod_st0;                            // global stencil id of rod node 1
@@ -705,7 +708,12 @@ dm_status do_finalize(dm_sim* s) {
   UP(mass, mass) UP(radius, radius)
   std::vector<double> forceS = soa3(force);
   UP(forceS, force) UP(node_owner, node_owner) UP(nh, node_home)
-  UP(en, en) UP(ebar, ebar) UP(EA, EA) UP(Ith, Ith) UP(moment, moment) UP(edge_home, edge_home)
+  std::vector<double> arc0(ebar.size(), 0.0);
+  for (int r = 0; r < nr; ++r) {
+    double acc = 0.0;
+    for (int e : s->rod_edge[r]) { arc0[e] = acc; acc += ebar[e]; }
+  }
+  UP(en, en) UP(ebar, ebar) UP(arc0, arc0) UP(EA, EA) UP(Ith, Ith) UP(moment, moment) UP(edge_home, edge_home)
   UP(sn, sn) UP(se, se) UP(ssign, ssign) UP(Vbar, Vbar) UP(kbend, kbend) UP(ktwist, ktwist)
   UP(s->h_kbar, kbar) UP(tbar, tbar) UP(s->h_act, act)
   std::vector<double> XS = soa3(X), trefS = soav(tref), d1S = soav(d1ref);
@@ -812,13 +820,29 @@ void fill_step_args(const dm_sim* s, double dt, int nsteps, DmStepArgs& A) {
   A.max_seg = std::max(s->max_seg, 1);
   A.warm = s->ws_mode;
   if (s->ws_mode == 2) dm_mlp_view(s->ws_net, &A.net);
+  if (s->sc_on) {
+    A.sc_on = 1;
+    A.sc_max_edges = std::max(s->sc_max_edges, 1);
+    int cap = 64;
+    while (cap < 4 * A.sc_max_edges) cap <<= 1;    // pair slots: four per edge, a power of two
+    A.sc_cap = cap;
+    A.sc_delta = s->sc_delta;
+    A.sc_kc = s->sc_kc;
+    A.sc_mu = s->sc_mu;
+    A.sc_nu = s->sc_nu;
+  }
 }
 
 // LDS bytes of a step launch; places the network's activations (warm mode 2) after the
 // solver's arrays, 16-byte aligned.
 size_t step_lds(DmStepArgs& A) {
-  const size_t base = sizeof(double) * ((size_t)A.max_nb * (A.max_nb + 1) + (size_t)A.max_arms * 110 + A.max_nb +
-                                         40 + 2 + (size_t)A.max_seg);
+  size_t base = sizeof(double) * ((size_t)A.max_nb * (A.max_nb + 1) + (size_t)A.max_arms * 110 + A.max_nb +
+                                   40 + 2 + (size_t)A.max_seg);
+  if (A.sc_on) {
+    // self-contact: boxes [6][max edges] floats, pair keys [cap], count and overflow flag
+    A.sc_lds = (int)((base + 15) / 16 * 16);
+    base = (size_t)A.sc_lds + 24 * (size_t)A.sc_max_edges + 4 * (size_t)A.sc_cap + 8;
+  }
   if (A.warm != 2) return base;
   A.net_lds = (int)((base + 15) / 16 * 16);
   return (size_t)A.net_lds + DM_NET_LDS_BYTES;
@@ -977,7 +1001,7 @@ dm_status worst_status(dm_sim* s) {
   DM_HIP(hipStreamSynchronize(s->stream));
   dm_status w = DM_OK;
   for (int v : status) {
-    if (v == DM_ERR_SINGULAR) w = DM_ERR_SINGULAR;
+    if (v == DM_ERR_SINGULAR || v == DM_ERR_UNSUPPORTED) w = DM_ERR_SINGULAR;
     else if (v == DM_NOT_CONVERGED && w == DM_OK) w = DM_NOT_CONVERGED;
   }
   return w;
@@ -988,6 +1012,7 @@ dm_status adjoint_supported(const dm_sim* s) {
   if (s->scheme != DM_BACKWARD_EULER) return fail(DM_ERR_UNSUPPORTED, "adjoint: only the backward-Euler step");
   if (s->max_halvings != 0) return fail(DM_ERR_UNSUPPORTED, "adjoint: adaptive time stepping is not supported");
   if (s->cfg.floor_contact) return fail(DM_ERR_UNSUPPORTED, "adjoint: floor contact is not supported");
+  if (s->sc_on) return fail(DM_ERR_UNSUPPORTED, "adjoint: self-contact is not supported");
   for (const DmSystem& S : s->sys)
     if (S.n_chains != 1 || S.n_jst != 0) return fail(DM_ERR_UNSUPPORTED, "adjoint: joined rods are not supported");
   for (const Rod& R : s->rods)
@@ -1007,6 +1032,7 @@ dm_status curvature_supported(const dm_sim* s, const char* who) {
   if (!s->finalized) return fail(DM_ERR_STATE, std::string(who) + " before dm_finalize");
   if (s->scheme != DM_BACKWARD_EULER) return fail(DM_ERR_UNSUPPORTED, std::string(who) + ": only the backward-Euler step");
   if (s->cfg.floor_contact) return fail(DM_ERR_UNSUPPORTED, std::string(who) + ": floor contact is not supported");
+  if (s->sc_on) return fail(DM_ERR_UNSUPPORTED, std::string(who) + ": self-contact is not supported");
   for (const Rod& R : s->rods)
     if (R.act) return fail(DM_ERR_UNSUPPORTED, std::string(who) + ": actuated rods are not supported");
   return DM_OK;
@@ -1234,6 +1260,8 @@ dm_status dm_finalize(dm_sim* s) {
 dm_status dm_step(dm_sim* s, double dt, int nsteps, dm_stats* stats) {
   if (!s) return fail(DM_ERR_INVALID_ARG, "null sim");
   if (!s->finalized) return fail(DM_ERR_STATE, "dm_step before dm_finalize");
+  if (s->sc_on && s->scheme != DM_BACKWARD_EULER)
+    return fail(DM_ERR_UNSUPPORTED, "dm_step: self-contact needs the backward-Euler step");
   if (!(dt > 0) || !std::isfinite(dt) || nsteps < 0) return fail(DM_ERR_INVALID_ARG, "dm_step: bad dt or nsteps");
   if (nsteps == 0) return DM_OK;
   DM_HIP(hipSetDevice(s->cfg.device));
@@ -1267,10 +1295,13 @@ dm_status dm_step(dm_sim* s, double dt, int nsteps, dm_stats* stats) {
       stats[i].halvings = halved[i];
       stats[i].floor_residual_max = fres[i]; stats[i].floor_estimate = fest[i];
     }
-    if (status[i] == DM_ERR_SINGULAR) worst = DM_ERR_SINGULAR;
+    if (status[i] == DM_ERR_UNSUPPORTED) worst = DM_ERR_UNSUPPORTED;
+    else if (status[i] == DM_ERR_SINGULAR && worst != DM_ERR_UNSUPPORTED) worst = DM_ERR_SINGULAR;
     else if (status[i] == DM_NOT_CONVERGED && worst == DM_OK) worst = DM_NOT_CONVERGED;
   }
   s->time += dt * nsteps;
+  if (worst == DM_ERR_UNSUPPORTED)
+    return fail(DM_ERR_UNSUPPORTED, "dm_step: more self-contact pairs in some system than its pair list holds");
   if (worst == DM_ERR_SINGULAR) return fail(DM_ERR_SINGULAR, "dm_step: zero or non-finite pivot in some system");
   if (worst == DM_NOT_CONVERGED) { g_err = "dm_step: Newton did not converge in some system"; }
   return worst;
@@ -1323,6 +1354,37 @@ dm_status dm_ws_targets(dm_sim* s, const double* F_prev, double dt, double* T) {
   DM_HIP(hipSetDevice(s->cfg.device));
   DM_HIP(dm_ws_launch_targets(&s->dev, s->ws_rows, s->cn_chain, F_prev, dt, T, s->stream));
   DM_HIP(hipStreamSynchronize(s->stream));
+  return DM_OK;
+}
+
+dm_status dm_set_self_contact(dm_sim* s, double delta, double k_c, double mu, double nu) {
+  if (!s) return fail(DM_ERR_INVALID_ARG, "dm_set_self_contact: null sim");
+  if (!s->finalized) return fail(DM_ERR_STATE, "dm_set_self_contact before dm_finalize");
+  if (k_c == 0.0) {
+    s->sc_on = 0;
+    return DM_OK;
+  }
+  if (!(delta > 0.0) || !(k_c > 0.0) || !(mu >= 0.0) || !(nu > 0.0) || !std::isfinite(delta) || !std::isfinite(k_c) ||
+      !std::isfinite(mu) || !std::isfinite(nu))
+    return fail(DM_ERR_INVALID_ARG, "dm_set_self_contact: need delta > 0, k_c > 0, mu >= 0, nu > 0");
+  int me = 0;
+  for (const DmSystem& S : s->sys) {
+    if (S.n_chains != 1) return fail(DM_ERR_UNSUPPORTED, "dm_set_self_contact: joined rods are not supported");
+    me = std::max(me, S.n_edges);
+  }
+  if (me > 4096) return fail(DM_ERR_UNSUPPORTED, "dm_set_self_contact: rods of more than 4097 nodes");
+  s->sc_on = 1;
+  s->sc_max_edges = me;
+  s->sc_delta = delta;
+  s->sc_kc = k_c;
+  s->sc_mu = mu;
+  s->sc_nu = nu;
+  DmStepArgs A;
+  fill_step_args(s, 1.0, 1, A);
+  if (step_lds(A) > 65536) {
+    s->sc_on = 0;
+    return fail(DM_ERR_UNSUPPORTED, "dm_set_self_contact: the pair list of the longest rod does not fit in LDS");
+  }
   return DM_OK;
 }
 

@@ -1,0 +1,111 @@
+"""Edge-edge self-contact inside the GPU step (dm_set_self_contact) against the oracle's
+step with self-contact (oracle/der.py, pinned in tests/test_oracle_self_contact.py).
+
+The GPU's Newton matrix keeps only each node's own block of the contact Hessian, the oracle's
+is exact, so the two iterate differently and stop at different points within the Newton
+tolerance (1e-9 N of residual): positions agree to 1e-9 relative and the step's displacement
+to 1e-6 after one step, and to 1e-6 after three steps."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import der
+from parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dm():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2311_18126_amd as m
+    assert os.path.exists(m.LIB_PATH), "libdmrod.so is not built"
+    return m
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_coils_match_live_oracle(dm, mu):
+    d = W.coiled_springs(2, seed=13, nmin=36, nmax=44, mu=mu)
+    say(f"case: two coils with self-contact, mu {mu}")
+    sim = dm.sim_from_description(d)
+    iters_gpu = 0
+    oracles = []
+    for r in range(2):
+        sub = W.subset(d, [r])
+        sub["self_contact"] = d["self_contact"]
+        oracles.append(list(der.build(sub)))
+    x0 = [sim.rod_state(r)[0].copy() for r in range(2)]
+    done = 0
+    for k in (1, 3):
+        st = sim.step(d["dt"], k - done)
+        assert (st["status"] == 0).all()
+        iters_gpu += int(st["iters"].sum())
+        for r in range(2):
+            sys_, s_ = oracles[r]
+            for _ in range(k - done):
+                s_, info = der.step(sys_, s_, d["dt"], d["tol"], d["max_iter"])
+                assert info.converged
+            oracles[r][1] = s_
+            n_pairs = len(der.contact_list(sys_, der.pack(s_.x, s_.theta)))
+            assert n_pairs > 40
+            assert_parity(sim.rod_state(r)[0], s_.x.numpy(), x0[r], 1e-9 if k == 1 else 1e-6, 1e-6,
+                          f"coil {r} step {k} ({n_pairs} pairs)")
+        done = k
+    say(f"GPU Newton iterations over 3 steps of 2 coils: {iters_gpu}")
+
+
+def test_off_is_the_plain_step_bit_for_bit(dm):
+    d = W.coiled_springs(2, seed=13, nmin=36, nmax=44)
+    plain = dict(d)
+    plain.pop("self_contact")
+    a = dm.sim_from_description(plain)
+    b = dm.sim_from_description(d)
+    b.set_self_contact(0.0, 0.0)
+    a.step(d["dt"], 3)
+    b.step(d["dt"], 3)
+    assert np.array_equal(a.state()[0], b.state()[0])
+    c = dm.sim_from_description(d)
+    c.step(d["dt"], 3)
+    assert not np.array_equal(a.state()[0], c.state()[0])
+
+
+def test_pair_list_overflow_is_reported(dm):
+    """An accordion-folded rod (pleats of four 5 mm edges, 3 mm apart) puts every edge within
+    reach of edges of several pleats: more than four pairs per edge, DM_ERR_UNSUPPORTED, and
+    the rod stays at the step start."""
+    pts = []
+    for p in range(15):
+        xs = np.linspace(0.0, 0.02, 5) if p % 2 == 0 else np.linspace(0.02, 0.0, 5)
+        pts += [(x, 0.003 * p, 0.0) for j, x in enumerate(xs) if p == 0 or j > 0]
+    x0 = np.array(pts)
+    d = W.desc([W.rod(x0, 4e-3, 1e6)], dt=1e-3, steps=1, gravity=(0.0, 0.0, 0.0))
+    sim = dm.sim_from_description(d)
+    sim.set_self_contact(5e-4, 10.0)
+    before = sim.state()[0].copy()
+    with pytest.raises(dm.DmError) as e:
+        sim.step(d["dt"], 1)
+    assert e.value.status == dm.DM_ERR_UNSUPPORTED and "pair list" in str(e.value)
+    assert np.array_equal(sim.state()[0], before)
+
+
+def test_unsupported_setups(dm):
+    star = W.star_robots(n_instances=1, steps=1)
+    sim = dm.sim_from_description(star)
+    with pytest.raises(dm.DmError) as e:
+        sim.set_self_contact(5e-4, 10.0)
+    assert e.value.status == dm.DM_ERR_UNSUPPORTED
+    d = W.coiled_springs(1, seed=13, nmin=36, nmax=36)
+    sim = dm.sim_from_description(d)
+    with pytest.raises(dm.DmError):
+        sim.set_self_contact(-1.0, 10.0)
+    sim.set_integrator("midpoint")
+    with pytest.raises(dm.DmError) as e:
+        sim.step(d["dt"], 1)
+    assert e.value.status == dm.DM_ERR_UNSUPPORTED
