@@ -40,7 +40,7 @@ INFER_FLOPS_PER_ROW = 2 * (26 * 256 + 256 * 256 + 256 * 3)
 TRAIN_FLOPS_PER_ROW = 2 * INFER_FLOPS_PER_ROW + 2 * (256 * 3 + 256 * 256)
 KERNEL_SOURCES = ["paper_2311_18126_amd/csrc/dm_kernels.hip", "paper_2311_18126_amd/csrc/dm_math.h",
                   "paper_2311_18126_amd/csrc/dm_layout.h", "paper_2311_18126_amd/csrc/dm_warm.h",
-                  "paper_2311_18126_amd/csrc/dm_bf16.h"]
+                  "paper_2311_18126_amd/csrc/dm_bf16.h", "paper_2311_18126_amd/csrc/dm_segment.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "dm_step_kernel_rod_batch_traffic.json")
 
 
@@ -279,6 +279,38 @@ def midpoint_section(dm, steps):
            "value": nodes * steps / wall, "unit": "node-steps/s",
            "newton_iters_per_step": float(st["iters"].mean() / steps), "block_size": sim.block_size}
     sim.close()
+    return out
+
+
+def self_contact_section(dm, steps, n_rods=4096):
+    """Coiled springs whose turns press on each other under gravity, stepped with each rod's
+    edge-edge self-contact and friction inside the implicit step (pairs found at every Newton
+    iterate, each rod's Newton matrix with its pairs' blocks), line search and adaptive halving
+    (three levels), and the same batch without self-contact (band solve) for comparison."""
+    import workloads as W
+    d = W.coiled_springs(n_rods, steps=steps)
+    out = {"workload": f"{n_rods} coiled springs: N ~ U{{40..80}}, h = 4 mm, pitch 8.1-8.4 mm, delta = 5e-4 m, "
+                       f"mu = 0.3 (seed 13)", "steps": steps, "unit": "node-steps/s"}
+    for key, on in (("with_self_contact", True), ("without", False)):
+        dd = dict(d)
+        if not on:
+            dd.pop("self_contact")
+        sim = dm.sim_from_description(dd)
+        sim.set_adaptive(3)
+        sim.step(d["dt"], 1)
+        import torch
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = sim.step(d["dt"], steps, allow_failure=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        failed = int((st["status"] != 0).sum())
+        # a system that fails stops early, so the rate is reported only when none did
+        out[key] = {"value": float(sim.num_nodes) * steps / wall if failed == 0 else None,
+                    "ms_per_step": 1e3 * wall / steps, "failed_systems": failed,
+                    "newton_iters_per_step": float(st["iters"].mean() / steps),
+                    "halved_steps": int(st["halvings"].sum())}
+        sim.close()
     return out
 
 
@@ -675,6 +707,7 @@ def main():
         out["adjoint"] = adjoint_section(dm)
         out["real2sim"] = real2sim_section(dm)
         out["contact"] = contact_section(dm)
+        out["self_contact"] = self_contact_section(dm, 20, n_rods=256)
     if not args.no_per_rod:
         out["per_rod_plain_value"] = per_rod_baseline(dm, desc, min(args.steps, 20))
     if not args.no_cpu_baseline:

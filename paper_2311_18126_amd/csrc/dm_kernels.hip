@@ -457,6 +457,14 @@ __device__ __noinline__ void eval_edges_nodes(ArgsP Ap, int sid, double dt) {
   for (int i = threadIdx.x; i < S.n_nodes; i += blockDim.x) eval_node(A, S.node0 + i, dt);
 }
 
+// LDS operations of a wavefront stay in program order: this keeps the compiler from moving
+// them across (the hardware runs one wavefront's LDS instructions in order).
+__device__ __forceinline__ void lds_order() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------------------
 // edge-edge self-contact of a single rod (Contact and Friction subsection: Eq. 10-13 applied
 // to pairs of the rod's edges)
@@ -486,15 +494,176 @@ __device__ __forceinline__ float sc_up(double v) {
   return (double)f < v ? nextafterf(f, INFINITY) : f;
 }
 
+// One pair of a rod's edges at the current iterate: the nodes of its roles (edge i's nodes a, b,
+// edge j's nodes c, d), the closest-point parameters (s, t), r = P(s) - Q(t), the edge vectors,
+// D, the contact profile's E_c' and E_c'', the inverse of f_zz over the free parameters and, with
+// friction, the slip quantities of Eq. 12-13 at (s, t).
+struct ScPair {
+  int node[4];
+  double s, t, r[3], u[3], v[3], Dd, invD, E1, E2, M00, M01, M11;
+  bool fric;
+  double un, ut[3], vr[3], u0[3], v0[3];
+};
+
+__device__ __forceinline__ void sc_pair(const DmDev DM_C& D, const DmChain& ch, int key, double delta, double mu,
+                                        ScPair& P) {
+  const int NN = D.n_nodes_tot, i = key >> 16, j = key & 0xffff;
+  P.node[0] = D.chain_node[ch.node_tab + i];
+  P.node[1] = D.chain_node[ch.node_tab + i + 1];
+  P.node[2] = D.chain_node[ch.node_tab + j];
+  P.node[3] = D.chain_node[ch.node_tab + j + 1];
+  const v3 pa = ld3(D.x, NN, P.node[0]), pb = ld3(D.x, NN, P.node[1]);
+  const v3 pc = ld3(D.x, NN, P.node[2]), pd = ld3(D.x, NN, P.node[3]);
+  const double p1[3] = {pa.x, pa.y, pa.z}, p2[3] = {pc.x, pc.y, pc.z};
+  P.u[0] = pb.x - pa.x; P.u[1] = pb.y - pa.y; P.u[2] = pb.z - pa.z;
+  P.v[0] = pd.x - pc.x; P.v[1] = pd.y - pc.y; P.v[2] = pd.z - pc.z;
+  P.Dd = sqrt(seg_closest(p1, P.u, p2, P.v, P.s, P.t, P.r));
+  P.invD = P.Dd > 0.0 ? 1.0 / P.Dd : 0.0;
+  sc_profile(P.Dd, D.radius[P.node[0]] + D.radius[P.node[2]], delta, P.E1, P.E2);
+  const bool fs = P.s > 0.0 && P.s < 1.0, ft = P.t > 0.0 && P.t < 1.0;
+  const double zss = seg_dot(P.u, P.u), ztt = seg_dot(P.v, P.v), zst = -seg_dot(P.u, P.v);
+  P.M00 = P.M01 = P.M11 = 0.0;
+  if (fs && ft) {
+    const double det = zss * ztt - zst * zst;
+    P.M00 = ztt / det;
+    P.M11 = zss / det;
+    P.M01 = -zst / det;
+  } else if (fs) {
+    P.M00 = 1.0 / zss;
+  } else if (ft) {
+    P.M11 = 1.0 / ztt;
+  }
+  P.fric = mu > 0.0 && P.E1 != 0.0 && P.Dd > 0.0;
+  P.un = 0.0;
+  if (P.fric) {
+    const v3 qa = ld3(D.x0, NN, P.node[0]), qb = ld3(D.x0, NN, P.node[1]);
+    const v3 qc = ld3(D.x0, NN, P.node[2]), qd = ld3(D.x0, NN, P.node[3]);
+    const double pn[3][4] = {{qa.x, qb.x, qc.x, qd.x}, {qa.y, qb.y, qc.y, qd.y}, {qa.z, qb.z, qc.z, qd.z}};
+#pragma unroll
+    for (int al = 0; al < 3; ++al) {
+      const double Pn = pn[al][0] + P.s * (pn[al][1] - pn[al][0]), Qn = pn[al][2] + P.t * (pn[al][3] - pn[al][2]);
+      P.vr[al] = P.r[al] - (Pn - Qn);       // the slip over the step; divided by dt where used
+      P.u0[al] = pn[al][1] - pn[al][0];     // the edges at the step start
+      P.v0[al] = pn[al][3] - pn[al][2];
+    }
+    const double vn = seg_dot(P.vr, P.r) * P.invD * P.invD;
+#pragma unroll
+    for (int al = 0; al < 3; ++al) P.ut[al] = P.vr[al] - vn * P.r[al];
+    P.un = sqrt(seg_dot(P.ut, P.ut));
+  }
+}
+
+// Closest-point weight of role k, and this role's block of D_x and of f_xs, f_xt.
+__device__ __forceinline__ double sc_role(const ScPair& P, int k, double gD[3], double Gs[3], double Gt[3]) {
+  const double w = k == 0 ? 1.0 - P.s : (k == 1 ? P.s : (k == 2 ? -(1.0 - P.t) : -P.t));
+#pragma unroll
+  for (int al = 0; al < 3; ++al) {
+    gD[al] = w * P.r[al] * P.invD;
+    Gs[al] = (k == 0 ? -P.r[al] : (k == 1 ? P.r[al] : 0.0)) + w * P.u[al];
+    Gt[al] = (k == 2 ? P.r[al] : (k == 3 ? -P.r[al] : 0.0)) - w * P.v[al];
+  }
+  return w;
+}
+
+// Block (rows of role k, columns of role l) of the pair's Jacobian: the contact energy's
+// Hessian k_c (E_c'' D_x D_x^T + E_c' D_xx), D_xx = (F_xx - D_x D_x^T) / D with
+// F_xx = f_xx - f_xz f_zz^-1 f_zx over the free parameters, and the derivative of the friction
+// term: with rho = mu F_n gamma(|u|) u_hat the friction residual of role k is w_k rho,
+// F_n = k_c |E_c'|, u = P_t vr / dt (vr here the slip over the step), so at fixed (s, t)
+// d(w_k rho)/dx_l = w_k (mu F_n K du/dx_l + mu gamma u_hat dF_n/dx_l), K = d(gamma u_hat)/du,
+// du/dx_l = w_l (P_t / dt - (n (P_t vr)^T + (vr.n) P_t) / (D dt)); the closest-point
+// parameters move with the nodes, dz/dx_l = -f_zz^-1 f_zx_l over the free ones, which adds
+// d(w_k rho)/dz dz/dx_l (D is stationary in z, so F_n is not).
+__device__ __forceinline__ void sc_block(const ScPair& P, int k, int l, double kc, double mu, double K2, double dt,
+                                         double H[3][3]) {
+  double gk[3], sk[3], tk[3], gl[3], sl[3], tl[3];
+  const double wk = sc_role(P, k, gk, sk, tk), wl = sc_role(P, l, gl, sl, tl);
+#pragma unroll
+  for (int al = 0; al < 3; ++al) {
+    const double Ws = sk[al] * P.M00 + tk[al] * P.M01, Wt = sk[al] * P.M01 + tk[al] * P.M11;
+#pragma unroll
+    for (int be = 0; be < 3; ++be) {
+      const double fxx = al == be ? wk * wl : 0.0;
+      H[al][be] = kc * P.E2 * gk[al] * gl[be] + kc * P.E1 * P.invD * (fxx - (Ws * sl[be] + Wt * tl[be]) - gk[al] * gl[be]);
+    }
+  }
+  if (!P.fric) return;
+  const double Fn = kc * fabs(P.E1), idt = 1.0 / dt;
+  const double u = P.un * idt;                       // |u|, the tangential slip velocity
+  double n[3], uh[3], Kf[3][3], Q[3][3];
+#pragma unroll
+  for (int al = 0; al < 3; ++al) {
+    n[al] = P.r[al] * P.invD;
+    uh[al] = u > 0.0 ? P.ut[al] / P.un : 0.0;
+  }
+  const double z = 0.5 * K2 * u, th = tanh(z);
+  const double gam = th;                             // gamma(u) = tanh(K2 u / 2)
+  const double gp = 0.5 * K2 * (1.0 - th * th);      // gamma'(u)
+  const double gu = u > 0.0 ? th / u : 0.5 * K2;     // gamma(u) / u
+  const double vn = seg_dot(P.vr, n) * idt;
+  double ptv[3];                                     // P_t vr / dt
+#pragma unroll
+  for (int al = 0; al < 3; ++al) ptv[al] = P.vr[al] * idt - vn * n[al];
+#pragma unroll
+  for (int al = 0; al < 3; ++al)
+#pragma unroll
+    for (int be = 0; be < 3; ++be) {
+      const double id = al == be ? 1.0 : 0.0, Pt = id - n[al] * n[be];
+      Kf[al][be] = u > 0.0 ? gp * uh[al] * uh[be] + gu * (id - uh[al] * uh[be]) : gu * id;
+      Q[al][be] = Pt * idt - (n[al] * ptv[be] + vn * Pt) * P.invD;
+    }
+  const double c1 = wk * wl * mu * Fn, c2 = -wk * mu * gam * kc * P.E2;
+#pragma unroll
+  for (int al = 0; al < 3; ++al)
+#pragma unroll
+    for (int be = 0; be < 3; ++be) {
+      const double kq = Kf[al][0] * Q[0][be] + Kf[al][1] * Q[1][be] + Kf[al][2] * Q[2][be];
+      H[al][be] += c1 * kq + c2 * uh[al] * gl[be];
+    }
+  // through (s, t): du/ds and du/dt at fixed nodes
+  double du[3], dv[3], nu_ = 0.0, nv_ = 0.0, nu0 = 0.0, nv0 = 0.0;
+#pragma unroll
+  for (int al = 0; al < 3; ++al) {
+    du[al] = P.u[al] - P.u0[al];
+    dv[al] = P.v[al] - P.v0[al];
+    nu_ += n[al] * P.u[al];
+    nv_ += n[al] * P.v[al];
+    nu0 += n[al] * du[al];
+    nv0 += n[al] * dv[al];
+  }
+  const double pu = seg_dot(ptv, P.u), pv = seg_dot(ptv, P.v);
+  double dus[3], dut[3];
+#pragma unroll
+  for (int al = 0; al < 3; ++al) {
+    dus[al] = (du[al] - n[al] * nu0) * idt - (n[al] * pu + vn * (P.u[al] - n[al] * nu_)) * P.invD;
+    dut[al] = -(dv[al] - n[al] * nv0) * idt + (n[al] * pv + vn * (P.v[al] - n[al] * nv_)) * P.invD;
+  }
+  const double dws = k == 0 ? -1.0 : (k == 1 ? 1.0 : 0.0), dwt = k == 2 ? 1.0 : (k == 3 ? -1.0 : 0.0);
+  double dRs[3], dRt[3], dsx[3], dtx[3];
+#pragma unroll
+  for (int al = 0; al < 3; ++al) {
+    const double rho = mu * Fn * gam * uh[al];
+    dRs[al] = dws * rho + wk * mu * Fn * (Kf[al][0] * dus[0] + Kf[al][1] * dus[1] + Kf[al][2] * dus[2]);
+    dRt[al] = dwt * rho + wk * mu * Fn * (Kf[al][0] * dut[0] + Kf[al][1] * dut[1] + Kf[al][2] * dut[2]);
+    dsx[al] = -(P.M00 * sl[al] + P.M01 * tl[al]);
+    dtx[al] = -(P.M01 * sl[al] + P.M11 * tl[al]);
+  }
+#pragma unroll
+  for (int al = 0; al < 3; ++al)
+#pragma unroll
+    for (int be = 0; be < 3; ++be) H[al][be] += dRs[al] * dsx[be] + dRt[al] * dtx[be];
+}
+
 // Self-contact of the rod of system sid at the current iterate.  The pairs of its edges within
 // reach, D < h_i + h_j + delta, are found over all pairs i < j by a test of boxes inflated by
 // h + delta / 2 (rounded outward to float32 in LDS), the rest-arclength exclusion (edges closer
 // than h_i + h_j + delta along the rest rod are never a pair) and the exact segment distance,
-// and sorted in LDS.  Then each node adds, over its pairs, the contact energy's gradient minus
-// the friction force to its residual terms, and its own 3 x 3 block of the contact Hessian to
-// its Jacobian block.  The couplings between different nodes of a pair are off the rod's band
-// and are left out of the Newton matrix: the residual is exact, the Newton matrix approximate.
-// LDS: box [6][sc_max_edges] floats, keys [sc_cap] ints, the pair count and the overflow flag.
+// and sorted in LDS; the sorted list stays in LDS for the Newton solve of the same iterate
+// (sc_solve).  Then each node adds, over its pairs, the contact energy's gradient minus the
+// friction force to its residual terms, and its own 3 x 3 block of the pair Jacobian to its
+// Jacobian block; sc_solve adds the blocks between different nodes.
+// LDS: box [6][sc_max_edges] floats, keys [sc_cap] ints, four ints (pair count, overflow flag,
+// half bandwidth), then sc_solve's vectors.
 __device__ __noinline__ void self_contact(ArgsP Ap, int sid, double dt, char DM_L* sc_lds) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   const DmDev DM_C& D = A.d;
@@ -503,7 +672,7 @@ __device__ __noinline__ void self_contact(ArgsP Ap, int sid, double dt, char DM_
   const int N = ch.n_nodes, E = N - 1, NN = D.n_nodes_tot, ME = A.sc_max_edges, cap = A.sc_cap;
   float DM_L* box = (float DM_L*)sc_lds;
   int DM_L* keys = (int DM_L*)(box + 6 * ME);
-  int DM_L* cnt = keys + cap;            // [0] pair count, [1] overflow flag
+  int DM_L* cnt = keys + cap;
   const double delta = A.sc_delta;
   const int tid = threadIdx.x, bd = blockDim.x;
   if (tid == 0) cnt[0] = 0;
@@ -571,71 +740,27 @@ __device__ __noinline__ void self_contact(ArgsP Ap, int sid, double dt, char DM_
       const int key = keys[q], i = key >> 16, j = key & 0xffff;
       const int role = k == i ? 0 : (k == i + 1 ? 1 : (k == j ? 2 : (k == j + 1 ? 3 : -1)));
       if (role < 0) continue;
-      const int a = D.chain_node[ch.node_tab + i], b = D.chain_node[ch.node_tab + i + 1];
-      const int c = D.chain_node[ch.node_tab + j], d = D.chain_node[ch.node_tab + j + 1];
-      const v3 pa = ld3(D.x, NN, a), pb = ld3(D.x, NN, b), pc = ld3(D.x, NN, c), pd = ld3(D.x, NN, d);
-      const double p1[3] = {pa.x, pa.y, pa.z}, u[3] = {pb.x - pa.x, pb.y - pa.y, pb.z - pa.z};
-      const double p2[3] = {pc.x, pc.y, pc.z}, v[3] = {pd.x - pc.x, pd.y - pc.y, pd.z - pc.z};
-      double s, t, r[3];
-      const double Dd = sqrt(seg_closest(p1, u, p2, v, s, t, r));
-      double E1, E2;
-      sc_profile(Dd, D.radius[a] + D.radius[c], delta, E1, E2);
-      const double cw[4] = {1.0 - s, s, -(1.0 - t), -t};
-      const double w = cw[role], invD = Dd > 0.0 ? 1.0 / Dd : 0.0;
-      // this node's block of D_x, of f_xs and f_xt (closed forms of the pair terms)
+      ScPair P;
+      sc_pair(D, ch, key, delta, mu, P);
       double gD[3], Gs[3], Gt[3];
+      const double w = sc_role(P, role, gD, Gs, Gt);
 #pragma unroll
-      for (int al = 0; al < 3; ++al) {
-        gD[al] = w * r[al] * invD;
-        Gs[al] = (role == 0 ? -r[al] : (role == 1 ? r[al] : 0.0)) + w * u[al];
-        Gt[al] = (role == 2 ? r[al] : (role == 3 ? -r[al] : 0.0)) - w * v[al];
-      }
-      const bool fs = s > 0.0 && s < 1.0, ft = t > 0.0 && t < 1.0;
-      const double zss = seg_dot(u, u), ztt = seg_dot(v, v), zst = -seg_dot(u, v);
-      double M00 = 0.0, M01 = 0.0, M11 = 0.0;
-      if (fs && ft) {
-        const double det = zss * ztt - zst * zst;
-        M00 = ztt / det;
-        M11 = zss / det;
-        M01 = -zst / det;
-      } else if (fs) {
-        M00 = 1.0 / zss;
-      } else if (ft) {
-        M11 = 1.0 / ztt;
-      }
-#pragma unroll
-      for (int al = 0; al < 3; ++al) {
-        g[al] += kc * E1 * gD[al];
-        const double Ws = Gs[al] * M00 + Gt[al] * M01, Wt = Gs[al] * M01 + Gt[al] * M11;
-#pragma unroll
-        for (int be = 0; be < 3; ++be) {
-          const double fxx = al == be ? w * w : 0.0;
-          H[al][be] += kc * E2 * gD[al] * gD[be] + kc * E1 * invD * (fxx - (Ws * Gs[be] + Wt * Gt[be]) - gD[al] * gD[be]);
-        }
-      }
-      if (mu > 0.0 && E1 != 0.0 && Dd > 0.0) {
-        // friction on edge i (Eq. 12-13): u_t the tangential relative velocity of the closest
+      for (int al = 0; al < 3; ++al) g[al] += kc * P.E1 * gD[al];
+      if (P.fric && P.un > 0.0) {
+        // friction on edge i (Eq. 12-13): u the tangential relative velocity of the closest
         // points over the step at (s, t); edge j takes the opposite force
-        const v3 qa = ld3(D.x0, NN, a), qb = ld3(D.x0, NN, b), qc = ld3(D.x0, NN, c), qd = ld3(D.x0, NN, d);
-        double vr[3];
-        const double pn[3][4] = {{qa.x, qb.x, qc.x, qd.x}, {qa.y, qb.y, qc.y, qd.y}, {qa.z, qb.z, qc.z, qd.z}};
+        const double un = P.un / dt;
+        const double gamma = 2.0 / (1.0 + exp(-K2 * un)) - 1.0;
+        const double m = -mu * gamma * kc * fabs(P.E1) / un;
 #pragma unroll
-        for (int al = 0; al < 3; ++al) {
-          const double Pn = pn[al][0] + s * (pn[al][1] - pn[al][0]), Qn = pn[al][2] + t * (pn[al][3] - pn[al][2]);
-          vr[al] = (r[al] - (Pn - Qn)) / dt;
-        }
-        const double vn = seg_dot(vr, r) * invD * invD;
-        double ut[3];
-#pragma unroll
-        for (int al = 0; al < 3; ++al) ut[al] = vr[al] - vn * r[al];
-        const double un = sqrt(seg_dot(ut, ut));
-        if (un > 0.0) {
-          const double gamma = 2.0 / (1.0 + exp(-K2 * un)) - 1.0;
-          const double m = -mu * gamma * kc * fabs(E1) / un;
-#pragma unroll
-          for (int al = 0; al < 3; ++al) g[al] -= w * m * ut[al];      // residual: minus the force
-        }
+        for (int al = 0; al < 3; ++al) g[al] -= w * m * (P.ut[al] / dt);      // residual: minus the force
       }
+      double B[3][3];
+      sc_block(P, role, role, kc, mu, K2, dt, B);
+#pragma unroll
+      for (int al = 0; al < 3; ++al)
+#pragma unroll
+        for (int be = 0; be < 3; ++be) H[al][be] += B[al][be];
     }
     const int n0 = D.chain_node[ch.node_tab + k];
 #pragma unroll
@@ -645,6 +770,195 @@ __device__ __noinline__ void self_contact(ArgsP Ap, int sid, double dt, char DM_
       for (int be = 0; be < 3; ++be) D.nd[(3 + 3 * al + be) * NN + n0] += H[al][be];
     }
   }
+}
+
+__device__ __forceinline__ double wave_sum64(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Newton step of a rod with self-contact.  The rod's Jacobian, its band (the border rows'
+// border columns included) plus the blocks between the different nodes of every pair, goes to
+// the system's dense n x n matrix over the half bandwidth w the pairs need (at least the
+// band's 10); LU without pivoting over that band (the pivot guard of the band solve: a pivot
+// below 1e-12 of its assembled diagonal, or not finite, sets the singular flag), forward and
+// back substitution by one wavefront, and the step goes to the delta and border-solution slots
+// the update reads.  Called by the whole workgroup after the matrix pass of the iterate whose
+// pairs self_contact left in LDS.
+__device__ __noinline__ void sc_solve(ArgsP Ap, int sid, double dt, char DM_L* sc_lds, double DM_L* xB,
+                                      int DM_L* flags) {
+  const DmStepArgs DM_C& A = *uniform(Ap);
+  const DmDev DM_C& D = A.d;
+  const DmSystem DM_C& S = D.sys[uniform(sid)];
+  const DmChain ch = D.chain[S.chain0];
+  const int N = ch.n_nodes, n = 4 * N - 1, ME = A.sc_max_edges, cap = A.sc_cap, NN = D.n_nodes_tot;
+  int DM_L* keys = (int DM_L*)(sc_lds + 24 * (size_t)ME);
+  int DM_L* cnt = keys + cap;
+  double DM_L* y = (double DM_L*)(cnt + 4);
+  double DM_L* lcol = y + (4 * ME + 3);
+  double DM_G* M = D.sc_mat + D.sc_off[uniform(sid)];
+  double DM_G* d0 = M + (size_t)n * n;
+  const int np = min(cnt[0], cap), tid = threadIdx.x, bd = blockDim.x, lane = tid & 63;
+  // half bandwidth: the band's, or the widest coupling of a pair (node i's rows, node j+1's
+  // columns)
+  if (tid == 0) cnt[2] = 10;
+  __syncthreads();
+  int wl = 10;
+  for (int q = tid; q < np; q += bd) wl = max(wl, 4 * ((keys[q] & 0xffff) + 1 - (keys[q] >> 16)) + 2);
+  if (wl > 10) atomicMax(cnt + 2, wl);
+  __syncthreads();
+  const int w = min(cnt[2], n - 1), W2 = 2 * w + 1;
+  // the band into the matrix
+  for (int idx = tid; idx < n * W2; idx += bd) {
+    const int r = idx / W2, c = r - w + (idx - r * W2);
+    if (c < 0 || c >= n) continue;
+    const int o = c - r + 10;
+    double v = 0.0;
+    if (o >= 0 && o < DM_NDIAG) {
+      v = D.band[(size_t)(ch.dof_off + r) * DM_NDIAG + o];
+      const unsigned m = D.nmask[4 * (size_t)(ch.node_tab + (r >> 2)) + 1], bit = 1u << (12 + (r & 3));
+      const unsigned f = D.nmask[4 * (size_t)(ch.node_tab + (r >> 2))];
+      if ((m & bit) && !(f & bit)) v += D.bpr[(size_t)(ch.bmap_off + r - ch.b_lo) * DM_NDIAG + o];
+    }
+    M[(size_t)r * n + c] = v;
+    if (c == r) d0[r] = v;
+  }
+  __syncthreads();
+  // the pairs' blocks between different nodes; each lane owns the rows of its node
+  const double kc = A.sc_kc, mu = A.sc_mu, K2 = 15.0 / A.sc_nu, delta = A.sc_delta;
+  for (int k = tid; k < N; k += bd) {
+    const unsigned fk = D.nmask[4 * (size_t)(ch.node_tab + k)] >> 12;
+    for (int q = 0; q < np; ++q) {
+      const int key = keys[q], i = key >> 16, j = key & 0xffff;
+      const int role = k == i ? 0 : (k == i + 1 ? 1 : (k == j ? 2 : (k == j + 1 ? 3 : -1)));
+      if (role < 0) continue;
+      ScPair P;
+      sc_pair(D, ch, key, delta, mu, P);
+      for (int l = 0; l < 4; ++l) {
+        if (l == role) continue;
+        const int kl = l == 0 ? i : (l == 1 ? i + 1 : (l == 2 ? j : j + 1));
+        const unsigned fl = D.nmask[4 * (size_t)(ch.node_tab + kl)] >> 12;
+        double B[3][3];
+        sc_block(P, role, l, kc, mu, K2, dt, B);
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+          if ((fk >> al) & 1u) continue;
+#pragma unroll
+          for (int be = 0; be < 3; ++be)
+            if (!((fl >> be) & 1u)) M[(size_t)(4 * k + al) * n + 4 * kl + be] += B[al][be];
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // LU without pivoting over the band of half width w.  Each lane's entries of an update are
+  // loaded in batches of SB before any of them is stored, so their loads overlap.
+  constexpr int SB = 12;
+  bool bad = false;
+  for (int k = 0; k < n; ++k) {
+    const double p = M[(size_t)k * n + k];
+    if (!(fabs(p) > 1e-12 * fabs(d0[k])) || !isfinite(p)) { bad = true; break; }
+    const int m = min(w, n - 1 - k);
+    if (m == 0) break;
+    const double inv = 1.0 / p;
+    for (int i = tid; i < m; i += bd) lcol[i] = M[(size_t)(k + 1 + i) * n + k] * inv;
+    __syncthreads();
+    const double DM_G* rk = M + (size_t)k * n + k;
+    const int tot = m * (m + 1);
+    for (int b0 = tid; b0 < tot; b0 += SB * bd) {
+      double val[SB], lv[SB], uv[SB];
+      size_t at[SB];
+      unsigned lmask = 0;                  // entries of column k: they take the multiplier
+#pragma unroll
+      for (int q = 0; q < SB; ++q) {
+        const int idx = min(b0 + q * bd, tot - 1);
+        const int i = idx / (m + 1), jj = idx - i * (m + 1);
+        at[q] = (size_t)(k + 1 + i) * n + k + jj;
+        val[q] = M[at[q]];
+        lv[q] = lcol[i];
+        uv[q] = rk[jj];
+        lmask |= (jj == 0 ? 1u : 0u) << q;
+      }
+#pragma unroll
+      for (int q = 0; q < SB; ++q)
+        if (b0 + q * bd < tot) M[at[q]] = ((lmask >> q) & 1u) ? lv[q] : val[q] - lv[q] * uv[q];
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) flags[0] = 1;
+    __syncthreads();
+    return;
+  }
+  // forward and back substitution, one wavefront; a lane holds entries lane and lane + 64 of
+  // a row's band part (w <= 128), and the next row's are loaded before the current row's sum
+  if (tid < 64) {
+    if (w <= 128) {
+      auto fwd = [&](int i, double& a0, double& a1) {
+        const double DM_G* row = M + (size_t)i * n;
+        const int j0 = i - w + lane, j1 = j0 + 64;
+        a0 = (j0 >= 0 && j0 < i) ? row[j0] : 0.0;
+        a1 = (j1 >= 0 && j1 < i) ? row[j1] : 0.0;
+      };
+      double c0, c1, r0 = D.R[ch.dof_off];
+      fwd(0, c0, c1);
+      for (int i = 0; i < n; ++i) {
+        double n0 = 0.0, n1 = 0.0, rn = 0.0;
+        if (i + 1 < n) { fwd(i + 1, n0, n1); rn = D.R[ch.dof_off + i + 1]; }
+        const int j0 = i - w + lane, j1 = j0 + 64;
+        double acc = c0 * (j0 >= 0 && j0 < i ? y[j0] : 0.0) + c1 * (j1 >= 0 && j1 < i ? y[j1] : 0.0);
+        acc = wave_sum64(acc);
+        if (lane == 0) y[i] = r0 - acc;
+        lds_order();
+        c0 = n0; c1 = n1; r0 = rn;
+      }
+      auto bwd = [&](int i, double& a0, double& a1, double& dg) {
+        const double DM_G* row = M + (size_t)i * n;
+        const int j0 = i + 1 + lane, j1 = j0 + 64, hi = min(n - 1, i + w);
+        a0 = j0 <= hi ? row[j0] : 0.0;
+        a1 = j1 <= hi ? row[j1] : 0.0;
+        dg = row[i];
+      };
+      double dg;
+      bwd(n - 1, c0, c1, dg);
+      for (int i = n - 1; i >= 0; --i) {
+        double n0 = 0.0, n1 = 0.0, dn = 1.0;
+        if (i > 0) bwd(i - 1, n0, n1, dn);
+        const int j0 = i + 1 + lane, j1 = j0 + 64, hi = min(n - 1, i + w);
+        double acc = c0 * (j0 <= hi ? y[j0] : 0.0) + c1 * (j1 <= hi ? y[j1] : 0.0);
+        acc = wave_sum64(acc);
+        if (lane == 0) y[i] = (y[i] - acc) / dg;
+        lds_order();
+        c0 = n0; c1 = n1; dg = dn;
+      }
+    } else {
+      for (int i = 0; i < n; ++i) {
+        const double DM_G* row = M + (size_t)i * n;
+        double acc = 0.0;
+        for (int j = max(0, i - w) + lane; j < i; j += 64) acc += row[j] * y[j];
+        acc = wave_sum64(acc);
+        if (lane == 0) y[i] = D.R[ch.dof_off + i] - acc;
+        lds_order();
+      }
+      for (int i = n - 1; i >= 0; --i) {
+        const double DM_G* row = M + (size_t)i * n;
+        double acc = 0.0;
+        for (int j = i + 1 + lane; j <= min(n - 1, i + w); j += 64) acc += row[j] * y[j];
+        acc = wave_sum64(acc);
+        if (lane == 0) y[i] = (y[i] - acc) / row[i];
+        lds_order();
+      }
+    }
+  }
+  __syncthreads();
+  for (int r = tid; r < n; r += bd) {
+    const int k = r >> 2, c = r & 3;
+    const int h = c < 3 ? D.node_home[c * NN + D.chain_node[ch.node_tab + k]] : D.edge_home[D.chain_edge[ch.edge_tab + k]];
+    if (h >= 0) D.delta[h] = y[r];
+    else xB[-1 - h] = y[r];
+  }
+  __syncthreads();
 }
 
 // Band rows of every chain node of the system; returns this lane's share of the squared
@@ -1209,14 +1523,6 @@ __device__ __forceinline__ void sweep_all(ArgsP Ap, const DmSystem DM_C& S, int 
 __device__ __forceinline__ void backsub_all(ArgsP Ap, const DmSystem DM_C& S, int wave, int nwaves,
                                             const double DM_L* xB) {
   for (int g = 4 * wave; g < S.n_arms; g += 4 * nwaves) backsub_arms(Ap, S.arm0 + g, min(4, S.n_arms - g), xB);
-}
-
-// LDS operations of a wavefront stay in program order: this keeps the compiler from moving
-// them across (the hardware runs one wavefront's LDS instructions in order).
-__device__ __forceinline__ void lds_order() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // 32-bit halves of a double through a DPP row rotation (row_ror:N), and the partner row's
@@ -2040,15 +2346,19 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
           // the arm sweeps, the border solve and the back-substitutions are serial chains on
           // the critical path of the system: their wavefronts take issue priority over the
           // other workgroups' element and assembly work sharing the SIMDs
-          __builtin_amdgcn_s_setprio(3);
-          sweep_all(Ap, S, wave, nwaves, deltas, flags);
-          __syncthreads();
-          DM_TP(3);
-          border_solve(Ap, sid, Bt, ld, deltas, xB, red + 34, flags);
-          DM_TP(4);
-          backsub_all(Ap, S, wave, nwaves, xB);
-          __builtin_amdgcn_s_setprio(0);
-          __syncthreads();
+          if (A.sc_on) {
+            sc_solve(Ap, sid, hn, sc_lds, xB, flags);     // the rod's Jacobian with its contact pairs
+          } else {
+            __builtin_amdgcn_s_setprio(3);
+            sweep_all(Ap, S, wave, nwaves, deltas, flags);
+            __syncthreads();
+            DM_TP(3);
+            border_solve(Ap, sid, Bt, ld, deltas, xB, red + 34, flags);
+            DM_TP(4);
+            backsub_all(Ap, S, wave, nwaves, xB);
+            __builtin_amdgcn_s_setprio(0);
+            __syncthreads();
+          }
           DM_TP(5);
           if (flags[0]) break;
           apply_update(Ap, sid, xB, 1.0);

@@ -121,6 +121,10 @@ struct DmDev {
   const int DM_C* en;           // [2][n_edges] tail, head
   const double DM_C* ebar;
   const double DM_C* arc0;      // rest arclength of the edge's rod at its first node
+  // self-contact (dm_set_self_contact): per system a dense n x n Newton matrix over its chain
+  // DOFs and n doubles after it, at sc_off[system] doubles into sc_mat
+  double DM_G* sc_mat;
+  const long long DM_C* sc_off;
   const double DM_C* EA;
   const double DM_C* Ith;
   const double DM_C* moment;

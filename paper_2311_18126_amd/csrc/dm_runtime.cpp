@@ -839,9 +839,12 @@ size_t step_lds(DmStepArgs& A) {
   size_t base = sizeof(double) * ((size_t)A.max_nb * (A.max_nb + 1) + (size_t)A.max_arms * 110 + A.max_nb +
                                    40 + 2 + (size_t)A.max_seg);
   if (A.sc_on) {
-    // self-contact: boxes [6][max edges] floats, pair keys [cap], count and overflow flag
+    // self-contact: boxes [6][max edges] floats, pair keys [cap], four ints (pair count,
+    // overflow flag, half bandwidth), then the solve's vector and multiplier column
+    // [4 max edges + 3] doubles each
     A.sc_lds = (int)((base + 15) / 16 * 16);
-    base = (size_t)A.sc_lds + 24 * (size_t)A.sc_max_edges + 4 * (size_t)A.sc_cap + 8;
+    base = (size_t)A.sc_lds + 24 * (size_t)A.sc_max_edges + 4 * (size_t)A.sc_cap + 16 +
+           2 * sizeof(double) * (4 * (size_t)A.sc_max_edges + 3);
   }
   if (A.warm != 2) return base;
   A.net_lds = (int)((base + 15) / 16 * 16);
@@ -1368,11 +1371,26 @@ dm_status dm_set_self_contact(dm_sim* s, double delta, double k_c, double mu, do
       !std::isfinite(mu) || !std::isfinite(nu))
     return fail(DM_ERR_INVALID_ARG, "dm_set_self_contact: need delta > 0, k_c > 0, mu >= 0, nu > 0");
   int me = 0;
+  size_t total = 0;
+  std::vector<long long> off;
   for (const DmSystem& S : s->sys) {
     if (S.n_chains != 1) return fail(DM_ERR_UNSUPPORTED, "dm_set_self_contact: joined rods are not supported");
     me = std::max(me, S.n_edges);
+    const size_t n = 4 * (size_t)S.n_nodes - 1;
+    off.push_back((long long)total);
+    total += n * n + n;
   }
   if (me > 4096) return fail(DM_ERR_UNSUPPORTED, "dm_set_self_contact: rods of more than 4097 nodes");
+  if (total * sizeof(double) > ((size_t)32 << 30))
+    return fail(DM_ERR_UNSUPPORTED, "dm_set_self_contact: the rods' Newton matrices would exceed 32 GiB");
+  if (!s->dev.sc_mat) {
+    // one dense Newton matrix per rod (the layout is fixed once finalized)
+    dm_status st = alloc(s, total, &s->dev.sc_mat);
+    if (st != DM_OK) return st;
+    long long* p = nullptr;
+    if ((st = upload(s, off, &p)) != DM_OK) return st;
+    s->dev.sc_off = p;
+  }
   s->sc_on = 1;
   s->sc_max_edges = me;
   s->sc_delta = delta;

@@ -1,10 +1,11 @@
 """Edge-edge self-contact inside the GPU step (dm_set_self_contact) against the oracle's
 step with self-contact (oracle/der.py, pinned in tests/test_oracle_self_contact.py).
 
-The GPU's Newton matrix keeps only each node's own block of the contact Hessian, the oracle's
-is exact, so the two iterate differently and stop at different points within the Newton
-tolerance (1e-9 N of residual): positions agree to 1e-9 relative and the step's displacement
-to 1e-6 after one step, and to 1e-6 after three steps."""
+The GPU's Newton matrix is the rod's band plus every pair's blocks with the friction derivative
+taken at fixed closest-point parameters, the oracle's is its exact autodiff Jacobian, so the two
+stop at different points within the Newton tolerance (1e-9 N of residual): positions agree to
+1e-9 relative and the step's displacement to 1e-6 after one step, and to 1e-6 after three and
+after ten steps.  The coils run with line search (their friction needs it)."""
 import os
 
 import numpy as np
@@ -50,7 +51,7 @@ def test_coils_match_live_oracle(dm, mu):
         for r in range(2):
             sys_, s_ = oracles[r]
             for _ in range(k - done):
-                s_, info = der.step(sys_, s_, d["dt"], d["tol"], d["max_iter"])
+                s_, info = der.step(sys_, s_, d["dt"], d["tol"], d["max_iter"], line_search=True)
                 assert info.converged
             oracles[r][1] = s_
             n_pairs = len(der.contact_list(sys_, der.pack(s_.x, s_.theta)))
@@ -59,6 +60,43 @@ def test_coils_match_live_oracle(dm, mu):
                           f"coil {r} step {k} ({n_pairs} pairs)")
         done = k
     say(f"GPU Newton iterations over 3 steps of 2 coils: {iters_gpu}")
+
+
+def test_coil_with_friction_over_ten_steps(dm):
+    """One coil (36 nodes) with friction over 10 steps as the turns settle on each other: the
+    friction between touching turns couples nodes a turn apart with a stiffness well above the
+    inertia's, which the step solves with the pairs' blocks in its matrix; line search on both
+    sides (the stick-slip transitions make plain Newton cycle)."""
+    d = W.coiled_springs(1, seed=13, nmin=36, nmax=36, mu=0.3)
+    say("case: one coil with friction, 10 steps")
+    sim = dm.sim_from_description(d)
+    sys_, s_ = der.build(d)
+    x0 = s_.x.numpy().copy()
+    st = sim.step(d["dt"], 10)
+    assert st["status"][0] == 0
+    iters = 0
+    for _ in range(10):
+        s_, info = der.step(sys_, s_, d["dt"], d["tol"], d["max_iter"], line_search=True)
+        assert info.converged
+        iters += info.iters
+    say(f"Newton iterations over 10 steps: GPU {int(st['iters'][0])}, oracle {iters}")
+    assert st["iters"][0] <= 2 * iters
+    assert_parity(sim.rod_state(0)[0], s_.x.numpy(), x0, 1e-6, 1e-6, "coil step 10")
+
+
+def test_batch_of_coils_converges(dm):
+    """256 coils over 30 steps with friction, line search and adaptive halving (up to three
+    levels): every system converges.  Without halving one coil's step 11 does not converge
+    within 50 line-searched Newton iterations, on the oracle as here."""
+    d = W.coiled_springs(256, steps=30)
+    sim = dm.sim_from_description(d)
+    sim.set_adaptive(3)
+    st = sim.step(d["dt"], 30)
+    assert (st["status"] == 0).all()
+    per_step = st["iters"] / 30.0
+    say(f"256 coils, 30 steps: Newton iterations per step mean {per_step.mean():.2f}, max {per_step.max():.2f}; "
+        f"halved steps {int(st['halvings'].sum())}")
+    assert per_step.mean() < 10.0
 
 
 def test_off_is_the_plain_step_bit_for_bit(dm):

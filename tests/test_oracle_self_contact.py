@@ -15,7 +15,7 @@ from oracle import der
 
 
 def coil(free=False, mu=0.0, squeeze=1.0):
-    d = W.coiled_springs(1, seed=21, nmin=34, nmax=34, mu=mu)
+    d = W.coiled_springs(1, seed=21, nmin=34, nmax=34, mu=mu, kc_nodes=1)
     d["rods"][0]["x0"][:, 2] *= squeeze          # squeeze < 1 presses the turns into each other
     if free:
         d["rods"][0]["fixed_nodes"] = []

@@ -259,13 +259,15 @@ def contact_tangle(n_scenes: int = 4096, seed: int = 7, fingers: int = 5, n_node
 
 
 def coiled_springs(n_rods: int = 4, seed: int = 13, nmin: int = 40, nmax: int = 80, radius: float = 4e-3,
-                   steps: int = 10, mu: float = 0.3) -> dict:
+                   steps: int = 10, mu: float = 0.3, kc_nodes=None) -> dict:
     """Coiled rods standing on their clamped first nodes (a helix rising along +z about a
     vertical axis), N ~ U{nmin..nmax} nodes over 3 to 4 turns, helix radius U(14, 18) mm, pitch
     U(8.1, 8.4) mm (the turns sit just inside the contact reach 2h + delta = 8.5 mm of their
     radius h = 4 mm), E = 10^U(5.5, 6.5) Pa, rho = 1200; gravity -9.81 z presses the turns
-    together; rods 1 m apart along x.  Self-contact: delta = 5e-4 m, k_c = (node mass) g /
-    delta of the first rod, mu as given, nu = 1e-3 m/s; dt = 1e-3 s."""
+    together; rods 1 m apart along x.  Self-contact: delta = 5e-4 m, k_c = (first rod's mass) g
+    / delta, so that a contact carries the whole coil's weight at a compression of about delta
+    (kc_nodes = m: m node weights instead), mu as given, nu = 1e-3 m/s; dt = 1e-3 s; line
+    search on."""
     rng = np.random.Generator(np.random.PCG64(seed))
     rods = []
     m0 = None
@@ -280,9 +282,14 @@ def coiled_springs(n_rods: int = 4, seed: int = 13, nmin: int = 40, nmax: int = 
         rods.append(_rod(x0, radius, E, 0.5, 1200.0))
         if m0 is None:
             m0 = 1200.0 * math.pi * radius ** 2 * float(np.linalg.norm(x0[1] - x0[0]))
+            n0 = n - 1
     d = _desc(rods, dt=1e-3, steps=steps)
     delta = 5e-4
-    d["self_contact"] = {"delta": delta, "k_c": m0 * 9.81 / delta, "mu": float(mu), "nu": 1e-3}
+    weights = n0 if kc_nodes is None else kc_nodes
+    d["self_contact"] = {"delta": delta, "k_c": weights * m0 * 9.81 / delta, "mu": float(mu), "nu": 1e-3}
+    # the regularised friction's stick-slip transitions make Newton cycle without it (as on the
+    # floor)
+    d["line_search"] = True
     return d
 
 
