@@ -290,13 +290,16 @@ dm_status dm_fit_limb_curvatures(dm_sim* sim, double dt, int n_settle, int n_con
  * 10-13 applied to pairs of a rod's edges): at every Newton iterate the pairs of each rod's
  * edges with D < 2h + delta are found (two edges closer than 2h + delta along the rest rod are
  * never a pair), their energy k_c E_c(D) joins the elastic energy and their friction (mu, nu)
- * the external forces, so the residual is exact; the Newton matrix takes each node's own 3 x 3
- * block of the contact Hessian (the couplings between the nodes of a pair lie off the rod's
- * band), so Newton converges linearly where contacts are stiff.  After dm_finalize; k_c = 0
- * turns it off; delta > 0, k_c > 0, mu >= 0, nu > 0 otherwise.  DM_ERR_UNSUPPORTED for joined
- * rods or rods of more than 4097 nodes; dm_step then needs the backward-Euler integrator, and
- * the adjoint and the Real2Sim gradient refuse it.  A rod with more than four times as many
- * pairs as edges at some iterate stops there with DM_ERR_UNSUPPORTED. */
+ * the external forces.  Each rod's Newton matrix is then its band plus every pair's blocks
+ * (the contact Hessian and the friction's derivative), held in a dense (4N - 1)^2 matrix per
+ * rod that this call allocates (at most 32 GiB for the simulation) and factorised over the
+ * half bandwidth the pairs need.  Stick-slip friction may need line search (dm_config) and
+ * adaptive halving (dm_set_adaptive).  After dm_finalize; k_c = 0 turns it off; delta > 0,
+ * k_c > 0, mu >= 0, nu > 0 otherwise.  DM_ERR_UNSUPPORTED for joined rods, for rods whose
+ * self-contact arrays do not fit in 64 KB of LDS (about 600 nodes) or matrices beyond the
+ * limit; dm_step then needs the backward-Euler integrator, and the adjoint and the Real2Sim
+ * gradient refuse it.  A rod with more than four times as many pairs as edges at some
+ * iterate stops there with DM_ERR_UNSUPPORTED. */
 dm_status dm_set_self_contact(dm_sim* sim, double delta, double k_c, double mu, double nu);
 
 /* ---- Edge-edge contact (Contact and Friction subsection, Eq. 10-13) ----------------------
