@@ -449,6 +449,7 @@ __device__ __noinline__ void eval_stencil_grads(ArgsP Ap, int sid, double t_end)
   for (int i = threadIdx.x; i < S.n_st; i += blockDim.x) eval_stencil_grad(A, S.st0 + i, t_end);
 }
 
+
 // dt: the Newton step of the (sub)step being solved.
 __device__ __noinline__ void eval_edges_nodes(ArgsP Ap, int sid, double dt) {
   const DmStepArgs DM_C& A = *uniform(Ap);
@@ -662,10 +663,12 @@ __device__ __forceinline__ void sc_block(const ScPair& P, int k, int l, double k
 // (sc_solve).  Then each node adds, over its pairs, the contact energy's gradient minus the
 // friction force to its residual terms, and its own 3 x 3 block of the pair Jacobian to its
 // Jacobian block; sc_solve adds the blocks between different nodes.
-// LDS: box [6][sc_max_edges] floats, keys [sc_cap] ints, four ints (pair count, overflow flag,
-// half bandwidth), then sc_solve's vectors.
-__device__ __noinline__ void self_contact(ArgsP Ap, int sid, double dt, char DM_L* sc_lds) {
+// LDS (at A.sc_lds): box [6][sc_max_edges] floats, keys [sc_cap] ints, four ints (pair count,
+// half bandwidth), then sc_solve's vectors; an overflow sets flags[1].
+__device__ __noinline__ void self_contact(ArgsP Ap, int sid, double dt, int DM_L* flags) {
   const DmStepArgs DM_C& A = *uniform(Ap);
+  extern __shared__ double lds_raw[];
+  char DM_L* sc_lds = (char DM_L*)lds_raw + A.sc_lds;
   const DmDev DM_C& D = A.d;
   const DmSystem DM_C& S = D.sys[uniform(sid)];
   const DmChain ch = D.chain[S.chain0];
@@ -711,7 +714,7 @@ __device__ __noinline__ void self_contact(ArgsP Ap, int sid, double dt, char DM_
   __syncthreads();
   int np = cnt[0];
   if (np > cap) {
-    if (tid == 0) cnt[1] = 1;
+    if (tid == 0) flags[1] = 1;
     np = cap;
   }
   int n2 = 1;
@@ -786,9 +789,10 @@ __device__ __forceinline__ double wave_sum64(double v) {
 // back substitution by one wavefront, and the step goes to the delta and border-solution slots
 // the update reads.  Called by the whole workgroup after the matrix pass of the iterate whose
 // pairs self_contact left in LDS.
-__device__ __noinline__ void sc_solve(ArgsP Ap, int sid, double dt, char DM_L* sc_lds, double DM_L* xB,
-                                      int DM_L* flags) {
+__device__ __noinline__ void sc_solve(ArgsP Ap, int sid, double dt, double DM_L* xB, int DM_L* flags) {
   const DmStepArgs DM_C& A = *uniform(Ap);
+  extern __shared__ double lds_raw[];
+  char DM_L* sc_lds = (char DM_L*)lds_raw + A.sc_lds;
   const DmDev DM_C& D = A.d;
   const DmSystem DM_C& S = D.sys[uniform(sid)];
   const DmChain ch = D.chain[S.chain0];
@@ -2231,7 +2235,10 @@ extern "C" hipError_t dm_launch_curvature_adjoint(const DmCurvArgs* args, int bl
   return hipGetLastError();
 }
 
-__global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
+// The step of every system (one workgroup each); SC: the rods' edge-edge self-contact
+// (dm_step_sc_kernel), compiled apart so that the plain kernel carries none of its code.
+template <bool SC>
+__device__ __forceinline__ void step_body() {
   extern __shared__ double lds_raw[];
   double DM_L* lds = (double DM_L*)lds_raw;
   // the by-value argument sits at offset 0 of the argument segment
@@ -2248,14 +2255,11 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
   int DM_L* flags = (int DM_L*)(red + 40);      // [4]; then border term segment sums at red + 42
   unsigned short DM_L* hbuf = (unsigned short DM_L*)((char DM_L*)lds_raw + A.net_lds);   // network (warm == 2)
   const int tid = threadIdx.x, wave = tid >> 6, nwaves = blockDim.x >> 6;
-  // self-contact pair list (LDS) and its overflow flag
-  char DM_L* sc_lds = (char DM_L*)lds_raw + A.sc_lds;
-  int DM_L* sc_over = (int DM_L*)(sc_lds + 24 * (size_t)A.sc_max_edges + 4 * (size_t)A.sc_cap) + 1;
   if (tid == 0) {
-    flags[0] = 0;
+    flags[0] = 0;       // singular pivot
+    flags[1] = 0;       // more self-contact pairs than the list holds
     red[37] = 0.0;      // largest floor-ended residual of this launch and its floor estimate
     red[38] = 0.0;
-    if (A.sc_on) *sc_over = 0;
   }
   int status = DM_STATUS_OK, iters = 0, steps = 0, floor_hits = 0, fallbacks = 0, halved = 0;
   double res = 0.0;
@@ -2296,10 +2300,10 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
           eval_stencil_grads(Ap, sid, t_end);
           eval_edges_nodes(Ap, sid, hn);
           __syncthreads();
-          if (A.sc_on) {
-            self_contact(Ap, sid, hn, sc_lds);
+          if (SC) {
+            self_contact(Ap, sid, hn, flags);
             __syncthreads();
-            if (*sc_over) break;        // more pairs than the list holds: the system fails
+            if (flags[1]) break;        // more pairs than the list holds: the system fails
           }
           DM_TP(0);
           double r2 = assemble_band<1>(Ap, sid, hn);
@@ -2346,8 +2350,8 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
           // the arm sweeps, the border solve and the back-substitutions are serial chains on
           // the critical path of the system: their wavefronts take issue priority over the
           // other workgroups' element and assembly work sharing the SIMDs
-          if (A.sc_on) {
-            sc_solve(Ap, sid, hn, sc_lds, xB, flags);     // the rod's Jacobian with its contact pairs
+          if (SC) {
+            sc_solve(Ap, sid, hn, xB, flags);     // the rod's Jacobian with its contact pairs
           } else {
             __builtin_amdgcn_s_setprio(3);
             sweep_all(Ap, S, wave, nwaves, deltas, flags);
@@ -2371,7 +2375,7 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
       iters += newton;
       if (!conv) {
         const bool singular = flags[0] != 0;
-        const bool overflow = A.sc_on && *sc_over;
+        const bool overflow = SC && flags[1];
         rollback(Ap, sid);
         if (lev < A.max_halvings && !overflow) {
           ++lev;
@@ -2420,8 +2424,14 @@ __global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) {
   }
 }
 
+__global__ void __launch_bounds__(512) dm_step_kernel(DmStepArgs) { step_body<false>(); }
+__global__ void __launch_bounds__(512) dm_step_sc_kernel(DmStepArgs) { step_body<true>(); }
+
 extern "C" hipError_t dm_launch_step(const DmStepArgs* args, int block, size_t lds_bytes, hipStream_t stream) {
-  hipLaunchKernelGGL(dm_step_kernel, dim3(args->n_systems), dim3(block), lds_bytes, stream, *args);
+  if (args->sc_on)
+    hipLaunchKernelGGL(dm_step_sc_kernel, dim3(args->n_systems), dim3(block), lds_bytes, stream, *args);
+  else
+    hipLaunchKernelGGL(dm_step_kernel, dim3(args->n_systems), dim3(block), lds_bytes, stream, *args);
   return hipGetLastError();
 }
 
