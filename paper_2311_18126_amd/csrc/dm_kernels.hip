@@ -495,6 +495,10 @@ __device__ __forceinline__ float sc_up(double v) {
   return (double)f < v ? nextafterf(f, INFINITY) : f;
 }
 
+// Blocked LU of the self-contact solve: the widest panel (the launch's sc_pb, 8 or 16, is what
+// its LDS holds) and the largest half bandwidth the LDS panel takes
+constexpr int SC_PBMAX = 16, SC_WPANEL = 128;
+
 // One pair of a rod's edges at the current iterate: the nodes of its roles (edge i's nodes a, b,
 // edge j's nodes c, d), the closest-point parameters (s, t), r = P(s) - Q(t), the edge vectors,
 // D, the contact profile's E_c' and E_c'', the inverse of f_zz over the free parameters and, with
@@ -655,6 +659,21 @@ __device__ __forceinline__ void sc_block(const ScPair& P, int k, int l, double k
     for (int be = 0; be < 3; ++be) H[al][be] += dRs[al] * dsx[be] + dRt[al] * dtx[be];
 }
 
+// The rod's pair area: after its n x n Newton matrix and n doubles, SC_PAIR doubles per pair
+// slot (the residual terms of the pair's four nodes, then its 12 x 12 Jacobian, row-major).
+constexpr int SC_PAIR = 12 + 144;
+__device__ __forceinline__ double DM_G* sc_pair_area(const DmDev DM_C& D, int sid, int N) {
+  const size_t n = 4 * (size_t)N - 1;
+  return D.sc_mat + D.sc_off[sid] + n * n + n;
+}
+
+// Each node's pairs for the gathers: SC_SLOTS ints per node (pair slot << 2 | role) and then
+// a count per node, over the solve's vector and multiplier area (unused until its LU).
+constexpr int SC_SLOTS = 14;
+__device__ __forceinline__ int DM_L* sc_node_lists(char DM_L* sc_lds, int ME, int cap) {
+  return (int DM_L*)(sc_lds + 24 * (size_t)ME + 4 * (size_t)cap + 16);
+}
+
 // Self-contact of the rod of system sid at the current iterate.  The pairs of its edges within
 // reach, D < h_i + h_j + delta, are found over all pairs i < j by a test of boxes inflated by
 // h + delta / 2 (rounded outward to float32 in LDS), the rest-arclength exclusion (edges closer
@@ -736,19 +755,35 @@ __device__ __noinline__ void self_contact(ArgsP Ap, int sid, double dt, int DM_L
       }
       __syncthreads();
     }
-  const double kc = A.sc_kc, mu = A.sc_mu, K2 = 15.0 / A.sc_nu;
+  // each node's pairs (slot and role, in the list's order) into LDS, for the gathers below
+  // and in sc_solve: SC_SLOTS per node, a longer list is walked over all pairs instead
+  int DM_L* nl = sc_node_lists(sc_lds, ME, cap);
+  int DM_L* ncount = nl + (ME + 1) * SC_SLOTS;
   for (int k = tid; k < N; k += bd) {
-    double g[3] = {0.0, 0.0, 0.0}, H[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    int c = 0;
     for (int q = 0; q < np; ++q) {
       const int key = keys[q], i = key >> 16, j = key & 0xffff;
       const int role = k == i ? 0 : (k == i + 1 ? 1 : (k == j ? 2 : (k == j + 1 ? 3 : -1)));
       if (role < 0) continue;
-      ScPair P;
-      sc_pair(D, ch, key, delta, mu, P);
+      if (c < SC_SLOTS) nl[k * SC_SLOTS + c] = (q << 2) | role;
+      ++c;
+    }
+    ncount[k] = c;
+  }
+  // each pair once, one lane per pair: its residual terms for its four nodes and its 12 x 12
+  // Jacobian, to the rod's pair area in HBM (SC_PAIR doubles per pair)
+  const double kc = A.sc_kc, mu = A.sc_mu, K2 = 15.0 / A.sc_nu;
+  double DM_G* pr = sc_pair_area(D, sid, N);
+  for (int q = tid; q < np; q += bd) {
+    ScPair P;
+    sc_pair(D, ch, keys[q], delta, mu, P);
+    double DM_G* o = pr + (size_t)q * SC_PAIR;
+    for (int k = 0; k < 4; ++k) {
       double gD[3], Gs[3], Gt[3];
-      const double w = sc_role(P, role, gD, Gs, Gt);
+      const double w = sc_role(P, k, gD, Gs, Gt);
+      double g[3];
 #pragma unroll
-      for (int al = 0; al < 3; ++al) g[al] += kc * P.E1 * gD[al];
+      for (int al = 0; al < 3; ++al) g[al] = kc * P.E1 * gD[al];
       if (P.fric && P.un > 0.0) {
         // friction on edge i (Eq. 12-13): u the tangential relative velocity of the closest
         // points over the step at (s, t); edge j takes the opposite force
@@ -758,12 +793,42 @@ __device__ __noinline__ void self_contact(ArgsP Ap, int sid, double dt, int DM_L
 #pragma unroll
         for (int al = 0; al < 3; ++al) g[al] -= w * m * (P.ut[al] / dt);      // residual: minus the force
       }
-      double B[3][3];
-      sc_block(P, role, role, kc, mu, K2, dt, B);
 #pragma unroll
-      for (int al = 0; al < 3; ++al)
+      for (int al = 0; al < 3; ++al) o[3 * k + al] = g[al];
+      for (int l = 0; l < 4; ++l) {
+        double B[3][3];
+        sc_block(P, k, l, kc, mu, K2, dt, B);
 #pragma unroll
-        for (int be = 0; be < 3; ++be) H[al][be] += B[al][be];
+        for (int al = 0; al < 3; ++al)
+#pragma unroll
+          for (int be = 0; be < 3; ++be) o[12 + (3 * k + al) * 12 + 3 * l + be] = B[al][be];
+      }
+    }
+  }
+  __syncthreads();
+  // each node sums its pairs' terms in the list's order (so the sums do not depend on timing):
+  // the residual terms and its own block
+  for (int k = tid; k < N; k += bd) {
+    double g[3] = {0.0, 0.0, 0.0}, H[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    const int cnk = ncount[k], walk = cnk <= SC_SLOTS ? cnk : np;
+    for (int e = 0; e < walk; ++e) {
+      int q, role;
+      if (cnk <= SC_SLOTS) {
+        q = nl[k * SC_SLOTS + e] >> 2;
+        role = nl[k * SC_SLOTS + e] & 3;
+      } else {
+        const int key = keys[e], i = key >> 16, j = key & 0xffff;
+        q = e;
+        role = k == i ? 0 : (k == i + 1 ? 1 : (k == j ? 2 : (k == j + 1 ? 3 : -1)));
+        if (role < 0) continue;
+      }
+      const double DM_G* o = pr + (size_t)q * SC_PAIR;
+#pragma unroll
+      for (int al = 0; al < 3; ++al) {
+        g[al] += o[3 * role + al];
+#pragma unroll
+        for (int be = 0; be < 3; ++be) H[al][be] += o[12 + (3 * role + al) * 12 + 3 * role + be];
+      }
     }
     const int n0 = D.chain_node[ch.node_tab + k];
 #pragma unroll
@@ -829,66 +894,175 @@ __device__ __noinline__ void sc_solve(ArgsP Ap, int sid, double dt, double DM_L*
     if (c == r) d0[r] = v;
   }
   __syncthreads();
-  // the pairs' blocks between different nodes; each lane owns the rows of its node
-  const double kc = A.sc_kc, mu = A.sc_mu, K2 = 15.0 / A.sc_nu, delta = A.sc_delta;
+  // the pairs' blocks between different nodes, from the pair area self_contact filled at this
+  // iterate; each lane owns the rows of its node and adds its pairs in the list's order, each
+  // pair's 27 entries loaded before any is stored
+  const double DM_G* pr = sc_pair_area(D, sid, N);
+  const int DM_L* nl = sc_node_lists(sc_lds, ME, cap);
+  const int DM_L* ncount = nl + (ME + 1) * SC_SLOTS;
   for (int k = tid; k < N; k += bd) {
     const unsigned fk = D.nmask[4 * (size_t)(ch.node_tab + k)] >> 12;
-    for (int q = 0; q < np; ++q) {
+    const int cnk = ncount[k], walk = cnk <= SC_SLOTS ? cnk : np;
+    for (int e = 0; e < walk; ++e) {
+      int q, role;
+      if (cnk <= SC_SLOTS) {
+        q = nl[k * SC_SLOTS + e] >> 2;
+        role = nl[k * SC_SLOTS + e] & 3;
+      } else {
+        const int key = keys[e], i0 = key >> 16, j0 = key & 0xffff;
+        q = e;
+        role = k == i0 ? 0 : (k == i0 + 1 ? 1 : (k == j0 ? 2 : (k == j0 + 1 ? 3 : -1)));
+        if (role < 0) continue;
+      }
       const int key = keys[q], i = key >> 16, j = key & 0xffff;
-      const int role = k == i ? 0 : (k == i + 1 ? 1 : (k == j ? 2 : (k == j + 1 ? 3 : -1)));
-      if (role < 0) continue;
-      ScPair P;
-      sc_pair(D, ch, key, delta, mu, P);
-      for (int l = 0; l < 4; ++l) {
-        if (l == role) continue;
+      const double DM_G* o = pr + (size_t)q * SC_PAIR + 12 + 3 * role * 12;
+      double add[3][3][3], cur[3][3][3];
+      size_t at[3][3][3];
+      bool use[3][3][3];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const int l = m < role ? m : m + 1;
         const int kl = l == 0 ? i : (l == 1 ? i + 1 : (l == 2 ? j : j + 1));
         const unsigned fl = D.nmask[4 * (size_t)(ch.node_tab + kl)] >> 12;
-        double B[3][3];
-        sc_block(P, role, l, kc, mu, K2, dt, B);
 #pragma unroll
-        for (int al = 0; al < 3; ++al) {
-          if ((fk >> al) & 1u) continue;
+        for (int al = 0; al < 3; ++al)
+#pragma unroll
+          for (int be = 0; be < 3; ++be) {
+            at[m][al][be] = (size_t)(4 * k + al) * n + 4 * kl + be;
+            use[m][al][be] = !((fk >> al) & 1u) && !((fl >> be) & 1u);
+            add[m][al][be] = o[al * 12 + 3 * l + be];
+            cur[m][al][be] = M[at[m][al][be]];
+          }
+      }
+#pragma unroll
+      for (int m = 0; m < 3; ++m)
+#pragma unroll
+        for (int al = 0; al < 3; ++al)
 #pragma unroll
           for (int be = 0; be < 3; ++be)
-            if (!((fl >> be) & 1u)) M[(size_t)(4 * k + al) * n + 4 * kl + be] += B[al][be];
-        }
-      }
+            if (use[m][al][be]) M[at[m][al][be]] = cur[m][al][be] + add[m][al][be];
     }
   }
   __syncthreads();
-  // LU without pivoting over the band of half width w.  Each lane's entries of an update are
-  // loaded in batches of SB before any of them is stored, so their loads overlap.
+  // LU without pivoting over the band of half width w.  Blocked: sc_pb pivot columns at a time
+  // are factorised in LDS (the panel of their rows below, and the block row of U to their
+  // right), then the trailing band takes one rank-sc_pb update in HBM, each lane loading its
+  // entries in batches before any is stored, so the loads overlap (the update streams the
+  // band through the caches once per panel: the wider the panel, the less traffic).  A rod
+  // whose half bandwidth exceeds the LDS panel takes one pivot at a time.
   constexpr int SB = 12;
   bool bad = false;
-  for (int k = 0; k < n; ++k) {
-    const double p = M[(size_t)k * n + k];
-    if (!(fabs(p) > 1e-12 * fabs(d0[k])) || !isfinite(p)) { bad = true; break; }
-    const int m = min(w, n - 1 - k);
-    if (m == 0) break;
-    const double inv = 1.0 / p;
-    for (int i = tid; i < m; i += bd) lcol[i] = M[(size_t)(k + 1 + i) * n + k] * inv;
-    __syncthreads();
-    const double DM_G* rk = M + (size_t)k * n + k;
-    const int tot = m * (m + 1);
-    for (int b0 = tid; b0 < tot; b0 += SB * bd) {
-      double val[SB], lv[SB], uv[SB];
-      size_t at[SB];
-      unsigned lmask = 0;                  // entries of column k: they take the multiplier
-#pragma unroll
-      for (int q = 0; q < SB; ++q) {
-        const int idx = min(b0 + q * bd, tot - 1);
-        const int i = idx / (m + 1), jj = idx - i * (m + 1);
-        at[q] = (size_t)(k + 1 + i) * n + k + jj;
-        val[q] = M[at[q]];
-        lv[q] = lcol[i];
-        uv[q] = rk[jj];
-        lmask |= (jj == 0 ? 1u : 0u) << q;
+  if (w <= SC_WPANEL) {
+    constexpr int RP = SC_WPANEL + SC_PBMAX, TB = 16;
+    const int PB = A.sc_pb;
+    double DM_L* pan = lcol + (4 * ME + 3);          // [PB][RP]: column q of the panel
+    double DM_L* ub = pan + PB * RP;                 // [PB][RP]: row q of U right of the panel
+    for (int k0 = 0; k0 < n; k0 += PB) {
+      const int b = min(PB, n - k0), R = min(n - k0, b + w), C = min(n - k0 - b, w);
+      for (int e = tid; e < R * b; e += bd) {        // a row's b entries by consecutive lanes
+        const int i = e / b, q = e - i * b;
+        pan[q * RP + i] = M[(size_t)(k0 + i) * n + k0 + q];
       }
+      for (int e = tid; e < b * C; e += bd) {
+        const int q = e / C, c = e - q * C;
+        ub[q * RP + c] = M[(size_t)(k0 + q) * n + k0 + b + c];
+      }
+      __syncthreads();
+      // the panel: each lane owns its rows, one barrier per pivot
+      for (int q = 0; q < b; ++q) {
+        const double p = pan[q * RP + q];
+        if (!(fabs(p) > 1e-12 * fabs(d0[k0 + q])) || !isfinite(p)) { bad = true; break; }
+        const double inv = 1.0 / p;
+        for (int i = q + 1 + tid; i < R; i += bd) {
+          const double l = pan[q * RP + i] * inv;
+          pan[q * RP + i] = l;
+          for (int c = q + 1; c < b; ++c) pan[c * RP + i] -= l * pan[c * RP + q];
+        }
+        __syncthreads();
+      }
+      if (bad) break;
+      // U's block row: the unit lower triangle of the panel's top solved per column
+      for (int c = tid; c < C; c += bd)
+        for (int t = 1; t < b; ++t) {
+          double v = ub[t * RP + c];
+          for (int q = 0; q < t; ++q) v -= pan[q * RP + t] * ub[q * RP + c];
+          ub[t * RP + c] = v;
+        }
+      __syncthreads();
+      // the trailing band's rank-b update: one column per lane (its U entries in registers),
+      // the lanes of a column group taking every G-th row, TB rows' loads before their stores;
+      // then the panel and U block back to HBM
+      const int tr = R - b;
+      if (C > 0 && tr > 0) {
+        const int G = bd >= C ? bd / C : 1;
+        for (int c0 = bd >= C ? tid % C : tid, g = bd >= C ? tid / C : 0; g < G && c0 < C; c0 += bd >= C ? C * G : bd) {
+          double u[SC_PBMAX];
 #pragma unroll
-      for (int q = 0; q < SB; ++q)
-        if (b0 + q * bd < tot) M[at[q]] = ((lmask >> q) & 1u) ? lv[q] : val[q] - lv[q] * uv[q];
+          for (int t = 0; t < SC_PBMAX; ++t) u[t] = t < b ? ub[t * RP + c0] : 0.0;
+          for (int i0 = g; i0 < tr; i0 += G * TB) {
+            double val[TB];
+            size_t at[TB];
+#pragma unroll
+            for (int q = 0; q < TB; ++q) {
+              const int i = min(i0 + q * G, tr - 1);
+              at[q] = (size_t)(k0 + b + i) * n + k0 + b + c0;
+              val[q] = M[at[q]];
+            }
+#pragma unroll
+            for (int q = 0; q < TB; ++q) {
+              const int i = i0 + q * G;
+              if (i < tr) {
+                double acc = val[q];
+#pragma unroll
+                for (int t = 0; t < SC_PBMAX; ++t)
+                  if (t < b) acc -= pan[t * RP + b + i] * u[t];
+                M[at[q]] = acc;
+              }
+            }
+          }
+        }
+      }
+      for (int e = tid; e < R * b; e += bd) {
+        const int i = e / b, q = e - i * b;
+        M[(size_t)(k0 + i) * n + k0 + q] = pan[q * RP + i];
+      }
+      for (int e = tid; e < b * C; e += bd) {
+        const int q = e / C, c = e - q * C;
+        M[(size_t)(k0 + q) * n + k0 + b + c] = ub[q * RP + c];
+      }
+      __syncthreads();
     }
-    __syncthreads();
+  } else {
+    for (int k = 0; k < n; ++k) {
+      const double p = M[(size_t)k * n + k];
+      if (!(fabs(p) > 1e-12 * fabs(d0[k])) || !isfinite(p)) { bad = true; break; }
+      const int m = min(w, n - 1 - k);
+      if (m == 0) break;
+      const double inv = 1.0 / p;
+      for (int i = tid; i < m; i += bd) lcol[i] = M[(size_t)(k + 1 + i) * n + k] * inv;
+      __syncthreads();
+      const double DM_G* rk = M + (size_t)k * n + k;
+      const int tot = m * (m + 1);
+      for (int b0 = tid; b0 < tot; b0 += SB * bd) {
+        double val[SB], lv[SB], uv[SB];
+        size_t at[SB];
+        unsigned lmask = 0;                  // entries of column k: they take the multiplier
+#pragma unroll
+        for (int q = 0; q < SB; ++q) {
+          const int idx = min(b0 + q * bd, tot - 1);
+          const int i = idx / (m + 1), jj = idx - i * (m + 1);
+          at[q] = (size_t)(k + 1 + i) * n + k + jj;
+          val[q] = M[at[q]];
+          lv[q] = lcol[i];
+          uv[q] = rk[jj];
+          lmask |= (jj == 0 ? 1u : 0u) << q;
+        }
+#pragma unroll
+        for (int q = 0; q < SB; ++q)
+          if (b0 + q * bd < tot) M[at[q]] = ((lmask >> q) & 1u) ? lv[q] : val[q] - lv[q] * uv[q];
+      }
+      __syncthreads();
+    }
   }
   if (bad) {
     if (tid == 0) flags[0] = 1;

@@ -214,7 +214,7 @@ struct DmStepArgs {
   int max_nb, max_arms;
   int max_seg;     // largest number of border term segments of a system (LDS partial sums)
   // edge-edge self-contact of single-rod systems (off: sc_on = 0)
-  int sc_on, sc_cap, sc_max_edges, sc_lds;   // pair slots per system (a power of two), LDS offset
+  int sc_on, sc_cap, sc_max_edges, sc_lds, sc_pb;   // pair slots per system (a power of two), LDS offset
   double sc_delta, sc_kc, sc_mu, sc_nu;
 };
 

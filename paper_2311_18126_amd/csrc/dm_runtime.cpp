@@ -841,10 +841,13 @@ size_t step_lds(DmStepArgs& A) {
   if (A.sc_on) {
     // self-contact: boxes [6][max edges] floats, pair keys [cap], four ints (pair count,
     // overflow flag, half bandwidth), then the solve's vector and multiplier column
-    // [4 max edges + 3] doubles each
+    // [4 max edges + 3] doubles each and its blocked LU's panel and U block, 2 x sc_pb x 144
+    // doubles: panels of 16 columns where they fit in 64 KB, else of 8
     A.sc_lds = (int)((base + 15) / 16 * 16);
     base = (size_t)A.sc_lds + 24 * (size_t)A.sc_max_edges + 4 * (size_t)A.sc_cap + 16 +
            2 * sizeof(double) * (4 * (size_t)A.sc_max_edges + 3);
+    A.sc_pb = base + sizeof(double) * 2 * 16 * 144 <= 65536 ? 16 : 8;
+    base += sizeof(double) * 2 * (size_t)A.sc_pb * 144;
   }
   if (A.warm != 2) return base;
   A.net_lds = (int)((base + 15) / 16 * 16);
@@ -1371,14 +1374,19 @@ dm_status dm_set_self_contact(dm_sim* s, double delta, double k_c, double mu, do
       !std::isfinite(mu) || !std::isfinite(nu))
     return fail(DM_ERR_INVALID_ARG, "dm_set_self_contact: need delta > 0, k_c > 0, mu >= 0, nu > 0");
   int me = 0;
-  size_t total = 0;
-  std::vector<long long> off;
   for (const DmSystem& S : s->sys) {
     if (S.n_chains != 1) return fail(DM_ERR_UNSUPPORTED, "dm_set_self_contact: joined rods are not supported");
     me = std::max(me, S.n_edges);
+  }
+  // per rod: its n x n Newton matrix, n doubles, and the pair area (156 doubles per pair slot)
+  size_t cap = 64;
+  while (cap < 4 * (size_t)std::max(me, 1)) cap <<= 1;
+  size_t total = 0;
+  std::vector<long long> off;
+  for (const DmSystem& S : s->sys) {
     const size_t n = 4 * (size_t)S.n_nodes - 1;
     off.push_back((long long)total);
-    total += n * n + n;
+    total += n * n + n + 156 * cap;
   }
   if (me > 4096) return fail(DM_ERR_UNSUPPORTED, "dm_set_self_contact: rods of more than 4097 nodes");
   if (total * sizeof(double) > ((size_t)32 << 30))
