@@ -11,6 +11,7 @@ warm start, star, midpoint, adjoint and per-rod figures.
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
     python bench.py --configs    # one line per benchmark configuration
     python bench.py --paper      # the paper's validation workloads against its wall times
+    python bench.py --section self_contact   # one extra section alone (for profiling)
 """
 from __future__ import annotations
 
@@ -613,6 +614,8 @@ def main():
                     help="instead of the headline line, one line per benchmark configuration")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES bytes device to device once (calibrates the HBM byte counters)")
+    ap.add_argument("--section", choices=["self_contact", "contact", "stars", "midpoint"], default=None,
+                    help="only this extra section (for profiling), one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU (asked for --gpus {args.gpus}); independent rod batches "
@@ -644,6 +647,13 @@ def main():
         return
     if args.paper:
         paper_table(dm, log)
+        return
+    if args.section:
+        run = {"self_contact": lambda: self_contact_section(dm, 20, n_rods=256),
+               "contact": lambda: contact_section(dm),
+               "stars": lambda: star_section(dm, max(args.steps // 5, 5)),
+               "midpoint": lambda: midpoint_section(dm, args.steps)}[args.section]
+        print(json.dumps({args.section: run()}), flush=True)
         return
     desc = W.rod_batch(1024)
     n_nodes = np.array([r["x0"].shape[0] for r in desc["rods"]])
