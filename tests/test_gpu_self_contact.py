@@ -99,6 +99,28 @@ def test_batch_of_coils_converges(dm):
     assert per_step.mean() < 10.0
 
 
+def test_wide_and_long_rods_match_the_band_solve_when_contact_is_negligible(dm):
+    """The solve's other paths against the plain band solve, with a contact stiffness so small
+    (1e-12) that the step is the plain one to within rounding while the pairs, and so the
+    matrix's half bandwidth, are those of the coils: a 60-node coil (half bandwidth 70), a
+    150-node coil (166: above the LDS panel, one pivot at a time) and a straight 300-node rod,
+    whose length leaves LDS for 8-column panels only, for the whole launch."""
+    c60 = W.coiled_springs(1, seed=13, nmin=60, nmax=60, mu=0.0)["rods"][0]
+    c150 = W.coiled_springs(1, seed=13, nmin=150, nmax=150, mu=0.0)["rods"][0]
+    c150 = dict(c150, x0=c150["x0"] + np.array([1.0, 0.0, 0.0]))
+    line = W.rod(W.straight_nodes(300, 1.5, (2.0, 0.0, 0.1)), 2e-3, 1e6)
+    d = W.desc([c60, c150, line], dt=1e-3, steps=3)
+    plain = dm.sim_from_description(d)
+    sc = dm.sim_from_description(d)
+    sc.set_self_contact(5e-4, 1e-12)
+    x0 = plain.state()[0].copy()
+    a = plain.step(d["dt"], 3)
+    b = sc.step(d["dt"], 3)
+    assert (a["status"] == 0).all() and (b["status"] == 0).all()
+    say(f"Newton iterations: band {a['iters'].tolist()}, with the pairs' matrix {b['iters'].tolist()}")
+    assert_parity(sc.state()[0], plain.state()[0], x0, 1e-9, 1e-6, "negligible contact vs plain")
+
+
 def test_off_is_the_plain_step_bit_for_bit(dm):
     d = W.coiled_springs(2, seed=13, nmin=36, nmax=44)
     plain = dict(d)
