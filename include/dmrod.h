@@ -296,7 +296,7 @@ dm_status dm_fit_limb_curvatures(dm_sim* sim, double dt, int n_settle, int n_con
  * half bandwidth the pairs need.  Stick-slip friction may need line search (dm_config) and
  * adaptive halving (dm_set_adaptive).  After dm_finalize; k_c = 0 turns it off; delta > 0,
  * k_c > 0, mu >= 0, nu > 0 otherwise.  DM_ERR_UNSUPPORTED for joined rods, for rods whose
- * self-contact arrays do not fit in 64 KB of LDS (about 600 nodes) or matrices beyond the
+ * self-contact arrays do not fit in 64 KB of LDS (about 400 nodes) or matrices beyond the
  * limit; dm_step then needs the backward-Euler integrator, and the adjoint and the Real2Sim
  * gradient refuse it.  A rod with more than four times as many pairs as edges at some
  * iterate stops there with DM_ERR_UNSUPPORTED. */
