@@ -679,11 +679,14 @@ __device__ __forceinline__ int DM_L* sc_node_lists(char DM_L* sc_lds, int ME, in
 // h + delta / 2 (rounded outward to float32 in LDS), the rest-arclength exclusion (edges closer
 // than h_i + h_j + delta along the rest rod are never a pair) and the exact segment distance,
 // and sorted in LDS; the sorted list stays in LDS for the Newton solve of the same iterate
-// (sc_solve).  Then each node adds, over its pairs, the contact energy's gradient minus the
-// friction force to its residual terms, and its own 3 x 3 block of the pair Jacobian to its
-// Jacobian block; sc_solve adds the blocks between different nodes.
+// (sc_solve).  Each pair's residual terms and 12 x 12 Jacobian are then computed once, one lane
+// per pair, into the rod's pair area, and each node's pairs are listed in LDS; each node adds,
+// over its pairs, the contact energy's gradient minus the friction force to its residual terms,
+// and its own 3 x 3 block of the pair Jacobian to its Jacobian block; sc_solve adds the blocks
+// between different nodes.
 // LDS (at A.sc_lds): box [6][sc_max_edges] floats, keys [sc_cap] ints, four ints (pair count,
-// half bandwidth), then sc_solve's vectors; an overflow sets flags[1].
+// half bandwidth), then sc_solve's vectors (the node lists until its LU); an overflow sets
+// flags[1].
 __device__ __noinline__ void self_contact(ArgsP Ap, int sid, double dt, int DM_L* flags) {
   const DmStepArgs DM_C& A = *uniform(Ap);
   extern __shared__ double lds_raw[];
