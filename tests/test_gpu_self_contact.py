@@ -121,6 +121,22 @@ def test_wide_and_long_rods_match_the_band_solve_when_contact_is_negligible(dm):
     assert_parity(sc.state()[0], plain.state()[0], x0, 1e-9, 1e-6, "negligible contact vs plain")
 
 
+def test_runs_are_bitwise_deterministic(dm):
+    """Pairs are found with an LDS atomic counter but sorted before any sum, and every node sums
+    its pairs in the list's order: two runs of 32 coils with friction agree bit for bit."""
+    d = W.coiled_springs(32, seed=5)
+    out = []
+    for _ in range(2):
+        sim = dm.sim_from_description(d)
+        sim.set_adaptive(3)
+        st = sim.step(d["dt"], 10)
+        assert (st["status"] == 0).all()
+        out.append(sim.state())
+        sim.close()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
 def test_off_is_the_plain_step_bit_for_bit(dm):
     d = W.coiled_springs(2, seed=13, nmin=36, nmax=44)
     plain = dict(d)
