@@ -723,8 +723,8 @@ def main():
     if not args.no_extras:
         out["warm_start"] = warm_start_section(dm, 1000, log)
         out["stars"] = star_section(dm, max(args.steps // 5, 5))
-        # over the whole 1000 steps the undamped rule loses some rods even with halving (22 of
-        # 1024, 429 halved steps): the section times the first 100
+        # over the whole 1000 steps some short stiff rods gain energy under the undamped rule
+        # until Newton fails (22 of 1024 even with halving): the section times the first 100
         out["midpoint"] = midpoint_section(dm, min(args.steps, 100))
         out["adjoint"] = adjoint_section(dm)
         out["real2sim"] = real2sim_section(dm)
