@@ -156,8 +156,8 @@ def test_adam_step_applies_the_update_rule(dm):
 
 def test_train_epoch_equals_its_steps(dm):
     """One library call per epoch gives the same weights, bit for bit, as the same mini-batches
-    fed to train_step one at a time, and the mean of their losses; an index outside 0..n-1 in
-    the order is reported as an error."""
+    fed to train_step one at a time, and the mean of their losses, epoch after epoch with other
+    training between them; an index outside 0..n-1 in the order is reported as an error."""
     import torch
     n, batch = 5000, 1024                      # four batches; the last 904 entries are unused
     F, T, mean, std, scale = raw_case(n, 7)
@@ -169,14 +169,22 @@ def test_train_epoch_equals_its_steps(dm):
     for net in (a, b):
         net.set_params(flat(p))
         net.set_normalisation(mean, std, scale)
-    La = a.train_epoch(Fd, Td, perm, batch, 1e-3)
-    losses = []
-    for k in range(n // batch):
-        idx = torch.tensor(order[k * batch:(k + 1) * batch], device="cuda")
-        losses.append(b.train_step(Fd[idx].contiguous(), Td[idx].contiguous(), 1e-3))
-    say(f"epoch loss {La:.6e}, mean of steps {np.mean(losses):.6e}")
-    assert np.array_equal(a.get_params(), b.get_params())
-    assert abs(La - np.mean(losses)) <= 1e-12 * abs(La)
+    # three epochs (the third at another rate), with single steps and host synchronisations
+    # between them, each checked against the same mini-batches fed to train_step
+    for epoch, lr in enumerate((1e-3, 1e-3, 5e-4)):
+        La = a.train_epoch(Fd, Td, perm, batch, lr)
+        losses = []
+        for k in range(n // batch):
+            idx = torch.tensor(order[k * batch:(k + 1) * batch], device="cuda")
+            losses.append(b.train_step(Fd[idx].contiguous(), Td[idx].contiguous(), lr))
+        say(f"epoch {epoch}: loss {La:.6e}, mean of steps {np.mean(losses):.6e}")
+        assert np.array_equal(a.get_params(), b.get_params()), epoch
+        assert abs(La - np.mean(losses)) <= 1e-12 * abs(La)
+        idx = torch.tensor(order[:batch], device="cuda")
+        for net in (a, b):                     # eager work between the replays
+            net.train_step(Fd[idx].contiguous(), Td[idx].contiguous(), 2e-4)
+        torch.cuda.synchronize()
+        assert np.array_equal(a.get_params(), b.get_params()), epoch
     bad = perm.clone()
     bad[3] = n
     with pytest.raises(dm.DmError):
