@@ -430,7 +430,9 @@ dm_status dm_ws_targets(dm_sim* sim, const double* F_prev, double dt, double* T)
  * network runs there on the matrix cores); a guess whose Newton solve fails within
  * warm_max_iter iterations is redone from x_n and counted in dm_stats.fallbacks.  The sim
  * keeps a reference to net, which must outlive its use.  After dm_set_state or
- * dm_load_checkpoint the velocity history is the current velocity (a = j = 0). */
+ * dm_load_checkpoint the velocity history is the current velocity (a = j = 0).  Mode 2 with
+ * self-contact on is DM_ERR_UNSUPPORTED where the network's activations and the self-contact
+ * arrays do not fit together in the workgroup's 64 KB of LDS. */
 dm_status dm_set_warm_start(dm_sim* sim, dm_mlp* net, int mode);
 /* The guessed displacement x^(0) - x_n of every feature row for a time step dt from the
  * current state under the current warm mode (not 0), into dx [rows][3] (device memory if

@@ -846,7 +846,8 @@ size_t step_lds(DmStepArgs& A) {
     A.sc_lds = (int)((base + 15) / 16 * 16);
     base = (size_t)A.sc_lds + 24 * (size_t)A.sc_max_edges + 4 * (size_t)A.sc_cap + 16 +
            2 * sizeof(double) * (4 * (size_t)A.sc_max_edges + 3);
-    A.sc_pb = base + sizeof(double) * 2 * 16 * 144 <= 65536 ? 16 : 8;
+    const size_t net = A.warm == 2 ? 16 + DM_NET_LDS_BYTES : 0;    // the network's area after it
+    A.sc_pb = base + sizeof(double) * 2 * 16 * 144 + net <= 65536 ? 16 : 8;
     base += sizeof(double) * 2 * (size_t)A.sc_pb * 144;
   }
   if (A.warm != 2) return base;
@@ -1435,8 +1436,20 @@ dm_status dm_set_warm_start(dm_sim* s, dm_mlp* net, int mode) {
   if (!s->finalized) return fail(DM_ERR_STATE, "dm_set_warm_start before dm_finalize");
   if (mode < 0 || mode > 4) return fail(DM_ERR_INVALID_ARG, "dm_set_warm_start: mode must be 0 .. 4");
   if (mode == 2 && !net) return fail(DM_ERR_INVALID_ARG, "dm_set_warm_start: mode 2 needs a network");
+  const int old_mode = s->ws_mode;
+  dm_mlp* const old_net = s->ws_net;
   s->ws_mode = mode;
   s->ws_net = mode == 2 ? net : nullptr;
+  if (s->sc_on && mode == 2) {
+    DmStepArgs A;
+    fill_step_args(s, 1.0, 1, A);
+    if (step_lds(A) > 65536) {
+      s->ws_mode = old_mode;
+      s->ws_net = old_net;
+      return fail(DM_ERR_UNSUPPORTED,
+                  "dm_set_warm_start: the network's activations and the self-contact arrays do not fit together in LDS");
+    }
+  }
   return DM_OK;
 }
 

@@ -185,3 +185,12 @@ def test_unsupported_setups(dm):
     with pytest.raises(dm.DmError) as e:
         sim.step(d["dt"], 1)
     assert e.value.status == dm.DM_ERR_UNSUPPORTED
+    sim.set_integrator("euler")
+    # the network's activations do not fit in LDS beside a 36-node rod's self-contact arrays:
+    # refused, and the analytic warm starts stay available
+    net = dm.Mlp(max_rows=64)
+    with pytest.raises(dm.DmError) as e:
+        sim.set_warm_start(net, 2)
+    assert e.value.status == dm.DM_ERR_UNSUPPORTED and "LDS" in str(e.value)
+    sim.set_warm_start(None, 4)
+    assert (sim.step(d["dt"], 2)["status"] == 0).all()
