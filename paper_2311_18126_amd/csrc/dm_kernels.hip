@@ -880,10 +880,14 @@ __device__ __noinline__ void sc_solve(ArgsP Ap, int sid, double dt, double DM_L*
   for (int q = tid; q < np; q += bd) wl = max(wl, 4 * ((keys[q] & 0xffff) + 1 - (keys[q] >> 16)) + 2);
   if (wl > 10) atomicMax(cnt + 2, wl);
   __syncthreads();
-  const int w = min(cnt[2], n - 1), W2 = 2 * w + 1;
-  // the band into the matrix
+  const int w = min(cnt[2], n - 1);
+  // the band into the matrix, zeros out to w plus the LU panel's width: the blocked LU reads
+  // its panel and U's block row that far from the diagonal (entries that are zero, and stay
+  // zero, in a band of half width w), where an earlier iterate's wider band may have left
+  // values
+  const int wz = min(w + (w <= SC_WPANEL ? A.sc_pb : 0), n - 1), W2 = 2 * wz + 1;
   for (int idx = tid; idx < n * W2; idx += bd) {
-    const int r = idx / W2, c = r - w + (idx - r * W2);
+    const int r = idx / W2, c = r - wz + (idx - r * W2);
     if (c < 0 || c >= n) continue;
     const int o = c - r + 10;
     double v = 0.0;

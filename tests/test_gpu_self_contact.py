@@ -137,6 +137,37 @@ def test_runs_are_bitwise_deterministic(dm):
         assert np.array_equal(a, b)
 
 
+def test_an_earlier_wider_band_leaves_no_trace(dm):
+    """A straight 151-node rod wound for one step into a three-turn helix whose turns touch
+    (50 nodes a turn: half bandwidth 210, the solve's one-pivot path writes the matrix far from
+    its diagonal), then the straight rod's checkpoint restored (no pairs: half bandwidth 10,
+    the blocked LU, whose panels reach 16 columns further): the next steps are bit for bit
+    those of a simulation that never held the helix."""
+    import math
+    n, L, h = 151, 1.5, 4e-3
+    d = W.desc([W.rod(W.straight_nodes(n, L), h, 1e6)], dt=1e-3, steps=3)
+    phi = np.arange(n) * 2.0 * math.pi / 50
+    R = 50 * (L / (n - 1)) / (2.0 * math.pi)
+    helix = np.stack([R * np.cos(phi), R * np.sin(phi), 7.5e-3 * phi / (2.0 * math.pi)], 1)
+    runs = []
+    for wind in (False, True):
+        sim = dm.sim_from_description(d)
+        sim.set_self_contact(5e-4, 10.0)
+        start = sim.checkpoint()
+        if wind:
+            sim.set_rod_state(0, x=helix)
+            st = sim.step(d["dt"], 1, allow_failure=True)
+            assert st["iters"][0] >= 1          # the wide matrix was factorised
+            sim.restore(start)
+        st = sim.step(d["dt"], 3)
+        assert (st["status"] == 0).all()
+        runs.append((sim.state()[0].copy(), int(st["iters"][0])))
+        sim.close()
+    say(f"Newton iterations: fresh {runs[0][1]}, after the helix {runs[1][1]}")
+    assert runs[0][1] == runs[1][1]
+    assert np.array_equal(runs[0][0], runs[1][0])
+
+
 def test_off_is_the_plain_step_bit_for_bit(dm):
     d = W.coiled_springs(2, seed=13, nmin=36, nmax=44)
     plain = dict(d)
