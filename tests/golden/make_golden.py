@@ -109,6 +109,24 @@ def golden_star100():
     return out
 
 
+def golden_coils():
+    """Two coils of the 256-coil self-contact batch (the one of most nodes and a seeded pick),
+    each with its own self-contact and friction, over 5 steps, with their initial shapes."""
+    d = W.coiled_springs(256, steps=5)
+    ns = np.array([r["x0"].shape[0] for r in d["rods"]])
+    rng = np.random.Generator(np.random.PCG64(BATCH_SAMPLE_SEED))
+    ids = sorted({int(np.argmax(ns)), int(rng.integers(0, len(ns)))})
+    outs = {}
+    for j, r in enumerate(ids):
+        o = run(d, [r], {1, 3, 5})
+        for k, v in o.items():
+            outs[f"{k}_r{j}"] = v
+        outs[f"x0_r{j}"] = d["rods"][r]["x0"]
+        print(f"  coils: coil {r} (N {ns[r]}) done", flush=True)
+    outs["rods"] = np.array(ids)
+    return outs
+
+
 # the adjoint workload at its full rod size and length (100 nodes, 200 steps, checkpoints every
 # 20), for its first two rods, from zero natural curvature toward the seeded target
 ADJ_FULL_RODS = 2
@@ -205,7 +223,8 @@ def golden_fit():
 GOLDEN = {"cantilever": golden_cantilever, "batch": golden_batch, "helix": golden_helix, "star": golden_star,
           "adjoint": golden_adjoint, "cantilever_midpoint": golden_cantilever_midpoint,
           "star_midpoint": golden_star_midpoint, "fit": golden_fit, "batch100": golden_batch100,
-          "star100": golden_star100, "adjoint_full": golden_adjoint_full, "real2sim": golden_real2sim}
+          "star100": golden_star100, "adjoint_full": golden_adjoint_full, "real2sim": golden_real2sim,
+          "coils": golden_coils}
 
 
 if __name__ == "__main__":

@@ -16,6 +16,7 @@ from oracle import der
 from parity import assert_parity
 
 pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 @pytest.fixture(scope="module")
@@ -60,6 +61,28 @@ def test_coils_match_live_oracle(dm, mu):
                           f"coil {r} step {k} ({n_pairs} pairs)")
         done = k
     say(f"GPU Newton iterations over 3 steps of 2 coils: {iters_gpu}")
+
+
+def test_full_batch_sampled_coils_match_golden(dm):
+    """The 256-coil batch stepped as bench.py steps it (one launch for all coils, adaptive
+    halving on) against the oracle's steps of two of its coils (tests/golden/coils.npz, written
+    by tests/golden/make_golden.py from the oracle alone): 1e-9 of the positions and 1e-6 of the
+    displacement after one step, 1e-6 of both after three and five."""
+    g = np.load(os.path.join(GOLD, "coils.npz"))
+    d = W.coiled_springs(256, steps=5)
+    sim = dm.sim_from_description(d)
+    sim.set_adaptive(3)
+    done = 0
+    for k in (1, 3, 5):
+        st = sim.step(d["dt"], k - done)
+        done = k
+        assert (st["status"] == 0).all()
+        for j, r in enumerate(g["rods"]):
+            r = int(r)
+            assert st["halvings"][sim.rod_system(r)] == 0, (r, k)
+            assert_parity(sim.rod_state(r)[0], g[f"x_{k}_0_r{j}"], g[f"x0_r{j}"], 1e-9 if k == 1 else 1e-6, 1e-6,
+                          f"coil {r} step {k}")
+    say(f"sampled coils {g['rods'].tolist()}: oracle Newton iterations {[g[f'iters_r{j}'].tolist() for j in range(len(g['rods']))]}")
 
 
 def test_coil_with_friction_over_ten_steps(dm):
