@@ -849,13 +849,60 @@ __device__ __forceinline__ double wave_sum64(double v) {
   return v;
 }
 
+// LU without pivoting of a panel of b <= SC_PBMAX columns and R <= blockDim.x rows, held in LDS
+// column by column (pan[c * RP + i]): thread tid keeps row tid in registers, and a row goes
+// back to LDS once it is final, so that pivot q reads row q there; one barrier per pivot.  The
+// pivot guard is the band solve's (a pivot below 1e-12 of its assembled diagonal dg, or not
+// finite): returns true, in every thread, when a pivot failed it (the later pivots still run,
+// on values the caller discards).  Otherwise pan holds the factorised panel, U on and above
+// the diagonal and the multipliers below it.  The pivot loop has no early exit, so that it
+// unrolls and the row stays in registers.
+__device__ __forceinline__ bool sc_panel(double DM_L* pan, const double DM_G* dg, int b, int R, int tid) {
+  constexpr int RP = SC_WPANEL + SC_PBMAX;
+  const bool mine = tid < R;
+  double row[SC_PBMAX];
+#pragma unroll
+  for (int c = 0; c < SC_PBMAX; ++c) row[c] = mine && c < b ? pan[c * RP + tid] : 0.0;
+  bool bad = false;
+#pragma unroll
+  for (int q = 0; q < SC_PBMAX; ++q) {
+    if (q < b) {
+      __syncthreads();                 // row q is final in LDS (row 0 as loaded)
+      const double p = pan[q * RP + q];
+      bad = bad || !(fabs(p) > 1e-12 * fabs(dg[q])) || !isfinite(p);
+      const double inv = 1.0 / p;
+      double pr[SC_PBMAX];
+#pragma unroll
+      for (int c = q + 1; c < SC_PBMAX; ++c) pr[c] = c < b ? pan[c * RP + q] : 0.0;
+      if (mine && tid > q) {
+        const double l = row[q] * inv;
+        row[q] = l;
+#pragma unroll
+        for (int c = q + 1; c < SC_PBMAX; ++c) row[c] -= l * pr[c];
+        if (tid == q + 1 && tid < b) {
+#pragma unroll
+          for (int c = 0; c < SC_PBMAX; ++c)
+            if (c < b) pan[c * RP + tid] = row[c];
+        }
+      }
+    }
+  }
+  if (mine && tid >= b) {               // the rows below the panel's top: their multipliers
+#pragma unroll
+    for (int c = 0; c < SC_PBMAX; ++c)
+      if (c < b) pan[c * RP + tid] = row[c];
+  }
+  __syncthreads();
+  return bad;
+}
+
 // Newton step of a rod with self-contact.  The rod's Jacobian, its band (the border rows'
 // border columns included) plus the blocks between the different nodes of every pair, goes to
 // the system's dense n x n matrix over the half bandwidth w the pairs need (at least the
 // band's 10); LU without pivoting over that band (the pivot guard of the band solve: a pivot
 // below 1e-12 of its assembled diagonal, or not finite, sets the singular flag), forward and
-// back substitution by one wavefront, and the step goes to the delta and border-solution slots
-// the update reads.  Called by the whole workgroup after the matrix pass of the iterate whose
+// back substitution, and the step goes to the delta and border-solution slots the update
+// reads.  Called by the whole workgroup after the matrix pass of the iterate whose
 // pairs self_contact left in LDS.
 __device__ __noinline__ void sc_solve(ArgsP Ap, int sid, double dt, double DM_L* xB, int DM_L* flags) {
   const DmStepArgs DM_C& A = *uniform(Ap);
@@ -952,11 +999,13 @@ __device__ __noinline__ void sc_solve(ArgsP Ap, int sid, double dt, double DM_L*
   }
   __syncthreads();
   // LU without pivoting over the band of half width w.  Blocked: sc_pb pivot columns at a time
-  // are factorised in LDS (the panel of their rows below, and the block row of U to their
-  // right), then the trailing band takes one rank-sc_pb update in HBM, each lane loading its
-  // entries in batches before any is stored, so the loads overlap (the update streams the
-  // band through the caches once per panel: the wider the panel, the less traffic).  A rod
-  // whose half bandwidth exceeds the LDS panel takes one pivot at a time.
+  // are factorised (the panel of their rows below, staged in LDS, each thread's rows in
+  // registers; the block row of U to their right solved per column in registers), the
+  // forward substitution passes through the panel, then the trailing band takes one rank-sc_pb
+  // update in HBM, each lane loading its entries in batches before any is stored, so the loads
+  // overlap (the update streams the band through the caches once per panel: the wider the
+  // panel, the less traffic).  A rod whose half bandwidth exceeds the LDS panel takes one
+  // pivot at a time and row-by-row substitutions.
   constexpr int SB = 12;
   bool bad = false;
   if (w <= SC_WPANEL) {
@@ -964,6 +1013,8 @@ __device__ __noinline__ void sc_solve(ArgsP Ap, int sid, double dt, double DM_L*
     const int PB = A.sc_pb;
     double DM_L* pan = lcol + (4 * ME + 3);          // [PB][RP]: column q of the panel
     double DM_L* ub = pan + PB * RP;                 // [PB][RP]: row q of U right of the panel
+    // the right-hand side: the forward substitution runs inside the LU, a panel at a time
+    for (int r = tid; r < n; r += bd) y[r] = D.R[ch.dof_off + r];
     for (int k0 = 0; k0 < n; k0 += PB) {
       const int b = min(PB, n - k0), R = min(n - k0, b + w), C = min(n - k0 - b, w);
       for (int e = tid; e < R * b; e += bd) {        // a row's b entries by consecutive lanes
@@ -975,26 +1026,61 @@ __device__ __noinline__ void sc_solve(ArgsP Ap, int sid, double dt, double DM_L*
         ub[q * RP + c] = M[(size_t)(k0 + q) * n + k0 + b + c];
       }
       __syncthreads();
-      // the panel: each lane owns its rows, one barrier per pivot
-      for (int q = 0; q < b; ++q) {
-        const double p = pan[q * RP + q];
-        if (!(fabs(p) > 1e-12 * fabs(d0[k0 + q])) || !isfinite(p)) { bad = true; break; }
-        const double inv = 1.0 / p;
-        for (int i = q + 1 + tid; i < R; i += bd) {
-          const double l = pan[q * RP + i] * inv;
-          pan[q * RP + i] = l;
-          for (int c = q + 1; c < b; ++c) pan[c * RP + i] -= l * pan[c * RP + q];
+      if (R <= bd) {
+        bad = sc_panel(pan, d0 + k0, b, R, tid);
+      } else {
+        // a workgroup narrower than the panel: each lane owns rows in LDS, one barrier per pivot
+        for (int q = 0; q < b; ++q) {
+          const double p = pan[q * RP + q];
+          if (!(fabs(p) > 1e-12 * fabs(d0[k0 + q])) || !isfinite(p)) { bad = true; break; }
+          const double inv = 1.0 / p;
+          for (int i = q + 1 + tid; i < R; i += bd) {
+            const double l = pan[q * RP + i] * inv;
+            pan[q * RP + i] = l;
+            for (int c = q + 1; c < b; ++c) pan[c * RP + i] -= l * pan[c * RP + q];
+          }
+          __syncthreads();
         }
-        __syncthreads();
       }
       if (bad) break;
-      // U's block row: the unit lower triangle of the panel's top solved per column
-      for (int c = tid; c < C; c += bd)
-        for (int t = 1; t < b; ++t) {
-          double v = ub[t * RP + c];
-          for (int q = 0; q < t; ++q) v -= pan[q * RP + t] * ub[q * RP + c];
-          ub[t * RP + c] = v;
+      // forward substitution through the panel (one wavefront, rows lane + 64 m): the top b
+      // rows' values are final here, and each goes out to the rows below by its multipliers
+      if (tid < 64) {
+        double z[3];
+#pragma unroll
+        for (int m = 0; m < 3; ++m) z[m] = lane + 64 * m < R ? y[k0 + lane + 64 * m] : 0.0;
+#pragma unroll
+        for (int q = 0; q < SC_PBMAX; ++q) {
+          if (q < b) {
+            const double yq = readlane_d(z[0], q);
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+              const int i = lane + 64 * m;
+              if (i > q && i < R) z[m] -= pan[q * RP + i] * yq;
+            }
+          }
         }
+#pragma unroll
+        for (int m = 0; m < 3; ++m)
+          if (lane + 64 * m < R) y[k0 + lane + 64 * m] = z[m];
+      }
+      // U's block row: the unit lower triangle of the panel's top solved per column
+      for (int c = tid; c < C; c += bd) {
+        double u[SC_PBMAX];
+#pragma unroll
+        for (int t = 0; t < SC_PBMAX; ++t) u[t] = t < b ? ub[t * RP + c] : 0.0;
+#pragma unroll
+        for (int t = 1; t < SC_PBMAX; ++t)
+          if (t < b) {
+            double v = u[t];
+#pragma unroll
+            for (int q = 0; q < t; ++q) v -= pan[q * RP + t] * u[q];
+            u[t] = v;
+          }
+#pragma unroll
+        for (int t = 1; t < SC_PBMAX; ++t)
+          if (t < b) ub[t * RP + c] = u[t];
+      }
       __syncthreads();
       // the trailing band's rank-b update: one column per lane (its U entries in registers),
       // the lanes of a column group taking every G-th row, TB rows' loads before their stores;
@@ -1039,6 +1125,92 @@ __device__ __noinline__ void sc_solve(ArgsP Ap, int sid, double dt, double DM_L*
       }
       __syncthreads();
     }
+    // back substitution a block of PB rows at a time from the bottom: the block's rows of U
+    // (from the diagonal to w right of it) come to LDS, each loaded while the block before is
+    // solved; the part right of the block is summed by 16 lanes per row, then one wavefront
+    // solves the block's triangle a column at a time
+    if (!bad) {
+      constexpr int PF = 12;
+      const int nblk = (n + PB - 1) / PB;
+      auto blk_entry = [&](int kb, int e, int Wd, bool& ok) -> size_t {
+        const int q = e / Wd, c = e - q * Wd;
+        ok = c >= q && c - q <= w;
+        return (size_t)(kb * PB + q) * n + kb * PB + c;
+      };
+      {
+        const int k0 = (nblk - 1) * PB, b = n - k0, Wd = min(n - k0, b + w);
+        double DM_L* buf = ((nblk - 1) & 1) ? ub : pan;
+        for (int e0 = tid; e0 < b * Wd; e0 += PF * bd) {
+          double v[PF];
+#pragma unroll
+          for (int j = 0; j < PF; ++j) {
+            const int e = min(e0 + j * bd, b * Wd - 1);
+            bool ok;
+            const size_t at = blk_entry(nblk - 1, e, Wd, ok);
+            v[j] = ok ? M[at] : 0.0;
+          }
+#pragma unroll
+          for (int j = 0; j < PF; ++j) {
+            const int e = e0 + j * bd;
+            if (e < b * Wd) buf[(e / Wd) * RP + e % Wd] = v[j];
+          }
+        }
+      }
+      for (int kb = nblk - 1; kb >= 0; --kb) {
+        __syncthreads();                             // block kb in LDS, the rows below solved
+        const int k0 = kb * PB, b = min(PB, n - k0), Wd = min(n - k0, b + w);
+        const double DM_L* buf = (kb & 1) ? ub : pan;
+        // the next block's entries: loads issued now, stored after this block's solve
+        const int kn = kb - 1, Wn = kn >= 0 ? min(n - kn * PB, PB + w) : 0, tn = kn >= 0 ? PB * Wn : 0;
+        double nv[PF];
+#pragma unroll
+        for (int j = 0; j < PF; ++j) {
+          const int e = min(tid + j * bd, max(tn - 1, 0));
+          bool ok = false;
+          const size_t at = tn > 0 ? blk_entry(kn, e, Wn, ok) : 0;
+          nv[j] = ok ? M[at] : 0.0;
+        }
+        for (int t = tid; t < b * 16; t += bd) {
+          const int q = t >> 4, sub = t & 15;
+          double acc = 0.0;
+          for (int c = b + sub; c < Wd; c += 16) acc += buf[q * RP + c] * y[k0 + c];
+          acc += __shfl_xor(acc, 8, 16);
+          acc += __shfl_xor(acc, 4, 16);
+          acc += __shfl_xor(acc, 2, 16);
+          acc += __shfl_xor(acc, 1, 16);
+          if (sub == 0) lcol[q] = acc;
+        }
+        __syncthreads();
+        if (tid < 64) {
+          double u[SC_PBMAX];
+#pragma unroll
+          for (int c = 0; c < SC_PBMAX; ++c) u[c] = lane < b && c < b ? buf[lane * RP + c] : 0.0;
+          double v = lane < b ? y[k0 + lane] - lcol[lane] : 0.0, mine = 0.0;
+#pragma unroll
+          for (int c = SC_PBMAX - 1; c >= 0; --c) {
+            if (c < b) {
+              const double yc = readlane_d(v / u[c], c);
+              if (lane == c) mine = yc;
+              if (lane < c) v -= u[c] * yc;
+            }
+          }
+          if (lane < b) y[k0 + lane] = mine;
+        }
+        if (kn >= 0) {
+          double DM_L* nb = (kn & 1) ? ub : pan;
+#pragma unroll
+          for (int j = 0; j < PF; ++j) {
+            const int e = tid + j * bd;
+            if (e < tn) nb[(e / Wn) * RP + e % Wn] = nv[j];
+          }
+          for (int e = tid + PF * bd; e < tn; e += bd) {
+            bool ok;
+            const size_t at = blk_entry(kn, e, Wn, ok);
+            nb[(e / Wn) * RP + e % Wn] = ok ? M[at] : 0.0;
+          }
+        }
+      }
+    }
   } else {
     for (int k = 0; k < n; ++k) {
       const double p = M[(size_t)k * n + k];
@@ -1070,54 +1242,8 @@ __device__ __noinline__ void sc_solve(ArgsP Ap, int sid, double dt, double DM_L*
       }
       __syncthreads();
     }
-  }
-  if (bad) {
-    if (tid == 0) flags[0] = 1;
-    __syncthreads();
-    return;
-  }
-  // forward and back substitution, one wavefront; a lane holds entries lane and lane + 64 of
-  // a row's band part (w <= 128), and the next row's are loaded before the current row's sum
-  if (tid < 64) {
-    if (w <= 128) {
-      auto fwd = [&](int i, double& a0, double& a1) {
-        const double DM_G* row = M + (size_t)i * n;
-        const int j0 = i - w + lane, j1 = j0 + 64;
-        a0 = (j0 >= 0 && j0 < i) ? row[j0] : 0.0;
-        a1 = (j1 >= 0 && j1 < i) ? row[j1] : 0.0;
-      };
-      double c0, c1, r0 = D.R[ch.dof_off];
-      fwd(0, c0, c1);
-      for (int i = 0; i < n; ++i) {
-        double n0 = 0.0, n1 = 0.0, rn = 0.0;
-        if (i + 1 < n) { fwd(i + 1, n0, n1); rn = D.R[ch.dof_off + i + 1]; }
-        const int j0 = i - w + lane, j1 = j0 + 64;
-        double acc = c0 * (j0 >= 0 && j0 < i ? y[j0] : 0.0) + c1 * (j1 >= 0 && j1 < i ? y[j1] : 0.0);
-        acc = wave_sum64(acc);
-        if (lane == 0) y[i] = r0 - acc;
-        lds_order();
-        c0 = n0; c1 = n1; r0 = rn;
-      }
-      auto bwd = [&](int i, double& a0, double& a1, double& dg) {
-        const double DM_G* row = M + (size_t)i * n;
-        const int j0 = i + 1 + lane, j1 = j0 + 64, hi = min(n - 1, i + w);
-        a0 = j0 <= hi ? row[j0] : 0.0;
-        a1 = j1 <= hi ? row[j1] : 0.0;
-        dg = row[i];
-      };
-      double dg;
-      bwd(n - 1, c0, c1, dg);
-      for (int i = n - 1; i >= 0; --i) {
-        double n0 = 0.0, n1 = 0.0, dn = 1.0;
-        if (i > 0) bwd(i - 1, n0, n1, dn);
-        const int j0 = i + 1 + lane, j1 = j0 + 64, hi = min(n - 1, i + w);
-        double acc = c0 * (j0 <= hi ? y[j0] : 0.0) + c1 * (j1 <= hi ? y[j1] : 0.0);
-        acc = wave_sum64(acc);
-        if (lane == 0) y[i] = (y[i] - acc) / dg;
-        lds_order();
-        c0 = n0; c1 = n1; dg = dn;
-      }
-    } else {
+    // forward and back substitution by one wavefront, a row's sum over the band at a time
+    if (!bad && tid < 64) {
       for (int i = 0; i < n; ++i) {
         const double DM_G* row = M + (size_t)i * n;
         double acc = 0.0;
@@ -1135,6 +1261,11 @@ __device__ __noinline__ void sc_solve(ArgsP Ap, int sid, double dt, double DM_L*
         lds_order();
       }
     }
+  }
+  if (bad) {
+    if (tid == 0) flags[0] = 1;
+    __syncthreads();
+    return;
   }
   __syncthreads();
   for (int r = tid; r < n; r += bd) {

@@ -144,6 +144,25 @@ def test_wide_and_long_rods_match_the_band_solve_when_contact_is_negligible(dm):
     assert_parity(sc.state()[0], plain.state()[0], x0, 1e-9, 1e-6, "negligible contact vs plain")
 
 
+@pytest.mark.parametrize("block", [64, 128])
+def test_small_workgroups_match_the_default(dm, block):
+    """The LU's panel keeps one, two or three rows per thread (workgroups of 256, 128 and 64
+    lanes for the up to 144 panel rows of a coil): four coils with friction over three steps
+    take the same Newton iterations and agree with the default workgroup to 1e-9 relative in
+    position and 1e-6 in displacement."""
+    d = W.coiled_springs(4, seed=13, nmin=60, nmax=80)
+    say(f"case: four coils, workgroup of {block} lanes against 256")
+    ref = dm.sim_from_description(d, block_size=256)
+    small = dm.sim_from_description(d, block_size=block)
+    x0 = ref.state()[0].copy()
+    a = ref.step(d["dt"], 3)
+    b = small.step(d["dt"], 3)
+    assert (a["status"] == 0).all() and (b["status"] == 0).all()
+    say(f"Newton iterations: 256 lanes {a['iters'].tolist()}, {block} lanes {b['iters'].tolist()}")
+    assert a["iters"].tolist() == b["iters"].tolist()
+    assert_parity(small.state()[0], ref.state()[0], x0, 1e-9, 1e-6, f"{block} lanes vs 256")
+
+
 def test_runs_are_bitwise_deterministic(dm):
     """Pairs are found with an LDS atomic counter but sorted before any sum, and every node sums
     its pairs in the list's order: two runs of 32 coils with friction agree bit for bit."""
