@@ -451,18 +451,18 @@ def config_table(dm, log):
     def fp64_frac(flops, kernel_s):
         return flops / kernel_s / (PEAK_FP64_VALU_TFLOPS * 1e12)
 
-    # cfg1: single cantilever
+    # single cantilever
     d = W.cantilever(steps=100)
     v, it, ks, nodes, iters = gpu_run(d, 100)
     vw, itw, _, _, _ = gpu_run(d, 100, warm=3)
     one = lambda: (lambda: der.simulate(d, steps=2), 2 * 51)
-    rows.append({"config": "cfg1 cantilever N=51, dt 1e-2, 100 steps", "plain_per_rod_gpu": v, "batched_gpu": None,
+    rows.append({"config": "cantilever N=51, dt 1e-2, 100 steps", "plain_per_rod_gpu": v, "batched_gpu": None,
                  "warm_started_gpu": vw, "cpu_oracle_1_thread": oracle_rate(one, 1, 4.0),
                  "cpu_oracle_all_cores": oracle_rate(one, threads, 4.0), "cores": threads,
                  "fp64_roof_fraction": fp64_frac(float(rod_iteration_flops(51)) * iters, ks), "hbm_roof_fraction": None,
                  "newton_iters_plain": it, "newton_iters_warm": itw})
     log(f"configs: {rows[-1]}")
-    # cfg2: 1024-rod batch
+    # 1024-rod batch
     d = W.rod_batch(1024)
     n_r = np.array([r["x0"].shape[0] for r in d["rods"]], dtype=float)
     sim = dm.sim_from_description(d)
@@ -483,28 +483,28 @@ def config_table(dm, log):
         return (lambda: der.simulate(sub, steps=1)), sub["rods"][0]["x0"].shape[0]
     c1 = oracle_rate(one_rod, 1, 6.0)
     call = oracle_rate(one_rod, threads, 6.0)
-    rows.append({"config": "cfg2 1024 rods N~U{20..400}, dt 1e-3", "plain_per_rod_gpu": per_rod_baseline(dm, d, 20),
+    rows.append({"config": "1024 rods N~U{20..400}, dt 1e-3", "plain_per_rod_gpu": per_rod_baseline(dm, d, 20),
                  "batched_gpu": v, "warm_started_gpu": vw, "cpu_oracle_1_thread": c1, "cpu_oracle_all_cores": call,
                  "cores": threads, "fp64_roof_fraction": fp64_frac(float((rod_iteration_flops(n_r) * st["iters"]).sum()), ks),
                  "hbm_roof_fraction": None if traffic is None else traffic / ks / 8e12,
                  "newton_iters_plain": it, "newton_iters_warm": itw})
     log(f"configs: {rows[-1]}")
-    # cfg3: six-limb stars
+    # six-limb stars
     d1 = W.star_robots(1, steps=10)
     v1, _, _, _, _ = gpu_run(d1, 10)
     d = W.star_robots(4096)
     v, it, ks, nodes, iters = gpu_run(d, 10)
     vw, itw, _, _, _ = gpu_run(d, 10, warm=3)
     star = lambda: (lambda: der.simulate(d1, steps=1), 6 * 30 + 1)
-    rows.append({"config": "cfg3 4096 six-limb stars, floor contact, actuation", "plain_per_rod_gpu": v1,
+    rows.append({"config": "4096 six-limb stars, floor contact, actuation", "plain_per_rod_gpu": v1,
                  "batched_gpu": v, "warm_started_gpu": vw, "cpu_oracle_1_thread": oracle_rate(star, 1, 6.0),
                  "cpu_oracle_all_cores": oracle_rate(star, threads, 6.0), "cores": threads,
                  "fp64_roof_fraction": fp64_frac(star_iteration_flops() * iters, ks),
                  "hbm_roof_fraction": None, "newton_iters_plain": it, "newton_iters_warm": itw})
     log(f"configs: {rows[-1]}")
-    # cfg4: learned warm start (network) on fresh rods
+    # learned warm start (network) on fresh rods
     ws = warm_start_section(dm, 1000, log)
-    rows.append({"config": "cfg4 learned warm start, trained on 1e6 rod-steps of cfg2, 1024 fresh rods "
+    rows.append({"config": "learned warm start, trained on 1e6 rod-steps of the 1024-rod batch, 1024 fresh rods "
                            "N~U{50..400}, 1000 steps", "plain_per_rod_gpu": None,
                  "batched_gpu": ws["plain_value"], "warm_started_gpu": ws["network_value"],
                  "warm_started_gpu_extrapolation": ws["extrapolation_value"],
@@ -512,7 +512,7 @@ def config_table(dm, log):
                  "cpu_oracle_all_cores": None, "cores": threads, "fp64_roof_fraction": None, "hbm_roof_fraction": None,
                  "newton_iters_plain": ws["plain_iters_per_step"], "newton_iters_warm": ws["network_iters_per_step"]})
     log(f"configs: {rows[-1]}")
-    # cfg5: adjoint
+    # adjoint
     adj = adjoint_section(dm)
     da, kstar = W.adjoint_rods(n_rods=1, n_nodes=100, steps=5)
     _, _, target = AD.rollout(da, [kstar[0]])
@@ -520,7 +520,7 @@ def config_table(dm, log):
 
     def adj_unit():
         return (lambda: AD.loss_and_grad(da, k0, target.numpy())), 100 * 5
-    rows.append({"config": "cfg5 adjoint 256 rods x 100 nodes x 200 steps (forward + backward)",
+    rows.append({"config": "adjoint 256 rods x 100 nodes x 200 steps (forward + backward)",
                  "plain_per_rod_gpu": None, "batched_gpu": adj["value"], "warm_started_gpu": None,
                  "cpu_oracle_1_thread": oracle_rate(adj_unit, 1, 8.0),
                  "cpu_oracle_all_cores": oracle_rate(adj_unit, threads, 8.0), "cores": threads,

@@ -69,7 +69,7 @@ def test_one_star_matches_golden_over_100_steps(dm):
 
 
 def test_full_star_batch_instance_matches_golden(dm):
-    """All 4096 stars in one launch (the cfg3 configuration); instance 0 against the oracle."""
+    """All 4096 stars in one launch (the star benchmark's size); instance 0 against the oracle."""
     g = np.load(os.path.join(GOLD, "star.npz"))
     d = W.star_robots(n_instances=4096, steps=5)
     print("case: 4096 stars, 5 steps", flush=True)
