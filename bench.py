@@ -251,18 +251,35 @@ def warm_start_section(dm, steps, log, train_steps=1000, skip=100):
 
 
 def star_section(dm, steps):
-    """4096 six-limb stars on the floor with actuation (joined rods, arrowhead solve)."""
+    """4096 six-limb stars on the floor with actuation (joined rods, arrowhead solve), from the
+    plain Newton start and from the analytic warm starts (explicit predictor, second-order
+    extrapolation), each from the same initial state; the warm-started end states are compared
+    with the plain one."""
     import workloads as W
     d = W.star_robots(4096)
-    sim = dm.sim_from_description(d)
-    sim.step(d["dt"], 1)
-    st, wall = timed_steps(sim, d["dt"], steps)
-    assert (st["status"] == 0).all()
-    nodes = float(sim.num_nodes)
-    return {"workload": "4096 stars: 6 limbs x 30 nodes on a shared hub, floor contact and friction, "
-                        "sinusoidal actuation (seed 1)", "steps": steps, "value": nodes * steps / wall,
-            "unit": "node-steps/s", "newton_iters_per_step": float(st["iters"].mean() / steps),
-            "block_size": sim.block_size}
+    out, x_plain = None, None
+    for mode, name in ((0, None), (1, "explicit"), (3, "second_order")):
+        sim = dm.sim_from_description(d)
+        if mode:
+            sim.set_warm_start(None, mode)
+        sim.step(d["dt"], 1)
+        st, wall = timed_steps(sim, d["dt"], steps)
+        assert (st["status"] == 0).all()
+        nodes = float(sim.num_nodes)
+        x = sim.state()[0]
+        res = {"value": nodes * steps / wall, "unit": "node-steps/s",
+               "newton_iters_per_step": float(st["iters"].mean() / steps)}
+        if mode == 0:
+            x_plain = x
+            out = {"workload": "4096 stars: 6 limbs x 30 nodes on a shared hub, floor contact and friction, "
+                               "sinusoidal actuation (seed 1)", "steps": steps, **res, "block_size": sim.block_size,
+                   "warm_started": {}}
+        else:
+            res["fallbacks"] = int(st["fallbacks"].sum())
+            res["max_position_difference_vs_plain_m"] = float(np.abs(x - x_plain).max())
+            out["warm_started"][name] = res
+        sim.close()
+    return out
 
 
 def midpoint_section(dm, steps):

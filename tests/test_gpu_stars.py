@@ -129,3 +129,25 @@ def test_many_limb_star_matches_oracle(dm, limbs):
         got = np.concatenate([sim.rod_state(a)[0] for a in range(limbs)])
         x0 = np.concatenate([d["rods"][a]["x0"] for a in range(limbs)])
         assert_parity(got, ref, x0, tol, 1e-6, f"{limbs} limbs, step {k}")
+
+
+@pytest.mark.parametrize("mode", [1, 3])
+def test_warm_started_stars_reach_the_plain_states(dm, mode):
+    """The analytic warm starts on joined limbs with floor contact and friction (explicit
+    predictor, second-order extrapolation): 64 stars over 50 steps end where the plain Newton
+    start ends (each solve stops within its 1e-9 N residual tolerance: positions within 1e-8 m)
+    in fewer Newton iterations, with no fallback to the plain start."""
+    d = W.star_robots(n_instances=64, steps=50)
+    print(f"case: 64 stars, 50 steps, warm-start mode {mode}", flush=True)
+    plain = dm.sim_from_description(d)
+    warm = dm.sim_from_description(d)
+    warm.set_warm_start(None, mode)
+    a = plain.step(d["dt"], 50)
+    b = warm.step(d["dt"], 50)
+    assert (a["status"] == 0).all() and (b["status"] == 0).all()
+    assert int(b["fallbacks"].sum()) == 0
+    ia, ib = int(a["iters"].sum()), int(b["iters"].sum())
+    diff = float(np.abs(warm.state()[0] - plain.state()[0]).max())
+    print(f"Newton iterations: plain {ia}, warm {ib}; max position difference {diff:.2e} m", flush=True)
+    assert ib < 0.9 * ia
+    assert diff < 1e-8
