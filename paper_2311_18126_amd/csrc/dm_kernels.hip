@@ -860,16 +860,19 @@ __device__ __forceinline__ double wave_sum64(double v) {
 __device__ __forceinline__ bool sc_panel(double DM_L* pan, const double DM_G* dg, int b, int R, int tid) {
   constexpr int RP = SC_WPANEL + SC_PBMAX;
   const bool mine = tid < R;
-  double row[SC_PBMAX];
+  double row[SC_PBMAX], guard[SC_PBMAX];
 #pragma unroll
-  for (int c = 0; c < SC_PBMAX; ++c) row[c] = mine && c < b ? pan[c * RP + tid] : 0.0;
+  for (int c = 0; c < SC_PBMAX; ++c) {
+    row[c] = mine && c < b ? pan[c * RP + tid] : 0.0;
+    guard[c] = c < b ? 1e-12 * fabs(dg[c]) : 0.0;     // loaded once, not after each barrier
+  }
   bool bad = false;
 #pragma unroll
   for (int q = 0; q < SC_PBMAX; ++q) {
     if (q < b) {
       __syncthreads();                 // row q is final in LDS (row 0 as loaded)
       const double p = pan[q * RP + q];
-      bad = bad || !(fabs(p) > 1e-12 * fabs(dg[q])) || !isfinite(p);
+      bad = bad || !(fabs(p) > guard[q]) || !isfinite(p);
       const double inv = 1.0 / p;
       double pr[SC_PBMAX];
 #pragma unroll
