@@ -337,7 +337,7 @@ def self_contact_section(dm, steps, n_rods=4096):
         out[key] = {"value": float(sim.num_nodes) * steps / wall if failed == 0 else None,
                     "ms_per_step": 1e3 * wall / steps, "failed_systems": failed,
                     "newton_iters_per_step": float(st["iters"].mean() / steps),
-                    "halved_steps": int(st["halvings"].sum())}
+                    "halved_steps": int(st["halvings"].sum()), "block_size": sim.block_size}
         sim.close()
     return out
 

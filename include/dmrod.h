@@ -299,7 +299,9 @@ dm_status dm_fit_limb_curvatures(dm_sim* sim, double dt, int n_settle, int n_con
  * self-contact arrays do not fit in 64 KB of LDS (about 400 nodes) or matrices beyond the
  * limit; dm_step then needs the backward-Euler integrator, and the adjoint and the Real2Sim
  * gradient refuse it.  A rod with more than four times as many pairs as edges at some
- * iterate stops there with DM_ERR_UNSUPPORTED. */
+ * iterate stops there with DM_ERR_UNSUPPORTED.  Without a workgroup size in dm_config (and
+ * before any dm_autotune), the step then runs 512 lanes per rod, 256 again when self-contact
+ * is turned off. */
 dm_status dm_set_self_contact(dm_sim* sim, double delta, double k_c, double mu, double nu);
 
 /* ---- Edge-edge contact (Contact and Friction subsection, Eq. 10-13) ----------------------

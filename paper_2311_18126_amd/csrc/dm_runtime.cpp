@@ -93,6 +93,7 @@ struct dm_sim {
   // layout
   int n_nodes = 0, n_edges = 0, n_st = 0, n_sys = 0, n_chains = 0, n_arms = 0, n_dof = 0;
   int max_nb = 0, max_arms = 0, max_seg = 0, block = 0;
+  bool block_auto = false;   // no workgroup size given or tuned: the step's default applies
   // edge-edge self-contact of single-rod systems (dm_set_self_contact)
   int sc_on = 0, sc_max_edges = 0;
   double sc_delta = 0.0, sc_kc = 0.0, sc_mu = 0.0, sc_nu = 1.0;
@@ -777,6 +778,7 @@ dm_status do_finalize(dm_sim* s) {
   // natural curvature and actuation may be set again later; keep a copy of stencil->rod
   s->finalized = true;
   int blk = s->cfg.block_size;
+  s->block_auto = blk <= 0;
   if (blk <= 0) blk = 256;   // four wavefronts: element work in parallel, up to 16 arms per sweep
   s->block = blk;
   return DM_OK;
@@ -1369,6 +1371,7 @@ dm_status dm_set_self_contact(dm_sim* s, double delta, double k_c, double mu, do
   if (!s->finalized) return fail(DM_ERR_STATE, "dm_set_self_contact before dm_finalize");
   if (k_c == 0.0) {
     s->sc_on = 0;
+    if (s->block_auto) s->block = 256;
     return DM_OK;
   }
   if (!(delta > 0.0) || !(k_c > 0.0) || !(mu >= 0.0) || !(nu > 0.0) || !std::isfinite(delta) || !std::isfinite(k_c) ||
@@ -1412,6 +1415,10 @@ dm_status dm_set_self_contact(dm_sim* s, double delta, double k_c, double mu, do
     s->sc_on = 0;
     return fail(DM_ERR_UNSUPPORTED, "dm_set_self_contact: the pair list of the longest rod does not fit in LDS");
   }
+  // eight wavefronts per rod by default: a rod's self-contact solve is bound by the latency of
+  // its own stages, which more lanes shorten (256 coils, one per CU: 12.3 ms per step at 512
+  // lanes against 16.2 at 256); dm_autotune picks per workload
+  if (s->block_auto) s->block = 512;
   return DM_OK;
 }
 
@@ -1786,8 +1793,8 @@ dm_status dm_autotune(dm_sim* s, double dt, int trial_steps, const char* cache_p
   int max_cn = 0;
   for (const DmSystem& S : s->sys) max_cn = std::max(max_cn, S.chain_nodes);
   char sig[512];
-  std::snprintf(sig, sizeof(sig), "dmrod1 %s sys=%d nodes=%d maxcn=%d arms=%d nb=%d dof=%d mode=%d", prop.gcnArchName,
-                s->n_sys, s->n_nodes, max_cn, s->max_arms, s->max_nb, s->n_dof, s->ws_mode);
+  std::snprintf(sig, sizeof(sig), "dmrod1 %s sys=%d nodes=%d maxcn=%d arms=%d nb=%d dof=%d mode=%d sc=%d", prop.gcnArchName,
+                s->n_sys, s->n_nodes, max_cn, s->max_arms, s->max_nb, s->n_dof, s->ws_mode, s->sc_on);
   for (char* c = sig; *c; ++c) if (*c == '\n') *c = ' ';
   if (cache_path) {
     std::ifstream in(cache_path);
@@ -1798,6 +1805,7 @@ dm_status dm_autotune(dm_sim* s, double dt, int trial_steps, const char* cache_p
         const int b = std::atoi(line.c_str() + p + 1);
         if (b >= 64 && b <= 512 && b % 64 == 0) {
           s->block = b;
+          s->block_auto = false;
           if (block_out) *block_out = b;
           return DM_OK;
         }
@@ -1821,6 +1829,7 @@ dm_status dm_autotune(dm_sim* s, double dt, int trial_steps, const char* cache_p
   if ((st = dm_load_checkpoint(s, s->tune_ck, 1)) != DM_OK) return st;
   s->time = t0;
   s->block = best;
+  s->block_auto = false;
   g_err.clear();
   if (cache_path) {
     std::ofstream out(cache_path, std::ios::app);

@@ -144,14 +144,16 @@ def test_wide_and_long_rods_match_the_band_solve_when_contact_is_negligible(dm):
     assert_parity(sc.state()[0], plain.state()[0], x0, 1e-9, 1e-6, "negligible contact vs plain")
 
 
-@pytest.mark.parametrize("block", [64, 128])
-def test_small_workgroups_match_the_default(dm, block):
-    """The LU's panel keeps one, two or three rows per thread (workgroups of 256, 128 and 64
-    lanes for the up to 144 panel rows of a coil): four coils with friction over three steps
-    take the same Newton iterations and agree with the default workgroup to 1e-9 relative in
-    position and 1e-6 in displacement."""
+@pytest.mark.parametrize("block", [64, 128, 512])
+def test_workgroup_sizes_agree(dm, block):
+    """The LU's panel keeps each row in a thread's registers where the workgroup has a lane per
+    panel row (up to 144 rows), else in LDS (64 and 128 lanes): four coils with friction over
+    three steps take the same Newton iterations at 64, 128 and 512 lanes as at 256, and agree
+    to 1e-9 relative in position and 1e-6 in displacement."""
     d = W.coiled_springs(4, seed=13, nmin=60, nmax=80)
     say(f"case: four coils, workgroup of {block} lanes against 256")
+    if block == 512:
+        assert dm.sim_from_description(d).block_size == 512      # the default with self-contact
     ref = dm.sim_from_description(d, block_size=256)
     small = dm.sim_from_description(d, block_size=block)
     x0 = ref.state()[0].copy()
@@ -217,6 +219,7 @@ def test_off_is_the_plain_step_bit_for_bit(dm):
     a = dm.sim_from_description(plain)
     b = dm.sim_from_description(d)
     b.set_self_contact(0.0, 0.0)
+    assert b.block_size == a.block_size == 256     # off again: the plain step's workgroup
     a.step(d["dt"], 3)
     b.step(d["dt"], 3)
     assert np.array_equal(a.state()[0], b.state()[0])
