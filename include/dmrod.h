@@ -70,8 +70,9 @@ typedef struct {
   double damping;         /* viscous damping eta [1/s]: F = -eta m (x - x_n)/dt */
   int device;             /* HIP device ordinal */
   void* stream;           /* hipStream_t to run on; NULL = the default stream */
-  int block_size;         /* threads per system workgroup: 0 = automatic, else 64..512,
-                             a multiple of 64 */
+  int block_size;         /* threads per system workgroup: 0 = automatic (256; 512 while
+                             self-contact is on; dm_autotune's choice once it has run), else
+                             64..512, a multiple of 64 */
   int warm_max_iter;      /* Newton iterations allowed to a warm-started solve before it is
                              redone from the step-start state (0 = max_iter) */
   int use_graphs;         /* 1 (default): dm_rollout and the adjoint's recomputation replay one
