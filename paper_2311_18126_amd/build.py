@@ -13,7 +13,10 @@ PEAKS = os.path.join(HERE, "dm_peaks")
 FLOPS = os.path.join(HERE, "dm_flops")
 SOURCES = ["dm_kernels.hip", "dm_mlp.hip", "dm_contact.hip", "dm_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+# gfx950 with XNACK off (the code object for GPUs without page-fault retry, the MI355X's
+# default): the compiler need not keep memory clauses' address registers live for a replay,
+# 0.9 % faster on the rod batch than a code object that also runs with XNACK on
+FLAGS = ["--offload-arch=gfx950:xnack-", "-O3", "-std=c++17", "-fPIC", "-shared",
          # keep the compiler from forming packed FP32 instructions
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          # instruction scheduling for latency hiding over occupancy: the step kernel runs two
