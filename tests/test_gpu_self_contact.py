@@ -165,6 +165,36 @@ def test_workgroup_sizes_agree(dm, block):
     assert_parity(small.state()[0], ref.state()[0], x0, 1e-9, 1e-6, f"{block} lanes vs 256")
 
 
+def test_autotuner_with_self_contact(dm, tmp_path):
+    """dm_autotune times the self-contact step at each workgroup size, restores the state, and
+    files its choice under a key of its own: the same rods without self-contact get another
+    cache line, and a second simulation with self-contact is served from the file."""
+    d = W.coiled_springs(16, seed=13, nmin=40, nmax=60)
+    cache = str(tmp_path / "tune.txt")
+    plain = dict(d)
+    plain.pop("self_contact")
+    p = dm.sim_from_description(plain)
+    p.autotune(d["dt"], trial_steps=1, cache=cache)
+    sim = dm.sim_from_description(d)
+    assert sim.block_size == 512                    # the default with self-contact on
+    sim.step(d["dt"], 1)
+    before = sim.state()
+    b = sim.autotune(d["dt"], trial_steps=1, cache=cache)
+    say(f"autotuned block size with self-contact {b}")
+    assert b in (64, 128, 256, 512) and sim.block_size == b
+    for u, w in zip(before, sim.state()):
+        assert np.array_equal(u, w)
+    with open(cache) as f:
+        lines = f.read().splitlines()
+    assert len(lines) == 2 and lines[0].rsplit(" ", 1)[0] != lines[1].rsplit(" ", 1)[0]
+    again = dm.sim_from_description(d)
+    assert again.autotune(d["dt"], trial_steps=1, cache=cache) == b
+    with open(cache) as f:
+        assert len(f.read().splitlines()) == 2
+    st = sim.step(d["dt"], 2)
+    assert (st["status"] == 0).all()
+
+
 def test_runs_are_bitwise_deterministic(dm):
     """Pairs are found with an LDS atomic counter but sorted before any sum, and every node sums
     its pairs in the list's order: two runs of 32 coils with friction agree bit for bit."""
